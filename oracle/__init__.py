@@ -1,0 +1,218 @@
+"""FP64 CPU oracle for Red-Green-Gray edge labels -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The device library never loads it and
+it never loads the device library; the two share only the seeded arrays made
+by ``paper_2603_28674_amd.synth``.
+
+The arithmetic lives in ``rgg_oracle.c`` (plain C, binary64, no FMA
+contraction); this module builds it with gcc and wraps it with ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rgg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+GREEN, GRAY, RED = 0, 1, 2
+
+_CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fno-builtin",
+           "-fPIC", "-shared", "-pthread", "-Wall", "-Wno-unused-function"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/liboracle.so``."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *_CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        L.orc_robot_new.restype = P
+        L.orc_robot_new.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, D, D]
+        L.orc_robot_free.argtypes = [P]
+        L.orc_rm_build.restype = P
+        L.orc_rm_build.argtypes = [P, I64, P, I64, P, D, C.c_int, I64, C.c_int]
+        L.orc_rm_free.argtypes = [P]
+        L.orc_rm_classify.restype = I64
+        L.orc_rm_classify.argtypes = [P, I64, P, P, P, I64, C.c_int]
+        L.orc_rm_update.restype = I64
+        L.orc_rm_update.argtypes = [P, I64, P, P, P, P, I64, C.c_int]
+        L.orc_rm_pair.argtypes = [P, I64, P, P, P]
+        L.orc_rm_n_edges.restype = I64
+        L.orc_rm_n_edges.argtypes = [P]
+        L.orc_rm_n_configs.restype = I64
+        L.orc_rm_n_configs.argtypes = [P, I64]
+        L.orc_rm_centres.argtypes = [P, I64, P]
+        L.orc_rm_capsule_radius.argtypes = [P, I64, P]
+        L.orc_rm_counters.argtypes = [P, P, P]
+        L.orc_interp.argtypes = [P, P, P, D, P]
+        L.orc_fk.argtypes = [P, P, P]
+        L.orc_deltas.argtypes = [P, P, P, P]
+        L.orc_n_segments.restype = I64
+        L.orc_n_segments.argtypes = [P, P, P, D, C.c_int]
+        L.orc_point_box_d2.restype = D
+        L.orc_point_box_d2.argtypes = [C.c_int, P, P]
+        L.orc_segbox_fmin.restype = D
+        L.orc_segbox_fmin.argtypes = [C.c_int, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Robot:
+    """Oracle-side copy of a ``synth.Robot``."""
+
+    def __init__(self, robot):
+        L = lib()
+        self.kind = robot.kind
+        self.B = robot.n_spheres
+        self.D = robot.dim
+        self.dof = robot.dof
+        self._pos = _f64(robot.sphere_pos).reshape(-1)
+        self._rad = _f64(robot.sphere_radius)
+        self._link = np.ascontiguousarray(
+            robot.sphere_link if robot.sphere_link is not None else np.zeros(self.B), dtype=np.int32)
+        self._len = _f64(robot.link_length if robot.link_length is not None else np.zeros(1))
+        self.h = L.orc_robot_new(robot.kind, self.B, robot.n_links, _p(self._pos), _p(self._link),
+                                 _p(self._rad), _p(self._len), float(robot.base[0]),
+                                 float(robot.base[1]))
+        if not self.h:
+            raise ValueError("oracle rejected the robot")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_robot_free(self.h)
+            self.h = None
+
+    def interp(self, qa, qb, t):
+        out = np.zeros(self.dof)
+        lib().orc_interp(self.h, _p(_f64(qa)), _p(_f64(qb)), float(t), _p(out))
+        return out
+
+    def fk(self, q):
+        out = np.zeros((self.B, self.D))
+        lib().orc_fk(self.h, _p(_f64(q)), _p(out))
+        return out
+
+    def deltas(self, qa, qb):
+        out = np.zeros(self.B)
+        lib().orc_deltas(self.h, _p(_f64(qa)), _p(_f64(qb)), _p(out))
+        return out
+
+    def n_segments(self, qa, qb, resolution, samples_per_edge=0):
+        return int(lib().orc_n_segments(self.h, _p(_f64(qa)), _p(_f64(qb)), float(resolution),
+                                        int(samples_per_edge)))
+
+
+def point_box_d2(c, box, D=None):
+    c = _f64(c)
+    D = D or c.shape[0]
+    return float(lib().orc_point_box_d2(D, _p(c), _p(_f64(box))))
+
+
+def segbox_fmin(a, b, box, D=None):
+    a = _f64(a)
+    D = D or a.shape[0]
+    return float(lib().orc_segbox_fmin(D, _p(a), _p(_f64(b)), _p(_f64(box))))
+
+
+class Roadmap:
+    """Roadmap geometry plus per-edge counters, built by the oracle."""
+
+    def __init__(self, robot, q, edges, resolution=0.0, samples_per_edge=0, n_slots=0, threads=0):
+        self.robot = robot if isinstance(robot, Robot) else Robot(robot)
+        self._q = _f64(q)
+        self._uv = np.ascontiguousarray(edges, dtype=np.int64)
+        self.E = int(self._uv.shape[0])
+        self.M = int(n_slots)
+        threads = threads or min(os.cpu_count() or 1, 16)
+        self.h = lib().orc_rm_build(self.robot.h, self._q.shape[0], _p(self._q), self.E,
+                                    _p(self._uv), float(resolution), int(samples_per_edge),
+                                    self.M, int(threads))
+        if not self.h:
+            raise ValueError("oracle rejected the roadmap")
+        self.threads = threads
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_rm_free(self.h)
+            self.h = None
+
+    def _out(self):
+        return np.zeros(self.E, dtype=np.uint8), np.zeros(max(self.E, 1), dtype=np.int64)
+
+    def classify(self, boxes, threads=None):
+        """From-scratch labels and gray list for the obstacle set ``boxes``."""
+        boxes = _f64(boxes).reshape(-1, 6)
+        lab, gray = self._out()
+        n = lib().orc_rm_classify(self.h, boxes.shape[0], _p(boxes), _p(lab), _p(gray),
+                                  gray.shape[0], int(threads or self.threads))
+        if n < 0:
+            raise ValueError(f"oracle classify failed ({n})")
+        return lab, gray[:n].copy()
+
+    def update(self, old, new, threads=None):
+        """Incremental update from ``old`` (must equal the resident slots)."""
+        old = _f64(old).reshape(-1, 6)
+        new = _f64(new).reshape(-1, 6)
+        lab, gray = self._out()
+        n = lib().orc_rm_update(self.h, old.shape[0], _p(old), _p(new), _p(lab), _p(gray),
+                                gray.shape[0], int(threads or self.threads))
+        if n < 0:
+            raise ValueError(f"oracle update failed ({n})")
+        return lab, gray[:n].copy()
+
+    def pair(self, e, box):
+        c, s = C.c_int32(0), C.c_int32(0)
+        lib().orc_rm_pair(self.h, int(e), _p(_f64(box)), C.byref(c), C.byref(s))
+        return c.value, s.value
+
+    def n_configs(self, e):
+        return int(lib().orc_rm_n_configs(self.h, int(e)))
+
+    def centres(self, e):
+        n = self.n_configs(e)
+        out = np.zeros((n, self.robot.B, self.robot.D))
+        lib().orc_rm_centres(self.h, int(e), _p(out))
+        return out
+
+    def capsule_radius(self, e):
+        out = np.zeros(self.robot.B)
+        lib().orc_rm_capsule_radius(self.h, int(e), _p(out))
+        return out
+
+    def counters(self):
+        o = np.zeros(self.E, dtype=np.int32)
+        i = np.zeros(self.E, dtype=np.int32)
+        lib().orc_rm_counters(self.h, _p(o), _p(i))
+        return o, i
+
+
+def from_workload(w, threads=0):
+    """Oracle roadmap for a ``synth.Workload``."""
+    return Roadmap(w.robot, w.q, w.edges, w.resolution, w.samples_per_edge, w.n_slots, threads)

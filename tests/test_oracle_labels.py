@@ -1,0 +1,223 @@
+"""Pins of the oracle's labels (paper Sec. 3.1 rule, Alg. 1 update).
+
+* hand-built one-edge cases with labels derived by hand (golden fixture);
+* soundness against a dense brute-force check of the continuous motion on
+  tiny roadmaps: RED implies a sampled configuration really collides, GREEN
+  implies no collision anywhere along the edge (Sec. 2.2: inner and outer
+  approximations are a subset and a superset of the swept volume);
+* monotonicity in the obstacle set, incremental == from scratch (Alg. 1 with
+  RevalidateOldIntersections realised as counters), permutation invariance,
+  and degenerate edges (nodes, Sec. 2.1).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2603_28674_amd import synth
+from refgeom import box_d2, centre_path
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "one_edge_cases.json")
+
+
+def _robot(spec):
+    kind = spec["kind"]
+    pos = np.array(spec["sphere_pos"], dtype=float)
+    rad = np.array(spec["sphere_radius"], dtype=float)
+    if kind == synth.ARM:
+        return synth.Robot(kind, pos, rad, np.array(spec["sphere_link"], dtype=np.int32),
+                           np.array(spec["link_length"], dtype=float), (0.0, 0.0))
+    return synth.Robot(kind, pos, rad)
+
+
+def load_cases():
+    with open(GOLDEN) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", load_cases(), ids=lambda c: c["name"])
+def test_one_edge_golden(oracle_lib, case):
+    rob = _robot(case["robot"])
+    q = np.array(case["nodes"], dtype=float)
+    rm = oracle_lib.Roadmap(rob, q, np.array([[0, 1]]), case["resolution"],
+                            case["samples_per_edge"], n_slots=1, threads=1)
+    box = np.array(case["box"], dtype=float)
+    C, S = rm.pair(0, box)
+    assert (C, S) == (case["expect"]["C"], case["expect"]["S"])
+    lab, gray = rm.classify(box[None])
+    assert int(lab[0]) == case["expect"]["label"]
+    assert list(gray) == ([0] if case["expect"]["label"] == 1 else [])
+
+
+# --------------------------------------------------------------------------
+# tiny random roadmaps
+# --------------------------------------------------------------------------
+
+def tiny(kind, seed, n_nodes=12, n_boxes=8):
+    rng = np.random.default_rng(seed)
+    if kind == synth.SE2:
+        rob = synth.robot_se2(rng)
+        q = synth.nodes_se2(rng, n_nodes, 6.0)
+        edges = synth.knn_se2(q, 4)
+        boxes = synth.random_boxes(rng, n_boxes, 2, 0.2, 1.5, 0.0, 6.0)
+        return rob, q, edges, 0.25, 0, boxes
+    if kind == synth.SE3:
+        rob = synth.robot_se3(rng)
+        q = synth.nodes_se3(rng, n_nodes, 2.5)
+        edges = synth.knn_se3(q, 4)
+        boxes = synth.random_boxes(rng, n_boxes, 3, 0.1, 0.6, 0.0, 2.5)
+        return rob, q, edges, 0.0, 6, boxes
+    rob = synth.robot_arm(rng, 3)
+    q = synth.nodes_arm(rng, n_nodes, 3)
+    edges = synth.knn_euclid(q, 4)
+    rho = float(np.sum(rob.link_length))
+    boxes = synth.random_boxes(rng, n_boxes, 2, 0.2, 1.0, -rho, rho)
+    return rob, q, edges, 0.0, 8, boxes
+
+
+@pytest.mark.parametrize("kind", [synth.SE2, synth.SE3, synth.ARM])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_soundness_brute_force(oracle_lib, kind, seed):
+    rob, q, edges, res, spe, boxes = tiny(kind, seed)
+    rm = oracle_lib.Roadmap(rob, q, edges, res, spe, n_slots=len(boxes), threads=2)
+    labels, _ = rm.classify(boxes)
+    D = rob.dim
+    rad2 = rob.sphere_radius ** 2
+    counts = np.zeros(3, dtype=int)
+    for e, (u, v) in enumerate(edges):
+        n = rm.n_configs(e) - 1
+        ts = np.linspace(0.0, 1.0, 64 * n + 1)
+        dense = centre_path(rob, q[u], q[v], ts)            # (T, B, D)
+        samples = centre_path(rob, q[u], q[v], np.arange(n + 1) / n)
+        # the oracle's own sample centres agree with the reference geometry
+        assert np.allclose(rm.centres(e), samples, atol=1e-9)
+        truly_hit = False
+        sample_hit = False
+        for b in boxes:
+            dd = box_d2(dense, b, D) - rad2                  # (T, B)
+            ds = box_d2(samples, b, D) - rad2
+            hit_dense = bool(np.any(dd <= -1e-9))
+            near = bool(np.any(np.abs(dd) < 1e-9))
+            C, S = rm.pair(e, b)
+            if hit_dense:
+                assert C == 1, "outer approximation missed a real collision"
+            if S:
+                assert np.any(ds <= 1e-9), "red without a colliding sample"
+            if np.any(ds <= -1e-9):
+                assert S == 1, "colliding sample not detected"
+            truly_hit |= hit_dense or near
+            sample_hit |= bool(S)
+        if labels[e] == synth_label("GREEN"):
+            assert not truly_hit
+        if labels[e] == synth_label("RED"):
+            assert sample_hit
+        counts[labels[e]] += 1
+    assert counts.sum() == len(edges)
+
+
+def synth_label(name):
+    return {"GREEN": 0, "GRAY": 1, "RED": 2}[name]
+
+
+@pytest.mark.parametrize("kind", [synth.SE2, synth.SE3, synth.ARM])
+def test_monotone_in_obstacles(oracle_lib, kind):
+    rob, q, edges, res, spe, boxes = tiny(kind, 40 + kind, n_nodes=20, n_boxes=6)
+    rm = oracle_lib.Roadmap(rob, q, edges, res, spe, n_slots=len(boxes), threads=2)
+    base, _ = rm.classify(boxes)
+    D = rob.dim
+    rng = np.random.default_rng(7)
+    for _ in range(6):
+        grown = boxes.copy()
+        k = rng.integers(len(boxes))
+        grown[k, :D] -= rng.uniform(0, 0.5, D)
+        grown[k, 3:3 + D] += rng.uniform(0, 0.5, D)
+        lab, _ = rm.classify(grown)
+        # growing never turns red into anything else, nor gray into green
+        assert np.all(lab[base == 2] == 2)
+        assert np.all(lab[base == 1] >= 1)
+        # and the converse for the shrink back
+        back, _ = rm.classify(boxes)
+        assert np.all(back == base)
+        assert np.all(back[lab == 0] == 0)
+        assert np.all(back[lab == 1] <= 1)
+
+
+@pytest.mark.parametrize("kind", [synth.SE2, synth.SE3, synth.ARM])
+def test_incremental_equals_scratch(oracle_lib, kind):
+    rob, q, edges, res, spe, boxes = tiny(kind, 60 + kind, n_nodes=25, n_boxes=10)
+    M = len(boxes)
+    inc = oracle_lib.Roadmap(rob, q, edges, res, spe, n_slots=M, threads=3)
+    scr = oracle_lib.Roadmap(rob, q, edges, res, spe, n_slots=M, threads=1)
+    rng = np.random.default_rng(3)
+    cur = np.tile(synth.ABSENT_BOX, (M, 1))
+    D = rob.dim
+    for step in range(12):
+        nxt = cur.copy()
+        for k in rng.choice(M, size=rng.integers(1, M + 1), replace=False):
+            r = rng.uniform()
+            if r < 0.2:
+                nxt[k] = synth.ABSENT_BOX                         # remove
+            elif np.any(cur[k, :D] > cur[k, 3:3 + D]) or r < 0.4:
+                nxt[k] = boxes[rng.integers(M)]                  # add / replace
+            else:
+                off = rng.normal(0, 0.4, D)
+                nxt[k, :D] += off
+                nxt[k, 3:3 + D] += off                           # move
+        li, gi = inc.update(cur, nxt)
+        ls, gs = scr.classify(nxt)
+        assert np.array_equal(li, ls)
+        assert np.array_equal(gi, gs)
+        assert np.array_equal(gi, np.nonzero(ls == 1)[0])
+        oi, ii = inc.counters()
+        os_, is_ = scr.counters()
+        assert np.array_equal(oi, os_) and np.array_equal(ii, is_)
+        # a red edge always has outer > 0 (S implies C)
+        assert np.all(oi[ii > 0] > 0)
+        cur = nxt
+    with pytest.raises(ValueError):
+        inc.update(np.tile(synth.ABSENT_BOX, (M, 1)), cur)     # stale `old`
+
+
+def test_permutation_invariance(oracle_lib):
+    rob, q, edges, res, spe, boxes = tiny(synth.SE2, 77, n_nodes=30, n_boxes=9)
+    rm = oracle_lib.Roadmap(rob, q, edges, res, spe, n_slots=len(boxes), threads=2)
+    lab, gray = rm.classify(boxes)
+    rng = np.random.default_rng(1)
+    lab2, _ = rm.classify(boxes[rng.permutation(len(boxes))])
+    assert np.array_equal(lab, lab2)
+    perm = rng.permutation(len(edges))
+    rm2 = oracle_lib.Roadmap(rob, q, edges[perm], res, spe, n_slots=len(boxes), threads=2)
+    lab3, gray3 = rm2.classify(boxes)
+    assert np.array_equal(lab3, lab[perm])
+    assert np.array_equal(np.sort(perm[gray3]), gray)
+
+
+def test_degenerate_edges_are_nodes(oracle_lib):
+    rng = np.random.default_rng(12)
+    rob = synth.robot_se2(rng)
+    q = synth.nodes_se2(rng, 40, 8.0)
+    q = np.concatenate([q, q])                     # node i and node i+40 coincide
+    edges = np.stack([np.arange(40), np.arange(40) + 40], axis=1)
+    boxes = synth.random_boxes(rng, 12, 2, 0.3, 2.0, 0.0, 8.0)
+    rm = oracle_lib.Roadmap(rob, q, edges, 0.1, 0, n_slots=len(boxes), threads=2)
+    lab, gray = rm.classify(boxes)
+    assert len(gray) == 0                          # never gray
+    from refgeom import fk_se2_ref
+    for i in range(40):
+        c = fk_se2_ref(rob, q[i])
+        hit = any(np.any(box_d2(c, b, 2) <= rob.sphere_radius ** 2) for b in boxes)
+        assert lab[i] == (2 if hit else 0)
+
+
+def test_absent_boxes_touch_nothing(oracle_lib):
+    rob, q, edges, res, spe, boxes = tiny(synth.SE3, 5)
+    rm = oracle_lib.Roadmap(rob, q, edges, res, spe, n_slots=len(boxes), threads=2)
+    lab, gray = rm.classify(np.tile(synth.ABSENT_BOX, (len(boxes), 1)))
+    assert np.all(lab == 0) and len(gray) == 0
+    # a box with lo > hi on a single axis is absent too
+    b = boxes.copy()
+    b[:, 2], b[:, 5] = 1.0, 0.0
+    lab, _ = rm.classify(b)
+    assert np.all(lab == 0)
