@@ -1,0 +1,247 @@
+/*
+ * rgg.h -- C ABI of librgg: Red-Green-Gray classification of roadmap edges
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Arad et al., "Serialized Red-Green-Gray: Quicker Heuristic
+ * Validation of Edges in Dynamic Roadmap Graphs"):
+ *   Sec. 3.1   an edge whose inner approximation meets an obstacle is RED,
+ *              one whose outer approximation misses every obstacle is GREEN,
+ *              any other edge is GRAY (unknown, left for a full check);
+ *   Sec. 2.2   cfg(e) = |e|/eps configurations along the edge; an outer
+ *              (inner) approximation is a superset (subset) of the swept
+ *              volume;
+ *   Alg. 1     when an obstacle moves, only the components it touched before
+ *              and touches now are revisited;
+ *   Sec. 3.3   the approximations are stored once, resident on the GPU, and
+ *              only the new obstacle poses go up per update; a uniform grid
+ *              restricts the tests to edges near the moved obstacles.
+ *
+ * Primitives of this library:
+ *   robot       a union of spheres on a planar rigid body (SE2: x, y, theta),
+ *               a spatial rigid body (SE3: x, y, z, qw, qx, qy, qz) or a planar
+ *               serial arm (joint angles q0..q_{L-1});
+ *   inner       the robot's spheres at every configuration of cfg(e);
+ *   outer       per sphere, a capsule around the chord of its centre path,
+ *               radius r_i + delta_i with delta_i = max|p''| / 8 (the
+ *               linear-interpolation error bound of the centre path);
+ *   obstacles   closed axis-aligned boxes.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an rgg_status: RGG_OK (0) or a negative error code.
+ *     After an error, rgg_last_error() gives a message for the calling thread.
+ *   - The caller owns every pointer it passes.  The library copies what it
+ *     keeps (robot, approximations, resident obstacle slots); no host array
+ *     is retained after a call returns.
+ *   - Host pointers are plain CPU memory; "device" pointers are GPU memory of
+ *     the context's device (e.g. torch tensors' data_ptr()).
+ *   - A roadmap is not thread-safe: calls on one roadmap must not overlap.
+ *     Different roadmaps may be used from different threads.
+ */
+#ifndef RGG_H
+#define RGG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rgg_status;
+#define RGG_OK 0
+#define RGG_E_INVALID_ARG (-1)     /* bad argument; nothing changed          */
+#define RGG_E_OUT_OF_MEMORY (-2)   /* host or device allocation failed       */
+#define RGG_E_STATE_MISMATCH (-3)  /* `old` differs from the resident slots  */
+#define RGG_E_CAPACITY (-4)        /* gray list longer than the caller's cap */
+#define RGG_E_DEVICE (-5)          /* HIP runtime error                      */
+#define RGG_E_UNSUPPORTED (-6)     /* valid request this build cannot serve  */
+
+/* robot kinds */
+#define RGG_SE2 0
+#define RGG_SE3 1
+#define RGG_PLANAR_ARM 2
+
+/* labels, one uint8_t per edge */
+#define RGG_GREEN 0
+#define RGG_GRAY 1
+#define RGG_RED 2
+
+/* precision of the distance tests */
+#define RGG_PREC_FP64 0           /* every test in binary64                   */
+#define RGG_PREC_FP32_RECHECK 1   /* binary32 tests; any pair with a margin in
+                                     the rounding band is re-tested in
+                                     binary64, so labels equal the FP64 ones */
+
+/* A closed axis-aligned box.  Planar roadmaps use indices 0 and 1; indices 2
+ * must still be finite.  A box with lo[k] > hi[k] on any used axis is ABSENT:
+ * it meets nothing.  The canonical ABSENT box, held by every slot after
+ * rgg_build, is lo = {1,1,1}, hi = {-1,-1,-1}. */
+typedef struct {
+    double lo[3];
+    double hi[3];
+} rgg_box;
+
+typedef struct {
+    int32_t kind;                 /* RGG_SE2 / RGG_SE3 / RGG_PLANAR_ARM        */
+    int32_t n_spheres;            /* B, 1..64                                   */
+    int32_t n_links;              /* arm only, 1..32                            */
+    int32_t reserved;
+    const double *sphere_pos;     /* SE2 [B][2], SE3 [B][3] body-frame offsets;
+                                     arm [B] distance along the sphere's link   */
+    const int32_t *sphere_link;   /* arm only: [B] link index of each sphere    */
+    const double *sphere_radius;  /* [B], > 0                                   */
+    const double *link_length;    /* arm only: [n_links]                        */
+    double base[2];               /* arm only: base position                    */
+} rgg_robot;
+
+typedef struct {
+    int64_t n_nodes;
+    const double *q;              /* [n_nodes][dof] host, dof = 3 / 7 / n_links;
+                                     SE3 quaternions (qw,qx,qy,qz) unit length   */
+    int64_t n_edges;
+    const int64_t *edge_uv;       /* [n_edges][2] host node ids; the caller's
+                                     edge order is the order of every output    */
+} rgg_roadmap_desc;
+
+typedef struct {
+    double resolution;            /* eps, C-space step between configurations */
+    int32_t samples_per_edge;     /* > 1 fixes |cfg(e)|, overriding resolution  */
+    int32_t precision;            /* RGG_PREC_*                                 */
+    double band_rel;              /* FP32 band: a test whose FP32 margin m has
+                                     |m| <= band_rel * s^2 (s = largest
+                                     magnitude among the pair's coordinates)
+                                     is decided in FP64; <= 0 selects 1e-5     */
+    int64_t n_obstacle_slots;     /* M, >= 0                                    */
+    double cell_size;             /* grid cell edge; 0 = heuristic; < 0 = one
+                                     cell covering everything                   */
+    int32_t host_threads;         /* threads for the host build; 0 = automatic  */
+    int32_t reserved;
+} rgg_build_opts;
+
+/* Written by the device at the end of every update (rgg_update_async) and
+ * returned by rgg_update. */
+typedef struct {
+    int32_t status;               /* RGG_OK, RGG_E_INVALID_ARG (non-finite box)
+                                     or RGG_E_STATE_MISMATCH; on error nothing
+                                     changed and no output was written          */
+    int32_t n_changed;            /* changed (box, sign) entries this update    */
+    int64_t n_gray;               /* number of GRAY edges (may exceed gray_cap) */
+    int64_t n_candidate_edges;    /* edges passing the grid + box pretest       */
+    int64_t n_pairs;              /* (edge, changed box) pairs tested           */
+    int64_t n_outer_hits;         /* pairs whose outer approximation met        */
+    int64_t n_rechecked;          /* pairs re-decided in binary64               */
+    int64_t n_cells_visited;      /* (cell, edge) entries scanned by the grid   */
+    int64_t test_bytes;           /* bytes the classify kernel read and wrote   */
+} rgg_update_result;
+
+typedef struct {
+    int64_t n_edges;
+    int64_t n_slots;
+    int32_t dim;                  /* workspace dimension D (2 or 3)             */
+    int32_t n_spheres;
+    int64_t n_sphere_samples;     /* sum over edges of |cfg(e)| * B             */
+    int64_t grid_cells[3];
+    double cell_size;
+    int64_t grid_entries;         /* (cell, edge) registrations                 */
+    int64_t device_bytes;         /* device memory held by the roadmap          */
+    double build_seconds;
+} rgg_roadmap_info;
+
+typedef struct rgg_context rgg_context;
+typedef struct rgg_roadmap rgg_roadmap;
+typedef struct rgg_graph rgg_graph;
+
+/* Opens `device` (HIP ordinal) for later builds.  *out receives the context. */
+rgg_status rgg_context_create(int device, rgg_context **out);
+void rgg_context_destroy(rgg_context *ctx);
+
+/* Builds the approximations of every edge (Sec. 3.3 offline storage: built
+ * once, resident on the GPU): FP64 forward kinematics at every configuration
+ * of cfg(e) (Sec. 2.2), per-sphere capsules, edge bounding boxes and the
+ * uniform grid (Sec. 3.3 spatial filtering).  Every obstacle slot starts
+ * ABSENT, so every label starts GREEN (Sec. 4: roadmaps are built without
+ * obstacles).  Errors: RGG_E_INVALID_ARG (null pointer, node id out of
+ * range, non-finite or non-unit input, bad option), RGG_E_OUT_OF_MEMORY,
+ * RGG_E_DEVICE.  *out receives the roadmap. */
+rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *roadmap, const rgg_robot *robot,
+                     const rgg_build_opts *opts, rgg_roadmap **out);
+rgg_status rgg_destroy(rgg_roadmap *rm);
+rgg_status rgg_roadmap_info_get(rgg_roadmap *rm, rgg_roadmap_info *out);
+
+/* One update (Alg. 1 for every slot whose box changed, Sec. 3.1 labels),
+ * host buffers.  `obstacles_old` and `obstacles_new` are [m] host boxes;
+ * m must equal n_obstacle_slots and `obstacles_old` must equal the resident
+ * slots bit for bit (else RGG_E_STATE_MISMATCH, nothing changes).  Slots
+ * whose old and new boxes differ are the moved obstacles; adding and removing
+ * go through ABSENT.  After the call the labels of all edges equal the rule
+ * applied to `obstacles_new`.  Outputs (each may be NULL): labels [E] host,
+ * gray [gray_cap] host (ascending GRAY edge ids), *n_gray, *result.  If
+ * n_gray > gray_cap the update is still committed, gray[0..gray_cap) is
+ * written and RGG_E_CAPACITY is returned.  Blocks until done. */
+rgg_status rgg_update(rgg_roadmap *rm, int64_t m, const rgg_box *obstacles_old,
+                      const rgg_box *obstacles_new, uint8_t *labels, int64_t *gray,
+                      int64_t gray_cap, int64_t *n_gray, rgg_update_result *result);
+
+/* The same update with every buffer in device memory, queued on `stream`
+ * (a hipStream_t; NULL = the null stream) and returning at once.
+ * d_old/d_new [m] boxes, d_labels [E] (or NULL), d_gray [gray_cap] (or NULL),
+ * d_result (required) receive the outputs in stream order.  Validation of the
+ * boxes happens on the device: on a bad box or a state mismatch
+ * d_result->status is set, nothing changes and no label or gray id is
+ * written.  Host-side errors (bad pointers, m != slots) return at once. */
+rgg_status rgg_update_async(rgg_roadmap *rm, void *stream, int64_t m, const rgg_box *d_old,
+                            const rgg_box *d_new, uint8_t *d_labels, int64_t *d_gray,
+                            int64_t gray_cap, rgg_update_result *d_result);
+
+/* A request for rgg_graph_create: the arguments of one rgg_update_async. */
+typedef struct {
+    rgg_roadmap *rm;
+    int64_t m;
+    const rgg_box *d_old, *d_new;
+    uint8_t *d_labels;
+    int64_t *d_gray;
+    int64_t gray_cap;
+    rgg_update_result *d_result;
+} rgg_update_req;
+
+/* Captures n updates into one HIP graph: requests naming the same roadmap run
+ * in the order given, requests on different roadmaps run as independent
+ * branches.  Every launch of the graph performs all n updates; the device
+ * pointers are fixed at creation.  *out receives the graph. */
+rgg_status rgg_graph_create(rgg_context *ctx, int32_t n, const rgg_update_req *reqs,
+                            rgg_graph **out);
+rgg_status rgg_graph_launch(rgg_graph *g, void *stream);
+rgg_status rgg_graph_destroy(rgg_graph *g);
+
+/* Current labels [E] / gray list of the last update, copied to host memory.
+ * rgg_gray_list writes min(n, cap) ids and sets *n to the full count. */
+rgg_status rgg_labels(rgg_roadmap *rm, uint8_t *out);
+rgg_status rgg_gray_list(rgg_roadmap *rm, int64_t *out, int64_t cap, int64_t *n);
+
+/* Per-update kernel timing with HIP events on the update's stream (off by
+ * default).  rgg_timing_read returns the summed milliseconds of each stage
+ * over the updates since the last read, and resets them:
+ * ms[0] diff, ms[1] grid cells, ms[2] grid scan, ms[3] classify, ms[4] labels
+ * and gray compaction.  *n_updates receives the number of updates timed. */
+rgg_status rgg_timing_enable(rgg_roadmap *rm, int32_t on);
+rgg_status rgg_timing_read(rgg_roadmap *rm, double ms[5], int64_t *n_updates);
+
+/* Host-only view of the build stage, for tests: computes the approximations
+ * of edge range [e0, e1) exactly as rgg_build does, without any device.
+ * n_configs [e1-e0] receives |cfg(e)|; centres [sum |cfg(e)|][B][D] the
+ * sphere centres; capsule [e1-e0][B][2D+1] (A, B, R); aabb [e1-e0][6] the
+ * padded FP32 edge box (lo, hi).  Pass NULL centres/capsule/aabb to query
+ * n_configs only. */
+rgg_status rgg_debug_geometry(const rgg_roadmap_desc *roadmap, const rgg_robot *robot,
+                              const rgg_build_opts *opts, int64_t e0, int64_t e1,
+                              int64_t *n_configs, double *centres, double *capsule,
+                              float *aabb);
+
+const char *rgg_last_error(void);
+const char *rgg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RGG_H */

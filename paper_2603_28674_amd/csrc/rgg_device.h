@@ -1,0 +1,92 @@
+// Device-side layout of a resident roadmap and the launch interface of the
+// update pipeline.  Internal to librgg (shared by kernels.hip and api.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rgg.h"
+
+namespace rgg {
+
+// Control block of one roadmap, in device memory.  k_diff resets it at the
+// start of every update; later kernels of the same update read it.
+struct Ctl {
+    int32_t status;        // RGG_OK / RGG_E_INVALID_ARG / RGG_E_STATE_MISMATCH
+    int32_t n_chg;         // changed (box, sign) entries
+    int32_t n_items;       // (cell, chunk) work items of the grid scan
+    int32_t n_work;        // candidate edges
+    unsigned long long n_pairs, n_outer, n_recheck, n_visited, test_bytes;
+};
+
+// One changed obstacle entry: the box a slot held before (sign -1) or holds
+// now (sign +1).  Entries are ordered by slot, old before new.
+struct ChgEntry {
+    float lo32[3], hi32[3];    // outward-rounded binary32 copy
+    float sbox;                // largest |coordinate| of the binary32 copy
+    int32_t sign;
+    double lo[3], hi[3];       // exact box (unused axes zero)
+    int32_t c0[3], c1[3];      // inclusive grid-cell range; empty when c0 > c1
+};
+
+// Everything a kernel needs about a roadmap, passed by value.
+struct RmDev {
+    int32_t D, B, mixed, chunk;
+    int64_t E, M;
+    float band_rel;
+    int32_t ntiles;            // label tiles of kLabelTile edges
+    // approximations (see HostGeometry for the layouts)
+    const int64_t *soff;
+    const float *samp32;
+    const double *samp64;
+    const float *cap32;
+    const double *cap64;
+    const float *aabb;
+    const float *rad2_32;      // [B] r_i^2 rounded to binary32
+    const double *rad64;       // [B]
+    // grid
+    int32_t gdim[3];
+    int32_t pad0;
+    double gorg[3];
+    double ginv;
+    int64_t ncells;
+    const int32_t *cell_start;
+    const int32_t *cell_edges;
+    int64_t items_cap;
+    // state and per-update scratch
+    int2 *cnt;                 // [E] (outer, inner) counters
+    uint32_t *edge_bits;       // [ceil(E/32)] candidate marks, zero between updates
+    uint32_t *cell_bits;       // [ceil(ncells/32)] touched cells, zero between updates
+    rgg_box *resident;         // [M] obstacle slots
+    ChgEntry *chg;             // [2M]
+    int2 *items;               // [items_cap] (cell, chunk)
+    int32_t *work;             // [E] candidate edge ids
+    int32_t *tile_cnt;         // [ntiles] gray edges per label tile
+    Ctl *ctl;
+};
+
+constexpr int kLabelTile = 4096;   // edges per block of the label kernels
+
+struct UpdateArgs {
+    const rgg_box *old_b;
+    const rgg_box *new_b;
+    uint8_t *labels;           // may be null
+    int64_t *gray;             // may be null
+    int64_t gray_cap;
+    rgg_update_result *res;
+};
+
+// Queues the five kernels of one update on `s`.  When `ev` is non-null,
+// ev[0..5] are recorded before, between and after the kernels.
+hipError_t launch_update(const RmDev &rm, const UpdateArgs &a, hipStream_t s, hipEvent_t *ev);
+
+// Appends the same five kernels to `g` as a chain; `dep` (may be null) is the
+// node they wait for, *last receives the final node.
+hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, hipGraphNode_t dep,
+                            hipGraphNode_t *last);
+
+// Recomputes labels and the gray list from the counters regardless of the
+// last update's status (used by rgg_labels / rgg_gray_list).
+hipError_t launch_labels(const RmDev &rm, const UpdateArgs &a, hipStream_t s);
+
+}  // namespace rgg

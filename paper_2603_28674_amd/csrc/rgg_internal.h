@@ -1,0 +1,68 @@
+// Internal declarations shared by librgg's own translation units (host build
+// stage, kernels, C ABI).  Not installed; the public interface is rgg.h.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "rgg.h"
+
+namespace rgg {
+
+constexpr int kMaxSpheres = 64;     // one wavefront covers every sphere of an edge
+constexpr int kMaxLinks = 32;
+constexpr int kAabbStride = 8;      // floats per edge box: lo[3], s, hi[3], pad
+
+// Approximations of a range of edges, built on the host in binary64.
+//
+// Sphere samples of edge e occupy [soff[e], soff[e+1]) in "sphere-sample"
+// units: sample n = j*B + i is sphere i at configuration j of cfg(e).  The
+// coordinates are stored per edge as a [D][P_e] block (P_e = soff[e+1] -
+// soff[e]) starting at float/double index D*soff[e], so a wavefront reads 64
+// consecutive samples of one coordinate with one coalesced load.
+struct HostGeometry {
+    int kind = 0, D = 0, B = 0;
+    int64_t E = 0;
+    std::vector<int64_t> soff;     // [E+1]
+    std::vector<double> samp;      // [sum_e D*P_e]
+    std::vector<double> cap;       // [E][2D+1][B]: A_0..A_{D-1}, B_0..B_{D-1}, R
+    std::vector<float> aabb;       // [E][8]: padded FP32 box lo[3], s, hi[3], 0
+    std::vector<double> radius;    // [B]
+};
+
+// Validates the inputs of rgg_build.  Returns RGG_OK or RGG_E_INVALID_ARG
+// with *err describing the problem.
+rgg_status validate_build_inputs(const rgg_roadmap_desc *rd, const rgg_robot *rob,
+                                 const rgg_build_opts *opts, std::string *err);
+
+// Builds the approximations of edges [e0, e1).  Inputs must be validated.
+rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *rob,
+                          const rgg_build_opts *opts, int64_t e0, int64_t e1, int threads,
+                          HostGeometry *out, std::string *err);
+
+// Uniform grid over the edge boxes (Sec. 3.3 spatially filtered checking).
+struct HostGrid {
+    int32_t dim[3] = {1, 1, 1};
+    double org[3] = {0, 0, 0};
+    double inv = 0.0;              // 1 / cell size; 0 = a single cell
+    double cell = 0.0;
+    std::vector<int32_t> start;    // [ncells+1]
+    std::vector<int32_t> edges;    // edge ids per cell, ascending
+    int64_t items_cap = 0;         // sum over cells of max(1, ceil(n/chunk))
+};
+
+// Cell of coordinate x: floor((x - org) * inv), as an integer in [-1, n]
+// (-1 below the grid, n above it).  The device evaluates the same binary64
+// expression, so registration and lookup agree and are monotone in x.
+int32_t cell_coord(double x, double org, double inv, int32_t n);
+
+rgg_status build_grid(const HostGeometry &g, double cell_size, int32_t chunk, HostGrid *out,
+                      std::string *err);
+
+// Rounds a binary64 value to binary32 toward -inf / +inf.
+float f32_down(double x);
+float f32_up(double x);
+
+}  // namespace rgg

@@ -1,0 +1,393 @@
+"""Python binding of librgg (include/rgg.h): argument marshalling only.
+
+Every function keeps the C name.  Host arrays are numpy arrays; device
+buffers are torch tensors on the library's device (torch supplies device
+memory and streams, nothing else).  Every step of an update runs in librgg's
+HIP kernels; if the library is not built this module raises on import of the
+library, and no Python fallback exists.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  -- loads torch's HIP runtime before librgg so both share one
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librgg.so")
+
+RGG_OK = 0
+RGG_E_INVALID_ARG = -1
+RGG_E_OUT_OF_MEMORY = -2
+RGG_E_STATE_MISMATCH = -3
+RGG_E_CAPACITY = -4
+RGG_E_DEVICE = -5
+RGG_E_UNSUPPORTED = -6
+
+RGG_SE2, RGG_SE3, RGG_PLANAR_ARM = 0, 1, 2
+RGG_GREEN, RGG_GRAY, RGG_RED = 0, 1, 2
+RGG_PREC_FP64, RGG_PREC_FP32_RECHECK = 0, 1
+
+
+class RggError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"librgg status {status}: {message}")
+        self.status = status
+
+
+class rgg_box(C.Structure):
+    _fields_ = [("lo", C.c_double * 3), ("hi", C.c_double * 3)]
+
+
+class rgg_robot(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_spheres", C.c_int32), ("n_links", C.c_int32),
+                ("reserved", C.c_int32), ("sphere_pos", C.c_void_p), ("sphere_link", C.c_void_p),
+                ("sphere_radius", C.c_void_p), ("link_length", C.c_void_p),
+                ("base", C.c_double * 2)]
+
+
+class rgg_roadmap_desc(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("q", C.c_void_p), ("n_edges", C.c_int64),
+                ("edge_uv", C.c_void_p)]
+
+
+class rgg_build_opts(C.Structure):
+    _fields_ = [("resolution", C.c_double), ("samples_per_edge", C.c_int32),
+                ("precision", C.c_int32), ("band_rel", C.c_double),
+                ("n_obstacle_slots", C.c_int64), ("cell_size", C.c_double),
+                ("host_threads", C.c_int32), ("reserved", C.c_int32)]
+
+
+class rgg_update_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_changed", C.c_int32), ("n_gray", C.c_int64),
+                ("n_candidate_edges", C.c_int64), ("n_pairs", C.c_int64),
+                ("n_outer_hits", C.c_int64), ("n_rechecked", C.c_int64),
+                ("n_cells_visited", C.c_int64), ("test_bytes", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class rgg_roadmap_info(C.Structure):
+    _fields_ = [("n_edges", C.c_int64), ("n_slots", C.c_int64), ("dim", C.c_int32),
+                ("n_spheres", C.c_int32), ("n_sphere_samples", C.c_int64),
+                ("grid_cells", C.c_int64 * 3), ("cell_size", C.c_double),
+                ("grid_entries", C.c_int64), ("device_bytes", C.c_int64),
+                ("build_seconds", C.c_double)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["grid_cells"] = list(self.grid_cells)
+        return d
+
+
+class rgg_update_req(C.Structure):
+    _fields_ = [("rm", C.c_void_p), ("m", C.c_int64), ("d_old", C.c_void_p),
+                ("d_new", C.c_void_p), ("d_labels", C.c_void_p), ("d_gray", C.c_void_p),
+                ("gray_cap", C.c_int64), ("d_result", C.c_void_p)]
+
+
+RESULT_BYTES = C.sizeof(rgg_update_result)
+
+#: every symbol include/rgg.h declares
+EXPORTS = ["rgg_context_create", "rgg_context_destroy", "rgg_build", "rgg_destroy",
+           "rgg_roadmap_info_get", "rgg_update", "rgg_update_async", "rgg_graph_create",
+           "rgg_graph_launch", "rgg_graph_destroy", "rgg_labels", "rgg_gray_list",
+           "rgg_timing_enable", "rgg_timing_read", "rgg_debug_geometry", "rgg_last_error",
+           "rgg_version"]
+
+_lib = None
+
+
+def lib():
+    """Loads librgg.so (fails loudly when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
+    sig = {
+        "rgg_context_create": (I32, [C.c_int, C.POINTER(P)]),
+        "rgg_context_destroy": (None, [P]),
+        "rgg_build": (I32, [P, P, P, P, C.POINTER(P)]),
+        "rgg_destroy": (I32, [P]),
+        "rgg_roadmap_info_get": (I32, [P, P]),
+        "rgg_update": (I32, [P, I64, P, P, P, P, I64, P, P]),
+        "rgg_update_async": (I32, [P, P, I64, P, P, P, P, I64, P]),
+        "rgg_graph_create": (I32, [P, I32, P, C.POINTER(P)]),
+        "rgg_graph_launch": (I32, [P, P]),
+        "rgg_graph_destroy": (I32, [P]),
+        "rgg_labels": (I32, [P, P]),
+        "rgg_gray_list": (I32, [P, P, I64, P]),
+        "rgg_timing_enable": (I32, [P, I32]),
+        "rgg_timing_read": (I32, [P, P, P]),
+        "rgg_debug_geometry": (I32, [P, P, P, I64, I64, P, P, P, P]),
+        "rgg_last_error": (C.c_char_p, []),
+        "rgg_version": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != RGG_OK:
+        raise RggError(st, lib().rgg_last_error().decode())
+    return st
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------------------
+# marshalling of robots, roadmaps and options
+# --------------------------------------------------------------------------
+
+class _Keep:
+    """Holds the numpy arrays a C struct points into."""
+
+    def __init__(self):
+        self.arrays = []
+
+    def f64(self, a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        self.arrays.append(a)
+        return a
+
+    def i(self, a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        self.arrays.append(a)
+        return a
+
+
+def make_robot(robot, keep):
+    """rgg_robot from an object with the fields of ``synth.Robot``."""
+    r = rgg_robot()
+    r.kind = robot.kind
+    r.n_spheres = robot.sphere_radius.shape[0]
+    r.n_links = 0 if robot.link_length is None else robot.link_length.shape[0]
+    r.sphere_pos = _ptr(keep.f64(robot.sphere_pos))
+    r.sphere_radius = _ptr(keep.f64(robot.sphere_radius))
+    if robot.sphere_link is not None:
+        r.sphere_link = _ptr(keep.i(robot.sphere_link, np.int32))
+    if robot.link_length is not None:
+        r.link_length = _ptr(keep.f64(robot.link_length))
+    r.base[0], r.base[1] = float(robot.base[0]), float(robot.base[1])
+    return r
+
+
+def make_desc(q, edges, keep):
+    d = rgg_roadmap_desc()
+    qa = keep.f64(q)
+    ea = keep.i(edges, np.int64)
+    d.n_nodes = qa.shape[0]
+    d.q = _ptr(qa)
+    d.n_edges = ea.shape[0]
+    d.edge_uv = _ptr(ea)
+    return d
+
+
+def make_opts(resolution=0.0, samples_per_edge=0, precision=RGG_PREC_FP64, band_rel=1e-5,
+              n_obstacle_slots=0, cell_size=0.0, host_threads=0):
+    o = rgg_build_opts()
+    o.resolution = resolution
+    o.samples_per_edge = samples_per_edge
+    o.precision = precision
+    o.band_rel = band_rel
+    o.n_obstacle_slots = n_obstacle_slots
+    o.cell_size = cell_size
+    o.host_threads = host_threads
+    return o
+
+
+def boxes_array(boxes):
+    """(M, 6) float64 rows lo_x lo_y lo_z hi_x hi_y hi_z, the rgg_box layout."""
+    a = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 6)
+    return a
+
+
+# --------------------------------------------------------------------------
+# C entry points (same names)
+# --------------------------------------------------------------------------
+
+def rgg_context_create(device=0):
+    h = C.c_void_p()
+    _check(lib().rgg_context_create(device, C.byref(h)))
+    return h
+
+
+def rgg_context_destroy(ctx):
+    lib().rgg_context_destroy(ctx)
+
+
+def rgg_build(ctx, desc, robot, opts):
+    h = C.c_void_p()
+    _check(lib().rgg_build(ctx, C.byref(desc), C.byref(robot), C.byref(opts), C.byref(h)))
+    return h
+
+
+def rgg_destroy(rm):
+    _check(lib().rgg_destroy(rm))
+
+
+def rgg_roadmap_info_get(rm):
+    info = rgg_roadmap_info()
+    _check(lib().rgg_roadmap_info_get(rm, C.byref(info)))
+    return info
+
+
+def rgg_update(rm, old, new, n_edges, want_labels=True, gray_cap=None):
+    """Host-buffer update.  Returns (labels or None, gray ids, n_gray, result)."""
+    old = boxes_array(old)
+    new = boxes_array(new)
+    labels = np.empty(n_edges, dtype=np.uint8) if want_labels else None
+    cap = n_edges if gray_cap is None else gray_cap
+    gray = np.empty(max(cap, 1), dtype=np.int64)
+    n = C.c_int64(0)
+    res = rgg_update_result()
+    st = lib().rgg_update(rm, old.shape[0], _ptr(old), _ptr(new), _ptr(labels), _ptr(gray), cap,
+                          C.byref(n), C.byref(res))
+    if st not in (RGG_OK, RGG_E_CAPACITY):
+        _check(st)
+    return labels, gray[:min(n.value, cap)].copy(), n.value, res
+
+
+def rgg_update_async(rm, stream, m, d_old, d_new, d_labels, d_gray, gray_cap, d_result):
+    """Device-buffer update queued on ``stream`` (a hipStream_t handle as int)."""
+    _check(lib().rgg_update_async(rm, C.c_void_p(stream), m, _dptr(d_old), _dptr(d_new),
+                                  _dptr(d_labels), _dptr(d_gray), gray_cap, _dptr(d_result)))
+
+
+def rgg_labels(rm, n_edges):
+    out = np.empty(max(n_edges, 1), dtype=np.uint8)
+    _check(lib().rgg_labels(rm, _ptr(out)))
+    return out[:n_edges]
+
+
+def rgg_gray_list(rm, cap):
+    out = np.empty(max(cap, 1), dtype=np.int64)
+    n = C.c_int64(0)
+    st = lib().rgg_gray_list(rm, _ptr(out), cap, C.byref(n))
+    if st not in (RGG_OK, RGG_E_CAPACITY):
+        _check(st)
+    return out[:min(n.value, cap)].copy(), n.value
+
+
+def rgg_graph_create(ctx, reqs):
+    arr = (rgg_update_req * len(reqs))(*reqs)
+    h = C.c_void_p()
+    _check(lib().rgg_graph_create(ctx, len(reqs), arr, C.byref(h)))
+    return h
+
+
+def rgg_graph_launch(g, stream):
+    _check(lib().rgg_graph_launch(g, C.c_void_p(stream)))
+
+
+def rgg_graph_destroy(g):
+    _check(lib().rgg_graph_destroy(g))
+
+
+def rgg_timing_enable(rm, on=True):
+    _check(lib().rgg_timing_enable(rm, 1 if on else 0))
+
+
+def rgg_timing_read(rm):
+    ms = np.zeros(5)
+    n = C.c_int64(0)
+    _check(lib().rgg_timing_read(rm, _ptr(ms), C.byref(n)))
+    return ms, n.value
+
+
+def rgg_debug_geometry(desc, robot, opts, e0, e1):
+    """Host build stage of edges [e0, e1): (n_configs, centres, capsules, boxes)."""
+    L = lib()
+    cnt = np.zeros(max(e1 - e0, 1), dtype=np.int64)
+    _check(L.rgg_debug_geometry(C.byref(desc), C.byref(robot), C.byref(opts), e0, e1, _ptr(cnt),
+                                None, None, None))
+    cnt = cnt[:e1 - e0]
+    B = robot.n_spheres
+    D = 3 if robot.kind == RGG_SE3 else 2
+    ctr = np.zeros((max(int(cnt.sum()), 1), B, D))
+    cap = np.zeros((max(e1 - e0, 1), B, 2 * D + 1))
+    box = np.zeros((max(e1 - e0, 1), 6), dtype=np.float32)
+    _check(L.rgg_debug_geometry(C.byref(desc), C.byref(robot), C.byref(opts), e0, e1, _ptr(cnt),
+                                _ptr(ctr), _ptr(cap), _ptr(box)))
+    return cnt, ctr[:int(cnt.sum())], cap[:e1 - e0], box[:e1 - e0]
+
+
+def rgg_last_error():
+    return lib().rgg_last_error().decode()
+
+
+def rgg_version():
+    return lib().rgg_version().decode()
+
+
+# --------------------------------------------------------------------------
+# convenience wrapper
+# --------------------------------------------------------------------------
+
+class Roadmap:
+    """A roadmap resident on the GPU (wraps rgg_build / rgg_update / rgg_destroy)."""
+
+    def __init__(self, ctx, robot, q, edges, n_slots, resolution=0.0, samples_per_edge=0,
+                 precision=RGG_PREC_FP64, band_rel=1e-5, cell_size=0.0, host_threads=0):
+        keep = _Keep()
+        self._keep = keep
+        self.robot = make_robot(robot, keep)
+        self.desc = make_desc(q, edges, keep)
+        self.opts = make_opts(resolution, samples_per_edge, precision, band_rel, n_slots,
+                              cell_size, host_threads)
+        self.h = rgg_build(ctx, self.desc, self.robot, self.opts)
+        self.E = int(np.asarray(edges).shape[0])
+        self.M = int(n_slots)
+
+    @classmethod
+    def from_workload(cls, ctx, w, precision=RGG_PREC_FP64, **kw):
+        return cls(ctx, w.robot, w.q, w.edges, w.n_slots, w.resolution, w.samples_per_edge,
+                   precision, **kw)
+
+    def update(self, old, new, **kw):
+        return rgg_update(self.h, old, new, self.E, **kw)
+
+    def update_async(self, stream, d_old, d_new, d_labels, d_gray, d_result, gray_cap=None):
+        cap = self.E if gray_cap is None else gray_cap
+        rgg_update_async(self.h, stream, self.M, d_old, d_new, d_labels, d_gray, cap, d_result)
+
+    def labels(self):
+        return rgg_labels(self.h, self.E)
+
+    def gray_list(self, cap=None):
+        return rgg_gray_list(self.h, self.E if cap is None else cap)
+
+    def info(self):
+        return rgg_roadmap_info_get(self.h).as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            rgg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def result_from_tensor(t):
+    """Decodes an rgg_update_result held in a uint8 tensor (device or host)."""
+    raw = t.detach().to("cpu").numpy().tobytes()
+    return rgg_update_result.from_buffer_copy(raw[:RESULT_BYTES])

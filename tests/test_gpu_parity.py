@@ -1,0 +1,192 @@
+"""GPU parity: librgg's labels and gray lists equal the FP64 oracle's.
+
+Every comparison is exact (labels are integers, gray lists are edge ids).
+Sizes span several label tiles (4096 edges) with a ragged tail; sequences
+start from the all-ABSENT state (Sec. 4: roadmaps are built without
+obstacles), add the first obstacle set, then move obstacles (Sec. 4: random
+translations), and include removals and re-additions through ABSENT.
+"""
+import numpy as np
+import pytest
+
+from paper_2603_28674_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2603_28674_amd import rgg
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = rgg.rgg_context_create(0)
+    yield c
+    rgg.rgg_context_destroy(c)
+
+
+def workload(kind, n_updates=6, seed=None):
+    if kind == "planar":
+        return synth.planar_rigid(seed=seed or 11, n_nodes=2000, n_boxes=50, n_updates=n_updates)
+    if kind == "spatial":
+        return synth.spatial_rigid(seed=seed or 12, n_nodes=3000, n_boxes=120, n_updates=n_updates,
+                                   world=4.0)
+    if kind == "arm":
+        return synth.planar_arm(seed=seed or 13, n_nodes=3000, n_boxes=60, n_updates=n_updates)
+    raise ValueError(kind)
+
+
+def with_removals(w, rng):
+    """Appends states that remove some slots (ABSENT) and add them back."""
+    last = w.boxes[-1].copy()
+    rem = last.copy()
+    idx = rng.choice(w.n_slots, size=max(1, w.n_slots // 5), replace=False)
+    rem[idx] = synth.ABSENT_BOX
+    back = rem.copy()
+    back[idx[: len(idx) // 2]] = last[idx[: len(idx) // 2]]
+    w.boxes = w.boxes + [rem, back]
+    return w
+
+
+def check_sequence(ctx, w, precision, cell_size=0.0, band_rel=1e-5, device_buffers=False):
+    import torch
+    from paper_2603_28674_amd import rgg
+    import oracle
+    print(f"[parity] {w.name} E={w.n_edges} M={w.n_slots} precision={precision} "
+          f"cell={cell_size} band={band_rel} device_buffers={device_buffers}", flush=True)
+    g = rgg.Roadmap.from_workload(ctx, w, precision=precision, cell_size=cell_size,
+                                  band_rel=band_rel)
+    o = oracle.from_workload(w)
+    prev = w.absent()
+    stats = []
+    if device_buffers:
+        dev = torch.device("cuda:0")
+        states = [torch.from_numpy(b.copy()).to(dev) for b in [prev] + w.boxes]
+        labels = torch.zeros(w.n_edges, dtype=torch.uint8, device=dev)
+        gray = torch.zeros(max(w.n_edges, 1), dtype=torch.int64, device=dev)
+        res = torch.zeros(rgg.RESULT_BYTES, dtype=torch.uint8, device=dev)
+        stream = torch.cuda.current_stream().cuda_stream
+    for u, cur in enumerate(w.boxes):
+        ol, og = o.update(prev, cur)
+        if device_buffers:
+            g.update_async(stream, states[u], states[u + 1], labels, gray, res)
+            torch.cuda.synchronize()
+            r = rgg.result_from_tensor(res)
+            assert r.status == 0
+            gl = labels.cpu().numpy()
+            gg = gray[: r.n_gray].cpu().numpy()
+            n = r.n_gray
+        else:
+            gl, gg, n, r = g.update(prev, cur)
+        assert n == len(og), f"update {u}: n_gray {n} vs oracle {len(og)}"
+        bad = np.nonzero(gl != ol)[0]
+        assert bad.size == 0, f"update {u}: {bad.size} labels differ, first {bad[:10]}"
+        assert np.array_equal(gg, og), f"update {u}: gray list differs"
+        stats.append(r.as_dict())
+        prev = cur
+    # the library's own label query agrees with the last update
+    assert np.array_equal(g.labels(), ol)
+    gl2, n2 = g.gray_list()
+    assert n2 == len(og) and np.array_equal(gl2, og)
+    g.close()
+    return stats
+
+
+@pytest.mark.parametrize("kind", ["planar", "spatial", "arm"])
+def test_parity_fp64(ctx, kind):
+    from paper_2603_28674_amd import rgg
+    w = with_removals(workload(kind), np.random.default_rng(1))
+    stats = check_sequence(ctx, w, rgg.RGG_PREC_FP64)
+    assert all(s["n_rechecked"] == 0 for s in stats)
+    assert sum(s["n_pairs"] for s in stats) > 0
+
+
+@pytest.mark.parametrize("kind", ["planar", "spatial", "arm"])
+def test_parity_fp32_recheck(ctx, kind):
+    from paper_2603_28674_amd import rgg
+    w = with_removals(workload(kind), np.random.default_rng(2))
+    stats = check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK)
+    assert sum(s["n_pairs"] for s in stats) > 0
+
+
+@pytest.mark.parametrize("cell_size", [-1.0, 0.0, 0.5, 3.0])
+def test_grid_cell_size_does_not_change_labels(ctx, cell_size):
+    from paper_2603_28674_amd import rgg
+    w = workload("spatial", n_updates=3, seed=21)
+    check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, cell_size=cell_size)
+
+
+def test_device_buffer_entry_point(ctx):
+    from paper_2603_28674_amd import rgg
+    w = workload("spatial", n_updates=4, seed=22)
+    check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, device_buffers=True)
+    w = workload("planar", n_updates=3, seed=23)
+    check_sequence(ctx, w, rgg.RGG_PREC_FP64, device_buffers=True)
+
+
+def test_band_infinite_rechecks_every_decision(ctx):
+    from paper_2603_28674_amd import rgg
+    w = workload("spatial", n_updates=2, seed=24)
+    stats = check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, band_rel=float("inf"))
+    assert all(s["n_rechecked"] == s["n_pairs"] for s in stats)
+
+
+def test_errors_leave_state_unchanged(ctx):
+    from paper_2603_28674_amd import rgg
+    import oracle
+    w = workload("planar", n_updates=2, seed=25)
+    print(f"[errors] E={w.n_edges}", flush=True)
+    g = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP64)
+    lab0, gray0, n0, _ = g.update(w.absent(), w.boxes[0])
+    # stale `old`
+    with pytest.raises(rgg.RggError) as ei:
+        g.update(w.absent(), w.boxes[1])
+    assert ei.value.status == rgg.RGG_E_STATE_MISMATCH
+    assert np.array_equal(g.labels(), lab0)
+    # non-finite box
+    bad = w.boxes[1].copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(rgg.RggError) as ei:
+        g.update(w.boxes[0], bad)
+    assert ei.value.status == rgg.RGG_E_INVALID_ARG
+    assert np.array_equal(g.labels(), lab0)
+    # wrong slot count
+    with pytest.raises(rgg.RggError):
+        g.update(w.boxes[0][:-1], w.boxes[1][:-1])
+    # gray capacity: committed, partial list, status CAPACITY
+    o = oracle.from_workload(w)
+    o.update(w.absent(), w.boxes[0])
+    ol, og = o.update(w.boxes[0], w.boxes[1])
+    lab, gray, n, _ = g.update(w.boxes[0], w.boxes[1], gray_cap=3)
+    assert n == len(og) and np.array_equal(gray, og[:3])
+    assert np.array_equal(lab, ol)
+    g.close()
+
+
+def test_empty_and_degenerate(ctx):
+    from paper_2603_28674_amd import rgg
+    import oracle
+    rng = np.random.default_rng(5)
+    rob = synth.robot_se2(rng)
+    q = synth.nodes_se2(rng, 50, 20.0)
+    print("[empty] no edges", flush=True)
+    g = rgg.Roadmap(ctx, rob, q, np.zeros((0, 2), dtype=np.int64), 3, resolution=0.1)
+    boxes = synth.random_boxes(rng, 3, 2, 1.0, 3.0, 0.0, 20.0)
+    lab, gray, n, _ = g.update(np.tile(synth.ABSENT_BOX, (3, 1)), boxes)
+    assert lab.size == 0 and n == 0
+    g.close()
+    print("[empty] no slots", flush=True)
+    edges = synth.knn_se2(q, 4)
+    g = rgg.Roadmap(ctx, rob, q, edges, 0, resolution=0.1)
+    lab, gray, n, _ = g.update(np.zeros((0, 6)), np.zeros((0, 6)))
+    assert np.all(lab == 0) and n == 0
+    g.close()
+    print("[degenerate] duplicated nodes, box over everything, box far away", flush=True)
+    q2 = np.concatenate([q, q])
+    e2 = np.concatenate([edges, np.stack([np.arange(50), np.arange(50) + 50], axis=1)])
+    big = np.array([[-100, -100, 0, 200, 200, 0], [500, 500, 0, 501, 501, 0]], dtype=float)
+    g = rgg.Roadmap(ctx, rob, q2, e2, 2, resolution=0.1)
+    o = oracle.Roadmap(rob, q2, e2, 0.1, 0, 2)
+    lab, gray, n, _ = g.update(np.tile(synth.ABSENT_BOX, (2, 1)), big)
+    ol, og = o.update(np.tile(synth.ABSENT_BOX, (2, 1)), big)
+    assert np.array_equal(lab, ol) and np.all(lab == 2) and n == 0
+    g.close()

@@ -1,0 +1,122 @@
+"""CPU checks of the C-ABI library (no GPU calls).
+
+* librgg.so loads and exports every function include/rgg.h declares;
+* its host build stage (rgg_debug_geometry) produces the same binary64
+  sphere centres and capsule radii as the oracle, bit for bit, although the
+  two are separate code: both evaluate the same stated expressions, so the
+  device's binary64 re-tests see the oracle's numbers;
+* its padded binary32 edge boxes contain every capsule;
+* invalid build inputs are rejected with RGG_E_INVALID_ARG.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2603_28674_amd import rgg, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "rgg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rgg_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_match_header():
+    L = rgg.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert sorted(names) == sorted(rgg.EXPORTS)
+    assert rgg.rgg_version().startswith("librgg")
+
+
+def _small(kind, seed=3):
+    if kind == synth.SE2:
+        return synth.planar_rigid(seed=seed, n_nodes=150, n_boxes=10, n_updates=1, resolution=0.1)
+    if kind == synth.SE3:
+        return synth.spatial_rigid(seed=seed, n_nodes=200, n_boxes=10, n_updates=1)
+    return synth.planar_arm(seed=seed, n_nodes=200, n_boxes=10, n_updates=1, n_links=5)
+
+
+@pytest.mark.parametrize("kind", [synth.SE2, synth.SE3, synth.ARM])
+def test_host_geometry_bitwise_equals_oracle(oracle_lib, kind):
+    w = _small(kind)
+    keep = rgg._Keep()
+    desc = rgg.make_desc(w.q, w.edges, keep)
+    robot = rgg.make_robot(w.robot, keep)
+    opts = rgg.make_opts(w.resolution, w.samples_per_edge, n_obstacle_slots=w.n_slots)
+    E = w.n_edges
+    cnt, ctr, cap, box = rgg.rgg_debug_geometry(desc, robot, opts, 0, E)
+    orc = oracle_lib.from_workload(w, threads=2)
+    D = w.robot.dim
+    row = 0
+    for e in range(E):
+        oc = orc.centres(e)                        # (n, B, D)
+        assert cnt[e] == oc.shape[0]
+        mine = ctr[row:row + cnt[e]]
+        row += cnt[e]
+        assert np.array_equal(mine.view(np.uint64), oc.view(np.uint64)), f"edge {e} centres differ"
+        # capsule endpoints are the first and last centres; radius r + delta
+        assert np.array_equal(cap[e, :, :D], oc[0])
+        assert np.array_equal(cap[e, :, D:2 * D], oc[-1])
+        assert np.array_equal(cap[e, :, 2 * D].view(np.uint64), orc.capsule_radius(e).view(np.uint64))
+        # the binary32 edge box contains every capsule
+        lo = np.minimum(cap[e, :, :D], cap[e, :, D:2 * D]) - cap[e, :, 2 * D:2 * D + 1]
+        hi = np.maximum(cap[e, :, :D], cap[e, :, D:2 * D]) + cap[e, :, 2 * D:2 * D + 1]
+        assert np.all(box[e, :D].astype(np.float64) <= lo.min(axis=0))
+        assert np.all(box[e, 3:3 + D].astype(np.float64) >= hi.max(axis=0))
+
+
+def test_partial_range_matches_full():
+    w = _small(synth.SE3, seed=9)
+    keep = rgg._Keep()
+    desc = rgg.make_desc(w.q, w.edges, keep)
+    robot = rgg.make_robot(w.robot, keep)
+    opts = rgg.make_opts(w.resolution, w.samples_per_edge, n_obstacle_slots=w.n_slots)
+    full = rgg.rgg_debug_geometry(desc, robot, opts, 0, w.n_edges)
+    part = rgg.rgg_debug_geometry(desc, robot, opts, 5, 17)
+    start = int(full[0][:5].sum())
+    assert np.array_equal(part[0], full[0][5:17])
+    assert np.array_equal(part[1], full[1][start:start + int(part[0].sum())])
+    assert np.array_equal(part[2], full[2][5:17])
+
+
+def test_invalid_inputs_rejected():
+    w = _small(synth.SE2)
+    keep = rgg._Keep()
+
+    def attempt(q=None, edges=None, robot=None, **optkw):
+        desc = rgg.make_desc(w.q if q is None else q, w.edges if edges is None else edges, keep)
+        rb = rgg.make_robot(robot or w.robot, keep)
+        kw = dict(resolution=0.1, n_obstacle_slots=4)
+        kw.update(optkw)
+        with pytest.raises(rgg.RggError) as ei:
+            rgg.rgg_debug_geometry(desc, rb, rgg.make_opts(**kw), 0, 1)
+        return ei.value.status
+
+    bad_edges = w.edges.copy()
+    bad_edges[0, 1] = len(w.q)
+    assert attempt(edges=bad_edges) == rgg.RGG_E_INVALID_ARG
+    q = w.q.copy()
+    q[0, 0] = np.nan
+    assert attempt(q=q) == rgg.RGG_E_INVALID_ARG
+    assert attempt(resolution=0.0) == rgg.RGG_E_INVALID_ARG
+    assert attempt(samples_per_edge=1) == rgg.RGG_E_INVALID_ARG
+    assert attempt(precision=7) == rgg.RGG_E_INVALID_ARG
+    r = synth.Robot(synth.SE2, w.robot.sphere_pos, -w.robot.sphere_radius)
+    assert attempt(robot=r) == rgg.RGG_E_INVALID_ARG
+    big = synth.Robot(synth.SE2, np.zeros((65, 2)), np.ones(65))
+    assert attempt(robot=big) == rgg.RGG_E_INVALID_ARG
+    # a non-unit quaternion is refused for spatial robots
+    w3 = _small(synth.SE3)
+    q3 = w3.q.copy()
+    q3[0, 3:] *= 1.5
+    desc = rgg.make_desc(q3, w3.edges, keep)
+    with pytest.raises(rgg.RggError):
+        rgg.rgg_debug_geometry(desc, rgg.make_robot(w3.robot, keep),
+                               rgg.make_opts(0.0, 20, n_obstacle_slots=1), 0, 1)
