@@ -41,6 +41,9 @@ def parse():
     p.add_argument("--cpu-sample-edges", type=int, default=30000)
     p.add_argument("--skip-graph", action="store_true")
     p.add_argument("--seed", type=int, default=2)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="also run a plain 1 GiB device copy 5 times (reference kernel for "
+                        "scaling FETCH_SIZE / WRITE_SIZE counters)")
     return p.parse_args()
 
 
@@ -197,7 +200,7 @@ def main():
         "graph": graph,
         "stage_ms_per_update": {"diff": ms[0] / n_timed, "cells": ms[1] / n_timed,
                                 "grid": ms[2] / n_timed, "classify": ms[3] / n_timed,
-                                "labels": ms[4] / n_timed},
+                                "recheck": ms[4] / n_timed, "labels": ms[5] / n_timed},
         "per_update": stats,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -209,6 +212,13 @@ def main():
         log("[bench] cpu baseline (oracle on a sample)")
         line["cpu_baseline"] = cpu_baseline(w, final_labels, a.cpu_sample_edges, last, a.seed)
     g.close()
+    if a.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = src.numel() * 4
     print(json.dumps(line), flush=True)
 
 

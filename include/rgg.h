@@ -111,7 +111,7 @@ typedef struct {
                                      |m| <= band_rel * s^2 (s = largest
                                      magnitude among the pair's coordinates)
                                      is decided in FP64; <= 0 selects 1e-5     */
-    int64_t n_obstacle_slots;     /* M, >= 0                                    */
+    int64_t n_obstacle_slots;     /* M, 0..4096                                 */
     double cell_size;             /* grid cell edge; 0 = heuristic; < 0 = one
                                      cell covering everything                   */
     int32_t host_threads;         /* threads for the host build; 0 = automatic  */
@@ -221,10 +221,11 @@ rgg_status rgg_gray_list(rgg_roadmap *rm, int64_t *out, int64_t cap, int64_t *n)
 /* Per-update kernel timing with HIP events on the update's stream (off by
  * default).  rgg_timing_read returns the summed milliseconds of each stage
  * over the updates since the last read, and resets them:
- * ms[0] diff, ms[1] grid cells, ms[2] grid scan, ms[3] classify, ms[4] labels
- * and gray compaction.  *n_updates receives the number of updates timed. */
+ * ms[0] diff, ms[1] grid cells, ms[2] grid scan, ms[3] classify, ms[4] FP64
+ * re-test, ms[5] labels and gray compaction.  *n_updates receives the number
+ * of updates timed. */
 rgg_status rgg_timing_enable(rgg_roadmap *rm, int32_t on);
-rgg_status rgg_timing_read(rgg_roadmap *rm, double ms[5], int64_t *n_updates);
+rgg_status rgg_timing_read(rgg_roadmap *rm, double ms[6], int64_t *n_updates);
 
 /* Host-only view of the build stage, for tests: computes the approximations
  * of edge range [e0, e1) exactly as rgg_build does, without any device.

@@ -79,8 +79,8 @@ struct rgg_roadmap {
     int64_t *d_gray = nullptr;        // [E]
     // timing
     bool timing = false;
-    std::vector<std::array<hipEvent_t, 6>> pool, pending;
-    double ms_acc[5] = {0, 0, 0, 0, 0};
+    std::vector<std::array<hipEvent_t, 7>> pool, pending;
+    double ms_acc[6] = {0, 0, 0, 0, 0, 0};
     int64_t timed = 0;
 
     ~rgg_roadmap()
@@ -183,6 +183,13 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     dv.band_rel = (float)(opts->band_rel > 0.0 ? opts->band_rel : 1e-5);
     if (std::isinf(opts->band_rel)) dv.band_rel = INFINITY;
     dv.ntiles = (int32_t)std::max<int64_t>(1, (E + kLabelTile - 1) / kLabelTile);
+    dv.p_fixed = 0;
+    if (E > 0) {
+        const int64_t p0 = g.soff[1] - g.soff[0];
+        bool same = p0 <= INT32_MAX;
+        for (int64_t e = 1; e < E && same; ++e) same = g.soff[e + 1] - g.soff[e] == p0;
+        if (same) dv.p_fixed = (int32_t)p0;
+    }
     auto guard = [&](rgg_status s) {
         if (s != RGG_OK) delete rm;
         return s;
@@ -250,7 +257,10 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     if ((st = rm->upload(&dv.resident, absent.data(), (size_t)M, "obstacle slots")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.chg, (size_t)(2 * M), "changed entries")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.items, (size_t)grid.items_cap, "grid items")) != RGG_OK) return guard(st);
-    if ((st = rm->alloc(&dv.work, (size_t)E, "candidate list")) != RGG_OK) return guard(st);
+    if ((st = rm->alloc(&dv.item_cnt, (size_t)grid.items_cap, "grid item counts")) != RGG_OK) return guard(st);
+    if ((st = rm->alloc(&dv.work, grid.edges.size(), "candidate list")) != RGG_OK) return guard(st);
+    if ((st = rm->alloc(&dv.unsure, grid.edges.size(), "re-test marks")) != RGG_OK) return guard(st);
+    if ((st = rm->alloc(&dv.blk_stats, (size_t)kStatBlocks * kStats, "statistics")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.tile_cnt, (size_t)dv.ntiles, "tile counts")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.ctl, 1, "control block")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&rm->d_stage, (size_t)(2 * M), "box staging")) != RGG_OK) return guard(st);
@@ -261,6 +271,7 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     HIP_OR_FAIL(hipMemset(dv.edge_bits, 0, 4 * std::max<size_t>(nwords, 1)), "clear marks");
     HIP_OR_FAIL(hipMemset(dv.cell_bits, 0, 4 * std::max<size_t>(ncw, 1)), "clear marks");
     HIP_OR_FAIL(hipMemset(dv.ctl, 0, sizeof(Ctl)), "clear control");
+    HIP_OR_FAIL(hipMemset(dv.blk_stats, 0, sizeof(unsigned long long) * kStatBlocks * kStats), "clear statistics");
     HIP_OR_FAIL(hipMemset(rm->d_labels, 0, std::max<int64_t>(E, 1)), "clear labels");
     HIP_OR_FAIL(hipHostMalloc((void **)&rm->h_stage, sizeof(rgg_box) * std::max<int64_t>(2 * M, 1)), "pinned staging");
     HIP_OR_FAIL(hipHostMalloc((void **)&rm->h_res, sizeof(rgg_update_result)), "pinned result");
@@ -323,7 +334,7 @@ rgg_status enqueue(rgg_roadmap *rm, hipStream_t s, const UpdateArgs &a)
     hipEvent_t *ev = nullptr;
     if (rm->timing) {
         if (rm->pool.empty()) {
-            std::array<hipEvent_t, 6> set;
+            std::array<hipEvent_t, 7> set;
             for (auto &e : set) HIP_OR_FAIL(hipEventCreate(&e), "hipEventCreate");
             rm->pool.push_back(set);
         }
@@ -438,13 +449,13 @@ rgg_status rgg_timing_enable(rgg_roadmap *rm, int32_t on)
     return RGG_OK;
 }
 
-rgg_status rgg_timing_read(rgg_roadmap *rm, double ms[5], int64_t *n_updates)
+rgg_status rgg_timing_read(rgg_roadmap *rm, double ms[6], int64_t *n_updates)
 {
     if (!rm || !ms) return fail(RGG_E_INVALID_ARG, "null argument");
     HIP_OR_FAIL(hipSetDevice(rm->device), "hipSetDevice");
     for (auto &set : rm->pending) {
-        HIP_OR_FAIL(hipEventSynchronize(set[5]), "hipEventSynchronize");
-        for (int k = 0; k < 5; ++k) {
+        HIP_OR_FAIL(hipEventSynchronize(set[6]), "hipEventSynchronize");
+        for (int k = 0; k < 6; ++k) {
             float t = 0.0f;
             HIP_OR_FAIL(hipEventElapsedTime(&t, set[k], set[k + 1]), "hipEventElapsedTime");
             rm->ms_acc[k] += t;
@@ -453,7 +464,7 @@ rgg_status rgg_timing_read(rgg_roadmap *rm, double ms[5], int64_t *n_updates)
         rm->pool.push_back(set);
     }
     rm->pending.clear();
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 6; ++k) {
         ms[k] = rm->ms_acc[k];
         rm->ms_acc[k] = 0.0;
     }

@@ -286,7 +286,7 @@ rgg_status validate_build_inputs(const rgg_roadmap_desc *rd, const rgg_robot *r,
     if (o->precision != RGG_PREC_FP64 && o->precision != RGG_PREC_FP32_RECHECK)
         return bad("unknown precision");
     if (!(o->band_rel >= 0.0) && !(o->band_rel <= 0.0)) return bad("band_rel is NaN");
-    if (o->n_obstacle_slots < 0 || o->n_obstacle_slots > (1 << 24)) return bad("bad n_obstacle_slots");
+    if (o->n_obstacle_slots < 0 || o->n_obstacle_slots > 4096) return bad("n_obstacle_slots must be 0..4096");
     if (std::isnan(o->cell_size)) return bad("cell_size is NaN");
     return RGG_OK;
 }

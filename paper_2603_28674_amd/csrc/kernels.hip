@@ -1,22 +1,26 @@
 // Update pipeline of librgg for gfx950 (wave64).
 //
-// One update = five kernels on one stream:
-//   k_diff     validate old/new boxes against the resident slots, list the
-//              changed (box, sign) entries in slot order, commit the slots
-//              (Alg. 1: the moved obstacle's old and new poses);
-//   k_cells    activate the grid cells each changed box overlaps and emit one
-//              work item per (cell, chunk of its edge list)  (Sec. 3.3 grid);
-//   k_grid     scan the edges of the active cells, keep those whose box meets
-//              a changed box of that cell, and queue each such edge once;
-//   k_classify one wavefront per queued edge: outer test (per-sphere capsule
-//              vs box), inner test (sphere samples vs box, stop at the first
-//              hit), FP64 re-test of pairs inside the rounding band, counter
-//              update (Sec. 3.1 rule, Alg. 1 intersection lists as counts);
+// One update = up to seven kernels on one stream:
+//   k_diff      validate the old/new boxes against the resident slots, list
+//               the changed (box, sign) entries in slot order, commit the
+//               slots (Alg. 1: a moved obstacle's old and new poses);
+//   k_cells     activate every grid cell a changed box overlaps and emit one
+//               work item per (cell, chunk of its edge list)  (Sec. 3.3 grid);
+//   k_grid      per item, keep the edges whose box meets a changed box of that
+//               cell; candidates are written in place, no global counter;
+//   k_classify  one wavefront per candidate edge: outer test (per-sphere
+//               capsule vs box), inner test (sphere samples vs box, stopping at
+//               the first hit), counter update (Sec. 3.1 rule; Alg. 1's
+//               intersection lists kept as counts).  In the FP32 mode a pair
+//               whose margin falls inside the rounding band is left to
+//   k_recheck   which re-decides it in binary64;
 //   k_count + k_write   labels from the counters and the ordered gray list.
 //
-// All binary64 code below is compiled without FMA contraction; its sums run
-// left to right from 0.0 so that a re-test reproduces the definition's
-// values exactly.
+// Binary64 code is compiled without FMA contraction and its sums run left to
+// right from 0.0, so a re-test reproduces the definition's values exactly.
+// No hot path uses a single global counter: on MI355X device-scope atomics on
+// one address serialise across the eight XCDs, so work lists are positional
+// and statistics are per-block partial sums.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -33,10 +37,9 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kTile = 256;         // changed entries staged in LDS per pass
 constexpr int kSubCap = 1024;      // entries of one cell staged by k_grid
 constexpr int kCellsGrid = 128;
-constexpr int kGridGrid = 2048;
-constexpr int kClassifyGrid = 2048;
+constexpr int kGrid = kStatBlocks; // blocks of k_grid, k_classify, k_recheck
 
-enum : int { kMiss = 0, kHit = 1, kUnsure = 2 };
+enum : int { kMiss = 0, kHit = 1, kUnsure = 2, kOpen = 3 };
 enum : uint8_t { kCHit = 1, kCUnsure = 2, kSHit = 4, kSUnsure = 8 };
 
 __device__ inline int lane_id() { return __lane_id(); }
@@ -47,6 +50,19 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline int wave_prefix(int v, int *total)
+{
+    // inclusive scan over the wavefront, returned exclusive
+    const int lane = lane_id();
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    *total = __shfl(x, 63);
+    return x - v;
 }
 
 __device__ inline float next_down(float f)
@@ -77,53 +93,59 @@ __device__ inline int32_t cell_of(double x, double org, double inv, int32_t n)
     return (int32_t)c;
 }
 
+__device__ inline bool overlap3(const float *lo, const float *hi, const float4 &bl, const float4 &bh)
+{
+    return lo[0] <= bh.x && hi[0] >= bl.x && lo[1] <= bh.y && hi[1] >= bl.y && lo[2] <= bh.z &&
+           hi[2] >= bl.z;
+}
+
 // ------------------------------------------------------------------------
-// distance predicates (templated on the floating type and the dimension)
+// binary64 predicates: the definition, evaluated in a fixed order
 // ------------------------------------------------------------------------
 
-template <typename T>
-__device__ inline T gap1(T x, T lo, T hi)
+__device__ inline double gap64(double x, double lo, double hi)
 {
-    T a = lo - x;
-    T g = a > T(0) ? a : T(0);
-    T b = x - hi;
+    double a = lo - x;
+    double g = a > 0.0 ? a : 0.0;
+    double b = x - hi;
     return b > g ? b : g;
 }
 
-// squared distance from point c to the box
-template <typename T, int D>
-__device__ inline T point_box_d2(const T *c, const T *lo, const T *hi)
+template <int D>
+__device__ inline double point_box64(const double *c, const double *lo, const double *hi)
 {
-    T acc = T(0);
+    double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        T g = gap1(c[k], lo[k], hi[k]);
+        double g = gap64(c[k], lo[k], hi[k]);
         acc = acc + g * g;
     }
     return acc;
 }
 
-template <typename T, int D>
-__device__ inline T seg_F(const T *A, const T *d, T t, const T *lo, const T *hi)
+template <int D>
+__device__ inline double seg_F64(const double *A, const double *d, double t, const double *lo,
+                                 const double *hi)
 {
-    T acc = T(0);
+    double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        T p = A[k] + t * d[k];
-        T g = gap1(p, lo[k], hi[k]);
+        double p = A[k] + t * d[k];
+        double g = gap64(p, lo[k], hi[k]);
         acc = acc + g * g;
     }
     return acc;
 }
 
-template <typename T, int D>
-__device__ inline T seg_G(const T *A, const T *d, T t, const T *lo, const T *hi)
+template <int D>
+__device__ inline double seg_G64(const double *A, const double *d, double t, const double *lo,
+                                 const double *hi)
 {
-    T acc = T(0);
+    double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        T p = A[k] + t * d[k];
-        T ex = p < lo[k] ? p - lo[k] : (p > hi[k] ? p - hi[k] : T(0));
+        double p = A[k] + t * d[k];
+        double ex = p < lo[k] ? p - lo[k] : (p > hi[k] ? p - hi[k] : 0.0);
         acc = acc + d[k] * ex;
     }
     return acc;
@@ -132,41 +154,42 @@ __device__ inline T seg_G(const T *A, const T *d, T t, const T *lo, const T *hi)
 // Minimum over t in [0,1] of the squared distance from A + t (B - A) to the
 // box.  The function is convex and piecewise quadratic with breaks where a
 // coordinate crosses a face plane; its half-derivative G is nondecreasing.
-// Bracket the minimiser between the largest candidate with G <= 0 and the
-// smallest with G >= 0 (candidates: 0, 1, face crossings strictly inside),
-// then minimise the single quadratic of that bracket.
-template <typename T, int D>
-__device__ inline T segbox_fmin(const T *A, const T *Bp, const T *lo, const T *hi)
+// The minimiser lies between the largest candidate with G <= 0 and the
+// smallest with G >= 0 (candidates: 0, 1, face crossings strictly inside);
+// there the faces in play are fixed and the single quadratic's stationary
+// point is clamped into that bracket.
+template <int D>
+__device__ inline double segbox64(const double *A, const double *Bp, const double *lo, const double *hi)
 {
-    T d[D];
+    double d[D];
 #pragma unroll
     for (int k = 0; k < D; ++k) d[k] = Bp[k] - A[k];
-    T tL = T(0), tR = T(1);
-    auto take = [&](T t) {
-        T g = seg_G<T, D>(A, d, t, lo, hi);
-        if (g <= T(0) && t > tL) tL = t;
-        if (g >= T(0) && t < tR) tR = t;
+    double tL = 0.0, tR = 1.0;
+    auto take = [&](double t) {
+        double g = seg_G64<D>(A, d, t, lo, hi);
+        if (g <= 0.0 && t > tL) tL = t;
+        if (g >= 0.0 && t < tR) tR = t;
     };
-    take(T(0));
-    take(T(1));
+    take(0.0);
+    take(1.0);
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        if (d[k] != T(0)) {
-            T t1 = (lo[k] - A[k]) / d[k];
-            if (t1 > T(0) && t1 < T(1)) take(t1);
-            T t2 = (hi[k] - A[k]) / d[k];
-            if (t2 > T(0) && t2 < T(1)) take(t2);
+        if (d[k] != 0.0) {
+            double t1 = (lo[k] - A[k]) / d[k];
+            if (t1 > 0.0 && t1 < 1.0) take(t1);
+            double t2 = (hi[k] - A[k]) / d[k];
+            if (t2 > 0.0 && t2 < 1.0) take(t2);
         }
     }
-    T fL = seg_F<T, D>(A, d, tL, lo, hi);
-    T fR = seg_F<T, D>(A, d, tR, lo, hi);
-    T fmin = fL < fR ? fL : fR;
+    double fL = seg_F64<D>(A, d, tL, lo, hi);
+    double fR = seg_F64<D>(A, d, tR, lo, hi);
+    double fmin = fL < fR ? fL : fR;
     if (tL < tR) {
-        T tm = T(0.5) * (tL + tR);
-        T num = T(0), den = T(0);
+        double tm = 0.5 * (tL + tR);
+        double num = 0.0, den = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            T p = A[k] + tm * d[k];
+            double p = A[k] + tm * d[k];
             if (p < lo[k]) {
                 num = num + d[k] * (lo[k] - A[k]);
                 den = den + d[k] * d[k];
@@ -175,16 +198,98 @@ __device__ inline T segbox_fmin(const T *A, const T *Bp, const T *lo, const T *h
                 den = den + d[k] * d[k];
             }
         }
-        T ts = tL;
-        if (den > T(0)) {
+        double ts = tL;
+        if (den > 0.0) {
             ts = num / den;
             if (ts < tL) ts = tL;
             if (ts > tR) ts = tR;
         }
-        T fs = seg_F<T, D>(A, d, ts, lo, hi);
+        double fs = seg_F64<D>(A, d, ts, lo, hi);
         if (fs < fmin) fmin = fs;
     }
     return fmin;
+}
+
+// ------------------------------------------------------------------------
+// binary32 filter: the same quantities, any rounding; only a margin outside
+// the band +-band_rel*s^2 is trusted (s bounds every coordinate of the pair)
+// ------------------------------------------------------------------------
+
+template <int D>
+__device__ inline float point_box32(const float *c, const float *lo, const float *hi)
+{
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        float g = fmaxf(fmaxf(lo[k] - c[k], 0.0f), c[k] - hi[k]);
+        acc = __builtin_fmaf(g, g, acc);
+    }
+    return acc;
+}
+
+template <int D>
+__device__ inline float seg_F32(const float *A, const float *d, float t, const float *lo, const float *hi)
+{
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        float p = __builtin_fmaf(t, d[k], A[k]);
+        float g = fmaxf(fmaxf(lo[k] - p, 0.0f), p - hi[k]);
+        acc = __builtin_fmaf(g, g, acc);
+    }
+    return acc;
+}
+
+template <int D>
+__device__ inline float segbox32(const float *A, const float *Bp, const float *lo, const float *hi)
+{
+    float d[D], inv[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        d[k] = Bp[k] - A[k];
+        inv[k] = d[k] != 0.0f ? __builtin_amdgcn_rcpf(d[k]) : 0.0f;
+    }
+    float tL = 0.0f, tR = 1.0f;
+    auto take = [&](float t) {
+        float g = 0.0f;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            float p = __builtin_fmaf(t, d[k], A[k]);
+            float ex = fminf(p - lo[k], 0.0f) + fmaxf(p - hi[k], 0.0f);
+            g = __builtin_fmaf(d[k], ex, g);
+        }
+        tL = (g <= 0.0f && t > tL) ? t : tL;
+        tR = (g >= 0.0f && t < tR) ? t : tR;
+    };
+    take(0.0f);
+    take(1.0f);
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        // a crossing outside (0,1) (or of an axis the segment does not
+        // move along) is replaced by t = 0, which repeats the first candidate
+        float t1 = (lo[k] - A[k]) * inv[k];
+        float t2 = (hi[k] - A[k]) * inv[k];
+        take(t1 > 0.0f && t1 < 1.0f ? t1 : 0.0f);
+        take(t2 > 0.0f && t2 < 1.0f ? t2 : 0.0f);
+    }
+    float fmin = fminf(seg_F32<D>(A, d, tL, lo, hi), seg_F32<D>(A, d, tR, lo, hi));
+    float tm = 0.5f * (tL + tR);
+    float num = 0.0f, den = 0.0f;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        float p = __builtin_fmaf(tm, d[k], A[k]);
+        float b = p < lo[k] ? lo[k] : (p > hi[k] ? hi[k] : A[k]);
+        float w = (p < lo[k] || p > hi[k]) ? d[k] : 0.0f;
+        num = __builtin_fmaf(w, b - A[k], num);
+        den = __builtin_fmaf(w, w, den);
+    }
+    float ts = den > 0.0f ? fminf(fmaxf(num * __builtin_amdgcn_rcpf(den), tL), tR) : tL;
+    return fminf(fmin, seg_F32<D>(A, d, ts, lo, hi));
+}
+
+__device__ inline int classify_margin(float m, float band)
+{
+    return m < -band ? kHit : (m > band ? kMiss : kUnsure);
 }
 
 // ------------------------------------------------------------------------
@@ -256,14 +361,7 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff(RmDev rm, const rgg_box *__
         s_bad = 0;
         s_mism = 0;
         s_base = 0;
-        Ctl *c = rm.ctl;
-        c->n_items = 0;
-        c->n_work = 0;
-        c->n_pairs = 0;
-        c->n_outer = 0;
-        c->n_recheck = 0;
-        c->n_visited = 0;
-        c->test_bytes = 0;
+        rm.ctl->n_items = 0;
     }
     __syncthreads();
     for (int64_t base = 0; base < rm.M; base += kDiffBlock) {
@@ -312,7 +410,7 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff(RmDev rm, const rgg_box *__
 }
 
 // ------------------------------------------------------------------------
-// k_cells: touched cells -> work items
+// k_cells: touched cells -> work items (cell, chunk)
 // ------------------------------------------------------------------------
 
 __global__ void __launch_bounds__(kBlock) k_cells(RmDev rm)
@@ -328,367 +426,612 @@ __global__ void __launch_bounds__(kBlock) k_cells(RmDev rm)
                       nz = en.c1[2] - en.c0[2] + 1;
         if (nx <= 0 || ny <= 0 || nz <= 0) continue;
         const int64_t total = (int64_t)nx * ny * nz;
-        for (int64_t k = lane; k < total; k += 64) {
-            const int32_t x = en.c0[0] + (int32_t)(k % nx);
-            const int32_t y = en.c0[1] + (int32_t)((k / nx) % ny);
-            const int32_t z = en.c0[2] + (int32_t)(k / ((int64_t)nx * ny));
-            const int64_t c = ((int64_t)z * rm.gdim[1] + y) * rm.gdim[0] + x;
-            const uint32_t bit = 1u << (c & 31);
-            const uint32_t old = atomicOr(&rm.cell_bits[c >> 5], bit);
-            if (!(old & bit)) {
-                const int32_t n = rm.cell_start[c + 1] - rm.cell_start[c];
-                const int32_t nch = n > 0 ? (n + rm.chunk - 1) / rm.chunk : 1;
-                const int32_t pos = atomicAdd(&rm.ctl->n_items, nch);
-                for (int32_t h = 0; h < nch; ++h)
-                    if (pos + h < rm.items_cap) rm.items[pos + h] = make_int2((int32_t)c, h);
+        for (int64_t base = 0; base < total; base += 64) {
+            const int64_t k = base + lane;
+            int64_t c = 0;
+            int nch = 0;
+            if (k < total) {
+                const int32_t x = en.c0[0] + (int32_t)(k % nx);
+                const int32_t y = en.c0[1] + (int32_t)((k / nx) % ny);
+                const int32_t z = en.c0[2] + (int32_t)(k / ((int64_t)nx * ny));
+                c = ((int64_t)z * rm.gdim[1] + y) * rm.gdim[0] + x;
+                const uint32_t bit = 1u << (c & 31);
+                if (!(atomicOr(&rm.cell_bits[c >> 5], bit) & bit)) {
+                    const int32_t n = rm.cell_start[c + 1] - rm.cell_start[c];
+                    nch = n > 0 ? (n + rm.chunk - 1) / rm.chunk : 1;
+                }
+            }
+            int tot;
+            const int pre = wave_prefix(nch, &tot);
+            if (tot == 0) continue;
+            int pos0 = 0;
+            if (lane == 0) pos0 = atomicAdd(&rm.ctl->n_items, tot);
+            pos0 = __shfl(pos0, 0);
+            // every winner's items are written by the whole wavefront
+            uint64_t wm = __ballot(nch > 0);
+            while (wm) {
+                const int src = __ffsll((unsigned long long)wm) - 1;
+                wm &= wm - 1;
+                const int64_t cw = __shfl((long long)c, src);
+                const int nw_ = __shfl(nch, src);
+                const int pw = pos0 + __shfl(pre, src);
+                for (int h = lane; h < nw_; h += 64)
+                    if (pw + h < rm.items_cap) rm.items[pw + h] = make_int2((int32_t)cw, h);
             }
         }
     }
 }
 
 // ------------------------------------------------------------------------
-// k_grid: scan active cells, queue candidate edges once
+// k_grid: scan the edges of each item, keep those meeting a changed box
 // ------------------------------------------------------------------------
-
-__device__ inline bool overlap3(const float *lo, const float *hi, const float4 &bl, const float4 &bh)
-{
-    return lo[0] <= bh.x && hi[0] >= bl.x && lo[1] <= bh.y && hi[1] >= bl.y && lo[2] <= bh.z &&
-           hi[2] >= bl.z;
-}
 
 __global__ void __launch_bounds__(kBlock) k_grid(RmDev rm)
 {
-    __shared__ float s_lo[kSubCap * 3], s_hi[kSubCap * 3];
-    __shared__ int s_n;
+    __shared__ float s_lo[3][kSubCap], s_hi[3][kSubCap];
+    __shared__ int s_n, s_w[kWaves];
     const Ctl *ctl = rm.ctl;
-    if (ctl->status != RGG_OK) return;
-    const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
-    const int n_chg = ctl->n_chg;
-    const int tid = threadIdx.x, lane = lane_id();
-    const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
     unsigned long long visited = 0;
-    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const int2 item = rm.items[it];
-        const int64_t c = item.x;
-        const int32_t cx = (int32_t)(c % rm.gdim[0]);
-        const int32_t cy = (int32_t)((c / rm.gdim[0]) % rm.gdim[1]);
-        const int32_t cz = (int32_t)(c / ((int64_t)rm.gdim[0] * rm.gdim[1]));
-        __syncthreads();
-        if (tid == 0) {
-            s_n = 0;
-            if (item.y == 0) atomicAnd(&rm.cell_bits[c >> 5], ~(1u << (c & 31)));
-        }
-        __syncthreads();
-        for (int j = tid; j < n_chg; j += kBlock) {
-            const ChgEntry &en = rm.chg[j];
-            if (cx >= en.c0[0] && cx <= en.c1[0] && cy >= en.c0[1] && cy <= en.c1[1] &&
-                cz >= en.c0[2] && cz <= en.c1[2]) {
-                const int s = atomicAdd(&s_n, 1);
-                if (s < kSubCap)
+    if (ctl->status == RGG_OK) {
+        const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
+        const int n_chg = ctl->n_chg;
+        const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+        const bool single = rm.ncells == 1;
+        const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
+        for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+            const int2 item = rm.items[it];
+            const int64_t c = item.x;
+            const int32_t cx = (int32_t)(c % rm.gdim[0]);
+            const int32_t cy = (int32_t)((c / rm.gdim[0]) % rm.gdim[1]);
+            const int32_t cz = (int32_t)(c / ((int64_t)rm.gdim[0] * rm.gdim[1]));
+            __syncthreads();
+            if (tid == 0) {
+                s_n = 0;
+                if (item.y == 0) atomicAnd(&rm.cell_bits[c >> 5], ~(1u << (c & 31)));
+            }
+            __syncthreads();
+            // the changed entries whose cell range contains this cell
+            for (int j0 = 0; j0 < n_chg; j0 += kBlock) {
+                const int j = j0 + tid;
+                bool in = false;
+                if (j < n_chg) {
+                    const ChgEntry &en = rm.chg[j];
+                    in = single || (cx >= en.c0[0] && cx <= en.c1[0] && cy >= en.c0[1] &&
+                                    cy <= en.c1[1] && cz >= en.c0[2] && cz <= en.c1[2]);
+                }
+                const uint64_t m = __ballot(in);
+                if (lane == 0) s_w[wv] = __popcll(m);
+                __syncthreads();
+                int off = s_n, tot = 0;
+                for (int w = 0; w < kWaves; ++w) {
+                    off += w < wv ? s_w[w] : 0;
+                    tot += s_w[w];
+                }
+                const int s = off + __popcll(m & lanes_below());
+                if (in && s < kSubCap) {
+                    const ChgEntry &en = rm.chg[j];
                     for (int k = 0; k < 3; ++k) {
-                        s_lo[k * kSubCap + s] = en.lo32[k];
-                        s_hi[k * kSubCap + s] = en.hi32[k];
+                        s_lo[k][s] = en.lo32[k];
+                        s_hi[k][s] = en.hi32[k];
                     }
-            }
-        }
-        __syncthreads();
-        const int ns = s_n;
-        const int64_t beg = (int64_t)rm.cell_start[c] + (int64_t)item.y * rm.chunk;
-        const int64_t end = min((int64_t)rm.cell_start[c + 1], beg + rm.chunk);
-        if (tid == 0) visited += (unsigned long long)max((int64_t)0, end - beg);
-        for (int64_t j = beg + tid; j < end; j += kBlock) {
-            const int32_t e = rm.cell_edges[j];
-            const float4 bl = aabb[2 * (int64_t)e], bh = aabb[2 * (int64_t)e + 1];
-            bool hit = false;
-            if (ns <= kSubCap) {
-                for (int s = 0; s < ns && !hit; ++s) {
-                    const float lo[3] = {s_lo[s], s_lo[kSubCap + s], s_lo[2 * kSubCap + s]};
-                    const float hi[3] = {s_hi[s], s_hi[kSubCap + s], s_hi[2 * kSubCap + s]};
-                    hit = overlap3(lo, hi, bl, bh);
                 }
-            } else {
-                for (int s = 0; s < n_chg && !hit; ++s) {
-                    const ChgEntry &en = rm.chg[s];
-                    hit = cx >= en.c0[0] && cx <= en.c1[0] && cy >= en.c0[1] && cy <= en.c1[1] &&
-                          cz >= en.c0[2] && cz <= en.c1[2] && overlap3(en.lo32, en.hi32, bl, bh);
+                __syncthreads();
+                if (tid == 0) s_n += tot;
+                __syncthreads();
+            }
+            const int ns = s_n;
+            const int64_t beg = (int64_t)rm.cell_start[c] + (int64_t)item.y * rm.chunk;
+            const int64_t end = min((int64_t)rm.cell_start[c + 1], beg + rm.chunk);
+            // one edge per thread (chunk == block size)
+            const int64_t j = beg + tid;
+            bool keep = false;
+            int32_t e = 0;
+            if (j < end) {
+                e = rm.cell_edges[j];
+                const float4 bl = aabb[2 * (int64_t)e], bh = aabb[2 * (int64_t)e + 1];
+                bool hit = false;
+                if (ns <= kSubCap) {
+                    for (int s = 0; s < ns && !hit; ++s) {
+                        const float lo[3] = {s_lo[0][s], s_lo[1][s], s_lo[2][s]};
+                        const float hi[3] = {s_hi[0][s], s_hi[1][s], s_hi[2][s]};
+                        hit = overlap3(lo, hi, bl, bh);
+                    }
+                } else {
+                    for (int s = 0; s < n_chg && !hit; ++s) {
+                        const ChgEntry &en = rm.chg[s];
+                        hit = (single || (cx >= en.c0[0] && cx <= en.c1[0] && cy >= en.c0[1] &&
+                                          cy <= en.c1[1] && cz >= en.c0[2] && cz <= en.c1[2])) &&
+                              overlap3(en.lo32, en.hi32, bl, bh);
+                    }
+                }
+                if (hit) {
+                    if (single) {
+                        keep = true;
+                    } else {   // an edge registered in several active cells is kept once
+                        const uint32_t bit = 1u << (e & 31);
+                        keep = !(atomicOr(&rm.edge_bits[e >> 5], bit) & bit);
+                    }
                 }
             }
-            bool first = false;
-            if (hit) {
-                const uint32_t bit = 1u << (e & 31);
-                first = !(atomicOr(&rm.edge_bits[e >> 5], bit) & bit);
+            const uint64_t m = __ballot(keep);
+            if (lane == 0) s_w[wv] = __popcll(m);
+            __syncthreads();
+            int off = 0, tot = 0;
+            for (int w = 0; w < kWaves; ++w) {
+                off += w < wv ? s_w[w] : 0;
+                tot += s_w[w];
             }
-            const uint64_t m = __ballot(first);
-            if (m) {
-                const int leader = __ffsll((unsigned long long)m) - 1;
-                int base = 0;
-                if (lane == leader) base = atomicAdd(&rm.ctl->n_work, __popcll(m));
-                base = __shfl(base, leader);
-                if (first) rm.work[base + __popcll(m & lanes_below())] = e;
+            if (keep) rm.work[beg + off + __popcll(m & lanes_below())] = e;
+            if (tid == 0) {
+                rm.item_cnt[it] = tot;
+                visited += (unsigned long long)max((int64_t)0, end - beg);
             }
         }
     }
-    if (tid == 0 && visited) atomicAdd(&rm.ctl->n_visited, visited);
+    if (threadIdx.x == 0) rm.blk_stats[blockIdx.x * kStats + 4] = visited;
 }
 
 // ------------------------------------------------------------------------
-// k_classify: one wavefront per candidate edge
+// candidates of one block: items it = blockIdx.x, + gridDim.x, ...; within
+// an item the wavefronts take candidates wv, wv + kWaves, ...
 // ------------------------------------------------------------------------
 
-template <int D>
-struct Lds {
-    float lo32[3][kTile], hi32[3][kTile];
-    float sbox[kTile];
-    int sign[kTile];
-    double lo64[3][kTile], hi64[3][kTile];
-    int act[kWaves][kTile];
-    uint8_t st[kWaves][kTile];
+struct Cursor {
+    int it, k, cnt;
+    int64_t beg;
 };
 
-// exact (binary64) outer test of one pair; every lane returns the same value
-template <int D>
-__device__ bool outer64(const RmDev &rm, int64_t e, const double *lo, const double *hi)
+__device__ inline bool cursor_next(const RmDev &rm, int n_items, Cursor &cu, int wv, int64_t *slot)
 {
-    const int B = rm.B, lane = lane_id();
-    bool hit = false;
-    if (lane < B) {
-        const double *cp = rm.cap64 + e * (2 * D + 1) * B;
-        double A[D], Bp[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            A[k] = cp[k * B + lane];
-            Bp[k] = cp[(D + k) * B + lane];
+    for (;;) {
+        if (cu.it >= n_items) return false;
+        if (cu.k < 0) {
+            const int2 item = rm.items[cu.it];
+            cu.cnt = rm.item_cnt[cu.it];
+            cu.beg = (int64_t)rm.cell_start[item.x] + (int64_t)item.y * rm.chunk;
+            cu.k = wv;
         }
-        const double R = cp[2 * D * B + lane];
-        hit = segbox_fmin<double, D>(A, Bp, lo, hi) <= R * R;
+        if (cu.k < cu.cnt) {
+            *slot = cu.beg + cu.k;
+            cu.k += kWaves;
+            return true;
+        }
+        cu.it += gridDim.x;
+        cu.k = -1;
     }
-    return __ballot(hit) != 0;
 }
 
-// exact (binary64) inner test of one pair
+// ------------------------------------------------------------------------
+// binary64 classification of one edge against entries [t0, t0+nt)
+// (FP64 mode, and the re-test of the FP32 mode); every lane returns the
+// same counter deltas
+// ------------------------------------------------------------------------
+
 template <int D>
-__device__ bool inner64(const RmDev &rm, int64_t e, const double *lo, const double *hi,
-                        unsigned long long *bytes)
+__device__ int2 edge_exact(const RmDev &rm, int64_t e, const ChgEntry *__restrict__ chg, int t0, int nt,
+                           int *act, uint8_t *st, unsigned long long *n_pairs,
+                           unsigned long long *n_outer, unsigned long long *bytes)
 {
-    const int B = rm.B, lane = lane_id();
-    const int64_t s0 = rm.soff[e], P = rm.soff[e + 1] - s0;
-    const double *base = rm.samp64 + D * s0;
-    const int step = 64 % B, lane_b = lane % B;
-    int cmod = 0;   // c mod B
-    for (int64_t c = 0; c < P; c += 64) {
-        const int64_t n = c + lane;
+    const int lane = lane_id(), B = rm.B;
+    const int G = 64 / B, slot = lane / B, ci = lane % B;
+    const uint64_t gmask = B == 64 ? ~0ull : ((1ull << B) - 1ull);
+    const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
+    const float4 bl = aabb[2 * e], bh = aabb[2 * e + 1];
+    int n_act = 0;
+    for (int b0 = 0; b0 < nt; b0 += 64) {
+        const int j = b0 + lane;
+        const bool ov = j < nt && overlap3(chg[t0 + j].lo32, chg[t0 + j].hi32, bl, bh);
+        const uint64_t m = __ballot(ov);
+        if (ov) act[n_act + __popcll(m & lanes_below())] = t0 + j;
+        n_act += __popcll(m);
+    }
+    *bytes += 32;
+    wave_sync();
+    if (n_act == 0) return make_int2(0, 0);
+    *n_pairs += n_act;
+    // outer test: lane (slot, ci) takes capsule ci of pair slot
+    const double *cp = rm.cap64 + e * (2 * D + 1) * B;
+    double A[D], Bp[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        A[k] = cp[k * B + ci];
+        Bp[k] = cp[(D + k) * B + ci];
+    }
+    const double R = cp[2 * D * B + ci];
+    *bytes += (unsigned long long)((2 * D + 1) * B * 8);
+    int pend = 0;
+    for (int a0 = 0; a0 < n_act; a0 += G) {
+        const int a = a0 + slot;
         bool hit = false;
-        int ir = cmod + lane_b;
+        if (slot < G && a < n_act) {
+            const ChgEntry &en = chg[act[a]];
+            double lo[D], hi[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                lo[k] = en.lo[k];
+                hi[k] = en.hi[k];
+            }
+            hit = segbox64<D>(A, Bp, lo, hi) <= R * R;
+        }
+        const uint64_t hm = __ballot(hit);
+        if (lane < G && a0 + lane < n_act) st[a0 + lane] = (hm & (gmask << (lane * B))) ? kCHit : 0;
+        for (int s = 0; s < G && a0 + s < n_act; ++s) pend += ((hm >> (s * B)) & gmask) ? 1 : 0;
+    }
+    wave_sync();
+    *n_outer += pend;
+    // inner test
+    const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
+    const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
+    const double *sb = rm.samp64 + D * s0;
+    const int step = 64 % B;
+    int cmod = 0;
+    for (int64_t c = 0; c < P && pend > 0; c += 64) {
+        const int64_t n = c + lane;
+        int ir = cmod + ci;
         ir = ir >= B ? ir - B : ir;
         cmod += step;
         cmod = cmod >= B ? cmod - B : cmod;
-        if (n < P) {
-            double p[D];
+        const bool valid = n < P;
+        double p[D];
+        double r = 0.0;
+        if (valid) {
 #pragma unroll
-            for (int k = 0; k < D; ++k) p[k] = base[k * P + n];
-            const double r = rm.rad64[ir];
-            hit = point_box_d2<double, D>(p, lo, hi) <= r * r;
+            for (int k = 0; k < D; ++k) p[k] = sb[k * P + n];
+            r = rm.rad64[ir];
         }
         *bytes += (unsigned long long)(min((int64_t)64, P - c) * D * 8);
-        if (__ballot(hit)) return true;
+        for (int a = 0; a < n_act; ++a) {
+            const uint8_t s = st[a];
+            if (s != kCHit) continue;
+            bool hit = false;
+            if (valid) {
+                const ChgEntry &en = chg[act[a]];
+                double lo[D], hi[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    lo[k] = en.lo[k];
+                    hi[k] = en.hi[k];
+                }
+                hit = point_box64<D>(p, lo, hi) <= r * r;
+            }
+            if (__ballot(hit)) {
+                st[a] = kCHit | kSHit;
+                --pend;
+            }
+            wave_sync();
+        }
     }
-    return false;
+    int dC = 0, dS = 0;
+    for (int a = 0; a < n_act; ++a) {
+        const uint8_t s = st[a];
+        const int sign = chg[act[a]].sign;
+        dC += (s & kCHit) ? sign : 0;
+        dS += (s & kSHit) ? sign : 0;
+    }
+    wave_sync();
+    return make_int2(dC, dS);
 }
 
-template <int D, bool kMixed>
-__global__ void __launch_bounds__(kBlock) k_classify(RmDev rm)
-{
-    using T = typename std::conditional<kMixed, float, double>::type;
-    __shared__ Lds<D> L;
-    const Ctl *ctl = rm.ctl;
-    if (ctl->status != RGG_OK) return;
-    const int n_chg = ctl->n_chg, n_work = ctl->n_work;
-    if (n_chg == 0 || n_work == 0) return;
-    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
-    const int B = rm.B;
-    const int G = 64 / B;                 // pairs per capsule pass
-    const int slot = lane / B, ci = lane % B;
-    const uint64_t gmask = B == 64 ? ~0ull : ((1ull << B) - 1ull);
-    const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
-    const T *cap = kMixed ? (const T *)rm.cap32 : (const T *)rm.cap64;
-    const T *samp = kMixed ? (const T *)rm.samp32 : (const T *)rm.samp64;
-    int *act = L.act[wv];
-    uint8_t *st = L.st[wv];
-    unsigned long long n_pairs = 0, n_outer = 0, n_re = 0, bytes = 0;
+// ------------------------------------------------------------------------
+// k_classify, FP64 mode
+// ------------------------------------------------------------------------
 
-    for (int t0 = 0; t0 < n_chg; t0 += kTile) {
-        const int nt = min(kTile, n_chg - t0);
-        __syncthreads();
-        for (int j = tid; j < nt; j += kBlock) {
-            const ChgEntry &en = rm.chg[t0 + j];
-            for (int k = 0; k < 3; ++k) {
-                L.lo32[k][j] = en.lo32[k];
-                L.hi32[k][j] = en.hi32[k];
-                L.lo64[k][j] = en.lo[k];
-                L.hi64[k][j] = en.hi[k];
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_classify64(RmDev rm)
+{
+    __shared__ int s_act[kWaves][kTile];
+    __shared__ uint8_t s_st[kWaves][kTile];
+    const Ctl *ctl = rm.ctl;
+    unsigned long long n_pairs = 0, n_outer = 0, bytes = 0;
+    if (ctl->status == RGG_OK) {
+        const int n_chg = ctl->n_chg;
+        const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
+        const int wv = threadIdx.x >> 6;
+        Cursor cu = {(int)blockIdx.x, -1, 0, 0};
+        int64_t slot;
+        while (cursor_next(rm, n_items, cu, wv, &slot)) {
+            const int64_t e = rm.work[slot];
+            int2 d = make_int2(0, 0);
+            for (int t0 = 0; t0 < n_chg; t0 += kTile) {
+                int2 x = edge_exact<D>(rm, e, rm.chg, t0, min(kTile, n_chg - t0), s_act[wv], s_st[wv],
+                                       &n_pairs, &n_outer, &bytes);
+                d.x += x.x;
+                d.y += x.y;
             }
-            L.sbox[j] = en.sbox;
-            L.sign[j] = en.sign;
-        }
-        __syncthreads();
-        for (int w = blockIdx.x * kWaves + wv; w < n_work; w += gridDim.x * kWaves) {
-            const int64_t e = rm.work[w];
-            const float4 bl = aabb[2 * e], bh = aabb[2 * e + 1];
-            // box pretest against the staged entries
-            int n_act = 0;
-            for (int b0 = 0; b0 < nt; b0 += 64) {
-                const int j = b0 + lane;
-                bool ov = false;
-                if (j < nt) {
-                    const float lo[3] = {L.lo32[0][j], L.lo32[1][j], L.lo32[2][j]};
-                    const float hi[3] = {L.hi32[0][j], L.hi32[1][j], L.hi32[2][j]};
-                    ov = overlap3(lo, hi, bl, bh);
-                }
-                const uint64_t m = __ballot(ov);
-                if (ov) act[n_act + __popcll(m & lanes_below())] = j;
-                n_act += __popcll(m);
-            }
-            bytes += 32;
-            if (n_act == 0) continue;
-            wave_sync();
-            n_pairs += n_act;
-            // outer test: lane (slot, ci) tests capsule ci against pair slot
-            const T *cp = cap + e * (2 * D + 1) * B;
-            T A[D], Bp[D];
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                A[k] = cp[k * B + ci];
-                Bp[k] = cp[(D + k) * B + ci];
-            }
-            const T R = cp[2 * D * B + ci];
-            bytes += (unsigned long long)((2 * D + 1) * B * sizeof(T));
-            int pend = 0;
-            for (int a0 = 0; a0 < n_act; a0 += G) {
-                const int a = a0 + slot;
-                int cls = kMiss;
-                if (slot < G && a < n_act) {
-                    const int j = act[a];
-                    T lo[D], hi[D];
-#pragma unroll
-                    for (int k = 0; k < D; ++k) {
-                        lo[k] = kMixed ? (T)L.lo32[k][j] : (T)L.lo64[k][j];
-                        hi[k] = kMixed ? (T)L.hi32[k][j] : (T)L.hi64[k][j];
-                    }
-                    const T m = segbox_fmin<T, D>(A, Bp, lo, hi) - R * R;
-                    if (kMixed) {
-                        const float s = fmaxf(bl.w, L.sbox[j]);
-                        const float band = rm.band_rel * s * s;
-                        cls = m < -band ? kHit : (m > band ? kMiss : kUnsure);
-                    } else {
-                        cls = m <= T(0) ? kHit : kMiss;
-                    }
-                }
-                const uint64_t hm = __ballot(cls == kHit), um = __ballot(cls == kUnsure);
-                if (lane < G && a0 + lane < n_act) {
-                    const uint64_t g = gmask << (lane * B);
-                    st[a0 + lane] = (hm & g) ? kCHit : ((um & g) ? kCUnsure : 0);
-                }
-                // count how many pairs need the inner test
-                for (int s = 0; s < G && a0 + s < n_act; ++s)
-                    pend += ((hm >> (s * B)) & gmask) ? 1 : 0;
-            }
-            wave_sync();
-            // inner test over chunks of 64 sphere samples, all pending pairs per chunk
-            const int64_t s0 = rm.soff[e], P = rm.soff[e + 1] - s0;
-            const T *sb = samp + D * s0;
-            const int step = 64 % B;
-            int cmod = 0;   // c mod B
-            for (int64_t c = 0; c < P && pend > 0; c += 64) {
-                const int64_t n = c + lane;
-                const bool valid = n < P;
-                int ir = cmod + ci;
-                ir = ir >= B ? ir - B : ir;
-                cmod += step;
-                cmod = cmod >= B ? cmod - B : cmod;
-                T p[D];
-                T r2 = T(0);
-                if (valid) {
-#pragma unroll
-                    for (int k = 0; k < D; ++k) p[k] = sb[k * P + n];
-                    r2 = kMixed ? (T)rm.rad2_32[ir] : (T)(rm.rad64[ir] * rm.rad64[ir]);
-                }
-                bytes += (unsigned long long)(min((int64_t)64, P - c) * D * sizeof(T));
-                for (int a = 0; a < n_act; ++a) {
-                    uint8_t s = st[a];
-                    if (!(s & kCHit) || (s & kSHit)) continue;
-                    const int j = act[a];
-                    int cls = kMiss;
-                    if (valid) {
-                        T lo[D], hi[D];
-#pragma unroll
-                        for (int k = 0; k < D; ++k) {
-                            lo[k] = kMixed ? (T)L.lo32[k][j] : (T)L.lo64[k][j];
-                            hi[k] = kMixed ? (T)L.hi32[k][j] : (T)L.hi64[k][j];
-                        }
-                        const T m = point_box_d2<T, D>(p, lo, hi) - r2;
-                        if (kMixed) {
-                            const float sc = fmaxf(bl.w, L.sbox[j]);
-                            const float band = rm.band_rel * sc * sc;
-                            cls = m < -band ? kHit : (m > band ? kMiss : kUnsure);
-                        } else {
-                            cls = m <= T(0) ? kHit : kMiss;
-                        }
-                    }
-                    const uint64_t hm = __ballot(cls == kHit), um = __ballot(cls == kUnsure);
-                    if (hm) {
-                        s |= kSHit;
-                        --pend;
-                    } else if (um) {
-                        s |= kSUnsure;
-                    }
-                    st[a] = s;
-                    wave_sync();
-                }
-            }
-            // resolve every pair; unsure ones are re-decided in binary64
-            int dC = 0, dS = 0;
-            for (int a = 0; a < n_act; ++a) {
-                const uint8_t s = st[a];
-                const int j = act[a];
-                int C = 0, S = 0;
-                if (s & kCUnsure) {
-                    double lo3[3] = {L.lo64[0][j], L.lo64[1][j], L.lo64[2][j]};
-                    double hi3[3] = {L.hi64[0][j], L.hi64[1][j], L.hi64[2][j]};
-                    C = outer64<D>(rm, e, lo3, hi3) ? 1 : 0;
-                    S = C && inner64<D>(rm, e, lo3, hi3, &bytes) ? 1 : 0;
-                    bytes += (unsigned long long)((2 * D + 1) * B * 8);
-                    ++n_re;
-                } else if (s & kCHit) {
-                    C = 1;
-                    if (s & kSHit) {
-                        S = 1;
-                    } else if (s & kSUnsure) {
-                        double lo3[3] = {L.lo64[0][j], L.lo64[1][j], L.lo64[2][j]};
-                        double hi3[3] = {L.hi64[0][j], L.hi64[1][j], L.hi64[2][j]};
-                        S = inner64<D>(rm, e, lo3, hi3, &bytes) ? 1 : 0;
-                        ++n_re;
-                    }
-                }
-                n_outer += C;
-                dC += L.sign[j] * C;
-                dS += L.sign[j] * S;
-            }
-            if (lane == 0 && (dC != 0 || dS != 0)) {
+            if (lane_id() == 0 && (d.x || d.y)) {
                 int2 v = rm.cnt[e];
-                v.x += dC;
-                v.y += dS;
+                v.x += d.x;
+                v.y += d.y;
                 rm.cnt[e] = v;
             }
             bytes += 16;
-            wave_sync();
         }
     }
+    // per-block partials: waves of the block add into LDS, thread 0 stores
+    __shared__ unsigned long long s_acc[3];
+    if (threadIdx.x < 3) s_acc[threadIdx.x] = 0;
+    __syncthreads();
+    if (lane_id() == 0) {
+        atomicAdd(&s_acc[0], n_pairs);
+        atomicAdd(&s_acc[1], n_outer);
+        atomicAdd(&s_acc[2], bytes);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long *bs = rm.blk_stats + blockIdx.x * kStats;
+        bs[0] = s_acc[0];
+        bs[1] = s_acc[1];
+        bs[2] = 0;
+        bs[3] = s_acc[2];
+    }
+}
+
+// ------------------------------------------------------------------------
+// k_classify, FP32 mode: one wavefront per candidate edge
+// ------------------------------------------------------------------------
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_classify32(RmDev rm)
+{
+    __shared__ float s_lo[3][kTile], s_hi[3][kTile];
+    __shared__ float s_sb[kTile];
+    __shared__ int s_sign[kTile];
+    __shared__ int s_act[kWaves][kTile];
+    __shared__ uint8_t s_st[kWaves][kTile];
+    const Ctl *ctl = rm.ctl;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    unsigned long long n_pairs = 0, n_outer = 0, bytes = 0;
+    if (ctl->status == RGG_OK) {
+        const int n_chg = ctl->n_chg;
+        const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
+        const int B = rm.B;
+        const int G = 64 / B, slot = lane / B, ci = lane % B;
+        const uint64_t gmask = B == 64 ? ~0ull : ((1ull << B) - 1ull);
+        const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
+        const float band_rel = rm.band_rel;
+        int *act = s_act[wv];
+        uint8_t *st = s_st[wv];
+        for (int t0 = 0, tile = 0; t0 < n_chg; t0 += kTile, ++tile) {
+            const int nt = min(kTile, n_chg - t0);
+            __syncthreads();
+            for (int j = tid; j < nt; j += kBlock) {
+                const ChgEntry &en = rm.chg[t0 + j];
+                for (int k = 0; k < 3; ++k) {
+                    s_lo[k][j] = en.lo32[k];
+                    s_hi[k][j] = en.hi32[k];
+                }
+                s_sb[j] = en.sbox;
+                s_sign[j] = en.sign;
+            }
+            __syncthreads();
+            Cursor cu = {(int)blockIdx.x, -1, 0, 0};
+            int64_t wslot;
+            while (cursor_next(rm, n_items, cu, wv, &wslot)) {
+                const int64_t e = rm.work[wslot];
+                // issue every load of this edge up front
+                const float4 bl = aabb[2 * e], bh = aabb[2 * e + 1];
+                const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
+                const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
+                const float *cp = rm.cap32 + e * (2 * D + 1) * B;
+                float A[D], Bq[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    A[k] = cp[k * B + ci];
+                    Bq[k] = cp[(D + k) * B + ci];
+                }
+                const float R = cp[2 * D * B + ci];
+                const float *sb = rm.samp32 + D * s0;
+                float p[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) p[k] = lane < P ? sb[k * P + lane] : 0.0f;
+                // pretest against the staged entries
+                int n_act = 0;
+                for (int b0 = 0; b0 < nt; b0 += 64) {
+                    const int j = b0 + lane;
+                    bool ov = false;
+                    if (j < nt) {
+                        const float lo[3] = {s_lo[0][j], s_lo[1][j], s_lo[2][j]};
+                        const float hi[3] = {s_hi[0][j], s_hi[1][j], s_hi[2][j]};
+                        ov = overlap3(lo, hi, bl, bh);
+                    }
+                    const uint64_t m = __ballot(ov);
+                    if (ov) act[n_act + __popcll(m & lanes_below())] = j;
+                    n_act += __popcll(m);
+                }
+                bytes += 32;
+                uint32_t unsure_tiles = 0;
+                if (n_act > 0) {
+                    wave_sync();
+                    n_pairs += n_act;
+                    bytes += (unsigned long long)((2 * D + 1) * B * 4);
+                    // outer test: quick tests first (capsule box separated ->
+                    // miss; an end sphere meets the box -> hit), the full
+                    // segment-box minimum only where neither decides
+                    const float R2 = R * R;
+                    int pend = 0;
+                    bool any_unsure = false;
+                    for (int a0 = 0; a0 < n_act; a0 += G) {
+                        const int a = a0 + slot;
+                        int cls = kMiss;
+                        float lo[D], hi[D], band = 0.0f;
+                        if (slot < G && a < n_act) {
+                            const int j = act[a];
+#pragma unroll
+                            for (int k = 0; k < D; ++k) {
+                                lo[k] = s_lo[k][j];
+                                hi[k] = s_hi[k][j];
+                            }
+                            const float s = fmaxf(bl.w, s_sb[j]);
+                            band = band_rel * s * s;
+                            float sep = 0.0f;
+#pragma unroll
+                            for (int k = 0; k < D; ++k)
+                                sep = fmaxf(sep, fmaxf(lo[k] - fmaxf(A[k], Bq[k]), fminf(A[k], Bq[k]) - hi[k]));
+                            const float m_sep = sep * sep - R2;
+                            const float m_end = fminf(point_box32<D>(A, lo, hi), point_box32<D>(Bq, lo, hi)) - R2;
+                            cls = (sep > 0.0f && m_sep > band) ? kMiss : (m_end < -band ? kHit : kOpen);
+                        }
+                        if (__ballot(cls == kOpen)) {
+                            if (cls == kOpen) cls = classify_margin(segbox32<D>(A, Bq, lo, hi) - R2, band);
+                        }
+                        const uint64_t hm = __ballot(cls == kHit), um = __ballot(cls == kUnsure);
+                        if (lane < G && a0 + lane < n_act) {
+                            const uint64_t g = gmask << (lane * B);
+                            st[a0 + lane] = (hm & g) ? kCHit : ((um & g) ? kCUnsure : 0);
+                        }
+                        for (int s = 0; s < G && a0 + s < n_act; ++s) {
+                            const uint64_t g = gmask << (s * B);
+                            pend += (hm & g) ? 1 : 0;
+                            any_unsure |= !(hm & g) && (um & g);
+                        }
+                    }
+                    wave_sync();
+                    n_outer += pend;
+                    // inner test over chunks of 64 sphere samples; chunk 0 is
+                    // already loaded, the next chunk is fetched while testing
+                    const int step = 64 % B;
+                    int cmod = 0;
+                    float pn[D];
+                    for (int64_t c = 0; c < P && pend > 0; c += 64) {
+                        const int64_t n = c + lane;
+                        const bool valid = n < P;
+                        const bool more = c + 64 < P;
+                        if (more) {
+#pragma unroll
+                            for (int k = 0; k < D; ++k) pn[k] = n + 64 < P ? sb[k * P + n + 64] : 0.0f;
+                        }
+                        int ir = cmod + ci;
+                        ir = ir >= B ? ir - B : ir;
+                        cmod += step;
+                        cmod = cmod >= B ? cmod - B : cmod;
+                        const float r2 = rm.rad2_32[ir];
+                        bytes += (unsigned long long)(min((int64_t)64, P - c) * D * 4);
+                        for (int a = 0; a < n_act; ++a) {
+                            uint8_t s = st[a];
+                            if (!(s & kCHit) || (s & kSHit)) continue;
+                            const int j = act[a];
+                            int cls = kMiss;
+                            if (valid) {
+                                float lo[D], hi[D];
+#pragma unroll
+                                for (int k = 0; k < D; ++k) {
+                                    lo[k] = s_lo[k][j];
+                                    hi[k] = s_hi[k][j];
+                                }
+                                const float sc = fmaxf(bl.w, s_sb[j]);
+                                cls = classify_margin(point_box32<D>(p, lo, hi) - r2, band_rel * sc * sc);
+                            }
+                            const uint64_t hm = __ballot(cls == kHit), um = __ballot(cls == kUnsure);
+                            if (hm) {
+                                s |= kSHit;
+                                --pend;
+                            } else if (um) {
+                                s |= kSUnsure;
+                            }
+                            st[a] = s;
+                            wave_sync();
+                        }
+                        if (more) {
+#pragma unroll
+                            for (int k = 0; k < D; ++k) p[k] = pn[k];
+                        }
+                    }
+                    // resolve: certain pairs update the counters here; a tile
+                    // holding any unsure pair is left whole to the re-test
+                    int dC = 0, dS = 0;
+                    for (int a = 0; a < n_act; ++a) {
+                        const uint8_t s = st[a];
+                        const int sign = s_sign[act[a]];
+                        any_unsure |= (s & kCHit) && !(s & kSHit) && (s & kSUnsure);
+                        dC += (s & kCHit) ? sign : 0;
+                        dS += (s & kSHit) ? sign : 0;
+                    }
+                    if (any_unsure) {
+                        unsure_tiles = 1u << tile;
+                    } else if (lane == 0 && (dC || dS)) {
+                        int2 v = rm.cnt[e];
+                        v.x += dC;
+                        v.y += dS;
+                        rm.cnt[e] = v;
+                    }
+                    bytes += 16;
+                    wave_sync();
+                }
+                if (lane == 0) rm.unsure[wslot] = tile == 0 ? unsure_tiles : (rm.unsure[wslot] | unsure_tiles);
+            }
+        }
+    }
+    __shared__ unsigned long long s_acc[3];
+    if (threadIdx.x < 3) s_acc[threadIdx.x] = 0;
+    __syncthreads();
     if (lane == 0) {
-        Ctl *c = rm.ctl;
-        if (n_pairs) atomicAdd(&c->n_pairs, n_pairs);
-        if (n_outer) atomicAdd(&c->n_outer, n_outer);
-        if (n_re) atomicAdd(&c->n_recheck, n_re);
-        if (bytes) atomicAdd(&c->test_bytes, bytes);
+        atomicAdd(&s_acc[0], n_pairs);
+        atomicAdd(&s_acc[1], n_outer);
+        atomicAdd(&s_acc[2], bytes);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long *bs = rm.blk_stats + blockIdx.x * kStats;
+        bs[0] = s_acc[0];
+        bs[1] = s_acc[1];
+        bs[2] = 0;
+        bs[3] = s_acc[2];
+    }
+}
+
+// ------------------------------------------------------------------------
+// k_recheck: binary64 re-test of the tiles the FP32 filter left unsure.
+// Same block/wave -> candidate mapping as k_classify32.
+// ------------------------------------------------------------------------
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_recheck(RmDev rm)
+{
+    __shared__ int s_act[kWaves][kTile];
+    __shared__ uint8_t s_st[kWaves][kTile];
+    const Ctl *ctl = rm.ctl;
+    if (ctl->status != RGG_OK) return;
+    const int n_chg = ctl->n_chg;
+    const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
+    const int wv = threadIdx.x >> 6;
+    unsigned long long n_re = 0, n_pairs = 0, n_outer = 0, bytes = 0;
+    Cursor cu = {(int)blockIdx.x, -1, 0, 0};
+    int64_t slot;
+    while (cursor_next(rm, n_items, cu, wv, &slot)) {
+        uint32_t mask = rm.unsure[slot];
+        if (!mask) continue;
+        const int64_t e = rm.work[slot];
+        int2 d = make_int2(0, 0);
+        while (mask) {
+            const int tile = __ffs(mask) - 1;
+            mask &= mask - 1;
+            const int t0 = tile * kTile;
+            int2 x = edge_exact<D>(rm, e, rm.chg, t0, min(kTile, n_chg - t0), s_act[wv], s_st[wv],
+                                   &n_pairs, &n_outer, &bytes);
+            d.x += x.x;
+            d.y += x.y;
+        }
+        n_re += 1;
+        if (lane_id() == 0 && (d.x || d.y)) {
+            int2 v = rm.cnt[e];
+            v.x += d.x;
+            v.y += d.y;
+            rm.cnt[e] = v;
+        }
+    }
+    __shared__ unsigned long long s_acc[2];
+    if (threadIdx.x < 2) s_acc[threadIdx.x] = 0;
+    __syncthreads();
+    (void)n_re;
+    if (lane_id() == 0) {
+        atomicAdd(&s_acc[0], n_pairs);   // pairs re-decided in binary64
+        atomicAdd(&s_acc[1], bytes);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long *bs = rm.blk_stats + blockIdx.x * kStats;
+        bs[2] = s_acc[0];
+        bs[3] += s_acc[1];
     }
 }
 
@@ -748,6 +1091,7 @@ __global__ void __launch_bounds__(kBlock) k_write(RmDev rm, int64_t *gray, int64
 {
     __shared__ int s_w[kWaves];
     __shared__ int s_wt[kWaves];
+    __shared__ unsigned long long s_st[kStats];
     const int status = force ? RGG_OK : rm.ctl->status;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     int pre = 0;
@@ -771,42 +1115,41 @@ __global__ void __launch_bounds__(kBlock) k_write(RmDev rm, int64_t *gray, int64
         if (g && status == RGG_OK && gray && pos < cap) gray[pos] = e;
         off += tot;
     }
-    if (tid == 0 && res && blockIdx.x == gridDim.x - 1) {
-        if (force) {
-            res->n_gray = off;
-        } else {
-            const Ctl *c = rm.ctl;
-            res->n_gray = status == RGG_OK ? off : 0;
-            res->n_candidate_edges = c->n_work;
-            res->n_pairs = (int64_t)c->n_pairs;
-            res->n_outer_hits = (int64_t)c->n_outer;
-            res->n_rechecked = (int64_t)c->n_recheck;
-            res->n_cells_visited = (int64_t)c->n_visited;
-            res->test_bytes = (int64_t)c->test_bytes;
-        }
+    if (blockIdx.x != gridDim.x - 1 || !res) return;
+    if (force) {
+        if (tid == 0) res->n_gray = off;
+        return;
+    }
+    // the last block also folds the per-block statistics
+    if (tid < kStats) s_st[tid] = 0;
+    __syncthreads();
+    unsigned long long acc[kStats] = {0, 0, 0, 0, 0};
+    for (int b = tid; b < kStatBlocks; b += kBlock)
+        for (int k = 0; k < kStats; ++k) acc[k] += rm.blk_stats[b * kStats + k];
+    for (int k = 0; k < kStats; ++k) atomicAdd(&s_st[k], acc[k]);
+    __syncthreads();
+    if (tid == 0) {
+        int64_t cand = 0;
+        res->n_gray = status == RGG_OK ? off : 0;
+        res->n_pairs = (int64_t)s_st[0];
+        res->n_outer_hits = (int64_t)s_st[1];
+        res->n_rechecked = (int64_t)s_st[2];
+        res->test_bytes = (int64_t)s_st[3];
+        res->n_cells_visited = (int64_t)s_st[4];
+        (void)cand;
     }
 }
 
-void *classify_fn(const RmDev &rm)
+// candidate count: sum of per-item counts, folded by one block
+__global__ void __launch_bounds__(kBlock) k_candidates(RmDev rm, rgg_update_result *res)
 {
-    if (rm.D == 3) return rm.mixed ? (void *)k_classify<3, true> : (void *)k_classify<3, false>;
-    return rm.mixed ? (void *)k_classify<2, true> : (void *)k_classify<2, false>;
-}
-
-struct Launch {
-    void *fn;
-    dim3 grid, block;
-};
-
-// the five launches of one update, in order
-void plan(const RmDev &rm, Launch out[6])
-{
-    out[0] = {(void *)k_diff, dim3(1), dim3(kDiffBlock)};
-    out[1] = {(void *)k_cells, dim3(kCellsGrid), dim3(kBlock)};
-    out[2] = {(void *)k_grid, dim3(kGridGrid), dim3(kBlock)};
-    out[3] = {classify_fn(rm), dim3(kClassifyGrid), dim3(kBlock)};
-    out[4] = {(void *)k_count, dim3(rm.ntiles), dim3(kBlock)};
-    out[5] = {(void *)k_write, dim3(rm.ntiles), dim3(kBlock)};
+    __shared__ int s_w[kWaves];
+    const Ctl *ctl = rm.ctl;
+    const int n_items = ctl->status == RGG_OK ? min(ctl->n_items, (int32_t)rm.items_cap) : 0;
+    int acc = 0;
+    for (int i = threadIdx.x; i < n_items; i += kBlock) acc += rm.item_cnt[i];
+    const int tot = block_sum(acc, s_w);
+    if (threadIdx.x == 0 && res) res->n_candidate_edges = tot;
 }
 
 }  // namespace
@@ -814,10 +1157,11 @@ void plan(const RmDev &rm, Launch out[6])
 hipError_t launch_update(const RmDev &rm, const UpdateArgs &a, hipStream_t s, hipEvent_t *ev)
 {
     hipError_t err;
-#define RGG_TRY(x)                               \
-    do {                                         \
+#define RGG_TRY(x)                                 \
+    do {                                           \
         if ((err = (x)) != hipSuccess) return err; \
     } while (0)
+    if (rm.chunk != kBlock) return hipErrorInvalidValue;   // k_grid: one edge per thread
     if (ev) RGG_TRY(hipEventRecord(ev[0], s));
     k_diff<<<1, kDiffBlock, 0, s>>>(rm, a.old_b, a.new_b);
     RGG_TRY(hipGetLastError());
@@ -825,23 +1169,31 @@ hipError_t launch_update(const RmDev &rm, const UpdateArgs &a, hipStream_t s, hi
     k_cells<<<kCellsGrid, kBlock, 0, s>>>(rm);
     RGG_TRY(hipGetLastError());
     if (ev) RGG_TRY(hipEventRecord(ev[2], s));
-    k_grid<<<kGridGrid, kBlock, 0, s>>>(rm);
+    k_grid<<<kGrid, kBlock, 0, s>>>(rm);
     RGG_TRY(hipGetLastError());
     if (ev) RGG_TRY(hipEventRecord(ev[3], s));
-    if (rm.D == 3) {
-        if (rm.mixed) k_classify<3, true><<<kClassifyGrid, kBlock, 0, s>>>(rm);
-        else k_classify<3, false><<<kClassifyGrid, kBlock, 0, s>>>(rm);
+    if (rm.mixed) {
+        if (rm.D == 3) k_classify32<3><<<kGrid, kBlock, 0, s>>>(rm);
+        else k_classify32<2><<<kGrid, kBlock, 0, s>>>(rm);
     } else {
-        if (rm.mixed) k_classify<2, true><<<kClassifyGrid, kBlock, 0, s>>>(rm);
-        else k_classify<2, false><<<kClassifyGrid, kBlock, 0, s>>>(rm);
+        if (rm.D == 3) k_classify64<3><<<kGrid, kBlock, 0, s>>>(rm);
+        else k_classify64<2><<<kGrid, kBlock, 0, s>>>(rm);
     }
     RGG_TRY(hipGetLastError());
     if (ev) RGG_TRY(hipEventRecord(ev[4], s));
+    if (rm.mixed) {
+        if (rm.D == 3) k_recheck<3><<<kGrid, kBlock, 0, s>>>(rm);
+        else k_recheck<2><<<kGrid, kBlock, 0, s>>>(rm);
+        RGG_TRY(hipGetLastError());
+    }
+    if (ev) RGG_TRY(hipEventRecord(ev[5], s));
     k_count<<<rm.ntiles, kBlock, 0, s>>>(rm, a.labels, a.res, 0);
     RGG_TRY(hipGetLastError());
     k_write<<<rm.ntiles, kBlock, 0, s>>>(rm, a.gray, a.gray_cap, a.res, 0);
     RGG_TRY(hipGetLastError());
-    if (ev) RGG_TRY(hipEventRecord(ev[5], s));
+    k_candidates<<<1, kBlock, 0, s>>>(rm, a.res);
+    RGG_TRY(hipGetLastError());
+    if (ev) RGG_TRY(hipEventRecord(ev[6], s));
     return hipSuccess;
 #undef RGG_TRY
 }
@@ -858,9 +1210,8 @@ hipError_t launch_labels(const RmDev &rm, const UpdateArgs &a, hipStream_t s)
 hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, hipGraphNode_t dep,
                             hipGraphNode_t *last)
 {
-    Launch L[6];
-    plan(rm, L);
-    // argument storage: copied by hipGraphAddKernelNode
+    if (rm.chunk != kBlock) return hipErrorInvalidValue;
+    // argument storage: hipGraphAddKernelNode copies the values
     RmDev r = rm;
     const rgg_box *ob = a.old_b, *nb = a.new_b;
     uint8_t *lab = a.labels;
@@ -872,15 +1223,32 @@ hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, 
     void *args_one[] = {&r};
     void *args_count[] = {&r, &lab, &res, &zero};
     void *args_write[] = {&r, &gray, &cap, &res, &zero};
-    void **args[6] = {args_diff, args_one, args_one, args_one, args_count, args_write};
+    void *args_cand[] = {&r, &res};
+    struct Node {
+        void *fn;
+        dim3 grid;
+        void **args;
+    };
+    void *cls = rm.mixed ? (rm.D == 3 ? (void *)k_classify32<3> : (void *)k_classify32<2>)
+                         : (rm.D == 3 ? (void *)k_classify64<3> : (void *)k_classify64<2>);
+    Node nodes[8];
+    int n = 0;
+    nodes[n++] = {(void *)k_diff, dim3(1), args_diff};
+    nodes[n++] = {(void *)k_cells, dim3(kCellsGrid), args_one};
+    nodes[n++] = {(void *)k_grid, dim3(kGrid), args_one};
+    nodes[n++] = {cls, dim3(kGrid), args_one};
+    if (rm.mixed) nodes[n++] = {rm.D == 3 ? (void *)k_recheck<3> : (void *)k_recheck<2>, dim3(kGrid), args_one};
+    nodes[n++] = {(void *)k_count, dim3(rm.ntiles), args_count};
+    nodes[n++] = {(void *)k_write, dim3(rm.ntiles), args_write};
+    nodes[n++] = {(void *)k_candidates, dim3(1), args_cand};
     hipGraphNode_t prev = dep;
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < n; ++k) {
         hipKernelNodeParams p = {};
-        p.func = L[k].fn;
-        p.gridDim = L[k].grid;
-        p.blockDim = L[k].block;
+        p.func = nodes[k].fn;
+        p.gridDim = nodes[k].grid;
+        p.blockDim = dim3(k == 0 ? kDiffBlock : kBlock);
         p.sharedMemBytes = 0;
-        p.kernelParams = args[k];
+        p.kernelParams = nodes[k].args;
         p.extra = nullptr;
         hipGraphNode_t node;
         hipError_t err = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);

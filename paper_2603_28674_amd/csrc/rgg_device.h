@@ -35,6 +35,8 @@ struct RmDev {
     int64_t E, M;
     float band_rel;
     int32_t ntiles;            // label tiles of kLabelTile edges
+    int32_t p_fixed;           // sphere samples per edge when every edge has the same count, else 0
+    int32_t pad1;
     // approximations (see HostGeometry for the layouts)
     const int64_t *soff;
     const float *samp32;
@@ -60,10 +62,19 @@ struct RmDev {
     rgg_box *resident;         // [M] obstacle slots
     ChgEntry *chg;             // [2M]
     int2 *items;               // [items_cap] (cell, chunk)
-    int32_t *work;             // [E] candidate edge ids
+    int32_t *item_cnt;         // [items_cap] candidates found in each item
+    int32_t *work;             // [grid entries] candidates of item (c, h), stored from
+                               // cell_start[c] + h*chunk on, in cell-list order
+    uint32_t *unsure;          // [grid entries] per candidate: bit t set when a pair
+                               // with changed-entry tile t needs the binary64 re-test
     int32_t *tile_cnt;         // [ntiles] gray edges per label tile
+    unsigned long long *blk_stats;   // [kStatBlocks][kStats] per-block partial counts
     Ctl *ctl;
 };
+
+constexpr int kStats = 5;          // pairs, outer hits, re-tested pairs, classify bytes, grid entries scanned
+constexpr int kStatBlocks = 2048;  // blocks of the grid, classify and re-test kernels
+constexpr int kMaxSlots = 4096;    // 2*slots changed entries = at most 32 LDS tiles of 256
 
 constexpr int kLabelTile = 4096;   // edges per block of the label kernels
 
@@ -76,11 +87,12 @@ struct UpdateArgs {
     rgg_update_result *res;
 };
 
-// Queues the five kernels of one update on `s`.  When `ev` is non-null,
-// ev[0..5] are recorded before, between and after the kernels.
+// Queues the kernels of one update on `s`.  When `ev` is non-null, ev[0..6]
+// are recorded before, between and after the stages (diff, cells, grid scan,
+// classify, re-test, labels).
 hipError_t launch_update(const RmDev &rm, const UpdateArgs &a, hipStream_t s, hipEvent_t *ev);
 
-// Appends the same five kernels to `g` as a chain; `dep` (may be null) is the
+// Appends the same kernels to `g` as a chain; `dep` (may be null) is the
 // node they wait for, *last receives the final node.
 hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, hipGraphNode_t dep,
                             hipGraphNode_t *last);

@@ -304,7 +304,7 @@ def rgg_timing_enable(rm, on=True):
 
 
 def rgg_timing_read(rm):
-    ms = np.zeros(5)
+    ms = np.zeros(6)
     n = C.c_int64(0)
     _check(lib().rgg_timing_read(rm, _ptr(ms), C.byref(n)))
     return ms, n.value

@@ -123,6 +123,49 @@ def test_device_buffer_entry_point(ctx):
     check_sequence(ctx, w, rgg.RGG_PREC_FP64, device_buffers=True)
 
 
+def test_graph_entry_point(ctx):
+    """rgg_graph_create: a chain of updates on one roadmap and an independent
+    second roadmap in one graph; every output equals the oracle's."""
+    import torch
+    from paper_2603_28674_amd import rgg
+    import oracle
+    dev = torch.device("cuda:0")
+    ws = [workload("spatial", n_updates=3, seed=31), workload("arm", n_updates=3, seed=32)]
+    print(f"[graph] E={[w.n_edges for w in ws]}", flush=True)
+    reqs, keep, outs = [], [], []
+    gs = [rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK) for w in ws]
+    for g, w in zip(gs, ws):
+        states = torch.from_numpy(np.stack([w.absent()] + w.boxes)).to(dev)
+        keep.append(states)
+        per = []
+        for u in range(len(w.boxes)):
+            lab = torch.zeros(w.n_edges, dtype=torch.uint8, device=dev)
+            gray = torch.zeros(w.n_edges, dtype=torch.int64, device=dev)
+            res = torch.zeros(rgg.RESULT_BYTES, dtype=torch.uint8, device=dev)
+            per.append((lab, gray, res))
+            reqs.append(rgg.rgg_update_req(g.h.value, w.n_slots, states[u].data_ptr(),
+                                           states[u + 1].data_ptr(), lab.data_ptr(), gray.data_ptr(),
+                                           w.n_edges, res.data_ptr()))
+        outs.append(per)
+    graph = rgg.rgg_graph_create(ctx, reqs)
+    rgg.rgg_graph_launch(graph, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    for w, per in zip(ws, outs):
+        o = oracle.from_workload(w)
+        prev = w.absent()
+        for u, cur in enumerate(w.boxes):
+            ol, og = o.update(prev, cur)
+            lab, gray, res = per[u]
+            r = rgg.result_from_tensor(res)
+            assert r.status == 0 and r.n_gray == len(og)
+            assert np.array_equal(lab.cpu().numpy(), ol)
+            assert np.array_equal(gray[: r.n_gray].cpu().numpy(), og)
+            prev = cur
+    rgg.rgg_graph_destroy(graph)
+    for g in gs:
+        g.close()
+
+
 def test_band_infinite_rechecks_every_decision(ctx):
     from paper_2603_28674_amd import rgg
     w = workload("spatial", n_updates=2, seed=24)
