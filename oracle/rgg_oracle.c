@@ -12,7 +12,8 @@
  *
  *   for every roadmap edge e and the current set O of present box obstacles
  *     C(e,o) = the outer approximation of e meets o
- *     S(e,o) = C(e,o) and the inner approximation of e meets o
+ *     S(e,o) = for some robot sphere, its part of the outer approximation
+ *              and its part of the inner approximation both meet o
  *     outer(e) = #{o : C(e,o)},  inner(e) = #{o : S(e,o)}
  *     label(e) = RED if inner(e) > 0, else GREEN if outer(e) == 0, else GRAY
  *   plus the ascending list of GRAY edge ids.
@@ -525,41 +526,53 @@ orc_rm *orc_rm_build(const orc_robot *rob, int64_t n_nodes, const double *q, int
 /* pair predicates                                                           */
 /* ------------------------------------------------------------------------ */
 
-static int pair_outer(const orc_rm *rm, int64_t e, const double *box)
+/* capsule of sphere i meets the box */
+static int capsule_meets(const orc_rm *rm, int64_t e, int i, const double *box)
 {
     const orc_robot *r = &rm->rob;
     int B = r->B, D = r->D;
     int64_t n = rm->soff[e + 1] - rm->soff[e] - 1;
     const double *first = rm->ctr + rm->soff[e] * B * D;
     const double *last = first + n * B * D;
-    for (int i = 0; i < B; ++i) {
-        double R = rm->capR[e * B + i];
-        if (segbox_fmin(D, first + i * D, last + i * D, box, box + 3) <= R * R) return 1;
-    }
-    return 0;
+    double R = rm->capR[e * B + i];
+    return segbox_fmin(D, first + i * D, last + i * D, box, box + 3) <= R * R;
 }
 
-static int pair_inner(const orc_rm *rm, int64_t e, const double *box)
+/* some copy of sphere i along the edge meets the box */
+static int copies_meet(const orc_rm *rm, int64_t e, int i, const double *box)
 {
     const orc_robot *r = &rm->rob;
     int B = r->B, D = r->D;
     const double *c = rm->ctr + rm->soff[e] * B * D;
     int64_t cnt = rm->soff[e + 1] - rm->soff[e];
+    double rr = r->rad[i];
     for (int64_t s = 0; s < cnt; ++s)
-        for (int i = 0; i < B; ++i) {
-            double rr = r->rad[i];
-            if (point_box_d2(D, c + (s * B + i) * D, box, box + 3) <= rr * rr) return 1;
-        }
+        if (point_box_d2(D, c + (s * B + i) * D, box, box + 3) <= rr * rr) return 1;
     return 0;
 }
 
-/* C and S of one (edge, box) pair; S = C and (some sample sphere meets the box) */
+/* C and S of one (edge, box) pair, sphere by sphere:
+ *   C = some capsule meets the box;
+ *   S = for some sphere i, its capsule meets the box and a copy of sphere i
+ *       meets it.
+ * Every copy of sphere i lies inside capsule i (the inflation delta_i bounds
+ * the centre's distance from the chord), so the conjunction never changes S
+ * in exact arithmetic; it makes S imply C, and the copies of a sphere whose
+ * capsule misses need no test. */
 void orc_rm_pair(const orc_rm *rm, int64_t e, const double *box, int32_t *C, int32_t *S)
 {
-    int D = rm->rob.D;
-    if (!box_present(D, box)) { *C = 0; *S = 0; return; }
-    *C = pair_outer(rm, e, box);
-    *S = *C ? pair_inner(rm, e, box) : 0;
+    const orc_robot *r = &rm->rob;
+    *C = 0;
+    *S = 0;
+    if (!box_present(r->D, box)) return;
+    for (int i = 0; i < r->B; ++i) {
+        if (!capsule_meets(rm, e, i, box)) continue;
+        *C = 1;
+        if (copies_meet(rm, e, i, box)) {
+            *S = 1;
+            return;
+        }
+    }
 }
 
 static int loose_overlap(const orc_rm *rm, int64_t e, const double *box)

@@ -16,5 +16,5 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def oracle_lib():
     import oracle
-    oracle.build(force=False)
+    oracle.build(force=True)    # always the current source
     return oracle
