@@ -51,6 +51,24 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy of known size),
+    or None when the kernel source changed since those counters were taken."""
+    import glob
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(root, "paper_2603_28674_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in glob.glob(os.path.join(root, "profiles", "*.md")):
+        for ln in open(path):
+            if ln.startswith("traffic-record:"):
+                rec = json.loads(ln.split(":", 1)[1])
+                if rec["kernel"] == kernel and rec["source_sha256"] == sha:
+                    return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
+    return None
+
+
 def cpu_baseline(w, gpu_labels_final, sample_edges, n_updates, seed):
     """The FP64 oracle, incremental mode, on a sample of the roadmap's edges,
     over the same obstacle sequence; also spot-checks the GPU's final labels
@@ -203,8 +221,8 @@ def main():
                                 "recheck": ms[4] / n_timed, "labels": ms[5] / n_timed},
         "per_update": stats,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_classify<3,true>", "bytes_per_launch": test_bytes,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("k_classify32<3>"),
+                     "kernel": "k_classify32<3>", "bytes_per_launch": test_bytes,
                      "kernel_ms": test_ms},
         "cpu_baseline": None,
     }

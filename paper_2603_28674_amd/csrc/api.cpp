@@ -559,8 +559,11 @@ rgg_status rgg_debug_geometry(const rgg_roadmap_desc *rd, const rgg_robot *robot
         n_configs[k] = P / B;
         if (centres) {
             const double *blk = g.samp.data() + D * g.soff[k];
-            for (int64_t n = 0; n < P; ++n)
-                for (int d = 0; d < D; ++d) centres[(row + n) * D + d] = blk[d * P + n];
+            const int64_t J = P / B;   // block layout [D][B][J] -> rows (j, i)
+            for (int64_t j = 0; j < J; ++j)
+                for (int i = 0; i < B; ++i)
+                    for (int d = 0; d < D; ++d)
+                        centres[(row + j * B + i) * D + d] = blk[d * P + i * J + j];
         }
         row += P;
         if (capsule) {

@@ -601,19 +601,92 @@ __device__ inline bool cursor_next(const RmDev &rm, int n_items, Cursor &cu, int
     }
 }
 
+// Adds the counter deltas of one edge.  Each edge is owned by one wavefront
+// within a kernel, so the adds need no returned value: they are issued as
+// fire-and-forget atomics and cost no round trip.
+__device__ inline void add_counts(const RmDev &rm, int64_t e, int dC, int dS)
+{
+    int *c = reinterpret_cast<int *>(rm.cnt + e);
+    if (dC) __hip_atomic_fetch_add(c, dC, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (dS) __hip_atomic_fetch_add(c + 1, dS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // ------------------------------------------------------------------------
-// binary64 classification of one edge against entries [t0, t0+nt)
-// (FP64 mode, and the re-test of the FP32 mode); every lane returns the
-// same counter deltas
+// per-wavefront LDS scratch of the classify kernels
+// ------------------------------------------------------------------------
+
+struct WaveScratch {
+    int act[kTile];   // staged-entry index of each pair of the current edge
+    int lst[64];      // sphere indices whose copies are tested
+};
+
+// Lane mapping of the copies of up to 64/jw spheres onto one wavefront:
+// lane -> (sub = lane / jw, jj = lane % jw), jw = min(J, 64) configurations.
+struct CopyMap {
+    int J, jw, spc, sub, jj;
+};
+
+__device__ inline CopyMap copy_map(int J)
+{
+    CopyMap c;
+    c.J = J;
+    c.jw = J < 64 ? J : 64;
+    c.spc = 64 / c.jw;
+    c.sub = lane_id() / c.jw;
+    c.jj = lane_id() - c.sub * c.jw;
+    return c;
+}
+
+// writes the indices of the set bits of m (wave-uniform, bits < B) to lst
+__device__ inline int list_spheres(uint64_t m, int B, int *lst)
+{
+    const int lane = lane_id();
+    if (lane < B && ((m >> lane) & 1ull)) lst[__popcll(m & lanes_below())] = lane;
+    wave_sync();
+    return __popcll(m);
+}
+
+// ------------------------------------------------------------------------
+// binary64 classification of one edge against entries [t0, t0+nt): the
+// definition, sphere by sphere (C: some capsule meets the box; S: for some
+// sphere, its capsule and one of its copies meet the box).  Used by the FP64
+// mode and by the re-test of the FP32 mode; every lane returns the same
+// counter deltas.
 // ------------------------------------------------------------------------
 
 template <int D>
+__device__ bool copies_meet64(const RmDev &rm, const double *sb, int64_t P, const CopyMap &cm,
+                              uint64_t m, const double *lo, const double *hi, const double *rad,
+                              int *lst, unsigned long long *bytes)
+{
+    const int nsph = list_spheres(m, rm.B, lst);
+    for (int sp0 = 0; sp0 < nsph; sp0 += cm.spc) {
+        for (int j0 = 0; j0 < cm.J; j0 += cm.jw) {
+            const int js = j0 + cm.jj;
+            const bool valid = cm.sub < cm.spc && sp0 + cm.sub < nsph && js < cm.J;
+            bool hit = false;
+            if (valid) {
+                const int i = lst[sp0 + cm.sub];
+                double p[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) p[k] = sb[k * P + (int64_t)i * cm.J + js];
+                const double r = rad[i];
+                hit = point_box64<D>(p, lo, hi) <= r * r;
+            }
+            *bytes += (unsigned long long)(__popcll(__ballot(valid)) * D * 8);
+            if (__ballot(hit)) return true;
+        }
+    }
+    return false;
+}
+
+template <int D>
 __device__ int2 edge_exact(const RmDev &rm, int64_t e, const ChgEntry *__restrict__ chg, int t0, int nt,
-                           int *act, uint8_t *st, unsigned long long *n_pairs,
+                           WaveScratch &ws, const double *rad, unsigned long long *n_pairs,
                            unsigned long long *n_outer, unsigned long long *bytes)
 {
     const int lane = lane_id(), B = rm.B;
-    const int G = 64 / B, slot = lane / B, ci = lane % B;
+    const int G = 64 / B, slot = lane / B, ci = lane - slot * B;
     const uint64_t gmask = B == 64 ? ~0ull : ((1ull << B) - 1ull);
     const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
     const float4 bl = aabb[2 * e], bh = aabb[2 * e + 1];
@@ -622,14 +695,13 @@ __device__ int2 edge_exact(const RmDev &rm, int64_t e, const ChgEntry *__restric
         const int j = b0 + lane;
         const bool ov = j < nt && overlap3(chg[t0 + j].lo32, chg[t0 + j].hi32, bl, bh);
         const uint64_t m = __ballot(ov);
-        if (ov) act[n_act + __popcll(m & lanes_below())] = t0 + j;
+        if (ov) ws.act[n_act + __popcll(m & lanes_below())] = t0 + j;
         n_act += __popcll(m);
     }
     *bytes += 32;
     wave_sync();
     if (n_act == 0) return make_int2(0, 0);
     *n_pairs += n_act;
-    // outer test: lane (slot, ci) takes capsule ci of pair slot
     const double *cp = rm.cap64 + e * (2 * D + 1) * B;
     double A[D], Bp[D];
 #pragma unroll
@@ -639,12 +711,16 @@ __device__ int2 edge_exact(const RmDev &rm, int64_t e, const ChgEntry *__restric
     }
     const double R = cp[2 * D * B + ci];
     *bytes += (unsigned long long)((2 * D + 1) * B * 8);
-    int pend = 0;
+    const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
+    const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
+    const double *sb = rm.samp64 + D * s0;
+    const CopyMap cm = copy_map((int)(P / B));
+    int dC = 0, dS = 0;
     for (int a0 = 0; a0 < n_act; a0 += G) {
         const int a = a0 + slot;
         bool hit = false;
         if (slot < G && a < n_act) {
-            const ChgEntry &en = chg[act[a]];
+            const ChgEntry &en = chg[ws.act[a]];
             double lo[D], hi[D];
 #pragma unroll
             for (int k = 0; k < D; ++k) {
@@ -654,59 +730,20 @@ __device__ int2 edge_exact(const RmDev &rm, int64_t e, const ChgEntry *__restric
             hit = segbox64<D>(A, Bp, lo, hi) <= R * R;
         }
         const uint64_t hm = __ballot(hit);
-        if (lane < G && a0 + lane < n_act) st[a0 + lane] = (hm & (gmask << (lane * B))) ? kCHit : 0;
-        for (int s = 0; s < G && a0 + s < n_act; ++s) pend += ((hm >> (s * B)) & gmask) ? 1 : 0;
-    }
-    wave_sync();
-    *n_outer += pend;
-    // inner test
-    const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
-    const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
-    const double *sb = rm.samp64 + D * s0;
-    const int step = 64 % B;
-    int cmod = 0;
-    for (int64_t c = 0; c < P && pend > 0; c += 64) {
-        const int64_t n = c + lane;
-        int ir = cmod + ci;
-        ir = ir >= B ? ir - B : ir;
-        cmod += step;
-        cmod = cmod >= B ? cmod - B : cmod;
-        const bool valid = n < P;
-        double p[D];
-        double r = 0.0;
-        if (valid) {
+        for (int s = 0; s < G && a0 + s < n_act; ++s) {
+            const uint64_t m = (hm >> (s * B)) & gmask;
+            if (!m) continue;
+            const ChgEntry &en = chg[ws.act[a0 + s]];
+            double lo[D], hi[D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) p[k] = sb[k * P + n];
-            r = rm.rad64[ir];
-        }
-        *bytes += (unsigned long long)(min((int64_t)64, P - c) * D * 8);
-        for (int a = 0; a < n_act; ++a) {
-            const uint8_t s = st[a];
-            if (s != kCHit) continue;
-            bool hit = false;
-            if (valid) {
-                const ChgEntry &en = chg[act[a]];
-                double lo[D], hi[D];
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    lo[k] = en.lo[k];
-                    hi[k] = en.hi[k];
-                }
-                hit = point_box64<D>(p, lo, hi) <= r * r;
+            for (int k = 0; k < D; ++k) {
+                lo[k] = en.lo[k];
+                hi[k] = en.hi[k];
             }
-            if (__ballot(hit)) {
-                st[a] = kCHit | kSHit;
-                --pend;
-            }
-            wave_sync();
+            ++*n_outer;
+            dC += en.sign;
+            if (copies_meet64<D>(rm, sb, P, cm, m, lo, hi, rad, ws.lst, bytes)) dS += en.sign;
         }
-    }
-    int dC = 0, dS = 0;
-    for (int a = 0; a < n_act; ++a) {
-        const uint8_t s = st[a];
-        const int sign = chg[act[a]].sign;
-        dC += (s & kCHit) ? sign : 0;
-        dS += (s & kSHit) ? sign : 0;
     }
     wave_sync();
     return make_int2(dC, dS);
@@ -716,38 +753,9 @@ __device__ int2 edge_exact(const RmDev &rm, int64_t e, const ChgEntry *__restric
 // k_classify, FP64 mode
 // ------------------------------------------------------------------------
 
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_classify64(RmDev rm)
+__device__ inline void store_partials(const RmDev &rm, unsigned long long n_pairs,
+                                      unsigned long long n_outer, unsigned long long bytes)
 {
-    __shared__ int s_act[kWaves][kTile];
-    __shared__ uint8_t s_st[kWaves][kTile];
-    const Ctl *ctl = rm.ctl;
-    unsigned long long n_pairs = 0, n_outer = 0, bytes = 0;
-    if (ctl->status == RGG_OK) {
-        const int n_chg = ctl->n_chg;
-        const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
-        const int wv = threadIdx.x >> 6;
-        Cursor cu = {(int)blockIdx.x, -1, 0, 0};
-        int64_t slot;
-        while (cursor_next(rm, n_items, cu, wv, &slot)) {
-            const int64_t e = rm.work[slot];
-            int2 d = make_int2(0, 0);
-            for (int t0 = 0; t0 < n_chg; t0 += kTile) {
-                int2 x = edge_exact<D>(rm, e, rm.chg, t0, min(kTile, n_chg - t0), s_act[wv], s_st[wv],
-                                       &n_pairs, &n_outer, &bytes);
-                d.x += x.x;
-                d.y += x.y;
-            }
-            if (lane_id() == 0 && (d.x || d.y)) {
-                int2 v = rm.cnt[e];
-                v.x += d.x;
-                v.y += d.y;
-                rm.cnt[e] = v;
-            }
-            bytes += 16;
-        }
-    }
-    // per-block partials: waves of the block add into LDS, thread 0 stores
     __shared__ unsigned long long s_acc[3];
     if (threadIdx.x < 3) s_acc[threadIdx.x] = 0;
     __syncthreads();
@@ -766,9 +774,71 @@ __global__ void __launch_bounds__(kBlock) k_classify64(RmDev rm)
     }
 }
 
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_classify64(RmDev rm)
+{
+    __shared__ WaveScratch s_ws[kWaves];
+    __shared__ double s_rad[64];
+    const Ctl *ctl = rm.ctl;
+    if (threadIdx.x < rm.B) s_rad[threadIdx.x] = rm.rad64[threadIdx.x];
+    __syncthreads();
+    unsigned long long n_pairs = 0, n_outer = 0, bytes = 0;
+    if (ctl->status == RGG_OK) {
+        const int n_chg = ctl->n_chg;
+        const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
+        const int wv = threadIdx.x >> 6;
+        Cursor cu = {(int)blockIdx.x, -1, 0, 0};
+        int64_t slot;
+        while (cursor_next(rm, n_items, cu, wv, &slot)) {
+            const int64_t e = rm.work[slot];
+            int2 d = make_int2(0, 0);
+            for (int t0 = 0; t0 < n_chg; t0 += kTile) {
+                int2 x = edge_exact<D>(rm, e, rm.chg, t0, min(kTile, n_chg - t0), s_ws[wv], s_rad,
+                                       &n_pairs, &n_outer, &bytes);
+                d.x += x.x;
+                d.y += x.y;
+            }
+            if (lane_id() == 0) add_counts(rm, e, d.x, d.y);
+            bytes += 16;
+        }
+    }
+    store_partials(rm, n_pairs, n_outer, bytes);
+}
+
 // ------------------------------------------------------------------------
-// k_classify, FP32 mode: one wavefront per candidate edge
+// k_classify, FP32 mode: one wavefront per candidate edge.  A decision is
+// kept only when its binary32 margin lies outside the rounding band; a tile
+// of pairs with any undecided pair is left whole to k_recheck.
 // ------------------------------------------------------------------------
+
+// copies of the spheres in m against one box: kHit (some copy certainly
+// meets it), kMiss (every copy certainly misses) or kUnsure
+template <int D>
+__device__ int copies_meet32(const float *sb, int64_t P, const CopyMap &cm, uint64_t m, int B,
+                             const float *lo, const float *hi, float band, const float *rad2,
+                             int *lst, unsigned long long *bytes)
+{
+    const int nsph = list_spheres(m, B, lst);
+    bool unsure = false;
+    for (int sp0 = 0; sp0 < nsph; sp0 += cm.spc) {
+        for (int j0 = 0; j0 < cm.J; j0 += cm.jw) {
+            const int js = j0 + cm.jj;
+            const bool valid = cm.sub < cm.spc && sp0 + cm.sub < nsph && js < cm.J;
+            int cls = kMiss;
+            if (valid) {
+                const int i = lst[sp0 + cm.sub];
+                float p[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) p[k] = sb[k * P + i * cm.J + js];
+                cls = classify_margin(point_box32<D>(p, lo, hi) - rad2[i], band);
+            }
+            *bytes += (unsigned long long)(__popcll(__ballot(valid)) * D * 4);
+            if (__ballot(cls == kHit)) return kHit;
+            unsure |= __ballot(cls == kUnsure) != 0;
+        }
+    }
+    return unsure ? kUnsure : kMiss;
+}
 
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_classify32(RmDev rm)
@@ -776,21 +846,21 @@ __global__ void __launch_bounds__(kBlock) k_classify32(RmDev rm)
     __shared__ float s_lo[3][kTile], s_hi[3][kTile];
     __shared__ float s_sb[kTile];
     __shared__ int s_sign[kTile];
-    __shared__ int s_act[kWaves][kTile];
-    __shared__ uint8_t s_st[kWaves][kTile];
+    __shared__ WaveScratch s_ws[kWaves];
+    __shared__ float s_rad2[64];
     const Ctl *ctl = rm.ctl;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    if (tid < rm.B) s_rad2[tid] = rm.rad2_32[tid];
     unsigned long long n_pairs = 0, n_outer = 0, bytes = 0;
     if (ctl->status == RGG_OK) {
         const int n_chg = ctl->n_chg;
         const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
         const int B = rm.B;
-        const int G = 64 / B, slot = lane / B, ci = lane % B;
+        const int G = 64 / B, slot = lane / B, ci = lane - slot * B;
         const uint64_t gmask = B == 64 ? ~0ull : ((1ull << B) - 1ull);
         const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
         const float band_rel = rm.band_rel;
-        int *act = s_act[wv];
-        uint8_t *st = s_st[wv];
+        WaveScratch &ws = s_ws[wv];
         for (int t0 = 0, tile = 0; t0 < n_chg; t0 += kTile, ++tile) {
             const int nt = min(kTile, n_chg - t0);
             __syncthreads();
@@ -808,10 +878,7 @@ __global__ void __launch_bounds__(kBlock) k_classify32(RmDev rm)
             int64_t wslot;
             while (cursor_next(rm, n_items, cu, wv, &wslot)) {
                 const int64_t e = rm.work[wslot];
-                // issue every load of this edge up front
                 const float4 bl = aabb[2 * e], bh = aabb[2 * e + 1];
-                const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
-                const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
                 const float *cp = rm.cap32 + e * (2 * D + 1) * B;
                 float A[D], Bq[D];
 #pragma unroll
@@ -820,10 +887,8 @@ __global__ void __launch_bounds__(kBlock) k_classify32(RmDev rm)
                     Bq[k] = cp[(D + k) * B + ci];
                 }
                 const float R = cp[2 * D * B + ci];
-                const float *sb = rm.samp32 + D * s0;
-                float p[D];
-#pragma unroll
-                for (int k = 0; k < D; ++k) p[k] = lane < P ? sb[k * P + lane] : 0.0f;
+                const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
+                const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
                 // pretest against the staged entries
                 int n_act = 0;
                 for (int b0 = 0; b0 < nt; b0 += 64) {
@@ -835,7 +900,7 @@ __global__ void __launch_bounds__(kBlock) k_classify32(RmDev rm)
                         ov = overlap3(lo, hi, bl, bh);
                     }
                     const uint64_t m = __ballot(ov);
-                    if (ov) act[n_act + __popcll(m & lanes_below())] = j;
+                    if (ov) ws.act[n_act + __popcll(m & lanes_below())] = j;
                     n_act += __popcll(m);
                 }
                 bytes += 32;
@@ -844,18 +909,19 @@ __global__ void __launch_bounds__(kBlock) k_classify32(RmDev rm)
                     wave_sync();
                     n_pairs += n_act;
                     bytes += (unsigned long long)((2 * D + 1) * B * 4);
-                    // outer test: quick tests first (capsule box separated ->
-                    // miss; an end sphere meets the box -> hit), the full
-                    // segment-box minimum only where neither decides
+                    const float *sb = rm.samp32 + D * s0;
+                    const CopyMap cm = copy_map((int)(P / B));
                     const float R2 = R * R;
-                    int pend = 0;
                     bool any_unsure = false;
+                    int dC = 0, dS = 0;
                     for (int a0 = 0; a0 < n_act; a0 += G) {
+                        // capsule tests: separation -> miss, an end sphere
+                        // meeting the box -> hit, else the full minimum
                         const int a = a0 + slot;
                         int cls = kMiss;
                         float lo[D], hi[D], band = 0.0f;
                         if (slot < G && a < n_act) {
-                            const int j = act[a];
+                            const int j = ws.act[a];
 #pragma unroll
                             for (int k = 0; k < D; ++k) {
                                 lo[k] = s_lo[k][j];
@@ -867,92 +933,46 @@ __global__ void __launch_bounds__(kBlock) k_classify32(RmDev rm)
 #pragma unroll
                             for (int k = 0; k < D; ++k)
                                 sep = fmaxf(sep, fmaxf(lo[k] - fmaxf(A[k], Bq[k]), fminf(A[k], Bq[k]) - hi[k]));
-                            const float m_sep = sep * sep - R2;
                             const float m_end = fminf(point_box32<D>(A, lo, hi), point_box32<D>(Bq, lo, hi)) - R2;
-                            cls = (sep > 0.0f && m_sep > band) ? kMiss : (m_end < -band ? kHit : kOpen);
+                            cls = (sep > 0.0f && sep * sep - R2 > band) ? kMiss : (m_end < -band ? kHit : kOpen);
                         }
                         if (__ballot(cls == kOpen)) {
                             if (cls == kOpen) cls = classify_margin(segbox32<D>(A, Bq, lo, hi) - R2, band);
                         }
                         const uint64_t hm = __ballot(cls == kHit), um = __ballot(cls == kUnsure);
-                        if (lane < G && a0 + lane < n_act) {
-                            const uint64_t g = gmask << (lane * B);
-                            st[a0 + lane] = (hm & g) ? kCHit : ((um & g) ? kCUnsure : 0);
-                        }
+                        // per pair: copies of the spheres whose capsule met
                         for (int s = 0; s < G && a0 + s < n_act; ++s) {
-                            const uint64_t g = gmask << (s * B);
-                            pend += (hm & g) ? 1 : 0;
-                            any_unsure |= !(hm & g) && (um & g);
-                        }
-                    }
-                    wave_sync();
-                    n_outer += pend;
-                    // inner test over chunks of 64 sphere samples; chunk 0 is
-                    // already loaded, the next chunk is fetched while testing
-                    const int step = 64 % B;
-                    int cmod = 0;
-                    float pn[D];
-                    for (int64_t c = 0; c < P && pend > 0; c += 64) {
-                        const int64_t n = c + lane;
-                        const bool valid = n < P;
-                        const bool more = c + 64 < P;
-                        if (more) {
-#pragma unroll
-                            for (int k = 0; k < D; ++k) pn[k] = n + 64 < P ? sb[k * P + n + 64] : 0.0f;
-                        }
-                        int ir = cmod + ci;
-                        ir = ir >= B ? ir - B : ir;
-                        cmod += step;
-                        cmod = cmod >= B ? cmod - B : cmod;
-                        const float r2 = rm.rad2_32[ir];
-                        bytes += (unsigned long long)(min((int64_t)64, P - c) * D * 4);
-                        for (int a = 0; a < n_act; ++a) {
-                            uint8_t s = st[a];
-                            if (!(s & kCHit) || (s & kSHit)) continue;
-                            const int j = act[a];
-                            int cls = kMiss;
-                            if (valid) {
-                                float lo[D], hi[D];
-#pragma unroll
-                                for (int k = 0; k < D; ++k) {
-                                    lo[k] = s_lo[k][j];
-                                    hi[k] = s_hi[k][j];
-                                }
-                                const float sc = fmaxf(bl.w, s_sb[j]);
-                                cls = classify_margin(point_box32<D>(p, lo, hi) - r2, band_rel * sc * sc);
+                            const uint64_t h = (hm >> (s * B)) & gmask, u = (um >> (s * B)) & gmask;
+                            if (!h) {
+                                any_unsure |= u != 0;   // C rests on undecided capsules
+                                continue;
                             }
-                            const uint64_t hm = __ballot(cls == kHit), um = __ballot(cls == kUnsure);
-                            if (hm) {
-                                s |= kSHit;
-                                --pend;
-                            } else if (um) {
-                                s |= kSUnsure;
-                            }
-                            st[a] = s;
-                            wave_sync();
-                        }
-                        if (more) {
+                            const int j = ws.act[a0 + s];
+                            float plo[D], phi[D];
 #pragma unroll
-                            for (int k = 0; k < D; ++k) p[k] = pn[k];
+                            for (int k = 0; k < D; ++k) {
+                                plo[k] = s_lo[k][j];
+                                phi[k] = s_hi[k][j];
+                            }
+                            const float sc = fmaxf(bl.w, s_sb[j]);
+                            const int r = copies_meet32<D>(sb, P, cm, h, B, plo, phi, band_rel * sc * sc,
+                                                           s_rad2, ws.lst, &bytes);
+                            const int sign = s_sign[j];
+                            ++n_outer;
+                            if (r == kHit) {
+                                dC += sign;
+                                dS += sign;
+                            } else if (r == kUnsure || u) {
+                                any_unsure = true;
+                            } else {
+                                dC += sign;
+                            }
                         }
-                    }
-                    // resolve: certain pairs update the counters here; a tile
-                    // holding any unsure pair is left whole to the re-test
-                    int dC = 0, dS = 0;
-                    for (int a = 0; a < n_act; ++a) {
-                        const uint8_t s = st[a];
-                        const int sign = s_sign[act[a]];
-                        any_unsure |= (s & kCHit) && !(s & kSHit) && (s & kSUnsure);
-                        dC += (s & kCHit) ? sign : 0;
-                        dS += (s & kSHit) ? sign : 0;
                     }
                     if (any_unsure) {
                         unsure_tiles = 1u << tile;
-                    } else if (lane == 0 && (dC || dS)) {
-                        int2 v = rm.cnt[e];
-                        v.x += dC;
-                        v.y += dS;
-                        rm.cnt[e] = v;
+                    } else if (lane == 0) {
+                        add_counts(rm, e, dC, dS);
                     }
                     bytes += 16;
                     wave_sync();
@@ -961,69 +981,57 @@ __global__ void __launch_bounds__(kBlock) k_classify32(RmDev rm)
             }
         }
     }
-    __shared__ unsigned long long s_acc[3];
-    if (threadIdx.x < 3) s_acc[threadIdx.x] = 0;
-    __syncthreads();
-    if (lane == 0) {
-        atomicAdd(&s_acc[0], n_pairs);
-        atomicAdd(&s_acc[1], n_outer);
-        atomicAdd(&s_acc[2], bytes);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long *bs = rm.blk_stats + blockIdx.x * kStats;
-        bs[0] = s_acc[0];
-        bs[1] = s_acc[1];
-        bs[2] = 0;
-        bs[3] = s_acc[2];
-    }
+    store_partials(rm, n_pairs, n_outer, bytes);
 }
 
 // ------------------------------------------------------------------------
 // k_recheck: binary64 re-test of the tiles the FP32 filter left unsure.
-// Same block/wave -> candidate mapping as k_classify32.
+// Wavefronts scan the unsure marks of whole items, 64 candidates at a time.
 // ------------------------------------------------------------------------
 
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_recheck(RmDev rm)
 {
-    __shared__ int s_act[kWaves][kTile];
-    __shared__ uint8_t s_st[kWaves][kTile];
+    __shared__ WaveScratch s_ws[kWaves];
+    __shared__ double s_rad[64];
     const Ctl *ctl = rm.ctl;
+    if (threadIdx.x < rm.B) s_rad[threadIdx.x] = rm.rad64[threadIdx.x];
+    __syncthreads();
     if (ctl->status != RGG_OK) return;
     const int n_chg = ctl->n_chg;
     const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
-    const int wv = threadIdx.x >> 6;
-    unsigned long long n_re = 0, n_pairs = 0, n_outer = 0, bytes = 0;
-    Cursor cu = {(int)blockIdx.x, -1, 0, 0};
-    int64_t slot;
-    while (cursor_next(rm, n_items, cu, wv, &slot)) {
-        uint32_t mask = rm.unsure[slot];
-        if (!mask) continue;
-        const int64_t e = rm.work[slot];
-        int2 d = make_int2(0, 0);
-        while (mask) {
-            const int tile = __ffs(mask) - 1;
-            mask &= mask - 1;
-            const int t0 = tile * kTile;
-            int2 x = edge_exact<D>(rm, e, rm.chg, t0, min(kTile, n_chg - t0), s_act[wv], s_st[wv],
-                                   &n_pairs, &n_outer, &bytes);
-            d.x += x.x;
-            d.y += x.y;
-        }
-        n_re += 1;
-        if (lane_id() == 0 && (d.x || d.y)) {
-            int2 v = rm.cnt[e];
-            v.x += d.x;
-            v.y += d.y;
-            rm.cnt[e] = v;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    unsigned long long n_pairs = 0, n_outer = 0, bytes = 0;
+    for (int it = blockIdx.x * kWaves + wv; it < n_items; it += gridDim.x * kWaves) {
+        const int2 item = rm.items[it];
+        const int cnt = rm.item_cnt[it];
+        const int64_t beg = (int64_t)rm.cell_start[item.x] + (int64_t)item.y * rm.chunk;
+        for (int k0 = 0; k0 < cnt; k0 += 64) {
+            const uint32_t mk = k0 + lane < cnt ? rm.unsure[beg + k0 + lane] : 0u;
+            uint64_t fl = __ballot(mk != 0u);
+            while (fl) {
+                const int src = __ffsll((unsigned long long)fl) - 1;
+                fl &= fl - 1;
+                uint32_t mask = (uint32_t)__shfl((int)mk, src);
+                const int64_t e = rm.work[beg + k0 + src];
+                int2 d = make_int2(0, 0);
+                while (mask) {
+                    const int tile = __ffs(mask) - 1;
+                    mask &= mask - 1;
+                    const int t0 = tile * kTile;
+                    int2 x = edge_exact<D>(rm, e, rm.chg, t0, min(kTile, n_chg - t0), s_ws[wv], s_rad,
+                                           &n_pairs, &n_outer, &bytes);
+                    d.x += x.x;
+                    d.y += x.y;
+                }
+                if (lane == 0) add_counts(rm, e, d.x, d.y);
+            }
         }
     }
     __shared__ unsigned long long s_acc[2];
     if (threadIdx.x < 2) s_acc[threadIdx.x] = 0;
     __syncthreads();
-    (void)n_re;
-    if (lane_id() == 0) {
+    if (lane == 0) {
         atomicAdd(&s_acc[0], n_pairs);   // pairs re-decided in binary64
         atomicAdd(&s_acc[1], bytes);
     }
@@ -1035,6 +1043,7 @@ __global__ void __launch_bounds__(kBlock) k_recheck(RmDev rm)
     }
 }
 
+// ------------------------------------------------------------------------
 // ------------------------------------------------------------------------
 // labels and the ordered gray list
 // ------------------------------------------------------------------------

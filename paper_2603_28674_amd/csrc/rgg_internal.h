@@ -18,10 +18,11 @@ constexpr int kAabbStride = 8;      // floats per edge box: lo[3], s, hi[3], pad
 // Approximations of a range of edges, built on the host in binary64.
 //
 // Sphere samples of edge e occupy [soff[e], soff[e+1]) in "sphere-sample"
-// units: sample n = j*B + i is sphere i at configuration j of cfg(e).  The
-// coordinates are stored per edge as a [D][P_e] block (P_e = soff[e+1] -
-// soff[e]) starting at float/double index D*soff[e], so a wavefront reads 64
-// consecutive samples of one coordinate with one coalesced load.
+// units, P_e = soff[e+1] - soff[e] = B * J_e for J_e configurations.  The
+// coordinates are stored per edge as a [D][B][J_e] block starting at
+// float/double index D*soff[e]: the copies of one sphere along the edge are
+// contiguous, so the copies of the spheres whose capsule met a box are read
+// with coalesced loads and the others are never touched.
 struct HostGeometry {
     int kind = 0, D = 0, B = 0;
     int64_t E = 0;
