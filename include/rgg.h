@@ -115,7 +115,11 @@ typedef struct {
     double cell_size;             /* grid cell edge; 0 = heuristic; < 0 = one
                                      cell covering everything                   */
     int32_t host_threads;         /* threads for the host build; 0 = automatic  */
-    int32_t reserved;
+    int32_t retest_capacity;      /* FP32 mode: undecided pairs each of the 2048
+                                     blocks may queue for the binary64 re-test
+                                     before it re-runs a whole work item in
+                                     binary64 instead; 0 = 1024.  Any value
+                                     gives the same labels.                     */
 } rgg_build_opts;
 
 /* Written by the device at the end of every update (rgg_update_async) and

@@ -257,9 +257,12 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     if ((st = rm->upload(&dv.resident, absent.data(), (size_t)M, "obstacle slots")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.chg, (size_t)(2 * M), "changed entries")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.items, (size_t)grid.items_cap, "grid items")) != RGG_OK) return guard(st);
-    if ((st = rm->alloc(&dv.item_cnt, (size_t)grid.items_cap, "grid item counts")) != RGG_OK) return guard(st);
-    if ((st = rm->alloc(&dv.work, grid.edges.size(), "candidate list")) != RGG_OK) return guard(st);
-    if ((st = rm->alloc(&dv.unsure, grid.edges.size(), "re-test marks")) != RGG_OK) return guard(st);
+    dv.rc_cap = opts->retest_capacity > 0 ? opts->retest_capacity : kRcCap;
+    dv.df_cap = (int32_t)((grid.items_cap + kStatBlocks - 1) / kStatBlocks);
+    if ((st = rm->alloc(&dv.rc, (size_t)kStatBlocks * dv.rc_cap, "re-test regions")) != RGG_OK) return guard(st);
+    if ((st = rm->alloc(&dv.rc_cnt, (size_t)kStatBlocks, "re-test counts")) != RGG_OK) return guard(st);
+    if ((st = rm->alloc(&dv.df, (size_t)kStatBlocks * dv.df_cap, "deferred items")) != RGG_OK) return guard(st);
+    if ((st = rm->alloc(&dv.df_cnt, (size_t)kStatBlocks, "deferred counts")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.blk_stats, (size_t)kStatBlocks * kStats, "statistics")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.tile_cnt, (size_t)dv.ntiles, "tile counts")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.ctl, 1, "control block")) != RGG_OK) return guard(st);
@@ -272,6 +275,8 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     HIP_OR_FAIL(hipMemset(dv.cell_bits, 0, 4 * std::max<size_t>(ncw, 1)), "clear marks");
     HIP_OR_FAIL(hipMemset(dv.ctl, 0, sizeof(Ctl)), "clear control");
     HIP_OR_FAIL(hipMemset(dv.blk_stats, 0, sizeof(unsigned long long) * kStatBlocks * kStats), "clear statistics");
+    HIP_OR_FAIL(hipMemset(dv.rc_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear re-test counts");
+    HIP_OR_FAIL(hipMemset(dv.df_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear deferred counts");
     HIP_OR_FAIL(hipMemset(rm->d_labels, 0, std::max<int64_t>(E, 1)), "clear labels");
     HIP_OR_FAIL(hipHostMalloc((void **)&rm->h_stage, sizeof(rgg_box) * std::max<int64_t>(2 * M, 1)), "pinned staging");
     HIP_OR_FAIL(hipHostMalloc((void **)&rm->h_res, sizeof(rgg_update_result)), "pinned result");

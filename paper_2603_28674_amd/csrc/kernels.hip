@@ -1,19 +1,19 @@
 // Update pipeline of librgg for gfx950 (wave64).
 //
-// One update = up to seven kernels on one stream:
+// One update = these kernels on one stream (or one graph):
 //   k_diff      validate the old/new boxes against the resident slots, list
 //               the changed (box, sign) entries in slot order, commit the
 //               slots (Alg. 1: a moved obstacle's old and new poses);
 //   k_cells     activate every grid cell a changed box overlaps and emit one
-//               work item per (cell, chunk of its edge list)  (Sec. 3.3 grid);
-//   k_grid      per item, keep the edges whose box meets a changed box of that
-//               cell; candidates are written in place, no global counter;
-//   k_classify  one wavefront per candidate edge: outer test (per-sphere
-//               capsule vs box), inner test (sphere samples vs box, stopping at
-//               the first hit), counter update (Sec. 3.1 rule; Alg. 1's
-//               intersection lists kept as counts).  In the FP32 mode a pair
-//               whose margin falls inside the rounding band is left to
-//   k_recheck   which re-decides it in binary64;
+//               work item per (cell, chunk of 256 of its edges)  (Sec. 3.3);
+//   k_item      one block per work item: pairs of the item's edges with the
+//               changed boxes of the cell, outer test (per-sphere capsule vs
+//               box), inner test (copies of the spheres whose capsule met),
+//               counter update (Sec. 3.1 rule; Alg. 1's intersection lists
+//               kept as counts).  In the FP32 mode a pair whose margin falls
+//               inside the rounding band is left to
+//   k_recheck_pairs   which decides it in binary64; an item whose block ran
+//               out of re-test room is run again whole by the binary64 k_item;
 //   k_count + k_write   labels from the counters and the ordered gray list.
 //
 // Binary64 code is compiled without FMA contraction and its sums run left to
@@ -34,13 +34,10 @@ namespace {
 constexpr int kDiffBlock = 1024;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kTile = 256;         // changed entries staged in LDS per pass
-constexpr int kSubCap = 1024;      // entries of one cell staged by k_grid
 constexpr int kCellsGrid = 128;
-constexpr int kGrid = kStatBlocks; // blocks of k_grid, k_classify, k_recheck
+constexpr int kGrid = kStatBlocks; // blocks of k_item and k_recheck_pairs
 
 enum : int { kMiss = 0, kHit = 1, kUnsure = 2, kOpen = 3 };
-enum : uint8_t { kCHit = 1, kCUnsure = 2, kSHit = 4, kSUnsure = 8 };
 
 __device__ inline int lane_id() { return __lane_id(); }
 __device__ inline uint64_t lanes_below() { return (1ull << lane_id()) - 1ull; }
@@ -463,147 +460,31 @@ __global__ void __launch_bounds__(kBlock) k_cells(RmDev rm)
 }
 
 // ------------------------------------------------------------------------
-// k_grid: scan the edges of each item, keep those meeting a changed box
+// block-level helpers
 // ------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock) k_grid(RmDev rm)
+// exclusive prefix of v over the block; *total receives the block sum.
+// Contains barriers: every thread must call it.
+__device__ inline int block_scan(int v, int *total, int *wsum)
 {
-    __shared__ float s_lo[3][kSubCap], s_hi[3][kSubCap];
-    __shared__ int s_n, s_w[kWaves];
-    const Ctl *ctl = rm.ctl;
-    unsigned long long visited = 0;
-    if (ctl->status == RGG_OK) {
-        const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
-        const int n_chg = ctl->n_chg;
-        const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
-        const bool single = rm.ncells == 1;
-        const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
-        for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
-            const int2 item = rm.items[it];
-            const int64_t c = item.x;
-            const int32_t cx = (int32_t)(c % rm.gdim[0]);
-            const int32_t cy = (int32_t)((c / rm.gdim[0]) % rm.gdim[1]);
-            const int32_t cz = (int32_t)(c / ((int64_t)rm.gdim[0] * rm.gdim[1]));
-            __syncthreads();
-            if (tid == 0) {
-                s_n = 0;
-                if (item.y == 0) atomicAnd(&rm.cell_bits[c >> 5], ~(1u << (c & 31)));
-            }
-            __syncthreads();
-            // the changed entries whose cell range contains this cell
-            for (int j0 = 0; j0 < n_chg; j0 += kBlock) {
-                const int j = j0 + tid;
-                bool in = false;
-                if (j < n_chg) {
-                    const ChgEntry &en = rm.chg[j];
-                    in = single || (cx >= en.c0[0] && cx <= en.c1[0] && cy >= en.c0[1] &&
-                                    cy <= en.c1[1] && cz >= en.c0[2] && cz <= en.c1[2]);
-                }
-                const uint64_t m = __ballot(in);
-                if (lane == 0) s_w[wv] = __popcll(m);
-                __syncthreads();
-                int off = s_n, tot = 0;
-                for (int w = 0; w < kWaves; ++w) {
-                    off += w < wv ? s_w[w] : 0;
-                    tot += s_w[w];
-                }
-                const int s = off + __popcll(m & lanes_below());
-                if (in && s < kSubCap) {
-                    const ChgEntry &en = rm.chg[j];
-                    for (int k = 0; k < 3; ++k) {
-                        s_lo[k][s] = en.lo32[k];
-                        s_hi[k][s] = en.hi32[k];
-                    }
-                }
-                __syncthreads();
-                if (tid == 0) s_n += tot;
-                __syncthreads();
-            }
-            const int ns = s_n;
-            const int64_t beg = (int64_t)rm.cell_start[c] + (int64_t)item.y * rm.chunk;
-            const int64_t end = min((int64_t)rm.cell_start[c + 1], beg + rm.chunk);
-            // one edge per thread (chunk == block size)
-            const int64_t j = beg + tid;
-            bool keep = false;
-            int32_t e = 0;
-            if (j < end) {
-                e = rm.cell_edges[j];
-                const float4 bl = aabb[2 * (int64_t)e], bh = aabb[2 * (int64_t)e + 1];
-                bool hit = false;
-                if (ns <= kSubCap) {
-                    for (int s = 0; s < ns && !hit; ++s) {
-                        const float lo[3] = {s_lo[0][s], s_lo[1][s], s_lo[2][s]};
-                        const float hi[3] = {s_hi[0][s], s_hi[1][s], s_hi[2][s]};
-                        hit = overlap3(lo, hi, bl, bh);
-                    }
-                } else {
-                    for (int s = 0; s < n_chg && !hit; ++s) {
-                        const ChgEntry &en = rm.chg[s];
-                        hit = (single || (cx >= en.c0[0] && cx <= en.c1[0] && cy >= en.c0[1] &&
-                                          cy <= en.c1[1] && cz >= en.c0[2] && cz <= en.c1[2])) &&
-                              overlap3(en.lo32, en.hi32, bl, bh);
-                    }
-                }
-                if (hit) {
-                    if (single) {
-                        keep = true;
-                    } else {   // an edge registered in several active cells is kept once
-                        const uint32_t bit = 1u << (e & 31);
-                        keep = !(atomicOr(&rm.edge_bits[e >> 5], bit) & bit);
-                    }
-                }
-            }
-            const uint64_t m = __ballot(keep);
-            if (lane == 0) s_w[wv] = __popcll(m);
-            __syncthreads();
-            int off = 0, tot = 0;
-            for (int w = 0; w < kWaves; ++w) {
-                off += w < wv ? s_w[w] : 0;
-                tot += s_w[w];
-            }
-            if (keep) rm.work[beg + off + __popcll(m & lanes_below())] = e;
-            if (tid == 0) {
-                rm.item_cnt[it] = tot;
-                visited += (unsigned long long)max((int64_t)0, end - beg);
-            }
-        }
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    int wt;
+    const int pre = wave_prefix(v, &wt);
+    __syncthreads();
+    if (lane == 0) wsum[wv] = wt;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < kWaves; ++w) {
+        off += w < wv ? wsum[w] : 0;
+        tot += wsum[w];
     }
-    if (threadIdx.x == 0) rm.blk_stats[blockIdx.x * kStats + 4] = visited;
+    *total = tot;
+    return off + pre;
 }
 
-// ------------------------------------------------------------------------
-// candidates of one block: items it = blockIdx.x, + gridDim.x, ...; within
-// an item the wavefronts take candidates wv, wv + kWaves, ...
-// ------------------------------------------------------------------------
-
-struct Cursor {
-    int it, k, cnt;
-    int64_t beg;
-};
-
-__device__ inline bool cursor_next(const RmDev &rm, int n_items, Cursor &cu, int wv, int64_t *slot)
-{
-    for (;;) {
-        if (cu.it >= n_items) return false;
-        if (cu.k < 0) {
-            const int2 item = rm.items[cu.it];
-            cu.cnt = rm.item_cnt[cu.it];
-            cu.beg = (int64_t)rm.cell_start[item.x] + (int64_t)item.y * rm.chunk;
-            cu.k = wv;
-        }
-        if (cu.k < cu.cnt) {
-            *slot = cu.beg + cu.k;
-            cu.k += kWaves;
-            return true;
-        }
-        cu.it += gridDim.x;
-        cu.k = -1;
-    }
-}
-
-// Adds the counter deltas of one edge.  Each edge is owned by one wavefront
-// within a kernel, so the adds need no returned value: they are issued as
-// fire-and-forget atomics and cost no round trip.
+// Adds the counter deltas of one edge as fire-and-forget atomics (no value is
+// returned, so they cost no round trip; integer adds commute, so the result
+// does not depend on their order).
 __device__ inline void add_counts(const RmDev &rm, int64_t e, int dC, int dS)
 {
     int *c = reinterpret_cast<int *>(rm.cnt + e);
@@ -611,17 +492,423 @@ __device__ inline void add_counts(const RmDev &rm, int64_t e, int dC, int dS)
     if (dS) __hip_atomic_fetch_add(c + 1, dS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+__device__ inline int32_t clamp_cell(double x, double org, double inv, int32_t n)
+{
+    int32_t c = cell_of(x, org, inv, n);
+    return c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
+}
+
 // ------------------------------------------------------------------------
-// per-wavefront LDS scratch of the classify kernels
+// k_item: one block per grid work item (cell c, chunk of 256 of its edges).
+//
+//   1. every thread owns one edge of the item; the changed entries covering
+//      the cell are staged in LDS (tiles of 256); a thread lists the entries
+//      whose box meets its edge's box.  With several cells a pair is taken
+//      only by the cell holding the lower corner of the two boxes'
+//      intersection, so each (edge, entry) pair is tested exactly once.
+//   2. outer test, lanes = (pair, sphere): capsule of sphere i against the
+//      entry's box (FP32: separation and end-sphere tests first, the exact
+//      segment-box minimum where they do not decide).
+//   3. inner test, lanes = (pair, sphere whose capsule met, configuration):
+//      that sphere's copies against the box.
+//   4. per pair C and S; the edge's counter deltas are summed in LDS and
+//      added once per edge.  In FP32 a pair whose decision fell inside the
+//      rounding band goes to the block's re-test region; if that region is
+//      full the whole item is deferred to the binary64 item kernel.
 // ------------------------------------------------------------------------
 
-struct WaveScratch {
-    int act[kTile];   // staged-entry index of each pair of the current edge
-    int lst[64];      // sphere indices whose copies are tested
+constexpr int kSubTile = 256;   // changed entries staged per tile
+constexpr int kPairCap = 512;   // pairs per round (two per thread)
+constexpr int kRowCap = 1024;   // (pair, sphere) rows per copy round
+
+template <typename T>
+struct ItemLds {
+    T lo[3][kSubTile], hi[3][kSubTile];
+    float sb[kSubTile];
+    int sign[kSubTile], gidx[kSubTile];
+    int64_t es0[kBlock];                 // first sample of each edge of the item
+    int edge[kBlock], ej[kBlock];        // edge id, configurations per sphere
+    float es[kBlock];                    // edge s (largest |coordinate| of its box)
+    int dC[kBlock], dS[kBlock];
+    uint16_t pe[kPairCap];               // edge slot << 8 | staged entry
+    unsigned long long hm[kPairCap], um[kPairCap];
+    uint32_t roff[kPairCap], sf[kPairCap];
+    uint32_t row[kRowCap];               // pair << 6 | sphere
+    uint32_t rcopy[kRowCap + 1];
+    int wsum[kWaves];
+    int rc_n, rc_start, defer, df_n;
+    unsigned long long acc[kStats];
 };
 
-// Lane mapping of the copies of up to 64/jw spheres onto one wavefront:
-// lane -> (sub = lane / jw, jj = lane % jw), jw = min(J, 64) configurations.
+template <int D, typename T>
+__device__ inline bool pair_owned(const RmDev &rm, const float4 &bl, const T *lo32, int64_t c)
+{
+    // lower corner of the intersection of the edge box and the entry box
+    int64_t cell = 0, mul = 1;
+    for (int k = 0; k < D; ++k) {
+        const float ek = k == 0 ? bl.x : (k == 1 ? bl.y : bl.z);
+        const float x = fmaxf(ek, (float)lo32[k]);
+        cell += (int64_t)clamp_cell((double)x, rm.gorg[k], rm.ginv, rm.gdim[k]) * mul;
+        mul *= rm.gdim[k];
+    }
+    return cell == c;
+}
+
+template <int D, typename T>
+__global__ void __launch_bounds__(kBlock) k_item(RmDev rm, int deferred)
+{
+    constexpr bool kF32 = std::is_same<T, float>::value;
+    __shared__ ItemLds<T> L;
+    __shared__ T s_rad2[64];
+    const Ctl *ctl = rm.ctl;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    const int B = rm.B;
+    const int Gw = 64 / B, slot = lane / B, ci = lane - slot * B;
+    const uint64_t gmask = B == 64 ? ~0ull : ((1ull << B) - 1ull);
+    if (tid < kStats) L.acc[tid] = 0;
+    if (tid < B) s_rad2[tid] = kF32 ? (T)rm.rad2_32[tid] : (T)(rm.rad64[tid] * rm.rad64[tid]);
+    if (tid == 0) {
+        L.rc_n = 0;
+        L.df_n = 0;
+    }
+    __syncthreads();
+    unsigned long long n_pairs = 0, n_outer = 0, bytes = 0, visited = 0, cand = 0;
+    const int status = ctl->status;
+    const int n_chg = ctl->n_chg;
+    const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
+    const bool single = rm.ncells == 1;
+    const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
+    const T *capb = kF32 ? (const T *)rm.cap32 : (const T *)rm.cap64;
+    const T *samp = kF32 ? (const T *)rm.samp32 : (const T *)rm.samp64;
+    const float band_rel = rm.band_rel;
+    const int n_list = status != RGG_OK ? 0 : (deferred ? rm.df_cnt[blockIdx.x] : n_items);
+    const int first = deferred ? 0 : (int)blockIdx.x, stride = deferred ? 1 : (int)gridDim.x;
+    for (int li = first; li < n_list; li += stride) {
+        const int it = deferred ? rm.df[(int64_t)blockIdx.x * rm.df_cap + li] : li;
+        const int2 item = rm.items[it];
+        const int64_t c = item.x;
+        const int32_t cx = (int32_t)(c % rm.gdim[0]);
+        const int32_t cy = (int32_t)((c / rm.gdim[0]) % rm.gdim[1]);
+        const int32_t cz = (int32_t)(c / ((int64_t)rm.gdim[0] * rm.gdim[1]));
+        const int64_t beg = (int64_t)rm.cell_start[c] + (int64_t)item.y * rm.chunk;
+        const int64_t end = min((int64_t)rm.cell_start[c + 1], beg + rm.chunk);
+        const bool have = beg + tid < end;
+        int e = 0;
+        float4 bl = make_float4(0, 0, 0, 0), bh = bl;
+        int64_t s0 = 0;
+        int J = 0;
+        if (have) {
+            e = rm.cell_edges[beg + tid];
+            bl = aabb[2 * (int64_t)e];
+            bh = aabb[2 * (int64_t)e + 1];
+            s0 = rm.p_fixed ? (int64_t)e * rm.p_fixed : rm.soff[e];
+            J = (int)((rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0) / B);
+            ++visited;
+            bytes += 32;
+        }
+        __syncthreads();
+        L.edge[tid] = e;
+        L.es[tid] = bl.w;
+        L.es0[tid] = s0;
+        L.ej[tid] = J;
+        L.dC[tid] = 0;
+        L.dS[tid] = 0;
+        if (tid == 0) {
+            L.rc_start = L.rc_n;
+            L.defer = 0;
+            // the main pass visits every item once: clear the cell's mark with
+            // its first chunk, so the next update starts from zero marks
+            if (!deferred && item.y == 0) atomicAnd(&rm.cell_bits[c >> 5], ~(1u << (c & 31)));
+        }
+        int my_pairs = 0;
+        for (int j0 = 0; j0 < n_chg; j0 += kSubTile) {
+            // stage the entries covering this cell
+            const int j = j0 + tid;
+            bool in = false;
+            if (j < n_chg) {
+                const ChgEntry &en = rm.chg[j];
+                in = single || (cx >= en.c0[0] && cx <= en.c1[0] && cy >= en.c0[1] && cy <= en.c1[1] &&
+                                cz >= en.c0[2] && cz <= en.c1[2]);
+            }
+            int nt;
+            const int pos = block_scan(in ? 1 : 0, &nt, L.wsum);
+            if (in) {
+                const ChgEntry &en = rm.chg[j];
+                for (int k = 0; k < 3; ++k) {
+                    L.lo[k][pos] = kF32 ? (T)en.lo32[k] : (T)en.lo[k];
+                    L.hi[k][pos] = kF32 ? (T)en.hi32[k] : (T)en.hi[k];
+                }
+                L.sb[pos] = en.sbox;
+                L.sign[pos] = en.sign;
+                L.gidx[pos] = j;
+            }
+            __syncthreads();
+            if (nt == 0) continue;
+            // pairs of this thread's edge with the staged entries
+            auto meets = [&](int s) {
+                float lo[3], hi[3];
+                if constexpr (kF32) {
+                    for (int k = 0; k < 3; ++k) {
+                        lo[k] = L.lo[k][s];
+                        hi[k] = L.hi[k][s];
+                    }
+                } else {
+                    const ChgEntry &en = rm.chg[L.gidx[s]];
+                    for (int k = 0; k < 3; ++k) {
+                        lo[k] = en.lo32[k];
+                        hi[k] = en.hi32[k];
+                    }
+                }
+                if (!overlap3(lo, hi, bl, bh)) return false;
+                return single || pair_owned<D, float>(rm, bl, lo, c);
+            };
+            int cnt = 0;
+            if (have)
+                for (int s = 0; s < nt; ++s) cnt += meets(s) ? 1 : 0;
+            my_pairs += cnt;
+            int tp;
+            const int pre = block_scan(cnt, &tp, L.wsum);
+            for (int r0 = 0; r0 < tp; r0 += kPairCap) {
+                const int np = min(kPairCap, tp - r0);
+                if (cnt > 0 && pre < r0 + np && pre + cnt > r0) {
+                    int k = pre;
+                    for (int s = 0; s < nt && k < r0 + np; ++s) {
+                        if (!meets(s)) continue;
+                        if (k >= r0) L.pe[k - r0] = (uint16_t)((tid << 8) | s);
+                        ++k;
+                    }
+                }
+                __syncthreads();
+                if (tid == 0) n_pairs += np;
+                // ---- outer test: lanes = (pair, sphere)
+                for (int p0 = 0; p0 < np; p0 += kWaves * Gw) {
+                    const int p = p0 + wv * Gw + slot;
+                    int cls = kMiss;
+                    T A[D], Bq[D], lo[D], hi[D], R2 = T(0);
+                    float band = 0.0f;
+                    if (slot < Gw && p < np) {
+                        const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
+                        const T *cp = capb + (int64_t)L.edge[te] * (2 * D + 1) * B;
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            A[k] = cp[k * B + ci];
+                            Bq[k] = cp[(D + k) * B + ci];
+                            lo[k] = L.lo[k][s];
+                            hi[k] = L.hi[k][s];
+                        }
+                        const T R = cp[2 * D * B + ci];
+                        R2 = R * R;
+                        if constexpr (kF32) {
+                            const float sc = fmaxf(L.es[te], L.sb[s]);
+                            band = band_rel * sc * sc;
+                            float sep = 0.0f;
+#pragma unroll
+                            for (int k = 0; k < D; ++k)
+                                sep = fmaxf(sep, fmaxf(lo[k] - fmaxf(A[k], Bq[k]), fminf(A[k], Bq[k]) - hi[k]));
+                            const float m_end = fminf(point_box32<D>(A, lo, hi), point_box32<D>(Bq, lo, hi)) - R2;
+                            cls = (sep > 0.0f && sep * sep - R2 > band) ? kMiss : (m_end < -band ? kHit : kOpen);
+                        } else {
+                            cls = segbox64<D>(A, Bq, lo, hi) <= R2 ? kHit : kMiss;
+                        }
+                    }
+                    if constexpr (kF32) {
+                        if (__ballot(cls == kOpen)) {
+                            if (cls == kOpen) cls = classify_margin(segbox32<D>(A, Bq, lo, hi) - R2, band);
+                        }
+                    }
+                    const uint64_t hmw = __ballot(cls == kHit), umw = __ballot(cls == kUnsure);
+                    if (slot < Gw && ci == 0 && p < np) {
+                        L.hm[p] = (hmw >> (slot * B)) & gmask;
+                        L.um[p] = (umw >> (slot * B)) & gmask;
+                    }
+                }
+                __syncthreads();
+                // ---- rows: one per (pair, sphere whose capsule met)
+                const int pa = tid, pb = tid + kBlock;
+                const int ra = pa < np ? __popcll(L.hm[pa]) : 0;
+                const int rb = pb < np ? __popcll(L.hm[pb]) : 0;
+                int nrows;
+                const int rpre = block_scan(ra + rb, &nrows, L.wsum);
+                if (pa < np) {
+                    L.roff[pa] = rpre;
+                    L.sf[pa] = 0;
+                }
+                if (pb < np) {
+                    L.roff[pb] = rpre + ra;
+                    L.sf[pb] = 0;
+                }
+                __syncthreads();
+                for (int q0 = 0; q0 < nrows; q0 += kRowCap) {
+                    const int nr = min(kRowCap, nrows - q0);
+                    for (int h = 0; h < 2; ++h) {
+                        const int p = tid + h * kBlock;
+                        if (p >= np) continue;
+                        uint64_t m = L.hm[p];
+                        int r = L.roff[p];
+                        while (m && r < q0 + nr) {
+                            const int i = __ffsll((unsigned long long)m) - 1;
+                            m &= m - 1;
+                            if (r >= q0) L.row[r - q0] = ((uint32_t)p << 6) | (uint32_t)i;
+                            ++r;
+                        }
+                    }
+                    __syncthreads();
+                    // copies of each row: fixed count, or a scan over the rows
+                    const int jfix = rm.p_fixed ? rm.p_fixed / B : 0;
+                    int ncopies = nr * jfix;
+                    if (!jfix) {
+                        int cj[4], sum = 0;
+                        for (int h = 0; h < 4; ++h) {
+                            const int r = tid * 4 + h;
+                            cj[h] = r < nr ? L.ej[L.pe[L.row[r] >> 6] >> 8] : 0;
+                            sum += cj[h];
+                        }
+                        const int cpre = block_scan(sum, &ncopies, L.wsum);
+                        int acc = cpre;
+                        for (int h = 0; h < 4; ++h) {
+                            const int r = tid * 4 + h;
+                            if (r < nr) L.rcopy[r] = acc;
+                            acc += cj[h];
+                        }
+                        if (tid == 0) L.rcopy[nr] = ncopies;
+                        __syncthreads();
+                    }
+                    for (int c0 = 0; c0 < ncopies; c0 += kBlock) {
+                        const int cidx = c0 + tid;
+                        int cls = kMiss, p = 0;
+                        if (cidx < ncopies) {
+                            int r, jj;
+                            if (jfix) {
+                                r = cidx / jfix;
+                                jj = cidx - r * jfix;
+                            } else {
+                                int lo_ = 0, hi_ = nr - 1;   // last row with rcopy[r] <= cidx
+                                while (lo_ < hi_) {
+                                    const int mid = (lo_ + hi_ + 1) >> 1;
+                                    if (L.rcopy[mid] <= (uint32_t)cidx) lo_ = mid;
+                                    else hi_ = mid - 1;
+                                }
+                                r = lo_;
+                                jj = cidx - (int)L.rcopy[r];
+                            }
+                            const uint32_t rv = L.row[r];
+                            p = (int)(rv >> 6);
+                            const int i = (int)(rv & 63u);
+                            const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
+                            const int Je = L.ej[te];
+                            const int64_t P = (int64_t)Je * B;
+                            const T *sb = samp + D * L.es0[te] + (int64_t)i * Je + jj;
+                            T q[D], lo[D], hi[D];
+#pragma unroll
+                            for (int k = 0; k < D; ++k) {
+                                q[k] = sb[k * P];
+                                lo[k] = L.lo[k][s];
+                                hi[k] = L.hi[k][s];
+                            }
+                            bytes += D * sizeof(T);
+                            if constexpr (kF32) {
+                                const float sc = fmaxf(L.es[te], L.sb[s]);
+                                cls = classify_margin(point_box32<D>(q, lo, hi) - s_rad2[i], band_rel * sc * sc);
+                            } else {
+                                cls = point_box64<D>(q, lo, hi) <= s_rad2[i] ? kHit : kMiss;
+                            }
+                        }
+                        if (cls == kHit) atomicOr(&L.sf[p], 1u);
+                        else if (cls == kUnsure) atomicOr(&L.sf[p], 2u);
+                    }
+                    __syncthreads();
+                }
+                // ---- decisions
+                int unsure_n = 0;
+                int2 rec0 = make_int2(0, 0), rec1 = make_int2(0, 0);   // registers, not a local array
+                for (int h = 0; h < 2; ++h) {
+                    const int p = tid + h * kBlock;
+                    if (p >= np) continue;
+                    const uint64_t hmp = L.hm[p], ump = kF32 ? L.um[p] : 0ull;
+                    if (!hmp && !ump) continue;
+                    const uint32_t f = L.sf[p];
+                    const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
+                    const bool unsure = kF32 && (!hmp || (!(f & 1u) && ((f & 2u) || ump)));
+                    if (unsure) {
+                        const int2 r = make_int2(L.edge[te], L.gidx[s]);
+                        if (unsure_n == 0) rec0 = r;
+                        else rec1 = r;
+                        ++unsure_n;
+                    } else {
+                        const int sign = L.sign[s];
+                        atomicAdd(&L.dC[te], sign);
+                        if (f & 1u) atomicAdd(&L.dS[te], sign);
+                        ++n_outer;
+                    }
+                }
+                if constexpr (kF32) {
+                    int tot_u;
+                    const int upre = block_scan(unsure_n, &tot_u, L.wsum);
+                    if (tot_u > 0) {
+                        const int base = L.rc_n;
+                        const bool fits = !L.defer && base + tot_u <= rm.rc_cap;
+                        if (fits) {
+                            int2 *dst = rm.rc + (int64_t)blockIdx.x * rm.rc_cap + base + upre;
+                            if (unsure_n > 0) dst[0] = rec0;
+                            if (unsure_n > 1) dst[1] = rec1;
+                        }
+                        __syncthreads();
+                        if (tid == 0) {
+                            if (fits) L.rc_n = base + tot_u;
+                            else L.defer = 1;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (have && my_pairs > 0) {
+            ++cand;
+            bytes += (2 * D + 1) * B * sizeof(T) + 16;
+        }
+        __syncthreads();
+        if (!L.defer) {
+            if (have) add_counts(rm, e, L.dC[tid], L.dS[tid]);
+        } else if (tid == 0) {
+            L.rc_n = L.rc_start;
+            rm.df[(int64_t)blockIdx.x * rm.df_cap + L.df_n] = it;
+            L.df_n += 1;
+        }
+    }
+    __syncthreads();
+    atomicAdd(&L.acc[0], n_pairs);
+    atomicAdd(&L.acc[1], n_outer);
+    atomicAdd(&L.acc[3], bytes);
+    atomicAdd(&L.acc[4], visited);
+    atomicAdd(&L.acc[5], cand);
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long *bs = rm.blk_stats + blockIdx.x * kStats;
+        if (!deferred) {
+            bs[0] = L.acc[0];
+            bs[1] = L.acc[1];
+            bs[2] = 0;
+            bs[3] = L.acc[3];
+            bs[4] = L.acc[4];
+            bs[5] = L.acc[5];
+            if (kF32) {
+                rm.rc_cnt[blockIdx.x] = L.rc_n;
+                rm.df_cnt[blockIdx.x] = L.df_n;
+            }
+        } else {
+            bs[1] += L.acc[1];
+            bs[2] += L.acc[0];
+            bs[3] += L.acc[3];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------
+// k_recheck_pairs: binary64 decision of every pair an FP32 block left unsure
+// (the definition: C = some capsule meets, S = some sphere's capsule and one
+// of its copies meet), one wavefront per pair
+// ------------------------------------------------------------------------
+
 struct CopyMap {
     int J, jw, spc, sub, jj;
 };
@@ -637,29 +924,15 @@ __device__ inline CopyMap copy_map(int J)
     return c;
 }
 
-// writes the indices of the set bits of m (wave-uniform, bits < B) to lst
-__device__ inline int list_spheres(uint64_t m, int B, int *lst)
+template <int D>
+__device__ bool copies_meet64(const RmDev &rm, const double *sb, int64_t P, const CopyMap &cm, uint64_t m,
+                              const double *lo, const double *hi, const double *rad, int *lst,
+                              unsigned long long *bytes)
 {
     const int lane = lane_id();
-    if (lane < B && ((m >> lane) & 1ull)) lst[__popcll(m & lanes_below())] = lane;
+    if (lane < rm.B && ((m >> lane) & 1ull)) lst[__popcll(m & lanes_below())] = lane;
     wave_sync();
-    return __popcll(m);
-}
-
-// ------------------------------------------------------------------------
-// binary64 classification of one edge against entries [t0, t0+nt): the
-// definition, sphere by sphere (C: some capsule meets the box; S: for some
-// sphere, its capsule and one of its copies meet the box).  Used by the FP64
-// mode and by the re-test of the FP32 mode; every lane returns the same
-// counter deltas.
-// ------------------------------------------------------------------------
-
-template <int D>
-__device__ bool copies_meet64(const RmDev &rm, const double *sb, int64_t P, const CopyMap &cm,
-                              uint64_t m, const double *lo, const double *hi, const double *rad,
-                              int *lst, unsigned long long *bytes)
-{
-    const int nsph = list_spheres(m, rm.B, lst);
+    const int nsph = __popcll(m);
     for (int sp0 = 0; sp0 < nsph; sp0 += cm.spc) {
         for (int j0 = 0; j0 < cm.J; j0 += cm.jw) {
             const int js = j0 + cm.jj;
@@ -674,376 +947,76 @@ __device__ bool copies_meet64(const RmDev &rm, const double *sb, int64_t P, cons
                 hit = point_box64<D>(p, lo, hi) <= r * r;
             }
             *bytes += (unsigned long long)(__popcll(__ballot(valid)) * D * 8);
-            if (__ballot(hit)) return true;
+            if (__ballot(hit)) {
+                wave_sync();
+                return true;
+            }
         }
     }
+    wave_sync();
     return false;
 }
 
 template <int D>
-__device__ int2 edge_exact(const RmDev &rm, int64_t e, const ChgEntry *__restrict__ chg, int t0, int nt,
-                           WaveScratch &ws, const double *rad, unsigned long long *n_pairs,
-                           unsigned long long *n_outer, unsigned long long *bytes)
+__global__ void __launch_bounds__(kBlock) k_recheck_pairs(RmDev rm)
 {
-    const int lane = lane_id(), B = rm.B;
-    const int G = 64 / B, slot = lane / B, ci = lane - slot * B;
-    const uint64_t gmask = B == 64 ? ~0ull : ((1ull << B) - 1ull);
-    const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
-    const float4 bl = aabb[2 * e], bh = aabb[2 * e + 1];
-    int n_act = 0;
-    for (int b0 = 0; b0 < nt; b0 += 64) {
-        const int j = b0 + lane;
-        const bool ov = j < nt && overlap3(chg[t0 + j].lo32, chg[t0 + j].hi32, bl, bh);
-        const uint64_t m = __ballot(ov);
-        if (ov) ws.act[n_act + __popcll(m & lanes_below())] = t0 + j;
-        n_act += __popcll(m);
-    }
-    *bytes += 32;
-    wave_sync();
-    if (n_act == 0) return make_int2(0, 0);
-    *n_pairs += n_act;
-    const double *cp = rm.cap64 + e * (2 * D + 1) * B;
-    double A[D], Bp[D];
+    __shared__ int s_lst[kWaves][64];
+    __shared__ double s_rad[64];
+    __shared__ unsigned long long s_acc[3];
+    const Ctl *ctl = rm.ctl;
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    if (threadIdx.x < rm.B) s_rad[threadIdx.x] = rm.rad64[threadIdx.x];
+    if (threadIdx.x < 3) s_acc[threadIdx.x] = 0;
+    __syncthreads();
+    unsigned long long n_re = 0, n_outer = 0, bytes = 0;
+    const int n = ctl->status == RGG_OK ? rm.rc_cnt[blockIdx.x] : 0;
+    const int B = rm.B;
+    for (int k = wv; k < n; k += kWaves) {
+        const int2 pr = rm.rc[(int64_t)blockIdx.x * rm.rc_cap + k];
+        const int64_t e = pr.x;
+        const ChgEntry &en = rm.chg[pr.y];
+        double lo[D], hi[D];
 #pragma unroll
-    for (int k = 0; k < D; ++k) {
-        A[k] = cp[k * B + ci];
-        Bp[k] = cp[(D + k) * B + ci];
-    }
-    const double R = cp[2 * D * B + ci];
-    *bytes += (unsigned long long)((2 * D + 1) * B * 8);
-    const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
-    const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
-    const double *sb = rm.samp64 + D * s0;
-    const CopyMap cm = copy_map((int)(P / B));
-    int dC = 0, dS = 0;
-    for (int a0 = 0; a0 < n_act; a0 += G) {
-        const int a = a0 + slot;
+        for (int d = 0; d < D; ++d) {
+            lo[d] = en.lo[d];
+            hi[d] = en.hi[d];
+        }
         bool hit = false;
-        if (slot < G && a < n_act) {
-            const ChgEntry &en = chg[ws.act[a]];
-            double lo[D], hi[D];
+        if (lane < B) {
+            const double *cp = rm.cap64 + e * (2 * D + 1) * B;
+            double A[D], Bp[D];
 #pragma unroll
-            for (int k = 0; k < D; ++k) {
-                lo[k] = en.lo[k];
-                hi[k] = en.hi[k];
+            for (int d = 0; d < D; ++d) {
+                A[d] = cp[d * B + lane];
+                Bp[d] = cp[(D + d) * B + lane];
             }
+            const double R = cp[2 * D * B + lane];
             hit = segbox64<D>(A, Bp, lo, hi) <= R * R;
         }
         const uint64_t hm = __ballot(hit);
-        for (int s = 0; s < G && a0 + s < n_act; ++s) {
-            const uint64_t m = (hm >> (s * B)) & gmask;
-            if (!m) continue;
-            const ChgEntry &en = chg[ws.act[a0 + s]];
-            double lo[D], hi[D];
-#pragma unroll
-            for (int k = 0; k < D; ++k) {
-                lo[k] = en.lo[k];
-                hi[k] = en.hi[k];
-            }
-            ++*n_outer;
-            dC += en.sign;
-            if (copies_meet64<D>(rm, sb, P, cm, m, lo, hi, rad, ws.lst, bytes)) dS += en.sign;
-        }
+        bytes += (2 * D + 1) * B * 8;
+        ++n_re;
+        if (!hm) continue;
+        const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
+        const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
+        const CopyMap cm = copy_map((int)(P / B));
+        const bool S = copies_meet64<D>(rm, rm.samp64 + D * s0, P, cm, hm, lo, hi, s_rad, s_lst[wv], &bytes);
+        ++n_outer;
+        if (lane == 0) add_counts(rm, e, en.sign, S ? en.sign : 0);
     }
-    wave_sync();
-    return make_int2(dC, dS);
-}
-
-// ------------------------------------------------------------------------
-// k_classify, FP64 mode
-// ------------------------------------------------------------------------
-
-__device__ inline void store_partials(const RmDev &rm, unsigned long long n_pairs,
-                                      unsigned long long n_outer, unsigned long long bytes)
-{
-    __shared__ unsigned long long s_acc[3];
-    if (threadIdx.x < 3) s_acc[threadIdx.x] = 0;
-    __syncthreads();
-    if (lane_id() == 0) {
-        atomicAdd(&s_acc[0], n_pairs);
+    if (lane == 0) {
+        atomicAdd(&s_acc[0], n_re);
         atomicAdd(&s_acc[1], n_outer);
         atomicAdd(&s_acc[2], bytes);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long *bs = rm.blk_stats + blockIdx.x * kStats;
-        bs[0] = s_acc[0];
-        bs[1] = s_acc[1];
-        bs[2] = 0;
-        bs[3] = s_acc[2];
+        bs[1] += s_acc[1];
+        bs[2] += s_acc[0];
+        bs[3] += s_acc[2];
     }
 }
-
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_classify64(RmDev rm)
-{
-    __shared__ WaveScratch s_ws[kWaves];
-    __shared__ double s_rad[64];
-    const Ctl *ctl = rm.ctl;
-    if (threadIdx.x < rm.B) s_rad[threadIdx.x] = rm.rad64[threadIdx.x];
-    __syncthreads();
-    unsigned long long n_pairs = 0, n_outer = 0, bytes = 0;
-    if (ctl->status == RGG_OK) {
-        const int n_chg = ctl->n_chg;
-        const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
-        const int wv = threadIdx.x >> 6;
-        Cursor cu = {(int)blockIdx.x, -1, 0, 0};
-        int64_t slot;
-        while (cursor_next(rm, n_items, cu, wv, &slot)) {
-            const int64_t e = rm.work[slot];
-            int2 d = make_int2(0, 0);
-            for (int t0 = 0; t0 < n_chg; t0 += kTile) {
-                int2 x = edge_exact<D>(rm, e, rm.chg, t0, min(kTile, n_chg - t0), s_ws[wv], s_rad,
-                                       &n_pairs, &n_outer, &bytes);
-                d.x += x.x;
-                d.y += x.y;
-            }
-            if (lane_id() == 0) add_counts(rm, e, d.x, d.y);
-            bytes += 16;
-        }
-    }
-    store_partials(rm, n_pairs, n_outer, bytes);
-}
-
-// ------------------------------------------------------------------------
-// k_classify, FP32 mode: one wavefront per candidate edge.  A decision is
-// kept only when its binary32 margin lies outside the rounding band; a tile
-// of pairs with any undecided pair is left whole to k_recheck.
-// ------------------------------------------------------------------------
-
-// copies of the spheres in m against one box: kHit (some copy certainly
-// meets it), kMiss (every copy certainly misses) or kUnsure
-template <int D>
-__device__ int copies_meet32(const float *sb, int64_t P, const CopyMap &cm, uint64_t m, int B,
-                             const float *lo, const float *hi, float band, const float *rad2,
-                             int *lst, unsigned long long *bytes)
-{
-    const int nsph = list_spheres(m, B, lst);
-    bool unsure = false;
-    for (int sp0 = 0; sp0 < nsph; sp0 += cm.spc) {
-        for (int j0 = 0; j0 < cm.J; j0 += cm.jw) {
-            const int js = j0 + cm.jj;
-            const bool valid = cm.sub < cm.spc && sp0 + cm.sub < nsph && js < cm.J;
-            int cls = kMiss;
-            if (valid) {
-                const int i = lst[sp0 + cm.sub];
-                float p[D];
-#pragma unroll
-                for (int k = 0; k < D; ++k) p[k] = sb[k * P + i * cm.J + js];
-                cls = classify_margin(point_box32<D>(p, lo, hi) - rad2[i], band);
-            }
-            *bytes += (unsigned long long)(__popcll(__ballot(valid)) * D * 4);
-            if (__ballot(cls == kHit)) return kHit;
-            unsure |= __ballot(cls == kUnsure) != 0;
-        }
-    }
-    return unsure ? kUnsure : kMiss;
-}
-
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_classify32(RmDev rm)
-{
-    __shared__ float s_lo[3][kTile], s_hi[3][kTile];
-    __shared__ float s_sb[kTile];
-    __shared__ int s_sign[kTile];
-    __shared__ WaveScratch s_ws[kWaves];
-    __shared__ float s_rad2[64];
-    const Ctl *ctl = rm.ctl;
-    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
-    if (tid < rm.B) s_rad2[tid] = rm.rad2_32[tid];
-    unsigned long long n_pairs = 0, n_outer = 0, bytes = 0;
-    if (ctl->status == RGG_OK) {
-        const int n_chg = ctl->n_chg;
-        const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
-        const int B = rm.B;
-        const int G = 64 / B, slot = lane / B, ci = lane - slot * B;
-        const uint64_t gmask = B == 64 ? ~0ull : ((1ull << B) - 1ull);
-        const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
-        const float band_rel = rm.band_rel;
-        WaveScratch &ws = s_ws[wv];
-        for (int t0 = 0, tile = 0; t0 < n_chg; t0 += kTile, ++tile) {
-            const int nt = min(kTile, n_chg - t0);
-            __syncthreads();
-            for (int j = tid; j < nt; j += kBlock) {
-                const ChgEntry &en = rm.chg[t0 + j];
-                for (int k = 0; k < 3; ++k) {
-                    s_lo[k][j] = en.lo32[k];
-                    s_hi[k][j] = en.hi32[k];
-                }
-                s_sb[j] = en.sbox;
-                s_sign[j] = en.sign;
-            }
-            __syncthreads();
-            Cursor cu = {(int)blockIdx.x, -1, 0, 0};
-            int64_t wslot;
-            while (cursor_next(rm, n_items, cu, wv, &wslot)) {
-                const int64_t e = rm.work[wslot];
-                const float4 bl = aabb[2 * e], bh = aabb[2 * e + 1];
-                const float *cp = rm.cap32 + e * (2 * D + 1) * B;
-                float A[D], Bq[D];
-#pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    A[k] = cp[k * B + ci];
-                    Bq[k] = cp[(D + k) * B + ci];
-                }
-                const float R = cp[2 * D * B + ci];
-                const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
-                const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
-                // pretest against the staged entries
-                int n_act = 0;
-                for (int b0 = 0; b0 < nt; b0 += 64) {
-                    const int j = b0 + lane;
-                    bool ov = false;
-                    if (j < nt) {
-                        const float lo[3] = {s_lo[0][j], s_lo[1][j], s_lo[2][j]};
-                        const float hi[3] = {s_hi[0][j], s_hi[1][j], s_hi[2][j]};
-                        ov = overlap3(lo, hi, bl, bh);
-                    }
-                    const uint64_t m = __ballot(ov);
-                    if (ov) ws.act[n_act + __popcll(m & lanes_below())] = j;
-                    n_act += __popcll(m);
-                }
-                bytes += 32;
-                uint32_t unsure_tiles = 0;
-                if (n_act > 0) {
-                    wave_sync();
-                    n_pairs += n_act;
-                    bytes += (unsigned long long)((2 * D + 1) * B * 4);
-                    const float *sb = rm.samp32 + D * s0;
-                    const CopyMap cm = copy_map((int)(P / B));
-                    const float R2 = R * R;
-                    bool any_unsure = false;
-                    int dC = 0, dS = 0;
-                    for (int a0 = 0; a0 < n_act; a0 += G) {
-                        // capsule tests: separation -> miss, an end sphere
-                        // meeting the box -> hit, else the full minimum
-                        const int a = a0 + slot;
-                        int cls = kMiss;
-                        float lo[D], hi[D], band = 0.0f;
-                        if (slot < G && a < n_act) {
-                            const int j = ws.act[a];
-#pragma unroll
-                            for (int k = 0; k < D; ++k) {
-                                lo[k] = s_lo[k][j];
-                                hi[k] = s_hi[k][j];
-                            }
-                            const float s = fmaxf(bl.w, s_sb[j]);
-                            band = band_rel * s * s;
-                            float sep = 0.0f;
-#pragma unroll
-                            for (int k = 0; k < D; ++k)
-                                sep = fmaxf(sep, fmaxf(lo[k] - fmaxf(A[k], Bq[k]), fminf(A[k], Bq[k]) - hi[k]));
-                            const float m_end = fminf(point_box32<D>(A, lo, hi), point_box32<D>(Bq, lo, hi)) - R2;
-                            cls = (sep > 0.0f && sep * sep - R2 > band) ? kMiss : (m_end < -band ? kHit : kOpen);
-                        }
-                        if (__ballot(cls == kOpen)) {
-                            if (cls == kOpen) cls = classify_margin(segbox32<D>(A, Bq, lo, hi) - R2, band);
-                        }
-                        const uint64_t hm = __ballot(cls == kHit), um = __ballot(cls == kUnsure);
-                        // per pair: copies of the spheres whose capsule met
-                        for (int s = 0; s < G && a0 + s < n_act; ++s) {
-                            const uint64_t h = (hm >> (s * B)) & gmask, u = (um >> (s * B)) & gmask;
-                            if (!h) {
-                                any_unsure |= u != 0;   // C rests on undecided capsules
-                                continue;
-                            }
-                            const int j = ws.act[a0 + s];
-                            float plo[D], phi[D];
-#pragma unroll
-                            for (int k = 0; k < D; ++k) {
-                                plo[k] = s_lo[k][j];
-                                phi[k] = s_hi[k][j];
-                            }
-                            const float sc = fmaxf(bl.w, s_sb[j]);
-                            const int r = copies_meet32<D>(sb, P, cm, h, B, plo, phi, band_rel * sc * sc,
-                                                           s_rad2, ws.lst, &bytes);
-                            const int sign = s_sign[j];
-                            ++n_outer;
-                            if (r == kHit) {
-                                dC += sign;
-                                dS += sign;
-                            } else if (r == kUnsure || u) {
-                                any_unsure = true;
-                            } else {
-                                dC += sign;
-                            }
-                        }
-                    }
-                    if (any_unsure) {
-                        unsure_tiles = 1u << tile;
-                    } else if (lane == 0) {
-                        add_counts(rm, e, dC, dS);
-                    }
-                    bytes += 16;
-                    wave_sync();
-                }
-                if (lane == 0) rm.unsure[wslot] = tile == 0 ? unsure_tiles : (rm.unsure[wslot] | unsure_tiles);
-            }
-        }
-    }
-    store_partials(rm, n_pairs, n_outer, bytes);
-}
-
-// ------------------------------------------------------------------------
-// k_recheck: binary64 re-test of the tiles the FP32 filter left unsure.
-// Wavefronts scan the unsure marks of whole items, 64 candidates at a time.
-// ------------------------------------------------------------------------
-
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_recheck(RmDev rm)
-{
-    __shared__ WaveScratch s_ws[kWaves];
-    __shared__ double s_rad[64];
-    const Ctl *ctl = rm.ctl;
-    if (threadIdx.x < rm.B) s_rad[threadIdx.x] = rm.rad64[threadIdx.x];
-    __syncthreads();
-    if (ctl->status != RGG_OK) return;
-    const int n_chg = ctl->n_chg;
-    const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
-    const int lane = lane_id(), wv = threadIdx.x >> 6;
-    unsigned long long n_pairs = 0, n_outer = 0, bytes = 0;
-    for (int it = blockIdx.x * kWaves + wv; it < n_items; it += gridDim.x * kWaves) {
-        const int2 item = rm.items[it];
-        const int cnt = rm.item_cnt[it];
-        const int64_t beg = (int64_t)rm.cell_start[item.x] + (int64_t)item.y * rm.chunk;
-        for (int k0 = 0; k0 < cnt; k0 += 64) {
-            const uint32_t mk = k0 + lane < cnt ? rm.unsure[beg + k0 + lane] : 0u;
-            uint64_t fl = __ballot(mk != 0u);
-            while (fl) {
-                const int src = __ffsll((unsigned long long)fl) - 1;
-                fl &= fl - 1;
-                uint32_t mask = (uint32_t)__shfl((int)mk, src);
-                const int64_t e = rm.work[beg + k0 + src];
-                int2 d = make_int2(0, 0);
-                while (mask) {
-                    const int tile = __ffs(mask) - 1;
-                    mask &= mask - 1;
-                    const int t0 = tile * kTile;
-                    int2 x = edge_exact<D>(rm, e, rm.chg, t0, min(kTile, n_chg - t0), s_ws[wv], s_rad,
-                                           &n_pairs, &n_outer, &bytes);
-                    d.x += x.x;
-                    d.y += x.y;
-                }
-                if (lane == 0) add_counts(rm, e, d.x, d.y);
-            }
-        }
-    }
-    __shared__ unsigned long long s_acc[2];
-    if (threadIdx.x < 2) s_acc[threadIdx.x] = 0;
-    __syncthreads();
-    if (lane == 0) {
-        atomicAdd(&s_acc[0], n_pairs);   // pairs re-decided in binary64
-        atomicAdd(&s_acc[1], bytes);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long *bs = rm.blk_stats + blockIdx.x * kStats;
-        bs[2] = s_acc[0];
-        bs[3] += s_acc[1];
-    }
-}
-
-// ------------------------------------------------------------------------
 // ------------------------------------------------------------------------
 // labels and the ordered gray list
 // ------------------------------------------------------------------------
@@ -1132,79 +1105,112 @@ __global__ void __launch_bounds__(kBlock) k_write(RmDev rm, int64_t *gray, int64
     // the last block also folds the per-block statistics
     if (tid < kStats) s_st[tid] = 0;
     __syncthreads();
-    unsigned long long acc[kStats] = {0, 0, 0, 0, 0};
+    unsigned long long acc[kStats] = {0, 0, 0, 0, 0, 0};
     for (int b = tid; b < kStatBlocks; b += kBlock)
         for (int k = 0; k < kStats; ++k) acc[k] += rm.blk_stats[b * kStats + k];
     for (int k = 0; k < kStats; ++k) atomicAdd(&s_st[k], acc[k]);
     __syncthreads();
     if (tid == 0) {
-        int64_t cand = 0;
         res->n_gray = status == RGG_OK ? off : 0;
         res->n_pairs = (int64_t)s_st[0];
         res->n_outer_hits = (int64_t)s_st[1];
         res->n_rechecked = (int64_t)s_st[2];
         res->test_bytes = (int64_t)s_st[3];
         res->n_cells_visited = (int64_t)s_st[4];
-        (void)cand;
+        res->n_candidate_edges = (int64_t)s_st[5];
     }
 }
 
-// candidate count: sum of per-item counts, folded by one block
-__global__ void __launch_bounds__(kBlock) k_candidates(RmDev rm, rgg_update_result *res)
+}  // namespace
+
+namespace {
+
+void *item_fn(const RmDev &rm, bool f64)
 {
-    __shared__ int s_w[kWaves];
-    const Ctl *ctl = rm.ctl;
-    const int n_items = ctl->status == RGG_OK ? min(ctl->n_items, (int32_t)rm.items_cap) : 0;
-    int acc = 0;
-    for (int i = threadIdx.x; i < n_items; i += kBlock) acc += rm.item_cnt[i];
-    const int tot = block_sum(acc, s_w);
-    if (threadIdx.x == 0 && res) res->n_candidate_edges = tot;
+    if (rm.D == 3) return f64 ? (void *)k_item<3, double> : (void *)k_item<3, float>;
+    return f64 ? (void *)k_item<2, double> : (void *)k_item<2, float>;
+}
+
+void *recheck_fn(const RmDev &rm)
+{
+    return rm.D == 3 ? (void *)k_recheck_pairs<3> : (void *)k_recheck_pairs<2>;
+}
+
+struct Node {
+    void *fn;
+    dim3 grid, block;
+    int kind;   // 0 diff, 1 rm only, 2 item (deferred flag), 3 count, 4 write
+    int flag;
+};
+
+// the kernels of one update, in order; stage boundaries for the events after
+// the indices listed in `marks`
+int plan(const RmDev &rm, Node out[8])
+{
+    int n = 0;
+    out[n++] = {(void *)k_diff, dim3(1), dim3(kDiffBlock), 0, 0};
+    out[n++] = {(void *)k_cells, dim3(kCellsGrid), dim3(kBlock), 1, 0};
+    out[n++] = {item_fn(rm, !rm.mixed), dim3(kGrid), dim3(kBlock), 2, 0};
+    if (rm.mixed) {
+        out[n++] = {recheck_fn(rm), dim3(kGrid), dim3(kBlock), 1, 0};
+        out[n++] = {item_fn(rm, true), dim3(kGrid), dim3(kBlock), 2, 1};
+    }
+    out[n++] = {(void *)k_count, dim3(rm.ntiles), dim3(kBlock), 3, 0};
+    out[n++] = {(void *)k_write, dim3(rm.ntiles), dim3(kBlock), 4, 0};
+    return n;
 }
 
 }  // namespace
 
 hipError_t launch_update(const RmDev &rm, const UpdateArgs &a, hipStream_t s, hipEvent_t *ev)
 {
+    if (rm.chunk != kBlock) return hipErrorInvalidValue;   // one edge of an item per thread
+    Node nodes[8];
+    const int n = plan(rm, nodes);
     hipError_t err;
-#define RGG_TRY(x)                                 \
-    do {                                           \
-        if ((err = (x)) != hipSuccess) return err; \
-    } while (0)
-    if (rm.chunk != kBlock) return hipErrorInvalidValue;   // k_grid: one edge per thread
-    if (ev) RGG_TRY(hipEventRecord(ev[0], s));
-    k_diff<<<1, kDiffBlock, 0, s>>>(rm, a.old_b, a.new_b);
-    RGG_TRY(hipGetLastError());
-    if (ev) RGG_TRY(hipEventRecord(ev[1], s));
-    k_cells<<<kCellsGrid, kBlock, 0, s>>>(rm);
-    RGG_TRY(hipGetLastError());
-    if (ev) RGG_TRY(hipEventRecord(ev[2], s));
-    k_grid<<<kGrid, kBlock, 0, s>>>(rm);
-    RGG_TRY(hipGetLastError());
-    if (ev) RGG_TRY(hipEventRecord(ev[3], s));
-    if (rm.mixed) {
-        if (rm.D == 3) k_classify32<3><<<kGrid, kBlock, 0, s>>>(rm);
-        else k_classify32<2><<<kGrid, kBlock, 0, s>>>(rm);
-    } else {
-        if (rm.D == 3) k_classify64<3><<<kGrid, kBlock, 0, s>>>(rm);
-        else k_classify64<2><<<kGrid, kBlock, 0, s>>>(rm);
+    RmDev r = rm;
+    const rgg_box *ob = a.old_b, *nb = a.new_b;
+    uint8_t *lab = a.labels;
+    int64_t *gray = a.gray;
+    int64_t cap = a.gray_cap;
+    rgg_update_result *res = a.res;
+    int zero = 0, one = 1;
+    if (ev && (err = hipEventRecord(ev[0], s)) != hipSuccess) return err;
+    for (int k = 0; k < n; ++k) {
+        void *args_diff[] = {&r, (void *)&ob, (void *)&nb};
+        void *args_one[] = {&r};
+        void *args_item[] = {&r, nodes[k].flag ? (void *)&one : (void *)&zero};
+        void *args_count[] = {&r, &lab, &res, &zero};
+        void *args_write[] = {&r, &gray, &cap, &res, &zero};
+        void **args = nodes[k].kind == 0 ? args_diff
+                    : nodes[k].kind == 1 ? args_one
+                    : nodes[k].kind == 2 ? args_item
+                    : nodes[k].kind == 3 ? args_count
+                                         : args_write;
+        if ((err = hipLaunchKernel(nodes[k].fn, nodes[k].grid, nodes[k].block, args, 0, s)) != hipSuccess) return err;
+        if (ev) {
+            // ev[1] after diff, ev[2] after cells, ev[3] == ev[2] (the grid scan is
+            // part of the item kernel), ev[4] after the item kernel, ev[5] after
+            // the binary64 re-test, ev[6] after the labels
+            int mark = -1;
+            if (k == 0) mark = 1;
+            if (k == 1) mark = 2;
+            if (k == 2) mark = 4;
+            if (nodes[k].kind == 2 && nodes[k].flag) mark = 5;
+            if (!rm.mixed && k == 2) mark = 4;
+            if (mark == 2) {
+                if ((err = hipEventRecord(ev[2], s)) != hipSuccess) return err;
+                mark = 3;
+            }
+            if (mark == 4 && !rm.mixed) {
+                if ((err = hipEventRecord(ev[4], s)) != hipSuccess) return err;
+                mark = 5;
+            }
+            if (mark >= 0 && (err = hipEventRecord(ev[mark], s)) != hipSuccess) return err;
+        }
     }
-    RGG_TRY(hipGetLastError());
-    if (ev) RGG_TRY(hipEventRecord(ev[4], s));
-    if (rm.mixed) {
-        if (rm.D == 3) k_recheck<3><<<kGrid, kBlock, 0, s>>>(rm);
-        else k_recheck<2><<<kGrid, kBlock, 0, s>>>(rm);
-        RGG_TRY(hipGetLastError());
-    }
-    if (ev) RGG_TRY(hipEventRecord(ev[5], s));
-    k_count<<<rm.ntiles, kBlock, 0, s>>>(rm, a.labels, a.res, 0);
-    RGG_TRY(hipGetLastError());
-    k_write<<<rm.ntiles, kBlock, 0, s>>>(rm, a.gray, a.gray_cap, a.res, 0);
-    RGG_TRY(hipGetLastError());
-    k_candidates<<<1, kBlock, 0, s>>>(rm, a.res);
-    RGG_TRY(hipGetLastError());
-    if (ev) RGG_TRY(hipEventRecord(ev[6], s));
+    if (ev && (err = hipEventRecord(ev[6], s)) != hipSuccess) return err;
     return hipSuccess;
-#undef RGG_TRY
 }
 
 hipError_t launch_labels(const RmDev &rm, const UpdateArgs &a, hipStream_t s)
@@ -1220,6 +1226,8 @@ hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, 
                             hipGraphNode_t *last)
 {
     if (rm.chunk != kBlock) return hipErrorInvalidValue;
+    Node nodes[8];
+    const int n = plan(rm, nodes);
     // argument storage: hipGraphAddKernelNode copies the values
     RmDev r = rm;
     const rgg_box *ob = a.old_b, *nb = a.new_b;
@@ -1227,37 +1235,25 @@ hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, 
     int64_t *gray = a.gray;
     int64_t cap = a.gray_cap;
     rgg_update_result *res = a.res;
-    int zero = 0;
-    void *args_diff[] = {&r, (void *)&ob, (void *)&nb};
-    void *args_one[] = {&r};
-    void *args_count[] = {&r, &lab, &res, &zero};
-    void *args_write[] = {&r, &gray, &cap, &res, &zero};
-    void *args_cand[] = {&r, &res};
-    struct Node {
-        void *fn;
-        dim3 grid;
-        void **args;
-    };
-    void *cls = rm.mixed ? (rm.D == 3 ? (void *)k_classify32<3> : (void *)k_classify32<2>)
-                         : (rm.D == 3 ? (void *)k_classify64<3> : (void *)k_classify64<2>);
-    Node nodes[8];
-    int n = 0;
-    nodes[n++] = {(void *)k_diff, dim3(1), args_diff};
-    nodes[n++] = {(void *)k_cells, dim3(kCellsGrid), args_one};
-    nodes[n++] = {(void *)k_grid, dim3(kGrid), args_one};
-    nodes[n++] = {cls, dim3(kGrid), args_one};
-    if (rm.mixed) nodes[n++] = {rm.D == 3 ? (void *)k_recheck<3> : (void *)k_recheck<2>, dim3(kGrid), args_one};
-    nodes[n++] = {(void *)k_count, dim3(rm.ntiles), args_count};
-    nodes[n++] = {(void *)k_write, dim3(rm.ntiles), args_write};
-    nodes[n++] = {(void *)k_candidates, dim3(1), args_cand};
+    int zero = 0, one = 1;
     hipGraphNode_t prev = dep;
     for (int k = 0; k < n; ++k) {
+        void *args_diff[] = {&r, (void *)&ob, (void *)&nb};
+        void *args_one[] = {&r};
+        void *args_item[] = {&r, nodes[k].flag ? (void *)&one : (void *)&zero};
+        void *args_count[] = {&r, &lab, &res, &zero};
+        void *args_write[] = {&r, &gray, &cap, &res, &zero};
+        void **args = nodes[k].kind == 0 ? args_diff
+                    : nodes[k].kind == 1 ? args_one
+                    : nodes[k].kind == 2 ? args_item
+                    : nodes[k].kind == 3 ? args_count
+                                         : args_write;
         hipKernelNodeParams p = {};
         p.func = nodes[k].fn;
         p.gridDim = nodes[k].grid;
-        p.blockDim = dim3(k == 0 ? kDiffBlock : kBlock);
+        p.blockDim = nodes[k].block;
         p.sharedMemBytes = 0;
-        p.kernelParams = nodes[k].args;
+        p.kernelParams = args;
         p.extra = nullptr;
         hipGraphNode_t node;
         hipError_t err = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);

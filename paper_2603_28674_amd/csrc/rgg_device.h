@@ -62,19 +62,25 @@ struct RmDev {
     rgg_box *resident;         // [M] obstacle slots
     ChgEntry *chg;             // [2M]
     int2 *items;               // [items_cap] (cell, chunk)
-    int32_t *item_cnt;         // [items_cap] candidates found in each item
-    int32_t *work;             // [grid entries] candidates of item (c, h), stored from
-                               // cell_start[c] + h*chunk on, in cell-list order
-    uint32_t *unsure;          // [grid entries] per candidate: bit t set when a pair
-                               // with changed-entry tile t needs the binary64 re-test
+    int2 *rc;                  // [kStatBlocks][rc_cap] (edge, entry) pairs left to the
+                               // binary64 re-test by each block of the FP32 item kernel
+    int32_t *rc_cnt;           // [kStatBlocks]
+    int32_t rc_cap;
+    int32_t df_cap;
+    int32_t *df;               // [kStatBlocks][df_cap] items a block left whole to the
+                               // binary64 item kernel (its re-test region was full)
+    int32_t *df_cnt;           // [kStatBlocks]
     int32_t *tile_cnt;         // [ntiles] gray edges per label tile
     unsigned long long *blk_stats;   // [kStatBlocks][kStats] per-block partial counts
     Ctl *ctl;
 };
 
-constexpr int kStats = 5;          // pairs, outer hits, re-tested pairs, classify bytes, grid entries scanned
-constexpr int kStatBlocks = 2048;  // blocks of the grid, classify and re-test kernels
-constexpr int kMaxSlots = 4096;    // 2*slots changed entries = at most 32 LDS tiles of 256
+// pairs, pairs whose outer approximation met, re-tested pairs, classify bytes,
+// grid entries scanned, candidate edges
+constexpr int kStats = 6;
+constexpr int kStatBlocks = 2048;  // blocks of the item and re-test kernels
+constexpr int kMaxSlots = 4096;    // 2*slots changed entries at most
+constexpr int kRcCap = 1024;       // default re-test pairs one item-kernel block may queue
 
 constexpr int kLabelTile = 4096;   // edges per block of the label kernels
 

@@ -56,7 +56,7 @@ class rgg_build_opts(C.Structure):
     _fields_ = [("resolution", C.c_double), ("samples_per_edge", C.c_int32),
                 ("precision", C.c_int32), ("band_rel", C.c_double),
                 ("n_obstacle_slots", C.c_int64), ("cell_size", C.c_double),
-                ("host_threads", C.c_int32), ("reserved", C.c_int32)]
+                ("host_threads", C.c_int32), ("retest_capacity", C.c_int32)]
 
 
 class rgg_update_result(C.Structure):
@@ -199,7 +199,7 @@ def make_desc(q, edges, keep):
 
 
 def make_opts(resolution=0.0, samples_per_edge=0, precision=RGG_PREC_FP64, band_rel=1e-5,
-              n_obstacle_slots=0, cell_size=0.0, host_threads=0):
+              n_obstacle_slots=0, cell_size=0.0, host_threads=0, retest_capacity=0):
     o = rgg_build_opts()
     o.resolution = resolution
     o.samples_per_edge = samples_per_edge
@@ -208,6 +208,7 @@ def make_opts(resolution=0.0, samples_per_edge=0, precision=RGG_PREC_FP64, band_
     o.n_obstacle_slots = n_obstacle_slots
     o.cell_size = cell_size
     o.host_threads = host_threads
+    o.retest_capacity = retest_capacity
     return o
 
 
@@ -343,13 +344,14 @@ class Roadmap:
     """A roadmap resident on the GPU (wraps rgg_build / rgg_update / rgg_destroy)."""
 
     def __init__(self, ctx, robot, q, edges, n_slots, resolution=0.0, samples_per_edge=0,
-                 precision=RGG_PREC_FP64, band_rel=1e-5, cell_size=0.0, host_threads=0):
+                 precision=RGG_PREC_FP64, band_rel=1e-5, cell_size=0.0, host_threads=0,
+                 retest_capacity=0):
         keep = _Keep()
         self._keep = keep
         self.robot = make_robot(robot, keep)
         self.desc = make_desc(q, edges, keep)
         self.opts = make_opts(resolution, samples_per_edge, precision, band_rel, n_slots,
-                              cell_size, host_threads)
+                              cell_size, host_threads, retest_capacity)
         self.h = rgg_build(ctx, self.desc, self.robot, self.opts)
         self.E = int(np.asarray(edges).shape[0])
         self.M = int(n_slots)

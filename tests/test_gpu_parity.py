@@ -47,14 +47,16 @@ def with_removals(w, rng):
     return w
 
 
-def check_sequence(ctx, w, precision, cell_size=0.0, band_rel=1e-5, device_buffers=False):
+def check_sequence(ctx, w, precision, cell_size=0.0, band_rel=1e-5, device_buffers=False,
+                   retest_capacity=0):
     import torch
     from paper_2603_28674_amd import rgg
     import oracle
     print(f"[parity] {w.name} E={w.n_edges} M={w.n_slots} precision={precision} "
-          f"cell={cell_size} band={band_rel} device_buffers={device_buffers}", flush=True)
+          f"cell={cell_size} band={band_rel} device_buffers={device_buffers} "
+          f"retest_capacity={retest_capacity}", flush=True)
     g = rgg.Roadmap.from_workload(ctx, w, precision=precision, cell_size=cell_size,
-                                  band_rel=band_rel)
+                                  band_rel=band_rel, retest_capacity=retest_capacity)
     o = oracle.from_workload(w)
     prev = w.absent()
     stats = []
@@ -171,6 +173,17 @@ def test_band_infinite_rechecks_every_decision(ctx):
     w = workload("spatial", n_updates=2, seed=24)
     stats = check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, band_rel=float("inf"))
     assert all(s["n_rechecked"] == s["n_pairs"] for s in stats)
+
+
+@pytest.mark.parametrize("kind", ["spatial", "planar"])
+def test_full_retest_regions_defer_whole_items(ctx, kind):
+    """With room for one re-test pair per block and every decision inside the
+    band, blocks defer whole work items to the binary64 item kernel."""
+    from paper_2603_28674_amd import rgg
+    w = workload(kind, n_updates=2, seed=26)
+    stats = check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, band_rel=float("inf"),
+                           retest_capacity=1)
+    assert all(s["n_rechecked"] > 0 for s in stats)
 
 
 def test_errors_leave_state_unchanged(ctx):
