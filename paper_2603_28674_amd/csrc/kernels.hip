@@ -662,9 +662,15 @@ __global__ void __launch_bounds__(kBlock) k_item(RmDev rm, int deferred)
                 if (!overlap3(lo, hi, bl, bh)) return false;
                 return single || pair_owned<D, float>(rm, bl, lo, c);
             };
+            // the staged entries this thread's edge meets, as a 256-bit mask
+            uint64_t om[kSubTile / 64] = {0, 0, 0, 0};
             int cnt = 0;
             if (have)
-                for (int s = 0; s < nt; ++s) cnt += meets(s) ? 1 : 0;
+                for (int s = 0; s < nt; ++s)
+                    if (meets(s)) {
+                        om[s >> 6] |= 1ull << (s & 63);
+                        ++cnt;
+                    }
             my_pairs += cnt;
             int tp;
             const int pre = block_scan(cnt, &tp, L.wsum);
@@ -672,54 +678,78 @@ __global__ void __launch_bounds__(kBlock) k_item(RmDev rm, int deferred)
                 const int np = min(kPairCap, tp - r0);
                 if (cnt > 0 && pre < r0 + np && pre + cnt > r0) {
                     int k = pre;
-                    for (int s = 0; s < nt && k < r0 + np; ++s) {
-                        if (!meets(s)) continue;
-                        if (k >= r0) L.pe[k - r0] = (uint16_t)((tid << 8) | s);
-                        ++k;
+#pragma unroll
+                    for (int w = 0; w < kSubTile / 64; ++w) {
+                        uint64_t m = om[w];
+                        while (m && k < r0 + np) {
+                            const int s = (w << 6) + __ffsll((unsigned long long)m) - 1;
+                            m &= m - 1;
+                            if (k >= r0) L.pe[k - r0] = (uint16_t)((tid << 8) | s);
+                            ++k;
+                        }
                     }
                 }
                 __syncthreads();
                 if (tid == 0) n_pairs += np;
-                // ---- outer test: lanes = (pair, sphere)
-                for (int p0 = 0; p0 < np; p0 += kWaves * Gw) {
-                    const int p = p0 + wv * Gw + slot;
-                    int cls = kMiss;
-                    T A[D], Bq[D], lo[D], hi[D], R2 = T(0);
-                    float band = 0.0f;
-                    if (slot < Gw && p < np) {
-                        const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
-                        const T *cp = capb + (int64_t)L.edge[te] * (2 * D + 1) * B;
+                // ---- outer test: lanes = (pair, sphere); each lane takes two
+                // pairs per step and issues both capsules' loads first
+                constexpr int kCapU = 2;
+                for (int p0 = 0; p0 < np; p0 += kWaves * Gw * kCapU) {
+                    T A[kCapU][D], Bq[kCapU][D], R2[kCapU];
+                    int pu[kCapU];
 #pragma unroll
-                        for (int k = 0; k < D; ++k) {
-                            A[k] = cp[k * B + ci];
-                            Bq[k] = cp[(D + k) * B + ci];
-                            lo[k] = L.lo[k][s];
-                            hi[k] = L.hi[k][s];
+                    for (int u = 0; u < kCapU; ++u) {
+                        pu[u] = p0 + (u * kWaves + wv) * Gw + slot;
+                        R2[u] = T(0);
+                        if (slot < Gw && pu[u] < np) {
+                            const int te = L.pe[pu[u]] >> 8;
+                            const T *cp = capb + (int64_t)L.edge[te] * (2 * D + 1) * B;
+#pragma unroll
+                            for (int k = 0; k < D; ++k) {
+                                A[u][k] = cp[k * B + ci];
+                                Bq[u][k] = cp[(D + k) * B + ci];
+                            }
+                            R2[u] = cp[2 * D * B + ci];
                         }
-                        const T R = cp[2 * D * B + ci];
-                        R2 = R * R;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kCapU; ++u) {
+                        const int p = pu[u];
+                        int cls = kMiss;
+                        T lo[D], hi[D];
+                        float band = 0.0f;
+                        const T R = R2[u];
+                        const T RR = R * R;
+                        if (slot < Gw && p < np) {
+                            const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
+#pragma unroll
+                            for (int k = 0; k < D; ++k) {
+                                lo[k] = L.lo[k][s];
+                                hi[k] = L.hi[k][s];
+                            }
+                            if constexpr (kF32) {
+                                const float sc = fmaxf(L.es[te], L.sb[s]);
+                                band = band_rel * sc * sc;
+                                float sep = 0.0f;
+#pragma unroll
+                                for (int k = 0; k < D; ++k)
+                                    sep = fmaxf(sep, fmaxf(lo[k] - fmaxf(A[u][k], Bq[u][k]), fminf(A[u][k], Bq[u][k]) - hi[k]));
+                                const float m_end = fminf(point_box32<D>(A[u], lo, hi), point_box32<D>(Bq[u], lo, hi)) - RR;
+                                cls = (sep > 0.0f && sep * sep - RR > band) ? kMiss : (m_end < -band ? kHit : kOpen);
+                            } else {
+                                cls = segbox64<D>(A[u], Bq[u], lo, hi) <= RR ? kHit : kMiss;
+                            }
+                        }
                         if constexpr (kF32) {
-                            const float sc = fmaxf(L.es[te], L.sb[s]);
-                            band = band_rel * sc * sc;
-                            float sep = 0.0f;
-#pragma unroll
-                            for (int k = 0; k < D; ++k)
-                                sep = fmaxf(sep, fmaxf(lo[k] - fmaxf(A[k], Bq[k]), fminf(A[k], Bq[k]) - hi[k]));
-                            const float m_end = fminf(point_box32<D>(A, lo, hi), point_box32<D>(Bq, lo, hi)) - R2;
-                            cls = (sep > 0.0f && sep * sep - R2 > band) ? kMiss : (m_end < -band ? kHit : kOpen);
-                        } else {
-                            cls = segbox64<D>(A, Bq, lo, hi) <= R2 ? kHit : kMiss;
+                            if (__ballot(cls == kOpen)) {
+                                if (cls == kOpen) cls = classify_margin(segbox32<D>(A[u], Bq[u], lo, hi) - RR, band);
+                            }
                         }
-                    }
-                    if constexpr (kF32) {
-                        if (__ballot(cls == kOpen)) {
-                            if (cls == kOpen) cls = classify_margin(segbox32<D>(A, Bq, lo, hi) - R2, band);
+                        const uint64_t hmw = __ballot(cls == kHit), umw = __ballot(cls == kUnsure);
+                        if (slot < Gw && ci == 0 && p < np) {
+                            L.hm[p] = (hmw >> (slot * B)) & gmask;
+                            L.um[p] = (umw >> (slot * B)) & gmask;
                         }
-                    }
-                    const uint64_t hmw = __ballot(cls == kHit), umw = __ballot(cls == kUnsure);
-                    if (slot < Gw && ci == 0 && p < np) {
-                        L.hm[p] = (hmw >> (slot * B)) & gmask;
-                        L.um[p] = (umw >> (slot * B)) & gmask;
                     }
                 }
                 __syncthreads();
@@ -773,48 +803,67 @@ __global__ void __launch_bounds__(kBlock) k_item(RmDev rm, int deferred)
                         if (tid == 0) L.rcopy[nr] = ncopies;
                         __syncthreads();
                     }
-                    for (int c0 = 0; c0 < ncopies; c0 += kBlock) {
-                        const int cidx = c0 + tid;
-                        int cls = kMiss, p = 0;
-                        if (cidx < ncopies) {
-                            int r, jj;
-                            if (jfix) {
-                                r = cidx / jfix;
-                                jj = cidx - r * jfix;
-                            } else {
-                                int lo_ = 0, hi_ = nr - 1;   // last row with rcopy[r] <= cidx
-                                while (lo_ < hi_) {
-                                    const int mid = (lo_ + hi_ + 1) >> 1;
-                                    if (L.rcopy[mid] <= (uint32_t)cidx) lo_ = mid;
-                                    else hi_ = mid - 1;
+                    // each thread gathers kCopyU copies (all their loads in
+                    // flight together), then tests them
+                    constexpr int kCopyU = 4;
+                    for (int c0 = 0; c0 < ncopies; c0 += kBlock * kCopyU) {
+                        T q[kCopyU][D];
+                        int cu_p[kCopyU], cu_i[kCopyU];
+#pragma unroll
+                        for (int u = 0; u < kCopyU; ++u) {
+                            const int cidx = c0 + u * kBlock + tid;
+                            cu_p[u] = -1;
+                            cu_i[u] = 0;
+                            if (cidx < ncopies) {
+                                int r, jj;
+                                if (jfix) {
+                                    r = cidx / jfix;
+                                    jj = cidx - r * jfix;
+                                } else {
+                                    int lo_ = 0, hi_ = nr - 1;   // last row with rcopy[r] <= cidx
+                                    while (lo_ < hi_) {
+                                        const int mid = (lo_ + hi_ + 1) >> 1;
+                                        if (L.rcopy[mid] <= (uint32_t)cidx) lo_ = mid;
+                                        else hi_ = mid - 1;
+                                    }
+                                    r = lo_;
+                                    jj = cidx - (int)L.rcopy[r];
                                 }
-                                r = lo_;
-                                jj = cidx - (int)L.rcopy[r];
+                                const uint32_t rv = L.row[r];
+                                const int p = (int)(rv >> 6);
+                                const int i = (int)(rv & 63u);
+                                const int te = L.pe[p] >> 8;
+                                const int Je = L.ej[te];
+                                const int64_t P = (int64_t)Je * B;
+                                const T *sb = samp + D * L.es0[te] + (int64_t)i * Je + jj;
+#pragma unroll
+                                for (int k = 0; k < D; ++k) q[u][k] = sb[k * P];
+                                cu_p[u] = p;
+                                cu_i[u] = i;
                             }
-                            const uint32_t rv = L.row[r];
-                            p = (int)(rv >> 6);
-                            const int i = (int)(rv & 63u);
+                        }
+#pragma unroll
+                        for (int u = 0; u < kCopyU; ++u) {
+                            const int p = cu_p[u];
+                            if (p < 0) continue;
                             const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
-                            const int Je = L.ej[te];
-                            const int64_t P = (int64_t)Je * B;
-                            const T *sb = samp + D * L.es0[te] + (int64_t)i * Je + jj;
-                            T q[D], lo[D], hi[D];
+                            T lo[D], hi[D];
 #pragma unroll
                             for (int k = 0; k < D; ++k) {
-                                q[k] = sb[k * P];
                                 lo[k] = L.lo[k][s];
                                 hi[k] = L.hi[k][s];
                             }
                             bytes += D * sizeof(T);
+                            int cls;
                             if constexpr (kF32) {
                                 const float sc = fmaxf(L.es[te], L.sb[s]);
-                                cls = classify_margin(point_box32<D>(q, lo, hi) - s_rad2[i], band_rel * sc * sc);
+                                cls = classify_margin(point_box32<D>(q[u], lo, hi) - s_rad2[cu_i[u]], band_rel * sc * sc);
                             } else {
-                                cls = point_box64<D>(q, lo, hi) <= s_rad2[i] ? kHit : kMiss;
+                                cls = point_box64<D>(q[u], lo, hi) <= s_rad2[cu_i[u]] ? kHit : kMiss;
                             }
+                            if (cls == kHit) atomicOr(&L.sf[p], 1u);
+                            else if (cls == kUnsure) atomicOr(&L.sf[p], 2u);
                         }
-                        if (cls == kHit) atomicOr(&L.sf[p], 1u);
-                        else if (cls == kUnsure) atomicOr(&L.sf[p], 2u);
                     }
                     __syncthreads();
                 }
