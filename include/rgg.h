@@ -107,19 +107,26 @@ typedef struct {
     double resolution;            /* eps, C-space step between configurations */
     int32_t samples_per_edge;     /* > 1 fixes |cfg(e)|, overriding resolution  */
     int32_t precision;            /* RGG_PREC_*                                 */
-    double band_rel;              /* FP32 band: a test whose FP32 margin m has
-                                     |m| <= band_rel * s^2 (s = largest
-                                     magnitude among the pair's coordinates)
-                                     is decided in FP64; <= 0 selects 1e-5     */
+    double band_rel;              /* FP32 band factor tau: a test whose FP32
+                                     margin m (squared distance minus squared
+                                     radius) has |m| <= tau (s + R)(R + L)
+                                     + tau^2 s^2 is decided in FP64, where s is
+                                     the largest |coordinate| of the pair, R
+                                     the radius tested and L the L1 length of
+                                     the capsule axis (0 for a sphere copy).
+                                     <= 0 selects 2^-18; +inf re-tests every
+                                     pair.  Labels do not depend on it for any
+                                     value >= 2^-18.                            */
     int64_t n_obstacle_slots;     /* M, 0..4096                                 */
     double cell_size;             /* grid cell edge; 0 = heuristic; < 0 = one
                                      cell covering everything                   */
     int32_t host_threads;         /* threads for the host build; 0 = automatic  */
     int32_t retest_capacity;      /* FP32 mode: undecided pairs each of the 2048
-                                     blocks may queue for the binary64 re-test
-                                     before it re-runs a whole work item in
-                                     binary64 instead; 0 = 1024.  Any value
-                                     gives the same labels.                     */
+                                     item blocks may queue for the binary64
+                                     re-test before it leaves a whole work item
+                                     to the binary64 pass instead; 0 = 1024,
+                                     at most 2^20.  Any value gives the same
+                                     labels.                                    */
 } rgg_build_opts;
 
 /* Written by the device at the end of every update (rgg_update_async) and

@@ -17,6 +17,8 @@
 #include "rgg_device.h"
 #include "rgg_internal.h"
 
+static_assert(rgg::kLocalGridCells == rgg::kLocalCells, "pruning-grid size of host and device");
+
 using namespace rgg;
 
 namespace {
@@ -180,7 +182,7 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     dv.chunk = kChunk;
     dv.E = E;
     dv.M = M;
-    dv.band_rel = (float)(opts->band_rel > 0.0 ? opts->band_rel : 1e-5);
+    dv.band_rel = (float)(opts->band_rel > 0.0 ? opts->band_rel : 0x1p-18);
     if (std::isinf(opts->band_rel)) dv.band_rel = INFINITY;
     dv.ntiles = (int32_t)std::max<int64_t>(1, (E + kLabelTile - 1) / kLabelTile);
     dv.p_fixed = 0;
@@ -236,6 +238,11 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
         dv.gorg[d] = grid.org[d];
     }
     dv.ginv = grid.inv;
+    for (int d = 0; d < 3; ++d) {
+        dv.lg_org[d] = grid.lg_org[d];
+        dv.lg_dim[d] = grid.lg_dim[d];
+    }
+    dv.lg_inv = grid.lg_inv;
     dv.ncells = (int64_t)grid.dim[0] * grid.dim[1] * grid.dim[2];
     dv.items_cap = grid.items_cap;
     int32_t *cstart, *cedges;
@@ -250,33 +257,38 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
             b.lo[k] = 1.0;
             b.hi[k] = -1.0;
         }
-    const size_t nwords = (size_t)((E + 31) / 32), ncw = (size_t)((dv.ncells + 31) / 32);
+    const size_t ncw = (size_t)((dv.ncells + 31) / 32);
     if ((st = rm->alloc(&dv.cnt, (size_t)E, "counters")) != RGG_OK) return guard(st);
-    if ((st = rm->alloc(&dv.edge_bits, nwords, "edge marks")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.cell_bits, ncw, "cell marks")) != RGG_OK) return guard(st);
     if ((st = rm->upload(&dv.resident, absent.data(), (size_t)M, "obstacle slots")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.chg, (size_t)(2 * M), "changed entries")) != RGG_OK) return guard(st);
-    if ((st = rm->alloc(&dv.items, (size_t)grid.items_cap, "grid items")) != RGG_OK) return guard(st);
     dv.rc_cap = opts->retest_capacity > 0 ? opts->retest_capacity : kRcCap;
     dv.df_cap = (int32_t)((grid.items_cap + kStatBlocks - 1) / kStatBlocks);
     if ((st = rm->alloc(&dv.rc, (size_t)kStatBlocks * dv.rc_cap, "re-test regions")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.rc_cnt, (size_t)kStatBlocks, "re-test counts")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.df, (size_t)kStatBlocks * dv.df_cap, "deferred items")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.df_cnt, (size_t)kStatBlocks, "deferred counts")) != RGG_OK) return guard(st);
+    if (dv.ncells == 1) {
+        // the one cell's work items never change: (0, chunk) for every chunk
+        std::vector<int2> items((size_t)grid.items_cap);
+        for (int64_t h = 0; h < grid.items_cap; ++h) items[(size_t)h] = make_int2(0, (int32_t)h);
+        if ((st = rm->upload(&dv.items, items.data(), items.size(), "grid items")) != RGG_OK) return guard(st);
+    } else if ((st = rm->alloc(&dv.items, (size_t)grid.items_cap, "grid items")) != RGG_OK) {
+        return guard(st);
+    }
     if ((st = rm->alloc(&dv.blk_stats, (size_t)kStatBlocks * kStats, "statistics")) != RGG_OK) return guard(st);
-    if ((st = rm->alloc(&dv.tile_cnt, (size_t)dv.ntiles, "tile counts")) != RGG_OK) return guard(st);
+    if ((st = rm->alloc(&dv.tile_cnt, (size_t)dv.ntiles + 1, "tile counts")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.ctl, 1, "control block")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&rm->d_stage, (size_t)(2 * M), "box staging")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&rm->d_res, 1, "result")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&rm->d_labels, (size_t)E, "labels")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&rm->d_gray, (size_t)E, "gray list")) != RGG_OK) return guard(st);
     HIP_OR_FAIL(hipMemset(dv.cnt, 0, sizeof(int2) * std::max<int64_t>(E, 1)), "clear counters");
-    HIP_OR_FAIL(hipMemset(dv.edge_bits, 0, 4 * std::max<size_t>(nwords, 1)), "clear marks");
     HIP_OR_FAIL(hipMemset(dv.cell_bits, 0, 4 * std::max<size_t>(ncw, 1)), "clear marks");
     HIP_OR_FAIL(hipMemset(dv.ctl, 0, sizeof(Ctl)), "clear control");
-    HIP_OR_FAIL(hipMemset(dv.blk_stats, 0, sizeof(unsigned long long) * kStatBlocks * kStats), "clear statistics");
     HIP_OR_FAIL(hipMemset(dv.rc_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear re-test counts");
     HIP_OR_FAIL(hipMemset(dv.df_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear deferred counts");
+    HIP_OR_FAIL(hipMemset(dv.blk_stats, 0, sizeof(unsigned long long) * kStatBlocks * kStats), "clear statistics");
     HIP_OR_FAIL(hipMemset(rm->d_labels, 0, std::max<int64_t>(E, 1)), "clear labels");
     HIP_OR_FAIL(hipHostMalloc((void **)&rm->h_stage, sizeof(rgg_box) * std::max<int64_t>(2 * M, 1)), "pinned staging");
     HIP_OR_FAIL(hipHostMalloc((void **)&rm->h_res, sizeof(rgg_update_result)), "pinned result");

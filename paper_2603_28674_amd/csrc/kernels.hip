@@ -6,14 +6,14 @@
 //               slots (Alg. 1: a moved obstacle's old and new poses);
 //   k_cells     activate every grid cell a changed box overlaps and emit one
 //               work item per (cell, chunk of 256 of its edges)  (Sec. 3.3);
-//   k_item      one block per work item: pairs of the item's edges with the
+//   k_item32/64 one block per work item: pairs of the item's edges with the
 //               changed boxes of the cell, outer test (per-sphere capsule vs
 //               box), inner test (copies of the spheres whose capsule met),
 //               counter update (Sec. 3.1 rule; Alg. 1's intersection lists
 //               kept as counts).  In the FP32 mode a pair whose margin falls
 //               inside the rounding band is left to
 //   k_recheck_pairs   which decides it in binary64; an item whose block ran
-//               out of re-test room is run again whole by the binary64 k_item;
+//               out of re-test room is run again whole by k_item64;
 //   k_count + k_write   labels from the counters and the ordered gray list.
 //
 // Binary64 code is compiled without FMA contraction and its sums run left to
@@ -35,7 +35,10 @@ constexpr int kDiffBlock = 1024;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kCellsGrid = 128;
-constexpr int kGrid = kStatBlocks; // blocks of k_item and k_recheck_pairs
+constexpr int kGrid = kStatBlocks; // blocks of the item kernels
+constexpr int kFp64Grid = 256;     // blocks of the binary64 pass of the FP32 mode
+static_assert(kStatBlocks % kFp64Grid == 0 && kStatBlocks / kFp64Grid < 64, "re-test regions per block");
+static_assert(kStatBlocks % 256 == 0, "statistics rows are folded 256 at a time");
 
 enum : int { kMiss = 0, kHit = 1, kUnsure = 2, kOpen = 3 };
 
@@ -84,10 +87,13 @@ __device__ inline float round_up(double x)
 
 __device__ inline int32_t cell_of(double x, double org, double inv, int32_t n)
 {
+    // c is integral, so comparing its int32 value with n decides c >= n
+    // exactly (and keeps n out of binary64 registers)
     double c = floor((x - org) * inv);
     if (c < 0.0) return -1;
-    if (c >= (double)n) return n;
-    return (int32_t)c;
+    if (!(c < 2147483647.0)) return n;
+    const int32_t ci = (int32_t)c;
+    return ci >= n ? n : ci;
 }
 
 __device__ inline bool overlap3(const float *lo, const float *hi, const float4 &bl, const float4 &bh)
@@ -155,8 +161,11 @@ __device__ inline double seg_G64(const double *A, const double *d, double t, con
 // smallest with G >= 0 (candidates: 0, 1, face crossings strictly inside);
 // there the faces in play are fixed and the single quadratic's stationary
 // point is clamped into that bracket.
+// When `targ` is given it receives the parameter of the value returned (which
+// does not change the value).
 template <int D>
-__device__ inline double segbox64(const double *A, const double *Bp, const double *lo, const double *hi)
+__device__ inline double segbox64(const double *A, const double *Bp, const double *lo, const double *hi,
+                                  double *targ = nullptr)
 {
     double d[D];
 #pragma unroll
@@ -181,6 +190,7 @@ __device__ inline double segbox64(const double *A, const double *Bp, const doubl
     double fL = seg_F64<D>(A, d, tL, lo, hi);
     double fR = seg_F64<D>(A, d, tR, lo, hi);
     double fmin = fL < fR ? fL : fR;
+    double tmin = fL < fR ? tL : tR;
     if (tL < tR) {
         double tm = 0.5 * (tL + tR);
         double num = 0.0, den = 0.0;
@@ -202,8 +212,12 @@ __device__ inline double segbox64(const double *A, const double *Bp, const doubl
             if (ts > tR) ts = tR;
         }
         double fs = seg_F64<D>(A, d, ts, lo, hi);
-        if (fs < fmin) fmin = fs;
+        if (fs < fmin) {
+            fmin = fs;
+            tmin = ts;
+        }
     }
+    if (targ) *targ = tmin;
     return fmin;
 }
 
@@ -237,8 +251,11 @@ __device__ inline float seg_F32(const float *A, const float *d, float t, const f
     return acc;
 }
 
+// `targ` receives the parameter of the value returned.  Scheduling barriers
+// between the candidates keep one candidate's temporaries live at a time, so
+// this binary32 filter stays small in registers.
 template <int D>
-__device__ inline float segbox32(const float *A, const float *Bp, const float *lo, const float *hi)
+__device__ inline float segbox32(const float *A, const float *Bp, const float *lo, const float *hi, float &targ)
 {
     float d[D], inv[D];
 #pragma unroll
@@ -257,6 +274,7 @@ __device__ inline float segbox32(const float *A, const float *Bp, const float *l
         }
         tL = (g <= 0.0f && t > tL) ? t : tL;
         tR = (g >= 0.0f && t < tR) ? t : tR;
+        __builtin_amdgcn_sched_barrier(0);
     };
     take(0.0f);
     take(1.0f);
@@ -265,11 +283,13 @@ __device__ inline float segbox32(const float *A, const float *Bp, const float *l
         // a crossing outside (0,1) (or of an axis the segment does not
         // move along) is replaced by t = 0, which repeats the first candidate
         float t1 = (lo[k] - A[k]) * inv[k];
-        float t2 = (hi[k] - A[k]) * inv[k];
         take(t1 > 0.0f && t1 < 1.0f ? t1 : 0.0f);
+        float t2 = (hi[k] - A[k]) * inv[k];
         take(t2 > 0.0f && t2 < 1.0f ? t2 : 0.0f);
     }
-    float fmin = fminf(seg_F32<D>(A, d, tL, lo, hi), seg_F32<D>(A, d, tR, lo, hi));
+    const float fL = seg_F32<D>(A, d, tL, lo, hi), fR = seg_F32<D>(A, d, tR, lo, hi);
+    const float fmin = fminf(fL, fR);
+    const float tmin = fL <= fR ? tL : tR;
     float tm = 0.5f * (tL + tR);
     float num = 0.0f, den = 0.0f;
 #pragma unroll
@@ -281,7 +301,9 @@ __device__ inline float segbox32(const float *A, const float *Bp, const float *l
         den = __builtin_fmaf(w, w, den);
     }
     float ts = den > 0.0f ? fminf(fmaxf(num * __builtin_amdgcn_rcpf(den), tL), tR) : tL;
-    return fminf(fmin, seg_F32<D>(A, d, ts, lo, hi));
+    const float fs = seg_F32<D>(A, d, ts, lo, hi);
+    targ = fs < fmin ? ts : tmin;
+    return fminf(fmin, fs);
 }
 
 __device__ inline int classify_margin(float m, float band)
@@ -311,12 +333,14 @@ __device__ inline bool same_box(const rgg_box &a, const rgg_box &b)
 
 __device__ inline bool present(const rgg_box &b, int D)
 {
-    for (int k = 0; k < D; ++k)
-        if (b.lo[k] > b.hi[k]) return false;
-    return true;
+    bool p = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p = p && (k >= D || b.lo[k] <= b.hi[k]);
+    return p;
 }
 
-__device__ void write_entry(const RmDev &rm, int pos, const rgg_box &b, int sign)
+// returns whether the box covers at least one grid cell
+__device__ bool write_entry(const RmDev &rm, int pos, const rgg_box &b, int sign)
 {
     ChgEntry en;
     float s = 0.0f;
@@ -346,21 +370,25 @@ __device__ void write_entry(const RmDev &rm, int pos, const rgg_box &b, int sign
     en.sbox = s;
     en.sign = sign;
     rm.chg[pos] = en;
+    return !empty;
 }
 
 __global__ void __launch_bounds__(kDiffBlock) k_diff(RmDev rm, const rgg_box *__restrict__ old_b,
                                                      const rgg_box *__restrict__ new_b)
 {
     __shared__ int s_tot[kDiffBlock / 64];
-    __shared__ int s_bad, s_mism, s_base;
+    __shared__ int s_bad, s_mism, s_base, s_any;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
     if (tid == 0) {
         s_bad = 0;
         s_mism = 0;
         s_base = 0;
+        s_any = 0;
         rm.ctl->n_items = 0;
     }
     __syncthreads();
+    bool dirty0 = false;   // the first chunk's slot changes (kept for the commit)
+    rgg_box n0;
     for (int64_t base = 0; base < rm.M; base += kDiffBlock) {
         const int64_t k = base + tid;
         int cnt = 0;
@@ -369,8 +397,13 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff(RmDev rm, const rgg_box *__
         if (k < rm.M) {
             o = old_b[k];
             n = new_b[k];
+            const rgg_box r = rm.resident[k];
             if (!box_ok(o) || !box_ok(n)) atomicOr(&s_bad, 1);
-            if (!same_box(o, rm.resident[k])) atomicOr(&s_mism, 1);
+            if (!same_box(o, r)) atomicOr(&s_mism, 1);
+            if (base == 0) {
+                dirty0 = !same_box(n, r);
+                n0 = n;
+            }
             if (!same_box(o, n)) {
                 po = present(o, rm.D);
                 pn = present(n, rm.D);
@@ -387,8 +420,10 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff(RmDev rm, const rgg_box *__
             tot += s_tot[w];
         }
         int pos = off + pre;
-        if (po) write_entry(rm, pos++, o, -1);
-        if (pn) write_entry(rm, pos, n, +1);
+        bool any = false;
+        if (po) any = write_entry(rm, pos++, o, -1);
+        if (pn) any = write_entry(rm, pos, n, +1) || any;
+        if (any) s_any = 1;
         __syncthreads();
         if (tid == 0) s_base += tot;
         __syncthreads();
@@ -397,9 +432,13 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff(RmDev rm, const rgg_box *__
     if (tid == 0) {
         rm.ctl->status = status;
         rm.ctl->n_chg = status ? 0 : s_base;
+        // one grid cell: its items (0, h) are fixed at build; they are all
+        // work as soon as one changed box lies inside the grid
+        if (rm.ncells == 1) rm.ctl->n_items = (status == RGG_OK && s_any) ? (int32_t)rm.items_cap : 0;
     }
     if (status == RGG_OK) {
-        for (int64_t k = tid; k < rm.M; k += kDiffBlock) {
+        if (dirty0) rm.resident[tid] = n0;
+        for (int64_t k = kDiffBlock + tid; k < rm.M; k += kDiffBlock) {
             rgg_box n = new_b[k];
             if (!same_box(n, rm.resident[k])) rm.resident[k] = n;
         }
@@ -499,463 +538,9 @@ __device__ inline int32_t clamp_cell(double x, double org, double inv, int32_t n
 }
 
 // ------------------------------------------------------------------------
-// k_item: one block per grid work item (cell c, chunk of 256 of its edges).
-//
-//   1. every thread owns one edge of the item; the changed entries covering
-//      the cell are staged in LDS (tiles of 256); a thread lists the entries
-//      whose box meets its edge's box.  With several cells a pair is taken
-//      only by the cell holding the lower corner of the two boxes'
-//      intersection, so each (edge, entry) pair is tested exactly once.
-//   2. outer test, lanes = (pair, sphere): capsule of sphere i against the
-//      entry's box (FP32: separation and end-sphere tests first, the exact
-//      segment-box minimum where they do not decide).
-//   3. inner test, lanes = (pair, sphere whose capsule met, configuration):
-//      that sphere's copies against the box.
-//   4. per pair C and S; the edge's counter deltas are summed in LDS and
-//      added once per edge.  In FP32 a pair whose decision fell inside the
-//      rounding band goes to the block's re-test region; if that region is
-//      full the whole item is deferred to the binary64 item kernel.
-// ------------------------------------------------------------------------
-
-constexpr int kSubTile = 256;   // changed entries staged per tile
-constexpr int kPairCap = 512;   // pairs per round (two per thread)
-constexpr int kRowCap = 1024;   // (pair, sphere) rows per copy round
-
-template <typename T>
-struct ItemLds {
-    T lo[3][kSubTile], hi[3][kSubTile];
-    float sb[kSubTile];
-    int sign[kSubTile], gidx[kSubTile];
-    int64_t es0[kBlock];                 // first sample of each edge of the item
-    int edge[kBlock], ej[kBlock];        // edge id, configurations per sphere
-    float es[kBlock];                    // edge s (largest |coordinate| of its box)
-    int dC[kBlock], dS[kBlock];
-    uint16_t pe[kPairCap];               // edge slot << 8 | staged entry
-    unsigned long long hm[kPairCap], um[kPairCap];
-    uint32_t roff[kPairCap], sf[kPairCap];
-    uint32_t row[kRowCap];               // pair << 6 | sphere
-    uint32_t rcopy[kRowCap + 1];
-    int wsum[kWaves];
-    int rc_n, rc_start, defer, df_n;
-    unsigned long long acc[kStats];
-};
-
-template <int D, typename T>
-__device__ inline bool pair_owned(const RmDev &rm, const float4 &bl, const T *lo32, int64_t c)
-{
-    // lower corner of the intersection of the edge box and the entry box
-    int64_t cell = 0, mul = 1;
-    for (int k = 0; k < D; ++k) {
-        const float ek = k == 0 ? bl.x : (k == 1 ? bl.y : bl.z);
-        const float x = fmaxf(ek, (float)lo32[k]);
-        cell += (int64_t)clamp_cell((double)x, rm.gorg[k], rm.ginv, rm.gdim[k]) * mul;
-        mul *= rm.gdim[k];
-    }
-    return cell == c;
-}
-
-template <int D, typename T>
-__global__ void __launch_bounds__(kBlock) k_item(RmDev rm, int deferred)
-{
-    constexpr bool kF32 = std::is_same<T, float>::value;
-    __shared__ ItemLds<T> L;
-    __shared__ T s_rad2[64];
-    const Ctl *ctl = rm.ctl;
-    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
-    const int B = rm.B;
-    const int Gw = 64 / B, slot = lane / B, ci = lane - slot * B;
-    const uint64_t gmask = B == 64 ? ~0ull : ((1ull << B) - 1ull);
-    if (tid < kStats) L.acc[tid] = 0;
-    if (tid < B) s_rad2[tid] = kF32 ? (T)rm.rad2_32[tid] : (T)(rm.rad64[tid] * rm.rad64[tid]);
-    if (tid == 0) {
-        L.rc_n = 0;
-        L.df_n = 0;
-    }
-    __syncthreads();
-    unsigned long long n_pairs = 0, n_outer = 0, bytes = 0, visited = 0, cand = 0;
-    const int status = ctl->status;
-    const int n_chg = ctl->n_chg;
-    const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
-    const bool single = rm.ncells == 1;
-    const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
-    const T *capb = kF32 ? (const T *)rm.cap32 : (const T *)rm.cap64;
-    const T *samp = kF32 ? (const T *)rm.samp32 : (const T *)rm.samp64;
-    const float band_rel = rm.band_rel;
-    const int n_list = status != RGG_OK ? 0 : (deferred ? rm.df_cnt[blockIdx.x] : n_items);
-    const int first = deferred ? 0 : (int)blockIdx.x, stride = deferred ? 1 : (int)gridDim.x;
-    for (int li = first; li < n_list; li += stride) {
-        const int it = deferred ? rm.df[(int64_t)blockIdx.x * rm.df_cap + li] : li;
-        const int2 item = rm.items[it];
-        const int64_t c = item.x;
-        const int32_t cx = (int32_t)(c % rm.gdim[0]);
-        const int32_t cy = (int32_t)((c / rm.gdim[0]) % rm.gdim[1]);
-        const int32_t cz = (int32_t)(c / ((int64_t)rm.gdim[0] * rm.gdim[1]));
-        const int64_t beg = (int64_t)rm.cell_start[c] + (int64_t)item.y * rm.chunk;
-        const int64_t end = min((int64_t)rm.cell_start[c + 1], beg + rm.chunk);
-        const bool have = beg + tid < end;
-        int e = 0;
-        float4 bl = make_float4(0, 0, 0, 0), bh = bl;
-        int64_t s0 = 0;
-        int J = 0;
-        if (have) {
-            e = rm.cell_edges[beg + tid];
-            bl = aabb[2 * (int64_t)e];
-            bh = aabb[2 * (int64_t)e + 1];
-            s0 = rm.p_fixed ? (int64_t)e * rm.p_fixed : rm.soff[e];
-            J = (int)((rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0) / B);
-            ++visited;
-            bytes += 32;
-        }
-        __syncthreads();
-        L.edge[tid] = e;
-        L.es[tid] = bl.w;
-        L.es0[tid] = s0;
-        L.ej[tid] = J;
-        L.dC[tid] = 0;
-        L.dS[tid] = 0;
-        if (tid == 0) {
-            L.rc_start = L.rc_n;
-            L.defer = 0;
-            // the main pass visits every item once: clear the cell's mark with
-            // its first chunk, so the next update starts from zero marks
-            if (!deferred && item.y == 0) atomicAnd(&rm.cell_bits[c >> 5], ~(1u << (c & 31)));
-        }
-        int my_pairs = 0;
-        for (int j0 = 0; j0 < n_chg; j0 += kSubTile) {
-            // stage the entries covering this cell
-            const int j = j0 + tid;
-            bool in = false;
-            if (j < n_chg) {
-                const ChgEntry &en = rm.chg[j];
-                in = single || (cx >= en.c0[0] && cx <= en.c1[0] && cy >= en.c0[1] && cy <= en.c1[1] &&
-                                cz >= en.c0[2] && cz <= en.c1[2]);
-            }
-            int nt;
-            const int pos = block_scan(in ? 1 : 0, &nt, L.wsum);
-            if (in) {
-                const ChgEntry &en = rm.chg[j];
-                for (int k = 0; k < 3; ++k) {
-                    L.lo[k][pos] = kF32 ? (T)en.lo32[k] : (T)en.lo[k];
-                    L.hi[k][pos] = kF32 ? (T)en.hi32[k] : (T)en.hi[k];
-                }
-                L.sb[pos] = en.sbox;
-                L.sign[pos] = en.sign;
-                L.gidx[pos] = j;
-            }
-            __syncthreads();
-            if (nt == 0) continue;
-            // pairs of this thread's edge with the staged entries
-            auto meets = [&](int s) {
-                float lo[3], hi[3];
-                if constexpr (kF32) {
-                    for (int k = 0; k < 3; ++k) {
-                        lo[k] = L.lo[k][s];
-                        hi[k] = L.hi[k][s];
-                    }
-                } else {
-                    const ChgEntry &en = rm.chg[L.gidx[s]];
-                    for (int k = 0; k < 3; ++k) {
-                        lo[k] = en.lo32[k];
-                        hi[k] = en.hi32[k];
-                    }
-                }
-                if (!overlap3(lo, hi, bl, bh)) return false;
-                return single || pair_owned<D, float>(rm, bl, lo, c);
-            };
-            // the staged entries this thread's edge meets, as a 256-bit mask
-            uint64_t om[kSubTile / 64] = {0, 0, 0, 0};
-            int cnt = 0;
-            if (have)
-                for (int s = 0; s < nt; ++s)
-                    if (meets(s)) {
-                        om[s >> 6] |= 1ull << (s & 63);
-                        ++cnt;
-                    }
-            my_pairs += cnt;
-            int tp;
-            const int pre = block_scan(cnt, &tp, L.wsum);
-            for (int r0 = 0; r0 < tp; r0 += kPairCap) {
-                const int np = min(kPairCap, tp - r0);
-                if (cnt > 0 && pre < r0 + np && pre + cnt > r0) {
-                    int k = pre;
-#pragma unroll
-                    for (int w = 0; w < kSubTile / 64; ++w) {
-                        uint64_t m = om[w];
-                        while (m && k < r0 + np) {
-                            const int s = (w << 6) + __ffsll((unsigned long long)m) - 1;
-                            m &= m - 1;
-                            if (k >= r0) L.pe[k - r0] = (uint16_t)((tid << 8) | s);
-                            ++k;
-                        }
-                    }
-                }
-                __syncthreads();
-                if (tid == 0) n_pairs += np;
-                // ---- outer test: lanes = (pair, sphere); each lane takes two
-                // pairs per step and issues both capsules' loads first
-                constexpr int kCapU = 2;
-                for (int p0 = 0; p0 < np; p0 += kWaves * Gw * kCapU) {
-                    T A[kCapU][D], Bq[kCapU][D], R2[kCapU];
-                    int pu[kCapU];
-#pragma unroll
-                    for (int u = 0; u < kCapU; ++u) {
-                        pu[u] = p0 + (u * kWaves + wv) * Gw + slot;
-                        R2[u] = T(0);
-                        if (slot < Gw && pu[u] < np) {
-                            const int te = L.pe[pu[u]] >> 8;
-                            const T *cp = capb + (int64_t)L.edge[te] * (2 * D + 1) * B;
-#pragma unroll
-                            for (int k = 0; k < D; ++k) {
-                                A[u][k] = cp[k * B + ci];
-                                Bq[u][k] = cp[(D + k) * B + ci];
-                            }
-                            R2[u] = cp[2 * D * B + ci];
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < kCapU; ++u) {
-                        const int p = pu[u];
-                        int cls = kMiss;
-                        T lo[D], hi[D];
-                        float band = 0.0f;
-                        const T R = R2[u];
-                        const T RR = R * R;
-                        if (slot < Gw && p < np) {
-                            const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
-#pragma unroll
-                            for (int k = 0; k < D; ++k) {
-                                lo[k] = L.lo[k][s];
-                                hi[k] = L.hi[k][s];
-                            }
-                            if constexpr (kF32) {
-                                const float sc = fmaxf(L.es[te], L.sb[s]);
-                                band = band_rel * sc * sc;
-                                float sep = 0.0f;
-#pragma unroll
-                                for (int k = 0; k < D; ++k)
-                                    sep = fmaxf(sep, fmaxf(lo[k] - fmaxf(A[u][k], Bq[u][k]), fminf(A[u][k], Bq[u][k]) - hi[k]));
-                                const float m_end = fminf(point_box32<D>(A[u], lo, hi), point_box32<D>(Bq[u], lo, hi)) - RR;
-                                cls = (sep > 0.0f && sep * sep - RR > band) ? kMiss : (m_end < -band ? kHit : kOpen);
-                            } else {
-                                cls = segbox64<D>(A[u], Bq[u], lo, hi) <= RR ? kHit : kMiss;
-                            }
-                        }
-                        if constexpr (kF32) {
-                            if (__ballot(cls == kOpen)) {
-                                if (cls == kOpen) cls = classify_margin(segbox32<D>(A[u], Bq[u], lo, hi) - RR, band);
-                            }
-                        }
-                        const uint64_t hmw = __ballot(cls == kHit), umw = __ballot(cls == kUnsure);
-                        if (slot < Gw && ci == 0 && p < np) {
-                            L.hm[p] = (hmw >> (slot * B)) & gmask;
-                            L.um[p] = (umw >> (slot * B)) & gmask;
-                        }
-                    }
-                }
-                __syncthreads();
-                // ---- rows: one per (pair, sphere whose capsule met)
-                const int pa = tid, pb = tid + kBlock;
-                const int ra = pa < np ? __popcll(L.hm[pa]) : 0;
-                const int rb = pb < np ? __popcll(L.hm[pb]) : 0;
-                int nrows;
-                const int rpre = block_scan(ra + rb, &nrows, L.wsum);
-                if (pa < np) {
-                    L.roff[pa] = rpre;
-                    L.sf[pa] = 0;
-                }
-                if (pb < np) {
-                    L.roff[pb] = rpre + ra;
-                    L.sf[pb] = 0;
-                }
-                __syncthreads();
-                for (int q0 = 0; q0 < nrows; q0 += kRowCap) {
-                    const int nr = min(kRowCap, nrows - q0);
-                    for (int h = 0; h < 2; ++h) {
-                        const int p = tid + h * kBlock;
-                        if (p >= np) continue;
-                        uint64_t m = L.hm[p];
-                        int r = L.roff[p];
-                        while (m && r < q0 + nr) {
-                            const int i = __ffsll((unsigned long long)m) - 1;
-                            m &= m - 1;
-                            if (r >= q0) L.row[r - q0] = ((uint32_t)p << 6) | (uint32_t)i;
-                            ++r;
-                        }
-                    }
-                    __syncthreads();
-                    // copies of each row: fixed count, or a scan over the rows
-                    const int jfix = rm.p_fixed ? rm.p_fixed / B : 0;
-                    int ncopies = nr * jfix;
-                    if (!jfix) {
-                        int cj[4], sum = 0;
-                        for (int h = 0; h < 4; ++h) {
-                            const int r = tid * 4 + h;
-                            cj[h] = r < nr ? L.ej[L.pe[L.row[r] >> 6] >> 8] : 0;
-                            sum += cj[h];
-                        }
-                        const int cpre = block_scan(sum, &ncopies, L.wsum);
-                        int acc = cpre;
-                        for (int h = 0; h < 4; ++h) {
-                            const int r = tid * 4 + h;
-                            if (r < nr) L.rcopy[r] = acc;
-                            acc += cj[h];
-                        }
-                        if (tid == 0) L.rcopy[nr] = ncopies;
-                        __syncthreads();
-                    }
-                    // each thread gathers kCopyU copies (all their loads in
-                    // flight together), then tests them
-                    constexpr int kCopyU = 4;
-                    for (int c0 = 0; c0 < ncopies; c0 += kBlock * kCopyU) {
-                        T q[kCopyU][D];
-                        int cu_p[kCopyU], cu_i[kCopyU];
-#pragma unroll
-                        for (int u = 0; u < kCopyU; ++u) {
-                            const int cidx = c0 + u * kBlock + tid;
-                            cu_p[u] = -1;
-                            cu_i[u] = 0;
-                            if (cidx < ncopies) {
-                                int r, jj;
-                                if (jfix) {
-                                    r = cidx / jfix;
-                                    jj = cidx - r * jfix;
-                                } else {
-                                    int lo_ = 0, hi_ = nr - 1;   // last row with rcopy[r] <= cidx
-                                    while (lo_ < hi_) {
-                                        const int mid = (lo_ + hi_ + 1) >> 1;
-                                        if (L.rcopy[mid] <= (uint32_t)cidx) lo_ = mid;
-                                        else hi_ = mid - 1;
-                                    }
-                                    r = lo_;
-                                    jj = cidx - (int)L.rcopy[r];
-                                }
-                                const uint32_t rv = L.row[r];
-                                const int p = (int)(rv >> 6);
-                                const int i = (int)(rv & 63u);
-                                const int te = L.pe[p] >> 8;
-                                const int Je = L.ej[te];
-                                const int64_t P = (int64_t)Je * B;
-                                const T *sb = samp + D * L.es0[te] + (int64_t)i * Je + jj;
-#pragma unroll
-                                for (int k = 0; k < D; ++k) q[u][k] = sb[k * P];
-                                cu_p[u] = p;
-                                cu_i[u] = i;
-                            }
-                        }
-#pragma unroll
-                        for (int u = 0; u < kCopyU; ++u) {
-                            const int p = cu_p[u];
-                            if (p < 0) continue;
-                            const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
-                            T lo[D], hi[D];
-#pragma unroll
-                            for (int k = 0; k < D; ++k) {
-                                lo[k] = L.lo[k][s];
-                                hi[k] = L.hi[k][s];
-                            }
-                            bytes += D * sizeof(T);
-                            int cls;
-                            if constexpr (kF32) {
-                                const float sc = fmaxf(L.es[te], L.sb[s]);
-                                cls = classify_margin(point_box32<D>(q[u], lo, hi) - s_rad2[cu_i[u]], band_rel * sc * sc);
-                            } else {
-                                cls = point_box64<D>(q[u], lo, hi) <= s_rad2[cu_i[u]] ? kHit : kMiss;
-                            }
-                            if (cls == kHit) atomicOr(&L.sf[p], 1u);
-                            else if (cls == kUnsure) atomicOr(&L.sf[p], 2u);
-                        }
-                    }
-                    __syncthreads();
-                }
-                // ---- decisions
-                int unsure_n = 0;
-                int2 rec0 = make_int2(0, 0), rec1 = make_int2(0, 0);   // registers, not a local array
-                for (int h = 0; h < 2; ++h) {
-                    const int p = tid + h * kBlock;
-                    if (p >= np) continue;
-                    const uint64_t hmp = L.hm[p], ump = kF32 ? L.um[p] : 0ull;
-                    if (!hmp && !ump) continue;
-                    const uint32_t f = L.sf[p];
-                    const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
-                    const bool unsure = kF32 && (!hmp || (!(f & 1u) && ((f & 2u) || ump)));
-                    if (unsure) {
-                        const int2 r = make_int2(L.edge[te], L.gidx[s]);
-                        if (unsure_n == 0) rec0 = r;
-                        else rec1 = r;
-                        ++unsure_n;
-                    } else {
-                        const int sign = L.sign[s];
-                        atomicAdd(&L.dC[te], sign);
-                        if (f & 1u) atomicAdd(&L.dS[te], sign);
-                        ++n_outer;
-                    }
-                }
-                if constexpr (kF32) {
-                    int tot_u;
-                    const int upre = block_scan(unsure_n, &tot_u, L.wsum);
-                    if (tot_u > 0) {
-                        const int base = L.rc_n;
-                        const bool fits = !L.defer && base + tot_u <= rm.rc_cap;
-                        if (fits) {
-                            int2 *dst = rm.rc + (int64_t)blockIdx.x * rm.rc_cap + base + upre;
-                            if (unsure_n > 0) dst[0] = rec0;
-                            if (unsure_n > 1) dst[1] = rec1;
-                        }
-                        __syncthreads();
-                        if (tid == 0) {
-                            if (fits) L.rc_n = base + tot_u;
-                            else L.defer = 1;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        }
-        if (have && my_pairs > 0) {
-            ++cand;
-            bytes += (2 * D + 1) * B * sizeof(T) + 16;
-        }
-        __syncthreads();
-        if (!L.defer) {
-            if (have) add_counts(rm, e, L.dC[tid], L.dS[tid]);
-        } else if (tid == 0) {
-            L.rc_n = L.rc_start;
-            rm.df[(int64_t)blockIdx.x * rm.df_cap + L.df_n] = it;
-            L.df_n += 1;
-        }
-    }
-    __syncthreads();
-    atomicAdd(&L.acc[0], n_pairs);
-    atomicAdd(&L.acc[1], n_outer);
-    atomicAdd(&L.acc[3], bytes);
-    atomicAdd(&L.acc[4], visited);
-    atomicAdd(&L.acc[5], cand);
-    __syncthreads();
-    if (tid == 0) {
-        unsigned long long *bs = rm.blk_stats + blockIdx.x * kStats;
-        if (!deferred) {
-            bs[0] = L.acc[0];
-            bs[1] = L.acc[1];
-            bs[2] = 0;
-            bs[3] = L.acc[3];
-            bs[4] = L.acc[4];
-            bs[5] = L.acc[5];
-            if (kF32) {
-                rm.rc_cnt[blockIdx.x] = L.rc_n;
-                rm.df_cnt[blockIdx.x] = L.df_n;
-            }
-        } else {
-            bs[1] += L.acc[1];
-            bs[2] += L.acc[0];
-            bs[3] += L.acc[3];
-        }
-    }
-}
-
-// ------------------------------------------------------------------------
-// k_recheck_pairs: binary64 decision of every pair an FP32 block left unsure
-// (the definition: C = some capsule meets, S = some sphere's capsule and one
-// of its copies meet), one wavefront per pair
+// binary64 re-test of one (edge, box) pair by one wavefront: the definition
+// (C = some capsule meets, S = some sphere's capsule and one of its copies
+// meet), used for the pairs whose binary32 decision fell inside the band
 // ------------------------------------------------------------------------
 
 struct CopyMap {
@@ -1006,22 +591,702 @@ __device__ bool copies_meet64(const RmDev &rm, const double *sb, int64_t P, cons
     return false;
 }
 
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_recheck_pairs(RmDev rm)
+// ------------------------------------------------------------------------
+// k_item: one block per grid work item (cell c, chunk of 256 of its edges).
+//
+//   1. every thread owns one edge of the item; the changed entries covering
+//      the cell are staged in LDS (tiles of kSubTile); a thread marks the
+//      entries whose box meets its edge's box, 32 per LDS word.  With several
+//      cells a pair is taken only by the cell holding the lower corner of the
+//      two boxes' intersection, so each (edge, entry) pair is tested once.
+//   2. outer test, lanes = (pair, sphere): capsule of sphere i against the
+//      entry's box (FP32: separation and end-sphere tests first, the exact
+//      segment-box minimum where they do not decide).  Each pair keeps the
+//      sphere whose capsule met deepest and the configuration nearest the
+//      capsule axis' closest point to the box.
+//   3. probe: that one copy is tested first.  S is an existence test, so a
+//      copy found to meet settles the pair and its other copies are not
+//      tested; the result is the same, only the order of the tests changes.
+//   4. inner test of the pairs the probe left open, lanes = (pair, sphere
+//      whose capsule met, configuration): every copy of those spheres.
+//   5. per pair C and S; the edge's counter deltas are summed in LDS and
+//      added once per edge.  In FP32 a pair whose decision fell inside the
+//      rounding band is decided again in binary64 by the same block, one
+//      wavefront per pair, before the item's counters are added.
+// ------------------------------------------------------------------------
+
+constexpr int kSubTile = 128;             // changed entries staged per tile
+constexpr int kWords = kSubTile / 32;     // overlap words per edge
+constexpr int kPairCap = kBlock;          // pairs per round (one per thread)
+constexpr int kRowCap = 512;              // (pair, sphere) rows per copy round
+constexpr int kWideCells = 64;            // pruning-grid cells an entry may cover
+constexpr int kEdgeCells = 64;            // pruning-grid cells an edge may visit
+static_assert(kWords == 4, "a pruning-grid cell holds one uint4 of entry bits");
+
+template <typename T>
+struct ExactBoxes {
+    T lo[3][kSubTile], hi[3][kSubTile];
+};
+struct NoBoxes {};
+struct Radii32 {
+    float r32[64];                        // sphere radii, binary32 (for the band)
+};
+struct NoRadii {};
+
+template <typename T>
+struct ItemLds {
+    float4 blo[kSubTile], bhi[kSubTile];  // binary32 boxes: (lo, sbox), (hi, 0)
+    int sign[kSubTile], gidx[kSubTile];
+    // binary64 boxes for the binary64 kernel (the binary32 ones serve FP32)
+    typename std::conditional<std::is_same<T, double>::value, ExactBoxes<double>, NoBoxes>::type x;
+    typename std::conditional<std::is_same<T, float>::value, Radii32, NoRadii>::type r;
+    uint32_t om[kWords][kBlock];          // staged entries each edge's box meets
+    uint4 lgm[kLocalCells];               // pruning grid: staged entries per cell
+    uint32_t wide[kWords];                // staged entries over many cells
+    int64_t es0[kBlock];                  // first sample of each edge of the item
+    int edge[kBlock], ej[kBlock];         // edge id, configurations per sphere
+    float es[kBlock];                     // edge s (largest |coordinate| of its box)
+    int dC[kBlock], dS[kBlock];
+    uint16_t pe[kPairCap];                // edge slot << 8 | staged entry
+    unsigned long long hm[kPairCap], um[kPairCap];
+    uint32_t probe[kPairCap];             // sphere << 24 | configuration tested first
+    uint32_t roff[kPairCap], sf[kPairCap];
+    uint32_t row[kRowCap];                // pair << 6 | sphere
+    uint32_t rcopy[kRowCap + 1];
+    int wsum[kWaves];
+    int rc_n, rc_start, defer, df_n;
+    unsigned long long acc[kStats];
+};
+
+template <int D, typename T>
+__device__ inline bool pair_owned(const RmDev &rm, const float4 &bl, const T *lo32, int64_t c)
 {
+    // lower corner of the intersection of the edge box and the entry box
+    int64_t cell = 0, mul = 1;
+    for (int k = 0; k < D; ++k) {
+        const float ek = k == 0 ? bl.x : (k == 1 ? bl.y : bl.z);
+        const float x = fmaxf(ek, (float)lo32[k]);
+        cell += (int64_t)clamp_cell((double)x, rm.gorg[k], rm.ginv, rm.gdim[k]) * mul;
+        mul *= rm.gdim[k];
+    }
+    return cell == c;
+}
+
+// Rounding band of a binary32 margin (squared-distance units): tau (s + R)
+// (R + L) + tau^2 s^2, where s bounds every coordinate of the pair, R is the
+// radius tested and L the L1 length of the capsule axis (0 for a sphere).
+// The margin's rounding error is below a third of it for tau = 2^-18 (the
+// derivation assumes s <= 2^20 R; beyond that every decision is re-tested).
+__device__ inline float band_of(float tau, float s, float R, float L)
+{
+    if (!(s <= 1048576.0f * R)) return INFINITY;
+    return tau * (s + R) * (R + L) + (s > 0.0f ? tau * tau * s * s : 0.0f);
+}
+
+// Pruning-grid cell range of a box (lo.xyz, hi.xyz), clamped to the grid.
+// floor, the subtraction and the product are monotone, so two boxes that
+// share a point share a cell.
+__device__ inline int lg_cell(float x, float org, float inv, int n)
+{
+    const float f = floorf((x - org) * inv);
+    return (int)fminf(fmaxf(f, 0.0f), (float)(n - 1));
+}
+
+__device__ inline void lg_range(const RmDev &rm, const float4 &lo, const float4 &hi, int r0[3], int r1[3])
+{
+    r0[0] = lg_cell(lo.x, rm.lg_org[0], rm.lg_inv, rm.lg_dim[0]);
+    r1[0] = lg_cell(hi.x, rm.lg_org[0], rm.lg_inv, rm.lg_dim[0]);
+    r0[1] = lg_cell(lo.y, rm.lg_org[1], rm.lg_inv, rm.lg_dim[1]);
+    r1[1] = lg_cell(hi.y, rm.lg_org[1], rm.lg_inv, rm.lg_dim[1]);
+    r0[2] = lg_cell(lo.z, rm.lg_org[2], rm.lg_inv, rm.lg_dim[2]);
+    r1[2] = lg_cell(hi.z, rm.lg_org[2], rm.lg_inv, rm.lg_dim[2]);
+}
+
+// order-preserving map of a binary32 value to an unsigned key
+__device__ inline uint32_t ordered_key(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// deferred == 0: the main pass, one block per item (grid kGrid).  deferred
+// == 1: the binary64 pass over the items the FP32 blocks left whole; block b
+// of that grid takes the item lists of FP32 blocks b, b + gridDim.x, ...
+template <int D, typename T>
+__device__ __forceinline__ void item_body(RmDev rm, int deferred)
+{
+    constexpr bool kF32 = std::is_same<T, float>::value;
+    __shared__ ItemLds<T> L;
+    __shared__ T s_rad2[64];
+    const Ctl *ctl = rm.ctl;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    const int B = rm.B;
+    const int Gw = 64 / B;
+    // lane -> (pair slot, sphere) of the capsule phase, read from LDS where
+    // needed rather than held in registers through the whole kernel
+    __shared__ int s_lane[64];
+    if (tid < 64) s_lane[tid] = ((tid / B) << 8) | (tid - (tid / B) * B);
+    const uint64_t gmask = B == 64 ? ~0ull : ((1ull << B) - 1ull);
+    if (tid < kStats) L.acc[tid] = 0;
+    if (tid < B) s_rad2[tid] = kF32 ? (T)rm.rad2_32[tid] : (T)(rm.rad64[tid] * rm.rad64[tid]);
+    if constexpr (kF32) {
+        if (tid < B) L.r.r32[tid] = (float)rm.rad64[tid];
+    }
+    if (tid == 0) {
+        L.rc_n = 0;
+        L.df_n = 0;
+    }
+    const int status = ctl->status;
+    __shared__ int s_dfn[kStatBlocks / kFp64Grid];
+    const int nreg = deferred ? kStatBlocks / (int)gridDim.x : 0;
+    if (tid < nreg) s_dfn[tid] = status == RGG_OK ? rm.df_cnt[blockIdx.x + tid * gridDim.x] : 0;
+    __syncthreads();
+    // wavefront-uniform counts (kept in scalar registers) and per-lane ones
+    uint32_t n_pairs = 0, visited = 0, cand = 0, n_outer = 0;
+    unsigned long long bytes = 0;
+    const int n_chg = ctl->n_chg;
+    const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
+    const bool single = rm.ncells == 1;
+    const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
+    const T *capb = kF32 ? (const T *)rm.cap32 : (const T *)rm.cap64;
+    const T *samp = kF32 ? (const T *)rm.samp32 : (const T *)rm.samp64;
+    const float band_rel = rm.band_rel;
+    const int jfix = rm.p_fixed ? rm.p_fixed / B : 0;
+    const int lgn = rm.lg_dim[0] * rm.lg_dim[1] * rm.lg_dim[2];
+    // next work item of this block; false when there is none
+    int rk = 0, li = deferred ? 0 : (int)blockIdx.x;
+    auto next_item = [&](int &it) -> bool {
+        if (!deferred) {
+            if (status != RGG_OK || li >= n_items) return false;
+            it = li;
+            li += gridDim.x;
+            return true;
+        }
+        while (rk < nreg && li >= s_dfn[rk]) {
+            ++rk;
+            li = 0;
+        }
+        if (rk >= nreg) return false;
+        it = rm.df[(int64_t)(blockIdx.x + rk * gridDim.x) * rm.df_cap + li];
+        ++li;
+        return true;
+    };
+    // coordinates of staged entry s in the kernel's precision
+    auto box_lo = [&](int k, int s) -> T {
+        if constexpr (kF32) return k == 0 ? L.blo[s].x : (k == 1 ? L.blo[s].y : L.blo[s].z);
+        else return L.x.lo[k][s];
+    };
+    auto box_hi = [&](int k, int s) -> T {
+        if constexpr (kF32) return k == 0 ? L.bhi[s].x : (k == 1 ? L.bhi[s].y : L.bhi[s].z);
+        else return L.x.hi[k][s];
+    };
+    int it;
+    while (next_item(it)) {
+        const int2 item = rm.items[it];
+        const int64_t c = item.x;
+        const int32_t cx = (int32_t)(c % rm.gdim[0]);
+        const int32_t cy = (int32_t)((c / rm.gdim[0]) % rm.gdim[1]);
+        const int32_t cz = (int32_t)(c / ((int64_t)rm.gdim[0] * rm.gdim[1]));
+        const int64_t beg = (int64_t)rm.cell_start[c] + (int64_t)item.y * rm.chunk;
+        const int64_t end = min((int64_t)rm.cell_start[c + 1], beg + rm.chunk);
+        const bool have = beg + tid < end;
+        int e = 0;
+        float es = 0.0f;
+        int64_t s0 = 0;
+        int J = 0;
+        if (have) {
+            e = rm.cell_edges[beg + tid];
+            es = aabb[2 * (int64_t)e].w;
+            s0 = rm.p_fixed ? (int64_t)e * rm.p_fixed : rm.soff[e];
+            J = (int)((rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0) / B);
+            bytes += 32;
+        }
+        visited += (uint32_t)__popcll(__ballot(have));
+        __syncthreads();
+        L.edge[tid] = e;
+        L.es[tid] = es;
+        L.es0[tid] = s0;
+        L.ej[tid] = J;
+        L.dC[tid] = 0;
+        L.dS[tid] = 0;
+        if (tid == 0) {
+            L.rc_start = L.rc_n;
+            L.defer = 0;
+            // the main pass visits every item once: clear the cell's mark with
+            // its first chunk, so the next update starts from zero marks
+            if (!deferred && item.y == 0) atomicAnd(&rm.cell_bits[c >> 5], ~(1u << (c & 31)));
+        }
+        int my_pairs = 0;
+        for (int j0 = 0; j0 < n_chg; j0 += kSubTile) {
+            // stage the entries covering this cell
+            const int j = j0 + tid;
+            bool in = false;
+            if (tid < kSubTile && j < n_chg) {
+                const ChgEntry &en = rm.chg[j];
+                in = single || (cx >= en.c0[0] && cx <= en.c1[0] && cy >= en.c0[1] && cy <= en.c1[1] &&
+                                cz >= en.c0[2] && cz <= en.c1[2]);
+            }
+            int nt;
+            const int pos = block_scan(in ? 1 : 0, &nt, L.wsum);
+            if (in) {
+                const ChgEntry &en = rm.chg[j];
+                L.blo[pos] = make_float4(en.lo32[0], en.lo32[1], en.lo32[2], en.sbox);
+                L.bhi[pos] = make_float4(en.hi32[0], en.hi32[1], en.hi32[2], 0.0f);
+                if constexpr (!kF32) {
+                    for (int k = 0; k < 3; ++k) {
+                        L.x.lo[k][pos] = en.lo[k];
+                        L.x.hi[k][pos] = en.hi[k];
+                    }
+                }
+                L.sign[pos] = en.sign;
+                L.gidx[pos] = j;
+            }
+            if (nt == 0) continue;   // uniform: nt is the block total
+            const int nw = (nt + 31) >> 5;
+            __syncthreads();
+            // block-local pruning grid: each cell's mask of the staged
+            // entries whose box covers it (an entry over more than kWideCells
+            // cells is a candidate of every edge)
+            for (int q = tid; q < lgn; q += kBlock) L.lgm[q] = make_uint4(0u, 0u, 0u, 0u);
+            if (tid < kWords) L.wide[tid] = 0u;
+            __syncthreads();
+            if (tid < nt) {
+                const float4 l = L.blo[tid], h = L.bhi[tid];
+                int r0[3], r1[3];
+                lg_range(rm, l, h, r0, r1);
+                const int ncov = (r1[0] - r0[0] + 1) * (r1[1] - r0[1] + 1) * (r1[2] - r0[2] + 1);
+                const uint32_t bit = 1u << (tid & 31);
+                const int wd = tid >> 5;
+                if (ncov > kWideCells) {
+                    atomicOr(&L.wide[wd], bit);
+                } else {
+                    uint32_t *mw = reinterpret_cast<uint32_t *>(L.lgm);
+                    for (int z = r0[2]; z <= r1[2]; ++z)
+                        for (int y = r0[1]; y <= r1[1]; ++y)
+                            for (int x = r0[0]; x <= r1[0]; ++x)
+                                atomicOr(&mw[((z * rm.lg_dim[1] + y) * rm.lg_dim[0] + x) * 4 + wd], bit);
+                }
+            }
+            __syncthreads();
+            // the staged entries this thread's edge meets, 32 per word: the
+            // candidates of the cells its box covers, then the exact test
+            // the edge's box (read per tile rather than held in registers)
+            float4 bl = make_float4(0, 0, 0, 0), bh = bl;
+            if (have) {
+                bl = aabb[2 * (int64_t)L.edge[tid]];
+                bh = aabb[2 * (int64_t)L.edge[tid] + 1];
+            }
+            uint32_t cw[kWords] = {0u, 0u, 0u, 0u};
+            if (have) {
+                int r0[3], r1[3];
+                lg_range(rm, bl, bh, r0, r1);
+                const int ncov = (r1[0] - r0[0] + 1) * (r1[1] - r0[1] + 1) * (r1[2] - r0[2] + 1);
+                if (ncov > kEdgeCells) {
+#pragma unroll
+                    for (int w = 0; w < kWords; ++w) cw[w] = ~0u;
+                } else {
+#pragma unroll
+                    for (int w = 0; w < kWords; ++w) cw[w] = L.wide[w];
+                    for (int z = r0[2]; z <= r1[2]; ++z)
+                        for (int y = r0[1]; y <= r1[1]; ++y)
+                            for (int x = r0[0]; x <= r1[0]; ++x) {
+                                const uint4 m = L.lgm[(z * rm.lg_dim[1] + y) * rm.lg_dim[0] + x];
+                                cw[0] |= m.x;
+                                cw[1] |= m.y;
+                                cw[2] |= m.z;
+                                cw[3] |= m.w;
+                            }
+                }
+            }
+            int cnt = 0;
+#pragma unroll
+            for (int w = 0; w < kWords; ++w) {
+                if (w < nw) {
+                    const int left = nt - 32 * w;   // staged entries from this word on
+                    uint32_t m = cw[w] & (left >= 32 ? ~0u : ((1u << left) - 1u)), bits = 0;
+                    while (m) {
+                        const int b = __ffs(m) - 1;
+                        m &= m - 1;
+                        const float4 l = L.blo[w * 32 + b], h = L.bhi[w * 32 + b];
+                        bool hit = (l.x <= bh.x) & (h.x >= bl.x) & (l.y <= bh.y) & (h.y >= bl.y) &
+                                   (l.z <= bh.z) & (h.z >= bl.z);
+                        if (hit && !single) {
+                            const float lo3[3] = {l.x, l.y, l.z};
+                            hit = pair_owned<D, float>(rm, bl, lo3, c);
+                        }
+                        bits |= (uint32_t)hit << b;
+                    }
+                    L.om[w][tid] = bits;
+                    cnt += __popc(bits);
+                }
+            }
+            my_pairs += cnt;
+            int tp;
+            const int pre = block_scan(cnt, &tp, L.wsum);
+            for (int r0 = 0; r0 < tp; r0 += kPairCap) {
+                const int np = min(kPairCap, tp - r0);
+                if (cnt > 0 && pre < r0 + np && pre + cnt > r0) {
+                    int k = pre;
+                    for (int w = 0; w < nw && k < r0 + np; ++w) {
+                        uint32_t m = L.om[w][tid];
+                        while (m && k < r0 + np) {
+                            const int s = (w << 5) + __ffs(m) - 1;
+                            m &= m - 1;
+                            if (k >= r0) L.pe[k - r0] = (uint16_t)((tid << 8) | s);
+                            ++k;
+                        }
+                    }
+                }
+                __syncthreads();
+                n_pairs += np;
+                // ---- outer test: lanes = (pair, sphere); each lane takes two
+                // pairs per step and issues both capsules' loads first
+                constexpr int kCapU = 2;
+                const int slot = s_lane[lane] >> 8, ci = s_lane[lane] & 255;
+                for (int p0 = 0; p0 < np; p0 += kWaves * Gw * kCapU) {
+                    T A[kCapU][D], Bq[kCapU][D], R2[kCapU];
+                    int pu[kCapU];
+#pragma unroll
+                    for (int u = 0; u < kCapU; ++u) {
+                        pu[u] = p0 + (u * kWaves + wv) * Gw + slot;
+                        R2[u] = T(0);
+                        if (slot < Gw && pu[u] < np) {
+                            const int te = L.pe[pu[u]] >> 8;
+                            const T *cp = capb + (int64_t)L.edge[te] * (2 * D + 1) * B;
+#pragma unroll
+                            for (int k = 0; k < D; ++k) {
+                                A[u][k] = cp[k * B + ci];
+                                Bq[u][k] = cp[(D + k) * B + ci];
+                            }
+                            R2[u] = cp[2 * D * B + ci];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kCapU; ++u) {
+                        const int p = pu[u];
+                        const bool act = slot < Gw && p < np;
+                        int cls = kMiss;
+                        T lo[D], hi[D];
+                        float band = 0.0f, mg = 0.0f, tpar = 0.0f;
+                        const T R = R2[u];
+                        const T RR = R * R;
+                        if (act) {
+                            const int s = L.pe[p] & 255;
+#pragma unroll
+                            for (int k = 0; k < D; ++k) {
+                                lo[k] = box_lo(k, s);
+                                hi[k] = box_hi(k, s);
+                            }
+                            if constexpr (kF32) {
+                                const float sc = fmaxf(L.es[L.pe[p] >> 8], L.blo[s].w);
+                                float len = 0.0f;
+#pragma unroll
+                                for (int k = 0; k < D; ++k) len += fabsf(Bq[u][k] - A[u][k]);
+                                band = band_of(band_rel, sc, R, len);
+                                float sep = 0.0f;
+#pragma unroll
+                                for (int k = 0; k < D; ++k)
+                                    sep = fmaxf(sep, fmaxf(lo[k] - fmaxf(A[u][k], Bq[u][k]), fminf(A[u][k], Bq[u][k]) - hi[k]));
+                                const float dA = point_box32<D>(A[u], lo, hi), dB = point_box32<D>(Bq[u], lo, hi);
+                                mg = fminf(dA, dB) - RR;
+                                tpar = dA <= dB ? 0.0f : 1.0f;
+                                cls = (sep > 0.0f && sep * sep - RR > band) ? kMiss : (mg < -band ? kHit : kOpen);
+                            } else {
+                                double ts;
+                                const double v = segbox64<D>(A[u], Bq[u], lo, hi, &ts);
+                                cls = v <= RR ? kHit : kMiss;
+                                mg = (float)(v - RR);
+                                tpar = (float)ts;
+                            }
+                        }
+                        if constexpr (kF32) {
+                            if (__ballot(cls == kOpen)) {
+                                if (cls == kOpen) {
+                                    float ts;
+                                    mg = segbox32<D>(A[u], Bq[u], lo, hi, ts) - RR;
+                                    tpar = ts;
+                                    cls = classify_margin(mg, band);
+                                }
+                            }
+                        }
+                        const uint64_t hmw = __ballot(cls == kHit), umw = __ballot(cls == kUnsure);
+                        // deepest certain hit of each pair: segmented minimum over its B lanes
+                        uint32_t key = cls == kHit ? ((ordered_key(mg) & ~63u) | (uint32_t)ci) : ~0u;
+                        for (int o = 1; o < B; o <<= 1) {
+                            const uint32_t v = __shfl_down(key, o);
+                            if (ci + o < B) key = min(key, v);
+                        }
+                        const int head = slot < Gw ? slot * B : lane;
+                        const uint32_t kb = __shfl(key, head);
+                        const int istar = (int)(kb & 63u);
+                        const float tstar = __shfl(tpar, kb != ~0u ? head + istar : lane);
+                        if (act && ci == 0) {
+                            L.hm[p] = (hmw >> (slot * B)) & gmask;
+                            L.um[p] = (umw >> (slot * B)) & gmask;
+                            if (kb != ~0u) {
+                                const int Je = L.ej[L.pe[p] >> 8];
+                                int js = (int)(tstar * (float)(Je - 1) + 0.5f);
+                                js = js < 0 ? 0 : (js > Je - 1 ? Je - 1 : js);
+                                L.probe[p] = ((uint32_t)istar << 24) | (uint32_t)js;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                // ---- probe: one copy per pair whose capsule met
+                const int p = tid;   // kPairCap == kBlock: this thread's pair
+                uint32_t f = 0;
+                uint64_t hmp = 0;
+                if (p < np) {
+                    hmp = L.hm[p];
+                    if (hmp) {
+                        const uint32_t pr = L.probe[p];
+                        const int i = (int)(pr >> 24), jj = (int)(pr & 0xFFFFFFu);
+                        const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
+                        const int Je = L.ej[te];
+                        const int64_t P = (int64_t)Je * B;
+                        const T *sb = samp + D * L.es0[te] + (int64_t)i * Je + jj;
+                        T q[D], lo[D], hi[D];
+#pragma unroll
+                        for (int k = 0; k < D; ++k) q[k] = sb[k * P];
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            lo[k] = box_lo(k, s);
+                            hi[k] = box_hi(k, s);
+                        }
+                        bytes += D * sizeof(T);
+                        if constexpr (kF32) {
+                            const float sc = fmaxf(L.es[te], L.blo[s].w);
+                            const int cls = classify_margin(point_box32<D>(q, lo, hi) - s_rad2[i],
+                                                            band_of(band_rel, sc, L.r.r32[i], 0.0f));
+                            f = cls == kHit ? 1u : (cls == kUnsure ? 2u : 0u);
+                        } else {
+                            f = point_box64<D>(q, lo, hi) <= s_rad2[i] ? 1u : 0u;
+                        }
+                    }
+                    L.sf[p] = f;
+                }
+                // ---- rows: one per (open pair, sphere whose capsule met)
+                const int ra = (p < np && !(f & 1u)) ? __popcll(hmp) : 0;
+                int nrows;
+                const int rpre = block_scan(ra, &nrows, L.wsum);
+                if (p < np) L.roff[p] = rpre;
+                __syncthreads();
+                for (int q0 = 0; q0 < nrows; q0 += kRowCap) {
+                    const int nr = min(kRowCap, nrows - q0);
+                    if (ra > 0 && rpre < q0 + nr && rpre + ra > q0) {
+                        uint64_t m = hmp;
+                        int r = rpre;
+                        while (m && r < q0 + nr) {
+                            const int i = __ffsll((unsigned long long)m) - 1;
+                            m &= m - 1;
+                            if (r >= q0) L.row[r - q0] = ((uint32_t)p << 6) | (uint32_t)i;
+                            ++r;
+                        }
+                    }
+                    __syncthreads();
+                    // copies of each row: fixed count, or a scan over the rows
+                    int ncopies = nr * jfix;
+                    if (!jfix) {
+                        int cj[2], sum = 0;
+                        for (int h = 0; h < 2; ++h) {
+                            const int r = tid * 2 + h;
+                            cj[h] = r < nr ? L.ej[L.pe[L.row[r] >> 6] >> 8] : 0;
+                            sum += cj[h];
+                        }
+                        const int cpre = block_scan(sum, &ncopies, L.wsum);
+                        int acc = cpre;
+                        for (int h = 0; h < 2; ++h) {
+                            const int r = tid * 2 + h;
+                            if (r < nr) L.rcopy[r] = acc;
+                            acc += cj[h];
+                        }
+                        if (tid == 0) L.rcopy[nr] = ncopies;
+                        __syncthreads();
+                    }
+                    // each thread gathers kCopyU copies (all their loads in
+                    // flight together), then tests them
+                    constexpr int kCopyU = 4;
+                    for (int c0 = 0; c0 < ncopies; c0 += kBlock * kCopyU) {
+                        T q[kCopyU][D];
+                        int cu_p[kCopyU], cu_i[kCopyU];
+#pragma unroll
+                        for (int u = 0; u < kCopyU; ++u) {
+                            const int cidx = c0 + u * kBlock + tid;
+                            cu_p[u] = -1;
+                            cu_i[u] = 0;
+                            if (cidx < ncopies) {
+                                int r, jj;
+                                if (jfix) {
+                                    r = cidx / jfix;
+                                    jj = cidx - r * jfix;
+                                } else {
+                                    int lo_ = 0, hi_ = nr - 1;   // last row with rcopy[r] <= cidx
+                                    while (lo_ < hi_) {
+                                        const int mid = (lo_ + hi_ + 1) >> 1;
+                                        if (L.rcopy[mid] <= (uint32_t)cidx) lo_ = mid;
+                                        else hi_ = mid - 1;
+                                    }
+                                    r = lo_;
+                                    jj = cidx - (int)L.rcopy[r];
+                                }
+                                const uint32_t rv = L.row[r];
+                                const int pp = (int)(rv >> 6);
+                                const int i = (int)(rv & 63u);
+                                const int te = L.pe[pp] >> 8;
+                                const int Je = L.ej[te];
+                                const int64_t P = (int64_t)Je * B;
+                                const T *sb = samp + D * L.es0[te] + (int64_t)i * Je + jj;
+#pragma unroll
+                                for (int k = 0; k < D; ++k) q[u][k] = sb[k * P];
+                                cu_p[u] = pp;
+                                cu_i[u] = i;
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < kCopyU; ++u) {
+                            const int pp = cu_p[u];
+                            if (pp < 0) continue;
+                            const int pv = L.pe[pp], te = pv >> 8, s = pv & 255;
+                            T lo[D], hi[D];
+#pragma unroll
+                            for (int k = 0; k < D; ++k) {
+                                lo[k] = box_lo(k, s);
+                                hi[k] = box_hi(k, s);
+                            }
+                            bytes += D * sizeof(T);
+                            int cls;
+                            if constexpr (kF32) {
+                                const float sc = fmaxf(L.es[te], L.blo[s].w);
+                                cls = classify_margin(point_box32<D>(q[u], lo, hi) - s_rad2[cu_i[u]],
+                                                      band_of(band_rel, sc, L.r.r32[cu_i[u]], 0.0f));
+                            } else {
+                                cls = point_box64<D>(q[u], lo, hi) <= s_rad2[cu_i[u]] ? kHit : kMiss;
+                            }
+                            if (cls == kHit) atomicOr(&L.sf[pp], 1u);
+                            else if (cls == kUnsure) atomicOr(&L.sf[pp], 2u);
+                        }
+                    }
+                    __syncthreads();
+                }
+                // ---- decisions
+                bool unsure = false;
+                int2 rec = make_int2(0, 0);
+                if (p < np) {
+                    const uint64_t ump = kF32 ? L.um[p] : 0ull;
+                    if (hmp || ump) {
+                        const uint32_t fp = L.sf[p];
+                        const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
+                        unsure = kF32 && (!hmp || (!(fp & 1u) && ((fp & 2u) || ump)));
+                        if (unsure) {
+                            rec = make_int2(L.edge[te], L.gidx[s]);
+                        } else {
+                            const int sign = L.sign[s];
+                            atomicAdd(&L.dC[te], sign);
+                            if (fp & 1u) atomicAdd(&L.dS[te], sign);
+                            ++n_outer;
+                        }
+                    }
+                }
+                if constexpr (kF32) {
+                    // undecided pairs go to this block's re-test region; when it
+                    // is full the item is left whole to the binary64 pass
+                    int tot_u;
+                    const int upre = block_scan(unsure ? 1 : 0, &tot_u, L.wsum);
+                    if (tot_u > 0) {
+                        const int base = L.rc_n;
+                        const bool fits = !L.defer && base + tot_u <= rm.rc_cap;
+                        if (fits && unsure) rm.rc[(int64_t)blockIdx.x * rm.rc_cap + base + upre] = rec;
+                        __syncthreads();
+                        if (tid == 0) {
+                            if (fits) L.rc_n = base + tot_u;
+                            else L.defer = 1;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        cand += (uint32_t)__popcll(__ballot(have && my_pairs > 0));
+        if (have && my_pairs > 0) bytes += (2 * D + 1) * B * sizeof(T) + 16;
+        __syncthreads();
+        if (!L.defer) {
+            if (have) add_counts(rm, L.edge[tid], L.dC[tid], L.dS[tid]);
+        } else if (tid == 0) {
+            L.rc_n = L.rc_start;
+            rm.df[(int64_t)blockIdx.x * rm.df_cap + L.df_n] = it;
+            L.df_n += 1;
+        }
+    }
+    __syncthreads();
+    // the binary64 pass counts its pairs as re-tested
+    if (tid == 0 && n_pairs) atomicAdd(&L.acc[deferred ? 2 : 0], (unsigned long long)n_pairs);
+    if (n_outer) atomicAdd(&L.acc[1], (unsigned long long)n_outer);
+    if (bytes) atomicAdd(&L.acc[3], bytes);
+    if (lane == 0 && visited) atomicAdd(&L.acc[4], (unsigned long long)visited);
+    if (lane == 0 && cand) atomicAdd(&L.acc[5], (unsigned long long)cand);
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long *bs = rm.blk_stats + blockIdx.x * kStats;
+        if (!deferred) {
+#pragma unroll
+            for (int k = 0; k < kStats; ++k) bs[k] = L.acc[k];
+            if (kF32) {
+                rm.rc_cnt[blockIdx.x] = L.rc_n;
+                rm.df_cnt[blockIdx.x] = L.df_n;
+            }
+        } else if (L.acc[1] | L.acc[2] | L.acc[3]) {
+            bs[1] += L.acc[1];
+            bs[2] += L.acc[2];
+            bs[3] += L.acc[3];
+        }
+    }
+}
+
+// The binary32 kernel is held to 128 VGPRs (four waves per SIMD, four
+// blocks per CU); the binary64 one keeps the compiler's choice.
+template <int D>
+__global__ void __launch_bounds__(kBlock, 4) k_item32(RmDev rm)
+{
+    item_body<D, float>(rm, 0);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_item64(RmDev rm)
+{
+    item_body<D, double>(rm, 0);
+}
+
+// Binary64 re-test of the pairs queued by the FP32 item blocks whose regions
+// this block takes (FP32 blocks b, b + gridDim.x, ...), one wavefront per pair.
+template <int D>
+__device__ void retest_pairs(const RmDev &rm)
+{
+    constexpr int kReg = kStatBlocks / kFp64Grid;
     __shared__ int s_lst[kWaves][64];
     __shared__ double s_rad[64];
+    __shared__ int s_off[kReg + 1];
     __shared__ unsigned long long s_acc[3];
-    const Ctl *ctl = rm.ctl;
-    const int lane = lane_id(), wv = threadIdx.x >> 6;
-    if (threadIdx.x < rm.B) s_rad[threadIdx.x] = rm.rad64[threadIdx.x];
-    if (threadIdx.x < 3) s_acc[threadIdx.x] = 0;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    const bool ok = rm.ctl->status == RGG_OK;
+    if (tid < rm.B) s_rad[tid] = rm.rad64[tid];
+    if (tid < 3) s_acc[tid] = 0;
+    // pair counts of this block's regions, as an exclusive prefix
+    if (tid < 64) {
+        const int n = (ok && tid < kReg) ? rm.rc_cnt[blockIdx.x + tid * gridDim.x] : 0;
+        int tot;
+        const int pre = wave_prefix(n, &tot);
+        if (tid <= kReg) s_off[tid] = pre;
+    }
     __syncthreads();
+    const int total = s_off[kReg];
     unsigned long long n_re = 0, n_outer = 0, bytes = 0;
-    const int n = ctl->status == RGG_OK ? rm.rc_cnt[blockIdx.x] : 0;
     const int B = rm.B;
-    for (int k = wv; k < n; k += kWaves) {
-        const int2 pr = rm.rc[(int64_t)blockIdx.x * rm.rc_cap + k];
+    int reg = 0;
+    for (int q = wv; q < total; q += kWaves) {
+        while (s_off[reg + 1] <= q) ++reg;
+        const int k = q - s_off[reg];
+        const int2 pr = rm.rc[(int64_t)(blockIdx.x + reg * gridDim.x) * rm.rc_cap + k];
         const int64_t e = pr.x;
         const ChgEntry &en = rm.chg[pr.y];
         double lo[D], hi[D];
@@ -1053,19 +1318,30 @@ __global__ void __launch_bounds__(kBlock) k_recheck_pairs(RmDev rm)
         ++n_outer;
         if (lane == 0) add_counts(rm, e, en.sign, S ? en.sign : 0);
     }
-    if (lane == 0) {
+    if (lane == 0 && n_re) {
         atomicAdd(&s_acc[0], n_re);
         atomicAdd(&s_acc[1], n_outer);
         atomicAdd(&s_acc[2], bytes);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0 && s_acc[0]) {
         unsigned long long *bs = rm.blk_stats + blockIdx.x * kStats;
         bs[1] += s_acc[1];
         bs[2] += s_acc[0];
         bs[3] += s_acc[2];
     }
 }
+
+// The binary64 pass of the FP32 mode: queued pairs, then the items left
+// whole (their blocks' re-test regions were full).
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_fp64(RmDev rm)
+{
+    retest_pairs<D>(rm);
+    __syncthreads();
+    item_body<D, double>(rm, 1);
+}
+
 // ------------------------------------------------------------------------
 // labels and the ordered gray list
 // ------------------------------------------------------------------------
@@ -1087,86 +1363,150 @@ __device__ inline int block_sum(int v, int *s_w)
     return t;
 }
 
-__global__ void __launch_bounds__(kBlock) k_count(RmDev rm, uint8_t *labels,
-                                                  rgg_update_result *res, int force)
+// Each thread of a label block owns kLabelRun consecutive edges of the tile.
+constexpr int kLabelRun = kLabelTile / kBlock;
+static_assert(kLabelRun == 16, "a run is stored as one 16-byte label word");
+
+__device__ inline void load_run(const RmDev &rm, int64_t e0, int2 (&c)[kLabelRun])
+{
+    if (e0 + kLabelRun <= rm.E) {
+        const int4 *src = reinterpret_cast<const int4 *>(rm.cnt + e0);   // 16-byte aligned: e0 % 16 == 0
+#pragma unroll
+        for (int h = 0; h < kLabelRun / 2; ++h) {
+            const int4 v = src[h];
+            c[2 * h] = make_int2(v.x, v.y);
+            c[2 * h + 1] = make_int2(v.z, v.w);
+        }
+    } else {
+#pragma unroll
+        for (int h = 0; h < kLabelRun; ++h) c[h] = e0 + h < rm.E ? rm.cnt[e0 + h] : make_int2(0, 0);
+    }
+}
+
+// k_count: gray edges per tile; the last block to finish turns the counts
+// into exclusive tile offsets (tile_cnt[t] becomes the first gray position of
+// tile t, tile_cnt[ntiles] the total) and reports the status and n_gray.
+__global__ void __launch_bounds__(kBlock) k_count(RmDev rm, rgg_update_result *res, int force)
 {
     __shared__ int s_w[kWaves];
-    const int status = force ? RGG_OK : rm.ctl->status;
-    const int64_t t0 = (int64_t)blockIdx.x * kLabelTile;
+    __shared__ int s_last;
+    const int tid = threadIdx.x;
+    const int64_t e0 = (int64_t)blockIdx.x * kLabelTile + (int64_t)tid * kLabelRun;
+    int2 c[kLabelRun];
+    load_run(rm, e0, c);
     int ng = 0;
-    for (int it = 0; it < kLabelTile / kBlock; ++it) {
-        const int64_t e = t0 + it * kBlock + threadIdx.x;
-        if (e < rm.E) {
-            const uint8_t lab = label_of(rm.cnt[e]);
-            if (status == RGG_OK && labels) labels[e] = lab;
-            ng += lab == RGG_GRAY;
-        }
-    }
-    const int64_t nwords = (rm.E + 31) / 32;
-    if (threadIdx.x < kLabelTile / 32) {
-        const int64_t w = t0 / 32 + threadIdx.x;
-        if (w < nwords) rm.edge_bits[w] = 0u;
-    }
+#pragma unroll
+    for (int h = 0; h < kLabelRun; ++h) ng += (e0 + h < rm.E && label_of(c[h]) == RGG_GRAY) ? 1 : 0;
     const int tot = block_sum(ng, s_w);
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         rm.tile_cnt[blockIdx.x] = tot;
-        if (blockIdx.x == 0 && res && !force) {
-            res->status = status;
-            res->n_changed = rm.ctl->n_chg;
+        const int done = __hip_atomic_fetch_add(&rm.ctl->tiles_done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = done == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // last block: exclusive scan of the tile counts, in place (each thread
+    // rewrites only its own run of tiles)
+    const int nt = (int)gridDim.x;
+    const int per = (nt + kBlock - 1) / kBlock;
+    const int t0 = tid * per, t1 = min(nt, t0 + per);
+    int sum = 0;
+    for (int t = t0; t < t1; ++t) sum += __hip_atomic_load(&rm.tile_cnt[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int total;
+    int run = block_scan(sum, &total, s_w);
+    for (int t = t0; t < t1; ++t) {
+        const int v = __hip_atomic_load(&rm.tile_cnt[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        rm.tile_cnt[t] = run;
+        run += v;
+    }
+    if (tid == 0) {
+        rm.tile_cnt[nt] = total;
+        rm.ctl->tiles_done = 0;   // ready for the next launch
+        if (res) {
+            const int status = force ? RGG_OK : rm.ctl->status;
+            res->n_gray = status == RGG_OK ? total : 0;
+            if (!force) {
+                res->status = status;
+                res->n_changed = rm.ctl->n_chg;
+            }
         }
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_write(RmDev rm, int64_t *gray, int64_t cap,
+// k_write: labels and the ordered gray list, one tile per block; block
+// `ntiles` instead folds the per-block statistics of the update.
+__global__ void __launch_bounds__(kBlock) k_write(RmDev rm, uint8_t *labels, int64_t *gray, int64_t cap,
                                                   rgg_update_result *res, int force)
 {
     __shared__ int s_w[kWaves];
-    __shared__ int s_wt[kWaves];
     __shared__ unsigned long long s_st[kStats];
-    const int status = force ? RGG_OK : rm.ctl->status;
-    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
-    int pre = 0;
-    for (int j = tid; j < (int)blockIdx.x; j += kBlock) pre += rm.tile_cnt[j];
-    int64_t off = block_sum(pre, s_w);
-    const int64_t t0 = (int64_t)blockIdx.x * kLabelTile;
-    for (int it = 0; it < kLabelTile / kBlock; ++it) {
-        const int64_t e = t0 + it * kBlock + tid;
-        const bool g = e < rm.E && label_of(rm.cnt[e]) == RGG_GRAY;
-        const uint64_t m = __ballot(g);
+    const int tid = threadIdx.x;
+    if ((int)blockIdx.x == rm.ntiles) {
+        if (force || !res) return;
+        if (tid < kStats) s_st[tid] = 0;
         __syncthreads();
-        if (lane == 0) s_wt[wv] = __popcll(m);
-        __syncthreads();
-        int64_t woff = off;
-        int tot = 0;
-        for (int w = 0; w < kWaves; ++w) {
-            if (w < wv) woff += s_wt[w];
-            tot += s_wt[w];
+        // all of this thread's loads are issued before the first add
+        constexpr int kRows = kStatBlocks / kBlock;
+        unsigned long long v[kRows][kStats];
+#pragma unroll
+        for (int h = 0; h < kRows; ++h)
+#pragma unroll
+            for (int k = 0; k < kStats; ++k) v[h][k] = rm.blk_stats[(h * kBlock + tid) * kStats + k];
+#pragma unroll
+        for (int k = 0; k < kStats; ++k) {
+            unsigned long long a = 0;
+#pragma unroll
+            for (int h = 0; h < kRows; ++h) a += v[h][k];
+            if (a) atomicAdd(&s_st[k], a);
         }
-        const int64_t pos = woff + __popcll(m & lanes_below());
-        if (g && status == RGG_OK && gray && pos < cap) gray[pos] = e;
-        off += tot;
-    }
-    if (blockIdx.x != gridDim.x - 1 || !res) return;
-    if (force) {
-        if (tid == 0) res->n_gray = off;
+        __syncthreads();
+        if (tid == 0) {
+            res->n_pairs = (int64_t)s_st[0];
+            res->n_outer_hits = (int64_t)s_st[1];
+            res->n_rechecked = (int64_t)s_st[2];
+            res->test_bytes = (int64_t)s_st[3];
+            res->n_cells_visited = (int64_t)s_st[4];
+            res->n_candidate_edges = (int64_t)s_st[5];
+        }
         return;
     }
-    // the last block also folds the per-block statistics
-    if (tid < kStats) s_st[tid] = 0;
-    __syncthreads();
-    unsigned long long acc[kStats] = {0, 0, 0, 0, 0, 0};
-    for (int b = tid; b < kStatBlocks; b += kBlock)
-        for (int k = 0; k < kStats; ++k) acc[k] += rm.blk_stats[b * kStats + k];
-    for (int k = 0; k < kStats; ++k) atomicAdd(&s_st[k], acc[k]);
-    __syncthreads();
-    if (tid == 0) {
-        res->n_gray = status == RGG_OK ? off : 0;
-        res->n_pairs = (int64_t)s_st[0];
-        res->n_outer_hits = (int64_t)s_st[1];
-        res->n_rechecked = (int64_t)s_st[2];
-        res->test_bytes = (int64_t)s_st[3];
-        res->n_cells_visited = (int64_t)s_st[4];
-        res->n_candidate_edges = (int64_t)s_st[5];
+    const int status = force ? RGG_OK : rm.ctl->status;
+    if (status != RGG_OK) return;
+    const int64_t e0 = (int64_t)blockIdx.x * kLabelTile + (int64_t)tid * kLabelRun;
+    int2 c[kLabelRun];
+    load_run(rm, e0, c);
+    uint8_t lab[kLabelRun];
+    int ng = 0;
+#pragma unroll
+    for (int h = 0; h < kLabelRun; ++h) {
+        lab[h] = label_of(c[h]);
+        ng += (e0 + h < rm.E && lab[h] == RGG_GRAY) ? 1 : 0;
+    }
+    if (labels) {
+        if (e0 + kLabelRun <= rm.E && ((uintptr_t)(labels + e0) & 15u) == 0) {
+            uint32_t wds[kLabelRun / 4];
+#pragma unroll
+            for (int q = 0; q < kLabelRun / 4; ++q)
+                wds[q] = (uint32_t)lab[4 * q] | ((uint32_t)lab[4 * q + 1] << 8) | ((uint32_t)lab[4 * q + 2] << 16) |
+                         ((uint32_t)lab[4 * q + 3] << 24);
+            *reinterpret_cast<uint4 *>(labels + e0) = make_uint4(wds[0], wds[1], wds[2], wds[3]);
+        } else {
+#pragma unroll
+            for (int h = 0; h < kLabelRun; ++h)
+                if (e0 + h < rm.E) labels[e0 + h] = lab[h];
+        }
+    }
+    int tot;
+    const int pre = block_scan(ng, &tot, s_w);
+    if (!gray || tot == 0) return;
+    int64_t pos = (int64_t)rm.tile_cnt[blockIdx.x] + pre;
+#pragma unroll
+    for (int h = 0; h < kLabelRun; ++h) {
+        if (e0 + h < rm.E && lab[h] == RGG_GRAY) {
+            if (pos < cap) gray[pos] = e0 + h;
+            ++pos;
+        }
     }
 }
 
@@ -1176,98 +1516,90 @@ namespace {
 
 void *item_fn(const RmDev &rm, bool f64)
 {
-    if (rm.D == 3) return f64 ? (void *)k_item<3, double> : (void *)k_item<3, float>;
-    return f64 ? (void *)k_item<2, double> : (void *)k_item<2, float>;
+    if (rm.D == 3) return f64 ? (void *)k_item64<3> : (void *)k_item32<3>;
+    return f64 ? (void *)k_item64<2> : (void *)k_item32<2>;
 }
 
-void *recheck_fn(const RmDev &rm)
+void *fp64_fn(const RmDev &rm)
 {
-    return rm.D == 3 ? (void *)k_recheck_pairs<3> : (void *)k_recheck_pairs<2>;
+    return rm.D == 3 ? (void *)k_fp64<3> : (void *)k_fp64<2>;
 }
 
 struct Node {
     void *fn;
-    dim3 grid, block;
-    int kind;   // 0 diff, 1 rm only, 2 item (deferred flag), 3 count, 4 write
-    int flag;
+    dim3 grid;
+    int kind;      // argument list: 0 diff, 1 (rm) only, 3 count, 4 write
+    int ev0, ev1;  // stage events ev[ev0..ev1] are recorded after the node
 };
 
-// the kernels of one update, in order; stage boundaries for the events after
-// the indices listed in `marks`
-int plan(const RmDev &rm, Node out[8])
+// The kernels of one update, in order.  Stage events: ev[0] before, ev[1]
+// after the diff, ev[2] and ev[3] after the cell activation, ev[4] after the
+// item kernel, ev[5] after the binary64 pass, ev[6] after the labels.  With
+// a single grid cell there is nothing to activate: k_diff emits the items.
+int plan(const RmDev &rm, Node out[6])
 {
     int n = 0;
-    out[n++] = {(void *)k_diff, dim3(1), dim3(kDiffBlock), 0, 0};
-    out[n++] = {(void *)k_cells, dim3(kCellsGrid), dim3(kBlock), 1, 0};
-    out[n++] = {item_fn(rm, !rm.mixed), dim3(kGrid), dim3(kBlock), 2, 0};
-    if (rm.mixed) {
-        out[n++] = {recheck_fn(rm), dim3(kGrid), dim3(kBlock), 1, 0};
-        out[n++] = {item_fn(rm, true), dim3(kGrid), dim3(kBlock), 2, 1};
-    }
-    out[n++] = {(void *)k_count, dim3(rm.ntiles), dim3(kBlock), 3, 0};
-    out[n++] = {(void *)k_write, dim3(rm.ntiles), dim3(kBlock), 4, 0};
+    const bool single = rm.ncells == 1;
+    out[n++] = {(void *)k_diff, dim3(1), 0, 1, single ? 3 : 1};
+    if (!single) out[n++] = {(void *)k_cells, dim3(kCellsGrid), 1, 2, 3};
+    out[n++] = {item_fn(rm, !rm.mixed), dim3(kGrid), 1, 4, rm.mixed ? 4 : 5};
+    if (rm.mixed) out[n++] = {fp64_fn(rm), dim3(kFp64Grid), 1, 5, 5};
+    out[n++] = {(void *)k_count, dim3(rm.ntiles), 3, -1, -1};
+    out[n++] = {(void *)k_write, dim3(rm.ntiles + 1), 4, 6, 6};
     return n;
 }
+
+// kernel arguments of one node (storage for the values lives in `Args`)
+struct Args {
+    RmDev r;
+    const rgg_box *ob, *nb;
+    uint8_t *lab;
+    int64_t *gray;
+    int64_t cap;
+    rgg_update_result *res;
+    int zero = 0;
+    void *diff[3], *one[1], *count[3], *write[6];
+    Args(const RmDev &rm, const UpdateArgs &a)
+        : r(rm), ob(a.old_b), nb(a.new_b), lab(a.labels), gray(a.gray), cap(a.gray_cap), res(a.res),
+          diff{&r, (void *)&ob, (void *)&nb}, one{&r}, count{&r, &res, &zero},
+          write{&r, &lab, &gray, &cap, &res, &zero}
+    {
+    }
+    Args(const Args &) = delete;
+    void **of(int kind)
+    {
+        return kind == 0 ? diff : (kind == 3 ? count : (kind == 4 ? write : one));
+    }
+    dim3 block(int kind) const { return dim3(kind == 0 ? kDiffBlock : kBlock); }
+};
 
 }  // namespace
 
 hipError_t launch_update(const RmDev &rm, const UpdateArgs &a, hipStream_t s, hipEvent_t *ev)
 {
     if (rm.chunk != kBlock) return hipErrorInvalidValue;   // one edge of an item per thread
-    Node nodes[8];
+    Node nodes[6];
     const int n = plan(rm, nodes);
+    Args args(rm, a);
     hipError_t err;
-    RmDev r = rm;
-    const rgg_box *ob = a.old_b, *nb = a.new_b;
-    uint8_t *lab = a.labels;
-    int64_t *gray = a.gray;
-    int64_t cap = a.gray_cap;
-    rgg_update_result *res = a.res;
-    int zero = 0, one = 1;
     if (ev && (err = hipEventRecord(ev[0], s)) != hipSuccess) return err;
     for (int k = 0; k < n; ++k) {
-        void *args_diff[] = {&r, (void *)&ob, (void *)&nb};
-        void *args_one[] = {&r};
-        void *args_item[] = {&r, nodes[k].flag ? (void *)&one : (void *)&zero};
-        void *args_count[] = {&r, &lab, &res, &zero};
-        void *args_write[] = {&r, &gray, &cap, &res, &zero};
-        void **args = nodes[k].kind == 0 ? args_diff
-                    : nodes[k].kind == 1 ? args_one
-                    : nodes[k].kind == 2 ? args_item
-                    : nodes[k].kind == 3 ? args_count
-                                         : args_write;
-        if ((err = hipLaunchKernel(nodes[k].fn, nodes[k].grid, nodes[k].block, args, 0, s)) != hipSuccess) return err;
-        if (ev) {
-            // ev[1] after diff, ev[2] after cells, ev[3] == ev[2] (the grid scan is
-            // part of the item kernel), ev[4] after the item kernel, ev[5] after
-            // the binary64 re-test, ev[6] after the labels
-            int mark = -1;
-            if (k == 0) mark = 1;
-            if (k == 1) mark = 2;
-            if (k == 2) mark = 4;
-            if (nodes[k].kind == 2 && nodes[k].flag) mark = 5;
-            if (!rm.mixed && k == 2) mark = 4;
-            if (mark == 2) {
-                if ((err = hipEventRecord(ev[2], s)) != hipSuccess) return err;
-                mark = 3;
-            }
-            if (mark == 4 && !rm.mixed) {
-                if ((err = hipEventRecord(ev[4], s)) != hipSuccess) return err;
-                mark = 5;
-            }
-            if (mark >= 0 && (err = hipEventRecord(ev[mark], s)) != hipSuccess) return err;
-        }
+        const Node &nd = nodes[k];
+        if ((err = hipLaunchKernel(nd.fn, nd.grid, args.block(nd.kind), args.of(nd.kind), 0, s)) != hipSuccess)
+            return err;
+        if (ev && nd.ev0 >= 0)
+            for (int m = nd.ev0; m <= nd.ev1; ++m)
+                if ((err = hipEventRecord(ev[m], s)) != hipSuccess) return err;
     }
-    if (ev && (err = hipEventRecord(ev[6], s)) != hipSuccess) return err;
     return hipSuccess;
 }
 
 hipError_t launch_labels(const RmDev &rm, const UpdateArgs &a, hipStream_t s)
 {
-    k_count<<<rm.ntiles, kBlock, 0, s>>>(rm, a.labels, a.res, 1);
+    k_count<<<rm.ntiles, kBlock, 0, s>>>(rm, a.res, 1);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    k_write<<<rm.ntiles, kBlock, 0, s>>>(rm, a.gray, a.gray_cap, a.res, 1);
+    k_write<<<rm.ntiles, kBlock, 0, s>>>(rm, a.labels, a.gray, a.gray_cap, a.res, 1);
     return hipGetLastError();
 }
 
@@ -1275,34 +1607,17 @@ hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, 
                             hipGraphNode_t *last)
 {
     if (rm.chunk != kBlock) return hipErrorInvalidValue;
-    Node nodes[8];
+    Node nodes[6];
     const int n = plan(rm, nodes);
-    // argument storage: hipGraphAddKernelNode copies the values
-    RmDev r = rm;
-    const rgg_box *ob = a.old_b, *nb = a.new_b;
-    uint8_t *lab = a.labels;
-    int64_t *gray = a.gray;
-    int64_t cap = a.gray_cap;
-    rgg_update_result *res = a.res;
-    int zero = 0, one = 1;
+    Args args(rm, a);   // hipGraphAddKernelNode copies the argument values
     hipGraphNode_t prev = dep;
     for (int k = 0; k < n; ++k) {
-        void *args_diff[] = {&r, (void *)&ob, (void *)&nb};
-        void *args_one[] = {&r};
-        void *args_item[] = {&r, nodes[k].flag ? (void *)&one : (void *)&zero};
-        void *args_count[] = {&r, &lab, &res, &zero};
-        void *args_write[] = {&r, &gray, &cap, &res, &zero};
-        void **args = nodes[k].kind == 0 ? args_diff
-                    : nodes[k].kind == 1 ? args_one
-                    : nodes[k].kind == 2 ? args_item
-                    : nodes[k].kind == 3 ? args_count
-                                         : args_write;
         hipKernelNodeParams p = {};
         p.func = nodes[k].fn;
         p.gridDim = nodes[k].grid;
-        p.blockDim = nodes[k].block;
+        p.blockDim = args.block(nodes[k].kind);
         p.sharedMemBytes = 0;
-        p.kernelParams = args;
+        p.kernelParams = args.of(nodes[k].kind);
         p.extra = nullptr;
         hipGraphNode_t node;
         hipError_t err = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);

@@ -15,8 +15,7 @@ struct Ctl {
     int32_t status;        // RGG_OK / RGG_E_INVALID_ARG / RGG_E_STATE_MISMATCH
     int32_t n_chg;         // changed (box, sign) entries
     int32_t n_items;       // (cell, chunk) work items of the grid scan
-    int32_t n_work;        // candidate edges
-    unsigned long long n_pairs, n_outer, n_recheck, n_visited, test_bytes;
+    int32_t tiles_done;    // label tiles counted so far (the last one resets it)
 };
 
 // One changed obstacle entry: the box a slot held before (sign -1) or holds
@@ -55,22 +54,27 @@ struct RmDev {
     const int32_t *cell_start;
     const int32_t *cell_edges;
     int64_t items_cap;
+    // block-local pruning grid (binary32): cell of x on axis d is
+    // clamp(floor((x - lg_org[d]) * lg_inv), 0, lg_dim[d] - 1)
+    float lg_org[3];
+    float lg_inv;
+    int32_t lg_dim[3];
+    int32_t pad2;
     // state and per-update scratch
     int2 *cnt;                 // [E] (outer, inner) counters
-    uint32_t *edge_bits;       // [ceil(E/32)] candidate marks, zero between updates
     uint32_t *cell_bits;       // [ceil(ncells/32)] touched cells, zero between updates
     rgg_box *resident;         // [M] obstacle slots
     ChgEntry *chg;             // [2M]
     int2 *items;               // [items_cap] (cell, chunk)
-    int2 *rc;                  // [kStatBlocks][rc_cap] (edge, entry) pairs left to the
-                               // binary64 re-test by each block of the FP32 item kernel
+    int2 *rc;                  // [kStatBlocks][rc_cap] (edge, entry) pairs each block of
+                               // the FP32 item kernel leaves to the binary64 re-test
     int32_t *rc_cnt;           // [kStatBlocks]
     int32_t rc_cap;
     int32_t df_cap;
     int32_t *df;               // [kStatBlocks][df_cap] items a block left whole to the
-                               // binary64 item kernel (its re-test region was full)
+                               // binary64 pass (its re-test region was full)
     int32_t *df_cnt;           // [kStatBlocks]
-    int32_t *tile_cnt;         // [ntiles] gray edges per label tile
+    int32_t *tile_cnt;         // [ntiles + 1] gray edges per label tile, then their offsets
     unsigned long long *blk_stats;   // [kStatBlocks][kStats] per-block partial counts
     Ctl *ctl;
 };
@@ -78,10 +82,11 @@ struct RmDev {
 // pairs, pairs whose outer approximation met, re-tested pairs, classify bytes,
 // grid entries scanned, candidate edges
 constexpr int kStats = 6;
-constexpr int kStatBlocks = 2048;  // blocks of the item and re-test kernels
+constexpr int kStatBlocks = 2048;  // blocks of the item kernels
 constexpr int kMaxSlots = 4096;    // 2*slots changed entries at most
-constexpr int kRcCap = 1024;       // default re-test pairs one item-kernel block may queue
 
+constexpr int kLocalCells = 512;   // cells of the item kernel's pruning grid (at most)
+constexpr int kRcCap = 1024;       // default re-test pairs one item-kernel block may queue
 constexpr int kLabelTile = 4096;   // edges per block of the label kernels
 
 struct UpdateArgs {

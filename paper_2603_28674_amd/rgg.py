@@ -198,7 +198,7 @@ def make_desc(q, edges, keep):
     return d
 
 
-def make_opts(resolution=0.0, samples_per_edge=0, precision=RGG_PREC_FP64, band_rel=1e-5,
+def make_opts(resolution=0.0, samples_per_edge=0, precision=RGG_PREC_FP64, band_rel=0.0,
               n_obstacle_slots=0, cell_size=0.0, host_threads=0, retest_capacity=0):
     o = rgg_build_opts()
     o.resolution = resolution
@@ -344,7 +344,7 @@ class Roadmap:
     """A roadmap resident on the GPU (wraps rgg_build / rgg_update / rgg_destroy)."""
 
     def __init__(self, ctx, robot, q, edges, n_slots, resolution=0.0, samples_per_edge=0,
-                 precision=RGG_PREC_FP64, band_rel=1e-5, cell_size=0.0, host_threads=0,
+                 precision=RGG_PREC_FP64, band_rel=0.0, cell_size=0.0, host_threads=0,
                  retest_capacity=0):
         keep = _Keep()
         self._keep = keep

@@ -47,7 +47,7 @@ def with_removals(w, rng):
     return w
 
 
-def check_sequence(ctx, w, precision, cell_size=0.0, band_rel=1e-5, device_buffers=False,
+def check_sequence(ctx, w, precision, cell_size=0.0, band_rel=0.0, device_buffers=False,
                    retest_capacity=0):
     import torch
     from paper_2603_28674_amd import rgg
@@ -178,12 +178,90 @@ def test_band_infinite_rechecks_every_decision(ctx):
 @pytest.mark.parametrize("kind", ["spatial", "planar"])
 def test_full_retest_regions_defer_whole_items(ctx, kind):
     """With room for one re-test pair per block and every decision inside the
-    band, blocks defer whole work items to the binary64 item kernel."""
+    band, blocks leave whole work items to the binary64 pass."""
     from paper_2603_28674_amd import rgg
     w = workload(kind, n_updates=2, seed=26)
     stats = check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, band_rel=float("inf"),
                            retest_capacity=1)
     assert all(s["n_rechecked"] > 0 for s in stats)
+
+
+@pytest.mark.parametrize("kind", ["planar", "arm"])
+def test_band_infinite_other_robots(ctx, kind):
+    """Every pair through the binary64 re-test, for the planar rigid body and
+    the arm."""
+    from paper_2603_28674_amd import rgg
+    w = workload(kind, n_updates=2, seed=26)
+    stats = check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, band_rel=float("inf"))
+    assert all(s["n_rechecked"] == s["n_pairs"] > 0 for s in stats)
+
+
+def near_tangent_boxes(o, w, rng, n_boxes):
+    """Small boxes, each just beyond the extreme point of one edge's swept
+    robot along one axis: one face at distance r (1 + eps) from the extreme
+    sphere copy, or at R (1 + eps) from the extreme capsule axis end (R =
+    capsule radius), |eps| log-uniform in [1e-9, 1e-3] with a random sign.
+    Each box puts one edge's decisive distance test at or inside binary32
+    rounding of its threshold."""
+    D = w.robot.dim
+    rad = w.robot.sphere_radius
+    out = np.zeros((n_boxes, 6))
+    for b in range(n_boxes):
+        e = int(rng.integers(w.n_edges))
+        cen = o.centres(e)                      # [J, B, D]
+        ax = int(rng.integers(D))
+        side = float(rng.choice([-1.0, 1.0]))
+        eps = float(rng.choice([-1.0, 1.0]) * 10.0 ** rng.uniform(-9.0, -3.0))
+        if rng.random() < 0.5:
+            reach = side * cen[:, :, ax] + rad[None, :]
+            j, i = np.unravel_index(int(np.argmax(reach)), reach.shape)
+            p = cen[j, i]
+            dist = rad[i] * (1.0 + eps)
+        else:
+            R = o.capsule_radius(e)
+            ends = np.stack([cen[0], cen[-1]])  # [2, B, D]
+            reach = side * ends[:, :, ax] + R[None, :]
+            j, i = np.unravel_index(int(np.argmax(reach)), reach.shape)
+            p = ends[j, i]
+            dist = R[i] * (1.0 + eps)
+        face = p[ax] + side * dist
+        depth = rng.uniform(0.01, 0.1)
+        lo = np.zeros(3)
+        hi = np.zeros(3)
+        for k in range(D):
+            if k == ax:
+                lo[k], hi[k] = (face, face + depth) if side > 0 else (face - depth, face)
+            else:
+                lo[k] = p[k] - rng.uniform(0.01, 0.1)
+                hi[k] = p[k] + rng.uniform(0.01, 0.1)
+        out[b, :3], out[b, 3:] = lo, hi
+    return out
+
+
+@pytest.mark.parametrize("kind", ["spatial", "planar", "arm"])
+def test_band_near_tangent(ctx, kind):
+    """Near-tangent boxes: with the default band every label equals the
+    oracle's (the undecided tests went to binary64).  With a band far below
+    the rounding error (1e-12) the same inputs give wrong labels, so they do
+    reach the cases the band has to cover."""
+    from paper_2603_28674_amd import rgg
+    import oracle
+    w = workload(kind, n_updates=1, seed=41)
+    o = oracle.from_workload(w)
+    # an arm edge sweeps a large area: few boxes keep labels other than RED
+    n_near = 4 if kind == "arm" else w.n_slots
+    boxes = w.absent()
+    boxes[:n_near] = near_tangent_boxes(o, w, np.random.default_rng(7), n_near)
+    w.boxes = [boxes]
+    stats = check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK)
+    assert stats[0]["n_rechecked"] > 0
+    ol, _ = oracle.from_workload(w).update(w.absent(), w.boxes[0])
+    g = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK, band_rel=1e-12)
+    lab, _, _, _ = g.update(w.absent(), w.boxes[0])
+    g.close()
+    bad = int(np.count_nonzero(lab != ol))
+    print(f"[teeth] {kind}: {bad} labels differ with band 1e-12", flush=True)
+    assert bad > 0
 
 
 def test_errors_leave_state_unchanged(ctx):
