@@ -5,7 +5,8 @@ Workload (default): the spatial rigid-body roadmap -- 8-sphere robot, 50,000
 (position, unit quaternion) nodes, k = 10 nearest-neighbour edges, 20
 configurations per edge, 500 box obstacles with sides U[0.2, 1.5] in a 10^3
 workspace; each update moves 10% of the boxes by N(0, 0.3) per axis; binary32
-tests with a binary64 re-test inside the rounding band (factor 2^-18).
+tests with a binary64 re-test inside a 1e-5 relative rounding band (relative to
+each test's own scale (s + R)(R + L)).
 
 A step is one update: every edge of the roadmap is classified (labels[E] and
 the gray list are produced).  Inputs (the roadmap and every obstacle state)
@@ -218,7 +219,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "spatial rigid-body roadmap (8 spheres, 50k nodes, k=10, 20 "
                                "configurations/edge, 500 boxes, 50 moved per update), "
-                               "FP32 tests + FP64 re-test in the rounding band",
+                               "FP32 tests + FP64 re-test inside a 1e-5 relative margin band",
                    "nodes": a.nodes, "edges": E, "obstacle_slots": M, "mode": "plain stream",
                    "cell_size": info["cell_size"], "grid_cells": info["grid_cells"]},
         "latency_p50_us": float(np.percentile(lat, 50)),

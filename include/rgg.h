@@ -114,9 +114,11 @@ typedef struct {
                                      the largest |coordinate| of the pair, R
                                      the radius tested and L the L1 length of
                                      the capsule axis (0 for a sphere copy).
-                                     <= 0 selects 2^-18; +inf re-tests every
-                                     pair.  Labels do not depend on it for any
-                                     value >= 2^-18.                            */
+                                     <= 0 selects 1e-5; +inf re-tests every
+                                     pair.  The FP32 rounding error is below
+                                     28 u s (R + L) + 7 u R^2 (u = 2^-24), so
+                                     labels do not depend on it for any value
+                                     >= 2^-18.                                  */
     int64_t n_obstacle_slots;     /* M, 0..4096                                 */
     double cell_size;             /* grid cell edge; 0 = heuristic; < 0 = one
                                      cell covering everything                   */
@@ -161,6 +163,7 @@ typedef struct {
 typedef struct rgg_context rgg_context;
 typedef struct rgg_roadmap rgg_roadmap;
 typedef struct rgg_graph rgg_graph;
+typedef struct rgg_batch rgg_batch;
 
 /* Opens `device` (HIP ordinal) for later builds.  *out receives the context. */
 rgg_status rgg_context_create(int device, rgg_context **out);
@@ -223,6 +226,30 @@ rgg_status rgg_graph_create(rgg_context *ctx, int32_t n, const rgg_update_req *r
                             rgg_graph **out);
 rgg_status rgg_graph_launch(rgg_graph *g, void *stream);
 rgg_status rgg_graph_destroy(rgg_graph *g);
+
+/* Batched updates of many roadmaps (at most 256, distinct, one device): one
+ * update of each roadmap per launch, all of them in a single captured graph
+ * whose kernels each process every roadmap of the batch (one launch per
+ * stage, not per roadmap; roadmaps of the same robot dimension and precision
+ * share one item kernel over the union of their work items).  Each update
+ * computes exactly what rgg_update_async computes for its roadmap.
+ *
+ * rgg_batch_create fixes the roadmaps (rms[n]).  rgg_batch_launch queues one
+ * batched update on `stream`: reqs[n] gives, in the same order, each
+ * roadmap's update arguments (reqs[k].rm must equal rms[k]); their device
+ * pointers may differ from launch to launch, since the request table is
+ * copied (from pinned host memory) in stream order before the graph runs.
+ * Errors: RGG_E_INVALID_ARG (null pointer, n out of range, a repeated
+ * roadmap, another device, a request that does not match its roadmap),
+ * RGG_E_DEVICE.  Device-side errors (bad box, state mismatch) are reported
+ * per request in its d_result, as for rgg_update_async. */
+rgg_status rgg_batch_create(rgg_context *ctx, int32_t n, rgg_roadmap *const *rms, rgg_batch **out);
+rgg_status rgg_batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *stream);
+rgg_status rgg_batch_destroy(rgg_batch *b);
+
+/* One batched update of n distinct roadmaps (create, launch, wait, destroy):
+ * the convenience form of the three calls above.  Blocks until done. */
+rgg_status rgg_update_batch(rgg_context *ctx, int32_t n, const rgg_update_req *reqs, void *stream);
 
 /* Current labels [E] / gray list of the last update, copied to host memory.
  * rgg_gray_list writes min(n, cap) ids and sets *n to the full count. */

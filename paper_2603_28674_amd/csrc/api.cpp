@@ -9,6 +9,7 @@
 #include <array>
 #include <chrono>
 #include <map>
+#include <memory>
 #include <string>
 #include <thread>
 #include <vector>
@@ -133,6 +134,38 @@ struct rgg_graph {
     std::vector<rgg_roadmap *> roadmaps;
 };
 
+struct rgg_batch {
+    static constexpr int kRing = 4;   // host request tables in flight
+    int device = 0;
+    int n = 0;
+    std::vector<rgg_roadmap *> rms;   // request order
+    std::vector<int32_t> order;       // request index of each table row
+    BatchReq *d_tab = nullptr;        // [n] rows, grouped by kernel variant
+    int32_t *d_grp = nullptr;         // [n] row indices, grouped
+    BatchReq *h_tab[kRing] = {};      // pinned
+    hipEvent_t copied[kRing] = {};
+    bool used[kRing] = {};
+    int ring = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    ~rgg_batch()
+    {
+        hipSetDevice(device);
+        for (int k = 0; k < kRing; ++k) {
+            if (copied[k]) {
+                if (used[k]) hipEventSynchronize(copied[k]);
+                hipEventDestroy(copied[k]);
+            }
+            if (h_tab[k]) hipHostFree(h_tab[k]);
+        }
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        if (d_tab) hipFree(d_tab);
+        if (d_grp) hipFree(d_grp);
+    }
+};
+
 extern "C" {
 
 const char *rgg_last_error(void) { return g_err.c_str(); }
@@ -182,7 +215,7 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     dv.chunk = kChunk;
     dv.E = E;
     dv.M = M;
-    dv.band_rel = (float)(opts->band_rel > 0.0 ? opts->band_rel : 0x1p-18);
+    dv.band_rel = (float)(opts->band_rel > 0.0 ? opts->band_rel : 1e-5);
     if (std::isinf(opts->band_rel)) dv.band_rel = INFINITY;
     dv.ntiles = (int32_t)std::max<int64_t>(1, (E + kLabelTile - 1) / kLabelTile);
     dv.p_fixed = 0;
@@ -556,6 +589,127 @@ rgg_status rgg_graph_destroy(rgg_graph *g)
     if (g->graph) hipGraphDestroy(g->graph);
     delete g;
     return RGG_OK;
+}
+
+rgg_status rgg_batch_create(rgg_context *ctx, int32_t n, rgg_roadmap *const *rms, rgg_batch **out)
+{
+    if (!ctx || !out || !rms) return fail(RGG_E_INVALID_ARG, "null argument");
+    if (n < 1 || n > kMaxBatch) return fail(RGG_E_INVALID_ARG, "n = %d, allowed 1..%d", n, kMaxBatch);
+    std::map<rgg_roadmap *, int> seen;
+    for (int32_t k = 0; k < n; ++k) {
+        if (!rms[k]) return fail(RGG_E_INVALID_ARG, "roadmap %d is null", k);
+        if (rms[k]->device != ctx->device) return fail(RGG_E_INVALID_ARG, "roadmap %d is on another device", k);
+        if (seen.count(rms[k])) return fail(RGG_E_INVALID_ARG, "roadmap %d repeats roadmap %d", k, seen[rms[k]]);
+        seen[rms[k]] = k;
+        if (rms[k]->dv.chunk != kChunk) return fail(RGG_E_INVALID_ARG, "roadmap %d has an unexpected chunk", k);
+    }
+    HIP_OR_FAIL(hipSetDevice(ctx->device), "hipSetDevice");
+    std::unique_ptr<rgg_batch> b(new rgg_batch());
+    b->device = ctx->device;
+    b->n = n;
+    b->rms.assign(rms, rms + n);
+    // table rows grouped by kernel variant (dimension, precision)
+    std::vector<BatchGroup> groups;
+    for (int D = 2; D <= 3; ++D)
+        for (int mixed = 0; mixed <= 1; ++mixed) {
+            BatchGroup g = {D, mixed, (int32_t)b->order.size(), 0};
+            for (int32_t k = 0; k < n; ++k)
+                if (rms[k]->dv.D == D && rms[k]->dv.mixed == mixed) {
+                    b->order.push_back(k);
+                    ++g.count;
+                }
+            if (g.count) groups.push_back(g);
+        }
+    bool any_grid = false;
+    int tiles = 0, wtiles = 0;
+    for (int32_t k = 0; k < n; ++k) {
+        any_grid = any_grid || rms[k]->dv.ncells > 1;
+        tiles += rms[k]->dv.ntiles;
+        wtiles += rms[k]->dv.ntiles + 1;
+    }
+    std::vector<int32_t> grp(n);
+    for (int32_t k = 0; k < n; ++k) grp[k] = k;   // rows are already grouped
+    HIP_OR_FAIL(hipMalloc(&b->d_tab, sizeof(BatchReq) * n), "batch table");
+    HIP_OR_FAIL(hipMalloc(&b->d_grp, sizeof(int32_t) * n), "batch groups");
+    HIP_OR_FAIL(hipMemcpy(b->d_grp, grp.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice), "batch groups");
+    for (int k = 0; k < rgg_batch::kRing; ++k) {
+        HIP_OR_FAIL(hipHostMalloc((void **)&b->h_tab[k], sizeof(BatchReq) * n, hipHostMallocDefault), "pinned table");
+        HIP_OR_FAIL(hipEventCreateWithFlags(&b->copied[k], hipEventDisableTiming), "hipEventCreate");
+    }
+    HIP_OR_FAIL(hipGraphCreate(&b->graph, 0), "hipGraphCreate");
+    hipGraphNode_t last = nullptr;
+    HIP_OR_FAIL(add_batch_nodes(b->graph, b->d_tab, b->d_grp, n, groups.data(), (int)groups.size(), any_grid,
+                                tiles, wtiles, nullptr, &last),
+                "hipGraphAddKernelNode");
+    HIP_OR_FAIL(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    *out = b.release();
+    return RGG_OK;
+}
+
+rgg_status rgg_batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *stream)
+{
+    if (!b || !reqs) return fail(RGG_E_INVALID_ARG, "null argument");
+    for (int k = 0; k < b->n; ++k) {
+        const rgg_update_req &q = reqs[k];
+        if (q.rm != b->rms[k]) return fail(RGG_E_INVALID_ARG, "request %d names another roadmap than the batch", k);
+        if (q.m != q.rm->dv.M || (q.m > 0 && (!q.d_old || !q.d_new)) || !q.d_result || q.gray_cap < 0)
+            return fail(RGG_E_INVALID_ARG, "bad request %d", k);
+    }
+    HIP_OR_FAIL(hipSetDevice(b->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    // a free host table: its previous copy has completed
+    const int slot = b->ring;
+    b->ring = (b->ring + 1) % rgg_batch::kRing;
+    if (b->used[slot]) HIP_OR_FAIL(hipEventSynchronize(b->copied[slot]), "hipEventSynchronize");
+    BatchReq *h = b->h_tab[slot];
+    int tile = 0, wtile = 0;
+    for (int row = 0; row < b->n; ++row) {
+        const rgg_update_req &q = reqs[b->order[row]];
+        BatchReq &t = h[row];
+        t.rm = q.rm->dv;
+        t.a = {q.d_old, q.d_new, q.d_labels, q.d_gray, q.d_gray ? q.gray_cap : 0, q.d_result};
+        t.tile0 = tile;
+        t.wtile0 = wtile;
+        tile += q.rm->dv.ntiles;
+        wtile += q.rm->dv.ntiles + 1;
+    }
+    for (rgg_roadmap *rm : b->rms) {
+        rgg_status st = order_after_previous(rm, s);
+        if (st != RGG_OK) return st;
+    }
+    HIP_OR_FAIL(hipMemcpyAsync(b->d_tab, h, sizeof(BatchReq) * b->n, hipMemcpyHostToDevice, s), "copy batch table");
+    HIP_OR_FAIL(hipEventRecord(b->copied[slot], s), "hipEventRecord");
+    b->used[slot] = true;
+    HIP_OR_FAIL(hipGraphLaunch(b->exec, s), "hipGraphLaunch");
+    for (rgg_roadmap *rm : b->rms) {
+        rgg_status st = finish_update(rm, s);
+        if (st != RGG_OK) return st;
+    }
+    return RGG_OK;
+}
+
+rgg_status rgg_batch_destroy(rgg_batch *b)
+{
+    if (!b) return fail(RGG_E_INVALID_ARG, "null batch");
+    delete b;
+    return RGG_OK;
+}
+
+rgg_status rgg_update_batch(rgg_context *ctx, int32_t n, const rgg_update_req *reqs, void *stream)
+{
+    if (!ctx || !reqs || n < 1 || n > kMaxBatch) return fail(RGG_E_INVALID_ARG, "bad argument");
+    std::vector<rgg_roadmap *> rms(n);
+    for (int32_t k = 0; k < n; ++k) rms[k] = reqs[k].rm;
+    rgg_batch *b = nullptr;
+    rgg_status st = rgg_batch_create(ctx, n, rms.data(), &b);
+    if (st != RGG_OK) return st;
+    st = rgg_batch_launch(b, reqs, stream);
+    if (st == RGG_OK) {
+        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) st = hip_fail(e, "batched update");
+    }
+    rgg_batch_destroy(b);
+    return st;
 }
 
 rgg_status rgg_debug_geometry(const rgg_roadmap_desc *rd, const rgg_robot *robot,

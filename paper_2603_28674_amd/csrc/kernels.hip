@@ -37,7 +37,8 @@ constexpr int kWaves = kBlock / 64;
 constexpr int kCellsGrid = 128;
 constexpr int kGrid = kStatBlocks; // blocks of the item kernels
 constexpr int kFp64Grid = 256;     // blocks of the binary64 pass of the FP32 mode
-static_assert(kStatBlocks % kFp64Grid == 0 && kStatBlocks / kFp64Grid < 64, "re-test regions per block");
+constexpr int kFp64BatchGrid = 32; // blocks per roadmap of the batched binary64 pass
+static_assert(kStatBlocks % kFp64Grid == 0 && kStatBlocks / kFp64BatchGrid <= 64, "re-test regions per block");
 static_assert(kStatBlocks % 256 == 0, "statistics rows are folded 256 at a time");
 
 enum : int { kMiss = 0, kHit = 1, kUnsure = 2, kOpen = 3 };
@@ -373,8 +374,8 @@ __device__ bool write_entry(const RmDev &rm, int pos, const rgg_box &b, int sign
     return !empty;
 }
 
-__global__ void __launch_bounds__(kDiffBlock) k_diff(RmDev rm, const rgg_box *__restrict__ old_b,
-                                                     const rgg_box *__restrict__ new_b)
+__device__ __forceinline__ void diff_body(const RmDev &rm, const rgg_box *__restrict__ old_b,
+                                          const rgg_box *__restrict__ new_b)
 {
     __shared__ int s_tot[kDiffBlock / 64];
     __shared__ int s_bad, s_mism, s_base, s_any;
@@ -445,11 +446,17 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff(RmDev rm, const rgg_box *__
     }
 }
 
+__global__ void __launch_bounds__(kDiffBlock) k_diff(RmDev rm, const rgg_box *__restrict__ old_b,
+                                                     const rgg_box *__restrict__ new_b)
+{
+    diff_body(rm, old_b, new_b);
+}
+
 // ------------------------------------------------------------------------
 // k_cells: touched cells -> work items (cell, chunk)
 // ------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kBlock) k_cells(RmDev rm)
+__device__ __forceinline__ void cells_body(const RmDev &rm)
 {
     const Ctl *ctl = rm.ctl;
     if (ctl->status != RGG_OK) return;
@@ -496,6 +503,11 @@ __global__ void __launch_bounds__(kBlock) k_cells(RmDev rm)
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cells(RmDev rm)
+{
+    cells_body(rm);
 }
 
 // ------------------------------------------------------------------------
@@ -618,7 +630,8 @@ __device__ bool copies_meet64(const RmDev &rm, const double *sb, int64_t P, cons
 constexpr int kSubTile = 128;             // changed entries staged per tile
 constexpr int kWords = kSubTile / 32;     // overlap words per edge
 constexpr int kPairCap = kBlock;          // pairs per round (one per thread)
-constexpr int kRowCap = 512;              // (pair, sphere) rows per copy round
+constexpr int kRowCap = 256;              // (pair, sphere) rows per copy round
+constexpr int kOpenCap = 1024;            // capsule tests queued for the exact part
 constexpr int kWideCells = 64;            // pruning-grid cells an entry may cover
 constexpr int kEdgeCells = 64;            // pruning-grid cells an edge may visit
 static_assert(kWords == 4, "a pruning-grid cell holds one uint4 of entry bits");
@@ -649,7 +662,9 @@ struct ItemLds {
     int dC[kBlock], dS[kBlock];
     uint16_t pe[kPairCap];                // edge slot << 8 | staged entry
     unsigned long long hm[kPairCap], um[kPairCap];
-    uint32_t probe[kPairCap];             // sphere << 24 | configuration tested first
+    uint32_t key[kPairCap];               // probe_key of the deepest capsule hit
+    uint32_t open[kOpenCap];              // queued (pair << 6 | sphere) capsule tests
+    int nopen;
     uint32_t roff[kPairCap], sf[kPairCap];
     uint32_t row[kRowCap];                // pair << 6 | sphere
     uint32_t rcopy[kRowCap + 1];
@@ -675,8 +690,9 @@ __device__ inline bool pair_owned(const RmDev &rm, const float4 &bl, const T *lo
 // Rounding band of a binary32 margin (squared-distance units): tau (s + R)
 // (R + L) + tau^2 s^2, where s bounds every coordinate of the pair, R is the
 // radius tested and L the L1 length of the capsule axis (0 for a sphere).
-// The margin's rounding error is below a third of it for tau = 2^-18 (the
-// derivation assumes s <= 2^20 R; beyond that every decision is re-tested).
+// The margin's rounding error is below 28 u s (R + L) + 7 u R^2 + O(u^2 s^2)
+// (u = 2^-24), so tau = 1e-5 (about 168 u) leaves a factor of six.  The
+// derivation assumes s <= 2^20 R; beyond that every decision is re-tested.
 __device__ inline float band_of(float tau, float s, float R, float L)
 {
     if (!(s <= 1048576.0f * R)) return INFINITY;
@@ -709,11 +725,23 @@ __device__ inline uint32_t ordered_key(float f)
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+// Probe key of a capsule hit: the margin's order (16 high bits), the
+// parameter of the closest point (10 bits) and the sphere (6 bits); the
+// minimum over a pair's hits names its deepest one.
+__device__ inline uint32_t probe_key(float mg, float t, int sphere)
+{
+    const uint32_t tq = (uint32_t)fminf(fmaxf(t, 0.0f) * 1023.0f + 0.5f, 1023.0f);
+    return (ordered_key(mg) & 0xFFFF0000u) | (tq << 6) | (uint32_t)sphere;
+}
+
 // deferred == 0: the main pass, one block per item (grid kGrid).  deferred
 // == 1: the binary64 pass over the items the FP32 blocks left whole; block b
 // of that grid takes the item lists of FP32 blocks b, b + gridDim.x, ...
+// deferred == 0: items li0, li0 + lstride, ... of the main pass; statistics
+// row and re-test region blockIdx.x.  deferred == 1: the items left whole in
+// re-test regions li0, li0 + lstride, ... (statistics row li0).
 template <int D, typename T>
-__device__ __forceinline__ void item_body(RmDev rm, int deferred)
+__device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0, int lstride)
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
     __shared__ ItemLds<T> L;
@@ -737,9 +765,15 @@ __device__ __forceinline__ void item_body(RmDev rm, int deferred)
         L.df_n = 0;
     }
     const int status = ctl->status;
-    __shared__ int s_dfn[kStatBlocks / kFp64Grid];
-    const int nreg = deferred ? kStatBlocks / (int)gridDim.x : 0;
-    if (tid < nreg) s_dfn[tid] = status == RGG_OK ? rm.df_cnt[blockIdx.x + tid * gridDim.x] : 0;
+    __shared__ int s_dfn[64];
+    const int nreg = deferred ? kStatBlocks / lstride : 0;
+    if (tid < nreg) {
+        // read, then clear for the next update (a batched pass leaves the
+        // regions of roadmaps a block did not visit untouched)
+        int *dc = rm.df_cnt + li0 + tid * lstride;
+        s_dfn[tid] = status == RGG_OK ? *dc : 0;
+        *dc = 0;
+    }
     __syncthreads();
     // wavefront-uniform counts (kept in scalar registers) and per-lane ones
     uint32_t n_pairs = 0, visited = 0, cand = 0, n_outer = 0;
@@ -754,12 +788,12 @@ __device__ __forceinline__ void item_body(RmDev rm, int deferred)
     const int jfix = rm.p_fixed ? rm.p_fixed / B : 0;
     const int lgn = rm.lg_dim[0] * rm.lg_dim[1] * rm.lg_dim[2];
     // next work item of this block; false when there is none
-    int rk = 0, li = deferred ? 0 : (int)blockIdx.x;
+    int rk = 0, li = deferred ? 0 : li0;
     auto next_item = [&](int &it) -> bool {
         if (!deferred) {
             if (status != RGG_OK || li >= n_items) return false;
             it = li;
-            li += gridDim.x;
+            li += lstride;
             return true;
         }
         while (rk < nreg && li >= s_dfn[rk]) {
@@ -767,7 +801,7 @@ __device__ __forceinline__ void item_body(RmDev rm, int deferred)
             li = 0;
         }
         if (rk >= nreg) return false;
-        it = rm.df[(int64_t)(blockIdx.x + rk * gridDim.x) * rm.df_cap + li];
+        it = rm.df[(int64_t)(li0 + rk * lstride) * rm.df_cap + li];
         ++li;
         return true;
     };
@@ -937,10 +971,29 @@ __device__ __forceinline__ void item_body(RmDev rm, int deferred)
                         }
                     }
                 }
+                // per-pair results start empty (kPairCap == kBlock: pair tid)
+                if (tid < np) {
+                    L.hm[tid] = 0ull;
+                    L.um[tid] = 0ull;
+                    L.key[tid] = ~0u;
+                }
+                if (tid == 0) L.nopen = 0;
                 __syncthreads();
                 n_pairs += np;
-                // ---- outer test: lanes = (pair, sphere); each lane takes two
-                // pairs per step and issues both capsules' loads first
+                // a (pair, sphere) result: capsule hit bits, the deepest hit as
+                // the probe key, undecided bits
+                auto record = [&](int p, int i, int cls, float mg, float tpar) {
+                    if (cls == kHit) {
+                        atomicOr(&L.hm[p], 1ull << i);
+                        atomicMin(&L.key[p], probe_key(mg, tpar, i));
+                    } else if (cls == kUnsure) {
+                        atomicOr(&L.um[p], 1ull << i);
+                    }
+                };
+                // ---- outer test, quick part: lanes = (pair, sphere); each lane
+                // takes two pairs per step and issues both capsules' loads first.
+                // FP32 lanes the quick tests leave open are queued for the exact
+                // part, so the segment-box minimum runs on dense wavefronts.
                 constexpr int kCapU = 2;
                 const int slot = s_lane[lane] >> 8, ci = s_lane[lane] & 255;
                 for (int p0 = 0; p0 < np; p0 += kWaves * Gw * kCapU) {
@@ -1000,39 +1053,54 @@ __device__ __forceinline__ void item_body(RmDev rm, int deferred)
                             }
                         }
                         if constexpr (kF32) {
-                            if (__ballot(cls == kOpen)) {
-                                if (cls == kOpen) {
-                                    float ts;
-                                    mg = segbox32<D>(A[u], Bq[u], lo, hi, ts) - RR;
-                                    tpar = ts;
-                                    cls = classify_margin(mg, band);
+                            const bool op = cls == kOpen;
+                            const uint64_t ob = __ballot(op);
+                            if (ob) {
+                                int base = 0;
+                                if (lane == 0) base = atomicAdd(&L.nopen, __popcll(ob));
+                                base = __shfl(base, 0);
+                                if (op) {
+                                    const int q = base + __popcll(ob & lanes_below());
+                                    if (q < kOpenCap) {
+                                        L.open[q] = ((uint32_t)p << 6) | (uint32_t)ci;
+                                        cls = kMiss;     // decided by the exact part
+                                    } else {
+                                        cls = kUnsure;   // queue full: the binary64 re-test decides
+                                    }
                                 }
                             }
                         }
-                        const uint64_t hmw = __ballot(cls == kHit), umw = __ballot(cls == kUnsure);
-                        // deepest certain hit of each pair: segmented minimum over its B lanes
-                        uint32_t key = cls == kHit ? ((ordered_key(mg) & ~63u) | (uint32_t)ci) : ~0u;
-                        for (int o = 1; o < B; o <<= 1) {
-                            const uint32_t v = __shfl_down(key, o);
-                            if (ci + o < B) key = min(key, v);
-                        }
-                        const int head = slot < Gw ? slot * B : lane;
-                        const uint32_t kb = __shfl(key, head);
-                        const int istar = (int)(kb & 63u);
-                        const float tstar = __shfl(tpar, kb != ~0u ? head + istar : lane);
-                        if (act && ci == 0) {
-                            L.hm[p] = (hmw >> (slot * B)) & gmask;
-                            L.um[p] = (umw >> (slot * B)) & gmask;
-                            if (kb != ~0u) {
-                                const int Je = L.ej[L.pe[p] >> 8];
-                                int js = (int)(tstar * (float)(Je - 1) + 0.5f);
-                                js = js < 0 ? 0 : (js > Je - 1 ? Je - 1 : js);
-                                L.probe[p] = ((uint32_t)istar << 24) | (uint32_t)js;
-                            }
-                        }
+                        if (act) record(p, ci, cls, mg, tpar);
                     }
                 }
                 __syncthreads();
+                if constexpr (kF32) {
+                    // ---- outer test, exact part: the queued tasks, one per lane
+                    const int nq = min(L.nopen, kOpenCap);
+                    for (int q = tid; q < nq; q += kBlock) {
+                        const uint32_t tk = L.open[q];
+                        const int p = (int)(tk >> 6), i = (int)(tk & 63u);
+                        const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
+                        const float *cp = (const float *)capb + (int64_t)L.edge[te] * (2 * D + 1) * B;
+                        float A[D], Bq[D], lo[D], hi[D];
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            A[k] = cp[k * B + i];
+                            Bq[k] = cp[(D + k) * B + i];
+                            lo[k] = box_lo(k, s);
+                            hi[k] = box_hi(k, s);
+                        }
+                        const float R = cp[2 * D * B + i];
+                        const float sc = fmaxf(L.es[te], L.blo[s].w);
+                        float len = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < D; ++k) len += fabsf(Bq[k] - A[k]);
+                        float ts;
+                        const float mg = segbox32<D>(A, Bq, lo, hi, ts) - R * R;
+                        record(p, i, classify_margin(mg, band_of(band_rel, sc, R, len)), mg, ts);
+                    }
+                    __syncthreads();
+                }
                 // ---- probe: one copy per pair whose capsule met
                 const int p = tid;   // kPairCap == kBlock: this thread's pair
                 uint32_t f = 0;
@@ -1040,10 +1108,12 @@ __device__ __forceinline__ void item_body(RmDev rm, int deferred)
                 if (p < np) {
                     hmp = L.hm[p];
                     if (hmp) {
-                        const uint32_t pr = L.probe[p];
-                        const int i = (int)(pr >> 24), jj = (int)(pr & 0xFFFFFFu);
+                        const uint32_t key = L.key[p];
+                        const int i = (int)(key & 63u);
                         const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
                         const int Je = L.ej[te];
+                        // the configuration nearest the deepest capsule's closest point
+                        const int jj = min(Je - 1, (int)((float)((key >> 6) & 1023u) * (1.0f / 1023.0f) * (float)(Je - 1) + 0.5f));
                         const int64_t P = (int64_t)Je * B;
                         const T *sb = samp + D * L.es0[te] + (int64_t)i * Je + jj;
                         T q[D], lo[D], hi[D];
@@ -1226,20 +1296,18 @@ __device__ __forceinline__ void item_body(RmDev rm, int deferred)
     if (lane == 0 && visited) atomicAdd(&L.acc[4], (unsigned long long)visited);
     if (lane == 0 && cand) atomicAdd(&L.acc[5], (unsigned long long)cand);
     __syncthreads();
-    if (tid == 0) {
-        unsigned long long *bs = rm.blk_stats + blockIdx.x * kStats;
-        if (!deferred) {
-#pragma unroll
-            for (int k = 0; k < kStats; ++k) bs[k] = L.acc[k];
-            if (kF32) {
-                rm.rc_cnt[blockIdx.x] = L.rc_n;
-                rm.df_cnt[blockIdx.x] = L.df_n;
-            }
-        } else if (L.acc[1] | L.acc[2] | L.acc[3]) {
-            bs[1] += L.acc[1];
-            bs[2] += L.acc[2];
-            bs[3] += L.acc[3];
+    // statistic k at bs[k * kStatBlocks]
+    unsigned long long *bs = rm.blk_stats + (deferred ? li0 : (int)blockIdx.x);
+    if (!deferred) {
+        if (tid < kStats) bs[tid * kStatBlocks] = L.acc[tid];
+        if (kF32 && tid == 0) {
+            rm.rc_cnt[blockIdx.x] = L.rc_n;
+            rm.df_cnt[blockIdx.x] = L.df_n;
         }
+    } else if (tid == 0 && (L.acc[1] | L.acc[2] | L.acc[3])) {
+        bs[1 * kStatBlocks] += L.acc[1];
+        bs[2 * kStatBlocks] += L.acc[2];
+        bs[3 * kStatBlocks] += L.acc[3];
     }
 }
 
@@ -1248,24 +1316,25 @@ __device__ __forceinline__ void item_body(RmDev rm, int deferred)
 template <int D>
 __global__ void __launch_bounds__(kBlock, 4) k_item32(RmDev rm)
 {
-    item_body<D, float>(rm, 0);
+    item_body<D, float>(rm, 0, (int)blockIdx.x, (int)gridDim.x);
 }
 
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_item64(RmDev rm)
 {
-    item_body<D, double>(rm, 0);
+    item_body<D, double>(rm, 0, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // Binary64 re-test of the pairs queued by the FP32 item blocks whose regions
 // this block takes (FP32 blocks b, b + gridDim.x, ...), one wavefront per pair.
+// Re-test regions b, b + G, ... (at most 64 of them); statistics row b.
 template <int D>
-__device__ void retest_pairs(const RmDev &rm)
+__device__ __forceinline__ void retest_pairs(const RmDev &rm, int b, int G)
 {
-    constexpr int kReg = kStatBlocks / kFp64Grid;
+    const int kReg = kStatBlocks / G;
     __shared__ int s_lst[kWaves][64];
     __shared__ double s_rad[64];
-    __shared__ int s_off[kReg + 1];
+    __shared__ int s_off[65];
     __shared__ unsigned long long s_acc[3];
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     const bool ok = rm.ctl->status == RGG_OK;
@@ -1273,10 +1342,16 @@ __device__ void retest_pairs(const RmDev &rm)
     if (tid < 3) s_acc[tid] = 0;
     // pair counts of this block's regions, as an exclusive prefix
     if (tid < 64) {
-        const int n = (ok && tid < kReg) ? rm.rc_cnt[blockIdx.x + tid * gridDim.x] : 0;
+        int n = 0;
+        if (tid < kReg) {
+            int *rc = rm.rc_cnt + b + tid * G;
+            n = ok ? *rc : 0;
+            *rc = 0;   // cleared for the next update
+        }
         int tot;
         const int pre = wave_prefix(n, &tot);
-        if (tid <= kReg) s_off[tid] = pre;
+        if (tid < kReg) s_off[tid] = pre;
+        if (tid == 0) s_off[kReg] = tot;
     }
     __syncthreads();
     const int total = s_off[kReg];
@@ -1286,7 +1361,7 @@ __device__ void retest_pairs(const RmDev &rm)
     for (int q = wv; q < total; q += kWaves) {
         while (s_off[reg + 1] <= q) ++reg;
         const int k = q - s_off[reg];
-        const int2 pr = rm.rc[(int64_t)(blockIdx.x + reg * gridDim.x) * rm.rc_cap + k];
+        const int2 pr = rm.rc[(int64_t)(b + reg * G) * rm.rc_cap + k];
         const int64_t e = pr.x;
         const ChgEntry &en = rm.chg[pr.y];
         double lo[D], hi[D];
@@ -1325,21 +1400,28 @@ __device__ void retest_pairs(const RmDev &rm)
     }
     __syncthreads();
     if (tid == 0 && s_acc[0]) {
-        unsigned long long *bs = rm.blk_stats + blockIdx.x * kStats;
-        bs[1] += s_acc[1];
-        bs[2] += s_acc[0];
-        bs[3] += s_acc[2];
+        unsigned long long *bs = rm.blk_stats + b;
+        bs[1 * kStatBlocks] += s_acc[1];
+        bs[2 * kStatBlocks] += s_acc[0];
+        bs[3 * kStatBlocks] += s_acc[2];
     }
 }
 
 // The binary64 pass of the FP32 mode: queued pairs, then the items left
 // whole (their blocks' re-test regions were full).
+// regions b, b + G, ... of one roadmap
+template <int D>
+__device__ __forceinline__ void fp64_body(const RmDev &rm, int b, int G)
+{
+    retest_pairs<D>(rm, b, G);
+    __syncthreads();
+    item_body<D, double>(rm, 1, b, G);
+}
+
 template <int D>
 __global__ void __launch_bounds__(kBlock) k_fp64(RmDev rm)
 {
-    retest_pairs<D>(rm);
-    __syncthreads();
-    item_body<D, double>(rm, 1);
+    fp64_body<D>(rm, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // ------------------------------------------------------------------------
@@ -1386,12 +1468,12 @@ __device__ inline void load_run(const RmDev &rm, int64_t e0, int2 (&c)[kLabelRun
 // k_count: gray edges per tile; the last block to finish turns the counts
 // into exclusive tile offsets (tile_cnt[t] becomes the first gray position of
 // tile t, tile_cnt[ntiles] the total) and reports the status and n_gray.
-__global__ void __launch_bounds__(kBlock) k_count(RmDev rm, rgg_update_result *res, int force)
+__device__ __forceinline__ void count_body(const RmDev &rm, rgg_update_result *res, int force, int tile)
 {
     __shared__ int s_w[kWaves];
     __shared__ int s_last;
     const int tid = threadIdx.x;
-    const int64_t e0 = (int64_t)blockIdx.x * kLabelTile + (int64_t)tid * kLabelRun;
+    const int64_t e0 = (int64_t)tile * kLabelTile + (int64_t)tid * kLabelRun;
     int2 c[kLabelRun];
     load_run(rm, e0, c);
     int ng = 0;
@@ -1399,16 +1481,16 @@ __global__ void __launch_bounds__(kBlock) k_count(RmDev rm, rgg_update_result *r
     for (int h = 0; h < kLabelRun; ++h) ng += (e0 + h < rm.E && label_of(c[h]) == RGG_GRAY) ? 1 : 0;
     const int tot = block_sum(ng, s_w);
     if (tid == 0) {
-        rm.tile_cnt[blockIdx.x] = tot;
+        rm.tile_cnt[tile] = tot;
         const int done = __hip_atomic_fetch_add(&rm.ctl->tiles_done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = done == (int)gridDim.x - 1;
+        s_last = done == rm.ntiles - 1;
     }
     __syncthreads();
     if (!s_last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     // last block: exclusive scan of the tile counts, in place (each thread
     // rewrites only its own run of tiles)
-    const int nt = (int)gridDim.x;
+    const int nt = rm.ntiles;
     const int per = (nt + kBlock - 1) / kBlock;
     const int t0 = tid * per, t1 = min(nt, t0 + per);
     int sum = 0;
@@ -1436,13 +1518,14 @@ __global__ void __launch_bounds__(kBlock) k_count(RmDev rm, rgg_update_result *r
 
 // k_write: labels and the ordered gray list, one tile per block; block
 // `ntiles` instead folds the per-block statistics of the update.
-__global__ void __launch_bounds__(kBlock) k_write(RmDev rm, uint8_t *labels, int64_t *gray, int64_t cap,
-                                                  rgg_update_result *res, int force)
+// tile == ntiles: fold (and clear) the per-block statistics instead
+__device__ __forceinline__ void write_body(const RmDev &rm, uint8_t *labels, int64_t *gray, int64_t cap,
+                                          rgg_update_result *res, int force, int tile)
 {
     __shared__ int s_w[kWaves];
     __shared__ unsigned long long s_st[kStats];
     const int tid = threadIdx.x;
-    if ((int)blockIdx.x == rm.ntiles) {
+    if (tile == rm.ntiles) {
         if (force || !res) return;
         if (tid < kStats) s_st[tid] = 0;
         __syncthreads();
@@ -1452,7 +1535,13 @@ __global__ void __launch_bounds__(kBlock) k_write(RmDev rm, uint8_t *labels, int
 #pragma unroll
         for (int h = 0; h < kRows; ++h)
 #pragma unroll
-            for (int k = 0; k < kStats; ++k) v[h][k] = rm.blk_stats[(h * kBlock + tid) * kStats + k];
+            for (int k = 0; k < kStats; ++k) v[h][k] = rm.blk_stats[k * kStatBlocks + h * kBlock + tid];
+        // cleared for the next update: a batched pass writes only the rows of
+        // the blocks that visited this roadmap
+#pragma unroll
+        for (int h = 0; h < kRows; ++h)
+#pragma unroll
+            for (int k = 0; k < kStats; ++k) rm.blk_stats[k * kStatBlocks + h * kBlock + tid] = 0ull;
 #pragma unroll
         for (int k = 0; k < kStats; ++k) {
             unsigned long long a = 0;
@@ -1473,7 +1562,7 @@ __global__ void __launch_bounds__(kBlock) k_write(RmDev rm, uint8_t *labels, int
     }
     const int status = force ? RGG_OK : rm.ctl->status;
     if (status != RGG_OK) return;
-    const int64_t e0 = (int64_t)blockIdx.x * kLabelTile + (int64_t)tid * kLabelRun;
+    const int64_t e0 = (int64_t)tile * kLabelTile + (int64_t)tid * kLabelRun;
     int2 c[kLabelRun];
     load_run(rm, e0, c);
     uint8_t lab[kLabelRun];
@@ -1500,7 +1589,7 @@ __global__ void __launch_bounds__(kBlock) k_write(RmDev rm, uint8_t *labels, int
     int tot;
     const int pre = block_scan(ng, &tot, s_w);
     if (!gray || tot == 0) return;
-    int64_t pos = (int64_t)rm.tile_cnt[blockIdx.x] + pre;
+    int64_t pos = (int64_t)rm.tile_cnt[tile] + pre;
 #pragma unroll
     for (int h = 0; h < kLabelRun; ++h) {
         if (e0 + h < rm.E && lab[h] == RGG_GRAY) {
@@ -1508,6 +1597,127 @@ __global__ void __launch_bounds__(kBlock) k_write(RmDev rm, uint8_t *labels, int
             ++pos;
         }
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_count(RmDev rm, rgg_update_result *res, int force)
+{
+    count_body(rm, res, force, (int)blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kBlock) k_write(RmDev rm, uint8_t *labels, int64_t *gray, int64_t cap,
+                                                  rgg_update_result *res, int force)
+{
+    write_body(rm, labels, gray, cap, res, force, (int)blockIdx.x);
+}
+
+// ------------------------------------------------------------------------
+// batched updates of distinct roadmaps: one launch per stage for all of
+// them; each kernel finds its request in the device table
+// ------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kDiffBlock) k_diff_batch(const BatchReq *tab)
+{
+    const BatchReq &q = tab[blockIdx.x];
+    diff_body(q.rm, q.a.old_b, q.a.new_b);
+}
+
+__global__ void __launch_bounds__(kBlock) k_cells_batch(const BatchReq *tab, int n)
+{
+    for (int r = 0; r < n; ++r)
+        if (tab[r].rm.ncells > 1) cells_body(tab[r].rm);
+}
+
+// copies a request's device view into LDS (all threads; barriers around)
+__device__ inline void load_rm(RmDev *dst, const RmDev &src)
+{
+    __syncthreads();
+    const uint32_t *a = reinterpret_cast<const uint32_t *>(&src);
+    uint32_t *b = reinterpret_cast<uint32_t *>(dst);
+    for (int k = threadIdx.x; k < (int)(sizeof(RmDev) / 4); k += blockDim.x) b[k] = a[k];
+    __syncthreads();
+}
+static_assert(sizeof(RmDev) % 4 == 0, "RmDev is copied as 32-bit words");
+
+// The items of all requests of one group form one range: request r owns
+// [P_r, P_r + n_items_r), and block b takes b, b + gridDim.x, ... of it.
+template <int D, typename T>
+__device__ __forceinline__ void item_batch_body(const BatchReq *tab, const int32_t *grp, int n)
+{
+    __shared__ RmDev s_rm;
+    __shared__ int s_pref[kMaxBatch + 1];
+    __shared__ int s_w[kWaves];
+    const int tid = threadIdx.x;
+    int v = 0;
+    if (tid < n) {
+        const RmDev &rm = tab[grp[tid]].rm;
+        v = rm.ctl->status == RGG_OK ? min(rm.ctl->n_items, (int32_t)rm.items_cap) : 0;
+    }
+    int tot;
+    const int pre = block_scan(v, &tot, s_w);
+    if (tid < n) s_pref[tid] = pre;
+    if (tid == 0) s_pref[n] = tot;
+    __syncthreads();
+    const int G = (int)gridDim.x, b = (int)blockIdx.x;
+    for (int r = 0; r < n; ++r) {
+        const int P = s_pref[r], N = s_pref[r + 1] - P;
+        const int first = P + ((b - P) % G + G) % G;   // first index >= P that is b mod G
+        if (first >= P + N) continue;
+        load_rm(&s_rm, tab[grp[r]].rm);
+        item_body<D, T>(s_rm, 0, first - P, G);
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock, 4) k_item32_batch(const BatchReq *tab, const int32_t *grp, int n)
+{
+    item_batch_body<D, float>(tab, grp, n);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_item64_batch(const BatchReq *tab, const int32_t *grp, int n)
+{
+    item_batch_body<D, double>(tab, grp, n);
+}
+
+// kFp64BatchGrid blocks per request of the group
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_fp64_batch(const BatchReq *tab, const int32_t *grp)
+{
+    __shared__ RmDev s_rm;
+    const int r = (int)blockIdx.x / kFp64BatchGrid, b = (int)blockIdx.x % kFp64BatchGrid;
+    load_rm(&s_rm, tab[grp[r]].rm);
+    fp64_body<D>(s_rm, b, kFp64BatchGrid);
+}
+
+// request owning a tile: the last r with first[r] <= tile (n <= kMaxBatch)
+__device__ inline int owner_of(const BatchReq *tab, int n, int tile, bool write_tiles)
+{
+    __shared__ int s_r;
+    if (threadIdx.x < 64) {
+        int best = -1;
+        for (int r = threadIdx.x; r < n; r += 64) {
+            const int f = write_tiles ? tab[r].wtile0 : tab[r].tile0;
+            if (f <= tile) best = max(best, r);
+        }
+        for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o));
+        if (threadIdx.x == 0) s_r = best;
+    }
+    __syncthreads();
+    return s_r;
+}
+
+__global__ void __launch_bounds__(kBlock) k_count_batch(const BatchReq *tab, int n)
+{
+    const int r = owner_of(tab, n, (int)blockIdx.x, false);
+    const BatchReq &q = tab[r];
+    count_body(q.rm, q.a.res, 0, (int)blockIdx.x - q.tile0);
+}
+
+__global__ void __launch_bounds__(kBlock) k_write_batch(const BatchReq *tab, int n)
+{
+    const int r = owner_of(tab, n, (int)blockIdx.x, true);
+    const BatchReq &q = tab[r];
+    write_body(q.rm, q.a.labels, q.a.gray, q.a.gray_cap, q.a.res, 0, (int)blockIdx.x - q.wtile0);
 }
 
 }  // namespace
@@ -1624,6 +1834,51 @@ hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, 
         if (err != hipSuccess) return err;
         prev = node;
     }
+    *last = prev;
+    return hipSuccess;
+}
+
+hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp, int n,
+                           const BatchGroup *groups, int n_groups, bool any_grid, int n_tiles,
+                           int n_wtiles, hipGraphNode_t dep, hipGraphNode_t *last)
+{
+    hipGraphNode_t prev = dep;
+    auto add = [&](void *fn, dim3 grid, dim3 block, void **args) -> hipError_t {
+        hipKernelNodeParams p = {};
+        p.func = fn;
+        p.gridDim = grid;
+        p.blockDim = block;
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        hipGraphNode_t node;
+        hipError_t err = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &p);
+        if (err == hipSuccess) prev = node;
+        return err;
+    };
+    const BatchReq *t = tab;
+    int nn = n;
+    hipError_t err;
+    void *a_diff[] = {(void *)&t};
+    if ((err = add((void *)k_diff_batch, dim3(n), dim3(kDiffBlock), a_diff)) != hipSuccess) return err;
+    void *a_tn[] = {(void *)&t, (void *)&nn};
+    if (any_grid && (err = add((void *)k_cells_batch, dim3(kCellsGrid), dim3(kBlock), a_tn)) != hipSuccess) return err;
+    for (int k = 0; k < n_groups; ++k) {
+        const BatchGroup &gr = groups[k];
+        const int32_t *gp = grp + gr.off;
+        int cnt = gr.count;
+        void *a_item[] = {(void *)&t, (void *)&gp, (void *)&cnt};
+        void *fn = gr.D == 3 ? (gr.mixed ? (void *)k_item32_batch<3> : (void *)k_item64_batch<3>)
+                             : (gr.mixed ? (void *)k_item32_batch<2> : (void *)k_item64_batch<2>);
+        if ((err = add(fn, dim3(kGrid), dim3(kBlock), a_item)) != hipSuccess) return err;
+        if (gr.mixed) {
+            void *a_fp[] = {(void *)&t, (void *)&gp};
+            void *f64 = gr.D == 3 ? (void *)k_fp64_batch<3> : (void *)k_fp64_batch<2>;
+            if ((err = add(f64, dim3(kFp64BatchGrid * cnt), dim3(kBlock), a_fp)) != hipSuccess) return err;
+        }
+    }
+    if ((err = add((void *)k_count_batch, dim3(n_tiles), dim3(kBlock), a_tn)) != hipSuccess) return err;
+    if ((err = add((void *)k_write_batch, dim3(n_wtiles), dim3(kBlock), a_tn)) != hipSuccess) return err;
     *last = prev;
     return hipSuccess;
 }

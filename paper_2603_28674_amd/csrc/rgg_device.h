@@ -75,7 +75,7 @@ struct RmDev {
                                // binary64 pass (its re-test region was full)
     int32_t *df_cnt;           // [kStatBlocks]
     int32_t *tile_cnt;         // [ntiles + 1] gray edges per label tile, then their offsets
-    unsigned long long *blk_stats;   // [kStatBlocks][kStats] per-block partial counts
+    unsigned long long *blk_stats;   // [kStats][kStatBlocks] per-block partial counts
     Ctl *ctl;
 };
 
@@ -97,6 +97,28 @@ struct UpdateArgs {
     int64_t gray_cap;
     rgg_update_result *res;
 };
+
+// One request of a batched update: the roadmap's device view, the update's
+// arguments, and the request's first label tile in the batch's tile range.
+struct BatchReq {
+    RmDev rm;
+    UpdateArgs a;
+    int32_t tile0;             // first count tile (ntiles per request)
+    int32_t wtile0;            // first write tile (ntiles + 1 per request)
+};
+
+constexpr int kMaxBatch = 256;     // requests per batched launch
+
+// The kernels of a batched update of distinct roadmaps, appended to `g` as a
+// chain after `dep` (may be null); *last receives the final node.  `tab` is
+// the device table of the n requests (groups of one kernel variant listed in
+// `grp`, sorted), `n_tiles`/`n_wtiles` the totals of the tile ranges.
+struct BatchGroup {
+    int32_t D, mixed, off, count;  // requests grp[off .. off + count)
+};
+hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp, int n,
+                           const BatchGroup *groups, int n_groups, bool any_grid, int n_tiles,
+                           int n_wtiles, hipGraphNode_t dep, hipGraphNode_t *last);
 
 // Queues the kernels of one update on `s`.  When `ev` is non-null, ev[0..6]
 // are recorded before, between and after the stages (diff, cells, grid scan,

@@ -93,7 +93,8 @@ RESULT_BYTES = C.sizeof(rgg_update_result)
 #: every symbol include/rgg.h declares
 EXPORTS = ["rgg_context_create", "rgg_context_destroy", "rgg_build", "rgg_destroy",
            "rgg_roadmap_info_get", "rgg_update", "rgg_update_async", "rgg_graph_create",
-           "rgg_graph_launch", "rgg_graph_destroy", "rgg_labels", "rgg_gray_list",
+           "rgg_graph_launch", "rgg_graph_destroy", "rgg_batch_create", "rgg_batch_launch",
+           "rgg_batch_destroy", "rgg_update_batch", "rgg_labels", "rgg_gray_list",
            "rgg_timing_enable", "rgg_timing_read", "rgg_debug_geometry", "rgg_last_error",
            "rgg_version"]
 
@@ -120,6 +121,10 @@ def lib():
         "rgg_graph_create": (I32, [P, I32, P, C.POINTER(P)]),
         "rgg_graph_launch": (I32, [P, P]),
         "rgg_graph_destroy": (I32, [P]),
+        "rgg_batch_create": (I32, [P, I32, P, C.POINTER(P)]),
+        "rgg_batch_launch": (I32, [P, P, P]),
+        "rgg_batch_destroy": (I32, [P]),
+        "rgg_update_batch": (I32, [P, I32, P, P]),
         "rgg_labels": (I32, [P, P]),
         "rgg_gray_list": (I32, [P, P, I64, P]),
         "rgg_timing_enable": (I32, [P, I32]),
@@ -298,6 +303,28 @@ def rgg_graph_launch(g, stream):
 
 def rgg_graph_destroy(g):
     _check(lib().rgg_graph_destroy(g))
+
+
+def rgg_batch_create(ctx, roadmaps):
+    """roadmaps: handles (rgg_roadmap pointers) of distinct roadmaps."""
+    arr = (C.c_void_p * len(roadmaps))(*[C.c_void_p(getattr(r, "value", r)) for r in roadmaps])
+    h = C.c_void_p()
+    _check(lib().rgg_batch_create(ctx, len(roadmaps), arr, C.byref(h)))
+    return h
+
+
+def rgg_batch_launch(b, reqs, stream):
+    arr = (rgg_update_req * len(reqs))(*reqs)
+    _check(lib().rgg_batch_launch(b, arr, C.c_void_p(stream)))
+
+
+def rgg_batch_destroy(b):
+    _check(lib().rgg_batch_destroy(b))
+
+
+def rgg_update_batch(ctx, reqs, stream):
+    arr = (rgg_update_req * len(reqs))(*reqs)
+    _check(lib().rgg_update_batch(ctx, len(reqs), arr, C.c_void_p(stream)))
 
 
 def rgg_timing_enable(rm, on=True):

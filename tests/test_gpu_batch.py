@@ -1,0 +1,114 @@
+"""GPU parity of batched updates: every roadmap of a batch gets exactly the
+labels and gray list of the FP64 oracle, after every batched update.
+
+A batch mixes robot kinds (planar rigid, spatial rigid, planar arm), both
+precisions, one-cell and grid roadmaps, and roadmaps of very different sizes,
+as the batched configuration of many planar roadmaps does."""
+import numpy as np
+import pytest
+
+from paper_2603_28674_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2603_28674_amd import rgg
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = rgg.rgg_context_create(0)
+    yield c
+    rgg.rgg_context_destroy(c)
+
+
+def mixed_workloads(n_updates):
+    from paper_2603_28674_amd import rgg
+    fp32, fp64 = rgg.RGG_PREC_FP32_RECHECK, rgg.RGG_PREC_FP64
+    specs = [
+        (synth.planar_rigid(seed=51, n_nodes=1500, n_boxes=40, n_updates=n_updates), fp32, -1.0),
+        (synth.spatial_rigid(seed=52, n_nodes=2500, n_boxes=100, n_updates=n_updates, world=4.0), fp32, -1.0),
+        (synth.planar_arm(seed=53, n_nodes=2000, n_boxes=40, n_updates=n_updates), fp32, 0.0),
+        (synth.planar_rigid(seed=54, n_nodes=300, n_boxes=20, n_updates=n_updates), fp64, -1.0),
+        (synth.spatial_rigid(seed=55, n_nodes=1200, n_boxes=60, n_updates=n_updates, world=3.0), fp32, 0.0),
+        (synth.planar_rigid(seed=56, n_nodes=80, n_boxes=5, n_updates=n_updates), fp32, -1.0),
+    ]
+    return specs
+
+
+def run_batched(ctx, specs, n_updates, one_shot=False):
+    import torch
+    from paper_2603_28674_amd import rgg
+    import oracle
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    gs, ors, bufs = [], [], []
+    for w, prec, cell in specs:
+        print(f"[batch] {w.name} E={w.n_edges} M={w.n_slots} prec={prec} cell={cell}", flush=True)
+        gs.append(rgg.Roadmap.from_workload(ctx, w, precision=prec, cell_size=cell))
+        ors.append(oracle.from_workload(w))
+        states = torch.from_numpy(np.stack([w.absent()] + w.boxes)).to(dev)
+        lab = torch.zeros(w.n_edges, dtype=torch.uint8, device=dev)
+        gray = torch.zeros(max(w.n_edges, 1), dtype=torch.int64, device=dev)
+        res = torch.zeros(rgg.RESULT_BYTES, dtype=torch.uint8, device=dev)
+        bufs.append((states, lab, gray, res))
+    batch = None if one_shot else rgg.rgg_batch_create(ctx, [g.h for g in gs])
+    for u in range(n_updates):
+        reqs = []
+        for (w, _, _), g, (states, lab, gray, res) in zip(specs, gs, bufs):
+            reqs.append(rgg.rgg_update_req(g.h.value, w.n_slots, states[u].data_ptr(), states[u + 1].data_ptr(),
+                                           lab.data_ptr(), gray.data_ptr(), w.n_edges, res.data_ptr()))
+        if one_shot:
+            rgg.rgg_update_batch(ctx, reqs, stream)
+        else:
+            rgg.rgg_batch_launch(batch, reqs, stream)
+        torch.cuda.synchronize()
+        for k, ((w, _, _), o, (states, lab, gray, res)) in enumerate(zip(specs, ors, bufs)):
+            prev = w.absent() if u == 0 else w.boxes[u - 1]
+            ol, og = o.update(prev, w.boxes[u])
+            r = rgg.result_from_tensor(res)
+            assert r.status == 0, f"roadmap {k} update {u}: status {r.status}"
+            assert r.n_gray == len(og), f"roadmap {k} update {u}: n_gray {r.n_gray} vs {len(og)}"
+            gl = lab.cpu().numpy()
+            bad = np.nonzero(gl != ol)[0]
+            assert bad.size == 0, f"roadmap {k} update {u}: {bad.size} labels differ"
+            assert np.array_equal(gray[: r.n_gray].cpu().numpy(), og), f"roadmap {k} update {u}: gray list"
+    if batch is not None:
+        rgg.rgg_batch_destroy(batch)
+    for g in gs:
+        g.close()
+
+
+def test_batch_mixed_parity(ctx):
+    run_batched(ctx, mixed_workloads(4), 4)
+
+
+def test_update_batch_one_shot(ctx):
+    run_batched(ctx, mixed_workloads(2)[:3], 2, one_shot=True)
+
+
+def test_batch_many_planar(ctx):
+    """Twenty planar roadmaps of 60..3000 nodes in one batch."""
+    from paper_2603_28674_amd import rgg
+    rng = np.random.default_rng(57)
+    specs = []
+    for k in range(20):
+        n = int(round(np.exp(rng.uniform(np.log(60), np.log(3000)))))
+        specs.append((synth.planar_rigid(seed=600 + k, n_nodes=n, n_boxes=int(rng.integers(5, 40)), n_updates=3),
+                      rgg.RGG_PREC_FP32_RECHECK, -1.0))
+    run_batched(ctx, specs, 3)
+
+
+def test_batch_errors(ctx):
+    from paper_2603_28674_amd import rgg
+    w = synth.planar_rigid(seed=58, n_nodes=200, n_boxes=5, n_updates=1)
+    print("[batch errors]", flush=True)
+    g = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK)
+    with pytest.raises(rgg.RggError):
+        rgg.rgg_batch_create(ctx, [g.h, g.h])   # a roadmap twice
+    b = rgg.rgg_batch_create(ctx, [g.h])
+    with pytest.raises(rgg.RggError):
+        # m does not match the roadmap
+        rgg.rgg_batch_launch(b, [rgg.rgg_update_req(g.h.value, w.n_slots + 1, 1, 1, 0, 0, 0, 1)], 0)
+    rgg.rgg_batch_destroy(b)
+    g.close()
