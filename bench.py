@@ -43,6 +43,10 @@ def parse():
     p.add_argument("--cpu-sample-edges", type=int, default=30000)
     p.add_argument("--skip-graph", action="store_true")
     p.add_argument("--seed", type=int, default=2)
+    p.add_argument("--no-batched", action="store_true",
+                   help="skip the batched-planar measurement (64 roadmaps)")
+    p.add_argument("--batched-steps", type=int, default=20)
+    p.add_argument("--batched-cell-size", type=float, default=0.0)
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 1 GiB device copy 5 times (reference kernel for "
                         "scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -69,6 +73,102 @@ def measured_traffic(kernel):
                 if rec["kernel"] == kernel and rec["source_sha256"] == sha:
                     return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
     return None
+
+
+def batched_planar(a):
+    """The batched configuration: 64 independent planar rigid-body roadmaps
+    (node counts log-uniform in [1e3, 1e5], k = 8, U{20..400} boxes each,
+    each update moving U{1..20} of them), FP32 tests + FP64 re-test.  One
+    update round updates every roadmap once.  Plain: 64 rgg_update_async
+    calls per round on one stream.  Batched: one rgg_batch_launch per round
+    (one graph, one kernel launch per stage for all 64 roadmaps).  Every
+    round's edges/s counts all edges of all roadmaps."""
+    import torch
+    from paper_2603_28674_amd import rgg, synth
+    K, W = a.batched_steps, 2
+    n_rounds = W + 3 * K
+    t0 = time.perf_counter()
+    ws = synth.batch_of_planar(seed=3, n_updates=n_rounds)
+    log(f"[bench] batched: generated {len(ws)} roadmaps, {sum(w.n_edges for w in ws)} edges "
+        f"in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    ctx = rgg.rgg_context_create(0)
+    t0 = time.perf_counter()
+    gs = [rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK,
+                                    cell_size=a.batched_cell_size) for w in ws]
+    log(f"[bench] batched: built in {time.perf_counter() - t0:.1f}s")
+    E_tot = sum(w.n_edges for w in ws)
+    bufs = []
+    for w in ws:
+        states = torch.from_numpy(np.stack([w.absent()] + w.boxes)).to(dev)
+        bufs.append((states, torch.zeros(w.n_edges, dtype=torch.uint8, device=dev),
+                     torch.zeros(w.n_edges, dtype=torch.int64, device=dev),
+                     torch.zeros(rgg.RESULT_BYTES, dtype=torch.uint8, device=dev)))
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def reqs(u):
+        return [rgg.rgg_update_req(g.h.value, w.n_slots, st[u].data_ptr(), st[u + 1].data_ptr(),
+                                   lab.data_ptr(), gr.data_ptr(), w.n_edges, res.data_ptr())
+                for w, g, (st, lab, gr, res) in zip(ws, gs, bufs)]
+
+    def plain(u):
+        for q in reqs(u):
+            rgg.lib().rgg_update_async(C_void(q.rm), C_void(stream), q.m, C_void(q.d_old), C_void(q.d_new),
+                                       C_void(q.d_labels), C_void(q.d_gray), q.gray_cap, C_void(q.d_result))
+
+    batch = rgg.rgg_batch_create(ctx, [g.h for g in gs])
+    rq = [reqs(u) for u in range(n_rounds)]
+
+    def batched(u):
+        rgg.rgg_batch_launch(batch, rq[u], stream)
+
+    u = 0
+    for _ in range(W):
+        batched(u)
+        u += 1
+    torch.cuda.synchronize()
+    out = {}
+    for name, fn in (("plain", plain), ("batched", batched)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        host = 0.0
+        for _ in range(K):
+            h0 = time.perf_counter()
+            fn(u)
+            host += time.perf_counter() - h0
+            u += 1
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[name] = {"edges_per_s": E_tot * K / wall, "ms_per_round": wall / K * 1e3,
+                     "host_ms_per_round": host / K * 1e3}
+    lat = []
+    for _ in range(K):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        batched(u)
+        u += 1
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e6)
+    ok = all(rgg.result_from_tensor(b[3]).status == 0 for b in bufs)
+    rgg.rgg_batch_destroy(batch)
+    for g in gs:
+        g.close()
+    rgg.rgg_context_destroy(ctx)
+    return {
+        "workload": "64 planar rigid-body roadmaps (4 disks; nodes log-uniform in [1e3, 1e5], k=8, "
+                    "U{20..400} boxes, each update moves U{1..20}), FP32 + FP64 re-test",
+        "roadmaps": len(ws), "edges": E_tot, "rounds": K, "cell_size": a.batched_cell_size,
+        "plain": out["plain"], "batched": out["batched"],
+        "speedup_batched_vs_plain": out["batched"]["edges_per_s"] / out["plain"]["edges_per_s"],
+        "batched_round_latency_p50_us": float(np.percentile(lat, 50)),
+        "batched_round_latency_p99_us": float(np.percentile(lat, 99)),
+        "status_ok": ok,
+    }
+
+
+def C_void(x):
+    import ctypes
+    return ctypes.c_void_p(x)
 
 
 def cpu_baseline(w, gpu_labels_final, sample_edges, n_updates, seed):
@@ -240,6 +340,9 @@ def main():
         log("[bench] cpu baseline (oracle on a sample)")
         line["cpu_baseline"] = cpu_baseline(w, final_labels, a.cpu_sample_edges, last, a.seed)
     g.close()
+    if not a.no_batched:
+        log("[bench] batched planar roadmaps")
+        line["batched_planar"] = batched_planar(a)
     if a.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)

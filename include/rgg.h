@@ -242,7 +242,9 @@ rgg_status rgg_graph_destroy(rgg_graph *g);
  * Errors: RGG_E_INVALID_ARG (null pointer, n out of range, a repeated
  * roadmap, another device, a request that does not match its roadmap),
  * RGG_E_DEVICE.  Device-side errors (bad box, state mismatch) are reported
- * per request in its d_result, as for rgg_update_async. */
+ * per request in its d_result, as for rgg_update_async.  A batch must be
+ * destroyed before any of its roadmaps; rgg_batch_destroy waits for its
+ * launches to finish. */
 rgg_status rgg_batch_create(rgg_context *ctx, int32_t n, rgg_roadmap *const *rms, rgg_batch **out);
 rgg_status rgg_batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *stream);
 rgg_status rgg_batch_destroy(rgg_batch *b);

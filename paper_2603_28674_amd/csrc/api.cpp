@@ -70,9 +70,10 @@ struct rgg_roadmap {
     rgg_roadmap_info info = {};
     std::vector<void *> allocs;
     hipStream_t stream = nullptr;     // for host-buffer calls
-    hipEvent_t done = nullptr;        // end of the most recent update
+    hipEvent_t done = nullptr;        // end of the most recent single update
+    hipEvent_t wait_ev = nullptr;     // event marking the end of the most recent update
+                                      // (done, or a batch's event); null = none pending
     hipStream_t last_stream = nullptr;
-    bool any_update = false;
     // staging for host-buffer updates
     rgg_box *h_stage = nullptr;       // pinned [2M]
     rgg_box *d_stage = nullptr;       // [2M]
@@ -89,6 +90,7 @@ struct rgg_roadmap {
     ~rgg_roadmap()
     {
         if (device >= 0) hipSetDevice(device);
+        if (wait_ev) hipEventSynchronize(wait_ev);   // the last update, on any stream
         if (stream) hipStreamSynchronize(stream);
         for (auto &set : pool)
             for (auto ev : set) hipEventDestroy(ev);
@@ -143,7 +145,7 @@ struct rgg_batch {
     BatchReq *d_tab = nullptr;        // [n] rows, grouped by kernel variant
     int32_t *d_grp = nullptr;         // [n] row indices, grouped
     BatchReq *h_tab[kRing] = {};      // pinned
-    hipEvent_t copied[kRing] = {};
+    hipEvent_t done[kRing] = {};      // end of the launch that used the slot
     bool used[kRing] = {};
     int ring = 0;
     hipGraph_t graph = nullptr;
@@ -152,11 +154,14 @@ struct rgg_batch {
     ~rgg_batch()
     {
         hipSetDevice(device);
+        for (int k = 0; k < kRing; ++k)
+            if (done[k] && used[k]) hipEventSynchronize(done[k]);
+        // the roadmaps' last updates have completed: nothing left to wait for
+        for (rgg_roadmap *rm : rms)
+            for (int k = 0; k < kRing; ++k)
+                if (rm->wait_ev == done[k]) rm->wait_ev = nullptr;
         for (int k = 0; k < kRing; ++k) {
-            if (copied[k]) {
-                if (used[k]) hipEventSynchronize(copied[k]);
-                hipEventDestroy(copied[k]);
-            }
+            if (done[k]) hipEventDestroy(done[k]);
             if (h_tab[k]) hipHostFree(h_tab[k]);
         }
         if (exec) hipGraphExecDestroy(exec);
@@ -364,16 +369,16 @@ namespace {
 // Orders this update after the roadmap's previous one when the streams differ.
 rgg_status order_after_previous(rgg_roadmap *rm, hipStream_t s)
 {
-    if (rm->any_update && rm->last_stream != s)
-        HIP_OR_FAIL(hipStreamWaitEvent(s, rm->done, 0), "hipStreamWaitEvent");
+    if (rm->wait_ev && rm->last_stream != s)
+        HIP_OR_FAIL(hipStreamWaitEvent(s, rm->wait_ev, 0), "hipStreamWaitEvent");
     return RGG_OK;
 }
 
 rgg_status finish_update(rgg_roadmap *rm, hipStream_t s)
 {
     HIP_OR_FAIL(hipEventRecord(rm->done, s), "hipEventRecord");
+    rm->wait_ev = rm->done;
     rm->last_stream = s;
-    rm->any_update = true;
     return RGG_OK;
 }
 
@@ -634,7 +639,7 @@ rgg_status rgg_batch_create(rgg_context *ctx, int32_t n, rgg_roadmap *const *rms
     HIP_OR_FAIL(hipMemcpy(b->d_grp, grp.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice), "batch groups");
     for (int k = 0; k < rgg_batch::kRing; ++k) {
         HIP_OR_FAIL(hipHostMalloc((void **)&b->h_tab[k], sizeof(BatchReq) * n, hipHostMallocDefault), "pinned table");
-        HIP_OR_FAIL(hipEventCreateWithFlags(&b->copied[k], hipEventDisableTiming), "hipEventCreate");
+        HIP_OR_FAIL(hipEventCreateWithFlags(&b->done[k], hipEventDisableTiming), "hipEventCreate");
     }
     HIP_OR_FAIL(hipGraphCreate(&b->graph, 0), "hipGraphCreate");
     hipGraphNode_t last = nullptr;
@@ -660,7 +665,7 @@ rgg_status rgg_batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *stre
     // a free host table: its previous copy has completed
     const int slot = b->ring;
     b->ring = (b->ring + 1) % rgg_batch::kRing;
-    if (b->used[slot]) HIP_OR_FAIL(hipEventSynchronize(b->copied[slot]), "hipEventSynchronize");
+    if (b->used[slot]) HIP_OR_FAIL(hipEventSynchronize(b->done[slot]), "hipEventSynchronize");
     BatchReq *h = b->h_tab[slot];
     int tile = 0, wtile = 0;
     for (int row = 0; row < b->n; ++row) {
@@ -678,12 +683,12 @@ rgg_status rgg_batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *stre
         if (st != RGG_OK) return st;
     }
     HIP_OR_FAIL(hipMemcpyAsync(b->d_tab, h, sizeof(BatchReq) * b->n, hipMemcpyHostToDevice, s), "copy batch table");
-    HIP_OR_FAIL(hipEventRecord(b->copied[slot], s), "hipEventRecord");
-    b->used[slot] = true;
     HIP_OR_FAIL(hipGraphLaunch(b->exec, s), "hipGraphLaunch");
-    for (rgg_roadmap *rm : b->rms) {
-        rgg_status st = finish_update(rm, s);
-        if (st != RGG_OK) return st;
+    HIP_OR_FAIL(hipEventRecord(b->done[slot], s), "hipEventRecord");
+    b->used[slot] = true;
+    for (rgg_roadmap *rm : b->rms) {   // one event stands for every roadmap's update
+        rm->wait_ev = b->done[slot];
+        rm->last_stream = s;
     }
     return RGG_OK;
 }

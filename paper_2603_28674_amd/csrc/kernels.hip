@@ -35,6 +35,7 @@ constexpr int kDiffBlock = 1024;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kCellsGrid = 128;
+constexpr int kCellsBatchGrid = 16;   // blocks per roadmap of the batched cell activation
 constexpr int kGrid = kStatBlocks; // blocks of the item kernels
 constexpr int kFp64Grid = 256;     // blocks of the binary64 pass of the FP32 mode
 constexpr int kFp64BatchGrid = 32; // blocks per roadmap of the batched binary64 pass
@@ -51,6 +52,12 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline unsigned long long wave_sum_u64(unsigned long long v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
 }
 
 __device__ inline int wave_prefix(int v, int *total)
@@ -386,6 +393,7 @@ __device__ __forceinline__ void diff_body(const RmDev &rm, const rgg_box *__rest
         s_base = 0;
         s_any = 0;
         rm.ctl->n_items = 0;
+        rm.ctl->any_df = 0;
     }
     __syncthreads();
     bool dirty0 = false;   // the first chunk's slot changes (kept for the commit)
@@ -456,14 +464,15 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff(RmDev rm, const rgg_box *__
 // k_cells: touched cells -> work items (cell, chunk)
 // ------------------------------------------------------------------------
 
-__device__ __forceinline__ void cells_body(const RmDev &rm)
+// block b of G blocks working on this roadmap
+__device__ __forceinline__ void cells_body(const RmDev &rm, int b, int G)
 {
     const Ctl *ctl = rm.ctl;
     if (ctl->status != RGG_OK) return;
     const int n_chg = ctl->n_chg;
     const int lane = lane_id();
-    const int nw = gridDim.x * kWaves;
-    for (int q = blockIdx.x * kWaves + (threadIdx.x >> 6); q < n_chg; q += nw) {
+    const int nw = G * kWaves;
+    for (int q = b * kWaves + (threadIdx.x >> 6); q < n_chg; q += nw) {
         const ChgEntry &en = rm.chg[q];
         const int32_t nx = en.c1[0] - en.c0[0] + 1, ny = en.c1[1] - en.c0[1] + 1,
                       nz = en.c1[2] - en.c0[2] + 1;
@@ -507,7 +516,7 @@ __device__ __forceinline__ void cells_body(const RmDev &rm)
 
 __global__ void __launch_bounds__(kBlock) k_cells(RmDev rm)
 {
-    cells_body(rm);
+    cells_body(rm, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // ------------------------------------------------------------------------
@@ -1290,11 +1299,16 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
     }
     __syncthreads();
     // the binary64 pass counts its pairs as re-tested
+    // per-lane counts are summed over the wavefront first: LDS atomics on
+    // one address from every lane are slow
+    const unsigned long long w_outer = wave_sum_u64(n_outer), w_bytes = wave_sum_u64(bytes);
     if (tid == 0 && n_pairs) atomicAdd(&L.acc[deferred ? 2 : 0], (unsigned long long)n_pairs);
-    if (n_outer) atomicAdd(&L.acc[1], (unsigned long long)n_outer);
-    if (bytes) atomicAdd(&L.acc[3], bytes);
-    if (lane == 0 && visited) atomicAdd(&L.acc[4], (unsigned long long)visited);
-    if (lane == 0 && cand) atomicAdd(&L.acc[5], (unsigned long long)cand);
+    if (lane == 0) {
+        if (w_outer) atomicAdd(&L.acc[1], w_outer);
+        if (w_bytes) atomicAdd(&L.acc[3], w_bytes);
+        if (visited) atomicAdd(&L.acc[4], (unsigned long long)visited);
+        if (cand) atomicAdd(&L.acc[5], (unsigned long long)cand);
+    }
     __syncthreads();
     // statistic k at bs[k * kStatBlocks]
     unsigned long long *bs = rm.blk_stats + (deferred ? li0 : (int)blockIdx.x);
@@ -1303,6 +1317,7 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
         if (kF32 && tid == 0) {
             rm.rc_cnt[blockIdx.x] = L.rc_n;
             rm.df_cnt[blockIdx.x] = L.df_n;
+            if (L.df_n) rm.ctl->any_df = 1;
         }
     } else if (tid == 0 && (L.acc[1] | L.acc[2] | L.acc[3])) {
         bs[1 * kStatBlocks] += L.acc[1];
@@ -1409,19 +1424,20 @@ __device__ __forceinline__ void retest_pairs(const RmDev &rm, int b, int G)
 
 // The binary64 pass of the FP32 mode: queued pairs, then the items left
 // whole (their blocks' re-test regions were full).
-// regions b, b + G, ... of one roadmap
+// Regions b, b + G, ... of one roadmap.  The items left whole are rare (a
+// block's re-test region overflowed): their kernel exits at once unless one
+// was deferred in this update.
 template <int D>
-__device__ __forceinline__ void fp64_body(const RmDev &rm, int b, int G)
+__global__ void __launch_bounds__(kBlock) k_retest(RmDev rm)
 {
-    retest_pairs<D>(rm, b, G);
-    __syncthreads();
-    item_body<D, double>(rm, 1, b, G);
+    retest_pairs<D>(rm, (int)blockIdx.x, (int)gridDim.x);
 }
 
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_fp64(RmDev rm)
+__global__ void __launch_bounds__(kBlock) k_deferred(RmDev rm)
 {
-    fp64_body<D>(rm, (int)blockIdx.x, (int)gridDim.x);
+    if (!rm.ctl->any_df) return;
+    item_body<D, double>(rm, 1, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // ------------------------------------------------------------------------
@@ -1465,13 +1481,10 @@ __device__ inline void load_run(const RmDev &rm, int64_t e0, int2 (&c)[kLabelRun
     }
 }
 
-// k_count: gray edges per tile; the last block to finish turns the counts
-// into exclusive tile offsets (tile_cnt[t] becomes the first gray position of
-// tile t, tile_cnt[ntiles] the total) and reports the status and n_gray.
-__device__ __forceinline__ void count_body(const RmDev &rm, rgg_update_result *res, int force, int tile)
+// k_count: gray edges per tile
+__device__ __forceinline__ void count_body(const RmDev &rm, int tile)
 {
     __shared__ int s_w[kWaves];
-    __shared__ int s_last;
     const int tid = threadIdx.x;
     const int64_t e0 = (int64_t)tile * kLabelTile + (int64_t)tid * kLabelRun;
     int2 c[kLabelRun];
@@ -1480,55 +1493,22 @@ __device__ __forceinline__ void count_body(const RmDev &rm, rgg_update_result *r
 #pragma unroll
     for (int h = 0; h < kLabelRun; ++h) ng += (e0 + h < rm.E && label_of(c[h]) == RGG_GRAY) ? 1 : 0;
     const int tot = block_sum(ng, s_w);
-    if (tid == 0) {
-        rm.tile_cnt[tile] = tot;
-        const int done = __hip_atomic_fetch_add(&rm.ctl->tiles_done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = done == rm.ntiles - 1;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    // last block: exclusive scan of the tile counts, in place (each thread
-    // rewrites only its own run of tiles)
-    const int nt = rm.ntiles;
-    const int per = (nt + kBlock - 1) / kBlock;
-    const int t0 = tid * per, t1 = min(nt, t0 + per);
-    int sum = 0;
-    for (int t = t0; t < t1; ++t) sum += __hip_atomic_load(&rm.tile_cnt[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int total;
-    int run = block_scan(sum, &total, s_w);
-    for (int t = t0; t < t1; ++t) {
-        const int v = __hip_atomic_load(&rm.tile_cnt[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        rm.tile_cnt[t] = run;
-        run += v;
-    }
-    if (tid == 0) {
-        rm.tile_cnt[nt] = total;
-        rm.ctl->tiles_done = 0;   // ready for the next launch
-        if (res) {
-            const int status = force ? RGG_OK : rm.ctl->status;
-            res->n_gray = status == RGG_OK ? total : 0;
-            if (!force) {
-                res->status = status;
-                res->n_changed = rm.ctl->n_chg;
-            }
-        }
-    }
+    if (tid == 0) rm.tile_cnt[tile] = tot;
 }
 
-// k_write: labels and the ordered gray list, one tile per block; block
+// k_write: labels and the ordered gray list, one tile per block (its first
+// position is the sum of the earlier tiles' counts; the last tile reports
+// n_gray, tile 0 the status); block
 // `ntiles` instead folds the per-block statistics of the update.
 // tile == ntiles: fold (and clear) the per-block statistics instead
 __device__ __forceinline__ void write_body(const RmDev &rm, uint8_t *labels, int64_t *gray, int64_t cap,
                                           rgg_update_result *res, int force, int tile)
 {
     __shared__ int s_w[kWaves];
-    __shared__ unsigned long long s_st[kStats];
+    __shared__ unsigned long long s_part[kWaves][kStats];
     const int tid = threadIdx.x;
     if (tile == rm.ntiles) {
         if (force || !res) return;
-        if (tid < kStats) s_st[tid] = 0;
-        __syncthreads();
         // all of this thread's loads are issued before the first add
         constexpr int kRows = kStatBlocks / kBlock;
         unsigned long long v[kRows][kStats];
@@ -1542,29 +1522,39 @@ __device__ __forceinline__ void write_body(const RmDev &rm, uint8_t *labels, int
         for (int h = 0; h < kRows; ++h)
 #pragma unroll
             for (int k = 0; k < kStats; ++k) rm.blk_stats[k * kStatBlocks + h * kBlock + tid] = 0ull;
+        const int lane = lane_id(), wv = tid >> 6;
 #pragma unroll
         for (int k = 0; k < kStats; ++k) {
             unsigned long long a = 0;
 #pragma unroll
             for (int h = 0; h < kRows; ++h) a += v[h][k];
-            if (a) atomicAdd(&s_st[k], a);
+            a = wave_sum_u64(a);
+            if (lane == 0) s_part[wv][k] = a;
         }
         __syncthreads();
-        if (tid == 0) {
-            res->n_pairs = (int64_t)s_st[0];
-            res->n_outer_hits = (int64_t)s_st[1];
-            res->n_rechecked = (int64_t)s_st[2];
-            res->test_bytes = (int64_t)s_st[3];
-            res->n_cells_visited = (int64_t)s_st[4];
-            res->n_candidate_edges = (int64_t)s_st[5];
+        if (tid < kStats) {
+            unsigned long long a = 0;
+            for (int w = 0; w < kWaves; ++w) a += s_part[w][tid];
+            int64_t *dst = tid == 0 ? &res->n_pairs : tid == 1 ? &res->n_outer_hits : tid == 2 ? &res->n_rechecked
+                         : tid == 3 ? &res->test_bytes : tid == 4 ? &res->n_cells_visited : &res->n_candidate_edges;
+            *dst = (int64_t)a;
         }
         return;
     }
     const int status = force ? RGG_OK : rm.ctl->status;
+    if (tid == 0 && tile == 0 && res && !force) {
+        res->status = status;
+        res->n_changed = rm.ctl->n_chg;
+        if (status != RGG_OK) res->n_gray = 0;
+    }
     if (status != RGG_OK) return;
     const int64_t e0 = (int64_t)tile * kLabelTile + (int64_t)tid * kLabelRun;
     int2 c[kLabelRun];
     load_run(rm, e0, c);
+    // gray edges before this tile
+    int before = 0;
+    for (int t = tid; t < tile; t += kBlock) before += rm.tile_cnt[t];
+    before = block_sum(before, s_w);
     uint8_t lab[kLabelRun];
     int ng = 0;
 #pragma unroll
@@ -1588,8 +1578,9 @@ __device__ __forceinline__ void write_body(const RmDev &rm, uint8_t *labels, int
     }
     int tot;
     const int pre = block_scan(ng, &tot, s_w);
+    if (tid == 0 && tile == rm.ntiles - 1 && res) res->n_gray = (int64_t)before + tot;
     if (!gray || tot == 0) return;
-    int64_t pos = (int64_t)rm.tile_cnt[tile] + pre;
+    int64_t pos = (int64_t)before + pre;
 #pragma unroll
     for (int h = 0; h < kLabelRun; ++h) {
         if (e0 + h < rm.E && lab[h] == RGG_GRAY) {
@@ -1599,9 +1590,9 @@ __device__ __forceinline__ void write_body(const RmDev &rm, uint8_t *labels, int
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_count(RmDev rm, rgg_update_result *res, int force)
+__global__ void __launch_bounds__(kBlock) k_count(RmDev rm)
 {
-    count_body(rm, res, force, (int)blockIdx.x);
+    count_body(rm, (int)blockIdx.x);
 }
 
 __global__ void __launch_bounds__(kBlock) k_write(RmDev rm, uint8_t *labels, int64_t *gray, int64_t cap,
@@ -1621,10 +1612,11 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff_batch(const BatchReq *tab)
     diff_body(q.rm, q.a.old_b, q.a.new_b);
 }
 
-__global__ void __launch_bounds__(kBlock) k_cells_batch(const BatchReq *tab, int n)
+// kCellsBatchGrid blocks per request
+__global__ void __launch_bounds__(kBlock) k_cells_batch(const BatchReq *tab)
 {
-    for (int r = 0; r < n; ++r)
-        if (tab[r].rm.ncells > 1) cells_body(tab[r].rm);
+    const BatchReq &q = tab[blockIdx.x / kCellsBatchGrid];
+    if (q.rm.ncells > 1) cells_body(q.rm, (int)(blockIdx.x % kCellsBatchGrid), kCellsBatchGrid);
 }
 
 // copies a request's device view into LDS (all threads; barriers around)
@@ -1681,12 +1673,20 @@ __global__ void __launch_bounds__(kBlock) k_item64_batch(const BatchReq *tab, co
 
 // kFp64BatchGrid blocks per request of the group
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_fp64_batch(const BatchReq *tab, const int32_t *grp)
+__global__ void __launch_bounds__(kBlock) k_retest_batch(const BatchReq *tab, const int32_t *grp)
+{
+    const int r = (int)blockIdx.x / kFp64BatchGrid, b = (int)blockIdx.x % kFp64BatchGrid;
+    retest_pairs<D>(tab[grp[r]].rm, b, kFp64BatchGrid);
+}
+
+template <int D>
+__global__ void __launch_bounds__(kBlock) k_deferred_batch(const BatchReq *tab, const int32_t *grp)
 {
     __shared__ RmDev s_rm;
     const int r = (int)blockIdx.x / kFp64BatchGrid, b = (int)blockIdx.x % kFp64BatchGrid;
+    if (!tab[grp[r]].rm.ctl->any_df) return;
     load_rm(&s_rm, tab[grp[r]].rm);
-    fp64_body<D>(s_rm, b, kFp64BatchGrid);
+    item_body<D, double>(s_rm, 1, b, kFp64BatchGrid);
 }
 
 // request owning a tile: the last r with first[r] <= tile (n <= kMaxBatch)
@@ -1710,7 +1710,7 @@ __global__ void __launch_bounds__(kBlock) k_count_batch(const BatchReq *tab, int
 {
     const int r = owner_of(tab, n, (int)blockIdx.x, false);
     const BatchReq &q = tab[r];
-    count_body(q.rm, q.a.res, 0, (int)blockIdx.x - q.tile0);
+    count_body(q.rm, (int)blockIdx.x - q.tile0);
 }
 
 __global__ void __launch_bounds__(kBlock) k_write_batch(const BatchReq *tab, int n)
@@ -1730,15 +1730,20 @@ void *item_fn(const RmDev &rm, bool f64)
     return f64 ? (void *)k_item64<2> : (void *)k_item32<2>;
 }
 
-void *fp64_fn(const RmDev &rm)
+void *retest_fn(const RmDev &rm)
 {
-    return rm.D == 3 ? (void *)k_fp64<3> : (void *)k_fp64<2>;
+    return rm.D == 3 ? (void *)k_retest<3> : (void *)k_retest<2>;
+}
+
+void *deferred_fn(const RmDev &rm)
+{
+    return rm.D == 3 ? (void *)k_deferred<3> : (void *)k_deferred<2>;
 }
 
 struct Node {
     void *fn;
     dim3 grid;
-    int kind;      // argument list: 0 diff, 1 (rm) only, 3 count, 4 write
+    int kind;      // argument list: 0 diff, 1 (rm) only, 4 write
     int ev0, ev1;  // stage events ev[ev0..ev1] are recorded after the node
 };
 
@@ -1746,15 +1751,18 @@ struct Node {
 // after the diff, ev[2] and ev[3] after the cell activation, ev[4] after the
 // item kernel, ev[5] after the binary64 pass, ev[6] after the labels.  With
 // a single grid cell there is nothing to activate: k_diff emits the items.
-int plan(const RmDev &rm, Node out[6])
+int plan(const RmDev &rm, Node out[7])
 {
     int n = 0;
     const bool single = rm.ncells == 1;
     out[n++] = {(void *)k_diff, dim3(1), 0, 1, single ? 3 : 1};
     if (!single) out[n++] = {(void *)k_cells, dim3(kCellsGrid), 1, 2, 3};
     out[n++] = {item_fn(rm, !rm.mixed), dim3(kGrid), 1, 4, rm.mixed ? 4 : 5};
-    if (rm.mixed) out[n++] = {fp64_fn(rm), dim3(kFp64Grid), 1, 5, 5};
-    out[n++] = {(void *)k_count, dim3(rm.ntiles), 3, -1, -1};
+    if (rm.mixed) {
+        out[n++] = {retest_fn(rm), dim3(kFp64Grid), 1, -1, -1};
+        out[n++] = {deferred_fn(rm), dim3(kFp64Grid), 1, 5, 5};
+    }
+    out[n++] = {(void *)k_count, dim3(rm.ntiles), 1, -1, -1};
     out[n++] = {(void *)k_write, dim3(rm.ntiles + 1), 4, 6, 6};
     return n;
 }
@@ -1768,17 +1776,17 @@ struct Args {
     int64_t cap;
     rgg_update_result *res;
     int zero = 0;
-    void *diff[3], *one[1], *count[3], *write[6];
+    void *diff[3], *one[1], *write[6];
     Args(const RmDev &rm, const UpdateArgs &a)
         : r(rm), ob(a.old_b), nb(a.new_b), lab(a.labels), gray(a.gray), cap(a.gray_cap), res(a.res),
-          diff{&r, (void *)&ob, (void *)&nb}, one{&r}, count{&r, &res, &zero},
+          diff{&r, (void *)&ob, (void *)&nb}, one{&r},
           write{&r, &lab, &gray, &cap, &res, &zero}
     {
     }
     Args(const Args &) = delete;
     void **of(int kind)
     {
-        return kind == 0 ? diff : (kind == 3 ? count : (kind == 4 ? write : one));
+        return kind == 0 ? diff : (kind == 4 ? write : one);
     }
     dim3 block(int kind) const { return dim3(kind == 0 ? kDiffBlock : kBlock); }
 };
@@ -1788,7 +1796,7 @@ struct Args {
 hipError_t launch_update(const RmDev &rm, const UpdateArgs &a, hipStream_t s, hipEvent_t *ev)
 {
     if (rm.chunk != kBlock) return hipErrorInvalidValue;   // one edge of an item per thread
-    Node nodes[6];
+    Node nodes[7];
     const int n = plan(rm, nodes);
     Args args(rm, a);
     hipError_t err;
@@ -1806,7 +1814,7 @@ hipError_t launch_update(const RmDev &rm, const UpdateArgs &a, hipStream_t s, hi
 
 hipError_t launch_labels(const RmDev &rm, const UpdateArgs &a, hipStream_t s)
 {
-    k_count<<<rm.ntiles, kBlock, 0, s>>>(rm, a.res, 1);
+    k_count<<<rm.ntiles, kBlock, 0, s>>>(rm);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     k_write<<<rm.ntiles, kBlock, 0, s>>>(rm, a.labels, a.gray, a.gray_cap, a.res, 1);
@@ -1817,7 +1825,7 @@ hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, 
                             hipGraphNode_t *last)
 {
     if (rm.chunk != kBlock) return hipErrorInvalidValue;
-    Node nodes[6];
+    Node nodes[7];
     const int n = plan(rm, nodes);
     Args args(rm, a);   // hipGraphAddKernelNode copies the argument values
     hipGraphNode_t prev = dep;
@@ -1862,7 +1870,8 @@ hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp
     void *a_diff[] = {(void *)&t};
     if ((err = add((void *)k_diff_batch, dim3(n), dim3(kDiffBlock), a_diff)) != hipSuccess) return err;
     void *a_tn[] = {(void *)&t, (void *)&nn};
-    if (any_grid && (err = add((void *)k_cells_batch, dim3(kCellsGrid), dim3(kBlock), a_tn)) != hipSuccess) return err;
+    if (any_grid && (err = add((void *)k_cells_batch, dim3(kCellsBatchGrid * n), dim3(kBlock), a_diff)) != hipSuccess)
+        return err;
     for (int k = 0; k < n_groups; ++k) {
         const BatchGroup &gr = groups[k];
         const int32_t *gp = grp + gr.off;
@@ -1873,8 +1882,10 @@ hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp
         if ((err = add(fn, dim3(kGrid), dim3(kBlock), a_item)) != hipSuccess) return err;
         if (gr.mixed) {
             void *a_fp[] = {(void *)&t, (void *)&gp};
-            void *f64 = gr.D == 3 ? (void *)k_fp64_batch<3> : (void *)k_fp64_batch<2>;
-            if ((err = add(f64, dim3(kFp64BatchGrid * cnt), dim3(kBlock), a_fp)) != hipSuccess) return err;
+            void *rt = gr.D == 3 ? (void *)k_retest_batch<3> : (void *)k_retest_batch<2>;
+            void *df = gr.D == 3 ? (void *)k_deferred_batch<3> : (void *)k_deferred_batch<2>;
+            if ((err = add(rt, dim3(kFp64BatchGrid * cnt), dim3(kBlock), a_fp)) != hipSuccess) return err;
+            if ((err = add(df, dim3(kFp64BatchGrid * cnt), dim3(kBlock), a_fp)) != hipSuccess) return err;
         }
     }
     if ((err = add((void *)k_count_batch, dim3(n_tiles), dim3(kBlock), a_tn)) != hipSuccess) return err;

@@ -15,7 +15,7 @@ struct Ctl {
     int32_t status;        // RGG_OK / RGG_E_INVALID_ARG / RGG_E_STATE_MISMATCH
     int32_t n_chg;         // changed (box, sign) entries
     int32_t n_items;       // (cell, chunk) work items of the grid scan
-    int32_t tiles_done;    // label tiles counted so far (the last one resets it)
+    int32_t any_df;        // some item was left whole to the binary64 pass
 };
 
 // One changed obstacle entry: the box a slot held before (sign -1) or holds
@@ -74,7 +74,7 @@ struct RmDev {
     int32_t *df;               // [kStatBlocks][df_cap] items a block left whole to the
                                // binary64 pass (its re-test region was full)
     int32_t *df_cnt;           // [kStatBlocks]
-    int32_t *tile_cnt;         // [ntiles + 1] gray edges per label tile, then their offsets
+    int32_t *tile_cnt;         // [ntiles] gray edges per label tile
     unsigned long long *blk_stats;   // [kStats][kStatBlocks] per-block partial counts
     Ctl *ctl;
 };
