@@ -81,12 +81,13 @@ def batched_planar(a):
     each update moving U{1..20} of them), FP32 tests + FP64 re-test.  One
     update round updates every roadmap once.  Plain: 64 rgg_update_async
     calls per round on one stream.  Batched: one rgg_batch_launch per round
-    (one graph, one kernel launch per stage for all 64 roadmaps).  Every
-    round's edges/s counts all edges of all roadmaps."""
+    (one kernel launch per stage for all 64 roadmaps); batched_graph: the
+    same stages as one captured-graph launch.  Every round's edges/s counts
+    all edges of all roadmaps."""
     import torch
     from paper_2603_28674_amd import rgg, synth
     K, W = a.batched_steps, 2
-    n_rounds = W + 3 * K
+    n_rounds = W + 4 * K
     t0 = time.perf_counter()
     ws = synth.batch_of_planar(seed=3, n_updates=n_rounds)
     log(f"[bench] batched: generated {len(ws)} roadmaps, {sum(w.n_edges for w in ws)} edges "
@@ -119,8 +120,13 @@ def batched_planar(a):
     batch = rgg.rgg_batch_create(ctx, [g.h for g in gs])
     rq = [reqs(u) for u in range(n_rounds)]
 
+    arrs = [(rgg.rgg_update_req * len(q))(*q) for q in rq]
+
     def batched(u):
-        rgg.rgg_batch_launch(batch, rq[u], stream)
+        rgg.lib().rgg_batch_launch(batch, arrs[u], C_void(stream))
+
+    def batched_graph(u):
+        rgg.lib().rgg_batch_launch_graph(batch, arrs[u], C_void(stream))
 
     u = 0
     for _ in range(W):
@@ -128,7 +134,7 @@ def batched_planar(a):
         u += 1
     torch.cuda.synchronize()
     out = {}
-    for name, fn in (("plain", plain), ("batched", batched)):
+    for name, fn in (("plain", plain), ("batched", batched), ("batched_graph", batched_graph)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         host = 0.0
@@ -158,7 +164,7 @@ def batched_planar(a):
         "workload": "64 planar rigid-body roadmaps (4 disks; nodes log-uniform in [1e3, 1e5], k=8, "
                     "U{20..400} boxes, each update moves U{1..20}), FP32 + FP64 re-test",
         "roadmaps": len(ws), "edges": E_tot, "rounds": K, "cell_size": a.batched_cell_size,
-        "plain": out["plain"], "batched": out["batched"],
+        "plain": out["plain"], "batched": out["batched"], "batched_graph": out["batched_graph"],
         "speedup_batched_vs_plain": out["batched"]["edges_per_s"] / out["plain"]["edges_per_s"],
         "batched_round_latency_p50_us": float(np.percentile(lat, 50)),
         "batched_round_latency_p99_us": float(np.percentile(lat, 99)),

@@ -235,7 +235,9 @@ rgg_status rgg_graph_destroy(rgg_graph *g);
  * computes exactly what rgg_update_async computes for its roadmap.
  *
  * rgg_batch_create fixes the roadmaps (rms[n]).  rgg_batch_launch queues one
- * batched update on `stream`: reqs[n] gives, in the same order, each
+ * batched update on `stream` (the stage kernels launched in stream order;
+ * rgg_batch_launch_graph launches them as the captured graph instead):
+ * reqs[n] gives, in the same order, each
  * roadmap's update arguments (reqs[k].rm must equal rms[k]); their device
  * pointers may differ from launch to launch, since the request table is
  * copied (from pinned host memory) in stream order before the graph runs.
@@ -247,6 +249,8 @@ rgg_status rgg_graph_destroy(rgg_graph *g);
  * launches to finish. */
 rgg_status rgg_batch_create(rgg_context *ctx, int32_t n, rgg_roadmap *const *rms, rgg_batch **out);
 rgg_status rgg_batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *stream);
+/* The same batched update as one launch of the batch's captured graph. */
+rgg_status rgg_batch_launch_graph(rgg_batch *b, const rgg_update_req *reqs, void *stream);
 rgg_status rgg_batch_destroy(rgg_batch *b);
 
 /* One batched update of n distinct roadmaps (create, launch, wait, destroy):

@@ -137,7 +137,7 @@ struct rgg_graph {
 };
 
 struct rgg_batch {
-    static constexpr int kRing = 4;   // host request tables in flight
+    static constexpr int kRing = 8;   // host request tables in flight
     int device = 0;
     int n = 0;
     std::vector<rgg_roadmap *> rms;   // request order
@@ -150,6 +150,9 @@ struct rgg_batch {
     int ring = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    std::vector<BatchGroup> groups;
+    bool any_grid = false;
+    int tiles = 0, wtiles = 0;
 
     ~rgg_batch()
     {
@@ -614,7 +617,7 @@ rgg_status rgg_batch_create(rgg_context *ctx, int32_t n, rgg_roadmap *const *rms
     b->n = n;
     b->rms.assign(rms, rms + n);
     // table rows grouped by kernel variant (dimension, precision)
-    std::vector<BatchGroup> groups;
+    std::vector<BatchGroup> &groups = b->groups;
     for (int D = 2; D <= 3; ++D)
         for (int mixed = 0; mixed <= 1; ++mixed) {
             BatchGroup g = {D, mixed, (int32_t)b->order.size(), 0};
@@ -625,12 +628,10 @@ rgg_status rgg_batch_create(rgg_context *ctx, int32_t n, rgg_roadmap *const *rms
                 }
             if (g.count) groups.push_back(g);
         }
-    bool any_grid = false;
-    int tiles = 0, wtiles = 0;
     for (int32_t k = 0; k < n; ++k) {
-        any_grid = any_grid || rms[k]->dv.ncells > 1;
-        tiles += rms[k]->dv.ntiles;
-        wtiles += rms[k]->dv.ntiles + 1;
+        b->any_grid = b->any_grid || rms[k]->dv.ncells > 1;
+        b->tiles += rms[k]->dv.ntiles;
+        b->wtiles += rms[k]->dv.ntiles + 1;
     }
     std::vector<int32_t> grp(n);
     for (int32_t k = 0; k < n; ++k) grp[k] = k;   // rows are already grouped
@@ -643,15 +644,15 @@ rgg_status rgg_batch_create(rgg_context *ctx, int32_t n, rgg_roadmap *const *rms
     }
     HIP_OR_FAIL(hipGraphCreate(&b->graph, 0), "hipGraphCreate");
     hipGraphNode_t last = nullptr;
-    HIP_OR_FAIL(add_batch_nodes(b->graph, b->d_tab, b->d_grp, n, groups.data(), (int)groups.size(), any_grid,
-                                tiles, wtiles, nullptr, &last),
+    HIP_OR_FAIL(add_batch_nodes(b->graph, b->d_tab, b->d_grp, n, groups.data(), (int)groups.size(), b->any_grid,
+                                b->tiles, b->wtiles, nullptr, &last),
                 "hipGraphAddKernelNode");
     HIP_OR_FAIL(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
     *out = b.release();
     return RGG_OK;
 }
 
-rgg_status rgg_batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *stream)
+static rgg_status batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *stream, bool graph)
 {
     if (!b || !reqs) return fail(RGG_E_INVALID_ARG, "null argument");
     for (int k = 0; k < b->n; ++k) {
@@ -683,7 +684,12 @@ rgg_status rgg_batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *stre
         if (st != RGG_OK) return st;
     }
     HIP_OR_FAIL(hipMemcpyAsync(b->d_tab, h, sizeof(BatchReq) * b->n, hipMemcpyHostToDevice, s), "copy batch table");
-    HIP_OR_FAIL(hipGraphLaunch(b->exec, s), "hipGraphLaunch");
+    if (graph)
+        HIP_OR_FAIL(hipGraphLaunch(b->exec, s), "hipGraphLaunch");
+    else
+        HIP_OR_FAIL(launch_batch(s, b->d_tab, b->d_grp, b->n, b->groups.data(), (int)b->groups.size(), b->any_grid,
+                                 b->tiles, b->wtiles),
+                    "batch launch");
     HIP_OR_FAIL(hipEventRecord(b->done[slot], s), "hipEventRecord");
     b->used[slot] = true;
     for (rgg_roadmap *rm : b->rms) {   // one event stands for every roadmap's update
@@ -691,6 +697,16 @@ rgg_status rgg_batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *stre
         rm->last_stream = s;
     }
     return RGG_OK;
+}
+
+rgg_status rgg_batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *stream)
+{
+    return batch_launch(b, reqs, stream, false);
+}
+
+rgg_status rgg_batch_launch_graph(rgg_batch *b, const rgg_update_req *reqs, void *stream)
+{
+    return batch_launch(b, reqs, stream, true);
 }
 
 rgg_status rgg_batch_destroy(rgg_batch *b)

@@ -1846,6 +1846,44 @@ hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, 
     return hipSuccess;
 }
 
+namespace {
+
+// The kernels of a batched update in order, each handed to `emit(fn, grid,
+// block, args)` (a graph-node adder or a stream launcher).
+template <typename Emit>
+hipError_t batch_kernels(Emit emit, const BatchReq *tab, const int32_t *grp, int n, const BatchGroup *groups,
+                         int n_groups, bool any_grid, int n_tiles, int n_wtiles)
+{
+    const BatchReq *t = tab;
+    int nn = n;
+    hipError_t err;
+    void *a_diff[] = {(void *)&t};
+    if ((err = emit((void *)k_diff_batch, dim3(n), dim3(kDiffBlock), a_diff)) != hipSuccess) return err;
+    void *a_tn[] = {(void *)&t, (void *)&nn};
+    if (any_grid && (err = emit((void *)k_cells_batch, dim3(kCellsBatchGrid * n), dim3(kBlock), a_diff)) != hipSuccess)
+        return err;
+    for (int k = 0; k < n_groups; ++k) {
+        const BatchGroup &gr = groups[k];
+        const int32_t *gp = grp + gr.off;
+        int cnt = gr.count;
+        void *a_item[] = {(void *)&t, (void *)&gp, (void *)&cnt};
+        void *fn = gr.D == 3 ? (gr.mixed ? (void *)k_item32_batch<3> : (void *)k_item64_batch<3>)
+                             : (gr.mixed ? (void *)k_item32_batch<2> : (void *)k_item64_batch<2>);
+        if ((err = emit(fn, dim3(kGrid), dim3(kBlock), a_item)) != hipSuccess) return err;
+        if (gr.mixed) {
+            void *a_fp[] = {(void *)&t, (void *)&gp};
+            void *rt = gr.D == 3 ? (void *)k_retest_batch<3> : (void *)k_retest_batch<2>;
+            void *df = gr.D == 3 ? (void *)k_deferred_batch<3> : (void *)k_deferred_batch<2>;
+            if ((err = emit(rt, dim3(kFp64BatchGrid * cnt), dim3(kBlock), a_fp)) != hipSuccess) return err;
+            if ((err = emit(df, dim3(kFp64BatchGrid * cnt), dim3(kBlock), a_fp)) != hipSuccess) return err;
+        }
+    }
+    if ((err = emit((void *)k_count_batch, dim3(n_tiles), dim3(kBlock), a_tn)) != hipSuccess) return err;
+    return emit((void *)k_write_batch, dim3(n_wtiles), dim3(kBlock), a_tn);
+}
+
+}  // namespace
+
 hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp, int n,
                            const BatchGroup *groups, int n_groups, bool any_grid, int n_tiles,
                            int n_wtiles, hipGraphNode_t dep, hipGraphNode_t *last)
@@ -1864,34 +1902,18 @@ hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp
         if (err == hipSuccess) prev = node;
         return err;
     };
-    const BatchReq *t = tab;
-    int nn = n;
-    hipError_t err;
-    void *a_diff[] = {(void *)&t};
-    if ((err = add((void *)k_diff_batch, dim3(n), dim3(kDiffBlock), a_diff)) != hipSuccess) return err;
-    void *a_tn[] = {(void *)&t, (void *)&nn};
-    if (any_grid && (err = add((void *)k_cells_batch, dim3(kCellsBatchGrid * n), dim3(kBlock), a_diff)) != hipSuccess)
-        return err;
-    for (int k = 0; k < n_groups; ++k) {
-        const BatchGroup &gr = groups[k];
-        const int32_t *gp = grp + gr.off;
-        int cnt = gr.count;
-        void *a_item[] = {(void *)&t, (void *)&gp, (void *)&cnt};
-        void *fn = gr.D == 3 ? (gr.mixed ? (void *)k_item32_batch<3> : (void *)k_item64_batch<3>)
-                             : (gr.mixed ? (void *)k_item32_batch<2> : (void *)k_item64_batch<2>);
-        if ((err = add(fn, dim3(kGrid), dim3(kBlock), a_item)) != hipSuccess) return err;
-        if (gr.mixed) {
-            void *a_fp[] = {(void *)&t, (void *)&gp};
-            void *rt = gr.D == 3 ? (void *)k_retest_batch<3> : (void *)k_retest_batch<2>;
-            void *df = gr.D == 3 ? (void *)k_deferred_batch<3> : (void *)k_deferred_batch<2>;
-            if ((err = add(rt, dim3(kFp64BatchGrid * cnt), dim3(kBlock), a_fp)) != hipSuccess) return err;
-            if ((err = add(df, dim3(kFp64BatchGrid * cnt), dim3(kBlock), a_fp)) != hipSuccess) return err;
-        }
-    }
-    if ((err = add((void *)k_count_batch, dim3(n_tiles), dim3(kBlock), a_tn)) != hipSuccess) return err;
-    if ((err = add((void *)k_write_batch, dim3(n_wtiles), dim3(kBlock), a_tn)) != hipSuccess) return err;
-    *last = prev;
-    return hipSuccess;
+    hipError_t err = batch_kernels(add, tab, grp, n, groups, n_groups, any_grid, n_tiles, n_wtiles);
+    if (err == hipSuccess) *last = prev;
+    return err;
+}
+
+hipError_t launch_batch(hipStream_t s, const BatchReq *tab, const int32_t *grp, int n, const BatchGroup *groups,
+                        int n_groups, bool any_grid, int n_tiles, int n_wtiles)
+{
+    auto launch = [&](void *fn, dim3 grid, dim3 block, void **args) -> hipError_t {
+        return hipLaunchKernel(fn, grid, block, args, 0, s);
+    };
+    return batch_kernels(launch, tab, grp, n, groups, n_groups, any_grid, n_tiles, n_wtiles);
 }
 
 }  // namespace rgg

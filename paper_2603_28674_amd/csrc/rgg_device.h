@@ -119,6 +119,9 @@ struct BatchGroup {
 hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp, int n,
                            const BatchGroup *groups, int n_groups, bool any_grid, int n_tiles,
                            int n_wtiles, hipGraphNode_t dep, hipGraphNode_t *last);
+// The same kernels launched on `s`.
+hipError_t launch_batch(hipStream_t s, const BatchReq *tab, const int32_t *grp, int n, const BatchGroup *groups,
+                        int n_groups, bool any_grid, int n_tiles, int n_wtiles);
 
 // Queues the kernels of one update on `s`.  When `ev` is non-null, ev[0..6]
 // are recorded before, between and after the stages (diff, cells, grid scan,

@@ -94,7 +94,7 @@ RESULT_BYTES = C.sizeof(rgg_update_result)
 EXPORTS = ["rgg_context_create", "rgg_context_destroy", "rgg_build", "rgg_destroy",
            "rgg_roadmap_info_get", "rgg_update", "rgg_update_async", "rgg_graph_create",
            "rgg_graph_launch", "rgg_graph_destroy", "rgg_batch_create", "rgg_batch_launch",
-           "rgg_batch_destroy", "rgg_update_batch", "rgg_labels", "rgg_gray_list",
+           "rgg_batch_launch_graph", "rgg_batch_destroy", "rgg_update_batch", "rgg_labels", "rgg_gray_list",
            "rgg_timing_enable", "rgg_timing_read", "rgg_debug_geometry", "rgg_last_error",
            "rgg_version"]
 
@@ -123,6 +123,7 @@ def lib():
         "rgg_graph_destroy": (I32, [P]),
         "rgg_batch_create": (I32, [P, I32, P, C.POINTER(P)]),
         "rgg_batch_launch": (I32, [P, P, P]),
+        "rgg_batch_launch_graph": (I32, [P, P, P]),
         "rgg_batch_destroy": (I32, [P]),
         "rgg_update_batch": (I32, [P, I32, P, P]),
         "rgg_labels": (I32, [P, P]),
@@ -316,6 +317,11 @@ def rgg_batch_create(ctx, roadmaps):
 def rgg_batch_launch(b, reqs, stream):
     arr = (rgg_update_req * len(reqs))(*reqs)
     _check(lib().rgg_batch_launch(b, arr, C.c_void_p(stream)))
+
+
+def rgg_batch_launch_graph(b, reqs, stream):
+    arr = (rgg_update_req * len(reqs))(*reqs)
+    _check(lib().rgg_batch_launch_graph(b, arr, C.c_void_p(stream)))
 
 
 def rgg_batch_destroy(b):

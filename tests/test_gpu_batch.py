@@ -60,6 +60,8 @@ def run_batched(ctx, specs, n_updates, one_shot=False):
                                            lab.data_ptr(), gray.data_ptr(), w.n_edges, res.data_ptr()))
         if one_shot:
             rgg.rgg_update_batch(ctx, reqs, stream)
+        elif u % 2:
+            rgg.rgg_batch_launch_graph(batch, reqs, stream)   # the captured-graph form
         else:
             rgg.rgg_batch_launch(batch, reqs, stream)
         torch.cuda.synchronize()
