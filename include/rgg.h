@@ -55,6 +55,7 @@ typedef int32_t rgg_status;
 #define RGG_E_CAPACITY (-4)        /* gray list longer than the caller's cap */
 #define RGG_E_DEVICE (-5)          /* HIP runtime error                      */
 #define RGG_E_UNSUPPORTED (-6)     /* valid request this build cannot serve  */
+#define RGG_E_BUSY (-7)            /* server queue full; submit again later  */
 
 /* robot kinds */
 #define RGG_SE2 0
@@ -256,6 +257,52 @@ rgg_status rgg_batch_destroy(rgg_batch *b);
 /* One batched update of n distinct roadmaps (create, launch, wait, destroy):
  * the convenience form of the three calls above.  Blocks until done. */
 rgg_status rgg_update_batch(rgg_context *ctx, int32_t n, const rgg_update_req *reqs, void *stream);
+
+/* Request server (continuous batching).  A worker thread takes the queued
+ * updates of device-resident roadmaps to the GPU as batches (one launch per
+ * stage for the whole batch, as rgg_batch_launch), on n_streams streams, so
+ * requests that arrive while others run are admitted into the next batch
+ * and their work overlaps on the device.  Admission is by memory: each
+ * request's obstacle boxes are staged in a device pool of pool_bytes, and a
+ * request is dispatched only when its 2*m boxes fit in the pool's free space
+ * (requests of one roadmap keep their submission order; the next one may
+ * start before the previous one has finished, ordered on the device).  Each
+ * request computes exactly what rgg_update_async computes for it. */
+typedef struct rgg_server rgg_server;
+
+typedef struct {
+    int32_t n_streams;            /* batches in flight at once; 0 = 4, max 16   */
+    int32_t max_queue;            /* queued requests; 0 = 4096                  */
+    int32_t max_batch;            /* requests per batch; 0 = 64, max 256        */
+    int32_t reserved;             /* must be 0                                  */
+    int64_t pool_bytes;           /* device staging for boxes; 0 = 64 MiB       */
+} rgg_server_opts;
+
+typedef struct {
+    rgg_roadmap *rm;              /* resident roadmap; not updated elsewhere
+                                     while the server holds requests for it     */
+    int64_t m;                    /* = its n_obstacle_slots                     */
+    const rgg_box *old_boxes;     /* [m] host; copied by rgg_server_submit      */
+    const rgg_box *new_boxes;     /* [m] host; copied by rgg_server_submit      */
+    uint8_t *d_labels;            /* [E] device or NULL; written in order       */
+    int64_t *d_gray;              /* [gray_cap] device or NULL                  */
+    int64_t gray_cap;
+} rgg_server_req;
+
+/* Starts the server (its worker thread and streams) on ctx's device. */
+rgg_status rgg_server_start(rgg_context *ctx, const rgg_server_opts *opts, rgg_server **out);
+/* Queues one update; *ticket identifies it.  RGG_E_BUSY if the queue is
+ * full, RGG_E_INVALID_ARG for a malformed request or one whose boxes can
+ * never fit the pool.  The boxes are copied before it returns. */
+rgg_status rgg_server_submit(rgg_server *srv, const rgg_server_req *req, uint64_t *ticket);
+/* State of a ticket: *done = 0 (queued or running) or 1 (finished; *result
+ * and *latency_us, submission to completion, are set and the ticket is
+ * released).  wait != 0 blocks until it has finished.  RGG_E_INVALID_ARG for
+ * an unknown ticket. */
+rgg_status rgg_server_poll(rgg_server *srv, uint64_t ticket, int32_t wait, int32_t *done,
+                           rgg_update_result *result, double *latency_us);
+/* Finishes every queued request, then stops the worker and frees the server. */
+rgg_status rgg_server_stop(rgg_server *srv);
 
 /* Current labels [E] / gray list of the last update, copied to host memory.
  * rgg_gray_list writes min(n, cap) ids and sets *n to the full count. */

@@ -24,6 +24,7 @@ RGG_E_STATE_MISMATCH = -3
 RGG_E_CAPACITY = -4
 RGG_E_DEVICE = -5
 RGG_E_UNSUPPORTED = -6
+RGG_E_BUSY = -7
 
 RGG_SE2, RGG_SE3, RGG_PLANAR_ARM = 0, 1, 2
 RGG_GREEN, RGG_GRAY, RGG_RED = 0, 1, 2
@@ -88,13 +89,24 @@ class rgg_update_req(C.Structure):
                 ("gray_cap", C.c_int64), ("d_result", C.c_void_p)]
 
 
+class rgg_server_opts(C.Structure):
+    _fields_ = [("n_streams", C.c_int32), ("max_queue", C.c_int32), ("max_batch", C.c_int32),
+                ("reserved", C.c_int32), ("pool_bytes", C.c_int64)]
+
+
+class rgg_server_req(C.Structure):
+    _fields_ = [("rm", C.c_void_p), ("m", C.c_int64), ("old_boxes", C.c_void_p), ("new_boxes", C.c_void_p),
+                ("d_labels", C.c_void_p), ("d_gray", C.c_void_p), ("gray_cap", C.c_int64)]
+
+
 RESULT_BYTES = C.sizeof(rgg_update_result)
 
 #: every symbol include/rgg.h declares
 EXPORTS = ["rgg_context_create", "rgg_context_destroy", "rgg_build", "rgg_destroy",
            "rgg_roadmap_info_get", "rgg_update", "rgg_update_async", "rgg_graph_create",
            "rgg_graph_launch", "rgg_graph_destroy", "rgg_batch_create", "rgg_batch_launch",
-           "rgg_batch_launch_graph", "rgg_batch_destroy", "rgg_update_batch", "rgg_labels", "rgg_gray_list",
+           "rgg_batch_launch_graph", "rgg_batch_destroy", "rgg_update_batch", "rgg_server_start",
+           "rgg_server_submit", "rgg_server_poll", "rgg_server_stop", "rgg_labels", "rgg_gray_list",
            "rgg_timing_enable", "rgg_timing_read", "rgg_debug_geometry", "rgg_last_error",
            "rgg_version"]
 
@@ -126,6 +138,10 @@ def lib():
         "rgg_batch_launch_graph": (I32, [P, P, P]),
         "rgg_batch_destroy": (I32, [P]),
         "rgg_update_batch": (I32, [P, I32, P, P]),
+        "rgg_server_start": (I32, [P, P, C.POINTER(P)]),
+        "rgg_server_submit": (I32, [P, P, C.POINTER(C.c_uint64)]),
+        "rgg_server_poll": (I32, [P, C.c_uint64, I32, C.POINTER(I32), P, C.POINTER(C.c_double)]),
+        "rgg_server_stop": (I32, [P]),
         "rgg_labels": (I32, [P, P]),
         "rgg_gray_list": (I32, [P, P, I64, P]),
         "rgg_timing_enable": (I32, [P, I32]),
@@ -331,6 +347,37 @@ def rgg_batch_destroy(b):
 def rgg_update_batch(ctx, reqs, stream):
     arr = (rgg_update_req * len(reqs))(*reqs)
     _check(lib().rgg_update_batch(ctx, len(reqs), arr, C.c_void_p(stream)))
+
+
+def rgg_server_start(ctx, n_streams=0, max_queue=0, max_batch=0, pool_bytes=0):
+    o = rgg_server_opts(n_streams, max_queue, max_batch, 0, pool_bytes)
+    h = C.c_void_p()
+    _check(lib().rgg_server_start(ctx, C.byref(o), C.byref(h)))
+    return h
+
+
+def rgg_server_submit(srv, rm, old, new, d_labels=0, d_gray=0, gray_cap=0):
+    """Queues one update of roadmap handle `rm` (host box arrays [m, 6]);
+    returns the ticket."""
+    old = boxes_array(old)
+    new = boxes_array(new)
+    q = rgg_server_req(getattr(rm, "value", rm), old.shape[0], _ptr(old), _ptr(new), d_labels, d_gray, gray_cap)
+    t = C.c_uint64()
+    _check(lib().rgg_server_submit(srv, C.byref(q), C.byref(t)))
+    return t.value
+
+
+def rgg_server_poll(srv, ticket, wait=False):
+    """(done, result, latency_us); result is None while the request runs."""
+    done = C.c_int32()
+    res = rgg_update_result()
+    lat = C.c_double()
+    _check(lib().rgg_server_poll(srv, ticket, 1 if wait else 0, C.byref(done), C.byref(res), C.byref(lat)))
+    return (True, res, lat.value) if done.value else (False, None, 0.0)
+
+
+def rgg_server_stop(srv):
+    _check(lib().rgg_server_stop(srv))
 
 
 def rgg_timing_enable(rm, on=True):

@@ -1,0 +1,147 @@
+"""GPU tests of the request server (continuous batching).
+
+Every request's labels and gray count equal the FP64 oracle's for that
+roadmap's update, whether the request ran alone (submitted after the
+previous one finished) or in the mix (all requests of all roadmaps submitted
+at once, so they share batches and overlap on the device)."""
+import numpy as np
+import pytest
+
+from paper_2603_28674_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2603_28674_amd import rgg
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = rgg.rgg_context_create(0)
+    yield c
+    rgg.rgg_context_destroy(c)
+
+
+def roadmap_specs(n_updates):
+    from paper_2603_28674_amd import rgg
+    fp32, fp64 = rgg.RGG_PREC_FP32_RECHECK, rgg.RGG_PREC_FP64
+    return [
+        (synth.spatial_rigid(seed=71, n_nodes=2000, n_boxes=80, n_updates=n_updates, world=4.0), fp32, -1.0),
+        (synth.planar_arm(seed=72, n_nodes=1500, n_boxes=30, n_updates=n_updates), fp32, 0.0),
+        (synth.planar_rigid(seed=73, n_nodes=1200, n_boxes=30, n_updates=n_updates), fp64, -1.0),
+        (synth.spatial_rigid(seed=74, n_nodes=800, n_boxes=40, n_updates=n_updates, world=3.0), fp32, 0.0),
+    ]
+
+
+def oracle_results(specs, n_updates):
+    import oracle
+    out = []
+    for w, _, _ in specs:
+        o = oracle.from_workload(w)
+        prev, per = w.absent(), []
+        for u in range(n_updates):
+            per.append(o.update(prev, w.boxes[u]))
+            prev = w.boxes[u]
+        out.append(per)
+    return out
+
+
+def run_server(ctx, specs, n_updates, mixed, **opts):
+    """Submits every update of every roadmap; returns per-(roadmap, update)
+    (labels, n_gray, gray, status, latency)."""
+    import torch
+    from paper_2603_28674_amd import rgg
+    dev = torch.device("cuda:0")
+    gs = [rgg.Roadmap.from_workload(ctx, w, precision=p, cell_size=c) for w, p, c in specs]
+    outs = {}
+    for k, (w, _, _) in enumerate(specs):
+        for u in range(n_updates):
+            outs[(k, u)] = (torch.zeros(w.n_edges, dtype=torch.uint8, device=dev),
+                            torch.zeros(max(w.n_edges, 1), dtype=torch.int64, device=dev))
+    srv = rgg.rgg_server_start(ctx, **opts)
+    order = [(k, u) for u in range(n_updates) for k in range(len(specs))]   # interleaved
+    tickets = {}
+    res = {}
+    for k, u in order:
+        w = specs[k][0]
+        prev = w.absent() if u == 0 else w.boxes[u - 1]
+        lab, gray = outs[(k, u)]
+        t = rgg.rgg_server_submit(srv, gs[k].h, prev, w.boxes[u], lab.data_ptr(), gray.data_ptr(), w.n_edges)
+        if mixed:
+            tickets[(k, u)] = t
+        else:
+            res[(k, u)] = rgg.rgg_server_poll(srv, t, wait=True)
+    for key, t in tickets.items():
+        res[key] = rgg.rgg_server_poll(srv, t, wait=True)
+    rgg.rgg_server_stop(srv)
+    for g in gs:
+        g.close()
+    out = {}
+    for key, (done, r, lat) in res.items():
+        assert done
+        lab, gray = outs[key]
+        out[key] = (lab.cpu().numpy(), r.n_gray, gray[: r.n_gray].cpu().numpy(), r.status, lat)
+    return out
+
+
+def test_server_alone_and_in_the_mix(ctx):
+    n_updates = 4
+    specs = roadmap_specs(n_updates)
+    for w, p, c in specs:
+        print(f"[server] {w.name} E={w.n_edges} M={w.n_slots} prec={p} cell={c}", flush=True)
+    expect = oracle_results(specs, n_updates)
+    print("[server] alone", flush=True)
+    alone = run_server(ctx, specs, n_updates, mixed=False)
+    print("[server] in the mix", flush=True)
+    mix = run_server(ctx, specs, n_updates, mixed=True, n_streams=3, max_batch=3)
+    for key in alone:
+        k, u = key
+        ol, og = expect[k][u]
+        for name, got in (("alone", alone[key]), ("mix", mix[key])):
+            lab, n_gray, gray, status, lat = got
+            assert status == 0, f"{name} {key}: status {status}"
+            assert n_gray == len(og), f"{name} {key}: n_gray {n_gray} vs {len(og)}"
+            assert np.array_equal(lab, ol), f"{name} {key}: labels differ"
+            assert np.array_equal(gray, og), f"{name} {key}: gray list differs"
+            assert lat > 0.0
+        assert np.array_equal(alone[key][0], mix[key][0])
+
+
+def test_server_small_pool_admits_by_memory(ctx):
+    """A pool that holds one request's boxes at a time still finishes every
+    request, in each roadmap's order, with exact results."""
+    n_updates = 3
+    specs = roadmap_specs(n_updates)[:3]
+    expect = oracle_results(specs, n_updates)
+    largest = max(w.n_slots for w, _, _ in specs)
+    pool = ((2 * largest * 48 + 255) // 256) * 256
+    print(f"[server] pool {pool} bytes", flush=True)
+    got = run_server(ctx, specs, n_updates, mixed=True, n_streams=2, pool_bytes=pool)
+    for (k, u), (lab, n_gray, gray, status, lat) in got.items():
+        ol, og = expect[k][u]
+        assert status == 0 and n_gray == len(og)
+        assert np.array_equal(lab, ol) and np.array_equal(gray, og)
+
+
+def test_server_errors(ctx):
+    from paper_2603_28674_amd import rgg
+    w = synth.planar_rigid(seed=75, n_nodes=200, n_boxes=10, n_updates=1)
+    print("[server errors]", flush=True)
+    g = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK)
+    srv = rgg.rgg_server_start(ctx, pool_bytes=256)
+    with pytest.raises(rgg.RggError) as ei:       # 2 x 10 boxes never fit 256 bytes
+        rgg.rgg_server_submit(srv, g.h, w.absent(), w.boxes[0])
+    assert ei.value.status == rgg.RGG_E_INVALID_ARG
+    with pytest.raises(rgg.RggError):             # wrong slot count
+        rgg.rgg_server_submit(srv, g.h, w.absent()[:-1], w.boxes[0][:-1])
+    with pytest.raises(rgg.RggError):             # unknown ticket
+        rgg.rgg_server_poll(srv, 12345)
+    rgg.rgg_server_stop(srv)
+    # a stale `old` is reported per request, and the roadmap is unchanged
+    srv = rgg.rgg_server_start(ctx)
+    t = rgg.rgg_server_submit(srv, g.h, w.boxes[0], w.boxes[0])
+    done, r, _ = rgg.rgg_server_poll(srv, t, wait=True)
+    assert done and r.status == rgg.RGG_E_STATE_MISMATCH
+    rgg.rgg_server_stop(srv)
+    assert np.all(g.labels() == 0)
+    g.close()
