@@ -47,6 +47,9 @@ def parse():
                    help="skip the batched-planar measurement (64 roadmaps)")
     p.add_argument("--batched-steps", type=int, default=20)
     p.add_argument("--batched-cell-size", type=float, default=0.0)
+    p.add_argument("--no-serving", action="store_true",
+                   help="skip the serving measurement (16 resident roadmaps, Poisson requests)")
+    p.add_argument("--serving-seconds", type=float, default=2.0)
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 1 GiB device copy 5 times (reference kernel for "
                         "scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -170,6 +173,76 @@ def batched_planar(a):
         "batched_round_latency_p99_us": float(np.percentile(lat, 99)),
         "status_ok": ok,
     }
+
+
+def serving(a):
+    """The serving configuration: 16 device-resident roadmaps (8 spatial
+    rigid-body, 8 planar arm; edge counts log-uniform in [1e4, 5e5]) behind
+    the request server (4 streams, batches of up to 64, 64 MiB box pool).
+    Open-loop Poisson arrivals at 100, 1000 and 10000 requests/s, each moving
+    U{1..50} boxes of a random roadmap.  Latency is the server's, from submit
+    to completion; edges/s counts the edges of every completed request."""
+    import torch
+    from paper_2603_28674_amd import rgg, synth
+    t0 = time.perf_counter()
+    ws = synth.serving_mix(seed=5)
+    log(f"[bench] serving: generated {len(ws)} roadmaps, {sum(w.n_edges for w in ws)} edges "
+        f"in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    ctx = rgg.rgg_context_create(0)
+    t0 = time.perf_counter()
+    gs = [rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK, cell_size=0.0) for w in ws]
+    log(f"[bench] serving: built in {time.perf_counter() - t0:.1f}s")
+    labs = [torch.zeros(w.n_edges, dtype=torch.uint8, device=dev) for w in ws]
+    grays = [torch.zeros(w.n_edges, dtype=torch.int64, device=dev) for w in ws]
+    for g, w in zip(gs, ws):
+        g.update(w.absent(), w.boxes[0], want_labels=False)
+    srv = rgg.rgg_server_start(ctx, n_streams=4, max_batch=64, pool_bytes=64 << 20)
+    rng = np.random.default_rng(a.seed + 77)
+    cur = [w.boxes[0] for w in ws]
+    levels = []
+    ok = True
+    for rate in (100.0, 1000.0, 10000.0):
+        reqs, cur = synth.serving_requests(rng, ws, rate, a.serving_seconds, start=cur)
+        tickets = []
+        busy = 0
+        t0 = time.perf_counter()
+        for (ta, r, old, new) in reqs:
+            while time.perf_counter() - t0 < ta:
+                pass
+            while True:
+                try:
+                    t = rgg.rgg_server_submit(srv, gs[r].h, old, new, labs[r].data_ptr(), grays[r].data_ptr(),
+                                              ws[r].n_edges)
+                    break
+                except rgg.RggError as e:
+                    if e.status != rgg.RGG_E_BUSY:
+                        raise
+                    busy += 1
+                    time.sleep(20e-6)
+            tickets.append((t, ws[r].n_edges))
+        lat, edges = [], 0
+        for t, e in tickets:
+            done, res, l = rgg.rgg_server_poll(srv, t, wait=True)
+            ok = ok and res.status == 0
+            lat.append(l)
+            edges += e
+        wall = time.perf_counter() - t0
+        lat = np.array(lat)
+        levels.append({"offered_rate": rate, "requests": len(tickets), "achieved_rate": len(tickets) / wall,
+                       "edges_per_s": edges / wall, "latency_p50_us": float(np.percentile(lat, 50)),
+                       "latency_p99_us": float(np.percentile(lat, 99)), "latency_mean_us": float(lat.mean()),
+                       "busy_retries": busy})
+        log(f"[bench] serving at {rate:.0f}/s: {levels[-1]}")
+    rgg.rgg_server_stop(srv)
+    for g in gs:
+        g.close()
+    rgg.rgg_context_destroy(ctx)
+    return {"workload": "16 resident roadmaps: 8 spatial rigid-body + 8 planar-arm, edges log-uniform in "
+                        "[1e4, 5e5]; Poisson requests moving U{1..50} boxes; FP32 + FP64 re-test",
+            "roadmaps": len(ws), "edges": int(sum(w.n_edges for w in ws)), "seconds_per_rate": a.serving_seconds,
+            "server": {"n_streams": 4, "max_batch": 64, "pool_bytes": 64 << 20}, "rates": levels,
+            "status_ok": bool(ok)}
 
 
 def C_void(x):
@@ -349,6 +422,9 @@ def main():
     if not a.no_batched:
         log("[bench] batched planar roadmaps")
         line["batched_planar"] = batched_planar(a)
+    if not a.no_serving:
+        log("[bench] serving")
+        line["serving"] = serving(a)
     if a.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)

@@ -296,3 +296,48 @@ def batch_of_planar(seed: int = 3, n_roadmaps: int = 64, n_lo: int = 1000, n_hi:
         w.name = f"planar_batch_{r}"
         out.append(w)
     return out
+
+
+def serving_mix(seed: int = 5, n_spatial: int = 8, n_arm: int = 8, e_lo: float = 1e4,
+                e_hi: float = 5e5) -> List[Workload]:
+    """Resident roadmaps of the serving configuration: spatial rigid-body and
+    planar-arm roadmaps whose edge counts are log-uniform in [e_lo, e_hi]
+    (node counts from the edges per node that k = 10 and k = 8 give: about
+    5.9 and 4.6).  Each carries only its first obstacle set; the requests'
+    moves are drawn by ``serving_requests``."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_spatial + n_arm):
+        e = math.exp(rng.uniform(math.log(e_lo), math.log(e_hi)))
+        if k < n_spatial:
+            out.append(spatial_rigid(seed=int(rng.integers(1 << 30)), n_nodes=max(200, int(e / 5.9)),
+                                     n_updates=0))
+        else:
+            out.append(planar_arm(seed=int(rng.integers(1 << 30)), n_nodes=max(200, int(e / 4.6)),
+                                  n_updates=0))
+    return out
+
+
+def serving_requests(rng: np.random.Generator, workloads: List[Workload], rate: float, duration: float,
+                     max_move: int = 50, start: Optional[List[np.ndarray]] = None):
+    """Open-loop Poisson arrivals at ``rate`` per second for ``duration``
+    seconds; each request moves U{1..max_move} boxes of a uniformly chosen
+    roadmap (N(0, 0.3) per axis for spatial roadmaps, N(0, 2) for arms),
+    starting from that roadmap's current state (``start``, else its first
+    obstacle set).  Returns a list of (arrival_time, roadmap_index,
+    old_boxes, new_boxes) and the final states."""
+    cur = [b.copy() for b in start] if start is not None else [w.boxes[0].copy() for w in workloads]
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            break
+        r = int(rng.integers(len(workloads)))
+        w = workloads[r]
+        dim = w.robot.dim
+        sigma = 0.3 if w.robot.kind == SE3 else 2.0
+        nxt = move_sequence(rng, cur[r], dim, 1, (1, max_move), sigma)[1]
+        out.append((t, r, cur[r], nxt))
+        cur[r] = nxt
+    return out, cur
+
