@@ -20,6 +20,7 @@
 #include "api_internal.h"
 
 static_assert(rgg::kLocalGridCells == rgg::kLocalCells, "pruning-grid size of host and device");
+static_assert(rgg::kCopyStride3 == 4 && rgg::kCopyStride2 == 2, "sample layout of host and device");
 
 using namespace rgg;
 
@@ -685,12 +686,13 @@ rgg_status rgg_debug_geometry(const rgg_roadmap_desc *rd, const rgg_robot *robot
         const int64_t P = g.soff[k + 1] - g.soff[k];
         n_configs[k] = P / B;
         if (centres) {
-            const double *blk = g.samp.data() + D * g.soff[k];
-            const int64_t J = P / B;   // block layout [D][B][J] -> rows (j, i)
+            const int S = copy_stride(D);
+            const double *blk = g.samp.data() + S * g.soff[k];
+            const int64_t J = P / B;   // block layout [B][J][S] -> rows (j, i)
             for (int64_t j = 0; j < J; ++j)
                 for (int i = 0; i < B; ++i)
                     for (int d = 0; d < D; ++d)
-                        centres[(row + j * B + i) * D + d] = blk[d * P + i * J + j];
+                        centres[(row + j * B + i) * D + d] = blk[(i * J + j) * S + d];
         }
         row += P;
         if (capsule) {

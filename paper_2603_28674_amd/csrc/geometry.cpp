@@ -104,9 +104,9 @@ void config_at(const rgg_robot *r, const Motion &m, double t, double *q)
     }
 }
 
-// Writes the sphere centres of configuration j (of J) into a [D][B][J] block:
-// coordinate d of sphere i lands at blk[d*P + i*J + j], P = B*J.
-void place_spheres(const rgg_robot *r, const double *q, double *blk, int64_t P, int64_t J, int64_t j)
+// Writes the sphere centres of configuration j (of J) into a [B][J][S] block:
+// coordinate d of sphere i lands at blk[(i*J + j)*S + d].
+void place_spheres(const rgg_robot *r, const double *q, double *blk, int64_t S, int64_t J, int64_t j)
 {
     const int B = r->n_spheres;
     if (r->kind == RGG_SE2) {
@@ -114,8 +114,8 @@ void place_spheres(const rgg_robot *r, const double *q, double *blk, int64_t P, 
         double s = sin(q[2]);
         for (int i = 0; i < B; ++i) {
             double ox = r->sphere_pos[2 * i], oy = r->sphere_pos[2 * i + 1];
-            blk[i * J + j] = q[0] + (c * ox - s * oy);
-            blk[P + i * J + j] = q[1] + (s * ox + c * oy);
+            blk[(i * J + j) * S] = q[0] + (c * ox - s * oy);
+            blk[(i * J + j) * S + 1] = q[1] + (s * ox + c * oy);
         }
     } else if (r->kind == RGG_SE3) {
         // v' = v + w*t + u x t, t = 2 (u x v), for the quaternion (w, u)
@@ -125,9 +125,9 @@ void place_spheres(const rgg_robot *r, const double *q, double *blk, int64_t P, 
             double tx = 2.0 * (uy * v[2] - uz * v[1]);
             double ty = 2.0 * (uz * v[0] - ux * v[2]);
             double tz = 2.0 * (ux * v[1] - uy * v[0]);
-            blk[i * J + j] = q[0] + ((v[0] + w * tx) + (uy * tz - uz * ty));
-            blk[P + i * J + j] = q[1] + ((v[1] + w * ty) + (uz * tx - ux * tz));
-            blk[2 * P + i * J + j] = q[2] + ((v[2] + w * tz) + (ux * ty - uy * tx));
+            blk[(i * J + j) * S] = q[0] + ((v[0] + w * tx) + (uy * tz - uz * ty));
+            blk[(i * J + j) * S + 1] = q[1] + ((v[1] + w * ty) + (uz * tx - ux * tz));
+            blk[(i * J + j) * S + 2] = q[2] + ((v[2] + w * tz) + (ux * ty - uy * tx));
         }
     } else {
         // planar chain: link angle Phi_m accumulates q_0..q_m; joint
@@ -145,8 +145,8 @@ void place_spheres(const rgg_robot *r, const double *q, double *blk, int64_t P, 
         }
         for (int i = 0; i < B; ++i) {
             int k = r->sphere_link[i];
-            blk[i * J + j] = jx[k] + r->sphere_pos[i] * cs[k];
-            blk[P + i * J + j] = jy[k] + r->sphere_pos[i] * sn[k];
+            blk[(i * J + j) * S] = jx[k] + r->sphere_pos[i] * cs[k];
+            blk[(i * J + j) * S + 1] = jy[k] + r->sphere_pos[i] * sn[k];
         }
     }
 }
@@ -324,12 +324,13 @@ rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *r, const 
     });
     for (int64_t k = 0; k < E; ++k) g->soff[k + 1] += g->soff[k];
     const int64_t total = g->soff[E];
-    if (total > ((int64_t)1 << 40) / D) {
+    const int S = copy_stride(D);
+    if (total > ((int64_t)1 << 40) / S) {
         *err = "too many sphere samples (resolution too fine)";
         return RGG_E_OUT_OF_MEMORY;
     }
     try {
-        g->samp.assign((size_t)(total * D), 0.0);
+        g->samp.assign((size_t)(total * S), 0.0);
         g->cap.assign((size_t)(E * (2 * D + 1) * B), 0.0);
         g->aabb.assign((size_t)(E * kAabbStride), 0.0f);
     } catch (const std::bad_alloc &) {
@@ -346,10 +347,10 @@ rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *r, const 
             make_motion(r, rd->q + rd->edge_uv[2 * e] * dof, rd->q + rd->edge_uv[2 * e + 1] * dof, &m);
             const int64_t P = g->soff[k + 1] - g->soff[k];
             const int64_t J = P / B, nseg = J - 1;
-            double *blk = g->samp.data() + D * g->soff[k];
+            double *blk = g->samp.data() + S * g->soff[k];
             for (int64_t j = 0; j <= nseg; ++j) {
                 config_at(r, m, (double)j / (double)nseg, q);
-                place_spheres(r, q, blk, P, J, j);
+                place_spheres(r, q, blk, S, J, j);
             }
             inflation(r, m, infl);
             double *cp = g->cap.data() + k * (2 * D + 1) * B;
@@ -358,7 +359,7 @@ rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *r, const 
                 const double R = r->sphere_radius[i] + infl[i];
                 cp[2 * D * B + i] = R;
                 for (int d = 0; d < D; ++d) {
-                    const double s = blk[d * P + i * J], t = blk[d * P + i * J + nseg];
+                    const double s = blk[(i * J) * S + d], t = blk[(i * J + nseg) * S + d];
                     cp[d * B + i] = s;
                     cp[(D + d) * B + i] = t;
                     lo[d] = std::min(lo[d], std::min(s, t) - R);

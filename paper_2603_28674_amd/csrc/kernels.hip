@@ -559,6 +559,37 @@ __device__ inline int32_t clamp_cell(double x, double org, double inv, int32_t n
 }
 
 // ------------------------------------------------------------------------
+// sphere samples: per edge a [B][J][S] block at S * soff[e], S values per copy
+// (xyz + pad in 3-D, xy in 2-D), so one copy is one aligned vector load
+// ------------------------------------------------------------------------
+
+template <int D>
+__host__ __device__ constexpr int copy_stride()
+{
+    return D == 3 ? kCopyStride3 : kCopyStride2;
+}
+
+// copy `idx` (= soff[e] + sphere * J + configuration) of the sample array
+template <int D, typename T>
+__device__ inline void load_copy(const T *samp, int64_t idx, T (&q)[D])
+{
+    const T *p = samp + copy_stride<D>() * idx;
+    if constexpr (std::is_same<T, float>::value && D == 3) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        q[0] = v.x;
+        q[1] = v.y;
+        q[2] = v.z;
+    } else if constexpr (std::is_same<T, float>::value && D == 2) {
+        const float2 v = *reinterpret_cast<const float2 *>(p);
+        q[0] = v.x;
+        q[1] = v.y;
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) q[k] = p[k];
+    }
+}
+
+// ------------------------------------------------------------------------
 // binary64 re-test of one (edge, box) pair by one wavefront: the definition
 // (C = some capsule meets, S = some sphere's capsule and one of its copies
 // meet), used for the pairs whose binary32 decision fell inside the band
@@ -597,7 +628,7 @@ __device__ bool copies_meet64(const RmDev &rm, const double *sb, int64_t P, cons
                 const int i = lst[sp0 + cm.sub];
                 double p[D];
 #pragma unroll
-                for (int k = 0; k < D; ++k) p[k] = sb[k * P + (int64_t)i * cm.J + js];
+                for (int k = 0; k < D; ++k) p[k] = sb[((int64_t)i * cm.J + js) * copy_stride<D>() + k];
                 const double r = rad[i];
                 hit = point_box64<D>(p, lo, hi) <= r * r;
             }
@@ -1123,11 +1154,8 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                         const int Je = L.ej[te];
                         // the configuration nearest the deepest capsule's closest point
                         const int jj = min(Je - 1, (int)((float)((key >> 6) & 1023u) * (1.0f / 1023.0f) * (float)(Je - 1) + 0.5f));
-                        const int64_t P = (int64_t)Je * B;
-                        const T *sb = samp + D * L.es0[te] + (int64_t)i * Je + jj;
                         T q[D], lo[D], hi[D];
-#pragma unroll
-                        for (int k = 0; k < D; ++k) q[k] = sb[k * P];
+                        load_copy<D>(samp, L.es0[te] + (int64_t)i * Je + jj, q);
 #pragma unroll
                         for (int k = 0; k < D; ++k) {
                             lo[k] = box_lo(k, s);
@@ -1214,10 +1242,7 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                                 const int i = (int)(rv & 63u);
                                 const int te = L.pe[pp] >> 8;
                                 const int Je = L.ej[te];
-                                const int64_t P = (int64_t)Je * B;
-                                const T *sb = samp + D * L.es0[te] + (int64_t)i * Je + jj;
-#pragma unroll
-                                for (int k = 0; k < D; ++k) q[u][k] = sb[k * P];
+                                load_copy<D>(samp, L.es0[te] + (int64_t)i * Je + jj, q[u]);
                                 cu_p[u] = pp;
                                 cu_i[u] = i;
                             }
@@ -1404,7 +1429,7 @@ __device__ __forceinline__ void retest_pairs(const RmDev &rm, int b, int G)
         const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
         const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
         const CopyMap cm = copy_map((int)(P / B));
-        const bool S = copies_meet64<D>(rm, rm.samp64 + D * s0, P, cm, hm, lo, hi, s_rad, s_lst[wv], &bytes);
+        const bool S = copies_meet64<D>(rm, rm.samp64 + copy_stride<D>() * s0, P, cm, hm, lo, hi, s_rad, s_lst[wv], &bytes);
         ++n_outer;
         if (lane == 0) add_counts(rm, e, en.sign, S ? en.sign : 0);
     }

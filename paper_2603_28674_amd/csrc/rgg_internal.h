@@ -19,15 +19,18 @@ constexpr int kAabbStride = 8;      // floats per edge box: lo[3], s, hi[3], pad
 //
 // Sphere samples of edge e occupy [soff[e], soff[e+1]) in "sphere-sample"
 // units, P_e = soff[e+1] - soff[e] = B * J_e for J_e configurations.  The
-// coordinates are stored per edge as a [D][B][J_e] block starting at
-// float/double index D*soff[e]: the copies of one sphere along the edge are
-// contiguous, so the copies of the spheres whose capsule met a box are read
-// with coalesced loads and the others are never touched.
+// coordinates are stored per edge as a [B][J_e][S] block starting at index
+// S*soff[e], S = copy_stride(D) (xyz and one pad value in 3-D, xy in 2-D):
+// one copy is one aligned 16- or 8-byte load, the copies of one sphere along
+// the edge are contiguous, and the spheres whose capsule missed are never
+// read.
+inline int copy_stride(int D) { return D == 3 ? 4 : 2; }
+
 struct HostGeometry {
     int kind = 0, D = 0, B = 0;
     int64_t E = 0;
     std::vector<int64_t> soff;     // [E+1]
-    std::vector<double> samp;      // [sum_e D*P_e]
+    std::vector<double> samp;      // [sum_e S*P_e], S = copy_stride(D)
     std::vector<double> cap;       // [E][2D+1][B]: A_0..A_{D-1}, B_0..B_{D-1}, R
     std::vector<float> aabb;       // [E][8]: padded FP32 box lo[3], s, hi[3], 0
     std::vector<double> radius;    // [B]
