@@ -40,7 +40,8 @@ def parse():
     p.add_argument("--nodes", type=int, default=50000)
     p.add_argument("--cell-size", type=float, default=-1.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-edges", type=int, default=30000)
+    p.add_argument("--cpu-sample-edges", type=int, default=300000,
+                   help="edges the oracle classifies (capped at the roadmap size)")
     p.add_argument("--skip-graph", action="store_true")
     p.add_argument("--seed", type=int, default=2)
     p.add_argument("--no-batched", action="store_true",
@@ -50,6 +51,8 @@ def parse():
     p.add_argument("--no-serving", action="store_true",
                    help="skip the serving measurement (16 resident roadmaps, Poisson requests)")
     p.add_argument("--serving-seconds", type=float, default=2.0)
+    p.add_argument("--no-other-configs", action="store_true",
+                   help="skip the planar (FP64 and FP32) and arm measurements")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 1 GiB device copy 5 times (reference kernel for "
                         "scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -175,6 +178,74 @@ def batched_planar(a):
     }
 
 
+def plain_config(ctx, w, precision, cell_size, K, W, what):
+    """A further workload on the plain per-update path (rgg_update_async on
+    one stream): pipelined throughput over K updates, then the latency of K
+    more, one at a time.  ``w`` must hold at least 1 + W + 2K updates."""
+    import torch
+    from paper_2603_28674_amd import rgg
+    dev = torch.device("cuda:0")
+    g = rgg.Roadmap.from_workload(ctx, w, precision=precision, cell_size=cell_size)
+    info = g.info()
+    E = w.n_edges
+    states = torch.from_numpy(np.stack([w.absent()] + w.boxes)).to(dev)
+    labels = torch.zeros(E, dtype=torch.uint8, device=dev)
+    gray = torch.zeros(E, dtype=torch.int64, device=dev)
+    res = torch.zeros((len(w.boxes), rgg.RESULT_BYTES), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def upd(u):
+        g.update_async(stream, states[u], states[u + 1], labels, gray, res[u])
+
+    for u in range(1 + W):
+        upd(u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for u in range(1 + W, 1 + W + K):
+        upd(u)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = []
+    for u in range(1 + W + K, 1 + W + 2 * K):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        upd(u)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e6)
+    results = [rgg.result_from_tensor(res[u]) for u in range(1 + W, 1 + W + 2 * K)]
+    g.close()
+    stats = {k: float(np.mean([getattr(r, k) for r in results]))
+             for k in ("n_changed", "n_pairs", "n_outer_hits", "n_rechecked", "n_gray")}
+    return {"workload": what, "edges": E, "obstacle_slots": w.n_slots,
+            "precision": "fp64" if precision == rgg.RGG_PREC_FP64 else "fp32+fp64 re-test",
+            "cell_size": info["cell_size"], "updates": K,
+            "edges_per_s": E * K / wall, "ms_per_update": wall / K * 1e3,
+            "latency_p50_us": float(np.percentile(lat, 50)),
+            "latency_p99_us": float(np.percentile(lat, 99)),
+            "per_update": stats, "status_ok": all(r.status == 0 for r in results)}
+
+
+def other_configs(a):
+    """The planar rigid-body roadmap (FP64, and FP32 + re-test beside it) and
+    the planar arm, each on the plain path."""
+    from paper_2603_28674_amd import rgg, synth
+    K, W = a.steps, a.warmup
+    ctx = rgg.rgg_context_create(0)
+    out = {}
+    w = synth.planar_rigid(n_updates=1 + W + 2 * K)
+    what = ("planar rigid-body roadmap (4 disks, 2000 nodes, k=10, configurations every 0.05, "
+            "50 boxes, 5 moved per update)")
+    out["planar_fp64"] = plain_config(ctx, w, rgg.RGG_PREC_FP64, 0.0, K, W, what)
+    out["planar_fp32"] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, 0.0, K, W, what)
+    log("[bench] arm workload")
+    w = synth.planar_arm(n_updates=1 + W + 2 * K)
+    what = ("planar 7-link arm (3 spheres per link, 100k nodes, k=8, 20 configurations/edge, "
+            "300 boxes, 30 moved per update)")
+    out["arm_fp32"] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, 0.0, K, W, what)
+    rgg.rgg_context_destroy(ctx)
+    return out
+
+
 def serving(a):
     """The serving configuration: 16 device-resident roadmaps (8 spatial
     rigid-body, 8 planar arm; edge counts log-uniform in [1e4, 5e5]) behind
@@ -289,7 +360,7 @@ def main():
     from paper_2603_28674_amd import rgg, synth
 
     K, W = a.steps, a.warmup
-    n_updates = W + 3 * K
+    n_updates = W + 4 * K
     log(f"[bench] generating spatial workload: {a.nodes} nodes, {n_updates} updates")
     w = synth.spatial_rigid(seed=a.seed, n_nodes=a.nodes, n_updates=n_updates)
     E, M = w.n_edges, w.n_slots
@@ -347,8 +418,24 @@ def main():
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e6)
     lat = np.array(lat)
+
+    # pass 3b: the same, with the caches cold: a 1 GiB buffer is rewritten
+    # before each update (more than the 256 MB Infinity Cache and the L2s)
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    lat_cold = []
+    for u in range(first + 3 * K, first + 4 * K):
+        flush.fill_(float(u))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        upd(u)
+        torch.cuda.synchronize()
+        lat_cold.append((time.perf_counter() - t1) * 1e6)
+    del flush
+    lat_cold = np.array(lat_cold)
+    results += [rgg.result_from_tensor(res[u]) for u in range(first + 2 * K, first + 4 * K)]
+    assert all(r.status == 0 for r in results), "update failed"
     final_labels = labels.cpu().numpy()
-    last = first + 3 * K - 1
+    last = first + 4 * K - 1
 
     # pass 4: the same kind of updates as HIP graphs (one graph per update,
     # instantiated before timing), replaying the sequence from the start
@@ -377,7 +464,7 @@ def main():
             rgg.rgg_graph_destroy(h)
         g2.close()
 
-    test_bytes = np.mean([r.test_bytes for r in results])
+    test_bytes = np.mean([r.test_bytes for r in results[K:2 * K]])   # the event-timed updates
     test_ms = ms[3] / max(n_timed, 1)
     achieved = test_bytes / (test_ms * 1e-3) / 1e9
     stats = {k: float(np.mean([getattr(r, k) for r in results]))
@@ -404,6 +491,8 @@ def main():
         "latency_p50_us": float(np.percentile(lat, 50)),
         "latency_p99_us": float(np.percentile(lat, 99)),
         "latency_mean_us": float(lat.mean()),
+        "latency_cold_p50_us": float(np.percentile(lat_cold, 50)),
+        "latency_cold_p99_us": float(np.percentile(lat_cold, 99)),
         "graph": graph,
         "stage_ms_per_update": {"diff": ms[0] / n_timed, "cells": ms[1] / n_timed,
                                 "classify": ms[3] / n_timed, "fp64_pass": ms[4] / n_timed,
@@ -419,6 +508,9 @@ def main():
         log("[bench] cpu baseline (oracle on a sample)")
         line["cpu_baseline"] = cpu_baseline(w, final_labels, a.cpu_sample_edges, last, a.seed)
     g.close()
+    if not a.no_other_configs:
+        log("[bench] planar and arm workloads")
+        line["other_workloads"] = other_configs(a)
     if not a.no_batched:
         log("[bench] batched planar roadmaps")
         line["batched_planar"] = batched_planar(a)
