@@ -51,6 +51,8 @@ def parse():
     p.add_argument("--no-serving", action="store_true",
                    help="skip the serving measurement (16 resident roadmaps, Poisson requests)")
     p.add_argument("--serving-seconds", type=float, default=2.0)
+    p.add_argument("--no-tune", action="store_true",
+                   help="keep the built work decomposition instead of running the autotuner")
     p.add_argument("--no-other-configs", action="store_true",
                    help="skip the planar (FP64 and FP32) and arm measurements")
     p.add_argument("--copy-calibration", action="store_true",
@@ -93,7 +95,7 @@ def batched_planar(a):
     import torch
     from paper_2603_28674_amd import rgg, synth
     K, W = a.batched_steps, 2
-    n_rounds = W + 4 * K
+    n_rounds = W + 5 * K
     t0 = time.perf_counter()
     ws = synth.batch_of_planar(seed=3, n_updates=n_rounds)
     log(f"[bench] batched: generated {len(ws)} roadmaps, {sum(w.n_edges for w in ws)} edges "
@@ -134,13 +136,7 @@ def batched_planar(a):
     def batched_graph(u):
         rgg.lib().rgg_batch_launch_graph(batch, arrs[u], C_void(stream))
 
-    u = 0
-    for _ in range(W):
-        batched(u)
-        u += 1
-    torch.cuda.synchronize()
-    out = {}
-    for name, fn in (("plain", plain), ("batched", batched), ("batched_graph", batched_graph)):
+    def timed(fn, u):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         host = 0.0
@@ -151,8 +147,32 @@ def batched_planar(a):
             u += 1
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        out[name] = {"edges_per_s": E_tot * K / wall, "ms_per_round": wall / K * 1e3,
-                     "host_ms_per_round": host / K * 1e3}
+        return {"edges_per_s": E_tot * K / wall, "ms_per_round": wall / K * 1e3,
+                "host_ms_per_round": host / K * 1e3}, u
+
+    u = 0
+    for _ in range(W):
+        batched(u)
+        u += 1
+    torch.cuda.synchronize()
+    out = {}
+    # the built (heuristic) work decomposition, then the autotuned one
+    out["batched_heuristic"], u = timed(batched, u)
+    tuned = None
+    if not a.no_tune:
+        # one decomposition for the whole batch, timed on batched updates;
+        # the state after rounds 0..u-1 is boxes[u-1], round u moves it to boxes[u]
+        t0 = time.perf_counter()
+        rep = rgg.rgg_batch_tune(batch, [w.boxes[u - 1] for w in ws], [w.boxes[u] for w in ws], reps=3)
+        tuned = {"seconds": time.perf_counter() - t0, "item_edges": rep["item_edges"],
+                 "cell_factor": None if not np.isfinite(rep["cell_size"]) else rep["cell_size"],
+                 "us_per_round": rep["us_per_update"], "us_before": rep["us_before"],
+                 "candidates": [{"item_edges": c["item_edges"],
+                                 "cell_factor": None if not np.isfinite(c["cell_size"]) else c["cell_size"],
+                                 "us": c["us"]} for c in rep["candidates"]]}
+        log(f"[bench] batched: tuned in {tuned['seconds']:.1f}s")
+    for name, fn in (("plain", plain), ("batched", batched), ("batched_graph", batched_graph)):
+        out[name], u = timed(fn, u)
     lat = []
     for _ in range(K):
         torch.cuda.synchronize()
@@ -170,6 +190,7 @@ def batched_planar(a):
         "workload": "64 planar rigid-body roadmaps (4 disks; nodes log-uniform in [1e3, 1e5], k=8, "
                     "U{20..400} boxes, each update moves U{1..20}), FP32 + FP64 re-test",
         "roadmaps": len(ws), "edges": E_tot, "rounds": K, "cell_size": a.batched_cell_size,
+        "autotune": tuned, "batched_heuristic": out["batched_heuristic"],
         "plain": out["plain"], "batched": out["batched"], "batched_graph": out["batched_graph"],
         "speedup_batched_vs_plain": out["batched"]["edges_per_s"] / out["plain"]["edges_per_s"],
         "batched_round_latency_p50_us": float(np.percentile(lat, 50)),
@@ -178,7 +199,7 @@ def batched_planar(a):
     }
 
 
-def plain_config(ctx, w, precision, cell_size, K, W, what):
+def plain_config(ctx, w, precision, cell_size, K, W, what, do_tune=True):
     """A further workload on the plain per-update path (rgg_update_async on
     one stream): pipelined throughput over K updates, then the latency of K
     more, one at a time.  ``w`` must hold at least 1 + W + 2K updates."""
@@ -197,7 +218,11 @@ def plain_config(ctx, w, precision, cell_size, K, W, what):
     def upd(u):
         g.update_async(stream, states[u], states[u + 1], labels, gray, res[u])
 
-    for u in range(1 + W):
+    upd(0)
+    torch.cuda.synchronize()
+    tuned = tune(g, w.boxes[0], w.boxes[1:9]) if do_tune else None
+    info = g.info()
+    for u in range(1, 1 + W):
         upd(u)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -218,7 +243,8 @@ def plain_config(ctx, w, precision, cell_size, K, W, what):
              for k in ("n_changed", "n_pairs", "n_outer_hits", "n_rechecked", "n_gray")}
     return {"workload": what, "edges": E, "obstacle_slots": w.n_slots,
             "precision": "fp64" if precision == rgg.RGG_PREC_FP64 else "fp32+fp64 re-test",
-            "cell_size": info["cell_size"], "updates": K,
+            "cell_size": info["cell_size"], "item_edges": info["item_edges"], "autotune": tuned,
+            "updates": K,
             "edges_per_s": E * K / wall, "ms_per_update": wall / K * 1e3,
             "latency_p50_us": float(np.percentile(lat, 50)),
             "latency_p99_us": float(np.percentile(lat, 99)),
@@ -235,13 +261,14 @@ def other_configs(a):
     w = synth.planar_rigid(n_updates=1 + W + 2 * K)
     what = ("planar rigid-body roadmap (4 disks, 2000 nodes, k=10, configurations every 0.05, "
             "50 boxes, 5 moved per update)")
-    out["planar_fp64"] = plain_config(ctx, w, rgg.RGG_PREC_FP64, 0.0, K, W, what)
-    out["planar_fp32"] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, 0.0, K, W, what)
+    t = not a.no_tune
+    out["planar_fp64"] = plain_config(ctx, w, rgg.RGG_PREC_FP64, 0.0, K, W, what, t)
+    out["planar_fp32"] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, 0.0, K, W, what, t)
     log("[bench] arm workload")
     w = synth.planar_arm(n_updates=1 + W + 2 * K)
     what = ("planar 7-link arm (3 spheres per link, 100k nodes, k=8, 20 configurations/edge, "
             "300 boxes, 30 moved per update)")
-    out["arm_fp32"] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, 0.0, K, W, what)
+    out["arm_fp32"] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, 0.0, K, W, what, t)
     rgg.rgg_context_destroy(ctx)
     return out
 
@@ -268,6 +295,21 @@ def serving(a):
     grays = [torch.zeros(w.n_edges, dtype=torch.int64, device=dev) for w in ws]
     for g, w in zip(gs, ws):
         g.update(w.absent(), w.boxes[0], want_labels=False)
+    tuned = None
+    if not a.no_tune:
+        # each roadmap tuned on four moves of 25 boxes (the middle of the
+        # requests' 1..50), before the server holds it
+        t0 = time.perf_counter()
+        trng = np.random.default_rng(a.seed + 78)
+        chosen = []
+        for g, w in zip(gs, ws):
+            sigma = 0.3 if w.robot.kind == synth.SE3 else 2.0
+            bs = [synth.move_sequence(trng, w.boxes[0], w.robot.dim, 1, 25, sigma)[1] for _ in range(4)]
+            chosen.append(tune(g, w.boxes[0], bs, reps=2))
+        tuned = {"seconds": time.perf_counter() - t0,
+                 "item_edges": {str(v): sum(r["item_edges"] == v for r in chosen) for v in (64, 128, 256)},
+                 "one_cell": sum(r["cell_size"] is None for r in chosen)}
+        log(f"[bench] serving: tuned in {tuned['seconds']:.1f}s")
     srv = rgg.rgg_server_start(ctx, n_streams=4, max_batch=64, pool_bytes=64 << 20)
     rng = np.random.default_rng(a.seed + 77)
     cur = [w.boxes[0] for w in ws]
@@ -312,8 +354,24 @@ def serving(a):
     return {"workload": "16 resident roadmaps: 8 spatial rigid-body + 8 planar-arm, edges log-uniform in "
                         "[1e4, 5e5]; Poisson requests moving U{1..50} boxes; FP32 + FP64 re-test",
             "roadmaps": len(ws), "edges": int(sum(w.n_edges for w in ws)), "seconds_per_rate": a.serving_seconds,
+            "autotune": tuned,
             "server": {"n_streams": 4, "max_batch": 64, "pool_bytes": 64 << 20}, "rates": levels,
             "status_ok": bool(ok)}
+
+
+def tune(g, a_boxes, b_states, reps=2, full=False):
+    """Runs the library's autotuner on the updates a -> b -> a for every b of
+    ``b_states`` (a is the roadmap's current state); returns a short summary
+    (every candidate when ``full``)."""
+    rep = g.tune(a_boxes, b_states, reps=reps)
+    out = {"item_edges": rep["item_edges"],
+           "cell_size": None if not np.isfinite(rep["cell_size"]) else rep["cell_size"],
+           "us_per_update": rep["us_per_update"], "us_before": rep["us_before"]}
+    if full:
+        out["candidates"] = [{"item_edges": c["item_edges"],
+                              "cell_size": None if not np.isfinite(c["cell_size"]) else c["cell_size"],
+                              "us": c["us"]} for c in rep["candidates"]]
+    return out
 
 
 def C_void(x):
@@ -382,6 +440,12 @@ def main():
         g.update_async(stream, states[u], states[u + 1], labels, gray, res[u])
 
     upd(0)        # first obstacle set (untimed)
+    torch.cuda.synchronize()
+    tuned = None
+    if not a.no_tune:
+        log("[bench] autotuning the work decomposition")
+        tuned = tune(g, w.boxes[0], w.boxes[1:9], full=True)
+        info = g.info()
     for u in range(1, 1 + W):
         upd(u)
     torch.cuda.synchronize()
@@ -441,8 +505,9 @@ def main():
     # instantiated before timing), replaying the sequence from the start
     graph = None
     if not a.skip_graph:
+        cell2 = info["cell_size"] if np.isfinite(info["cell_size"]) else -1.0
         g2 = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK,
-                                       cell_size=a.cell_size)
+                                       cell_size=cell2, item_edges=info["item_edges"])
         lab2 = torch.zeros(E, dtype=torch.uint8, device=dev)
         gray2 = torch.zeros(E, dtype=torch.int64, device=dev)
         res2 = torch.zeros((n_updates + 2, rgg.RESULT_BYTES), dtype=torch.uint8, device=dev)
@@ -487,7 +552,8 @@ def main():
                                "configurations/edge, 500 boxes, 50 moved per update), "
                                "FP32 tests + FP64 re-test inside a 1e-5 relative margin band",
                    "nodes": a.nodes, "edges": E, "obstacle_slots": M, "mode": "plain stream",
-                   "cell_size": info["cell_size"], "grid_cells": info["grid_cells"]},
+                   "cell_size": info["cell_size"], "grid_cells": info["grid_cells"],
+                   "item_edges": info["item_edges"], "autotune": tuned},
         "latency_p50_us": float(np.percentile(lat, 50)),
         "latency_p99_us": float(np.percentile(lat, 99)),
         "latency_mean_us": float(lat.mean()),

@@ -130,6 +130,10 @@ typedef struct {
                                      to the binary64 pass instead; 0 = 1024,
                                      at most 2^20.  Any value gives the same
                                      labels.                                    */
+    int32_t item_edges;           /* edges per work item of the classify
+                                     kernels (one block each), 1..256; 0 = 256.
+                                     rgg_tune may change it.  Any value gives
+                                     the same labels.                           */
 } rgg_build_opts;
 
 /* Written by the device at the end of every update (rgg_update_async) and
@@ -159,6 +163,7 @@ typedef struct {
     int64_t grid_entries;         /* (cell, edge) registrations                 */
     int64_t device_bytes;         /* device memory held by the roadmap          */
     double build_seconds;
+    int32_t item_edges;           /* edges per work item                         */
 } rgg_roadmap_info;
 
 typedef struct rgg_context rgg_context;
@@ -257,6 +262,64 @@ rgg_status rgg_batch_destroy(rgg_batch *b);
 /* One batched update of n distinct roadmaps (create, launch, wait, destroy):
  * the convenience form of the three calls above.  Blocks until done. */
 rgg_status rgg_update_batch(rgg_context *ctx, int32_t n, const rgg_update_req *reqs, void *stream);
+
+/* Autotuner of the work decomposition (Sec. 3.3 sizes grid cells by what
+ * one kernel can process; here the choice is made by measurement).  The
+ * candidates are the roadmap's current configuration and every combination
+ * of work-item size (256, 128 or 64 edges per item, one block each) and grid
+ * cell size (one cell covering the roadmap, or 1, 2, 4 or 8 times the mean
+ * edge extent).  For each, the grid is rebuilt on the device and the updates
+ * a -> b_i -> a for i = 0..n_b-1 are run `reps` times (0 selects 5) after one
+ * untimed pass, timed with HIP events on the roadmap's own stream; the
+ * fastest configuration is kept (the current one unless another is at least
+ * 3% faster).  Labels never depend on the choice: every candidate must
+ * reproduce the first candidate's gray counts, otherwise RGG_E_DEVICE.
+ *
+ * obstacles_a (m slots) must equal the resident obstacle slots, so the
+ * roadmap's state is the same before and after (its counters return to their
+ * values after each round trip); obstacles_b holds n_b (1..64) representative
+ * next obstacle sets of m slots each, one after the other.  Host arrays.  The
+ * call blocks.  It is refused with RGG_E_BUSY while a graph, a batch or a
+ * server request holds the roadmap (their kernels hold its grid arrays);
+ * RGG_E_STATE_MISMATCH if obstacles_a is not the resident state (nothing
+ * changes); RGG_E_INVALID_ARG for bad arguments or a state b_i with an
+ * invalid box; RGG_E_OUT_OF_MEMORY when a candidate grid does not fit.  After
+ * an error the roadmap's state and labels are unchanged, its grid may be any
+ * of the candidates.  *report (may be null) receives the choice and every
+ * candidate's mean time per update. */
+#define RGG_TUNE_MAX_CANDIDATES 16
+typedef struct {
+    int32_t n_candidates;
+    int32_t item_edges;                               /* chosen                         */
+    double cell_size;                                 /* chosen; +inf = one cell.
+                                                         rgg_batch_tune: the factor of
+                                                         each roadmap's mean edge extent */
+    int64_t grid_cells[3];                            /* rgg_tune only                  */
+    double us_per_update;                             /* chosen configuration           */
+    double us_before;                                 /* the configuration before tuning */
+    int32_t cand_item_edges[RGG_TUNE_MAX_CANDIDATES]; /* candidate 0 = before tuning
+                                                         (rgg_batch_tune: 0, each
+                                                         roadmap's own)                 */
+    double cand_cell_size[RGG_TUNE_MAX_CANDIDATES];   /* +inf = one cell; rgg_batch_tune:
+                                                         factor (0 = each roadmap's own) */
+    double cand_us[RGG_TUNE_MAX_CANDIDATES];
+} rgg_tune_report;
+rgg_status rgg_tune(rgg_roadmap *rm, int64_t m, const rgg_box *obstacles_a, int32_t n_b,
+                    const rgg_box *obstacles_b, int32_t reps, rgg_tune_report *report);
+
+/* The autotuner for a batch: one work decomposition for all of the batch's
+ * roadmaps (the same candidates as rgg_tune, the cell size as a factor of
+ * each roadmap's own mean edge extent), timed on whole batched updates (the
+ * batch's stage kernels over every roadmap, as rgg_batch_launch runs them):
+ * roadmap k (in the batch's order) goes from obstacles_a[k] to
+ * obstacles_b[k] and back, both host arrays of its own slot count, and
+ * obstacles_a[k] must be its resident state.  us_per_update is the time of
+ * one batched update.  The batch's previous launches are waited for; the
+ * captured graph is rebuilt for the chosen decomposition.  RGG_E_BUSY if
+ * another graph, batch or server request also holds one of the roadmaps.
+ * Other errors as for rgg_tune. */
+rgg_status rgg_batch_tune(rgg_batch *b, const rgg_box *const *obstacles_a, const rgg_box *const *obstacles_b,
+                          int32_t reps, rgg_tune_report *report);
 
 /* Request server (continuous batching).  A worker thread takes the queued
  * updates of device-resident roadmaps to the GPU as batches (one launch per

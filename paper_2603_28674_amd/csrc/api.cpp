@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <array>
 #include <chrono>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -57,7 +58,258 @@ int host_threads(int requested)
     return (int)std::max(1u, std::min(n, 16u));
 }
 
-constexpr int32_t kChunk = 256;   // edges per grid work item
+constexpr int32_t kChunk = 256;   // edges per grid work item by default (one per thread)
+
+// Puts `grid` (built for work items of `chunk` edges) in place of the
+// roadmap's current grid, if any.  The new arrays are allocated first, so a
+// failure leaves the old grid in use.  The caller makes sure no queued work
+// still reads the old arrays.
+rgg_status install_grid(rgg_roadmap *rm, const HostGrid &grid, int32_t chunk)
+{
+    RmDev &dv = rm->dv;
+    const int64_t ncells = (int64_t)grid.dim[0] * grid.dim[1] * grid.dim[2];
+    const size_t ncw = (size_t)((ncells + 31) / 32);
+    const int32_t df_cap = (int32_t)((grid.items_cap + kStatBlocks - 1) / kStatBlocks);
+    int32_t *cstart = nullptr, *cedges = nullptr, *df = nullptr;
+    uint32_t *bits = nullptr;
+    int2 *items = nullptr;
+    auto undo = [&](rgg_status s) {
+        rm->release(cstart);
+        rm->release(cedges);
+        rm->release(bits);
+        rm->release(df);
+        rm->release(items);
+        return s;
+    };
+    rgg_status st;
+    if ((st = rm->upload(&cstart, grid.start.data(), grid.start.size(), "grid starts")) != RGG_OK) return undo(st);
+    if ((st = rm->upload(&cedges, grid.edges.data(), grid.edges.size(), "grid lists")) != RGG_OK) return undo(st);
+    if ((st = rm->alloc(&bits, ncw, "cell marks")) != RGG_OK) return undo(st);
+    if ((st = rm->alloc(&df, (size_t)kStatBlocks * df_cap, "deferred items")) != RGG_OK) return undo(st);
+    if (ncells == 1) {
+        // the one cell's work items never change: (0, h) for every chunk h
+        std::vector<int2> fixed((size_t)grid.items_cap);
+        for (int64_t h = 0; h < grid.items_cap; ++h) fixed[(size_t)h] = make_int2(0, (int32_t)h);
+        if ((st = rm->upload(&items, fixed.data(), fixed.size(), "grid items")) != RGG_OK) return undo(st);
+    } else if ((st = rm->alloc(&items, (size_t)grid.items_cap, "grid items")) != RGG_OK) {
+        return undo(st);
+    }
+    hipError_t e = hipMemset(bits, 0, 4 * std::max<size_t>(ncw, 1));
+    if (e != hipSuccess) return undo(hip_fail(e, "clear marks"));
+    rm->release(dv.cell_start);
+    rm->release(dv.cell_edges);
+    rm->release(dv.cell_bits);
+    rm->release(dv.df);
+    rm->release(dv.items);
+    dv.cell_start = cstart;
+    dv.cell_edges = cedges;
+    dv.cell_bits = bits;
+    dv.df = df;
+    dv.items = items;
+    dv.df_cap = df_cap;
+    dv.chunk = chunk;
+    for (int d = 0; d < 3; ++d) {
+        dv.gdim[d] = grid.dim[d];
+        dv.gorg[d] = grid.org[d];
+        dv.lg_org[d] = grid.lg_org[d];
+        dv.lg_dim[d] = grid.lg_dim[d];
+    }
+    dv.ginv = grid.inv;
+    dv.lg_inv = grid.lg_inv;
+    dv.ncells = ncells;
+    dv.items_cap = grid.items_cap;
+    rgg_roadmap_info &in = rm->info;
+    for (int d = 0; d < 3; ++d) in.grid_cells[d] = grid.dim[d];
+    in.cell_size = grid.cell;
+    in.grid_entries = (int64_t)grid.edges.size();
+    in.item_edges = chunk;
+    return RGG_OK;
+}
+
+constexpr int kTuneMaxStates = 64;
+
+// One roadmap under tuning: its edge boxes on the host (for candidate
+// grids), its configuration before tuning, and device copies of the state a
+// (the resident one) and of the states b_i it is moved to and back from.
+struct TuneSubject {
+    rgg_roadmap *rm = nullptr;
+    HostGeometry g;
+    double mean_ext = 0.0;
+    double cur_cell = -1.0;     // < 0: one cell
+    int32_t cur_chunk = 0;
+    int n_b = 0;
+    rgg_box *d_states = nullptr;            // [(1 + n_b) * M]
+    rgg_update_result *d_res = nullptr;     // [2 * n_b]
+    std::vector<int64_t> gray_ref;          // gray counts of the first candidate
+    ~TuneSubject()
+    {
+        if (d_states) (void)hipFree(d_states);
+        if (d_res) (void)hipFree(d_res);
+    }
+    // the update a -> b_i (to == true) or b_i -> a
+    UpdateArgs args(int i, bool to) const
+    {
+        const int64_t M = rm->dv.M;
+        const rgg_box *a = d_states, *bi = d_states + (size_t)(1 + i) * M;
+        return {to ? a : bi, to ? bi : a, rm->d_labels, rm->d_gray, rm->dv.E, d_res + 2 * i + (to ? 0 : 1)};
+    }
+};
+
+// Waits for the roadmap's queued work, checks that `a` is its resident state
+// (bit for bit, as an update checks it, so that the round trips end where
+// they start) and stages the states on the device.
+rgg_status tune_subject(rgg_roadmap *rm, const rgg_box *a, int n_b, const rgg_box *const *bs, TuneSubject *t)
+{
+    const int64_t M = rm->dv.M, E = rm->dv.E;
+    if (rm->wait_ev) HIP_OR_FAIL(hipEventSynchronize(rm->wait_ev), "wait for the previous update");
+    HIP_OR_FAIL(hipStreamSynchronize(rm->stream), "roadmap stream");
+    if (M > 0) {
+        std::vector<rgg_box> cur((size_t)M);
+        HIP_OR_FAIL(hipMemcpy(cur.data(), rm->dv.resident, sizeof(rgg_box) * M, hipMemcpyDeviceToHost),
+                    "read obstacle slots");
+        if (memcmp(cur.data(), a, sizeof(rgg_box) * M) != 0)
+            return fail(RGG_E_STATE_MISMATCH, "obstacles_a differs from the resident obstacle slots");
+    }
+    t->rm = rm;
+    t->n_b = n_b;
+    t->g.D = rm->dv.D;
+    t->g.E = E;
+    t->g.aabb.resize((size_t)std::max<int64_t>(E, 1) * kAabbStride);
+    if (E > 0)
+        HIP_OR_FAIL(hipMemcpy(t->g.aabb.data(), rm->dv.aabb, sizeof(float) * (size_t)E * kAabbStride,
+                              hipMemcpyDeviceToHost),
+                    "read edge boxes");
+    double ext_sum = 0.0;
+    for (int64_t e = 0; e < E; ++e) {
+        const float *b = t->g.aabb.data() + e * kAabbStride;
+        double ext = 0.0;
+        for (int d = 0; d < t->g.D; ++d) ext = std::max(ext, (double)b[4 + d] - (double)b[d]);
+        ext_sum += ext;
+    }
+    t->mean_ext = E > 0 ? ext_sum / (double)E : 0.0;
+    t->cur_cell = rm->dv.ncells == 1 ? -1.0 : rm->info.cell_size;
+    t->cur_chunk = rm->dv.chunk;
+    HIP_OR_FAIL(hipMalloc(&t->d_states, sizeof(rgg_box) * std::max<int64_t>(1, (1 + n_b) * M)), "tuning states");
+    HIP_OR_FAIL(hipMalloc(&t->d_res, sizeof(rgg_update_result) * 2 * n_b), "tuning results");
+    if (M > 0) {
+        HIP_OR_FAIL(hipMemcpy(t->d_states, a, sizeof(rgg_box) * M, hipMemcpyHostToDevice), "upload boxes");
+        for (int i = 0; i < n_b; ++i)
+            HIP_OR_FAIL(hipMemcpy(t->d_states + (size_t)(1 + i) * M, bs[i], sizeof(rgg_box) * M, hipMemcpyHostToDevice),
+                        "upload boxes");
+    }
+    return RGG_OK;
+}
+
+// A candidate work decomposition: items of `chunk` edges and grid cells of
+// `factor` times the roadmap's mean edge extent (factor < 0: one cell;
+// factor == 0: each roadmap's configuration before tuning).
+struct TuneCand {
+    double factor;
+    int32_t chunk;
+};
+
+rgg_status tune_apply(TuneSubject &t, const TuneCand &c)
+{
+    double cell = -1.0;
+    int32_t chunk = c.chunk;
+    if (c.factor == 0.0) {
+        cell = t.cur_cell;
+        chunk = t.cur_chunk;
+    } else if (c.factor > 0.0 && t.mean_ext > 0.0 && std::isfinite(c.factor * t.mean_ext)) {
+        cell = c.factor * t.mean_ext;
+    }
+    HostGrid grid;
+    std::string err;
+    rgg_status st = build_grid(t.g, cell, chunk, &grid, &err);
+    if (st != RGG_OK) return fail(st, "%s", err.c_str());
+    return install_grid(t.rm, grid, chunk);
+}
+
+// Times every candidate with `run(count)` (count round trips of `per_rt`
+// updates each) after one untimed round trip, checks that the gray counts
+// never change, and keeps the fastest (candidate 0, the configuration before
+// tuning, unless another is at least 3% faster).  `refresh` (optional) runs
+// after each change of configuration.
+template <typename Run>
+rgg_status tune_search(std::vector<TuneSubject *> &subj, hipStream_t s, int reps, int per_rt, Run &&run,
+                       bool per_batch, rgg_tune_report *report,
+                       const std::function<rgg_status()> &refresh = nullptr)
+{
+    std::vector<TuneCand> cands = {{0.0, 0}};
+    for (int32_t chunk : {256, 128, 64})
+        for (double f : {-1.0, 1.0, 2.0, 4.0, 8.0}) cands.push_back({f, chunk});
+    if ((int)cands.size() > RGG_TUNE_MAX_CANDIDATES) cands.resize(RGG_TUNE_MAX_CANDIDATES);
+    struct Ev {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Ev()
+        {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } ev;
+    HIP_OR_FAIL(hipEventCreate(&ev.e0), "hipEventCreate");
+    HIP_OR_FAIL(hipEventCreate(&ev.e1), "hipEventCreate");
+    std::vector<double> us(cands.size(), 0.0);
+    rgg_status st;
+    auto apply = [&](const TuneCand &c) -> rgg_status {
+        for (TuneSubject *t : subj)
+            if ((st = tune_apply(*t, c)) != RGG_OK) return st;
+        return refresh ? refresh() : RGG_OK;
+    };
+    for (size_t k = 0; k < cands.size(); ++k) {
+        if ((st = apply(cands[k])) != RGG_OK) return st;
+        if ((st = run(1)) != RGG_OK) return st;
+        HIP_OR_FAIL(hipEventRecord(ev.e0, s), "hipEventRecord");
+        if ((st = run(reps)) != RGG_OK) return st;
+        HIP_OR_FAIL(hipEventRecord(ev.e1, s), "hipEventRecord");
+        HIP_OR_FAIL(hipEventSynchronize(ev.e1), "tuning run");
+        float ms = 0.0f;
+        HIP_OR_FAIL(hipEventElapsedTime(&ms, ev.e0, ev.e1), "hipEventElapsedTime");
+        us[k] = 1e3 * (double)ms / ((double)reps * per_rt);
+        for (size_t j = 0; j < subj.size(); ++j) {
+            TuneSubject &t = *subj[j];
+            std::vector<rgg_update_result> r((size_t)(2 * t.n_b));
+            HIP_OR_FAIL(hipMemcpy(r.data(), t.d_res, sizeof(rgg_update_result) * r.size(), hipMemcpyDeviceToHost),
+                        "read results");
+            for (size_t i = 0; i < r.size(); ++i)
+                if (r[i].status != RGG_OK)
+                    return fail(r[i].status, "roadmap %zu: a state to tune on holds an invalid box", j);
+            if (k == 0) {
+                t.gray_ref.resize(r.size());
+                for (size_t i = 0; i < r.size(); ++i) t.gray_ref[i] = r[i].n_gray;
+            } else {
+                for (size_t i = 0; i < r.size(); ++i)
+                    if (r[i].n_gray != t.gray_ref[i])
+                        return fail(RGG_E_DEVICE, "roadmap %zu: candidate %zu changed a gray count (%lld vs %lld)", j,
+                                    k, (long long)r[i].n_gray, (long long)t.gray_ref[i]);
+            }
+        }
+    }
+    size_t best = 0;
+    for (size_t k = 1; k < cands.size(); ++k)
+        if (us[k] < us[best]) best = k;
+    if (us[best] > 0.97 * us[0]) best = 0;
+    if ((st = apply(cands[best])) != RGG_OK) return st;
+    if (report) {
+        *report = rgg_tune_report{};
+        report->n_candidates = (int32_t)cands.size();
+        const rgg_roadmap *rm0 = subj[0]->rm;
+        report->item_edges = rm0->dv.chunk;
+        report->cell_size = per_batch ? (cands[best].factor < 0 ? INFINITY : cands[best].factor) : rm0->info.cell_size;
+        for (int d = 0; d < 3; ++d) report->grid_cells[d] = per_batch ? 0 : rm0->info.grid_cells[d];
+        report->us_per_update = us[best];
+        report->us_before = us[0];
+        for (size_t k = 0; k < cands.size(); ++k) {
+            const bool cur = cands[k].factor == 0.0;
+            report->cand_item_edges[k] = cur ? (per_batch ? 0 : subj[0]->cur_chunk) : cands[k].chunk;
+            double cell = cands[k].factor < 0 ? INFINITY : cands[k].factor * (per_batch ? 1.0 : subj[0]->mean_ext);
+            if (cur) cell = per_batch ? 0.0 : (subj[0]->cur_cell < 0 ? INFINITY : subj[0]->cur_cell);
+            report->cand_cell_size[k] = cell;
+            report->cand_us[k] = us[k];
+        }
+    }
+    return RGG_OK;
+}
 
 }  // namespace
 
@@ -92,9 +344,11 @@ struct rgg_batch {
         for (int k = 0; k < kRing; ++k)
             if (done[k] && used[k]) hipEventSynchronize(done[k]);
         // the roadmaps' last updates have completed: nothing left to wait for
-        for (rgg_roadmap *rm : rms)
+        for (rgg_roadmap *rm : rms) {
             for (int k = 0; k < kRing; ++k)
                 if (rm->wait_ev == done[k]) rm->wait_ev = nullptr;
+            rm->holders--;
+        }
         for (int k = 0; k < kRing; ++k) {
             if (done[k]) hipEventDestroy(done[k]);
             if (h_tab[k]) hipHostFree(h_tab[k]);
@@ -138,8 +392,9 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     HostGeometry g;
     st = build_geometry(rd, robot, opts, 0, rd->n_edges, host_threads(opts->host_threads), &g, &err);
     if (st != RGG_OK) return fail(st, "%s", err.c_str());
+    const int32_t chunk = opts->item_edges > 0 ? opts->item_edges : kChunk;
     HostGrid grid;
-    st = build_grid(g, opts->cell_size, kChunk, &grid, &err);
+    st = build_grid(g, opts->cell_size, chunk, &grid, &err);
     if (st != RGG_OK) return fail(st, "%s", err.c_str());
 
     auto *rm = new rgg_roadmap();
@@ -152,7 +407,6 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     dv.D = D;
     dv.B = B;
     dv.mixed = mixed ? 1 : 0;
-    dv.chunk = kChunk;
     dv.E = E;
     dv.M = M;
     dv.band_rel = (float)(opts->band_rel > 0.0 ? opts->band_rel : 1e-5);
@@ -205,24 +459,7 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
         dv.samp32 = s32;
         dv.cap32 = c32;
     }
-    // grid
-    for (int d = 0; d < 3; ++d) {
-        dv.gdim[d] = grid.dim[d];
-        dv.gorg[d] = grid.org[d];
-    }
-    dv.ginv = grid.inv;
-    for (int d = 0; d < 3; ++d) {
-        dv.lg_org[d] = grid.lg_org[d];
-        dv.lg_dim[d] = grid.lg_dim[d];
-    }
-    dv.lg_inv = grid.lg_inv;
-    dv.ncells = (int64_t)grid.dim[0] * grid.dim[1] * grid.dim[2];
-    dv.items_cap = grid.items_cap;
-    int32_t *cstart, *cedges;
-    if ((st = rm->upload(&cstart, grid.start.data(), grid.start.size(), "grid starts")) != RGG_OK) return guard(st);
-    if ((st = rm->upload(&cedges, grid.edges.data(), grid.edges.size(), "grid lists")) != RGG_OK) return guard(st);
-    dv.cell_start = cstart;
-    dv.cell_edges = cedges;
+    if ((st = install_grid(rm, grid, chunk)) != RGG_OK) return guard(st);
     // state and scratch
     std::vector<rgg_box> absent((size_t)M);
     for (auto &b : absent)
@@ -230,25 +467,13 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
             b.lo[k] = 1.0;
             b.hi[k] = -1.0;
         }
-    const size_t ncw = (size_t)((dv.ncells + 31) / 32);
     if ((st = rm->alloc(&dv.cnt, (size_t)E, "counters")) != RGG_OK) return guard(st);
-    if ((st = rm->alloc(&dv.cell_bits, ncw, "cell marks")) != RGG_OK) return guard(st);
     if ((st = rm->upload(&dv.resident, absent.data(), (size_t)M, "obstacle slots")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.chg, (size_t)(2 * M), "changed entries")) != RGG_OK) return guard(st);
     dv.rc_cap = opts->retest_capacity > 0 ? opts->retest_capacity : kRcCap;
-    dv.df_cap = (int32_t)((grid.items_cap + kStatBlocks - 1) / kStatBlocks);
     if ((st = rm->alloc(&dv.rc, (size_t)kStatBlocks * dv.rc_cap, "re-test regions")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.rc_cnt, (size_t)kStatBlocks, "re-test counts")) != RGG_OK) return guard(st);
-    if ((st = rm->alloc(&dv.df, (size_t)kStatBlocks * dv.df_cap, "deferred items")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.df_cnt, (size_t)kStatBlocks, "deferred counts")) != RGG_OK) return guard(st);
-    if (dv.ncells == 1) {
-        // the one cell's work items never change: (0, chunk) for every chunk
-        std::vector<int2> items((size_t)grid.items_cap);
-        for (int64_t h = 0; h < grid.items_cap; ++h) items[(size_t)h] = make_int2(0, (int32_t)h);
-        if ((st = rm->upload(&dv.items, items.data(), items.size(), "grid items")) != RGG_OK) return guard(st);
-    } else if ((st = rm->alloc(&dv.items, (size_t)grid.items_cap, "grid items")) != RGG_OK) {
-        return guard(st);
-    }
     if ((st = rm->alloc(&dv.blk_stats, (size_t)kStatBlocks * kStats, "statistics")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.tile_cnt, (size_t)dv.ntiles + 1, "tile counts")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.ctl, 1, "control block")) != RGG_OK) return guard(st);
@@ -257,7 +482,6 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     if ((st = rm->alloc(&rm->d_labels, (size_t)E, "labels")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&rm->d_gray, (size_t)E, "gray list")) != RGG_OK) return guard(st);
     HIP_OR_FAIL(hipMemset(dv.cnt, 0, sizeof(int2) * std::max<int64_t>(E, 1)), "clear counters");
-    HIP_OR_FAIL(hipMemset(dv.cell_bits, 0, 4 * std::max<size_t>(ncw, 1)), "clear marks");
     HIP_OR_FAIL(hipMemset(dv.ctl, 0, sizeof(Ctl)), "clear control");
     HIP_OR_FAIL(hipMemset(dv.rc_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear re-test counts");
     HIP_OR_FAIL(hipMemset(dv.df_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear deferred counts");
@@ -275,9 +499,6 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     in.dim = D;
     in.n_spheres = B;
     in.n_sphere_samples = g.soff.back();
-    for (int d = 0; d < 3; ++d) in.grid_cells[d] = grid.dim[d];
-    in.cell_size = grid.cell;
-    in.grid_entries = (int64_t)grid.edges.size();
     in.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = rm;
     return RGG_OK;
@@ -504,6 +725,7 @@ rgg_status rgg_graph_create(rgg_context *ctx, int32_t n, const rgg_update_req *r
         delete g;
         return hip_fail(e, "hipGraphInstantiate");
     }
+    for (rgg_roadmap *rm : g->roadmaps) rm->holders++;   // the nodes hold its arrays
     *out = g;
     return RGG_OK;
 }
@@ -531,6 +753,7 @@ rgg_status rgg_graph_destroy(rgg_graph *g)
     hipSetDevice(g->device);
     if (g->exec) hipGraphExecDestroy(g->exec);
     if (g->graph) hipGraphDestroy(g->graph);
+    for (rgg_roadmap *rm : g->roadmaps) rm->holders--;
     delete g;
     return RGG_OK;
 }
@@ -545,13 +768,15 @@ rgg_status rgg_batch_create(rgg_context *ctx, int32_t n, rgg_roadmap *const *rms
         if (rms[k]->device != ctx->device) return fail(RGG_E_INVALID_ARG, "roadmap %d is on another device", k);
         if (seen.count(rms[k])) return fail(RGG_E_INVALID_ARG, "roadmap %d repeats roadmap %d", k, seen[rms[k]]);
         seen[rms[k]] = k;
-        if (rms[k]->dv.chunk != kChunk) return fail(RGG_E_INVALID_ARG, "roadmap %d has an unexpected chunk", k);
+        if (rms[k]->dv.chunk < 1 || rms[k]->dv.chunk > kChunk)
+            return fail(RGG_E_INVALID_ARG, "roadmap %d has work items of %d edges", k, rms[k]->dv.chunk);
     }
     HIP_OR_FAIL(hipSetDevice(ctx->device), "hipSetDevice");
     std::unique_ptr<rgg_batch> b(new rgg_batch());
     b->device = ctx->device;
     b->n = n;
     b->rms.assign(rms, rms + n);
+    for (rgg_roadmap *rm : b->rms) rm->holders++;   // released by ~rgg_batch
     // table rows grouped by kernel variant (dimension, precision)
     std::vector<BatchGroup> &groups = b->groups;
     for (int D = 2; D <= 3; ++D)
@@ -667,6 +892,129 @@ rgg_status rgg_update_batch(rgg_context *ctx, int32_t n, const rgg_update_req *r
     }
     rgg_batch_destroy(b);
     return st;
+}
+
+rgg_status rgg_tune(rgg_roadmap *rm, int64_t m, const rgg_box *obstacles_a, int32_t n_b,
+                    const rgg_box *obstacles_b, int32_t reps, rgg_tune_report *report)
+{
+    if (!rm) return fail(RGG_E_INVALID_ARG, "null roadmap");
+    const int64_t M = rm->dv.M;
+    if (m != M) return fail(RGG_E_INVALID_ARG, "m = %lld but the roadmap has %lld slots", (long long)m, (long long)M);
+    if (n_b < 1 || n_b > kTuneMaxStates) return fail(RGG_E_INVALID_ARG, "n_b = %d, allowed 1..%d", n_b, kTuneMaxStates);
+    if (M > 0 && (!obstacles_a || !obstacles_b)) return fail(RGG_E_INVALID_ARG, "null box arrays");
+    if (reps < 0 || reps > 1000) return fail(RGG_E_INVALID_ARG, "reps = %d, allowed 0..1000", reps);
+    if (reps == 0) reps = 5;
+    if (rm->holders.load() > 0)
+        return fail(RGG_E_BUSY, "the roadmap is held by a graph, a batch or a server request");
+    HIP_OR_FAIL(hipSetDevice(rm->device), "hipSetDevice");
+    std::vector<const rgg_box *> bs((size_t)n_b);
+    for (int i = 0; i < n_b; ++i) bs[(size_t)i] = obstacles_b + (size_t)i * M;
+    TuneSubject t;
+    rgg_status st = tune_subject(rm, obstacles_a, n_b, bs.data(), &t);
+    if (st != RGG_OK) return st;
+    hipStream_t s = rm->stream;
+    // every state b_i is visited from a and left back to a
+    auto run = [&](int count) -> rgg_status {
+        for (int r = 0; r < count; ++r)
+            for (int i = 0; i < n_b; ++i) {
+                HIP_OR_FAIL(launch_update(rm->dv, t.args(i, true), s, nullptr), "update launch");
+                HIP_OR_FAIL(launch_update(rm->dv, t.args(i, false), s, nullptr), "update launch");
+            }
+        return RGG_OK;
+    };
+    std::vector<TuneSubject *> subj = {&t};
+    st = tune_search(subj, s, reps, 2 * n_b, run, false, report);
+    if (st != RGG_OK) return st;
+    return finish_update(rm, s);
+}
+
+rgg_status rgg_batch_tune(rgg_batch *b, const rgg_box *const *obstacles_a, const rgg_box *const *obstacles_b,
+                          int32_t reps, rgg_tune_report *report)
+{
+    if (!b || !obstacles_a || !obstacles_b) return fail(RGG_E_INVALID_ARG, "null argument");
+    if (reps < 0 || reps > 1000) return fail(RGG_E_INVALID_ARG, "reps = %d, allowed 0..1000", reps);
+    if (reps == 0) reps = 5;
+    for (int k = 0; k < b->n; ++k) {
+        if (b->rms[k]->dv.M > 0 && (!obstacles_a[k] || !obstacles_b[k]))
+            return fail(RGG_E_INVALID_ARG, "null box arrays for roadmap %d", k);
+        if (b->rms[k]->holders.load() != 1)
+            return fail(RGG_E_BUSY, "roadmap %d is also held by another graph, batch or server request", k);
+    }
+    HIP_OR_FAIL(hipSetDevice(b->device), "hipSetDevice");
+    for (int k = 0; k < rgg_batch::kRing; ++k)
+        if (b->used[k]) HIP_OR_FAIL(hipEventSynchronize(b->done[k]), "batch launches");
+    std::vector<std::unique_ptr<TuneSubject>> subj((size_t)b->n);
+    std::vector<TuneSubject *> ptrs((size_t)b->n);
+    for (int k = 0; k < b->n; ++k) {
+        subj[(size_t)k].reset(new TuneSubject());
+        rgg_status st = tune_subject(b->rms[k], obstacles_a[k], 1, &obstacles_b[k], subj[(size_t)k].get());
+        if (st != RGG_OK) return fail(st, "roadmap %d: %s", k, rgg_last_error());
+        ptrs[(size_t)k] = subj[(size_t)k].get();
+    }
+    hipStream_t s = b->rms[0]->stream;
+    // request tables of the two directions, in the batch's row order
+    std::vector<BatchReq> fwd((size_t)b->n), back((size_t)b->n);
+    BatchReq *d_fwd = nullptr, *d_back = nullptr;
+    struct Free {
+        BatchReq **p[2];
+        ~Free()
+        {
+            for (auto q : p)
+                if (*q) (void)hipFree(*q);
+        }
+    } fr{{&d_fwd, &d_back}};
+    HIP_OR_FAIL(hipMalloc(&d_fwd, sizeof(BatchReq) * b->n), "tuning tables");
+    HIP_OR_FAIL(hipMalloc(&d_back, sizeof(BatchReq) * b->n), "tuning tables");
+    auto fill = [&]() -> rgg_status {
+        int tile = 0, wtile = 0;
+        for (int row = 0; row < b->n; ++row) {
+            const int k = b->order[row];
+            rgg_roadmap *rm = b->rms[k];
+            fwd[(size_t)row] = {rm->dv, subj[(size_t)k]->args(0, true), tile, wtile};
+            back[(size_t)row] = {rm->dv, subj[(size_t)k]->args(0, false), tile, wtile};
+            tile += rm->dv.ntiles;
+            wtile += rm->dv.ntiles + 1;
+        }
+        b->any_grid = false;
+        for (rgg_roadmap *rm : b->rms) b->any_grid = b->any_grid || rm->dv.ncells > 1;
+        HIP_OR_FAIL(hipMemcpy(d_fwd, fwd.data(), sizeof(BatchReq) * b->n, hipMemcpyHostToDevice), "tuning tables");
+        HIP_OR_FAIL(hipMemcpy(d_back, back.data(), sizeof(BatchReq) * b->n, hipMemcpyHostToDevice), "tuning tables");
+        return RGG_OK;
+    };
+    auto run = [&](int count) -> rgg_status {
+        for (int r = 0; r < count; ++r)
+            for (BatchReq *tab : {d_fwd, d_back})
+                HIP_OR_FAIL(launch_batch(s, tab, b->d_grp, b->n, b->groups.data(), (int)b->groups.size(), b->any_grid,
+                                         b->tiles, b->wtiles),
+                            "batch launch");
+        return RGG_OK;
+    };
+    rgg_status st = tune_search(ptrs, s, reps, 2, run, true, report, fill);
+    // whatever happened, the launches follow the roadmaps' grids as they now
+    // are; the captured graph's kernels depend on whether any uses a grid
+    b->any_grid = false;
+    for (rgg_roadmap *rm : b->rms) b->any_grid = b->any_grid || rm->dv.ncells > 1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t last = nullptr;
+    HIP_OR_FAIL(hipGraphCreate(&graph, 0), "hipGraphCreate");
+    hipError_t e = add_batch_nodes(graph, b->d_tab, b->d_grp, b->n, b->groups.data(), (int)b->groups.size(),
+                                   b->any_grid, b->tiles, b->wtiles, nullptr, &last);
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(graph);
+        return hip_fail(e, "batch graph");
+    }
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->graph = graph;
+    b->exec = exec;
+    if (st != RGG_OK) return st;
+    for (rgg_roadmap *rm : b->rms) {
+        st = finish_update(rm, s);
+        if (st != RGG_OK) return st;
+    }
+    return RGG_OK;
 }
 
 rgg_status rgg_debug_geometry(const rgg_roadmap_desc *rd, const rgg_robot *robot,

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -38,7 +39,10 @@ struct rgg_roadmap {
     int device = 0;
     rgg::RmDev dv = {};
     rgg_roadmap_info info = {};
-    std::vector<void *> allocs;
+    std::vector<std::pair<void *, size_t>> allocs;   // device buffers and their sizes
+    // graphs, batches and server requests that hold the roadmap's device
+    // arrays; its grid is not rebuilt while any do
+    std::atomic<int> holders{0};
     hipStream_t stream = nullptr;     // for host-buffer calls
     hipEvent_t done = nullptr;        // end of the most recent single update
     hipEvent_t wait_ev = nullptr;     // event marking the end of the most recent update
@@ -66,7 +70,7 @@ struct rgg_roadmap {
             for (auto ev : set) hipEventDestroy(ev);
         for (auto &set : pending)
             for (auto ev : set) hipEventDestroy(ev);
-        for (void *p : allocs) hipFree(p);
+        for (auto &a : allocs) hipFree(a.first);
         if (h_stage) hipHostFree(h_stage);
         if (h_res) hipHostFree(h_res);
         if (done) hipEventDestroy(done);
@@ -83,10 +87,23 @@ struct rgg_roadmap {
             (void)hipGetLastError();
             return fail(RGG_E_OUT_OF_MEMORY, "device allocation of %zu bytes for %s failed", bytes, what);
         }
-        allocs.push_back(q);
+        allocs.emplace_back(q, bytes);
         info.device_bytes += (int64_t)bytes;
         *p = (T *)q;
         return RGG_OK;
+    }
+
+    // frees a buffer obtained from alloc (null is ignored)
+    void release(const void *p)
+    {
+        if (!p) return;
+        for (size_t k = 0; k < allocs.size(); ++k)
+            if (allocs[k].first == p) {
+                (void)hipFree(allocs[k].first);
+                info.device_bytes -= (int64_t)allocs[k].second;
+                allocs.erase(allocs.begin() + (std::ptrdiff_t)k);
+                return;
+            }
     }
 
     template <typename T>

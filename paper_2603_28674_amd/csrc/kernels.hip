@@ -1820,7 +1820,7 @@ struct Args {
 
 hipError_t launch_update(const RmDev &rm, const UpdateArgs &a, hipStream_t s, hipEvent_t *ev)
 {
-    if (rm.chunk != kBlock) return hipErrorInvalidValue;   // one edge of an item per thread
+    if (rm.chunk < 1 || rm.chunk > kBlock) return hipErrorInvalidValue;   // at most one edge of an item per thread
     Node nodes[7];
     const int n = plan(rm, nodes);
     Args args(rm, a);
@@ -1849,7 +1849,7 @@ hipError_t launch_labels(const RmDev &rm, const UpdateArgs &a, hipStream_t s)
 hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, hipGraphNode_t dep,
                             hipGraphNode_t *last)
 {
-    if (rm.chunk != kBlock) return hipErrorInvalidValue;
+    if (rm.chunk < 1 || rm.chunk > kBlock) return hipErrorInvalidValue;
     Node nodes[7];
     const int n = plan(rm, nodes);
     Args args(rm, a);   // hipGraphAddKernelNode copies the argument values

@@ -118,6 +118,7 @@ struct rgg_server {
     std::string worker_error;
     std::thread worker;
     std::vector<rgg_roadmap *> seen;   // roadmaps this server has updated (worker only)
+    std::vector<rgg_roadmap *> held;   // roadmaps named by a submitted request (under mu)
 
     void run();
     bool dispatch(Slot &slot, std::vector<Pending> &batch);
@@ -389,6 +390,10 @@ rgg_status rgg_server_submit(rgg_server *srv, const rgg_server_req *req, uint64_
         if (!srv->worker_error.empty()) return fail(RGG_E_DEVICE, "server stopped: %s", srv->worker_error.c_str());
         if (srv->stopping) return fail(RGG_E_INVALID_ARG, "server is stopping");
         if ((int64_t)srv->queue.size() >= srv->opts.max_queue) return fail(RGG_E_BUSY, "server queue is full");
+        if (std::find(srv->held.begin(), srv->held.end(), rm) == srv->held.end()) {
+            srv->held.push_back(rm);
+            rm->holders++;   // until rgg_server_stop
+        }
         p.ticket = srv->next_ticket++;
         p.submitted = Clock::now();
         srv->tickets[p.ticket] = Ticket();
@@ -443,6 +448,7 @@ rgg_status rgg_server_stop(rgg_server *srv)
     for (rgg_roadmap *rm : srv->seen)
         for (Slot &sl : srv->slots)
             if (rm->wait_ev == sl.ev) rm->wait_ev = nullptr;
+    for (rgg_roadmap *rm : srv->held) rm->holders--;
     free_server(srv);
     if (!err.empty()) return fail(RGG_E_DEVICE, "server worker: %s", err.c_str());
     return RGG_OK;

@@ -57,7 +57,8 @@ class rgg_build_opts(C.Structure):
     _fields_ = [("resolution", C.c_double), ("samples_per_edge", C.c_int32),
                 ("precision", C.c_int32), ("band_rel", C.c_double),
                 ("n_obstacle_slots", C.c_int64), ("cell_size", C.c_double),
-                ("host_threads", C.c_int32), ("retest_capacity", C.c_int32)]
+                ("host_threads", C.c_int32), ("retest_capacity", C.c_int32),
+                ("item_edges", C.c_int32)]
 
 
 class rgg_update_result(C.Structure):
@@ -75,12 +76,33 @@ class rgg_roadmap_info(C.Structure):
                 ("n_spheres", C.c_int32), ("n_sphere_samples", C.c_int64),
                 ("grid_cells", C.c_int64 * 3), ("cell_size", C.c_double),
                 ("grid_entries", C.c_int64), ("device_bytes", C.c_int64),
-                ("build_seconds", C.c_double)]
+                ("build_seconds", C.c_double), ("item_edges", C.c_int32)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["grid_cells"] = list(self.grid_cells)
         return d
+
+
+TUNE_MAX_CANDIDATES = 16
+
+
+class rgg_tune_report(C.Structure):
+    _fields_ = [("n_candidates", C.c_int32), ("item_edges", C.c_int32),
+                ("cell_size", C.c_double), ("grid_cells", C.c_int64 * 3),
+                ("us_per_update", C.c_double), ("us_before", C.c_double),
+                ("cand_item_edges", C.c_int32 * TUNE_MAX_CANDIDATES),
+                ("cand_cell_size", C.c_double * TUNE_MAX_CANDIDATES),
+                ("cand_us", C.c_double * TUNE_MAX_CANDIDATES)]
+
+    def as_dict(self):
+        n = self.n_candidates
+        return {"n_candidates": n, "item_edges": self.item_edges, "cell_size": self.cell_size,
+                "grid_cells": list(self.grid_cells), "us_per_update": self.us_per_update,
+                "us_before": self.us_before,
+                "candidates": [{"item_edges": self.cand_item_edges[k],
+                                "cell_size": self.cand_cell_size[k], "us": self.cand_us[k]}
+                               for k in range(n)]}
 
 
 class rgg_update_req(C.Structure):
@@ -107,8 +129,8 @@ EXPORTS = ["rgg_context_create", "rgg_context_destroy", "rgg_build", "rgg_destro
            "rgg_graph_launch", "rgg_graph_destroy", "rgg_batch_create", "rgg_batch_launch",
            "rgg_batch_launch_graph", "rgg_batch_destroy", "rgg_update_batch", "rgg_server_start",
            "rgg_server_submit", "rgg_server_poll", "rgg_server_stop", "rgg_labels", "rgg_gray_list",
-           "rgg_timing_enable", "rgg_timing_read", "rgg_debug_geometry", "rgg_last_error",
-           "rgg_version"]
+           "rgg_timing_enable", "rgg_timing_read", "rgg_tune", "rgg_batch_tune", "rgg_debug_geometry",
+           "rgg_last_error", "rgg_version"]
 
 _lib = None
 
@@ -146,6 +168,8 @@ def lib():
         "rgg_gray_list": (I32, [P, P, I64, P]),
         "rgg_timing_enable": (I32, [P, I32]),
         "rgg_timing_read": (I32, [P, P, P]),
+        "rgg_tune": (I32, [P, I64, P, I32, P, I32, P]),
+        "rgg_batch_tune": (I32, [P, P, P, I32, P]),
         "rgg_debug_geometry": (I32, [P, P, P, I64, I64, P, P, P, P]),
         "rgg_last_error": (C.c_char_p, []),
         "rgg_version": (C.c_char_p, []),
@@ -221,7 +245,8 @@ def make_desc(q, edges, keep):
 
 
 def make_opts(resolution=0.0, samples_per_edge=0, precision=RGG_PREC_FP64, band_rel=0.0,
-              n_obstacle_slots=0, cell_size=0.0, host_threads=0, retest_capacity=0):
+              n_obstacle_slots=0, cell_size=0.0, host_threads=0, retest_capacity=0,
+              item_edges=0):
     o = rgg_build_opts()
     o.resolution = resolution
     o.samples_per_edge = samples_per_edge
@@ -231,6 +256,7 @@ def make_opts(resolution=0.0, samples_per_edge=0, precision=RGG_PREC_FP64, band_
     o.cell_size = cell_size
     o.host_threads = host_threads
     o.retest_capacity = retest_capacity
+    o.item_edges = item_edges
     return o
 
 
@@ -391,6 +417,31 @@ def rgg_timing_read(rm):
     return ms, n.value
 
 
+def rgg_tune(rm, a, bs, reps=0):
+    """Autotunes the roadmap's work decomposition on the updates a -> b -> a
+    for each b in ``bs`` (one (M, 6) array, or a list of them); ``a`` must be
+    the resident state.  Returns the report as a dict."""
+    a = boxes_array(a)
+    if isinstance(bs, np.ndarray) and bs.ndim == 2:
+        bs = [bs]
+    b = np.ascontiguousarray(np.concatenate([boxes_array(x) for x in bs]))
+    rep = rgg_tune_report()
+    _check(lib().rgg_tune(rm, a.shape[0], _ptr(a), len(bs), _ptr(b), int(reps), C.byref(rep)))
+    return rep.as_dict()
+
+
+def rgg_batch_tune(batch, a_list, b_list, reps=0):
+    """Autotunes one work decomposition for every roadmap of ``batch`` on
+    batched updates a[k] -> b[k] -> a[k] (lists in the batch's order)."""
+    a_arr = [np.ascontiguousarray(boxes_array(x)) for x in a_list]
+    b_arr = [np.ascontiguousarray(boxes_array(x)) for x in b_list]
+    pa = (C.c_void_p * len(a_arr))(*[x.ctypes.data for x in a_arr])
+    pb = (C.c_void_p * len(b_arr))(*[x.ctypes.data for x in b_arr])
+    rep = rgg_tune_report()
+    _check(lib().rgg_batch_tune(batch, pa, pb, int(reps), C.byref(rep)))
+    return rep.as_dict()
+
+
 def rgg_debug_geometry(desc, robot, opts, e0, e1):
     """Host build stage of edges [e0, e1): (n_configs, centres, capsules, boxes)."""
     L = lib()
@@ -425,13 +476,13 @@ class Roadmap:
 
     def __init__(self, ctx, robot, q, edges, n_slots, resolution=0.0, samples_per_edge=0,
                  precision=RGG_PREC_FP64, band_rel=0.0, cell_size=0.0, host_threads=0,
-                 retest_capacity=0):
+                 retest_capacity=0, item_edges=0):
         keep = _Keep()
         self._keep = keep
         self.robot = make_robot(robot, keep)
         self.desc = make_desc(q, edges, keep)
         self.opts = make_opts(resolution, samples_per_edge, precision, band_rel, n_slots,
-                              cell_size, host_threads, retest_capacity)
+                              cell_size, host_threads, retest_capacity, item_edges)
         self.h = rgg_build(ctx, self.desc, self.robot, self.opts)
         self.E = int(np.asarray(edges).shape[0])
         self.M = int(n_slots)
@@ -456,6 +507,9 @@ class Roadmap:
 
     def info(self):
         return rgg_roadmap_info_get(self.h).as_dict()
+
+    def tune(self, a, bs, reps=0):
+        return rgg_tune(self.h, a, bs, reps)
 
     def close(self):
         if getattr(self, "h", None):

@@ -48,15 +48,16 @@ def with_removals(w, rng):
 
 
 def check_sequence(ctx, w, precision, cell_size=0.0, band_rel=0.0, device_buffers=False,
-                   retest_capacity=0):
+                   retest_capacity=0, item_edges=0):
     import torch
     from paper_2603_28674_amd import rgg
     import oracle
     print(f"[parity] {w.name} E={w.n_edges} M={w.n_slots} precision={precision} "
           f"cell={cell_size} band={band_rel} device_buffers={device_buffers} "
-          f"retest_capacity={retest_capacity}", flush=True)
+          f"retest_capacity={retest_capacity} item_edges={item_edges}", flush=True)
     g = rgg.Roadmap.from_workload(ctx, w, precision=precision, cell_size=cell_size,
-                                  band_rel=band_rel, retest_capacity=retest_capacity)
+                                  band_rel=band_rel, retest_capacity=retest_capacity,
+                                  item_edges=item_edges)
     o = oracle.from_workload(w)
     prev = w.absent()
     stats = []
@@ -115,6 +116,14 @@ def test_grid_cell_size_does_not_change_labels(ctx, cell_size):
     from paper_2603_28674_amd import rgg
     w = workload("spatial", n_updates=3, seed=21)
     check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, cell_size=cell_size)
+
+
+@pytest.mark.parametrize("item_edges", [64, 128, 200])
+@pytest.mark.parametrize("cell_size", [-1.0, 0.0])
+def test_item_size_does_not_change_labels(ctx, item_edges, cell_size):
+    from paper_2603_28674_amd import rgg
+    w = with_removals(workload("spatial", seed=31), np.random.default_rng(8))
+    check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, cell_size=cell_size, item_edges=item_edges)
 
 
 def test_device_buffer_entry_point(ctx):
