@@ -3,18 +3,23 @@
 // One update = these kernels on one stream (or one graph):
 //   k_diff      validate the old/new boxes against the resident slots, list
 //               the changed (box, sign) entries in slot order, commit the
-//               slots (Alg. 1: a moved obstacle's old and new poses);
-//   k_cells     activate every grid cell a changed box overlaps and emit one
-//               work item per (cell, chunk of 256 of its edges)  (Sec. 3.3);
+//               slots (Alg. 1: a moved obstacle's old and new poses); with
+//               one grid cell it also hands out the fixed work items;
+//   k_cells     grid mode: activate every grid cell a changed box overlaps
+//               and emit one work item per (cell, chunk of its edges)
+//               (Sec. 3.3);
 //   k_item32/64 one block per work item: pairs of the item's edges with the
 //               changed boxes of the cell, outer test (per-sphere capsule vs
 //               box), inner test (copies of the spheres whose capsule met),
 //               counter update (Sec. 3.1 rule; Alg. 1's intersection lists
 //               kept as counts).  In the FP32 mode a pair whose margin falls
 //               inside the rounding band is left to
-//   k_recheck_pairs   which decides it in binary64; an item whose block ran
-//               out of re-test room is run again whole by k_item64;
+//   k_retest    which decides it in binary64, one wavefront per pair; an
+//               item whose block ran out of re-test room is run again whole
+//               in binary64 by k_deferred (which exits at once otherwise);
 //   k_count + k_write   labels from the counters and the ordered gray list.
+// The *_batch kernels run the same stages for many roadmaps in one launch
+// each, reading every roadmap's arguments from a request table.
 //
 // Binary64 code is compiled without FMA contraction and its sums run left to
 // right from 0.0, so a re-test reproduces the definition's values exactly.
@@ -644,27 +649,33 @@ __device__ bool copies_meet64(const RmDev &rm, const double *sb, int64_t P, cons
 }
 
 // ------------------------------------------------------------------------
-// k_item: one block per grid work item (cell c, chunk of 256 of its edges).
+// k_item: one block per work item (grid cell c, a chunk of at most 256 of
+// its edges; the chunk size is the roadmap's work-item size).
 //
-//   1. every thread owns one edge of the item; the changed entries covering
-//      the cell are staged in LDS (tiles of kSubTile); a thread marks the
-//      entries whose box meets its edge's box, 32 per LDS word.  With several
-//      cells a pair is taken only by the cell holding the lower corner of the
-//      two boxes' intersection, so each (edge, entry) pair is tested once.
-//   2. outer test, lanes = (pair, sphere): capsule of sphere i against the
-//      entry's box (FP32: separation and end-sphere tests first, the exact
-//      segment-box minimum where they do not decide).  Each pair keeps the
-//      sphere whose capsule met deepest and the configuration nearest the
-//      capsule axis' closest point to the box.
+//   1. every thread owns one edge of the item.  The changed entries covering
+//      the cell are staged in LDS (tiles of kSubTile) and registered in a
+//      block-local pruning grid (an entry over more than kWideCells of its
+//      cells is a candidate of every edge); a thread ORs the masks of the
+//      pruning cells its edge's box covers and marks the candidates whose
+//      box meets its edge's box, 32 per LDS word.  With several grid cells a
+//      pair is taken only by the cell holding the lower corner of the two
+//      boxes' intersection, so each (edge, entry) pair is tested once.
+//   2. outer test, lanes = (pair, sphere): separation and end-sphere tests
+//      first; the tests they leave open are queued in LDS and run densely
+//      with the exact segment-box minimum.  Each pair keeps the sphere whose
+//      capsule met deepest and the configuration nearest the capsule axis'
+//      closest point to the box.
 //   3. probe: that one copy is tested first.  S is an existence test, so a
 //      copy found to meet settles the pair and its other copies are not
 //      tested; the result is the same, only the order of the tests changes.
-//   4. inner test of the pairs the probe left open, lanes = (pair, sphere
-//      whose capsule met, configuration): every copy of those spheres.
+//   4. inner test of the pairs the probe left open, rows = (pair, sphere
+//      whose capsule met), lanes = configurations: every copy of those
+//      spheres.
 //   5. per pair C and S; the edge's counter deltas are summed in LDS and
 //      added once per edge.  In FP32 a pair whose decision fell inside the
-//      rounding band is decided again in binary64 by the same block, one
-//      wavefront per pair, before the item's counters are added.
+//      rounding band goes to the block's re-test region, decided in binary64
+//      by k_retest (one wavefront per pair); when the region is full the
+//      whole item is left to k_deferred, which runs it in binary64.
 // ------------------------------------------------------------------------
 
 constexpr int kSubTile = 128;             // changed entries staged per tile

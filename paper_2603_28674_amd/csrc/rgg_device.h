@@ -85,9 +85,9 @@ constexpr int kStats = 6;
 constexpr int kStatBlocks = 2048;  // blocks of the item kernels
 constexpr int kMaxSlots = 4096;    // 2*slots changed entries at most
 
-constexpr int kLocalCells = 512;
+constexpr int kLocalCells = 512;   // cells of the item kernel's pruning grid (at most)
 constexpr int kCopyStride3 = 4;    // values per sample copy in 3-D (xyz + pad)
-constexpr int kCopyStride2 = 2;    // in 2-D   // cells of the item kernel's pruning grid (at most)
+constexpr int kCopyStride2 = 2;    // in 2-D
 constexpr int kRcCap = 1024;       // default re-test pairs one item-kernel block may queue
 constexpr int kLabelTile = 4096;   // edges per block of the label kernels
 
