@@ -39,6 +39,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=10)
     p.add_argument("--nodes", type=int, default=50000)
     p.add_argument("--cell-size", type=float, default=-1.0)
+    p.add_argument("--item-edges", type=int, default=0,
+                   help="edges per work item at build (0 = 256); the autotuner may change it")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-edges", type=int, default=300000,
                    help="edges the oracle classifies (capped at the roadmap size)")
@@ -426,7 +428,7 @@ def main():
     ctx = rgg.rgg_context_create(0)
     log(f"[bench] building roadmap E={E} M={M}")
     g = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK,
-                                  cell_size=a.cell_size)
+                                  cell_size=a.cell_size, item_edges=a.item_edges)
     info = g.info()
     log(f"[bench] built in {info['build_seconds']:.2f}s, device {info['device_bytes'] / 1e9:.2f} GB, "
         f"grid {info['grid_cells']}")

@@ -131,7 +131,9 @@ typedef struct {
                                      at most 2^20.  Any value gives the same
                                      labels.                                    */
     int32_t item_edges;           /* edges per work item of the classify
-                                     kernels (one block each), 1..256; 0 = 256.
+                                     kernels (one block of 256 threads each,
+                                     up to two edges per thread), 1..512;
+                                     0 = 256.
                                      rgg_tune may change it.  Any value gives
                                      the same labels.                           */
 } rgg_build_opts;
@@ -265,10 +267,11 @@ rgg_status rgg_update_batch(rgg_context *ctx, int32_t n, const rgg_update_req *r
 
 /* Autotuner of the work decomposition (Sec. 3.3 sizes grid cells by what
  * one kernel can process; here the choice is made by measurement).  The
- * candidates are the roadmap's current configuration and every combination
- * of work-item size (256, 128 or 64 edges per item, one block each) and grid
- * cell size (one cell covering the roadmap, or 1, 2, 4 or 8 times the mean
- * edge extent).  For each, the grid is rebuilt on the device and the updates
+ * candidates are the roadmap's current configuration, every combination
+ * of work-item size (512, 256, 128 or 64 edges per item, one block each) and
+ * grid cell size (one cell covering the roadmap, or 1, 2, 4 or 8 times the
+ * mean edge extent), and one cell with items sized so that their count fills
+ * 1, 2 or 3 rounds of the item blocks the device holds at once.  For each, the grid is rebuilt on the device and the updates
  * a -> b_i -> a for i = 0..n_b-1 are run `reps` times (0 selects 5) after one
  * untimed pass, timed with HIP events on the roadmap's own stream; the
  * fastest configuration is kept (the current one unless another is at least
@@ -287,7 +290,7 @@ rgg_status rgg_update_batch(rgg_context *ctx, int32_t n, const rgg_update_req *r
  * an error the roadmap's state and labels are unchanged, its grid may be any
  * of the candidates.  *report (may be null) receives the choice and every
  * candidate's mean time per update. */
-#define RGG_TUNE_MAX_CANDIDATES 16
+#define RGG_TUNE_MAX_CANDIDATES 32
 typedef struct {
     int32_t n_candidates;
     int32_t item_edges;                               /* chosen                         */

@@ -233,11 +233,13 @@ rgg_status tune_apply(TuneSubject &t, const TuneCand &c)
 template <typename Run>
 rgg_status tune_search(std::vector<TuneSubject *> &subj, hipStream_t s, int reps, int per_rt, Run &&run,
                        bool per_batch, rgg_tune_report *report,
-                       const std::function<rgg_status()> &refresh = nullptr)
+                       const std::function<rgg_status()> &refresh = nullptr,
+                       const std::vector<TuneCand> &extra = {})
 {
     std::vector<TuneCand> cands = {{0.0, 0}};
-    for (int32_t chunk : {256, 128, 64})
+    for (int32_t chunk : {512, 256, 128, 64})
         for (double f : {-1.0, 1.0, 2.0, 4.0, 8.0}) cands.push_back({f, chunk});
+    for (const TuneCand &c : extra) cands.push_back(c);
     if ((int)cands.size() > RGG_TUNE_MAX_CANDIDATES) cands.resize(RGG_TUNE_MAX_CANDIDATES);
     struct Ev {
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -392,6 +394,9 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     HostGeometry g;
     st = build_geometry(rd, robot, opts, 0, rd->n_edges, host_threads(opts->host_threads), &g, &err);
     if (st != RGG_OK) return fail(st, "%s", err.c_str());
+    if (g.B > 0 && g.soff.back() / g.B > (int64_t)UINT32_MAX)
+        return fail(RGG_E_INVALID_ARG, "%lld configurations over all edges; at most 2^32 - 1",
+                    (long long)(g.soff.back() / g.B));
     const int32_t chunk = opts->item_edges > 0 ? opts->item_edges : kChunk;
     HostGrid grid;
     st = build_grid(g, opts->cell_size, chunk, &grid, &err);
@@ -768,7 +773,7 @@ rgg_status rgg_batch_create(rgg_context *ctx, int32_t n, rgg_roadmap *const *rms
         if (rms[k]->device != ctx->device) return fail(RGG_E_INVALID_ARG, "roadmap %d is on another device", k);
         if (seen.count(rms[k])) return fail(RGG_E_INVALID_ARG, "roadmap %d repeats roadmap %d", k, seen[rms[k]]);
         seen[rms[k]] = k;
-        if (rms[k]->dv.chunk < 1 || rms[k]->dv.chunk > kChunk)
+        if (rms[k]->dv.chunk < 1 || rms[k]->dv.chunk > item_edges_max())
             return fail(RGG_E_INVALID_ARG, "roadmap %d has work items of %d edges", k, rms[k]->dv.chunk);
     }
     HIP_OR_FAIL(hipSetDevice(ctx->device), "hipSetDevice");
@@ -922,8 +927,18 @@ rgg_status rgg_tune(rgg_roadmap *rm, int64_t m, const rgg_box *obstacles_a, int3
             }
         return RGG_OK;
     };
+    // one cell with items sized so that their count fills 1, 2 or 3 rounds
+    // of the resident item blocks exactly
+    std::vector<TuneCand> extra;
+    int resident = 0;
+    HIP_OR_FAIL(item_blocks_resident(rm->dv.D, rm->device, &resident), "occupancy query");
+    for (int rounds = 1; rounds <= 3 && resident > 0; ++rounds) {
+        const int64_t chunk = (rm->dv.E + (int64_t)rounds * resident - 1) / ((int64_t)rounds * resident);
+        if (chunk >= 32 && chunk <= item_edges_max() && chunk != 512 && chunk != 256 && chunk != 128 && chunk != 64)
+            extra.push_back({-1.0, (int32_t)chunk});
+    }
     std::vector<TuneSubject *> subj = {&t};
-    st = tune_search(subj, s, reps, 2 * n_b, run, false, report);
+    st = tune_search(subj, s, reps, 2 * n_b, run, false, report, nullptr, extra);
     if (st != RGG_OK) return st;
     return finish_update(rm, s);
 }

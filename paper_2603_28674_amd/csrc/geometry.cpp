@@ -289,7 +289,7 @@ rgg_status validate_build_inputs(const rgg_roadmap_desc *rd, const rgg_robot *r,
     if (!(o->band_rel >= 0.0) && !(o->band_rel <= 0.0)) return bad("band_rel is NaN");
     if (o->n_obstacle_slots < 0 || o->n_obstacle_slots > 4096) return bad("n_obstacle_slots must be 0..4096");
     if (o->retest_capacity < 0 || o->retest_capacity > (1 << 20)) return bad("retest_capacity must be 0..2^20");
-    if (o->item_edges < 0 || o->item_edges > 256) return bad("item_edges must be 0..256");
+    if (o->item_edges < 0 || o->item_edges > 512) return bad("item_edges must be 0..512");
     if (std::isnan(o->cell_size)) return bad("cell_size is NaN");
     return RGG_OK;
 }

@@ -14,9 +14,9 @@
 //               counter update (Sec. 3.1 rule; Alg. 1's intersection lists
 //               kept as counts).  In the FP32 mode a pair whose margin falls
 //               inside the rounding band is left to
-//   k_retest    which decides it in binary64, one wavefront per pair; an
-//               item whose block ran out of re-test room is run again whole
-//               in binary64 by k_deferred (which exits at once otherwise);
+//   k_fp64      which decides it in binary64, one wavefront per pair; an
+//               item whose block ran out of re-test room is then run again
+//               whole in binary64 by the same kernel (skipped otherwise);
 //   k_count + k_write   labels from the counters and the ordered gray list.
 // The *_batch kernels run the same stages for many roadmaps in one launch
 // each, reading every roadmap's arguments from a request table.
@@ -674,11 +674,13 @@ __device__ bool copies_meet64(const RmDev &rm, const double *sb, int64_t P, cons
 //   5. per pair C and S; the edge's counter deltas are summed in LDS and
 //      added once per edge.  In FP32 a pair whose decision fell inside the
 //      rounding band goes to the block's re-test region, decided in binary64
-//      by k_retest (one wavefront per pair); when the region is full the
-//      whole item is left to k_deferred, which runs it in binary64.
+//      by k_fp64 (one wavefront per pair); when the region is full the
+//      whole item is left to k_fp64's second part, which runs it in binary64.
 // ------------------------------------------------------------------------
 
 constexpr int kSubTile = 128;             // changed entries staged per tile
+constexpr int kSlots = 2;                 // edge slots per thread
+constexpr int kItemCap = kSlots * kBlock; // edges per work item at most
 constexpr int kWords = kSubTile / 32;     // overlap words per edge
 constexpr int kPairCap = kBlock;          // pairs per round (one per thread)
 constexpr int kRowCap = 256;              // (pair, sphere) rows per copy round
@@ -686,6 +688,12 @@ constexpr int kOpenCap = 1024;            // capsule tests queued for the exact 
 constexpr int kWideCells = 64;            // pruning-grid cells an entry may cover
 constexpr int kEdgeCells = 64;            // pruning-grid cells an edge may visit
 static_assert(kWords == 4, "a pruning-grid cell holds one uint4 of entry bits");
+static_assert(kSubTile <= 128 && kItemCap <= 512, "a pair is (edge slot << 7) | staged entry in 16 bits");
+static_assert(kLocalCells * 4 == kWords * kItemCap, "the overlap words reuse the pruning grid's storage");
+static_assert(kOpenCap >= 2 * kRowCap + 1, "the rows fit the capsule queue's storage");
+
+__device__ inline int pe_slot(int v) { return v >> 7; }
+__device__ inline int pe_entry(int v) { return v & 127; }
 
 template <typename T>
 struct ExactBoxes {
@@ -704,21 +712,29 @@ struct ItemLds {
     // binary64 boxes for the binary64 kernel (the binary32 ones serve FP32)
     typename std::conditional<std::is_same<T, double>::value, ExactBoxes<double>, NoBoxes>::type x;
     typename std::conditional<std::is_same<T, float>::value, Radii32, NoRadii>::type r;
-    uint32_t om[kWords][kBlock];          // staged entries each edge's box meets
-    uint4 lgm[kLocalCells];               // pruning grid: staged entries per cell
+    union {
+        uint4 lgm[kLocalCells];           // pruning grid: staged entries per cell,
+        uint32_t om[kWords][kItemCap];    // then the staged entries each edge's box meets
+    } g;
     uint32_t wide[kWords];                // staged entries over many cells
-    int64_t es0[kBlock];                  // first sample of each edge of the item
-    int edge[kBlock], ej[kBlock];         // edge id, configurations per sphere
-    float es[kBlock];                     // edge s (largest |coordinate| of its box)
-    int dC[kBlock], dS[kBlock];
-    uint16_t pe[kPairCap];                // edge slot << 8 | staged entry
+    uint32_t cfg0[kItemCap];              // first configuration of each edge (sample / B)
+    int edge[kItemCap], ej[kItemCap];     // edge id, configurations per sphere
+    float es[kItemCap];                   // edge s (largest |coordinate| of its box)
+    int dC[kItemCap], dS[kItemCap];
+    uint16_t pe[kPairCap];                // edge slot << 7 | staged entry
     unsigned long long hm[kPairCap], um[kPairCap];
     uint32_t key[kPairCap];               // probe_key of the deepest capsule hit
-    uint32_t open[kOpenCap];              // queued (pair << 6 | sphere) capsule tests
+    // the capsule-test queue is dead once the exact part has run; the rows
+    // and their copy offsets live after it, in the same storage
+    union {
+        uint32_t open[kOpenCap];          // queued (pair << 6 | sphere) capsule tests
+        struct {
+            uint32_t row[kRowCap];        // pair << 6 | sphere
+            uint32_t rcopy[kRowCap + 1];
+        } rw;
+    } u;
     int nopen;
-    uint32_t roff[kPairCap], sf[kPairCap];
-    uint32_t row[kRowCap];                // pair << 6 | sphere
-    uint32_t rcopy[kRowCap + 1];
+    uint32_t sf[kPairCap];
     int wsum[kWaves];
     int rc_n, rc_start, defer, df_n;
     unsigned long long acc[kStats];
@@ -867,41 +883,66 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
     };
     int it;
     while (next_item(it)) {
-        const int2 item = rm.items[it];
+        // with one cell the items are (0, h) and the cell's list is every
+        // edge in order: the item's edges are beg .. end - 1 themselves
+        const int2 item = single ? make_int2(0, it) : rm.items[it];
         const int64_t c = item.x;
         const int32_t cx = (int32_t)(c % rm.gdim[0]);
         const int32_t cy = (int32_t)((c / rm.gdim[0]) % rm.gdim[1]);
         const int32_t cz = (int32_t)(c / ((int64_t)rm.gdim[0] * rm.gdim[1]));
-        const int64_t beg = (int64_t)rm.cell_start[c] + (int64_t)item.y * rm.chunk;
-        const int64_t end = min((int64_t)rm.cell_start[c + 1], beg + rm.chunk);
-        const bool have = beg + tid < end;
-        int e = 0;
-        float es = 0.0f;
-        int64_t s0 = 0;
-        int J = 0;
-        if (have) {
-            e = rm.cell_edges[beg + tid];
-            es = aabb[2 * (int64_t)e].w;
-            s0 = rm.p_fixed ? (int64_t)e * rm.p_fixed : rm.soff[e];
-            J = (int)((rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0) / B);
-            bytes += 32;
+        int64_t beg, end;
+        if (single) {
+            beg = (int64_t)item.y * rm.chunk;
+            end = min(rm.E, beg + rm.chunk);
+        } else {
+            beg = (int64_t)rm.cell_start[c] + (int64_t)item.y * rm.chunk;
+            end = min((int64_t)rm.cell_start[c + 1], beg + rm.chunk);
         }
-        visited += (uint32_t)__popcll(__ballot(have));
-        __syncthreads();
-        L.edge[tid] = e;
-        L.es[tid] = es;
-        L.es0[tid] = s0;
-        L.ej[tid] = J;
-        L.dC[tid] = 0;
-        L.dS[tid] = 0;
+        const int n_e = (int)(end - beg);   // edge slots in use: tid, tid + kBlock
+        int e[kSlots], J[kSlots];
+        float es[kSlots];
+        uint32_t j0[kSlots];
+#pragma unroll
+        for (int h = 0; h < kSlots; ++h) {
+            const int sl = tid + h * kBlock;
+            e[h] = 0;
+            J[h] = 0;
+            es[h] = 0.0f;
+            j0[h] = 0;
+            if (sl < n_e) {
+                e[h] = single ? (int)(beg + sl) : rm.cell_edges[beg + sl];
+                es[h] = aabb[2 * (int64_t)e[h]].w;
+                if (jfix) {
+                    J[h] = jfix;
+                    j0[h] = (uint32_t)((int64_t)e[h] * jfix);
+                } else {
+                    const int64_t s0 = rm.soff[e[h]];
+                    j0[h] = (uint32_t)(s0 / B);
+                    J[h] = (int)((rm.soff[e[h] + 1] - s0) / B);
+                }
+                bytes += 32;
+            }
+        }
+        __syncthreads();   // the previous item is done with the LDS arrays
+#pragma unroll
+        for (int h = 0; h < kSlots; ++h) {
+            const int sl = tid + h * kBlock;
+            L.edge[sl] = e[h];
+            L.es[sl] = es[h];
+            L.cfg0[sl] = j0[h];
+            L.ej[sl] = J[h];
+            L.dC[sl] = 0;
+            L.dS[sl] = 0;
+        }
+        if (wv == 0) visited += (uint32_t)n_e;
         if (tid == 0) {
             L.rc_start = L.rc_n;
             L.defer = 0;
             // the main pass visits every item once: clear the cell's mark with
             // its first chunk, so the next update starts from zero marks
-            if (!deferred && item.y == 0) atomicAnd(&rm.cell_bits[c >> 5], ~(1u << (c & 31)));
+            if (!deferred && !single && item.y == 0) atomicAnd(&rm.cell_bits[c >> 5], ~(1u << (c & 31)));
         }
-        int my_pairs = 0;
+        uint32_t had = 0;   // bit h: edge slot h has pairs
         for (int j0 = 0; j0 < n_chg; j0 += kSubTile) {
             // stage the entries covering this cell
             const int j = j0 + tid;
@@ -932,7 +973,7 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
             // block-local pruning grid: each cell's mask of the staged
             // entries whose box covers it (an entry over more than kWideCells
             // cells is a candidate of every edge)
-            for (int q = tid; q < lgn; q += kBlock) L.lgm[q] = make_uint4(0u, 0u, 0u, 0u);
+            for (int q = tid; q < lgn; q += kBlock) L.g.lgm[q] = make_uint4(0u, 0u, 0u, 0u);
             if (tid < kWords) L.wide[tid] = 0u;
             __syncthreads();
             if (tid < nt) {
@@ -945,7 +986,7 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                 if (ncov > kWideCells) {
                     atomicOr(&L.wide[wd], bit);
                 } else {
-                    uint32_t *mw = reinterpret_cast<uint32_t *>(L.lgm);
+                    uint32_t *mw = reinterpret_cast<uint32_t *>(L.g.lgm);
                     for (int z = r0[2]; z <= r1[2]; ++z)
                         for (int y = r0[1]; y <= r1[1]; ++y)
                             for (int x = r0[0]; x <= r1[0]; ++x)
@@ -953,72 +994,98 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                 }
             }
             __syncthreads();
-            // the staged entries this thread's edge meets, 32 per word: the
-            // candidates of the cells its box covers, then the exact test
-            // the edge's box (read per tile rather than held in registers)
-            float4 bl = make_float4(0, 0, 0, 0), bh = bl;
-            if (have) {
-                bl = aabb[2 * (int64_t)L.edge[tid]];
-                bh = aabb[2 * (int64_t)L.edge[tid] + 1];
-            }
-            uint32_t cw[kWords] = {0u, 0u, 0u, 0u};
-            if (have) {
-                int r0[3], r1[3];
-                lg_range(rm, bl, bh, r0, r1);
-                const int ncov = (r1[0] - r0[0] + 1) * (r1[1] - r0[1] + 1) * (r1[2] - r0[2] + 1);
-                if (ncov > kEdgeCells) {
+            // the staged entries each of this thread's edges meets, 32 per
+            // word: the candidates of the cells its box covers (all reads of
+            // the pruning grid first: its storage then takes the words), then
+            // the exact test against the edge's box
+            float4 bl[kSlots], bh[kSlots];
+            uint32_t cw[kSlots][kWords];
+            // both slots' boxes are requested before either is used
 #pragma unroll
-                    for (int w = 0; w < kWords; ++w) cw[w] = ~0u;
-                } else {
-#pragma unroll
-                    for (int w = 0; w < kWords; ++w) cw[w] = L.wide[w];
-                    for (int z = r0[2]; z <= r1[2]; ++z)
-                        for (int y = r0[1]; y <= r1[1]; ++y)
-                            for (int x = r0[0]; x <= r1[0]; ++x) {
-                                const uint4 m = L.lgm[(z * rm.lg_dim[1] + y) * rm.lg_dim[0] + x];
-                                cw[0] |= m.x;
-                                cw[1] |= m.y;
-                                cw[2] |= m.z;
-                                cw[3] |= m.w;
-                            }
+            for (int h = 0; h < kSlots; ++h) {
+                const int sl = tid + h * kBlock;
+                bl[h] = make_float4(0, 0, 0, 0);
+                bh[h] = bl[h];
+                if (sl < n_e) {
+                    bl[h] = aabb[2 * (int64_t)L.edge[sl]];
+                    bh[h] = aabb[2 * (int64_t)L.edge[sl] + 1];
                 }
             }
+#pragma unroll
+            for (int h = 0; h < kSlots; ++h) {
+                const int sl = tid + h * kBlock;
+#pragma unroll
+                for (int w = 0; w < kWords; ++w) cw[h][w] = 0u;
+                if (sl < n_e) {
+                    int r0[3], r1[3];
+                    lg_range(rm, bl[h], bh[h], r0, r1);
+                    const int ncov = (r1[0] - r0[0] + 1) * (r1[1] - r0[1] + 1) * (r1[2] - r0[2] + 1);
+                    if (ncov > kEdgeCells) {
+#pragma unroll
+                        for (int w = 0; w < kWords; ++w) cw[h][w] = ~0u;
+                    } else {
+#pragma unroll
+                        for (int w = 0; w < kWords; ++w) cw[h][w] = L.wide[w];
+                        for (int z = r0[2]; z <= r1[2]; ++z)
+                            for (int y = r0[1]; y <= r1[1]; ++y)
+                                for (int x = r0[0]; x <= r1[0]; ++x) {
+                                    const uint4 m = L.g.lgm[(z * rm.lg_dim[1] + y) * rm.lg_dim[0] + x];
+                                    cw[h][0] |= m.x;
+                                    cw[h][1] |= m.y;
+                                    cw[h][2] |= m.z;
+                                    cw[h][3] |= m.w;
+                                }
+                    }
+                }
+            }
+            __syncthreads();
             int cnt = 0;
 #pragma unroll
-            for (int w = 0; w < kWords; ++w) {
-                if (w < nw) {
-                    const int left = nt - 32 * w;   // staged entries from this word on
-                    uint32_t m = cw[w] & (left >= 32 ? ~0u : ((1u << left) - 1u)), bits = 0;
-                    while (m) {
-                        const int b = __ffs(m) - 1;
-                        m &= m - 1;
-                        const float4 l = L.blo[w * 32 + b], h = L.bhi[w * 32 + b];
-                        bool hit = (l.x <= bh.x) & (h.x >= bl.x) & (l.y <= bh.y) & (h.y >= bl.y) &
-                                   (l.z <= bh.z) & (h.z >= bl.z);
-                        if (hit && !single) {
-                            const float lo3[3] = {l.x, l.y, l.z};
-                            hit = pair_owned<D, float>(rm, bl, lo3, c);
+            for (int h = 0; h < kSlots; ++h) {
+                const int sl = tid + h * kBlock;
+                if (sl >= n_e) continue;
+                int ch = 0;
+#pragma unroll
+                for (int w = 0; w < kWords; ++w) {
+                    if (w < nw) {
+                        const int left = nt - 32 * w;   // staged entries from this word on
+                        uint32_t m = cw[h][w] & (left >= 32 ? ~0u : ((1u << left) - 1u)), bits = 0;
+                        while (m) {
+                            const int b = __ffs(m) - 1;
+                            m &= m - 1;
+                            const float4 l = L.blo[w * 32 + b], hb = L.bhi[w * 32 + b];
+                            bool hit = (l.x <= bh[h].x) & (hb.x >= bl[h].x) & (l.y <= bh[h].y) & (hb.y >= bl[h].y) &
+                                       (l.z <= bh[h].z) & (hb.z >= bl[h].z);
+                            if (hit && !single) {
+                                const float lo3[3] = {l.x, l.y, l.z};
+                                hit = pair_owned<D, float>(rm, bl[h], lo3, c);
+                            }
+                            bits |= (uint32_t)hit << b;
                         }
-                        bits |= (uint32_t)hit << b;
+                        L.g.om[w][sl] = bits;
+                        ch += __popc(bits);
                     }
-                    L.om[w][tid] = bits;
-                    cnt += __popc(bits);
                 }
+                cnt += ch;
+                if (ch) had |= 1u << h;
             }
-            my_pairs += cnt;
             int tp;
             const int pre = block_scan(cnt, &tp, L.wsum);
             for (int r0 = 0; r0 < tp; r0 += kPairCap) {
                 const int np = min(kPairCap, tp - r0);
                 if (cnt > 0 && pre < r0 + np && pre + cnt > r0) {
                     int k = pre;
-                    for (int w = 0; w < nw && k < r0 + np; ++w) {
-                        uint32_t m = L.om[w][tid];
-                        while (m && k < r0 + np) {
-                            const int s = (w << 5) + __ffs(m) - 1;
-                            m &= m - 1;
-                            if (k >= r0) L.pe[k - r0] = (uint16_t)((tid << 8) | s);
-                            ++k;
+                    for (int h = 0; h < kSlots && k < r0 + np; ++h) {
+                        const int sl = tid + h * kBlock;
+                        if (sl >= n_e) break;
+                        for (int w = 0; w < nw && k < r0 + np; ++w) {
+                            uint32_t m = L.g.om[w][sl];
+                            while (m && k < r0 + np) {
+                                const int s = (w << 5) + __ffs(m) - 1;
+                                m &= m - 1;
+                                if (k >= r0) L.pe[k - r0] = (uint16_t)((sl << 7) | s);
+                                ++k;
+                            }
                         }
                     }
                 }
@@ -1055,7 +1122,7 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                         pu[u] = p0 + (u * kWaves + wv) * Gw + slot;
                         R2[u] = T(0);
                         if (slot < Gw && pu[u] < np) {
-                            const int te = L.pe[pu[u]] >> 8;
+                            const int te = pe_slot(L.pe[pu[u]]);
                             const T *cp = capb + (int64_t)L.edge[te] * (2 * D + 1) * B;
 #pragma unroll
                             for (int k = 0; k < D; ++k) {
@@ -1075,14 +1142,14 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                         const T R = R2[u];
                         const T RR = R * R;
                         if (act) {
-                            const int s = L.pe[p] & 255;
+                            const int s = pe_entry(L.pe[p]);
 #pragma unroll
                             for (int k = 0; k < D; ++k) {
                                 lo[k] = box_lo(k, s);
                                 hi[k] = box_hi(k, s);
                             }
                             if constexpr (kF32) {
-                                const float sc = fmaxf(L.es[L.pe[p] >> 8], L.blo[s].w);
+                                const float sc = fmaxf(L.es[pe_slot(L.pe[p])], L.blo[s].w);
                                 float len = 0.0f;
 #pragma unroll
                                 for (int k = 0; k < D; ++k) len += fabsf(Bq[u][k] - A[u][k]);
@@ -1113,7 +1180,7 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                                 if (op) {
                                     const int q = base + __popcll(ob & lanes_below());
                                     if (q < kOpenCap) {
-                                        L.open[q] = ((uint32_t)p << 6) | (uint32_t)ci;
+                                        L.u.open[q] = ((uint32_t)p << 6) | (uint32_t)ci;
                                         cls = kMiss;     // decided by the exact part
                                     } else {
                                         cls = kUnsure;   // queue full: the binary64 re-test decides
@@ -1129,9 +1196,9 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                     // ---- outer test, exact part: the queued tasks, one per lane
                     const int nq = min(L.nopen, kOpenCap);
                     for (int q = tid; q < nq; q += kBlock) {
-                        const uint32_t tk = L.open[q];
+                        const uint32_t tk = L.u.open[q];
                         const int p = (int)(tk >> 6), i = (int)(tk & 63u);
-                        const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
+                        const int pv = L.pe[p], te = pe_slot(pv), s = pe_entry(pv);
                         const float *cp = (const float *)capb + (int64_t)L.edge[te] * (2 * D + 1) * B;
                         float A[D], Bq[D], lo[D], hi[D];
 #pragma unroll
@@ -1161,12 +1228,12 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                     if (hmp) {
                         const uint32_t key = L.key[p];
                         const int i = (int)(key & 63u);
-                        const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
+                        const int pv = L.pe[p], te = pe_slot(pv), s = pe_entry(pv);
                         const int Je = L.ej[te];
                         // the configuration nearest the deepest capsule's closest point
                         const int jj = min(Je - 1, (int)((float)((key >> 6) & 1023u) * (1.0f / 1023.0f) * (float)(Je - 1) + 0.5f));
                         T q[D], lo[D], hi[D];
-                        load_copy<D>(samp, L.es0[te] + (int64_t)i * Je + jj, q);
+                        load_copy<D>(samp, (int64_t)L.cfg0[te] * B + (int64_t)i * Je + jj, q);
 #pragma unroll
                         for (int k = 0; k < D; ++k) {
                             lo[k] = box_lo(k, s);
@@ -1188,7 +1255,6 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                 const int ra = (p < np && !(f & 1u)) ? __popcll(hmp) : 0;
                 int nrows;
                 const int rpre = block_scan(ra, &nrows, L.wsum);
-                if (p < np) L.roff[p] = rpre;
                 __syncthreads();
                 for (int q0 = 0; q0 < nrows; q0 += kRowCap) {
                     const int nr = min(kRowCap, nrows - q0);
@@ -1198,7 +1264,7 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                         while (m && r < q0 + nr) {
                             const int i = __ffsll((unsigned long long)m) - 1;
                             m &= m - 1;
-                            if (r >= q0) L.row[r - q0] = ((uint32_t)p << 6) | (uint32_t)i;
+                            if (r >= q0) L.u.rw.row[r - q0] = ((uint32_t)p << 6) | (uint32_t)i;
                             ++r;
                         }
                     }
@@ -1209,17 +1275,17 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                         int cj[2], sum = 0;
                         for (int h = 0; h < 2; ++h) {
                             const int r = tid * 2 + h;
-                            cj[h] = r < nr ? L.ej[L.pe[L.row[r] >> 6] >> 8] : 0;
+                            cj[h] = r < nr ? L.ej[pe_slot(L.pe[L.u.rw.row[r] >> 6])] : 0;
                             sum += cj[h];
                         }
                         const int cpre = block_scan(sum, &ncopies, L.wsum);
                         int acc = cpre;
                         for (int h = 0; h < 2; ++h) {
                             const int r = tid * 2 + h;
-                            if (r < nr) L.rcopy[r] = acc;
+                            if (r < nr) L.u.rw.rcopy[r] = acc;
                             acc += cj[h];
                         }
-                        if (tid == 0) L.rcopy[nr] = ncopies;
+                        if (tid == 0) L.u.rw.rcopy[nr] = ncopies;
                         __syncthreads();
                     }
                     // each thread gathers kCopyU copies (all their loads in
@@ -1242,18 +1308,18 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                                     int lo_ = 0, hi_ = nr - 1;   // last row with rcopy[r] <= cidx
                                     while (lo_ < hi_) {
                                         const int mid = (lo_ + hi_ + 1) >> 1;
-                                        if (L.rcopy[mid] <= (uint32_t)cidx) lo_ = mid;
+                                        if (L.u.rw.rcopy[mid] <= (uint32_t)cidx) lo_ = mid;
                                         else hi_ = mid - 1;
                                     }
                                     r = lo_;
-                                    jj = cidx - (int)L.rcopy[r];
+                                    jj = cidx - (int)L.u.rw.rcopy[r];
                                 }
-                                const uint32_t rv = L.row[r];
+                                const uint32_t rv = L.u.rw.row[r];
                                 const int pp = (int)(rv >> 6);
                                 const int i = (int)(rv & 63u);
-                                const int te = L.pe[pp] >> 8;
+                                const int te = pe_slot(L.pe[pp]);
                                 const int Je = L.ej[te];
-                                load_copy<D>(samp, L.es0[te] + (int64_t)i * Je + jj, q[u]);
+                                load_copy<D>(samp, (int64_t)L.cfg0[te] * B + (int64_t)i * Je + jj, q[u]);
                                 cu_p[u] = pp;
                                 cu_i[u] = i;
                             }
@@ -1262,7 +1328,7 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                         for (int u = 0; u < kCopyU; ++u) {
                             const int pp = cu_p[u];
                             if (pp < 0) continue;
-                            const int pv = L.pe[pp], te = pv >> 8, s = pv & 255;
+                            const int pv = L.pe[pp], te = pe_slot(pv), s = pe_entry(pv);
                             T lo[D], hi[D];
 #pragma unroll
                             for (int k = 0; k < D; ++k) {
@@ -1291,7 +1357,7 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                     const uint64_t ump = kF32 ? L.um[p] : 0ull;
                     if (hmp || ump) {
                         const uint32_t fp = L.sf[p];
-                        const int pv = L.pe[p], te = pv >> 8, s = pv & 255;
+                        const int pv = L.pe[p], te = pe_slot(pv), s = pe_entry(pv);
                         unsure = kF32 && (!hmp || (!(fp & 1u) && ((fp & 2u) || ump)));
                         if (unsure) {
                             rec = make_int2(L.edge[te], L.gidx[s]);
@@ -1322,11 +1388,15 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                 __syncthreads();
             }
         }
-        cand += (uint32_t)__popcll(__ballot(have && my_pairs > 0));
-        if (have && my_pairs > 0) bytes += (2 * D + 1) * B * sizeof(T) + 16;
+        cand += (uint32_t)(__popcll(__ballot(had & 1u)) + __popcll(__ballot(had & 2u)));
+        bytes += (unsigned long long)__popc(had) * ((2 * D + 1) * B * sizeof(T) + 16);
         __syncthreads();
         if (!L.defer) {
-            if (have) add_counts(rm, L.edge[tid], L.dC[tid], L.dS[tid]);
+#pragma unroll
+            for (int h = 0; h < kSlots; ++h) {
+                const int sl = tid + h * kBlock;
+                if (sl < n_e) add_counts(rm, L.edge[sl], L.dC[sl], L.dS[sl]);
+            }
         } else if (tid == 0) {
             L.rc_n = L.rc_start;
             rm.df[(int64_t)blockIdx.x * rm.df_cap + L.df_n] = it;
@@ -1458,21 +1528,17 @@ __device__ __forceinline__ void retest_pairs(const RmDev &rm, int b, int G)
     }
 }
 
-// The binary64 pass of the FP32 mode: queued pairs, then the items left
-// whole (their blocks' re-test regions were full).
-// Regions b, b + G, ... of one roadmap.  The items left whole are rare (a
-// block's re-test region overflowed): their kernel exits at once unless one
-// was deferred in this update.
+// The binary64 pass of the FP32 mode, regions b, b + G, ... of one roadmap:
+// the queued pairs, then the items left whole because their blocks' re-test
+// regions were full (rare: skipped unless one was deferred in this update).
+// One kernel for both, so the common case costs one launch; it runs one
+// block per CU, so the binary64 item path's registers cost no occupancy.
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_retest(RmDev rm)
+__global__ void __launch_bounds__(kBlock) k_fp64(RmDev rm)
 {
+    const int any_df = rm.ctl->any_df;
     retest_pairs<D>(rm, (int)blockIdx.x, (int)gridDim.x);
-}
-
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_deferred(RmDev rm)
-{
-    if (!rm.ctl->any_df) return;
+    if (!any_df) return;
     item_body<D, double>(rm, 1, (int)blockIdx.x, (int)gridDim.x);
 }
 
@@ -1707,20 +1773,16 @@ __global__ void __launch_bounds__(kBlock) k_item64_batch(const BatchReq *tab, co
     item_batch_body<D, double>(tab, grp, n);
 }
 
-// kFp64BatchGrid blocks per request of the group
+// kFp64BatchGrid blocks per request of the group: its queued pairs, then
+// (if any) its items left whole
 template <int D>
-__global__ void __launch_bounds__(kBlock) k_retest_batch(const BatchReq *tab, const int32_t *grp)
-{
-    const int r = (int)blockIdx.x / kFp64BatchGrid, b = (int)blockIdx.x % kFp64BatchGrid;
-    retest_pairs<D>(tab[grp[r]].rm, b, kFp64BatchGrid);
-}
-
-template <int D>
-__global__ void __launch_bounds__(kBlock) k_deferred_batch(const BatchReq *tab, const int32_t *grp)
+__global__ void __launch_bounds__(kBlock) k_fp64_batch(const BatchReq *tab, const int32_t *grp)
 {
     __shared__ RmDev s_rm;
     const int r = (int)blockIdx.x / kFp64BatchGrid, b = (int)blockIdx.x % kFp64BatchGrid;
-    if (!tab[grp[r]].rm.ctl->any_df) return;
+    const int any_df = tab[grp[r]].rm.ctl->any_df;
+    retest_pairs<D>(tab[grp[r]].rm, b, kFp64BatchGrid);
+    if (!any_df) return;
     load_rm(&s_rm, tab[grp[r]].rm);
     item_body<D, double>(s_rm, 1, b, kFp64BatchGrid);
 }
@@ -1766,15 +1828,11 @@ void *item_fn(const RmDev &rm, bool f64)
     return f64 ? (void *)k_item64<2> : (void *)k_item32<2>;
 }
 
-void *retest_fn(const RmDev &rm)
+void *fp64_fn(const RmDev &rm)
 {
-    return rm.D == 3 ? (void *)k_retest<3> : (void *)k_retest<2>;
+    return rm.D == 3 ? (void *)k_fp64<3> : (void *)k_fp64<2>;
 }
 
-void *deferred_fn(const RmDev &rm)
-{
-    return rm.D == 3 ? (void *)k_deferred<3> : (void *)k_deferred<2>;
-}
 
 struct Node {
     void *fn;
@@ -1795,8 +1853,7 @@ int plan(const RmDev &rm, Node out[7])
     if (!single) out[n++] = {(void *)k_cells, dim3(kCellsGrid), 1, 2, 3};
     out[n++] = {item_fn(rm, !rm.mixed), dim3(kGrid), 1, 4, rm.mixed ? 4 : 5};
     if (rm.mixed) {
-        out[n++] = {retest_fn(rm), dim3(kFp64Grid), 1, -1, -1};
-        out[n++] = {deferred_fn(rm), dim3(kFp64Grid), 1, 5, 5};
+        out[n++] = {fp64_fn(rm), dim3(kFp64Grid), 1, 5, 5};
     }
     out[n++] = {(void *)k_count, dim3(rm.ntiles), 1, -1, -1};
     out[n++] = {(void *)k_write, dim3(rm.ntiles + 1), 4, 6, 6};
@@ -1831,7 +1888,7 @@ struct Args {
 
 hipError_t launch_update(const RmDev &rm, const UpdateArgs &a, hipStream_t s, hipEvent_t *ev)
 {
-    if (rm.chunk < 1 || rm.chunk > kBlock) return hipErrorInvalidValue;   // at most one edge of an item per thread
+    if (rm.chunk < 1 || rm.chunk > kItemCap) return hipErrorInvalidValue;   // at most kSlots edges of an item per thread
     Node nodes[7];
     const int n = plan(rm, nodes);
     Args args(rm, a);
@@ -1848,6 +1905,19 @@ hipError_t launch_update(const RmDev &rm, const UpdateArgs &a, hipStream_t s, hi
     return hipSuccess;
 }
 
+int item_edges_max() { return kItemCap; }
+
+hipError_t item_blocks_resident(int D, int device, int *out)
+{
+    int per_cu = 0, n_cu = 0;
+    hipError_t e = D == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_item32<3>, kBlock, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_item32<2>, kBlock, 0);
+    if (e != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess) return e;
+    *out = per_cu * n_cu;
+    return hipSuccess;
+}
+
 hipError_t launch_labels(const RmDev &rm, const UpdateArgs &a, hipStream_t s)
 {
     k_count<<<rm.ntiles, kBlock, 0, s>>>(rm);
@@ -1860,7 +1930,7 @@ hipError_t launch_labels(const RmDev &rm, const UpdateArgs &a, hipStream_t s)
 hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, hipGraphNode_t dep,
                             hipGraphNode_t *last)
 {
-    if (rm.chunk < 1 || rm.chunk > kBlock) return hipErrorInvalidValue;
+    if (rm.chunk < 1 || rm.chunk > kItemCap) return hipErrorInvalidValue;
     Node nodes[7];
     const int n = plan(rm, nodes);
     Args args(rm, a);   // hipGraphAddKernelNode copies the argument values
@@ -1908,10 +1978,8 @@ hipError_t batch_kernels(Emit emit, const BatchReq *tab, const int32_t *grp, int
         if ((err = emit(fn, dim3(kGrid), dim3(kBlock), a_item)) != hipSuccess) return err;
         if (gr.mixed) {
             void *a_fp[] = {(void *)&t, (void *)&gp};
-            void *rt = gr.D == 3 ? (void *)k_retest_batch<3> : (void *)k_retest_batch<2>;
-            void *df = gr.D == 3 ? (void *)k_deferred_batch<3> : (void *)k_deferred_batch<2>;
-            if ((err = emit(rt, dim3(kFp64BatchGrid * cnt), dim3(kBlock), a_fp)) != hipSuccess) return err;
-            if ((err = emit(df, dim3(kFp64BatchGrid * cnt), dim3(kBlock), a_fp)) != hipSuccess) return err;
+            void *fp = gr.D == 3 ? (void *)k_fp64_batch<3> : (void *)k_fp64_batch<2>;
+            if ((err = emit(fp, dim3(kFp64BatchGrid * cnt), dim3(kBlock), a_fp)) != hipSuccess) return err;
         }
     }
     if ((err = emit((void *)k_count_batch, dim3(n_tiles), dim3(kBlock), a_tn)) != hipSuccess) return err;

@@ -139,4 +139,10 @@ hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, 
 // last update's status (used by rgg_labels / rgg_gray_list).
 hipError_t launch_labels(const RmDev &rm, const UpdateArgs &a, hipStream_t s);
 
+// Edges a work item of the classify kernels may hold (at most two per thread).
+int item_edges_max();
+// Blocks of the binary32 item kernel for dimension D resident on `device` at
+// once (blocks per CU times CUs).
+hipError_t item_blocks_resident(int D, int device, int *out);
+
 }  // namespace rgg

@@ -84,7 +84,7 @@ class rgg_roadmap_info(C.Structure):
         return d
 
 
-TUNE_MAX_CANDIDATES = 16
+TUNE_MAX_CANDIDATES = 32
 
 
 class rgg_tune_report(C.Structure):

@@ -118,7 +118,7 @@ def test_grid_cell_size_does_not_change_labels(ctx, cell_size):
     check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, cell_size=cell_size)
 
 
-@pytest.mark.parametrize("item_edges", [64, 128, 200])
+@pytest.mark.parametrize("item_edges", [64, 200, 300, 512])
 @pytest.mark.parametrize("cell_size", [-1.0, 0.0])
 def test_item_size_does_not_change_labels(ctx, item_edges, cell_size):
     from paper_2603_28674_amd import rgg

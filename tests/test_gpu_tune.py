@@ -47,7 +47,7 @@ def test_tune_then_updates_match_oracle(ctx, kind):
     assert 10 <= rep["n_candidates"] <= rgg.TUNE_MAX_CANDIDATES
     assert all(c["us"] > 0.0 for c in rep["candidates"])
     assert rep["us_per_update"] <= rep["us_before"]
-    assert rep["item_edges"] in (64, 128, 256)
+    assert 1 <= rep["item_edges"] <= 512
     info = g.info()
     assert info["item_edges"] == rep["item_edges"]
     # the state is unchanged: current labels and gray list are the oracle's
