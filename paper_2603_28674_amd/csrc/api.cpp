@@ -481,6 +481,7 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     if ((st = rm->alloc(&dv.df_cnt, (size_t)kStatBlocks, "deferred counts")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.blk_stats, (size_t)kStatBlocks * kStats, "statistics")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.tile_cnt, (size_t)dv.ntiles + 1, "tile counts")) != RGG_OK) return guard(st);
+    if ((st = rm->alloc(&dv.tile_state, (size_t)dv.ntiles, "tile states")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.ctl, 1, "control block")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&rm->d_stage, (size_t)(2 * M), "box staging")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&rm->d_res, 1, "result")) != RGG_OK) return guard(st);
@@ -488,6 +489,7 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     if ((st = rm->alloc(&rm->d_gray, (size_t)E, "gray list")) != RGG_OK) return guard(st);
     HIP_OR_FAIL(hipMemset(dv.cnt, 0, sizeof(int2) * std::max<int64_t>(E, 1)), "clear counters");
     HIP_OR_FAIL(hipMemset(dv.ctl, 0, sizeof(Ctl)), "clear control");
+    HIP_OR_FAIL(hipMemset(dv.tile_state, 0, sizeof(unsigned long long) * dv.ntiles), "clear tile states");
     HIP_OR_FAIL(hipMemset(dv.rc_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear re-test counts");
     HIP_OR_FAIL(hipMemset(dv.df_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear deferred counts");
     HIP_OR_FAIL(hipMemset(dv.blk_stats, 0, sizeof(unsigned long long) * kStatBlocks * kStats), "clear statistics");

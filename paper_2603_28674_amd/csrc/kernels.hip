@@ -399,7 +399,9 @@ __device__ __forceinline__ void diff_body(const RmDev &rm, const rgg_box *__rest
         s_any = 0;
         rm.ctl->n_items = 0;
         rm.ctl->any_df = 0;
+        rm.ctl->label_ticket = 0;
     }
+    for (int t = tid; t < rm.ntiles; t += kDiffBlock) rm.tile_state[t] = 0ull;
     __syncthreads();
     bool dirty0 = false;   // the first chunk's slot changes (kept for the commit)
     rgg_box n0;
@@ -923,6 +925,15 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                 bytes += 32;
             }
         }
+        // with one cell every entry covers it: the first tile's entries are
+        // requested together with the edges (binary32 boxes, size, sign)
+        const bool pf = kF32 && single;
+        float4 pf_a = make_float4(0.0f, 0.0f, 0.0f, 0.0f), pf_b = pf_a;
+        if (pf && tid < kSubTile && tid < n_chg) {
+            const float4 *q = reinterpret_cast<const float4 *>(&rm.chg[tid]);
+            pf_a = q[0];   // lo32[0..2], hi32[0]
+            pf_b = q[1];   // hi32[1..2], sbox, sign
+        }
         __syncthreads();   // the previous item is done with the LDS arrays
 #pragma unroll
         for (int h = 0; h < kSlots; ++h) {
@@ -944,27 +955,43 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
         }
         uint32_t had = 0;   // bit h: edge slot h has pairs
         for (int j0 = 0; j0 < n_chg; j0 += kSubTile) {
+            // the pruning grid starts empty (the previous tile or item is
+            // done with its storage); the staging scan's barriers order this
+            // before the grid is filled
+            for (int q = tid; q < lgn; q += kBlock) L.g.lgm[q] = make_uint4(0u, 0u, 0u, 0u);
+            if (tid < kWords) L.wide[tid] = 0u;
             // stage the entries covering this cell
             const int j = j0 + tid;
+            const bool first = pf && j0 == 0;
             bool in = false;
             if (tid < kSubTile && j < n_chg) {
-                const ChgEntry &en = rm.chg[j];
-                in = single || (cx >= en.c0[0] && cx <= en.c1[0] && cy >= en.c0[1] && cy <= en.c1[1] &&
-                                cz >= en.c0[2] && cz <= en.c1[2]);
+                if (first) {
+                    in = true;
+                } else {
+                    const ChgEntry &en = rm.chg[j];
+                    in = single || (cx >= en.c0[0] && cx <= en.c1[0] && cy >= en.c0[1] && cy <= en.c1[1] &&
+                                    cz >= en.c0[2] && cz <= en.c1[2]);
+                }
             }
             int nt;
             const int pos = block_scan(in ? 1 : 0, &nt, L.wsum);
             if (in) {
-                const ChgEntry &en = rm.chg[j];
-                L.blo[pos] = make_float4(en.lo32[0], en.lo32[1], en.lo32[2], en.sbox);
-                L.bhi[pos] = make_float4(en.hi32[0], en.hi32[1], en.hi32[2], 0.0f);
-                if constexpr (!kF32) {
-                    for (int k = 0; k < 3; ++k) {
-                        L.x.lo[k][pos] = en.lo[k];
-                        L.x.hi[k][pos] = en.hi[k];
+                if (first) {
+                    L.blo[pos] = make_float4(pf_a.x, pf_a.y, pf_a.z, pf_b.z);
+                    L.bhi[pos] = make_float4(pf_a.w, pf_b.x, pf_b.y, 0.0f);
+                    L.sign[pos] = __float_as_int(pf_b.w);
+                } else {
+                    const ChgEntry &en = rm.chg[j];
+                    L.blo[pos] = make_float4(en.lo32[0], en.lo32[1], en.lo32[2], en.sbox);
+                    L.bhi[pos] = make_float4(en.hi32[0], en.hi32[1], en.hi32[2], 0.0f);
+                    if constexpr (!kF32) {
+                        for (int k = 0; k < 3; ++k) {
+                            L.x.lo[k][pos] = en.lo[k];
+                            L.x.hi[k][pos] = en.hi[k];
+                        }
                     }
+                    L.sign[pos] = en.sign;
                 }
-                L.sign[pos] = en.sign;
                 L.gidx[pos] = j;
             }
             if (nt == 0) continue;   // uniform: nt is the block total
@@ -973,9 +1000,6 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
             // block-local pruning grid: each cell's mask of the staged
             // entries whose box covers it (an entry over more than kWideCells
             // cells is a candidate of every edge)
-            for (int q = tid; q < lgn; q += kBlock) L.g.lgm[q] = make_uint4(0u, 0u, 0u, 0u);
-            if (tid < kWords) L.wide[tid] = 0u;
-            __syncthreads();
             if (tid < nt) {
                 const float4 l = L.blo[tid], h = L.bhi[tid];
                 int r0[3], r1[3];
@@ -1598,72 +1622,62 @@ __device__ __forceinline__ void count_body(const RmDev &rm, int tile)
     if (tid == 0) rm.tile_cnt[tile] = tot;
 }
 
-// k_write: labels and the ordered gray list, one tile per block (its first
-// position is the sum of the earlier tiles' counts; the last tile reports
-// n_gray, tile 0 the status); block
-// `ntiles` instead folds the per-block statistics of the update.
-// tile == ntiles: fold (and clear) the per-block statistics instead
-__device__ __forceinline__ void write_body(const RmDev &rm, uint8_t *labels, int64_t *gray, int64_t cap,
-                                          rgg_update_result *res, int force, int tile)
+// Folds (and clears) the per-block statistics of the update into *res.
+__device__ __forceinline__ void fold_stats(const RmDev &rm, rgg_update_result *res)
 {
-    __shared__ int s_w[kWaves];
     __shared__ unsigned long long s_part[kWaves][kStats];
     const int tid = threadIdx.x;
-    if (tile == rm.ntiles) {
-        if (force || !res) return;
-        // all of this thread's loads are issued before the first add
-        constexpr int kRows = kStatBlocks / kBlock;
-        unsigned long long v[kRows][kStats];
+    // all of this thread's loads are issued before the first add
+    constexpr int kRows = kStatBlocks / kBlock;
+    unsigned long long v[kRows][kStats];
 #pragma unroll
-        for (int h = 0; h < kRows; ++h)
+    for (int h = 0; h < kRows; ++h)
 #pragma unroll
-            for (int k = 0; k < kStats; ++k) v[h][k] = rm.blk_stats[k * kStatBlocks + h * kBlock + tid];
-        // cleared for the next update: a batched pass writes only the rows of
-        // the blocks that visited this roadmap
+        for (int k = 0; k < kStats; ++k) v[h][k] = rm.blk_stats[k * kStatBlocks + h * kBlock + tid];
+    // cleared for the next update: a batched pass writes only the rows of
+    // the blocks that visited this roadmap
 #pragma unroll
-        for (int h = 0; h < kRows; ++h)
+    for (int h = 0; h < kRows; ++h)
 #pragma unroll
-            for (int k = 0; k < kStats; ++k) rm.blk_stats[k * kStatBlocks + h * kBlock + tid] = 0ull;
-        const int lane = lane_id(), wv = tid >> 6;
+        for (int k = 0; k < kStats; ++k) rm.blk_stats[k * kStatBlocks + h * kBlock + tid] = 0ull;
+    const int lane = lane_id(), wv = tid >> 6;
 #pragma unroll
-        for (int k = 0; k < kStats; ++k) {
-            unsigned long long a = 0;
+    for (int k = 0; k < kStats; ++k) {
+        unsigned long long a = 0;
 #pragma unroll
-            for (int h = 0; h < kRows; ++h) a += v[h][k];
-            a = wave_sum_u64(a);
-            if (lane == 0) s_part[wv][k] = a;
-        }
-        __syncthreads();
-        if (tid < kStats) {
-            unsigned long long a = 0;
-            for (int w = 0; w < kWaves; ++w) a += s_part[w][tid];
-            int64_t *dst = tid == 0 ? &res->n_pairs : tid == 1 ? &res->n_outer_hits : tid == 2 ? &res->n_rechecked
-                         : tid == 3 ? &res->test_bytes : tid == 4 ? &res->n_cells_visited : &res->n_candidate_edges;
-            *dst = (int64_t)a;
-        }
-        return;
+        for (int h = 0; h < kRows; ++h) a += v[h][k];
+        a = wave_sum_u64(a);
+        if (lane == 0) s_part[wv][k] = a;
     }
-    const int status = force ? RGG_OK : rm.ctl->status;
-    if (tid == 0 && tile == 0 && res && !force) {
-        res->status = status;
-        res->n_changed = rm.ctl->n_chg;
-        if (status != RGG_OK) res->n_gray = 0;
+    __syncthreads();
+    if (tid < kStats) {
+        unsigned long long a = 0;
+        for (int w = 0; w < kWaves; ++w) a += s_part[w][tid];
+        int64_t *dst = tid == 0 ? &res->n_pairs : tid == 1 ? &res->n_outer_hits : tid == 2 ? &res->n_rechecked
+                     : tid == 3 ? &res->test_bytes : tid == 4 ? &res->n_cells_visited : &res->n_candidate_edges;
+        *dst = (int64_t)a;
     }
-    if (status != RGG_OK) return;
-    const int64_t e0 = (int64_t)tile * kLabelTile + (int64_t)tid * kLabelRun;
+}
+
+// Labels of this thread's run of edges e0 .. e0 + kLabelRun - 1; returns
+// how many are GRAY.
+__device__ __forceinline__ int run_labels(const RmDev &rm, int64_t e0, uint8_t (&lab)[kLabelRun])
+{
     int2 c[kLabelRun];
     load_run(rm, e0, c);
-    // gray edges before this tile
-    int before = 0;
-    for (int t = tid; t < tile; t += kBlock) before += rm.tile_cnt[t];
-    before = block_sum(before, s_w);
-    uint8_t lab[kLabelRun];
     int ng = 0;
 #pragma unroll
     for (int h = 0; h < kLabelRun; ++h) {
         lab[h] = label_of(c[h]);
         ng += (e0 + h < rm.E && lab[h] == RGG_GRAY) ? 1 : 0;
     }
+    return ng;
+}
+
+// Stores a run's labels and its GRAY ids from gray-list position pos on.
+__device__ __forceinline__ void store_run(const RmDev &rm, uint8_t *labels, int64_t *gray, int64_t cap, int64_t e0,
+                                          const uint8_t (&lab)[kLabelRun], int64_t pos)
+{
     if (labels) {
         if (e0 + kLabelRun <= rm.E && ((uintptr_t)(labels + e0) & 15u) == 0) {
             uint32_t wds[kLabelRun / 4];
@@ -1678,11 +1692,7 @@ __device__ __forceinline__ void write_body(const RmDev &rm, uint8_t *labels, int
                 if (e0 + h < rm.E) labels[e0 + h] = lab[h];
         }
     }
-    int tot;
-    const int pre = block_scan(ng, &tot, s_w);
-    if (tid == 0 && tile == rm.ntiles - 1 && res) res->n_gray = (int64_t)before + tot;
-    if (!gray || tot == 0) return;
-    int64_t pos = (int64_t)before + pre;
+    if (!gray) return;
 #pragma unroll
     for (int h = 0; h < kLabelRun; ++h) {
         if (e0 + h < rm.E && lab[h] == RGG_GRAY) {
@@ -1690,6 +1700,133 @@ __device__ __forceinline__ void write_body(const RmDev &rm, uint8_t *labels, int
             ++pos;
         }
     }
+}
+
+// k_write: labels and the ordered gray list, one tile per block (its first
+// position is the sum of the earlier tiles' counts from k_count; the last
+// tile reports n_gray, tile 0 the status); block `ntiles` instead folds the
+// per-block statistics of the update.
+__device__ __forceinline__ void write_body(const RmDev &rm, uint8_t *labels, int64_t *gray, int64_t cap,
+                                          rgg_update_result *res, int force, int tile)
+{
+    __shared__ int s_w[kWaves];
+    const int tid = threadIdx.x;
+    if (tile == rm.ntiles) {
+        if (!force && res) fold_stats(rm, res);
+        return;
+    }
+    const int status = force ? RGG_OK : rm.ctl->status;
+    if (tid == 0 && tile == 0 && res && !force) {
+        res->status = status;
+        res->n_changed = rm.ctl->n_chg;
+        if (status != RGG_OK) res->n_gray = 0;
+    }
+    if (status != RGG_OK) return;
+    const int64_t e0 = (int64_t)tile * kLabelTile + (int64_t)tid * kLabelRun;
+    uint8_t lab[kLabelRun];
+    const int ng = run_labels(rm, e0, lab);
+    // gray edges before this tile
+    int before = 0;
+    for (int t = tid; t < tile; t += kBlock) before += rm.tile_cnt[t];
+    before = block_sum(before, s_w);
+    int tot;
+    const int pre = block_scan(ng, &tot, s_w);
+    if (tid == 0 && tile == rm.ntiles - 1 && res) res->n_gray = (int64_t)before + tot;
+    if (tot == 0 && labels == nullptr) return;
+    store_run(rm, labels, gray, cap, e0, lab, (int64_t)before + pre);
+}
+
+// k_labels: k_count and k_write in one pass.  Blocks take their tiles in
+// dispatch order (a ticket), publish their gray count, and add up the
+// earlier tiles' counts by looking back over their published words,
+// sixty-four at a time, stopping at the nearest tile that already published
+// its inclusive prefix (the decoupled look-back scan of Merrill and Garland,
+// "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016).  A
+// block only waits on tiles whose blocks took earlier tickets and are
+// therefore running, so every wait ends; the waits are bounded all the same
+// and report RGG_E_DEVICE if a bound is ever reached.  The block with the
+// last ticket folds the statistics.  k_diff clears the words and the ticket
+// before each update.
+constexpr unsigned long long kTileAgg = 1ull << 62, kTilePre = 2ull << 62, kTileVal = (1ull << 62) - 1;
+constexpr int kLookBackSpins = 1 << 20;
+
+__device__ __forceinline__ void labels_body(const RmDev &rm, uint8_t *labels, int64_t *gray, int64_t cap,
+                                           rgg_update_result *res)
+{
+    __shared__ int s_w[kWaves];
+    __shared__ int s_tile, s_fail;
+    __shared__ long long s_before;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    if (tid == 0) s_tile = __hip_atomic_fetch_add(&rm.ctl->label_ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int tile = s_tile;
+    if (tile >= rm.ntiles) {
+        // every block has its ticket: the counter starts from zero next time
+        if (tid == 0) __hip_atomic_store(&rm.ctl->label_ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (res) fold_stats(rm, res);
+        return;
+    }
+    const int status = rm.ctl->status;
+    if (tid == 0 && tile == 0 && res) {
+        res->status = status;
+        res->n_changed = rm.ctl->n_chg;
+        if (status != RGG_OK) res->n_gray = 0;
+    }
+    if (status != RGG_OK) return;   // every block returns here: no one waits
+    const int64_t e0 = (int64_t)tile * kLabelTile + (int64_t)tid * kLabelRun;
+    uint8_t lab[kLabelRun];
+    const int ng = run_labels(rm, e0, lab);
+    int tot;
+    const int pre = block_scan(ng, &tot, s_w);
+    unsigned long long *st = rm.tile_state;
+    if (tid == 0)
+        __hip_atomic_store(&st[tile], (tile == 0 ? kTilePre : kTileAgg) | (unsigned long long)tot, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    if (wv == 0) {
+        unsigned long long before = 0;
+        bool fail = false;
+        for (int t = tile - 1; t >= 0; t -= 64) {
+            const int q = t - lane;              // lane l looks at tile t - l
+            unsigned long long v = kTilePre;     // before tile 0: an inclusive prefix of 0
+            bool ready = q < 0;
+            for (int spin = 0;; ++spin) {
+                if (!ready) {
+                    v = __hip_atomic_load(&st[q], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                    ready = (v >> 62) != 0;
+                }
+                if (__ballot(!ready) == 0) break;
+                if (spin >= kLookBackSpins) {
+                    fail = true;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (fail) break;
+            const uint64_t pm = __ballot((v >> 62) == 2);
+            const int stop = pm ? __ffsll((unsigned long long)pm) - 1 : 63;
+            before += wave_sum_u64(lane <= stop ? (v & kTileVal) : 0ull);
+            if (pm) break;
+        }
+        if (lane == 0) {
+            s_before = (long long)before;
+            s_fail = fail ? 1 : 0;
+        }
+    }
+    __syncthreads();
+    const long long before = s_before;
+    if (tid == 0) {
+        __hip_atomic_store(&st[tile], kTilePre | (unsigned long long)(before + tot), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        if (res && s_fail) res->status = RGG_E_DEVICE;
+        if (res && tile == rm.ntiles - 1) res->n_gray = before + tot;
+    }
+    store_run(rm, labels, gray, cap, e0, lab, before + pre);
+}
+
+__global__ void __launch_bounds__(kBlock) k_labels(RmDev rm, uint8_t *labels, int64_t *gray, int64_t cap,
+                                                   rgg_update_result *res, int)
+{
+    labels_body(rm, labels, gray, cap, res);
 }
 
 __global__ void __launch_bounds__(kBlock) k_count(RmDev rm)
@@ -1855,8 +1992,7 @@ int plan(const RmDev &rm, Node out[7])
     if (rm.mixed) {
         out[n++] = {fp64_fn(rm), dim3(kFp64Grid), 1, 5, 5};
     }
-    out[n++] = {(void *)k_count, dim3(rm.ntiles), 1, -1, -1};
-    out[n++] = {(void *)k_write, dim3(rm.ntiles + 1), 4, 6, 6};
+    out[n++] = {(void *)k_labels, dim3(rm.ntiles + 1), 4, 6, 6};
     return n;
 }
 

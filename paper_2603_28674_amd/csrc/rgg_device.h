@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "rgg.h"
@@ -16,17 +17,22 @@ struct Ctl {
     int32_t n_chg;         // changed (box, sign) entries
     int32_t n_items;       // (cell, chunk) work items of the grid scan
     int32_t any_df;        // some item was left whole to the binary64 pass
+    int32_t label_ticket;  // next tile of the one-pass label kernel (dispatch order)
+    int32_t pad;
 };
 
 // One changed obstacle entry: the box a slot held before (sign -1) or holds
 // now (sign +1).  Entries are ordered by slot, old before new.
-struct ChgEntry {
+struct alignas(16) ChgEntry {
+    // the first 32 bytes are what the binary32 kernels stage: two 16-byte loads
     float lo32[3], hi32[3];    // outward-rounded binary32 copy
     float sbox;                // largest |coordinate| of the binary32 copy
     int32_t sign;
     double lo[3], hi[3];       // exact box (unused axes zero)
     int32_t c0[3], c1[3];      // inclusive grid-cell range; empty when c0 > c1
 };
+static_assert(offsetof(ChgEntry, sbox) == 24 && offsetof(ChgEntry, sign) == 28 && alignof(ChgEntry) == 16,
+              "the binary32 part of an entry is two aligned 16-byte words");
 
 // Everything a kernel needs about a roadmap, passed by value.
 struct RmDev {
@@ -75,6 +81,8 @@ struct RmDev {
                                // binary64 pass (its re-test region was full)
     int32_t *df_cnt;           // [kStatBlocks]
     int32_t *tile_cnt;         // [ntiles] gray edges per label tile
+    unsigned long long *tile_state;   // [ntiles] look-back words of the one-pass label
+                                      // kernel: flag (bits 62-63) | gray count
     unsigned long long *blk_stats;   // [kStats][kStatBlocks] per-block partial counts
     Ctl *ctl;
 };
