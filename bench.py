@@ -44,6 +44,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-edges", type=int, default=300000,
                    help="edges the oracle classifies (capped at the roadmap size)")
+    p.add_argument("--cpu-single-edges", type=int, default=20000,
+                   help="edges of the one-thread oracle measurement (0 skips it)")
     p.add_argument("--skip-graph", action="store_true")
     p.add_argument("--seed", type=int, default=2)
     p.add_argument("--no-batched", action="store_true",
@@ -309,7 +311,8 @@ def serving(a):
             bs = [synth.move_sequence(trng, w.boxes[0], w.robot.dim, 1, 25, sigma)[1] for _ in range(4)]
             chosen.append(tune(g, w.boxes[0], bs, reps=2))
         tuned = {"seconds": time.perf_counter() - t0,
-                 "item_edges": {str(v): sum(r["item_edges"] == v for r in chosen) for v in (64, 128, 256)},
+                 "item_edges": {str(v): sum(r["item_edges"] == v for r in chosen)
+                                for v in sorted({r["item_edges"] for r in chosen})},
                  "one_cell": sum(r["cell_size"] is None for r in chosen)}
         log(f"[bench] serving: tuned in {tuned['seconds']:.1f}s")
     srv = rgg.rgg_server_start(ctx, n_streams=4, max_batch=64, pool_bytes=64 << 20)
@@ -381,15 +384,10 @@ def C_void(x):
     return ctypes.c_void_p(x)
 
 
-def cpu_baseline(w, gpu_labels_final, sample_edges, n_updates, seed):
-    """The FP64 oracle, incremental mode, on a sample of the roadmap's edges,
-    over the same obstacle sequence; also spot-checks the GPU's final labels
-    on that sample."""
+def oracle_rate(w, idx, n_updates, threads):
+    """Edges/s of the FP64 oracle's incremental update over updates
+    1..n_updates on the edges idx; returns (rate, final labels)."""
     import oracle
-    rng = np.random.default_rng(seed + 1000)
-    E = w.n_edges
-    idx = np.sort(rng.choice(E, size=min(sample_edges, E), replace=False))
-    threads = min(16, os.cpu_count() or 1)
     o = oracle.Roadmap(w.robot, w.q, w.edges[idx], w.resolution, w.samples_per_edge,
                        w.n_slots, threads)
     o.update(w.absent(), w.boxes[0], threads=threads)
@@ -397,17 +395,53 @@ def cpu_baseline(w, gpu_labels_final, sample_edges, n_updates, seed):
     lab = None
     for u in range(1, n_updates + 1):
         lab, _ = o.update(w.boxes[u - 1], w.boxes[u], threads=threads)
-    dt = time.perf_counter() - t0
-    match = bool(np.array_equal(lab, gpu_labels_final[idx]))
-    return {
-        "value": len(idx) * n_updates / dt,
+    return len(idx) * n_updates / (time.perf_counter() - t0), lab
+
+
+def cpu_baseline(w, gpu_labels_final, sample_edges, n_updates, seed, single_edges):
+    """The FP64 oracle, incremental mode, on a sample of the roadmap's edges
+    (every edge by default), over the same obstacle sequence, on the host's
+    cores (at most 16); also checks the GPU's final labels on that sample.
+    Beside it, the oracle on one thread over a smaller sample."""
+    rng = np.random.default_rng(seed + 1000)
+    E = w.n_edges
+    idx = np.sort(rng.choice(E, size=min(sample_edges, E), replace=False))
+    threads = min(16, os.cpu_count() or 1)
+    rate, lab = oracle_rate(w, idx, n_updates, threads)
+    out = {
+        "value": rate,
         "unit": "edges/s",
         "cores": threads,
         "kind": "oracle",
         "sample": f"{len(idx)} of {E} edges, {n_updates} incremental updates, FP64, "
                   f"{threads} threads",
-        "labels_match_gpu_on_sample": match,
+        "labels_match_gpu_on_sample": bool(np.array_equal(lab, gpu_labels_final[idx])),
     }
+    if single_edges > 0:
+        idx1 = np.sort(rng.choice(E, size=min(single_edges, E), replace=False))
+        rate1, _ = oracle_rate(w, idx1, n_updates, 1)
+        out["single_thread"] = {"value": rate1, "unit": "edges/s", "cores": 1,
+                                "sample": f"{len(idx1)} of {E} edges, {n_updates} incremental "
+                                          f"updates, FP64, 1 thread"}
+    return out
+
+
+def copy_bandwidth(torch, dev):
+    """HBM bandwidth a plain device-to-device copy of 1 GiB reaches (read +
+    write bytes over the HIP-event time of 10 copies)."""
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * src.numel() * 4 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
 
 
 def main():
@@ -532,6 +566,9 @@ def main():
         g2.close()
 
     test_bytes = np.mean([r.test_bytes for r in results[K:2 * K]])   # the event-timed updates
+    stats_tp = {k: float(np.mean([getattr(r, k) for r in results[:K]]))   # the throughput pass
+                for k in ("n_pairs", "n_outer_hits", "test_bytes")}
+    copy_gbs = copy_bandwidth(torch, dev)
     test_ms = ms[3] / max(n_timed, 1)
     achieved = test_bytes / (test_ms * 1e-3) / 1e9
     stats = {k: float(np.mean([getattr(r, k) for r in results]))
@@ -569,12 +606,17 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("k_item32<3>"),
                      "kernel": "k_item32<3>", "bytes_per_launch": test_bytes,
-                     "kernel_ms": test_ms},
+                     "kernel_ms": test_ms, "copy_GBps": copy_gbs,
+                     "frac_of_copy": achieved / copy_gbs},
+        "work_rates": {"pairs_per_s": stats_tp["n_pairs"] * K / wall,
+                       "outer_hits_per_s": stats_tp["n_outer_hits"] * K / wall,
+                       "classify_bytes_per_s": stats_tp["test_bytes"] * K / wall},
         "cpu_baseline": None,
     }
     if not a.no_cpu_baseline:
         log("[bench] cpu baseline (oracle on a sample)")
-        line["cpu_baseline"] = cpu_baseline(w, final_labels, a.cpu_sample_edges, last, a.seed)
+        line["cpu_baseline"] = cpu_baseline(w, final_labels, a.cpu_sample_edges, last, a.seed,
+                                            a.cpu_single_edges)
     g.close()
     if not a.no_other_configs:
         log("[bench] planar and arm workloads")
