@@ -448,7 +448,7 @@ def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {a.gpus}); the update path is not "
-              f"sharded across GPUs in this build", file=sys.stderr)
+              f"sharded across GPUs", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2603_28674_amd import rgg, synth

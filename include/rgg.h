@@ -54,7 +54,7 @@ typedef int32_t rgg_status;
 #define RGG_E_STATE_MISMATCH (-3)  /* `old` differs from the resident slots  */
 #define RGG_E_CAPACITY (-4)        /* gray list longer than the caller's cap */
 #define RGG_E_DEVICE (-5)          /* HIP runtime error                      */
-#define RGG_E_UNSUPPORTED (-6)     /* valid request this build cannot serve  */
+#define RGG_E_UNSUPPORTED (-6)     /* valid request the library cannot serve */
 #define RGG_E_BUSY (-7)            /* server queue full; submit again later  */
 
 /* robot kinds */
