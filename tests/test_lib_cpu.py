@@ -120,3 +120,25 @@ def test_invalid_inputs_rejected():
     with pytest.raises(rgg.RggError):
         rgg.rgg_debug_geometry(desc, rgg.make_robot(w3.robot, keep),
                                rgg.make_opts(0.0, 20, n_obstacle_slots=1), 0, 1)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """No fallback path: without librgg.so every call raises."""
+    monkeypatch.setattr(rgg, "_lib", None)
+    monkeypatch.setattr(rgg, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "librgg.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        rgg.lib()
+    with pytest.raises(RuntimeError, match="missing"):
+        rgg.rgg_context_create(0)
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; asked for more it exits with a message
+    before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
