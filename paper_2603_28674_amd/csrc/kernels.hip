@@ -17,15 +17,18 @@
 //   k_fp64      which decides it in binary64, one wavefront per pair; an
 //               item whose block ran out of re-test room is then run again
 //               whole in binary64 by the same kernel (skipped otherwise);
-//   k_count + k_write   labels from the counters and the ordered gray list.
+//   k_labels    labels from the counters and the ordered gray list, in one
+//               pass (k_count + k_write, the two-pass form, serve the label
+//               queries and the batch).
 // The *_batch kernels run the same stages for many roadmaps in one launch
 // each, reading every roadmap's arguments from a request table.
 //
 // Binary64 code is compiled without FMA contraction and its sums run left to
 // right from 0.0, so a re-test reproduces the definition's values exactly.
-// No hot path uses a single global counter: on MI355X device-scope atomics on
+// Hot loops use no single global counter: on MI355X device-scope atomics on
 // one address serialise across the eight XCDs, so work lists are positional
-// and statistics are per-block partial sums.
+// and statistics are per-block partial sums (k_labels takes one ticket per
+// 4096-edge tile, a few dozen per update).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
