@@ -36,7 +36,7 @@ def roadmap_specs(n_updates):
 def oracle_results(specs, n_updates):
     import oracle
     out = []
-    for w, _, _ in specs:
+    for w, *_ in specs:
         o = oracle.from_workload(w)
         prev, per = w.absent(), []
         for u in range(n_updates):
@@ -52,9 +52,10 @@ def run_server(ctx, specs, n_updates, mixed, **opts):
     import torch
     from paper_2603_28674_amd import rgg
     dev = torch.device("cuda:0")
-    gs = [rgg.Roadmap.from_workload(ctx, w, precision=p, cell_size=c) for w, p, c in specs]
+    gs = [rgg.Roadmap.from_workload(ctx, w, precision=p, cell_size=c, item_edges=(ie[0] if ie else 0))
+          for w, p, c, *ie in specs]
     outs = {}
-    for k, (w, _, _) in enumerate(specs):
+    for k, (w, *_) in enumerate(specs):
         for u in range(n_updates):
             outs[(k, u)] = (torch.zeros(w.n_edges, dtype=torch.uint8, device=dev),
                             torch.zeros(max(w.n_edges, 1), dtype=torch.int64, device=dev))
@@ -87,7 +88,7 @@ def run_server(ctx, specs, n_updates, mixed, **opts):
 def test_server_alone_and_in_the_mix(ctx):
     n_updates = 4
     specs = roadmap_specs(n_updates)
-    for w, p, c in specs:
+    for w, p, c, *_ in specs:
         print(f"[server] {w.name} E={w.n_edges} M={w.n_slots} prec={p} cell={c}", flush=True)
     expect = oracle_results(specs, n_updates)
     print("[server] alone", flush=True)
@@ -113,7 +114,7 @@ def test_server_small_pool_admits_by_memory(ctx):
     n_updates = 3
     specs = roadmap_specs(n_updates)[:3]
     expect = oracle_results(specs, n_updates)
-    largest = max(w.n_slots for w, _, _ in specs)
+    largest = max(w.n_slots for w, *_ in specs)
     pool = ((2 * largest * 48 + 255) // 256) * 256
     print(f"[server] pool {pool} bytes", flush=True)
     got = run_server(ctx, specs, n_updates, mixed=True, n_streams=2, pool_bytes=pool)
@@ -145,3 +146,24 @@ def test_server_errors(ctx):
     rgg.rgg_server_stop(srv)
     assert np.all(g.labels() == 0)
     g.close()
+
+
+def test_server_mixed_decompositions(ctx):
+    """Roadmaps with different work decompositions (one cell or a grid; work
+    items of 64 to 512 edges) share batches: every result is the oracle's."""
+    from paper_2603_28674_amd import rgg
+    n_updates = 3
+    fp32, fp64 = rgg.RGG_PREC_FP32_RECHECK, rgg.RGG_PREC_FP64
+    specs = [
+        (synth.spatial_rigid(seed=81, n_nodes=2000, n_boxes=80, n_updates=n_updates, world=4.0), fp32, -1.0, 512),
+        (synth.spatial_rigid(seed=82, n_nodes=1500, n_boxes=60, n_updates=n_updates, world=4.0), fp32, 0.0, 64),
+        (synth.planar_arm(seed=83, n_nodes=1500, n_boxes=30, n_updates=n_updates), fp32, -1.0, 300),
+        (synth.planar_rigid(seed=84, n_nodes=1200, n_boxes=30, n_updates=n_updates), fp64, 0.0, 128),
+        (synth.planar_rigid(seed=85, n_nodes=1000, n_boxes=25, n_updates=n_updates), fp32, 0.0, 200),
+    ]
+    expect = oracle_results(specs, n_updates)
+    got = run_server(ctx, specs, n_updates, mixed=True, n_streams=2, max_batch=5)
+    for (k, u), (lab, n_gray, gray, status, lat) in got.items():
+        ol, og = expect[k][u]
+        assert status == 0, f"roadmap {k} update {u}: status {status}"
+        assert n_gray == len(og) and np.array_equal(lab, ol) and np.array_equal(gray, og), f"roadmap {k} update {u}"
