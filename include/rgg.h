@@ -101,7 +101,11 @@ typedef struct {
                                      SE3 quaternions (qw,qx,qy,qz) unit length   */
     int64_t n_edges;
     const int64_t *edge_uv;       /* [n_edges][2] host node ids; the caller's
-                                     edge order is the order of every output    */
+                                     edge order is the order of every output.
+                                     An edge (v, v) is node v (Sec. 2.1: a node
+                                     is a degenerate edge): its one configuration
+                                     gives node v's label, RED or GREEN, never
+                                     GRAY                                       */
 } rgg_roadmap_desc;
 
 typedef struct {
@@ -323,6 +327,24 @@ rgg_status rgg_tune(rgg_roadmap *rm, int64_t m, const rgg_box *obstacles_a, int3
  * Other errors as for rgg_tune. */
 rgg_status rgg_batch_tune(rgg_batch *b, const rgg_box *const *obstacles_a, const rgg_box *const *obstacles_b,
                           int32_t reps, rgg_tune_report *report);
+
+/* Persistence between planning iterations (Sec. 1 and Sec. 3.3: the
+ * approximations are computed once and then stored and reloaded).
+ * rgg_save writes `rm` to the file `path`: its binary64 sphere centres and
+ * capsules, edge boxes, sphere radii, the resident obstacle slots, the per-edge
+ * counters, the precision mode, band, re-test capacity and the work
+ * decomposition (cell size, edges per item), followed by an FNV-1a 64-bit
+ * checksum; host byte order, format version 1.  It first waits for the
+ * roadmap's queued updates.  RGG_E_BUSY if a graph, batch or server request
+ * holds the roadmap; RGG_E_INVALID_ARG if the file cannot be written.
+ * rgg_load builds a roadmap on ctx's device from such a file without
+ * recomputing the kinematics: its labels, gray list and every later update
+ * equal those of the saved roadmap.  RGG_E_INVALID_ARG if the file cannot be
+ * read, is not a roadmap file, has another version, an inconsistent header,
+ * is truncated or fails the checksum; RGG_E_OUT_OF_MEMORY, RGG_E_DEVICE.
+ * *out receives the roadmap (destroy it with rgg_destroy). */
+rgg_status rgg_save(rgg_roadmap *rm, const char *path);
+rgg_status rgg_load(rgg_context *ctx, const char *path, rgg_roadmap **out);
 
 /* Request server (continuous batching).  A worker thread takes the queued
  * updates of device-resident roadmaps to the GPU as batches (one launch per

@@ -381,41 +381,41 @@ rgg_status rgg_context_create(int device, rgg_context **out)
 
 void rgg_context_destroy(rgg_context *ctx) { delete ctx; }
 
-rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_robot *robot,
-                     const rgg_build_opts *opts, rgg_roadmap **out)
+namespace {
+
+// What a roadmap's device state is built from besides its geometry and grid.
+struct RoadmapParams {
+    int64_t M;                 // obstacle slots
+    bool mixed;                // binary32 tests with the binary64 re-test
+    double band_rel;           // as rgg_build_opts.band_rel
+    int32_t retest_capacity;   // as rgg_build_opts.retest_capacity
+    int32_t chunk;             // edges per work item
+};
+
+rgg_status hip_ok(hipError_t e, const char *what) { return e == hipSuccess ? RGG_OK : hip_fail(e, what); }
+
+// Device arrays, scratch and state of a roadmap from its host geometry and
+// grid.  resident and cnt (may be null) are the obstacle slots and counters
+// to start from; otherwise every slot is ABSENT and every counter zero.  On
+// failure nothing is left allocated.
+rgg_status make_roadmap(rgg_context *ctx, const HostGeometry &g, const HostGrid &grid, const RoadmapParams &p,
+                        const rgg_box *resident, const int2 *cnt, rgg_roadmap **out)
 {
-    if (!ctx || !out) return fail(RGG_E_INVALID_ARG, "null context or output pointer");
-    std::string err;
-    rgg_status st = validate_build_inputs(rd, robot, opts, &err);
-    if (st != RGG_OK) return fail(st, "%s", err.c_str());
-    auto t0 = std::chrono::steady_clock::now();
-    HIP_OR_FAIL(hipSetDevice(ctx->device), "hipSetDevice");
-
-    HostGeometry g;
-    st = build_geometry(rd, robot, opts, 0, rd->n_edges, host_threads(opts->host_threads), &g, &err);
-    if (st != RGG_OK) return fail(st, "%s", err.c_str());
-    if (g.B > 0 && g.soff.back() / g.B > (int64_t)UINT32_MAX)
-        return fail(RGG_E_INVALID_ARG, "%lld configurations over all edges; at most 2^32 - 1",
-                    (long long)(g.soff.back() / g.B));
-    const int32_t chunk = opts->item_edges > 0 ? opts->item_edges : kChunk;
-    HostGrid grid;
-    st = build_grid(g, opts->cell_size, chunk, &grid, &err);
-    if (st != RGG_OK) return fail(st, "%s", err.c_str());
-
+    rgg_status st;
     auto *rm = new rgg_roadmap();
     rm->ctx = ctx;
     rm->device = ctx->device;
-    const int64_t E = g.E, M = opts->n_obstacle_slots;
+    const int64_t E = g.E, M = p.M;
     const int D = g.D, B = g.B;
-    const bool mixed = opts->precision == RGG_PREC_FP32_RECHECK;
+    const bool mixed = p.mixed;
     RmDev &dv = rm->dv;
     dv.D = D;
     dv.B = B;
     dv.mixed = mixed ? 1 : 0;
     dv.E = E;
     dv.M = M;
-    dv.band_rel = (float)(opts->band_rel > 0.0 ? opts->band_rel : 1e-5);
-    if (std::isinf(opts->band_rel)) dv.band_rel = INFINITY;
+    dv.band_rel = (float)(p.band_rel > 0.0 ? p.band_rel : 1e-5);
+    if (std::isinf(p.band_rel)) dv.band_rel = INFINITY;
     dv.ntiles = (int32_t)std::max<int64_t>(1, (E + kLabelTile - 1) / kLabelTile);
     dv.p_fixed = 0;
     if (E > 0) {
@@ -464,7 +464,7 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
         dv.samp32 = s32;
         dv.cap32 = c32;
     }
-    if ((st = install_grid(rm, grid, chunk)) != RGG_OK) return guard(st);
+    if ((st = install_grid(rm, grid, p.chunk)) != RGG_OK) return guard(st);
     // state and scratch
     std::vector<rgg_box> absent((size_t)M);
     for (auto &b : absent)
@@ -473,9 +473,10 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
             b.hi[k] = -1.0;
         }
     if ((st = rm->alloc(&dv.cnt, (size_t)E, "counters")) != RGG_OK) return guard(st);
-    if ((st = rm->upload(&dv.resident, absent.data(), (size_t)M, "obstacle slots")) != RGG_OK) return guard(st);
+    if ((st = rm->upload(&dv.resident, resident ? resident : absent.data(), (size_t)M, "obstacle slots")) != RGG_OK)
+        return guard(st);
     if ((st = rm->alloc(&dv.chg, (size_t)(2 * M), "changed entries")) != RGG_OK) return guard(st);
-    dv.rc_cap = opts->retest_capacity > 0 ? opts->retest_capacity : kRcCap;
+    dv.rc_cap = p.retest_capacity > 0 ? p.retest_capacity : kRcCap;
     if ((st = rm->alloc(&dv.rc, (size_t)kStatBlocks * dv.rc_cap, "re-test regions")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.rc_cnt, (size_t)kStatBlocks, "re-test counts")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.df_cnt, (size_t)kStatBlocks, "deferred counts")) != RGG_OK) return guard(st);
@@ -487,18 +488,22 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     if ((st = rm->alloc(&rm->d_res, 1, "result")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&rm->d_labels, (size_t)E, "labels")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&rm->d_gray, (size_t)E, "gray list")) != RGG_OK) return guard(st);
-    HIP_OR_FAIL(hipMemset(dv.cnt, 0, sizeof(int2) * std::max<int64_t>(E, 1)), "clear counters");
-    HIP_OR_FAIL(hipMemset(dv.ctl, 0, sizeof(Ctl)), "clear control");
-    HIP_OR_FAIL(hipMemset(dv.tile_state, 0, sizeof(unsigned long long) * dv.ntiles), "clear tile states");
-    HIP_OR_FAIL(hipMemset(dv.rc_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear re-test counts");
-    HIP_OR_FAIL(hipMemset(dv.df_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear deferred counts");
-    HIP_OR_FAIL(hipMemset(dv.blk_stats, 0, sizeof(unsigned long long) * kStatBlocks * kStats), "clear statistics");
-    HIP_OR_FAIL(hipMemset(rm->d_labels, 0, std::max<int64_t>(E, 1)), "clear labels");
-    HIP_OR_FAIL(hipHostMalloc((void **)&rm->h_stage, sizeof(rgg_box) * std::max<int64_t>(2 * M, 1)), "pinned staging");
-    HIP_OR_FAIL(hipHostMalloc((void **)&rm->h_res, sizeof(rgg_update_result)), "pinned result");
-    HIP_OR_FAIL(hipStreamCreateWithFlags(&rm->stream, hipStreamNonBlocking), "stream");
-    HIP_OR_FAIL(hipEventCreateWithFlags(&rm->done, hipEventDisableTiming), "event");
-    HIP_OR_FAIL(hipDeviceSynchronize(), "build upload");
+    if (cnt && E > 0)
+        st = hip_ok(hipMemcpy(dv.cnt, cnt, sizeof(int2) * E, hipMemcpyHostToDevice), "restore counters");
+    else
+        st = hip_ok(hipMemset(dv.cnt, 0, sizeof(int2) * std::max<int64_t>(E, 1)), "clear counters");
+    if (st != RGG_OK) return guard(st);
+    if ((st = hip_ok(hipMemset(dv.ctl, 0, sizeof(Ctl)), "clear control")) != RGG_OK) return guard(st);
+    if ((st = hip_ok(hipMemset(dv.tile_state, 0, sizeof(unsigned long long) * dv.ntiles), "clear tile states")) != RGG_OK) return guard(st);
+    if ((st = hip_ok(hipMemset(dv.rc_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear re-test counts")) != RGG_OK) return guard(st);
+    if ((st = hip_ok(hipMemset(dv.df_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear deferred counts")) != RGG_OK) return guard(st);
+    if ((st = hip_ok(hipMemset(dv.blk_stats, 0, sizeof(unsigned long long) * kStatBlocks * kStats), "clear statistics")) != RGG_OK) return guard(st);
+    if ((st = hip_ok(hipMemset(rm->d_labels, 0, std::max<int64_t>(E, 1)), "clear labels")) != RGG_OK) return guard(st);
+    if ((st = hip_ok(hipHostMalloc((void **)&rm->h_stage, sizeof(rgg_box) * std::max<int64_t>(2 * M, 1)), "pinned staging")) != RGG_OK) return guard(st);
+    if ((st = hip_ok(hipHostMalloc((void **)&rm->h_res, sizeof(rgg_update_result)), "pinned result")) != RGG_OK) return guard(st);
+    if ((st = hip_ok(hipStreamCreateWithFlags(&rm->stream, hipStreamNonBlocking), "stream")) != RGG_OK) return guard(st);
+    if ((st = hip_ok(hipEventCreateWithFlags(&rm->done, hipEventDisableTiming), "event")) != RGG_OK) return guard(st);
+    if ((st = hip_ok(hipDeviceSynchronize(), "build upload")) != RGG_OK) return guard(st);
 
     rgg_roadmap_info &in = rm->info;
     in.n_edges = E;
@@ -506,7 +511,38 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     in.dim = D;
     in.n_spheres = B;
     in.n_sphere_samples = g.soff.back();
-    in.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = rm;
+    return RGG_OK;
+}
+
+}  // namespace
+
+rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_robot *robot,
+                     const rgg_build_opts *opts, rgg_roadmap **out)
+{
+    if (!ctx || !out) return fail(RGG_E_INVALID_ARG, "null context or output pointer");
+    std::string err;
+    rgg_status st = validate_build_inputs(rd, robot, opts, &err);
+    if (st != RGG_OK) return fail(st, "%s", err.c_str());
+    auto t0 = std::chrono::steady_clock::now();
+    HIP_OR_FAIL(hipSetDevice(ctx->device), "hipSetDevice");
+
+    HostGeometry g;
+    st = build_geometry(rd, robot, opts, 0, rd->n_edges, host_threads(opts->host_threads), &g, &err);
+    if (st != RGG_OK) return fail(st, "%s", err.c_str());
+    if (g.B > 0 && g.soff.back() / g.B > (int64_t)UINT32_MAX)
+        return fail(RGG_E_INVALID_ARG, "%lld configurations over all edges; at most 2^32 - 1",
+                    (long long)(g.soff.back() / g.B));
+    const int32_t chunk = opts->item_edges > 0 ? opts->item_edges : kChunk;
+    HostGrid grid;
+    st = build_grid(g, opts->cell_size, chunk, &grid, &err);
+    if (st != RGG_OK) return fail(st, "%s", err.c_str());
+
+    const RoadmapParams p = {opts->n_obstacle_slots, opts->precision == RGG_PREC_FP32_RECHECK, opts->band_rel,
+                             opts->retest_capacity, chunk};
+    rgg_roadmap *rm = nullptr;
+    if ((st = make_roadmap(ctx, g, grid, p, nullptr, nullptr, &rm)) != RGG_OK) return st;
+    rm->info.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = rm;
     return RGG_OK;
 }
@@ -1031,6 +1067,200 @@ rgg_status rgg_batch_tune(rgg_batch *b, const rgg_box *const *obstacles_a, const
         st = finish_update(rm, s);
         if (st != RGG_OK) return st;
     }
+    return RGG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Roadmap files: a header, the binary64 geometry, the state, and an FNV-1a
+// 64-bit checksum of every preceding byte.  Host byte order.
+constexpr char kMagic[8] = {'R', 'G', 'G', 'M', 'A', 'P', '0', '1'};
+constexpr uint32_t kFileVersion = 1;
+
+struct FileHeader {
+    char magic[8];
+    uint32_t version;
+    int32_t D, B, mixed, chunk, retest_capacity;
+    int64_t E, M;
+    float band_rel;
+    int32_t one_cell;
+    double cell;
+    int64_t n_samp, n_cap;
+};
+
+struct Fnv {
+    uint64_t h = 1469598103934665603ull;
+    void add(const void *p, size_t n)
+    {
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    }
+};
+
+struct FileOut {
+    FILE *f = nullptr;
+    Fnv sum;
+    bool ok = true;
+    ~FileOut()
+    {
+        if (f) fclose(f);
+    }
+    void put(const void *p, size_t n)
+    {
+        if (!ok || n == 0) return;
+        sum.add(p, n);
+        ok = fwrite(p, 1, n, f) == n;
+    }
+};
+
+struct FileIn {
+    FILE *f = nullptr;
+    Fnv sum;
+    bool ok = true;
+    ~FileIn()
+    {
+        if (f) fclose(f);
+    }
+    void get(void *p, size_t n)
+    {
+        if (!ok || n == 0) return;
+        ok = fread(p, 1, n, f) == n;
+        if (ok) sum.add(p, n);
+    }
+};
+
+template <typename T>
+rgg_status read_back(std::vector<T> *v, const T *d, size_t n, const char *what)
+{
+    try {
+        v->resize(n);
+    } catch (const std::bad_alloc &) {
+        return fail(RGG_E_OUT_OF_MEMORY, "host memory for %s", what);
+    }
+    if (n) HIP_OR_FAIL(hipMemcpy(v->data(), d, sizeof(T) * n, hipMemcpyDeviceToHost), what);
+    return RGG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rgg_status rgg_save(rgg_roadmap *rm, const char *path)
+{
+    if (!rm || !path) return fail(RGG_E_INVALID_ARG, "null argument");
+    if (rm->holders.load() > 0)
+        return fail(RGG_E_BUSY, "the roadmap is held by a graph, a batch or a server request");
+    HIP_OR_FAIL(hipSetDevice(rm->device), "hipSetDevice");
+    if (rm->wait_ev) HIP_OR_FAIL(hipEventSynchronize(rm->wait_ev), "wait for the previous update");
+    HIP_OR_FAIL(hipStreamSynchronize(rm->stream), "roadmap stream");
+    const RmDev &dv = rm->dv;
+    const int64_t E = dv.E, M = dv.M;
+    std::vector<int64_t> soff;
+    std::vector<double> samp, cap, rad;
+    std::vector<float> aabb;
+    std::vector<rgg_box> resident;
+    std::vector<int2> cnt;
+    rgg_status st;
+    if ((st = read_back(&soff, dv.soff, (size_t)(E + 1), "sample offsets")) != RGG_OK) return st;
+    const int64_t n_samp = (int64_t)copy_stride(dv.D) * soff.back();
+    const int64_t n_cap = E * (2 * dv.D + 1) * dv.B;
+    if ((st = read_back(&samp, dv.samp64, (size_t)n_samp, "samples")) != RGG_OK) return st;
+    if ((st = read_back(&cap, dv.cap64, (size_t)n_cap, "capsules")) != RGG_OK) return st;
+    if ((st = read_back(&rad, dv.rad64, (size_t)dv.B, "radii")) != RGG_OK) return st;
+    if ((st = read_back(&aabb, dv.aabb, (size_t)(E * kAabbStride), "edge boxes")) != RGG_OK) return st;
+    if ((st = read_back(&resident, dv.resident, (size_t)M, "obstacle slots")) != RGG_OK) return st;
+    if ((st = read_back(&cnt, dv.cnt, (size_t)E, "counters")) != RGG_OK) return st;
+    FileHeader h = {};
+    memcpy(h.magic, kMagic, sizeof kMagic);
+    h.version = kFileVersion;
+    h.D = dv.D;
+    h.B = dv.B;
+    h.mixed = dv.mixed;
+    h.chunk = dv.chunk;
+    h.retest_capacity = dv.rc_cap;
+    h.E = E;
+    h.M = M;
+    h.band_rel = dv.band_rel;
+    h.one_cell = std::isfinite(rm->info.cell_size) ? 0 : 1;
+    h.cell = rm->info.cell_size;
+    h.n_samp = n_samp;
+    h.n_cap = n_cap;
+    FileOut out;
+    out.f = fopen(path, "wb");
+    if (!out.f) return fail(RGG_E_INVALID_ARG, "cannot open %s for writing", path);
+    out.put(&h, sizeof h);
+    out.put(soff.data(), sizeof(int64_t) * soff.size());
+    out.put(samp.data(), sizeof(double) * samp.size());
+    out.put(cap.data(), sizeof(double) * cap.size());
+    out.put(rad.data(), sizeof(double) * rad.size());
+    out.put(aabb.data(), sizeof(float) * aabb.size());
+    out.put(resident.data(), sizeof(rgg_box) * resident.size());
+    out.put(cnt.data(), sizeof(int2) * cnt.size());
+    const uint64_t sum = out.sum.h;
+    out.put(&sum, sizeof sum);
+    if (!out.ok || fflush(out.f) != 0) return fail(RGG_E_INVALID_ARG, "writing %s failed", path);
+    return RGG_OK;
+}
+
+rgg_status rgg_load(rgg_context *ctx, const char *path, rgg_roadmap **out)
+{
+    if (!ctx || !path || !out) return fail(RGG_E_INVALID_ARG, "null argument");
+    auto t0 = std::chrono::steady_clock::now();
+    FileIn in;
+    in.f = fopen(path, "rb");
+    if (!in.f) return fail(RGG_E_INVALID_ARG, "cannot open %s", path);
+    FileHeader h;
+    in.get(&h, sizeof h);
+    if (!in.ok || memcmp(h.magic, kMagic, sizeof kMagic) != 0) return fail(RGG_E_INVALID_ARG, "%s is not a roadmap file", path);
+    if (h.version != kFileVersion) return fail(RGG_E_INVALID_ARG, "roadmap file version %u, expected %u", h.version, kFileVersion);
+    if ((h.D != 2 && h.D != 3) || h.B < 1 || h.B > kMaxSpheres || h.E < 0 || h.E > INT32_MAX || h.M < 0 ||
+        h.M > 4096 || h.chunk < 1 || h.chunk > 512 || h.retest_capacity < 1 ||
+        h.retest_capacity > (1 << 20) || !(h.band_rel > 0.0f) || h.n_cap != h.E * (2 * h.D + 1) * h.B || h.n_samp < 0)
+        return fail(RGG_E_INVALID_ARG, "%s: inconsistent header", path);
+    HostGeometry g;
+    g.D = h.D;
+    g.B = h.B;
+    g.E = h.E;
+    try {
+        g.soff.resize((size_t)(h.E + 1));
+        in.get(g.soff.data(), sizeof(int64_t) * g.soff.size());
+        if (!in.ok || g.soff[0] != 0 || (int64_t)copy_stride(h.D) * g.soff.back() != h.n_samp)
+            return fail(RGG_E_INVALID_ARG, "%s: inconsistent sample offsets", path);
+        for (int64_t e = 0; e < h.E; ++e)
+            if (g.soff[(size_t)e + 1] < g.soff[(size_t)e] || (g.soff[(size_t)e + 1] - g.soff[(size_t)e]) % h.B != 0)
+                return fail(RGG_E_INVALID_ARG, "%s: inconsistent sample offsets", path);
+        g.samp.resize((size_t)h.n_samp);
+        g.cap.resize((size_t)h.n_cap);
+        g.radius.resize((size_t)h.B);
+        g.aabb.resize((size_t)h.E * kAabbStride);
+    } catch (const std::bad_alloc &) {
+        return fail(RGG_E_OUT_OF_MEMORY, "host memory for %s", path);
+    }
+    std::vector<rgg_box> resident((size_t)h.M);
+    std::vector<int2> cnt((size_t)h.E);
+    in.get(g.samp.data(), sizeof(double) * g.samp.size());
+    in.get(g.cap.data(), sizeof(double) * g.cap.size());
+    in.get(g.radius.data(), sizeof(double) * g.radius.size());
+    in.get(g.aabb.data(), sizeof(float) * g.aabb.size());
+    in.get(resident.data(), sizeof(rgg_box) * resident.size());
+    in.get(cnt.data(), sizeof(int2) * cnt.size());
+    const uint64_t want = in.sum.h;
+    uint64_t sum = 0;
+    if (in.ok) in.get(&sum, sizeof sum);
+    if (!in.ok) return fail(RGG_E_INVALID_ARG, "%s is truncated", path);
+    if (sum != want) return fail(RGG_E_INVALID_ARG, "%s: checksum mismatch", path);
+    HIP_OR_FAIL(hipSetDevice(ctx->device), "hipSetDevice");
+    HostGrid grid;
+    std::string err;
+    rgg_status st = build_grid(g, h.one_cell ? -1.0 : h.cell, h.chunk, &grid, &err);
+    if (st != RGG_OK) return fail(st, "%s", err.c_str());
+    const RoadmapParams p = {h.M, h.mixed != 0, (double)h.band_rel, h.retest_capacity, h.chunk};
+    rgg_roadmap *rm = nullptr;
+    if ((st = make_roadmap(ctx, g, grid, p, resident.data(), cnt.data(), &rm)) != RGG_OK) return st;
+    rm->info.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = rm;
     return RGG_OK;
 }
 

@@ -129,7 +129,8 @@ EXPORTS = ["rgg_context_create", "rgg_context_destroy", "rgg_build", "rgg_destro
            "rgg_graph_launch", "rgg_graph_destroy", "rgg_batch_create", "rgg_batch_launch",
            "rgg_batch_launch_graph", "rgg_batch_destroy", "rgg_update_batch", "rgg_server_start",
            "rgg_server_submit", "rgg_server_poll", "rgg_server_stop", "rgg_labels", "rgg_gray_list",
-           "rgg_timing_enable", "rgg_timing_read", "rgg_tune", "rgg_batch_tune", "rgg_debug_geometry",
+           "rgg_timing_enable", "rgg_timing_read", "rgg_tune", "rgg_batch_tune", "rgg_save", "rgg_load",
+           "rgg_debug_geometry",
            "rgg_last_error", "rgg_version"]
 
 _lib = None
@@ -170,6 +171,8 @@ def lib():
         "rgg_timing_read": (I32, [P, P, P]),
         "rgg_tune": (I32, [P, I64, P, I32, P, I32, P]),
         "rgg_batch_tune": (I32, [P, P, P, I32, P]),
+        "rgg_save": (I32, [P, C.c_char_p]),
+        "rgg_load": (I32, [P, C.c_char_p, C.POINTER(P)]),
         "rgg_debug_geometry": (I32, [P, P, P, I64, I64, P, P, P, P]),
         "rgg_last_error": (C.c_char_p, []),
         "rgg_version": (C.c_char_p, []),
@@ -442,6 +445,16 @@ def rgg_batch_tune(batch, a_list, b_list, reps=0):
     return rep.as_dict()
 
 
+def rgg_save(rm, path):
+    _check(lib().rgg_save(rm, os.fsencode(path)))
+
+
+def rgg_load(ctx, path):
+    h = C.c_void_p()
+    _check(lib().rgg_load(ctx, os.fsencode(path), C.byref(h)))
+    return h
+
+
 def rgg_debug_geometry(desc, robot, opts, e0, e1):
     """Host build stage of edges [e0, e1): (n_configs, centres, capsules, boxes)."""
     L = lib()
@@ -510,6 +523,18 @@ class Roadmap:
 
     def tune(self, a, bs, reps=0):
         return rgg_tune(self.h, a, bs, reps)
+
+    def save(self, path):
+        rgg_save(self.h, path)
+
+    @classmethod
+    def load(cls, ctx, path):
+        """A roadmap read back from a file rgg_save wrote."""
+        self = cls.__new__(cls)
+        self.h = rgg_load(ctx, path)
+        info = rgg_roadmap_info_get(self.h)
+        self.E, self.M = int(info.n_edges), int(info.n_slots)
+        return self
 
     def close(self):
         if getattr(self, "h", None):
