@@ -72,6 +72,10 @@ def lib():
         L.orc_point_box_d2.argtypes = [C.c_int, P, P]
         L.orc_segbox_fmin.restype = D
         L.orc_segbox_fmin.argtypes = [C.c_int, P, P, P]
+        L.orc_rm_validate.restype = C.c_int
+        L.orc_rm_validate.argtypes = [P, P, I64, C.c_int, C.c_int, P, P, P, C.c_int]
+        L.orc_vsincos.argtypes = [D, P, P]
+        L.orc_centres_v.argtypes = [P, P, P, D, P]
         _lib = L
     return _lib
 
@@ -124,9 +128,22 @@ class Robot:
         lib().orc_deltas(self.h, _p(_f64(qa)), _p(_f64(qb)), _p(out))
         return out
 
+    def centres_v(self, qa, qb, t):
+        """Sphere centres at parameter t as the full validation evaluates them."""
+        out = np.zeros((self.B, self.D))
+        lib().orc_centres_v(self.h, _p(_f64(qa)), _p(_f64(qb)), float(t), _p(out))
+        return out
+
     def n_segments(self, qa, qb, resolution, samples_per_edge=0):
         return int(lib().orc_n_segments(self.h, _p(_f64(qa)), _p(_f64(qb)), float(resolution),
                                         int(samples_per_edge)))
+
+
+def vsincos(x):
+    """The validation's sin and cos (fixed binary64 steps)."""
+    s, c = C.c_double(0.0), C.c_double(0.0)
+    lib().orc_vsincos(float(x), C.byref(s), C.byref(c))
+    return s.value, c.value
 
 
 def point_box_d2(c, box, D=None):
@@ -186,6 +203,21 @@ class Roadmap:
         if n < 0:
             raise ValueError(f"oracle update failed ({n})")
         return lab, gray[:n].copy()
+
+    def validate(self, ids, max_level=24, max_active=256, threads=None):
+        """Full validation (continuous collision check) of edges ``ids``
+        against the resident obstacles: (verdict, level, witness) arrays;
+        verdict 0 FREE, 2 COLLIDES, 3 UNRESOLVED."""
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        n = ids.shape[0]
+        verdict = np.zeros(max(n, 1), dtype=np.uint8)
+        level = np.zeros(max(n, 1), dtype=np.int32)
+        witness = np.zeros(max(n, 1), dtype=np.float64)
+        st = lib().orc_rm_validate(self.h, _p(ids), n, int(max_level), int(max_active), _p(verdict),
+                                   _p(level), _p(witness), int(threads or self.threads))
+        if st != 0:
+            raise ValueError("oracle validate rejected its arguments")
+        return verdict[:n], level[:n], witness[:n]
 
     def pair(self, e, box):
         c, s = C.c_int32(0), C.c_int32(0)

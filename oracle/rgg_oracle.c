@@ -16,7 +16,10 @@
  *              and its part of the inner approximation both meet o
  *     outer(e) = #{o : C(e,o)},  inner(e) = #{o : S(e,o)}
  *     label(e) = RED if inner(e) > 0, else GREEN if outer(e) == 0, else GRAY
- *   plus the ascending list of GRAY edge ids.
+ *   plus the ascending list of GRAY edge ids;
+ *   and, for edges a caller names (the unknown ones, Alg. 1 when not lazy),
+ *   a full continuous collision check by dyadic refinement of the same two
+ *   approximations (orc_rm_validate, below).
  *
  * Primitives (the readings of the paper used throughout this project):
  *   robot             a union of spheres (centre, radius r_i) carried by a
@@ -35,7 +38,8 @@
  *
  * Arithmetic: IEEE binary64, round to nearest, compiled without FMA
  * contraction; every sum is taken left to right in the order written here.
- * sin, cos, acos and sqrt come from the C library.  The incremental mode's
+ * sin, cos, acos and sqrt come from the C library, except in the full
+ * validation, whose sin and cos are a fixed sequence of binary64 steps.  The incremental mode's
  * bounding-box pretest only skips pairs whose predicates are false with a
  * wide margin, so it never changes a result (tests check scratch == incremental).
  */
@@ -384,6 +388,8 @@ typedef struct {
     int32_t *outer, *inner;
     int64_t M;
     double *resident;  /* [M][6] obstacle slots for the incremental mode  */
+    double *q;         /* [n_nodes][dof] node configurations (validation) */
+    int64_t *uv;       /* [E][2] edge end nodes (validation)              */
 } orc_rm;
 
 typedef struct {
@@ -474,6 +480,8 @@ void orc_rm_free(orc_rm *rm)
     free(rm->outer);
     free(rm->inner);
     free(rm->resident);
+    free(rm->q);
+    free(rm->uv);
     free(rm);
 }
 
@@ -500,10 +508,15 @@ orc_rm *orc_rm_build(const orc_robot *rob, int64_t n_nodes, const double *q, int
     rm->inner = (int32_t *)calloc((size_t)n_edges + 1, sizeof(int32_t));
     rm->M = n_slots;
     rm->resident = (double *)malloc(sizeof(double) * (size_t)(n_slots * 6 + 1));
-    if (!rm->soff || !rm->capR || !rm->aabb || !rm->outer || !rm->inner || !rm->resident) {
+    rm->q = (double *)malloc(sizeof(double) * (size_t)(n_nodes * rob->dof + 1));
+    rm->uv = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_edges * 2 + 1));
+    if (!rm->soff || !rm->capR || !rm->aabb || !rm->outer || !rm->inner || !rm->resident || !rm->q ||
+        !rm->uv) {
         orc_rm_free(rm);
         return NULL;
     }
+    if (n_nodes > 0) memcpy(rm->q, q, sizeof(double) * (size_t)(n_nodes * rob->dof));
+    if (n_edges > 0) memcpy(rm->uv, edge_uv, sizeof(int64_t) * (size_t)(n_edges * 2));
     for (int64_t s = 0; s < n_slots; ++s) {
         for (int k = 0; k < 3; ++k) {
             rm->resident[s * 6 + k] = 1.0;
@@ -706,6 +719,285 @@ int64_t orc_rm_update(orc_rm *rm, int64_t M, const double *old_boxes, const doub
     free(chg);
     memcpy(rm->resident, new_boxes, sizeof(double) * 6 * (size_t)M);
     return emit(rm, labels, gray, gray_cap);
+}
+
+/* ------------------------------------------------------------------------ */
+/* full validation of an edge (Alg. 1, the branch taken when not lazy)       */
+/* ------------------------------------------------------------------------ */
+/*
+ * Alg. 1 gives every edge left unknown a full collision check.  Here that
+ * check is continuous: it decides whether any configuration q(t), t in
+ * [0,1], of the edge's motion puts a robot sphere into a present box.  It
+ * refines the outer and inner approximations of Sec. 2.2 on dyadic
+ * sub-intervals [j 2^-l, (j+1) 2^-l] of the edge:
+ *   free(l, j): for every sphere i and every present box, the capsule from
+ *               sphere i's centre at the interval's start to its centre at
+ *               the interval's end, radius r_i + delta_i 4^-l, misses the
+ *               box.  delta_i bounds max|p''|/8 over the whole edge, so
+ *               delta_i 4^-l bounds the chord deviation over an interval
+ *               of length 2^-l and the capsule holds sphere i's swept volume
+ *               over that interval;
+ *   hit(t):     some sphere at configuration q(t) meets a present box.
+ * The search is level by level:
+ *   hit(0) or hit(1)                  -> COLLIDES, witness 0 or 1
+ *   free(0, 0)                        -> FREE at level 0
+ *   A_0 = {0}; for l = 0, 1, ..., max_level - 1:
+ *     |A_l| > max_active              -> UNRESOLVED at level l
+ *     some j in A_l with hit((2j+1) 2^-(l+1))
+ *                                     -> COLLIDES at level l+1, witness the
+ *                                        smallest such midpoint
+ *     A_{l+1} = {c in {2j, 2j+1}, j in A_l : not free(l+1, c)}
+ *     A_{l+1} empty                   -> FREE at level l+1
+ *   otherwise                         -> UNRESOLVED at level max_level.
+ * COLLIDES is exact (a witness configuration).  FREE certifies the whole
+ * motion up to the rounding of its binary64 evaluation.  UNRESOLVED edges
+ * graze a box within the resolution the limits allow; a caller treats them
+ * as invalid.
+ *
+ * The configurations are evaluated like the build's, except that sin and
+ * cos come from vsincos below: a fixed sequence of binary64 +, -, * and
+ * rint, which any IEEE evaluator (this oracle, a GPU) reproduces bit for
+ * bit.  The build's samples keep the C library's sin and cos.
+ */
+
+#define V_FREE 0
+#define V_COLLIDES 2
+#define V_UNRESOLVED 3
+
+/* sin and cos by Cody and Waite's reduction x = k (pi/2) + r, pi/2 split
+ * into a 24-bit head (exact products with k) and its binary64 remainder,
+ * then the Taylor series of sin r to r^19 and of cos r to r^20 in Horner
+ * form (|r| <= pi/4 up to rounding; the first omitted terms are below
+ * 1e-19).  The quadrant k mod 4 maps (sin r, cos r) to (sin x, cos x). */
+static void vsincos(double x, double *sn, double *cs)
+{
+    const double pi = 3.14159265358979323846;
+    const double half_pi = pi / 2.0;
+    const double head = (double)(float)half_pi;
+    const double tail = half_pi - head;
+    double k = rint(x * (2.0 / pi));
+    double r = (x - k * head) - k * tail;
+    double z = r * r;
+    double ps = -1.0 / 121645100408832000.0;     /* -1/19! */
+    ps = ps * z + 1.0 / 355687428096000.0;       /* 1/17!  */
+    ps = ps * z - 1.0 / 1307674368000.0;         /* -1/15! */
+    ps = ps * z + 1.0 / 6227020800.0;            /* 1/13!  */
+    ps = ps * z - 1.0 / 39916800.0;              /* -1/11! */
+    ps = ps * z + 1.0 / 362880.0;                /* 1/9!   */
+    ps = ps * z - 1.0 / 5040.0;                  /* -1/7!  */
+    ps = ps * z + 1.0 / 120.0;                   /* 1/5!   */
+    ps = ps * z - 1.0 / 6.0;                     /* -1/3!  */
+    double s = r + (r * z) * ps;
+    double pc = 1.0 / 2432902008176640000.0;     /* 1/20!  */
+    pc = pc * z - 1.0 / 6402373705728000.0;      /* -1/18! */
+    pc = pc * z + 1.0 / 20922789888000.0;        /* 1/16!  */
+    pc = pc * z - 1.0 / 87178291200.0;           /* -1/14! */
+    pc = pc * z + 1.0 / 479001600.0;             /* 1/12!  */
+    pc = pc * z - 1.0 / 3628800.0;               /* -1/10! */
+    pc = pc * z + 1.0 / 40320.0;                 /* 1/8!   */
+    pc = pc * z - 1.0 / 720.0;                   /* -1/6!  */
+    pc = pc * z + 1.0 / 24.0;                    /* 1/4!   */
+    pc = pc * z - 1.0 / 2.0;                     /* -1/2!  */
+    double c = 1.0 + z * pc;
+    int64_t quadrant = (int64_t)k & 3;
+    if (quadrant == 0) { *sn = s; *cs = c; }
+    else if (quadrant == 1) { *sn = c; *cs = -s; }
+    else if (quadrant == 2) { *sn = -s; *cs = -c; }
+    else { *sn = -c; *cs = s; }
+}
+
+/* q(t) as motion_at, with vsincos for the slerp weights */
+static void motion_at_v(const orc_robot *r, const motion *m, double t, double *q)
+{
+    if (r->kind == ORC_SE3 && !(m->sh < 1e-12)) {
+        for (int c = 0; c < 3; ++c) q[c] = m->qa[c] + t * (m->qb[c] - m->qa[c]);
+        double sa, ca, sb, cb;
+        vsincos((1.0 - t) * m->h, &sa, &ca);
+        vsincos(t * m->h, &sb, &cb);
+        double wa = sa / m->sh;
+        double wb = sb / m->sh;
+        for (int c = 3; c < 7; ++c) q[c] = wa * m->qa[c] + wb * m->qb[c];
+        return;
+    }
+    motion_at(r, m, t, q);   /* no trigonometry on the other paths */
+}
+
+/* sphere centres at q, as fk, with vsincos */
+static void fk_v(const orc_robot *r, const double *q, double *ctr)
+{
+    if (r->kind == ORC_SE2) {
+        double s, c;
+        vsincos(q[2], &s, &c);
+        for (int i = 0; i < r->B; ++i) {
+            double ox = r->pos[2 * i], oy = r->pos[2 * i + 1];
+            ctr[2 * i] = q[0] + (c * ox - s * oy);
+            ctr[2 * i + 1] = q[1] + (s * ox + c * oy);
+        }
+    } else if (r->kind == ORC_SE3) {
+        fk(r, q, ctr);           /* quaternion rotation: no trigonometry */
+    } else {
+        double jx[MAX_LINKS + 1], jy[MAX_LINKS + 1], cph[MAX_LINKS], sph[MAX_LINKS];
+        double phi = 0.0;
+        jx[0] = r->base[0];
+        jy[0] = r->base[1];
+        for (int m = 0; m < r->L; ++m) {
+            phi = m == 0 ? q[0] : phi + q[m];
+            vsincos(phi, &sph[m], &cph[m]);
+            jx[m + 1] = jx[m] + r->len[m] * cph[m];
+            jy[m + 1] = jy[m] + r->len[m] * sph[m];
+        }
+        for (int i = 0; i < r->B; ++i) {
+            int m = r->link[i];
+            ctr[2 * i] = jx[m] + r->pos[i] * cph[m];
+            ctr[2 * i + 1] = jy[m] + r->pos[i] * sph[m];
+        }
+    }
+}
+
+typedef struct {
+    const orc_rm *rm;
+    motion m;
+    double dl[MAX_SPHERES];
+} vedge;
+
+static void centres_v(const vedge *v, double t, double *ctr)
+{
+    double q[MAX_LINKS + 7];
+    motion_at_v(&v->rm->rob, &v->m, t, q);
+    fk_v(&v->rm->rob, q, ctr);
+}
+
+/* hit(t): some sphere at q(t) meets a present box */
+static int hit_v(const vedge *v, double t)
+{
+    const orc_robot *r = &v->rm->rob;
+    double ctr[MAX_SPHERES * 3];
+    centres_v(v, t, ctr);
+    for (int64_t s = 0; s < v->rm->M; ++s) {
+        const double *b = v->rm->resident + 6 * s;
+        if (!box_present(r->D, b)) continue;
+        for (int i = 0; i < r->B; ++i)
+            if (point_box_d2(r->D, ctr + i * r->D, b, b + 3) <= r->rad[i] * r->rad[i]) return 1;
+    }
+    return 0;
+}
+
+/* free(l, j) */
+static int free_v(const vedge *v, int l, int64_t j)
+{
+    const orc_robot *r = &v->rm->rob;
+    double w = ldexp(1.0, -l);
+    double ca[MAX_SPHERES * 3], cb[MAX_SPHERES * 3];
+    centres_v(v, ldexp((double)j, -l), ca);
+    centres_v(v, ldexp((double)(j + 1), -l), cb);
+    for (int64_t s = 0; s < v->rm->M; ++s) {
+        const double *b = v->rm->resident + 6 * s;
+        if (!box_present(r->D, b)) continue;
+        for (int i = 0; i < r->B; ++i) {
+            double R = r->rad[i] + v->dl[i] * (w * w);
+            if (segbox_fmin(r->D, ca + i * r->D, cb + i * r->D, b, b + 3) <= R * R) return 0;
+        }
+    }
+    return 1;
+}
+
+static int validate_edge(const orc_rm *rm, int64_t e, int max_level, int max_active, int32_t *level,
+                         double *witness, int64_t *act, int64_t *nxt)
+{
+    vedge v;
+    v.rm = rm;
+    const orc_robot *r = &rm->rob;
+    motion_init(r, rm->q + rm->uv[2 * e] * r->dof, rm->q + rm->uv[2 * e + 1] * r->dof, &v.m);
+    deltas(r, &v.m, v.dl);
+    *witness = NAN;
+    *level = 0;
+    if (hit_v(&v, 0.0)) { *witness = 0.0; return V_COLLIDES; }
+    if (hit_v(&v, 1.0)) { *witness = 1.0; return V_COLLIDES; }
+    if (free_v(&v, 0, 0)) return V_FREE;
+    int64_t na = 1;
+    act[0] = 0;
+    for (int l = 0; l < max_level; ++l) {
+        *level = l;
+        if (na > max_active) return V_UNRESOLVED;
+        for (int64_t a = 0; a < na; ++a) {
+            double t = ldexp((double)(2 * act[a] + 1), -(l + 1));
+            if (hit_v(&v, t)) {
+                *level = l + 1;
+                *witness = t;
+                return V_COLLIDES;
+            }
+        }
+        int64_t nn = 0;
+        for (int64_t a = 0; a < na; ++a)
+            for (int64_t c = 2 * act[a]; c <= 2 * act[a] + 1; ++c)
+                if (!free_v(&v, l + 1, c)) nxt[nn++] = c;
+        *level = l + 1;
+        if (nn == 0) return V_FREE;
+        for (int64_t a = 0; a < nn; ++a) act[a] = nxt[a];
+        na = nn;
+    }
+    *level = max_level;
+    return V_UNRESOLVED;
+}
+
+typedef struct {
+    const orc_rm *rm;
+    const int64_t *ids;
+    int64_t i0, i1;
+    int max_level, max_active;
+    uint8_t *verdict;
+    int32_t *level;
+    double *witness;
+} val_job;
+
+static void *val_worker(void *arg)
+{
+    val_job *j = (val_job *)arg;
+    int64_t *act = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * j->max_active + 2));
+    int64_t *nxt = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * j->max_active + 2));
+    for (int64_t i = j->i0; i < j->i1; ++i)
+        j->verdict[i] = (uint8_t)validate_edge(j->rm, j->ids[i], j->max_level, j->max_active, &j->level[i],
+                                               &j->witness[i], act, nxt);
+    free(act);
+    free(nxt);
+    return NULL;
+}
+
+/* Full validation of edges ids[0..n) against the resident obstacle slots.
+ * verdict[i] is 0 (FREE), 2 (COLLIDES) or 3 (UNRESOLVED); level[i] the
+ * level where the search stopped; witness[i] the colliding parameter t
+ * (NaN unless COLLIDES).  Returns 0, or -1 on bad input. */
+int orc_rm_validate(const orc_rm *rm, const int64_t *ids, int64_t n, int max_level, int max_active,
+                    uint8_t *verdict, int32_t *level, double *witness, int threads)
+{
+    if (n < 0 || max_level < 0 || max_level > 30 || max_active < 1 || max_active > 1024) return -1;
+    for (int64_t i = 0; i < n; ++i)
+        if (ids[i] < 0 || ids[i] >= rm->E) return -1;
+    if (n == 0) return 0;
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    if (n < threads) threads = (int)n;
+    pthread_t tid[256];
+    val_job jobs[256];
+    for (int t = 0; t < threads; ++t) {
+        jobs[t] = (val_job){rm, ids, n * t / threads, n * (t + 1) / threads, max_level, max_active,
+                            verdict, level, witness};
+        pthread_create(&tid[t], NULL, val_worker, &jobs[t]);
+    }
+    for (int t = 0; t < threads; ++t) pthread_join(tid[t], NULL);
+    return 0;
+}
+
+void orc_vsincos(double x, double *s, double *c) { vsincos(x, s, c); }
+
+/* centres at parameter t of the motion qa -> qb, as the validation evaluates them */
+void orc_centres_v(const orc_robot *r, const double *qa, const double *qb, double t, double *ctr)
+{
+    motion m;
+    motion_init(r, qa, qb, &m);
+    double q[MAX_LINKS + 7];
+    motion_at_v(r, &m, t, q);
+    fk_v(r, q, ctr);
 }
 
 /* ------------------------------------------------------------------------ */
