@@ -67,6 +67,12 @@ typedef int32_t rgg_status;
 #define RGG_GRAY 1
 #define RGG_RED 2
 
+/* verdicts of the full validation (rgg_validate) */
+#define RGG_VERDICT_FREE 0        /* no configuration of the motion collides     */
+#define RGG_VERDICT_COLLIDES 2    /* a witness configuration collides           */
+#define RGG_VERDICT_UNRESOLVED 3  /* undecided within the refinement limits     */
+#define RGG_VERDICT_BAD_ID 255    /* the listed id is not an edge of the roadmap */
+
 /* precision of the distance tests */
 #define RGG_PREC_FP64 0           /* every test in binary64                   */
 #define RGG_PREC_FP32_RECHECK 1   /* binary32 tests; any pair with a margin in
@@ -328,13 +334,52 @@ rgg_status rgg_tune(rgg_roadmap *rm, int64_t m, const rgg_box *obstacles_a, int3
 rgg_status rgg_batch_tune(rgg_batch *b, const rgg_box *const *obstacles_a, const rgg_box *const *obstacles_b,
                           int32_t reps, rgg_tune_report *report);
 
+/* Full validation (Alg. 1 when not lazy: every edge left unknown gets a
+ * full collision check).  Decides, for each listed edge, whether any
+ * configuration q(t), t in [0, 1], of its motion puts a robot sphere into a
+ * present obstacle slot, by refining the outer and inner approximations of
+ * Sec. 2.2 on dyadic sub-intervals [j 2^-l, (j+1) 2^-l]: an interval is
+ * free when every sphere's capsule between its centres at the interval's
+ * ends, inflated to r_i + delta_i 4^-l, misses every box; the search tests
+ * the robot at the midpoints of the intervals that are not free, level by
+ * level, and splits them.
+ *   verdict RGG_VERDICT_COLLIDES: witness[i] is the colliding parameter
+ *     (0 or 1 first, else the smallest colliding midpoint of the first level
+ *     with one); RGG_VERDICT_FREE: no configuration collides;
+ *     RGG_VERDICT_UNRESOLVED: more than max_active intervals stayed unknown
+ *     at some level, or max_level levels were not enough (a caller treats
+ *     the edge as invalid); witness[i] is NaN unless COLLIDES; level[i] is
+ *     the level where the search stopped.
+ * Configurations use the binary64 motion of the build with a sin/cos made of
+ * fixed binary64 steps, so verdicts are reproducible bit for bit.  The
+ * obstacles are the roadmap's resident slots when the validation runs (after
+ * its queued updates).  max_level 0..30 (0: RGG_VALIDATE_DEFAULT_LEVELS),
+ * max_active 1..1024 (0: RGG_VALIDATE_DEFAULT_ACTIVE).
+ * rgg_validate: host arrays ids[n] (each an edge id, else RGG_E_INVALID_ARG),
+ * verdict[n], level[n] and witness[n] (level and witness may be NULL);
+ * returns when done.
+ * rgg_validate_async: device arrays, queued on `stream` after the roadmap's
+ * previous update.  When d_count is non-null (the result of an update queued
+ * before, e.g. with d_ids its gray list), only the first
+ * min(n, d_count->n_gray) ids are validated, and none if that update failed;
+ * an id that is not an edge gets RGG_VERDICT_BAD_ID.  Entries past the
+ * validated count are left as they were. */
+#define RGG_VALIDATE_DEFAULT_LEVELS 24
+#define RGG_VALIDATE_DEFAULT_ACTIVE 256
+rgg_status rgg_validate(rgg_roadmap *rm, const int64_t *ids, int64_t n, int32_t max_level, int32_t max_active,
+                        uint8_t *verdict, int32_t *level, double *witness);
+rgg_status rgg_validate_async(rgg_roadmap *rm, void *stream, const int64_t *d_ids, int64_t n,
+                              const rgg_update_result *d_count, int32_t max_level, int32_t max_active,
+                              uint8_t *d_verdict, int32_t *d_level, double *d_witness);
+
 /* Persistence between planning iterations (Sec. 1 and Sec. 3.3: the
  * approximations are computed once and then stored and reloaded).
  * rgg_save writes `rm` to the file `path`: its binary64 sphere centres and
  * capsules, edge boxes, sphere radii, the resident obstacle slots, the per-edge
  * counters, the precision mode, band, re-test capacity and the work
- * decomposition (cell size, edges per item), followed by an FNV-1a 64-bit
- * checksum; host byte order, format version 1.  It first waits for the
+ * decomposition (cell size, edges per item), the robot and the edges'
+ * motions for rgg_validate, followed by an FNV-1a 64-bit checksum; host byte
+ * order, format version 2.  It first waits for the
  * roadmap's queued updates.  RGG_E_BUSY if a graph, batch or server request
  * holds the roadmap; RGG_E_INVALID_ARG if the file cannot be written.
  * rgg_load builds a roadmap on ctx's device from such a file without

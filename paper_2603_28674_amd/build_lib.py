@@ -3,8 +3,9 @@
 * ``geometry.cpp`` (host build stage, binary64 with the C library's sin, cos,
   acos, sqrt) is compiled by g++ with FMA contraction and builtin folding off,
   so the approximations are exactly the stated binary64 expressions;
-* ``api.cpp`` (C ABI, host side), ``server.cpp`` (request server) and
-  ``kernels.hip`` (device code) by hipcc,
+* ``api.cpp`` (C ABI, host side), ``server.cpp`` (request server),
+  ``kernels.hip`` (update kernels) and ``validate.hip`` (full validation) by
+  hipcc,
   device code with ``-ffp-contract=off`` so binary64 re-tests evaluate the same
   expressions, and with packed FP32 instruction selection disabled.
 """
@@ -55,8 +56,12 @@ def build(verbose: bool = False) -> str:
     _run([hipcc, *common, "-Wall", "-c", os.path.join(CSRC, "server.cpp"), "-o", srv], verbose)
     _run([hipcc, *common, f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops", "-c", os.path.join(CSRC, "kernels.hip"), "-o", ker], verbose)
+    val = os.path.join(BUILD, "validate.o")
+    _run([hipcc, *common, f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
+          "-packed-fp32-ops", "-c", os.path.join(CSRC, "validate.hip"), "-o", val], verbose)
     tmp = OUT + ".tmp"
-    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, geo, api, srv, ker, "-lpthread"], verbose)
+    _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, geo, api, srv, ker, val, "-lpthread"],
+         verbose)
     os.replace(tmp, OUT)
     return OUT
 

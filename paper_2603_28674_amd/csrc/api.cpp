@@ -488,6 +488,42 @@ rgg_status make_roadmap(rgg_context *ctx, const HostGeometry &g, const HostGrid 
     if ((st = rm->alloc(&rm->d_res, 1, "result")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&rm->d_labels, (size_t)E, "labels")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&rm->d_gray, (size_t)E, "gray list")) != RGG_OK) return guard(st);
+    // full validation
+    {
+        static_assert(sizeof(((VRobot *)nullptr)->pos) == sizeof(double) * kMaxSpheres * 3 &&
+                          sizeof(((VRobot *)nullptr)->len) == sizeof(double) * kMaxLinks,
+                      "VRobot holds the largest robot");
+        VRobot hr = {};
+        hr.kind = g.kind;
+        hr.B = B;
+        hr.L = g.L;
+        hr.dof = g.dof;
+        hr.base[0] = g.rob_base[0];
+        hr.base[1] = g.rob_base[1];
+        for (size_t k = 0; k < g.rob_pos.size(); ++k) hr.pos[k] = g.rob_pos[k];
+        for (int i = 0; i < B; ++i) {
+            hr.rad[i] = g.radius[i];
+            hr.link[i] = i < (int)g.rob_link.size() ? g.rob_link[i] : 0;
+        }
+        for (size_t k = 0; k < g.rob_len.size(); ++k) hr.len[k] = g.rob_len[k];
+        ValDev &vd = rm->val;
+        VRobot *d_rob;
+        double *d_mot, *d_del;
+        if ((st = rm->upload(&d_rob, &hr, 1, "validation robot")) != RGG_OK) return guard(st);
+        if ((st = rm->upload(&d_mot, g.motion.data(), g.motion.size(), "edge motions")) != RGG_OK) return guard(st);
+        if ((st = rm->upload(&d_del, g.delta.data(), g.delta.size(), "chord deviations")) != RGG_OK) return guard(st);
+        vd.D = D;
+        vd.B = B;
+        vd.dof = g.dof;
+        vd.vstride = 2 * g.dof + 3;
+        vd.E = E;
+        vd.M = M;
+        vd.rob = d_rob;
+        vd.motion = d_mot;
+        vd.delta = d_del;
+        vd.cap64 = cap64;
+        vd.resident = dv.resident;
+    }
     if (cnt && E > 0)
         st = hip_ok(hipMemcpy(dv.cnt, cnt, sizeof(int2) * E, hipMemcpyHostToDevice), "restore counters");
     else
@@ -661,6 +697,71 @@ rgg_status rgg_update(rgg_roadmap *rm, int64_t m, const rgg_box *obstacles_old,
     if (gray && r.n_gray > gray_cap)
         return fail(RGG_E_CAPACITY, "gray list has %lld edges, capacity %lld", (long long)r.n_gray, (long long)gray_cap);
     return RGG_OK;
+}
+
+static rgg_status check_validate_args(rgg_roadmap *rm, int64_t n, int32_t *max_level, int32_t *max_active)
+{
+    if (!rm) return fail(RGG_E_INVALID_ARG, "null roadmap");
+    if (n < 0) return fail(RGG_E_INVALID_ARG, "negative edge count");
+    if (*max_level == 0) *max_level = RGG_VALIDATE_DEFAULT_LEVELS;
+    if (*max_active == 0) *max_active = RGG_VALIDATE_DEFAULT_ACTIVE;
+    if (*max_level < 0 || *max_level > 30) return fail(RGG_E_INVALID_ARG, "max_level must be 0..30");
+    if (*max_active < 1 || *max_active > kValMaxActive) return fail(RGG_E_INVALID_ARG, "max_active must be 0..1024");
+    return RGG_OK;
+}
+
+rgg_status rgg_validate_async(rgg_roadmap *rm, void *stream, const int64_t *d_ids, int64_t n,
+                              const rgg_update_result *d_count, int32_t max_level, int32_t max_active,
+                              uint8_t *d_verdict, int32_t *d_level, double *d_witness)
+{
+    rgg_status st = check_validate_args(rm, n, &max_level, &max_active);
+    if (st != RGG_OK) return st;
+    if (n > 0 && (!d_ids || !d_verdict || !d_level || !d_witness)) return fail(RGG_E_INVALID_ARG, "null array");
+    HIP_OR_FAIL(hipSetDevice(rm->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = order_after_previous(rm, s)) != RGG_OK) return st;
+    HIP_OR_FAIL(launch_validate(rm->val, d_ids, n, d_count, max_level, max_active, d_verdict, d_level, d_witness, s),
+                "validate launch");
+    return finish_update(rm, s);
+}
+
+rgg_status rgg_validate(rgg_roadmap *rm, const int64_t *ids, int64_t n, int32_t max_level, int32_t max_active,
+                        uint8_t *verdict, int32_t *level, double *witness)
+{
+    rgg_status st = check_validate_args(rm, n, &max_level, &max_active);
+    if (st != RGG_OK) return st;
+    if (n == 0) return RGG_OK;
+    if (!ids || !verdict) return fail(RGG_E_INVALID_ARG, "null array");
+    for (int64_t i = 0; i < n; ++i)
+        if (ids[i] < 0 || ids[i] >= rm->dv.E)
+            return fail(RGG_E_INVALID_ARG, "ids[%lld] = %lld is not an edge", (long long)i, (long long)ids[i]);
+    HIP_OR_FAIL(hipSetDevice(rm->device), "hipSetDevice");
+    hipStream_t s = rm->stream;
+    // one device block: ids, then verdicts, levels and witnesses
+    const size_t b_ids = sizeof(int64_t) * n, b_wit = sizeof(double) * n, b_lev = sizeof(int32_t) * n;
+    char *d = nullptr;
+    HIP_OR_FAIL(hipMalloc((void **)&d, b_ids + b_wit + b_lev + (size_t)n), "validation buffers");
+    int64_t *d_ids = (int64_t *)d;
+    double *d_wit = (double *)(d + b_ids);
+    int32_t *d_lev = (int32_t *)(d + b_ids + b_wit);
+    uint8_t *d_ver = (uint8_t *)(d + b_ids + b_wit + b_lev);
+    auto run = [&]() -> rgg_status {
+        rgg_status r = order_after_previous(rm, s);
+        if (r != RGG_OK) return r;
+        HIP_OR_FAIL(hipMemcpyAsync(d_ids, ids, b_ids, hipMemcpyHostToDevice, s), "upload ids");
+        HIP_OR_FAIL(launch_validate(rm->val, d_ids, n, nullptr, max_level, max_active, d_ver, d_lev, d_wit, s),
+                    "validate launch");
+        if ((r = finish_update(rm, s)) != RGG_OK) return r;
+        HIP_OR_FAIL(hipMemcpyAsync(verdict, d_ver, (size_t)n, hipMemcpyDeviceToHost, s), "read verdicts");
+        if (level) HIP_OR_FAIL(hipMemcpyAsync(level, d_lev, b_lev, hipMemcpyDeviceToHost, s), "read levels");
+        if (witness) HIP_OR_FAIL(hipMemcpyAsync(witness, d_wit, b_wit, hipMemcpyDeviceToHost, s), "read witnesses");
+        HIP_OR_FAIL(hipStreamSynchronize(s), "validate");
+        return RGG_OK;
+    };
+    st = run();
+    if (st != RGG_OK) (void)hipStreamSynchronize(s);
+    (void)hipFree(d);
+    return st;
 }
 
 static rgg_status refresh_labels(rgg_roadmap *rm, rgg_update_result *r)
@@ -1077,7 +1178,7 @@ namespace {
 // Roadmap files: a header, the binary64 geometry, the state, and an FNV-1a
 // 64-bit checksum of every preceding byte.  Host byte order.
 constexpr char kMagic[8] = {'R', 'G', 'G', 'M', 'A', 'P', '0', '1'};
-constexpr uint32_t kFileVersion = 1;
+constexpr uint32_t kFileVersion = 2;
 
 struct FileHeader {
     char magic[8];
@@ -1172,6 +1273,12 @@ rgg_status rgg_save(rgg_roadmap *rm, const char *path)
     if ((st = read_back(&aabb, dv.aabb, (size_t)(E * kAabbStride), "edge boxes")) != RGG_OK) return st;
     if ((st = read_back(&resident, dv.resident, (size_t)M, "obstacle slots")) != RGG_OK) return st;
     if ((st = read_back(&cnt, dv.cnt, (size_t)E, "counters")) != RGG_OK) return st;
+    const ValDev &vd = rm->val;
+    std::vector<VRobot> vrob;
+    std::vector<double> vmot, vdel;
+    if ((st = read_back(&vrob, vd.rob, 1, "validation robot")) != RGG_OK) return st;
+    if ((st = read_back(&vmot, vd.motion, (size_t)(E * vd.vstride), "edge motions")) != RGG_OK) return st;
+    if ((st = read_back(&vdel, vd.delta, (size_t)(E * dv.B), "chord deviations")) != RGG_OK) return st;
     FileHeader h = {};
     memcpy(h.magic, kMagic, sizeof kMagic);
     h.version = kFileVersion;
@@ -1198,6 +1305,9 @@ rgg_status rgg_save(rgg_roadmap *rm, const char *path)
     out.put(aabb.data(), sizeof(float) * aabb.size());
     out.put(resident.data(), sizeof(rgg_box) * resident.size());
     out.put(cnt.data(), sizeof(int2) * cnt.size());
+    out.put(vrob.data(), sizeof(VRobot));
+    out.put(vmot.data(), sizeof(double) * vmot.size());
+    out.put(vdel.data(), sizeof(double) * vdel.size());
     const uint64_t sum = out.sum.h;
     out.put(&sum, sizeof sum);
     if (!out.ok || fflush(out.f) != 0) return fail(RGG_E_INVALID_ARG, "writing %s failed", path);
@@ -1246,6 +1356,33 @@ rgg_status rgg_load(rgg_context *ctx, const char *path, rgg_roadmap **out)
     in.get(g.aabb.data(), sizeof(float) * g.aabb.size());
     in.get(resident.data(), sizeof(rgg_box) * resident.size());
     in.get(cnt.data(), sizeof(int2) * cnt.size());
+    VRobot vr;
+    in.get(&vr, sizeof vr);
+    if (!in.ok) return fail(RGG_E_INVALID_ARG, "%s is truncated", path);
+    const int want_dof = vr.kind == RGG_SE2 ? 3 : (vr.kind == RGG_SE3 ? 7 : vr.L);
+    bool robot_ok = (vr.kind == RGG_SE2 || vr.kind == RGG_SE3 || vr.kind == RGG_PLANAR_ARM) &&
+                    (vr.kind == RGG_SE3 ? 3 : 2) == h.D && vr.B == h.B && vr.dof == want_dof &&
+                    (vr.kind != RGG_PLANAR_ARM || (vr.L >= 1 && vr.L <= kMaxLinks));
+    for (int i = 0; robot_ok && vr.kind == RGG_PLANAR_ARM && i < vr.B; ++i)
+        robot_ok = vr.link[i] >= 0 && vr.link[i] < vr.L;
+    if (!robot_ok) return fail(RGG_E_INVALID_ARG, "%s: inconsistent robot", path);
+    g.kind = vr.kind;
+    g.dof = vr.dof;
+    g.L = vr.kind == RGG_PLANAR_ARM ? vr.L : 0;
+    const int per = vr.kind == RGG_SE2 ? 2 : (vr.kind == RGG_SE3 ? 3 : 1);
+    g.rob_pos.assign(vr.pos, vr.pos + vr.B * per);
+    g.rob_link.assign(vr.link, vr.link + vr.B);
+    g.rob_len.assign(vr.len, vr.len + g.L);
+    g.rob_base[0] = vr.base[0];
+    g.rob_base[1] = vr.base[1];
+    try {
+        g.motion.resize((size_t)(h.E * (2 * vr.dof + 3)));
+        g.delta.resize((size_t)(h.E * h.B));
+    } catch (const std::bad_alloc &) {
+        return fail(RGG_E_OUT_OF_MEMORY, "host memory for %s", path);
+    }
+    in.get(g.motion.data(), sizeof(double) * g.motion.size());
+    in.get(g.delta.data(), sizeof(double) * g.delta.size());
     const uint64_t want = in.sum.h;
     uint64_t sum = 0;
     if (in.ok) in.get(&sum, sizeof sum);

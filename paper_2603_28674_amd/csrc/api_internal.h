@@ -55,6 +55,8 @@ struct rgg_roadmap {
     rgg_update_result *d_res = nullptr;
     uint8_t *d_labels = nullptr;      // [E]
     int64_t *d_gray = nullptr;        // [E]
+    // full validation: robot, per-edge motions and chord-deviation bounds
+    rgg::ValDev val = {};
     // timing
     bool timing = false;
     std::vector<std::array<hipEvent_t, 7>> pool, pending;

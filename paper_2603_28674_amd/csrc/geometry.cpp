@@ -305,6 +305,18 @@ rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *r, const 
     g->E = E;
     g->radius.assign(r->sphere_radius, r->sphere_radius + B);
     g->soff.assign(E + 1, 0);
+    g->dof = dof;
+    g->L = r->kind == RGG_PLANAR_ARM ? r->n_links : 0;
+    const int per = r->kind == RGG_SE2 ? 2 : (r->kind == RGG_SE3 ? 3 : 1);
+    g->rob_pos.assign(r->sphere_pos, r->sphere_pos + B * per);
+    g->rob_link.assign((size_t)B, 0);
+    if (r->kind == RGG_PLANAR_ARM) {
+        g->rob_link.assign(r->sphere_link, r->sphere_link + B);
+        g->rob_len.assign(r->link_length, r->link_length + r->n_links);
+        g->rob_base[0] = r->base[0];
+        g->rob_base[1] = r->base[1];
+    }
+    const int vstride = 2 * dof + 3;
     if (threads < 1) threads = 1;
     threads = (int)std::min<int64_t>(threads, std::max<int64_t>(E, 1));
 
@@ -334,6 +346,8 @@ rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *r, const 
         g->samp.assign((size_t)(total * S), 0.0);
         g->cap.assign((size_t)(E * (2 * D + 1) * B), 0.0);
         g->aabb.assign((size_t)(E * kAabbStride), 0.0f);
+        g->motion.assign((size_t)(E * vstride), 0.0);
+        g->delta.assign((size_t)(E * B), 0.0);
     } catch (const std::bad_alloc &) {
         *err = "host memory for the build";
         return RGG_E_OUT_OF_MEMORY;
@@ -354,6 +368,15 @@ rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *r, const 
                 place_spheres(r, q, blk, S, J, j);
             }
             inflation(r, m, infl);
+            double *mv = g->motion.data() + k * vstride;
+            for (int c = 0; c < dof; ++c) {
+                mv[c] = m.a[c];
+                mv[dof + c] = m.b[c];
+            }
+            mv[2 * dof] = m.turn;
+            mv[2 * dof + 1] = m.half;
+            mv[2 * dof + 2] = m.sin_half;
+            for (int i = 0; i < B; ++i) g->delta[k * B + i] = infl[i];
             double *cp = g->cap.data() + k * (2 * D + 1) * B;
             double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
             for (int i = 0; i < B; ++i) {

@@ -133,6 +133,36 @@ hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp
 hipError_t launch_batch(hipStream_t s, const BatchReq *tab, const int32_t *grp, int n, const BatchGroup *groups,
                         int n_groups, bool any_grid, int n_tiles, int n_wtiles);
 
+// Full validation of listed edges (rgg_validate): the robot, each edge's
+// motion parameters and chord-deviation bounds, and the resident slots.
+constexpr int kValMaxActive = 1024;  // unknown sub-intervals per level, at most
+constexpr int kValBoxes = 256;       // candidate boxes staged in LDS per page
+
+struct VRobot {
+    int32_t kind, B, L, dof;
+    double base[2];
+    double pos[64 * 3];        // SE2 [B][2], SE3 [B][3], arm [B]
+    double rad[64];
+    double len[32];
+    int32_t link[64];
+};
+
+struct ValDev {
+    int32_t D, B, dof, vstride;      // vstride = 2 dof + 3
+    int64_t E, M;
+    const VRobot *rob;
+    const double *motion;      // [E][vstride]: a[dof], b[dof] (SE3: short-arc sign), turn, half, sin_half
+    const double *delta;       // [E][B] chord-deviation bounds
+    const double *cap64;       // [E][2D+1][B] capsules (their chords bound the search)
+    const rgg_box *resident;   // [M]
+};
+
+// Queues the validation of ids[0 .. n) (n capped by count->n_gray when
+// count is non-null, and zero when count->status is not RGG_OK) on `s`.
+hipError_t launch_validate(const ValDev &v, const int64_t *ids, int64_t n, const rgg_update_result *count,
+                           int32_t max_level, int32_t max_active, uint8_t *verdict, int32_t *level,
+                           double *witness, hipStream_t s);
+
 // Queues the kernels of one update on `s`.  When `ev` is non-null, ev[0..6]
 // are recorded before, between and after the stages (diff, cells, grid scan,
 // classify, re-test, labels).

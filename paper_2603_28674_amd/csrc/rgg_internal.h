@@ -34,6 +34,14 @@ struct HostGeometry {
     std::vector<double> cap;       // [E][2D+1][B]: A_0..A_{D-1}, B_0..B_{D-1}, R
     std::vector<float> aabb;       // [E][8]: padded FP32 box lo[3], s, hi[3], 0
     std::vector<double> radius;    // [B]
+    // full validation: the robot and each edge's motion
+    int dof = 0, L = 0;
+    std::vector<double> rob_pos;   // SE2 [B][2], SE3 [B][3], arm [B]
+    std::vector<int32_t> rob_link; // arm [B]
+    std::vector<double> rob_len;   // arm [L]
+    double rob_base[2] = {0.0, 0.0};
+    std::vector<double> motion;    // [E][2 dof + 3]: a, b (SE3: short-arc sign), turn, half, sin_half
+    std::vector<double> delta;     // [E][B] chord-deviation bounds delta_i
 };
 
 // Validates the inputs of rgg_build.  Returns RGG_OK or RGG_E_INVALID_ARG

@@ -29,6 +29,8 @@ RGG_E_BUSY = -7
 RGG_SE2, RGG_SE3, RGG_PLANAR_ARM = 0, 1, 2
 RGG_GREEN, RGG_GRAY, RGG_RED = 0, 1, 2
 RGG_PREC_FP64, RGG_PREC_FP32_RECHECK = 0, 1
+RGG_VERDICT_FREE, RGG_VERDICT_COLLIDES, RGG_VERDICT_UNRESOLVED, RGG_VERDICT_BAD_ID = 0, 2, 3, 255
+RGG_VALIDATE_DEFAULT_LEVELS, RGG_VALIDATE_DEFAULT_ACTIVE = 24, 256
 
 
 class RggError(RuntimeError):
@@ -130,6 +132,7 @@ EXPORTS = ["rgg_context_create", "rgg_context_destroy", "rgg_build", "rgg_destro
            "rgg_batch_launch_graph", "rgg_batch_destroy", "rgg_update_batch", "rgg_server_start",
            "rgg_server_submit", "rgg_server_poll", "rgg_server_stop", "rgg_labels", "rgg_gray_list",
            "rgg_timing_enable", "rgg_timing_read", "rgg_tune", "rgg_batch_tune", "rgg_save", "rgg_load",
+           "rgg_validate", "rgg_validate_async",
            "rgg_debug_geometry",
            "rgg_last_error", "rgg_version"]
 
@@ -172,6 +175,8 @@ def lib():
         "rgg_tune": (I32, [P, I64, P, I32, P, I32, P]),
         "rgg_batch_tune": (I32, [P, P, P, I32, P]),
         "rgg_save": (I32, [P, C.c_char_p]),
+        "rgg_validate": (I32, [P, P, I64, I32, I32, P, P, P]),
+        "rgg_validate_async": (I32, [P, P, P, I64, P, I32, I32, P, P, P]),
         "rgg_load": (I32, [P, C.c_char_p, C.POINTER(P)]),
         "rgg_debug_geometry": (I32, [P, P, P, I64, I64, P, P, P, P]),
         "rgg_last_error": (C.c_char_p, []),
@@ -445,6 +450,27 @@ def rgg_batch_tune(batch, a_list, b_list, reps=0):
     return rep.as_dict()
 
 
+def rgg_validate(rm, ids, max_level=0, max_active=0):
+    """Full validation of edges ``ids`` against the resident obstacles:
+    (verdict uint8, level int32, witness float64) arrays."""
+    ids = np.ascontiguousarray(ids, dtype=np.int64).reshape(-1)
+    n = ids.shape[0]
+    verdict = np.zeros(max(n, 1), dtype=np.uint8)
+    level = np.zeros(max(n, 1), dtype=np.int32)
+    witness = np.zeros(max(n, 1), dtype=np.float64)
+    _check(lib().rgg_validate(rm, _ptr(ids), n, int(max_level), int(max_active), _ptr(verdict), _ptr(level),
+                              _ptr(witness)))
+    return verdict[:n], level[:n], witness[:n]
+
+
+def rgg_validate_async(rm, stream, d_ids, n, d_count, d_verdict, d_level, d_witness, max_level=0, max_active=0):
+    """Device-buffer validation queued on ``stream``; ``d_count`` (a result
+    tensor of an earlier update, or None) caps the count at its n_gray."""
+    _check(lib().rgg_validate_async(rm, C.c_void_p(stream), _dptr(d_ids), int(n), _dptr(d_count),
+                                    int(max_level), int(max_active), _dptr(d_verdict), _dptr(d_level),
+                                    _dptr(d_witness)))
+
+
 def rgg_save(rm, path):
     _check(lib().rgg_save(rm, os.fsencode(path)))
 
@@ -523,6 +549,9 @@ class Roadmap:
 
     def tune(self, a, bs, reps=0):
         return rgg_tune(self.h, a, bs, reps)
+
+    def validate(self, ids, max_level=0, max_active=0):
+        return rgg_validate(self.h, ids, max_level, max_active)
 
     def save(self, path):
         rgg_save(self.h, path)

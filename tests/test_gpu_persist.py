@@ -75,6 +75,10 @@ def test_save_load_round_trip(ctx, tmp_path, kind, prec, cell, item_edges, tune)
     assert np.array_equal(g.labels(), h.labels())
     (ga, na), (gb, nb) = g.gray_list(), h.gray_list()
     assert na == nb and np.array_equal(ga, gb)
+    # the full validation reads the stored robot and motions
+    ids = np.arange(0, w.n_edges, 7)
+    va, vb = g.validate(ids), h.validate(ids)
+    assert all(np.array_equal(x, y, equal_nan=True) for x, y in zip(va, vb))
     for u in range(2, n_updates):
         ol, og = o.update(prev, w.boxes[u])
         for name, r in (("saved", g), ("loaded", h)):
