@@ -18,6 +18,9 @@ are resident in HBM before timing starts.  The JSON line reports:
   roofline        the classify kernel's algorithmic bytes per launch over its
                   event-timed duration, against 8 TB/s
   cpu_baseline    the FP64 CPU oracle on a bounded sample of the same edges
+  validation      full continuous validation of the last update's gray list
+                  (rgg_validate_async chained after the update), HIP-event
+                  timed, beside the oracle on a sample of the same edges
 """
 from __future__ import annotations
 
@@ -59,6 +62,10 @@ def parse():
                    help="keep the built work decomposition instead of running the autotuner")
     p.add_argument("--no-other-configs", action="store_true",
                    help="skip the planar (FP64 and FP32) and arm measurements")
+    p.add_argument("--no-validate", action="store_true",
+                   help="skip the full validation of the last update's gray list")
+    p.add_argument("--cpu-validate-edges", type=int, default=2000,
+                   help="gray edges the oracle validates for the CPU comparison")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 1 GiB device copy 5 times (reference kernel for "
                         "scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -444,6 +451,52 @@ def copy_bandwidth(torch, dev):
     return gbs
 
 
+def validate_pass(a, torch, rgg, g, w, stream, gray, res_last, last, reps=5):
+    """Times rgg_validate_async over the gray list of update `last` (HIP
+    events on the update stream) and the oracle on a sample of it."""
+    E = w.n_edges
+    r = rgg.result_from_tensor(res_last)
+    n = int(r.n_gray)
+    dev = gray.device
+    ver = torch.zeros(max(n, 1), dtype=torch.uint8, device=dev)
+    lev = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
+    wit = torch.zeros(max(n, 1), dtype=torch.float64, device=dev)
+    rgg.rgg_validate_async(g.h, stream, gray, n, res_last, ver, lev, wit)   # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        rgg.rgg_validate_async(g.h, stream, gray, n, res_last, ver, lev, wit)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    v = ver[:n].cpu().numpy()
+    lv = lev[:n].cpu().numpy()
+    out = {"gray_edges": n, "ms": ms, "gray_edges_per_s": n / (ms * 1e-3) if ms > 0 else None,
+           "free": int(np.sum(v == rgg.RGG_VERDICT_FREE)),
+           "collides": int(np.sum(v == rgg.RGG_VERDICT_COLLIDES)),
+           "unresolved": int(np.sum(v == rgg.RGG_VERDICT_UNRESOLVED)),
+           "level_mean": float(lv.mean()) if n else 0.0, "level_max": int(lv.max(initial=0)),
+           "max_level": rgg.RGG_VALIDATE_DEFAULT_LEVELS, "max_active": rgg.RGG_VALIDATE_DEFAULT_ACTIVE,
+           "cpu_oracle": None}
+    if not a.no_cpu_baseline and n:
+        import oracle
+        ids = gray[:n].cpu().numpy()
+        rng = np.random.default_rng(a.seed)
+        sample = np.sort(rng.choice(ids, size=min(n, a.cpu_validate_edges), replace=False))
+        threads = min(os.cpu_count() or 1, 16)
+        o = oracle.Roadmap(w.robot, w.q, w.edges[sample], w.resolution, w.samples_per_edge, w.n_slots, threads)
+        o.classify(w.boxes[last])
+        t0 = time.perf_counter()
+        ov, _, _ = o.validate(np.arange(len(sample)))
+        dt = time.perf_counter() - t0
+        at = np.searchsorted(ids, sample)
+        out["cpu_oracle"] = {"gray_edges_per_s": len(sample) / dt, "cores": threads, "kind": "oracle",
+                             "sample": f"{len(sample)} of the {n} gray edges",
+                             "verdicts_equal": bool(np.array_equal(ov, v[at]))}
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -537,6 +590,13 @@ def main():
     final_labels = labels.cpu().numpy()
     last = first + 4 * K - 1
 
+    # pass 3d: full validation of the last update's gray list (the non-lazy
+    # step after the classification), chained on the device after the
+    # update; the oracle validates a sample of the same edges on the host
+    validation = None
+    if not a.no_validate:
+        validation = validate_pass(a, torch, rgg, g, w, stream, gray, res[last], last)
+
     # pass 3c: the host-buffer entry point (boxes from host memory, labels and
     # gray ids back to host memory), continuing the same sequence: the
     # PCIe-inclusive rate, reported beside the value, never as it
@@ -611,6 +671,7 @@ def main():
         "latency_cold_p50_us": float(np.percentile(lat_cold, 50)),
         "latency_cold_p99_us": float(np.percentile(lat_cold, 99)),
         "graph": graph,
+        "validation": validation,
         "host_buffers": {"edges_per_s": E / (host_lat.mean() * 1e-6), "latency_p50_us": float(np.percentile(host_lat, 50)),
                          "latency_p99_us": float(np.percentile(host_lat, 99)), "updates": int(n_host),
                          "note": "rgg_update: boxes uploaded from host memory, labels and gray ids "

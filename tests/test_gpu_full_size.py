@@ -84,6 +84,25 @@ def test_full_size_sampled(ctx, name):
         print(f"[full] {name} update {u}: gray {r.n_gray}, pairs {r.n_pairs}, "
               f"rechecked {r.n_rechecked}, sample mix "
               f"{np.bincount(ol, minlength=3).tolist()}", flush=True)
+        if u == n_updates - 1:
+            # full validation of the whole gray list, chained on the device
+            # after the update; the sampled gray edges against the oracle
+            n = r.n_gray
+            ver = torch.zeros(max(n, 1), dtype=torch.uint8, device=dev)
+            lev = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
+            wit = torch.zeros(max(n, 1), dtype=torch.float64, device=dev)
+            rgg.rgg_validate_async(g.h, stream, gray, n, res, ver, lev, wit)
+            torch.cuda.synchronize()
+            gids = gray[:n].cpu().numpy()
+            pos = np.nonzero(np.isin(idx, gids))[0]            # sampled edges that are gray
+            at = np.searchsorted(gids, idx[pos])
+            ov, olv, ow = o.validate(pos)
+            gv, glv, gw = ver.cpu().numpy()[at], lev.cpu().numpy()[at], wit.cpu().numpy()[at]
+            assert np.array_equal(gv, ov) and np.array_equal(glv, olv)
+            assert np.array_equal(gw, ow, equal_nan=True)
+            print(f"[full] {name} validation: {n} gray -> verdicts "
+                  f"{np.bincount(ver[:n].cpu().numpy(), minlength=4).tolist()}, "
+                  f"{len(pos)} sampled match the oracle", flush=True)
         prev = w.boxes[u]
     g.close()
 
