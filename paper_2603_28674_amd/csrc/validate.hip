@@ -282,6 +282,16 @@ struct ValShared {
     int32_t n_cand, n_page, hit, n_next, nonfree;
 };
 
+// Threads per (point or interval, sphere) item: the block's threads are
+// spread over the items and then over the staged boxes, so few items with
+// many boxes still use the whole block (each group recomputes the centres).
+__device__ inline int groups(int items, int nb)
+{
+    int g = items > 0 ? kVT / items : 1;
+    if (g > nb) g = nb;
+    return g < 1 ? 1 : g;
+}
+
 __device__ inline bool present_near(const rgg_box &b, const double *ebox, int D)
 {
     bool ok = true;
@@ -385,14 +395,16 @@ __device__ void validate_one(ValShared &sh, const ValDev &v, int64_t e, int max_
         if (tid == 0) sh.hit = kNoHit;
         __syncthreads();
         over_pages<D>(sh, v, n_pages, [&](int nb) {
-            for (int w = tid; w < n_pts * B; w += kVT) {
-                const int k = w / B, i = w - k * B;
+            const int G = groups(n_pts * B, nb);
+            for (int w = tid; w < n_pts * B * G; w += kVT) {
+                const int item = w / G, grp = w - item * G;
+                const int k = item / B, i = item - k * B;
                 const int32_t kk = key(k);
                 if (kk >= sh.hit) continue;
                 double c[D];
                 centre_at<D>(sh.rob, sh.mot, ldexp((double)kk, -ex), i, c);
                 const double r2 = sh.rob.rad[i] * sh.rob.rad[i];
-                for (int b = 0; b < nb; ++b) {
+                for (int b = grp; b < nb; b += G) {
                     if (vpoint_box<D>(c, sh.box[b], sh.box[b] + 3) <= r2) {
                         atomicMin(&sh.hit, kk);
                         break;
@@ -408,15 +420,17 @@ __device__ void validate_one(ValShared &sh, const ValDev &v, int64_t e, int max_
         __syncthreads();
         const double wl = ldexp(1.0, -l);
         over_pages<D>(sh, v, n_pages, [&](int nb) {
-            for (int w = tid; w < n_children * B; w += kVT) {
-                const int k = w / B, i = w - k * B;
+            const int G = groups(n_children * B, nb);
+            for (int w = tid; w < n_children * B * G; w += kVT) {
+                const int item = w / G, grp = w - item * G;
+                const int k = item / B, i = item - k * B;
                 if (sh.flag[k]) continue;
                 const int32_t j = child(k);
                 double ca[D], cb[D];
                 centre_at<D>(sh.rob, sh.mot, ldexp((double)j, -l), i, ca);
                 centre_at<D>(sh.rob, sh.mot, ldexp((double)(j + 1), -l), i, cb);
                 const double R = sh.rob.rad[i] + sh.del[i] * (wl * wl);
-                for (int b = 0; b < nb; ++b) {
+                for (int b = grp; b < nb; b += G) {
                     if (vsegbox<D>(ca, cb, sh.box[b], sh.box[b] + 3) <= R * R) {
                         sh.flag[k] = 1;
                         break;
@@ -492,7 +506,7 @@ __device__ void validate_one(ValShared &sh, const ValDev &v, int64_t e, int max_
 }
 
 template <int D>
-__global__ __launch_bounds__(kVT) void k_validate(ValDev v, const int64_t *ids, int64_t n,
+__global__ __launch_bounds__(kVT, 4) void k_validate(ValDev v, const int64_t *ids, int64_t n,
                                                   const rgg_update_result *count, int max_level, int max_active,
                                                   uint8_t *verdict, int32_t *level, double *witness)
 {
