@@ -40,7 +40,7 @@ namespace rgg {
 namespace {
 
 constexpr int kVT = 256;           // threads per block
-constexpr int kVGrid = 2048;       // blocks at most
+constexpr int kVGrid = 16384;      // blocks at most (the hardware balances them)
 constexpr int kNoHit = 0x7fffffff;
 
 constexpr uint8_t kFree = RGG_VERDICT_FREE;
@@ -389,65 +389,77 @@ __device__ void validate_one(ValShared &sh, const ValDev &v, int64_t e, int max_
     int32_t out_level = 0;
     double out_t = NAN;
 
-    // hit(t) at the points ldexp(key(k), -sh_l), k < n_pts; returns the
-    // smallest key that hits (kNoHit if none)
-    auto hits = [&](int n_pts, int ex, auto &&key) {
+    // One phase of the search: hit(t) at the points ldexp(key(k), -ex),
+    // k < n_pts (sh.hit = the smallest key that hits, kNoHit if none), and
+    // free(lc, child(k)) for k < n_children (sh.flag[k] = 1 when not free).
+    // The children's tests only matter when no point hits; computing both in
+    // one pass saves a barrier-separated phase per level.
+    auto step = [&](int n_pts, int ex, auto &&key, int lc, int n_children, auto &&child) {
         if (tid == 0) sh.hit = kNoHit;
+        for (int k = tid; k < n_children; k += kVT) sh.flag[k] = 0;
         __syncthreads();
+        const double wl = ldexp(1.0, -lc);
+        const int hit_items = n_pts * B, all_items = (n_pts + n_children) * B;
         over_pages<D>(sh, v, n_pages, [&](int nb) {
-            const int G = groups(n_pts * B, nb);
-            for (int w = tid; w < n_pts * B * G; w += kVT) {
+            const int G = groups(all_items, nb);
+            for (int w = tid; w < all_items * G; w += kVT) {
                 const int item = w / G, grp = w - item * G;
-                const int k = item / B, i = item - k * B;
-                const int32_t kk = key(k);
-                if (kk >= sh.hit) continue;
-                double c[D];
-                centre_at<D>(sh.rob, sh.mot, ldexp((double)kk, -ex), i, c);
-                const double r2 = sh.rob.rad[i] * sh.rob.rad[i];
-                for (int b = grp; b < nb; b += G) {
-                    if (vpoint_box<D>(c, sh.box[b], sh.box[b] + 3) <= r2) {
-                        atomicMin(&sh.hit, kk);
-                        break;
+                if (item < hit_items) {
+                    const int k = item / B, i = item - k * B;
+                    const int32_t kk = key(k);
+                    if (kk >= sh.hit) continue;
+                    double c[D];
+                    centre_at<D>(sh.rob, sh.mot, ldexp((double)kk, -ex), i, c);
+                    const double r2 = sh.rob.rad[i] * sh.rob.rad[i];
+                    for (int b = grp; b < nb; b += G) {
+                        if (vpoint_box<D>(c, sh.box[b], sh.box[b] + 3) <= r2) {
+                            atomicMin(&sh.hit, kk);
+                            break;
+                        }
+                    }
+                } else {
+                    const int it = item - hit_items;
+                    const int k = it / B, i = it - k * B;
+                    if (sh.flag[k] || sh.hit != kNoHit) continue;
+                    const int32_t j = child(k);
+                    double ca[D], cb[D];
+                    centre_at<D>(sh.rob, sh.mot, ldexp((double)j, -lc), i, ca);
+                    centre_at<D>(sh.rob, sh.mot, ldexp((double)(j + 1), -lc), i, cb);
+                    const double R = sh.rob.rad[i] + sh.del[i] * (wl * wl);
+                    // the capsule's bounding box, widened far beyond rounding:
+                    // a box outside it is farther than R from the segment
+                    double clo[D], chi[D];
+#pragma unroll
+                    for (int d = 0; d < D; ++d) {
+                        const double mn = ca[d] < cb[d] ? ca[d] : cb[d], mx = ca[d] < cb[d] ? cb[d] : ca[d];
+                        clo[d] = mn - (R * 1.000001 + 1e-9 * (1.0 + fabs(mn)));
+                        chi[d] = mx + (R * 1.000001 + 1e-9 * (1.0 + fabs(mx)));
+                    }
+                    for (int b = grp; b < nb; b += G) {
+                        bool apart = false;
+#pragma unroll
+                        for (int d = 0; d < D; ++d)
+                            apart = apart || sh.box[b][d] > chi[d] || sh.box[b][3 + d] < clo[d];
+                        if (apart) continue;
+                        if (vsegbox<D>(ca, cb, sh.box[b], sh.box[b] + 3) <= R * R) {
+                            sh.flag[k] = 1;
+                            break;
+                        }
                     }
                 }
             }
         });
         return sh.hit;
     };
-    // free(l, child(k)) for k < n_children; sh.flag[k] = 1 when not free
-    auto nonfree = [&](int l, int n_children, auto &&child) {
-        for (int k = tid; k < n_children; k += kVT) sh.flag[k] = 0;
-        __syncthreads();
-        const double wl = ldexp(1.0, -l);
-        over_pages<D>(sh, v, n_pages, [&](int nb) {
-            const int G = groups(n_children * B, nb);
-            for (int w = tid; w < n_children * B * G; w += kVT) {
-                const int item = w / G, grp = w - item * G;
-                const int k = item / B, i = item - k * B;
-                if (sh.flag[k]) continue;
-                const int32_t j = child(k);
-                double ca[D], cb[D];
-                centre_at<D>(sh.rob, sh.mot, ldexp((double)j, -l), i, ca);
-                centre_at<D>(sh.rob, sh.mot, ldexp((double)(j + 1), -l), i, cb);
-                const double R = sh.rob.rad[i] + sh.del[i] * (wl * wl);
-                for (int b = grp; b < nb; b += G) {
-                    if (vsegbox<D>(ca, cb, sh.box[b], sh.box[b] + 3) <= R * R) {
-                        sh.flag[k] = 1;
-                        break;
-                    }
-                }
-            }
-        });
-    };
 
     do {
-        const int h0 = hits(2, 0, [](int k) { return (int32_t)k; });   // t = 0, then t = 1
+        // t = 0, then t = 1 (key = t), and the whole edge's capsules
+        const int h0 = step(2, 0, [](int k) { return (int32_t)k; }, 0, 1, [](int) { return 0; });
         if (h0 != kNoHit) {
             out = kCollides;
             out_t = (double)h0;
             break;
         }
-        nonfree(0, 1, [](int) { return 0; });
         if (!sh.flag[0]) {
             out = kFree;
             break;
@@ -463,7 +475,8 @@ __device__ void validate_one(ValShared &sh, const ValDev &v, int64_t e, int max_
                 done = true;
                 break;
             }
-            const int h = hits(na, l + 1, [&](int k) { return 2 * sh.act[k] + 1; });
+            const int h = step(na, l + 1, [&](int k) { return 2 * sh.act[k] + 1; }, l + 1, 2 * na,
+                               [&](int k) { return 2 * sh.act[k >> 1] + (k & 1); });
             if (h != kNoHit) {
                 out = kCollides;
                 out_level = l + 1;
@@ -471,7 +484,6 @@ __device__ void validate_one(ValShared &sh, const ValDev &v, int64_t e, int max_
                 done = true;
                 break;
             }
-            nonfree(l + 1, 2 * na, [&](int k) { return 2 * sh.act[k >> 1] + (k & 1); });
             if (tid == 0) sh.n_next = 0;
             __syncthreads();
             for (int k = tid; k < 2 * na; k += kVT)
