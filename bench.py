@@ -83,8 +83,11 @@ def measured_traffic(kernel):
     import glob
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
-    src = os.path.join(root, "paper_2603_28674_amd", "csrc", "kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    csrc = os.path.join(root, "paper_2603_28674_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "predicates64.h"):     # the update kernels' device source
+        h.update(open(os.path.join(csrc, name), "rb").read())
+    sha = h.hexdigest()
     for path in glob.glob(os.path.join(root, "profiles", "*.md")):
         for ln in open(path):
             if ln.startswith("traffic-record:"):

@@ -22,7 +22,7 @@
 // reduction by pi/2, Taylor series to degree 19/20), compiled without
 // contraction, so any IEEE evaluator of the same steps reaches the same
 // verdicts.  The distance predicates are the binary64 definitions of the
-// update kernels.
+// update kernels (predicates64.h).
 //
 // One block of 256 threads validates one listed edge at a time (grid-stride
 // over the list).  Its present boxes near the edge are staged in LDS: a box
@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "predicates64.h"
 #include "rgg_device.h"
 
 namespace rgg {
@@ -46,109 +47,6 @@ constexpr int kNoHit = 0x7fffffff;
 constexpr uint8_t kFree = RGG_VERDICT_FREE;
 constexpr uint8_t kCollides = RGG_VERDICT_COLLIDES;
 constexpr uint8_t kUnresolved = RGG_VERDICT_UNRESOLVED;
-
-// ---- binary64 predicates (the definitions the update kernels evaluate) ----
-
-__device__ inline double vgap(double x, double lo, double hi)
-{
-    double a = lo - x;
-    double g = a > 0.0 ? a : 0.0;
-    double b = x - hi;
-    return b > g ? b : g;
-}
-
-template <int D>
-__device__ inline double vpoint_box(const double *c, const double *lo, const double *hi)
-{
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        double g = vgap(c[k], lo[k], hi[k]);
-        acc = acc + g * g;
-    }
-    return acc;
-}
-
-template <int D>
-__device__ inline double vseg_F(const double *A, const double *d, double t, const double *lo, const double *hi)
-{
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        double p = A[k] + t * d[k];
-        double g = vgap(p, lo[k], hi[k]);
-        acc = acc + g * g;
-    }
-    return acc;
-}
-
-template <int D>
-__device__ inline double vseg_G(const double *A, const double *d, double t, const double *lo, const double *hi)
-{
-    double acc = 0.0;
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        double p = A[k] + t * d[k];
-        double ex = p < lo[k] ? p - lo[k] : (p > hi[k] ? p - hi[k] : 0.0);
-        acc = acc + d[k] * ex;
-    }
-    return acc;
-}
-
-// minimum over the segment A->B of the squared distance to the box (convex,
-// piecewise quadratic; bracket the minimiser between face crossings, then
-// clamp the stationary point of the one quadratic in the bracket)
-template <int D>
-__device__ inline double vsegbox(const double *A, const double *Bp, const double *lo, const double *hi)
-{
-    double d[D];
-#pragma unroll
-    for (int k = 0; k < D; ++k) d[k] = Bp[k] - A[k];
-    double tL = 0.0, tR = 1.0;
-    auto take = [&](double t) {
-        double g = vseg_G<D>(A, d, t, lo, hi);
-        if (g <= 0.0 && t > tL) tL = t;
-        if (g >= 0.0 && t < tR) tR = t;
-    };
-    take(0.0);
-    take(1.0);
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-        if (d[k] != 0.0) {
-            double t1 = (lo[k] - A[k]) / d[k];
-            if (t1 > 0.0 && t1 < 1.0) take(t1);
-            double t2 = (hi[k] - A[k]) / d[k];
-            if (t2 > 0.0 && t2 < 1.0) take(t2);
-        }
-    }
-    double fL = vseg_F<D>(A, d, tL, lo, hi);
-    double fR = vseg_F<D>(A, d, tR, lo, hi);
-    double fmin = fL < fR ? fL : fR;
-    if (tL < tR) {
-        double tm = 0.5 * (tL + tR);
-        double num = 0.0, den = 0.0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            double p = A[k] + tm * d[k];
-            if (p < lo[k]) {
-                num = num + d[k] * (lo[k] - A[k]);
-                den = den + d[k] * d[k];
-            } else if (p > hi[k]) {
-                num = num + d[k] * (hi[k] - A[k]);
-                den = den + d[k] * d[k];
-            }
-        }
-        double ts = tL;
-        if (den > 0.0) {
-            ts = num / den;
-            if (ts < tL) ts = tL;
-            if (ts > tR) ts = tR;
-        }
-        double fs = vseg_F<D>(A, d, ts, lo, hi);
-        if (fs < fmin) fmin = fs;
-    }
-    return fmin;
-}
 
 // ---- configurations --------------------------------------------------------
 
@@ -305,7 +203,7 @@ __device__ inline bool present_near(const rgg_box &b, const double *ebox, int D)
 // Stages candidate boxes [page * kValBoxes, ...) into sh.box (in slot order)
 // and leaves their number in sh.n_page and the total in sh.n_cand.
 template <int D>
-__device__ void gather_page(ValShared &sh, const ValDev &v, int page)
+__device__ __forceinline__ void gather_page(ValShared &sh, const ValDev &v, int page)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t lo_rank = (int64_t)page * kValBoxes;
@@ -344,7 +242,7 @@ __device__ void gather_page(ValShared &sh, const ValDev &v, int page)
 // Runs `test(n_boxes)` over every page of candidate boxes (the staged page
 // when there is only one).
 template <int D, typename F>
-__device__ void over_pages(ValShared &sh, const ValDev &v, int n_pages, F &&test)
+__device__ __forceinline__ void over_pages(ValShared &sh, const ValDev &v, int n_pages, F &&test)
 {
     if (n_pages <= 1) {
         test(sh.n_page);
@@ -359,7 +257,7 @@ __device__ void over_pages(ValShared &sh, const ValDev &v, int n_pages, F &&test
 }
 
 template <int D>
-__device__ void validate_one(ValShared &sh, const ValDev &v, int64_t e, int max_level, int max_active,
+__device__ __forceinline__ void validate_one(ValShared &sh, const ValDev &v, int64_t e, int max_level, int max_active,
                              uint8_t *verdict, int32_t *level, double *witness)
 {
     const int tid = threadIdx.x;
@@ -412,7 +310,7 @@ __device__ void validate_one(ValShared &sh, const ValDev &v, int64_t e, int max_
                     centre_at<D>(sh.rob, sh.mot, ldexp((double)kk, -ex), i, c);
                     const double r2 = sh.rob.rad[i] * sh.rob.rad[i];
                     for (int b = grp; b < nb; b += G) {
-                        if (vpoint_box<D>(c, sh.box[b], sh.box[b] + 3) <= r2) {
+                        if (point_box64<D>(c, sh.box[b], sh.box[b] + 3) <= r2) {
                             atomicMin(&sh.hit, kk);
                             break;
                         }
@@ -441,7 +339,7 @@ __device__ void validate_one(ValShared &sh, const ValDev &v, int64_t e, int max_
                         for (int d = 0; d < D; ++d)
                             apart = apart || sh.box[b][d] > chi[d] || sh.box[b][3 + d] < clo[d];
                         if (apart) continue;
-                        if (vsegbox<D>(ca, cb, sh.box[b], sh.box[b] + 3) <= R * R) {
+                        if (segbox64<D>(ca, cb, sh.box[b], sh.box[b] + 3) <= R * R) {
                             sh.flag[k] = 1;
                             break;
                         }
