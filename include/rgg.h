@@ -363,14 +363,19 @@ rgg_status rgg_batch_tune(rgg_batch *b, const rgg_box *const *obstacles_a, const
  * before, e.g. with d_ids its gray list), only the first
  * min(n, d_count->n_gray) ids are validated, and none if that update failed;
  * an id that is not an edge gets RGG_VERDICT_BAD_ID.  Entries past the
- * validated count are left as they were. */
+ * validated count are left as they were.  When d_labels (a device label
+ * array of the roadmap's E edges, e.g. the update's) is non-null, each
+ * validated edge's label becomes RGG_GREEN (FREE) or RGG_RED (COLLIDES or
+ * UNRESOLVED): after rgg_update_async and this call on one stream it holds
+ * the non-lazy labels, with no GRAY left among the validated edges.  The
+ * roadmap's own state (its counters, rgg_labels) keeps the RGG labels. */
 #define RGG_VALIDATE_DEFAULT_LEVELS 24
 #define RGG_VALIDATE_DEFAULT_ACTIVE 256
 rgg_status rgg_validate(rgg_roadmap *rm, const int64_t *ids, int64_t n, int32_t max_level, int32_t max_active,
                         uint8_t *verdict, int32_t *level, double *witness);
 rgg_status rgg_validate_async(rgg_roadmap *rm, void *stream, const int64_t *d_ids, int64_t n,
                               const rgg_update_result *d_count, int32_t max_level, int32_t max_active,
-                              uint8_t *d_verdict, int32_t *d_level, double *d_witness);
+                              uint8_t *d_verdict, int32_t *d_level, double *d_witness, uint8_t *d_labels);
 
 /* Persistence between planning iterations (Sec. 1 and Sec. 3.3: the
  * approximations are computed once and then stored and reloaded).

@@ -712,7 +712,7 @@ static rgg_status check_validate_args(rgg_roadmap *rm, int64_t n, int32_t *max_l
 
 rgg_status rgg_validate_async(rgg_roadmap *rm, void *stream, const int64_t *d_ids, int64_t n,
                               const rgg_update_result *d_count, int32_t max_level, int32_t max_active,
-                              uint8_t *d_verdict, int32_t *d_level, double *d_witness)
+                              uint8_t *d_verdict, int32_t *d_level, double *d_witness, uint8_t *d_labels)
 {
     rgg_status st = check_validate_args(rm, n, &max_level, &max_active);
     if (st != RGG_OK) return st;
@@ -720,7 +720,8 @@ rgg_status rgg_validate_async(rgg_roadmap *rm, void *stream, const int64_t *d_id
     HIP_OR_FAIL(hipSetDevice(rm->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     if ((st = order_after_previous(rm, s)) != RGG_OK) return st;
-    HIP_OR_FAIL(launch_validate(rm->val, d_ids, n, d_count, max_level, max_active, d_verdict, d_level, d_witness, s),
+    HIP_OR_FAIL(launch_validate(rm->val, d_ids, n, d_count, max_level, max_active, d_verdict, d_level, d_witness,
+                                d_labels, s),
                 "validate launch");
     return finish_update(rm, s);
 }
@@ -749,7 +750,8 @@ rgg_status rgg_validate(rgg_roadmap *rm, const int64_t *ids, int64_t n, int32_t 
         rgg_status r = order_after_previous(rm, s);
         if (r != RGG_OK) return r;
         HIP_OR_FAIL(hipMemcpyAsync(d_ids, ids, b_ids, hipMemcpyHostToDevice, s), "upload ids");
-        HIP_OR_FAIL(launch_validate(rm->val, d_ids, n, nullptr, max_level, max_active, d_ver, d_lev, d_wit, s),
+        HIP_OR_FAIL(launch_validate(rm->val, d_ids, n, nullptr, max_level, max_active, d_ver, d_lev, d_wit, nullptr,
+                                    s),
                     "validate launch");
         if ((r = finish_update(rm, s)) != RGG_OK) return r;
         HIP_OR_FAIL(hipMemcpyAsync(verdict, d_ver, (size_t)n, hipMemcpyDeviceToHost, s), "read verdicts");

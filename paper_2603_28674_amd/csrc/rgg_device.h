@@ -159,9 +159,11 @@ struct ValDev {
 
 // Queues the validation of ids[0 .. n) (n capped by count->n_gray when
 // count is non-null, and zero when count->status is not RGG_OK) on `s`.
+// When labels is non-null, each validated edge's entry becomes GREEN (FREE)
+// or RED (COLLIDES, UNRESOLVED).
 hipError_t launch_validate(const ValDev &v, const int64_t *ids, int64_t n, const rgg_update_result *count,
                            int32_t max_level, int32_t max_active, uint8_t *verdict, int32_t *level,
-                           double *witness, hipStream_t s);
+                           double *witness, uint8_t *labels, hipStream_t s);
 
 // Queues the kernels of one update on `s`.  When `ev` is non-null, ev[0..6]
 // are recorded before, between and after the stages (diff, cells, grid scan,

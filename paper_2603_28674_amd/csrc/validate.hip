@@ -258,7 +258,7 @@ __device__ __forceinline__ void over_pages(ValShared &sh, const ValDev &v, int n
 
 template <int D>
 __device__ __forceinline__ void validate_one(ValShared &sh, const ValDev &v, int64_t e, int max_level, int max_active,
-                             uint8_t *verdict, int32_t *level, double *witness)
+                             uint8_t *verdict, int32_t *level, double *witness, uint8_t *labels)
 {
     const int tid = threadIdx.x;
     const int B = v.B;
@@ -411,6 +411,7 @@ __device__ __forceinline__ void validate_one(ValShared &sh, const ValDev &v, int
         verdict[0] = out;
         level[0] = out_level;
         witness[0] = out_t;
+        if (labels) labels[e] = out == kFree ? (uint8_t)RGG_GREEN : (uint8_t)RGG_RED;
     }
     __syncthreads();
 }
@@ -418,7 +419,7 @@ __device__ __forceinline__ void validate_one(ValShared &sh, const ValDev &v, int
 template <int D>
 __global__ __launch_bounds__(kVT, 4) void k_validate(ValDev v, const int64_t *ids, int64_t n,
                                                   const rgg_update_result *count, int max_level, int max_active,
-                                                  uint8_t *verdict, int32_t *level, double *witness)
+                                                  uint8_t *verdict, int32_t *level, double *witness, uint8_t *labels)
 {
     __shared__ ValShared sh;
     const int tid = threadIdx.x;
@@ -443,7 +444,7 @@ __global__ __launch_bounds__(kVT, 4) void k_validate(ValDev v, const int64_t *id
             }
             continue;
         }
-        validate_one<D>(sh, v, e, max_level, max_active, verdict + i, level + i, witness + i);
+        validate_one<D>(sh, v, e, max_level, max_active, verdict + i, level + i, witness + i, labels);
     }
 }
 
@@ -451,14 +452,14 @@ __global__ __launch_bounds__(kVT, 4) void k_validate(ValDev v, const int64_t *id
 
 hipError_t launch_validate(const ValDev &v, const int64_t *ids, int64_t n, const rgg_update_result *count,
                            int32_t max_level, int32_t max_active, uint8_t *verdict, int32_t *level,
-                           double *witness, hipStream_t s)
+                           double *witness, uint8_t *labels, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const int grid = (int)(n < kVGrid ? n : kVGrid);
     if (v.D == 3)
-        k_validate<3><<<grid, kVT, 0, s>>>(v, ids, n, count, max_level, max_active, verdict, level, witness);
+        k_validate<3><<<grid, kVT, 0, s>>>(v, ids, n, count, max_level, max_active, verdict, level, witness, labels);
     else
-        k_validate<2><<<grid, kVT, 0, s>>>(v, ids, n, count, max_level, max_active, verdict, level, witness);
+        k_validate<2><<<grid, kVT, 0, s>>>(v, ids, n, count, max_level, max_active, verdict, level, witness, labels);
     return hipGetLastError();
 }
 

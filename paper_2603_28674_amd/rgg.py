@@ -176,7 +176,7 @@ def lib():
         "rgg_batch_tune": (I32, [P, P, P, I32, P]),
         "rgg_save": (I32, [P, C.c_char_p]),
         "rgg_validate": (I32, [P, P, I64, I32, I32, P, P, P]),
-        "rgg_validate_async": (I32, [P, P, P, I64, P, I32, I32, P, P, P]),
+        "rgg_validate_async": (I32, [P, P, P, I64, P, I32, I32, P, P, P, P]),
         "rgg_load": (I32, [P, C.c_char_p, C.POINTER(P)]),
         "rgg_debug_geometry": (I32, [P, P, P, I64, I64, P, P, P, P]),
         "rgg_last_error": (C.c_char_p, []),
@@ -463,12 +463,14 @@ def rgg_validate(rm, ids, max_level=0, max_active=0):
     return verdict[:n], level[:n], witness[:n]
 
 
-def rgg_validate_async(rm, stream, d_ids, n, d_count, d_verdict, d_level, d_witness, max_level=0, max_active=0):
+def rgg_validate_async(rm, stream, d_ids, n, d_count, d_verdict, d_level, d_witness, max_level=0, max_active=0,
+                       d_labels=None):
     """Device-buffer validation queued on ``stream``; ``d_count`` (a result
-    tensor of an earlier update, or None) caps the count at its n_gray."""
+    tensor of an earlier update, or None) caps the count at its n_gray;
+    ``d_labels`` (or None) receives GREEN / RED for the validated edges."""
     _check(lib().rgg_validate_async(rm, C.c_void_p(stream), _dptr(d_ids), int(n), _dptr(d_count),
                                     int(max_level), int(max_active), _dptr(d_verdict), _dptr(d_level),
-                                    _dptr(d_witness)))
+                                    _dptr(d_witness), _dptr(d_labels)))
 
 
 def rgg_save(rm, path):

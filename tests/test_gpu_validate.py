@@ -153,6 +153,18 @@ def test_validate_async_after_update(ctx):
     assert n == len(og)
     same((ver[:n].cpu().numpy(), lev[:n].cpu().numpy(), wit[:n].cpu().numpy()), o.validate(og), "async")
     assert torch.all(ver[n:] == 77) and torch.all(lev[n:] == -7)
+    # non-lazy labels: the validated gray edges become GREEN (FREE) or RED
+    final = labels.clone()
+    rgg.rgg_validate_async(g.h, stream, gray, E, res, ver, lev, wit, d_labels=final)
+    torch.cuda.synchronize()
+    before, after = labels.cpu().numpy(), final.cpu().numpy()
+    ov = o.validate(og)[0]
+    assert not np.any(after == 1), "a validated label stayed GRAY"
+    assert np.array_equal(after[og], np.where(ov == FREE, 0, 2))
+    rest = np.ones(E, dtype=bool)
+    rest[og] = False
+    assert np.array_equal(after[rest], before[rest])
+    assert np.array_equal(g.labels(), before), "the roadmap keeps its RGG labels"
     # a failed update (stale `old`) validates nothing
     ver.fill_(77)
     g.update_async(stream, states[0], states[2], labels, gray, res)
