@@ -358,8 +358,9 @@ rgg_status rgg_batch_tune(rgg_batch *b, const rgg_box *const *obstacles_a, const
  * rgg_validate: host arrays ids[n] (each an edge id, else RGG_E_INVALID_ARG),
  * verdict[n], level[n] and witness[n] (level and witness may be NULL);
  * returns when done.
- * rgg_validate_async: device arrays, queued on `stream` after the roadmap's
- * previous update.  When d_count is non-null (the result of an update queued
+ * rgg_validate_async: device arrays (d_verdict, d_level and d_witness may
+ * each be NULL when d_labels is given), queued on `stream` after the
+ * roadmap's previous update.  When d_count is non-null (the result of an update queued
  * before, e.g. with d_ids its gray list), only the first
  * min(n, d_count->n_gray) ids are validated, and none if that update failed;
  * an id that is not an edge gets RGG_VERDICT_BAD_ID.  Entries past the
@@ -425,6 +426,14 @@ typedef struct {
     uint8_t *d_labels;            /* [E] device or NULL; written in order       */
     int64_t *d_gray;              /* [gray_cap] device or NULL                  */
     int64_t gray_cap;
+    int32_t validate;             /* non-zero: non-lazy (Alg. 1 when not lazy):
+                                     after the update, the gray list is validated
+                                     as rgg_validate_async with default limits and
+                                     d_labels / d_gray (both required) given, so
+                                     d_labels ends with GREEN or RED for every
+                                     validated gray edge                        */
+    uint8_t *d_verdict;           /* [gray_cap] device or NULL: the verdicts of
+                                     the validated gray list entries            */
 } rgg_server_req;
 
 /* Starts the server (its worker thread and streams) on ctx's device. */

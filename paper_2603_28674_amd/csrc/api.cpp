@@ -716,7 +716,8 @@ rgg_status rgg_validate_async(rgg_roadmap *rm, void *stream, const int64_t *d_id
 {
     rgg_status st = check_validate_args(rm, n, &max_level, &max_active);
     if (st != RGG_OK) return st;
-    if (n > 0 && (!d_ids || !d_verdict || !d_level || !d_witness)) return fail(RGG_E_INVALID_ARG, "null array");
+    if (n > 0 && (!d_ids || (!d_verdict && !d_labels)))
+        return fail(RGG_E_INVALID_ARG, "null ids, or neither verdicts nor labels requested");
     HIP_OR_FAIL(hipSetDevice(rm->device), "hipSetDevice");
     hipStream_t s = (hipStream_t)stream;
     if ((st = order_after_previous(rm, s)) != RGG_OK) return st;

@@ -160,7 +160,7 @@ struct ValDev {
 // Queues the validation of ids[0 .. n) (n capped by count->n_gray when
 // count is non-null, and zero when count->status is not RGG_OK) on `s`.
 // When labels is non-null, each validated edge's entry becomes GREEN (FREE)
-// or RED (COLLIDES, UNRESOLVED).
+// or RED (COLLIDES, UNRESOLVED).  verdict, level and witness may be null.
 hipError_t launch_validate(const ValDev &v, const int64_t *ids, int64_t n, const rgg_update_result *count,
                            int32_t max_level, int32_t max_active, uint8_t *verdict, int32_t *level,
                            double *witness, uint8_t *labels, hipStream_t s);

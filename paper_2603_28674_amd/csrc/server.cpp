@@ -78,6 +78,8 @@ struct Pending {
     uint8_t *d_labels;
     int64_t *d_gray;
     int64_t gray_cap;
+    bool validate;
+    uint8_t *d_verdict;
     Clock::time_point submitted;
     int64_t bytes;                // pool bytes
 };
@@ -186,6 +188,15 @@ bool rgg_server::dispatch(Slot &slot, std::vector<Pending> &batch)
     if (launch_batch(s, slot.d_tab, slot.d_grp, n, groups.data(), (int)groups.size(), any_grid, tiles, wtiles) !=
         hipSuccess)
         return false;
+    // non-lazy requests: validate each gray list after the batch, on the
+    // same stream, capped by the request's own result
+    for (int r = 0; r < n; ++r) {
+        const Pending &q = batch[r];
+        if (!q.validate || q.gray_cap == 0) continue;
+        if (launch_validate(q.rm->val, q.d_gray, q.gray_cap, slot.d_res + r, RGG_VALIDATE_DEFAULT_LEVELS,
+                            RGG_VALIDATE_DEFAULT_ACTIVE, q.d_verdict, nullptr, nullptr, q.d_labels, s) != hipSuccess)
+            return false;
+    }
     if (hipMemcpyAsync(slot.h_res, slot.d_res, sizeof(rgg_update_result) * n, hipMemcpyDeviceToHost, s) != hipSuccess)
         return false;
     if (hipEventRecord(slot.ev, s) != hipSuccess) return false;
@@ -381,9 +392,13 @@ rgg_status rgg_server_submit(rgg_server *srv, const rgg_server_req *req, uint64_
         memcpy(p.boxes.data(), req->old_boxes, sizeof(rgg_box) * M);
         memcpy(p.boxes.data() + M, req->new_boxes, sizeof(rgg_box) * M);
     }
+    if (req->validate && (!req->d_labels || !req->d_gray))
+        return fail(RGG_E_INVALID_ARG, "a validated request needs d_labels and d_gray");
     p.d_labels = req->d_labels;
     p.d_gray = req->d_gray;
     p.gray_cap = req->gray_cap;
+    p.validate = req->validate != 0;
+    p.d_verdict = req->d_verdict;
     p.bytes = bytes;
     {
         std::lock_guard<std::mutex> lk(srv->mu);

@@ -408,9 +408,9 @@ __device__ __forceinline__ void validate_one(ValShared &sh, const ValDev &v, int
     } while (false);
     __syncthreads();
     if (tid == 0) {
-        verdict[0] = out;
-        level[0] = out_level;
-        witness[0] = out_t;
+        if (verdict) verdict[0] = out;
+        if (level) level[0] = out_level;
+        if (witness) witness[0] = out_t;
         if (labels) labels[e] = out == kFree ? (uint8_t)RGG_GREEN : (uint8_t)RGG_RED;
     }
     __syncthreads();
@@ -438,13 +438,14 @@ __global__ __launch_bounds__(kVT, 4) void k_validate(ValDev v, const int64_t *id
         const int64_t e = ids[i];
         if (e < 0 || e >= v.E) {
             if (tid == 0) {
-                verdict[i] = RGG_VERDICT_BAD_ID;
-                level[i] = 0;
-                witness[i] = NAN;
+                if (verdict) verdict[i] = RGG_VERDICT_BAD_ID;
+                if (level) level[i] = 0;
+                if (witness) witness[i] = NAN;
             }
             continue;
         }
-        validate_one<D>(sh, v, e, max_level, max_active, verdict + i, level + i, witness + i, labels);
+        validate_one<D>(sh, v, e, max_level, max_active, verdict ? verdict + i : nullptr, level ? level + i : nullptr,
+                        witness ? witness + i : nullptr, labels);
     }
 }
 

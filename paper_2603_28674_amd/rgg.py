@@ -120,7 +120,8 @@ class rgg_server_opts(C.Structure):
 
 class rgg_server_req(C.Structure):
     _fields_ = [("rm", C.c_void_p), ("m", C.c_int64), ("old_boxes", C.c_void_p), ("new_boxes", C.c_void_p),
-                ("d_labels", C.c_void_p), ("d_gray", C.c_void_p), ("gray_cap", C.c_int64)]
+                ("d_labels", C.c_void_p), ("d_gray", C.c_void_p), ("gray_cap", C.c_int64),
+                ("validate", C.c_int32), ("d_verdict", C.c_void_p)]
 
 
 RESULT_BYTES = C.sizeof(rgg_update_result)
@@ -390,12 +391,14 @@ def rgg_server_start(ctx, n_streams=0, max_queue=0, max_batch=0, pool_bytes=0):
     return h
 
 
-def rgg_server_submit(srv, rm, old, new, d_labels=0, d_gray=0, gray_cap=0):
+def rgg_server_submit(srv, rm, old, new, d_labels=0, d_gray=0, gray_cap=0, validate=False, d_verdict=0):
     """Queues one update of roadmap handle `rm` (host box arrays [m, 6]);
-    returns the ticket."""
+    with ``validate`` the gray list is then validated and the gray labels
+    rewritten (non-lazy).  Returns the ticket."""
     old = boxes_array(old)
     new = boxes_array(new)
-    q = rgg_server_req(getattr(rm, "value", rm), old.shape[0], _ptr(old), _ptr(new), d_labels, d_gray, gray_cap)
+    q = rgg_server_req(getattr(rm, "value", rm), old.shape[0], _ptr(old), _ptr(new), d_labels, d_gray, gray_cap,
+                       1 if validate else 0, d_verdict)
     t = C.c_uint64()
     _check(lib().rgg_server_submit(srv, C.byref(q), C.byref(t)))
     return t.value

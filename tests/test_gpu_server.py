@@ -167,3 +167,53 @@ def test_server_mixed_decompositions(ctx):
         ol, og = expect[k][u]
         assert status == 0, f"roadmap {k} update {u}: status {status}"
         assert n_gray == len(og) and np.array_equal(lab, ol) and np.array_equal(gray, og), f"roadmap {k} update {u}"
+
+
+def test_server_non_lazy(ctx):
+    """Requests flagged for validation (Alg. 1 when not lazy): after each
+    update the server validates the gray list on the device and rewrites its
+    labels, in the mix with lazy requests.  The labels equal the oracle's
+    labels with every gray edge replaced by its validation outcome, and the
+    verdicts equal the oracle's."""
+    import torch
+    from paper_2603_28674_amd import rgg
+    import oracle
+    n_updates = 3
+    specs = roadmap_specs(n_updates)
+    dev = torch.device("cuda:0")
+    gs = [rgg.Roadmap.from_workload(ctx, w, precision=p, cell_size=c) for w, p, c, *_ in specs]
+    os_ = [oracle.from_workload(w) for w, *_ in specs]
+    srv = rgg.rgg_server_start(ctx, n_streams=2, max_batch=4)
+    outs, tickets = {}, {}
+    for u in range(n_updates):
+        for k, (w, *_) in enumerate(specs):
+            E = w.n_edges
+            lab = torch.zeros(E, dtype=torch.uint8, device=dev)
+            gray = torch.zeros(E, dtype=torch.int64, device=dev)
+            ver = torch.full((E,), 77, dtype=torch.uint8, device=dev)
+            non_lazy = (k + u) % 2 == 0
+            prev = w.absent() if u == 0 else w.boxes[u - 1]
+            tickets[(k, u)] = rgg.rgg_server_submit(srv, gs[k].h, prev, w.boxes[u], lab.data_ptr(), gray.data_ptr(),
+                                                    E, validate=non_lazy, d_verdict=ver.data_ptr())
+            outs[(k, u)] = (lab, gray, ver, non_lazy)
+    res = {key: rgg.rgg_server_poll(srv, t, wait=True) for key, t in tickets.items()}
+    rgg.rgg_server_stop(srv)
+    for u in range(n_updates):
+        for k, (w, *_) in enumerate(specs):
+            prev = w.absent() if u == 0 else w.boxes[u - 1]
+            ol, og = os_[k].update(prev, w.boxes[u])
+            done, r, _ = res[(k, u)]
+            lab, gray, ver, non_lazy = outs[(k, u)]
+            assert done and r.status == 0 and r.n_gray == len(og)
+            assert np.array_equal(gray[:r.n_gray].cpu().numpy(), og)
+            if non_lazy:
+                ov = os_[k].validate(og)[0]
+                want = ol.copy()
+                want[og] = np.where(ov == 0, 0, 2)
+                assert np.array_equal(lab.cpu().numpy(), want), f"roadmap {k} update {u}: non-lazy labels"
+                assert np.array_equal(ver[:r.n_gray].cpu().numpy(), ov)
+            else:
+                assert np.array_equal(lab.cpu().numpy(), ol)
+                assert torch.all(ver == 77)
+    for g in gs:
+        g.close()
