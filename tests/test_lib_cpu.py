@@ -142,3 +142,32 @@ def test_bench_refuses_several_gpus():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every struct the binding mirrors has the header's size and field
+    offsets (a C program built against include/rgg.h prints them)."""
+    import ctypes
+    import subprocess
+    structs = [getattr(rgg, n) for n in dir(rgg)
+               if n.startswith("rgg_") and isinstance(getattr(rgg, n), type)
+               and issubclass(getattr(rgg, n), ctypes.Structure)]
+    assert len(structs) >= 10
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "rgg.h"', 'int main(void) {']
+    for st in structs:
+        name = st.__name__
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, *_ in st._fields_:
+            lines.append(f'  printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                               check=True).stdout.split("\n") if line)
+    for st in structs:
+        name = st.__name__
+        assert int(out[f"{name} size"]) == ctypes.sizeof(st), name
+        for field, *_ in st._fields_:
+            assert int(out[f"{name}.{field}"]) == getattr(st, field).offset, f"{name}.{field}"
