@@ -187,7 +187,7 @@ def batched_planar(a):
         log(f"[bench] batched: tuned in {tuned['seconds']:.1f}s")
     for name, fn in (("plain", plain), ("batched", batched), ("batched_graph", batched_graph)):
         out[name], u = timed(fn, u)
-    lat = []
+    lat, round_bytes = [], []
     for _ in range(K):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -195,7 +195,12 @@ def batched_planar(a):
         u += 1
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e6)
+        round_bytes.append(sum(rgg.result_from_tensor(b[3]).test_bytes for b in bufs))
     ok = all(rgg.result_from_tensor(b[3]).status == 0 for b in bufs)
+    # the classify kernels' algorithmic bytes of a round over the whole
+    # round's time (every stage): a lower bound for the batched item kernel
+    rb = float(np.mean(round_bytes))
+    achieved = rb / (out["batched"]["ms_per_round"] * 1e-3) / 1e9
     rgg.rgg_batch_destroy(batch)
     for g in gs:
         g.close()
@@ -209,6 +214,10 @@ def batched_planar(a):
         "speedup_batched_vs_plain": out["batched"]["edges_per_s"] / out["plain"]["edges_per_s"],
         "batched_round_latency_p50_us": float(np.percentile(lat, 50)),
         "batched_round_latency_p99_us": float(np.percentile(lat, 99)),
+        "roofline_round": {"bound": "hbm", "bytes_per_round": rb, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "note": "classify bytes of all roadmaps per round over the round's wall time "
+                                   "(all stages, pipelined rounds): a lower bound for k_item32_batch"},
         "status_ok": ok,
     }
 
