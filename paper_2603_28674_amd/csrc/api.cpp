@@ -1313,7 +1313,10 @@ rgg_status rgg_save(rgg_roadmap *rm, const char *path)
     out.put(vdel.data(), sizeof(double) * vdel.size());
     const uint64_t sum = out.sum.h;
     out.put(&sum, sizeof sum);
-    if (!out.ok || fflush(out.f) != 0) return fail(RGG_E_INVALID_ARG, "writing %s failed", path);
+    const bool flushed = out.ok && fflush(out.f) == 0;
+    const bool closed = fclose(out.f) == 0;
+    out.f = nullptr;
+    if (!flushed || !closed) return fail(RGG_E_INVALID_ARG, "writing %s failed", path);
     return RGG_OK;
 }
 
@@ -1351,8 +1354,14 @@ rgg_status rgg_load(rgg_context *ctx, const char *path, rgg_roadmap **out)
     } catch (const std::bad_alloc &) {
         return fail(RGG_E_OUT_OF_MEMORY, "host memory for %s", path);
     }
-    std::vector<rgg_box> resident((size_t)h.M);
-    std::vector<int2> cnt((size_t)h.E);
+    std::vector<rgg_box> resident;
+    std::vector<int2> cnt;
+    try {
+        resident.resize((size_t)h.M);
+        cnt.resize((size_t)h.E);
+    } catch (const std::bad_alloc &) {
+        return fail(RGG_E_OUT_OF_MEMORY, "host memory for %s", path);
+    }
     in.get(g.samp.data(), sizeof(double) * g.samp.size());
     in.get(g.cap.data(), sizeof(double) * g.cap.size());
     in.get(g.radius.data(), sizeof(double) * g.radius.size());

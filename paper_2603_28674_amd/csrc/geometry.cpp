@@ -20,6 +20,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <new>
 #include <thread>
 
 #include "rgg_internal.h"
@@ -418,8 +419,10 @@ int32_t cell_coord(double x, double org, double inv, int32_t n)
     return (int32_t)c;
 }
 
-rgg_status build_grid(const HostGeometry &g, double cell_size, int32_t chunk, HostGrid *out,
-                      std::string *err)
+namespace {
+
+rgg_status build_grid_body(const HostGeometry &g, double cell_size, int32_t chunk, HostGrid *out,
+                           std::string *err)
 {
     const int D = g.D;
     const int64_t E = g.E;
@@ -522,6 +525,19 @@ rgg_status build_grid(const HostGeometry &g, double cell_size, int32_t chunk, Ho
     }
     out->items_cap = items;
     return RGG_OK;
+}
+
+}  // namespace
+
+rgg_status build_grid(const HostGeometry &g, double cell_size, int32_t chunk, HostGrid *out,
+                      std::string *err)
+{
+    try {
+        return build_grid_body(g, cell_size, chunk, out, err);
+    } catch (const std::bad_alloc &) {
+        *err = "host memory for the grid";
+        return RGG_E_OUT_OF_MEMORY;
+    }
 }
 
 }  // namespace rgg
