@@ -200,3 +200,29 @@ def test_validate_argument_errors(ctx):
     v, lv, wt = g.validate(np.zeros(0, dtype=np.int64))
     assert v.size == 0
     g.close()
+
+
+def test_validate_deep_searches(ctx):
+    """Grazing contacts that take the search to level 21-28 (dyadic indices
+    near 2^28), at several limits: verdicts, levels and witnesses equal the
+    oracle's."""
+    import math
+    from paper_2603_28674_amd import rgg
+    import oracle
+    rob = synth.Robot(synth.SE2, np.array([[2.0, 0.0]]), np.array([0.1]))
+    q = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, math.pi / 2]])
+    edges = np.array([[0, 1]])
+    print("[validate] deep searches", flush=True)
+    for rc in (1.9, 1.9 - 1e-12, 1.9 + 1e-12, 1.9 - 1e-6):
+        cx, cy = rc * math.cos(math.pi / 6), rc * math.sin(math.pi / 6)
+        box = np.array([[cx - 0.3, cy - 0.3, 0.0, cx, cy, 0.0]])
+        g = rgg.Roadmap(ctx, rob, q, edges, 1, samples_per_edge=2, precision=rgg.RGG_PREC_FP32_RECHECK)
+        o = oracle.Roadmap(rob, q, edges, 0.0, 2, 1)
+        absent = np.tile(synth.ABSENT_BOX, (1, 1))
+        g.update(absent, box)
+        o.update(absent, box)
+        for ml, ma in ((30, 1024), (30, 4), (24, 256), (16, 1)):
+            got, want = g.validate([0], ml, ma), o.validate([0], ml, ma)
+            same(got, want, f"corner radius {rc!r} limits {ml}/{ma}")
+        print(f"[validate] corner {rc!r}: {got[0].tolist()} level {got[1].tolist()}", flush=True)
+        g.close()

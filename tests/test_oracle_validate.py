@@ -229,3 +229,34 @@ def test_nodes_validate_to_their_label(oracle_lib):
     v, lv, w = rm.validate(np.arange(len(q)))
     assert np.all(v[lab == 2] == COLLIDES) and np.all(w[lab == 2] == 0.0)
     assert np.all(v[lab == 0] == FREE) and np.all(lv == 0)
+
+
+def grazing_case(oracle_lib, radius_of_corner):
+    """The quarter turn of rotating_case with a box whose corner lies on the
+    ray at 30 degrees (t = 1/3, not dyadic), at `radius_of_corner` from the
+    origin: 1.9 touches the disc's sweep, less clears it, more enters it."""
+    rob = one_sphere_se2((2.0, 0.0), 0.1)
+    q = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, math.pi / 2]])
+    rm = oracle_lib.Roadmap(rob, q, np.array([[0, 1]]), 0.0, 2, n_slots=1, threads=1)
+    cx, cy = radius_of_corner * math.cos(math.pi / 6), radius_of_corner * math.sin(math.pi / 6)
+    rm.classify(np.array([[cx - 0.3, cy - 0.3, 0.0, cx, cy, 0.0]]))
+    return rm
+
+
+def test_deep_search_tracks_the_clearance(oracle_lib):
+    """The chord deviation of a level-l interval is delta 4^-l, so a clearance
+    g is certified once delta 4^-l falls below about g: dividing g by 10^6
+    deepens the FREE level by log4(10^6) ~ 10 levels.  A penetration is
+    found once a midpoint lands inside it, within 2^-l of t = 1/3."""
+    levels = {}
+    for g in (1e-6, 1e-12):
+        v, lv, _ = grazing_case(oracle_lib, 1.9 - g).validate([0], max_level=30, max_active=1024)
+        assert v[0] == FREE
+        levels[g] = int(lv[0])
+    assert abs((levels[1e-12] - levels[1e-6]) - math.log(1e6, 4)) <= 1.5, levels
+    assert 4.0 ** -levels[1e-6] * math.pi ** 2 / 16 < 1e-5
+    v, lv, w = grazing_case(oracle_lib, 1.9 + 1e-12).validate([0], max_level=30, max_active=1024)
+    assert v[0] == COLLIDES and abs(w[0] - 1.0 / 3.0) < 2.0 ** -(int(lv[0]) - 1)
+    # not enough levels: UNRESOLVED at the limit
+    v, lv, _ = grazing_case(oracle_lib, 1.9 + 1e-12).validate([0], max_level=16, max_active=1024)
+    assert (v[0], lv[0]) == (UNRESOLVED, 16)
