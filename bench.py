@@ -334,12 +334,15 @@ def serving(a):
                                 for v in sorted({r["item_edges"] for r in chosen})},
                  "one_cell": sum(r["cell_size"] is None for r in chosen)}
         log(f"[bench] serving: tuned in {tuned['seconds']:.1f}s")
+    vers = [torch.zeros(w.n_edges, dtype=torch.uint8, device=dev) for w in ws]
     srv = rgg.rgg_server_start(ctx, n_streams=4, max_batch=64, pool_bytes=64 << 20)
     rng = np.random.default_rng(a.seed + 77)
     cur = [w.boxes[0] for w in ws]
     levels = []
     ok = True
-    for rate in (100.0, 1000.0, 10000.0):
+
+    def run_rate(rate, validate):
+        nonlocal cur, ok
         reqs, cur = synth.serving_requests(rng, ws, rate, a.serving_seconds, start=cur)
         tickets = []
         busy = 0
@@ -350,7 +353,7 @@ def serving(a):
             while True:
                 try:
                     t = rgg.rgg_server_submit(srv, gs[r].h, old, new, labs[r].data_ptr(), grays[r].data_ptr(),
-                                              ws[r].n_edges)
+                                              ws[r].n_edges, validate=validate, d_verdict=vers[r].data_ptr())
                     break
                 except rgg.RggError as e:
                     if e.status != rgg.RGG_E_BUSY:
@@ -366,11 +369,18 @@ def serving(a):
             edges += e
         wall = time.perf_counter() - t0
         lat = np.array(lat)
-        levels.append({"offered_rate": rate, "requests": len(tickets), "achieved_rate": len(tickets) / wall,
-                       "edges_per_s": edges / wall, "latency_p50_us": float(np.percentile(lat, 50)),
-                       "latency_p99_us": float(np.percentile(lat, 99)), "latency_mean_us": float(lat.mean()),
-                       "busy_retries": busy})
+        return {"offered_rate": rate, "requests": len(tickets), "achieved_rate": len(tickets) / wall,
+                "edges_per_s": edges / wall, "latency_p50_us": float(np.percentile(lat, 50)),
+                "latency_p99_us": float(np.percentile(lat, 99)), "latency_mean_us": float(lat.mean()),
+                "busy_retries": busy}
+
+    for rate in (100.0, 1000.0, 10000.0):
+        levels.append(run_rate(rate, False))
         log(f"[bench] serving at {rate:.0f}/s: {levels[-1]}")
+    # non-lazy requests: each update followed by the full validation of its
+    # gray list, the labels rewritten to green / red
+    non_lazy = run_rate(1000.0, True)
+    log(f"[bench] serving non-lazy at 1000/s: {non_lazy}")
     rgg.rgg_server_stop(srv)
     for g in gs:
         g.close()
@@ -380,6 +390,7 @@ def serving(a):
             "roadmaps": len(ws), "edges": int(sum(w.n_edges for w in ws)), "seconds_per_rate": a.serving_seconds,
             "autotune": tuned,
             "server": {"n_streams": 4, "max_batch": 64, "pool_bytes": 64 << 20}, "rates": levels,
+            "non_lazy": non_lazy,
             "status_ok": bool(ok)}
 
 
