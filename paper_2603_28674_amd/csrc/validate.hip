@@ -423,15 +423,18 @@ __global__ __launch_bounds__(kVT, 4) void k_validate(ValDev v, const int64_t *id
 {
     __shared__ ValShared sh;
     const int tid = threadIdx.x;
-    {
-        const int32_t *src = reinterpret_cast<const int32_t *>(v.rob);
-        int32_t *dst = reinterpret_cast<int32_t *>(&sh.rob);
-        for (int k = tid; k < (int)(sizeof(VRobot) / 4); k += kVT) dst[k] = src[k];
-    }
     int64_t nn = n;
     if (count) {
         const int64_t g = count->status == RGG_OK ? count->n_gray : 0;
         nn = g < n ? g : n;
+    }
+    // blocks beyond the list (the grid is sized for its capacity when the
+    // count comes from the device) leave at once
+    if ((int64_t)blockIdx.x >= nn) return;
+    {
+        const int32_t *src = reinterpret_cast<const int32_t *>(v.rob);
+        int32_t *dst = reinterpret_cast<int32_t *>(&sh.rob);
+        for (int k = tid; k < (int)(sizeof(VRobot) / 4); k += kVT) dst[k] = src[k];
     }
     __syncthreads();
     for (int64_t i = blockIdx.x; i < nn; i += gridDim.x) {
