@@ -333,3 +333,55 @@ def test_empty_and_degenerate(ctx):
     ol, og = o.update(np.tile(synth.ABSENT_BOX, (2, 1)), big)
     assert np.array_equal(lab, ol) and np.all(lab == 2) and n == 0
     g.close()
+
+
+@pytest.mark.parametrize("case", ["se3_64_spheres_4096_slots", "arm_32_links_64_spheres"])
+def test_maximum_sizes(ctx, case):
+    """The largest robot (64 spheres, one wavefront of lanes per edge), the
+    longest arm (32 links) and the most obstacle slots (4096): labels, gray
+    lists and the full validation of the gray list equal the oracle's."""
+    from paper_2603_28674_amd import rgg
+    import oracle
+    rng = np.random.default_rng(91)
+    if case.startswith("se3"):
+        rob = synth.robot_se3(rng, n_spheres=64)
+        q = synth.nodes_se3(rng, 600, 4.0)
+        edges = synth.knn_se3(q, 6)
+        M = 4096
+        seq = [synth.random_boxes(rng, M, 3, 0.02, 0.1, -12.0, 16.0)]
+        res, spe = 0.0, 12
+    else:
+        L = 32
+        lengths = rng.uniform(0.1, 0.3, size=L)
+        along = np.concatenate([[0.25 * l, 0.75 * l] for l in lengths])
+        link = np.repeat(np.arange(L, dtype=np.int32), 2)
+        rad = np.repeat(lengths / 4.0, 2)
+        rob = synth.Robot(synth.ARM, along, rad, link, lengths, (0.0, 0.0))
+        q = rng.uniform(-0.3, 0.3, size=(500, L))
+        edges = synth.knn_euclid(q, 6)
+        M = 30
+        rho = float(lengths.sum())
+        seq = [synth.random_boxes(rng, M, 2, 0.1, 0.5, -rho, rho)]
+        res, spe = 0.0, 10
+    for _ in range(2):
+        nxt = seq[-1].copy()
+        k = rng.choice(M, size=max(1, M // 10), replace=False)
+        nxt[k, :rob.dim] += rng.normal(0, 0.2, (len(k), rob.dim))
+        nxt[k, 3:3 + rob.dim] = nxt[k, :rob.dim] + (seq[-1][k, 3:3 + rob.dim] - seq[-1][k, :rob.dim])
+        seq.append(nxt)
+    print(f"[max] {case}: B={rob.n_spheres} E={len(edges)} M={M}", flush=True)
+    g = rgg.Roadmap(ctx, rob, q, edges, M, resolution=res, samples_per_edge=spe,
+                    precision=rgg.RGG_PREC_FP32_RECHECK)
+    o = oracle.Roadmap(rob, q, edges, res, spe, M)
+    prev = np.tile(synth.ABSENT_BOX, (M, 1))
+    for u, cur in enumerate(seq):
+        lab, gray, n, _ = g.update(prev, cur)
+        ol, og = o.update(prev, cur)
+        assert np.array_equal(lab, ol), f"update {u}: labels differ"
+        assert np.array_equal(gray, og), f"update {u}: gray list differs"
+        got, want = g.validate(gray), o.validate(og)
+        assert all(np.array_equal(x, y, equal_nan=True) for x, y in zip(got, want)), f"update {u}: validation"
+        print(f"[max] update {u}: labels {np.bincount(lab, minlength=3).tolist()}, "
+              f"verdicts {np.bincount(got[0], minlength=4).tolist()}", flush=True)
+        prev = cur
+    g.close()
