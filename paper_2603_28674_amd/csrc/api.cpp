@@ -1195,11 +1195,11 @@ struct FileHeader {
 };
 
 struct Fnv {
-    uint64_t h = 1469598103934665603ull;
+    uint64_t h = 0xcbf29ce484222325ull;   // FNV-1a 64-bit offset basis
     void add(const void *p, size_t n)
     {
         const unsigned char *b = static_cast<const unsigned char *>(p);
-        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 0x100000001b3ull;   // FNV 64-bit prime
     }
 };
 

@@ -165,3 +165,52 @@ def test_node_labels(ctx, kind):
         print(f"[nodes] update {u}: {red_nodes.size} red nodes, {int(inc.sum())} edges at them", flush=True)
         prev = w.boxes[u]
     g.close()
+
+
+def _fnv1a64(data):
+    h = 14695981039346656037
+    for b in data:
+        h = ((h ^ b) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_load_rejects_inconsistent_contents(ctx, tmp_path):
+    """Files whose checksum is right but whose contents contradict each other
+    (header dimension, sample offsets, robot kind) are refused."""
+    import struct
+    from paper_2603_28674_amd import rgg
+    w = synth.planar_rigid(seed=44, n_nodes=60, n_boxes=5, n_updates=1, resolution=0.5)
+    g = rgg.Roadmap.from_workload(ctx, w)
+    g.update(w.absent(), w.boxes[0])
+    path = tmp_path / "small.rgg"
+    g.save(path)
+    g.close()
+    raw = bytearray(path.read_bytes())
+    assert struct.unpack_from("<Q", raw, len(raw) - 8)[0] == _fnv1a64(raw[:-8])
+    print(f"[persist] {len(raw)} bytes", flush=True)
+    D, B = struct.unpack_from("<ii", raw, 12)
+    E, M = struct.unpack_from("<qq", raw, 32)
+    n_samp, n_cap = struct.unpack_from("<qq", raw, 64)
+    hdr = 80
+    robot_at = hdr + 8 * (E + 1) + 8 * n_samp + 8 * n_cap + 8 * B + 32 * E + 48 * M + 8 * E
+
+    def refused(mutate, name):
+        data = bytearray(raw)
+        mutate(data)
+        struct.pack_into("<Q", data, len(data) - 8, _fnv1a64(data[:-8]))
+        p = tmp_path / name
+        p.write_bytes(bytes(data))
+        with pytest.raises(rgg.RggError) as ei:
+            rgg.rgg_load(ctx, p)
+        assert ei.value.status == rgg.RGG_E_INVALID_ARG, name
+
+    assert (D, B) == (2, 4) and struct.unpack_from("<i", raw, robot_at)[0] == 0   # an SE2 robot record
+    refused(lambda d: struct.pack_into("<i", d, 12, 3), "dimension")
+    refused(lambda d: struct.pack_into("<q", d, hdr + 8, -4), "offsets")
+    refused(lambda d: struct.pack_into("<i", d, robot_at, 1), "robot_kind")
+    refused(lambda d: struct.pack_into("<i", d, robot_at + 4, B + 1), "robot_spheres")
+    # the unmodified bytes with a recomputed checksum still load
+    p = tmp_path / "same.rgg"
+    p.write_bytes(bytes(raw))
+    h = rgg.Roadmap.load(ctx, p)
+    h.close()
