@@ -354,7 +354,7 @@ rgg_status rgg_batch_tune(rgg_batch *b, const rgg_box *const *obstacles_a, const
  * fixed binary64 steps, so verdicts are reproducible bit for bit.  The
  * obstacles are the roadmap's resident slots when the validation runs (after
  * its queued updates).  max_level 0..30 (0: RGG_VALIDATE_DEFAULT_LEVELS),
- * max_active 1..1024 (0: RGG_VALIDATE_DEFAULT_ACTIVE).
+ * max_active 1..512 (0: RGG_VALIDATE_DEFAULT_ACTIVE).
  * rgg_validate: host arrays ids[n] (each an edge id, else RGG_E_INVALID_ARG),
  * verdict[n], level[n] and witness[n] (level and witness may be NULL);
  * returns when done.

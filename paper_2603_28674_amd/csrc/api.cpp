@@ -706,7 +706,7 @@ static rgg_status check_validate_args(rgg_roadmap *rm, int64_t n, int32_t *max_l
     if (*max_level == 0) *max_level = RGG_VALIDATE_DEFAULT_LEVELS;
     if (*max_active == 0) *max_active = RGG_VALIDATE_DEFAULT_ACTIVE;
     if (*max_level < 0 || *max_level > 30) return fail(RGG_E_INVALID_ARG, "max_level must be 0..30");
-    if (*max_active < 1 || *max_active > kValMaxActive) return fail(RGG_E_INVALID_ARG, "max_active must be 0..1024");
+    if (*max_active < 1 || *max_active > kValMaxActive) return fail(RGG_E_INVALID_ARG, "max_active must be 0..512");
     return RGG_OK;
 }
 

@@ -196,7 +196,7 @@ def test_validate_argument_errors(ctx):
     with pytest.raises(rgg.RggError):
         g.validate([0], max_level=31)
     with pytest.raises(rgg.RggError):
-        g.validate([0], max_active=1025)
+        g.validate([0], max_active=513)
     v, lv, wt = g.validate(np.zeros(0, dtype=np.int64))
     assert v.size == 0
     g.close()
@@ -221,7 +221,7 @@ def test_validate_deep_searches(ctx):
         absent = np.tile(synth.ABSENT_BOX, (1, 1))
         g.update(absent, box)
         o.update(absent, box)
-        for ml, ma in ((30, 1024), (30, 4), (24, 256), (16, 1)):
+        for ml, ma in ((30, 512), (30, 4), (24, 256), (16, 1)):
             got, want = g.validate([0], ml, ma), o.validate([0], ml, ma)
             same(got, want, f"corner radius {rc!r} limits {ml}/{ma}")
         print(f"[validate] corner {rc!r}: {got[0].tolist()} level {got[1].tolist()}", flush=True)
