@@ -136,7 +136,7 @@ hipError_t launch_batch(hipStream_t s, const BatchReq *tab, const int32_t *grp, 
 // Full validation of listed edges (rgg_validate): the robot, each edge's
 // motion parameters and chord-deviation bounds, and the resident slots.
 constexpr int kValMaxActive = 512;   // unknown sub-intervals per level, at most
-constexpr int kValBoxes = 128;       // candidate boxes staged in LDS per page
+constexpr int kValBoxes = 64;        // candidate boxes staged in LDS per page
 
 struct VRobot {
     int32_t kind, B, L, dof;

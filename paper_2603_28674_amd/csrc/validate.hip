@@ -24,7 +24,7 @@
 // verdicts.  The distance predicates are the binary64 definitions of the
 // update kernels (predicates64.h).
 //
-// One block of 128 threads validates one listed edge at a time (grid-stride
+// One wavefront (a 64-thread block) validates one listed edge at a time (grid-stride
 // over the list).  Its present boxes near the edge are staged in LDS: a box
 // can matter only if it meets the box around the edge's chords widened by
 // r_i + 2 delta_i (each sub-chord stays within delta_i of the edge's chord,
@@ -40,7 +40,7 @@ namespace rgg {
 
 namespace {
 
-constexpr int kVT = 128;           // threads per block
+constexpr int kVT = 64;            // threads per block
 constexpr int kVGrid = 16384;      // blocks at most (the hardware balances them)
 constexpr int kNoHit = 0x7fffffff;
 
@@ -416,10 +416,9 @@ __device__ __forceinline__ void validate_one(ValShared &sh, const ValDev &v, int
     __syncthreads();
 }
 
-// Four waves per SIMD (128 VGPRs): with 17 KB of LDS per block, eight
-// blocks, so eight edges, are in flight per CU.  The search is a chain of
-// dependent phases per edge, so edges in flight matter more than threads
-// per edge.
+// One wavefront per edge with 14 KB of LDS: about eleven edges are in
+// flight per CU.  The search is a chain of dependent phases per edge, so
+// edges in flight matter more than threads per edge.
 template <int D>
 __global__ __launch_bounds__(kVT) __attribute__((amdgpu_waves_per_eu(4))) void k_validate(
     ValDev v, const int64_t *ids, int64_t n, const rgg_update_result *count, int max_level, int max_active,
