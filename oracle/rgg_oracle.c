@@ -6,7 +6,7 @@
  * or constant table with the device library; both read the same seeded
  * arrays and nothing else.
  *
- * What it computes (paper Sec. 3.1, the Red-Green-Gray rule; Sec. 2.2, the
+ * What it computes (paper Sec. 4.1, the Red-Green-Gray rule; Sec. 3.2, the
  * definitions of swept volumes and of outer/inner approximations; Alg. 1,
  * the per-obstacle update):
  *
@@ -26,7 +26,7 @@
  *                     planar rigid body (SE2), a spatial rigid body (SE3) or
  *                     a planar serial arm (ARM);
  *   cfg(e)            n+1 configurations q(t_j), t_j = j/n, along the edge's
- *                     motion q(t) (Sec. 2.2: |e|/eps configurations);
+ *                     motion q(t) (Sec. 3.2: |e|/eps configurations);
  *   inner approx.     the robot's spheres placed at every configuration of
  *                     cfg(e): a subset of the swept volume;
  *   outer approx.     per sphere i, the capsule around the chord from its
@@ -252,7 +252,8 @@ static void deltas(const orc_robot *r, const motion *m, double *dl)
             double acc = 0.0, dphi = 0.0;
             for (int k = 0; k <= L; ++k) {
                 dphi = dphi + (m->qb[k] - m->qa[k]);
-                double arm = k < L ? r->len[k] : r->pos[i];
+                /* |p''| <= sum_k |lever_k| dPhi_k^2: the lever's length */
+                double arm = fabs(k < L ? r->len[k] : r->pos[i]);
                 acc = acc + (arm * dphi) * dphi;
             }
             dl[i] = acc / 8.0;
@@ -728,7 +729,7 @@ int64_t orc_rm_update(orc_rm *rm, int64_t M, const double *old_boxes, const doub
  * Alg. 1 gives every edge left unknown a full collision check.  Here that
  * check is continuous: it decides whether any configuration q(t), t in
  * [0,1], of the edge's motion puts a robot sphere into a present box.  It
- * refines the outer and inner approximations of Sec. 2.2 on dyadic
+ * refines the outer and inner approximations of Sec. 3.2 on dyadic
  * sub-intervals [j 2^-l, (j+1) 2^-l] of the edge:
  *   free(l, j): for every sphere i and every present box, the capsule from
  *               sphere i's centre at the interval's start to its centre at

@@ -1,6 +1,6 @@
 // Host build stage of librgg: approximations of every roadmap edge.
 //
-// Paper Sec. 2.2 defines cfg(e) (|e|/eps configurations along an edge), the
+// Paper Sec. 3.2 defines cfg(e) (|e|/eps configurations along an edge), the
 // forward kinematics FK and outer/inner approximations (superset/subset of the
 // swept volume).  This file computes, in binary64 with the C library's sin,
 // cos, acos and sqrt and without FMA contraction (compile flags), for each
@@ -183,7 +183,9 @@ int64_t segments_of(const rgg_robot *r, const rgg_build_opts *o, const Motion &m
 // Chord-deviation bound of each sphere centre: max|p''| / 8.
 //   SE2: |o| turn^2 / 8   (centre moves on a circle at the turning rate)
 //   SE3: |o| phi^2 / 8    (slerp turns about a fixed axis at rate phi = 2*half)
-//   arm: (sum_{k<L} l_k dPhi_k^2 + s dPhi_L^2) / 8, dPhi_k = sum_{j<=k} (qb_j - qa_j)
+//   arm: (sum_{k<L} |l_k| dPhi_k^2 + |s| dPhi_L^2) / 8, dPhi_k = sum_{j<=k} (qb_j - qa_j);
+//        a lever enters by its length, so a sphere behind its joint (s < 0) is
+//        bounded as one in front of it
 void inflation(const rgg_robot *r, const Motion &m, double *out)
 {
     const int B = r->n_spheres;
@@ -206,7 +208,7 @@ void inflation(const rgg_robot *r, const Motion &m, double *out)
             double sum = 0.0, dphi = 0.0;
             for (int k = 0; k <= link; ++k) {
                 dphi = dphi + (m.b[k] - m.a[k]);
-                double lever = k < link ? r->link_length[k] : r->sphere_pos[i];
+                double lever = fabs(k < link ? r->link_length[k] : r->sphere_pos[i]);
                 sum = sum + (lever * dphi) * dphi;
             }
             out[i] = sum / 8.0;
@@ -333,9 +335,14 @@ rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *r, const 
             const int64_t e = e0 + k;
             Motion m;
             make_motion(r, rd->q + rd->edge_uv[2 * e] * dof, rd->q + rd->edge_uv[2 * e + 1] * dof, &m);
-            g->soff[k + 1] = (segments_of(r, o, m) + 1) * B;
+            g->soff[k + 1] = std::min(segments_of(r, o, m) + 1, kMaxEdgeConfigs + 1) * B;
         }
     });
+    for (int64_t k = 0; k < E; ++k)
+        if (g->soff[k + 1] > kMaxEdgeConfigs * B) {
+            *err = "an edge needs more than 2^24 configurations (resolution too fine)";
+            return RGG_E_INVALID_ARG;
+        }
     for (int64_t k = 0; k < E; ++k) g->soff[k + 1] += g->soff[k];
     const int64_t total = g->soff[E];
     const int S = copy_stride(D);
@@ -407,7 +414,6 @@ rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *r, const 
             bx[7] = 0.0f;
         }
     });
-    (void)err;
     return RGG_OK;
 }
 

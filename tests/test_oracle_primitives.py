@@ -6,7 +6,7 @@
   distance function, and dense sampling;
 * motion and forward kinematics: scipy's rotations and Slerp, plain rotation
   matrices, and the planar chain written with cumulative sums;
-* the chord-deviation bound delta (Sec. 2.2's swept volume, outer
+* the chord-deviation bound delta (Sec. 3.2's swept volume, outer
   approximation as a superset): dense sampling of the true centre path, and
   its tightness for small rotations.
 """
@@ -203,6 +203,53 @@ def test_sample_count(oracle_lib):
     assert R.n_segments([0, 0, 0], [3, 4, 0], 0.5, samples_per_edge=20) == 19
 
 
+def _quat_z(angle):
+    """Unit quaternion (w, x, y, z) of a turn by `angle` about +z."""
+    return [math.cos(angle / 2), 0.0, 0.0, math.sin(angle / 2)]
+
+
+def test_sample_count_se3(oracle_lib):
+    """Sec. 3.2's |e|/eps for a spatial body: |e| is the Euclidean length of
+    (translation, rotation angle), the angle being that of the relative turn
+    (twice the half-angle of the quaternion arc), taken the short way round.
+    The expected counts come from angles known by construction."""
+    rob = synth.Robot(synth.SE3, np.array([[0.5, 0.0, 0.0]]), np.array([0.1]))
+    R = oracle_lib.Robot(rob)
+    qa = [0.0, 0.0, 0.0, *_quat_z(0.0)]
+    # a quarter turn about z and no translation: |e| = pi/2 -> ceil(15.7) = 16
+    assert R.n_segments(qa, [0.0, 0.0, 0.0, *_quat_z(math.pi / 2)], 0.1) == 16
+    # the same turn written with the opposite quaternion sign: same motion
+    assert R.n_segments(qa, [0.0, 0.0, 0.0, *(-np.array(_quat_z(math.pi / 2)))], 0.1) == 16
+    # a three-quarter turn is a quarter turn the other way round
+    assert R.n_segments(qa, [0.0, 0.0, 0.0, *_quat_z(1.5 * math.pi)], 0.1) == 16
+    # translation (3, 4, 0) plus the quarter turn: sqrt(25 + pi^2/4) = 5.2406
+    # -> ceil(52.41) = 53 (a half-angle slip would give 51, no rotation 50)
+    assert R.n_segments(qa, [3.0, 4.0, 0.0, *_quat_z(math.pi / 2)], 0.1) == 53
+    # a turn about a tilted axis: the angle does not depend on the axis
+    ax = np.array([1.0, 2.0, 2.0]) / 3.0
+    qb = [1.0, 0.0, 0.0, math.cos(0.6), *(math.sin(0.6) * ax)]   # angle 1.2
+    # sqrt(1 + 1.44) = 1.5620 -> ceil(15.62) = 16 with eps 0.1, 32 with 0.05
+    assert R.n_segments(qa, qb, 0.1) == 16
+    assert R.n_segments(qa, qb, 0.05) == 32
+    # a fixed count wins
+    assert R.n_segments(qa, qb, 0.1, samples_per_edge=20) == 19
+
+
+def test_sample_count_arm(oracle_lib):
+    """Sec. 3.2's |e|/eps for a serial arm: |e| is the Euclidean length of the
+    joint-angle change (not of the absolute link angles)."""
+    rng = np.random.default_rng(3)
+    rob = synth.robot_arm(rng, 3)
+    R = oracle_lib.Robot(rob)
+    # dq = (0.3, -0.4, 1.2): |dq| = 1.3 -> 1.3/0.07 = 18.57 -> 19; the
+    # cumulative angles (0.3, -0.1, 1.1) would give 1.1446 -> 17
+    assert R.n_segments([0.0, 0.0, 0.0], [0.3, -0.4, 1.2], 0.07) == 19
+    assert R.n_segments([1.0, 2.0, -1.0], [1.3, 1.6, 0.2], 0.07) == 19
+    # no wrap for joints: -3 to 3 is a change of 6, not 2 pi - 6
+    assert R.n_segments([-3.0, 0.0, 0.0], [3.0, 0.0, 0.0], 0.7) == 9
+    assert R.n_segments([0.5, 0.5, 0.5], [0.5, 0.5, 0.5], 0.1) == 1
+
+
 # --------------------------------------------------------------------------
 # delta: the chord-deviation bound
 # --------------------------------------------------------------------------
@@ -230,6 +277,31 @@ def test_delta_bounds_chord_deviation(oracle_lib, kind):
         dl = R.deltas(qa, qb)
         dev = chord_dev(centre_path(rob, qa, qb, ts))
         assert np.all(dev <= dl * (1 + 1e-9) + 1e-12), (dev, dl)
+
+
+def test_delta_bounds_levers_behind_their_joint(oracle_lib):
+    """Spheres behind their joint (negative distance along the link) and a
+    link of negative length: the bound takes each lever by its length
+    (|p''| <= sum |l_k| dPhi_k^2 + |s| dPhi_L^2).  Dense sampling of the true
+    centre path checks it; the same edges show that a signed lever would
+    understate the deviation, so the case has teeth."""
+    rng = np.random.default_rng(31)
+    rob = synth.Robot(synth.ARM, np.array([-0.6, 0.4, -0.9, 0.2]), np.array([0.1, 0.1, 0.1, 0.1]),
+                      np.array([0, 1, 1, 2], dtype=np.int32), np.array([1.0, -0.7, 0.8]), (0.0, 0.0))
+    R = oracle_lib.Robot(rob)
+    ts = np.linspace(0, 1, 2001)
+    understated = 0
+    for _ in range(80):
+        qa, qb = rng.uniform(-math.pi, math.pi, 3), rng.uniform(-math.pi, math.pi, 3)
+        dl = R.deltas(qa, qb)
+        dev = chord_dev(centre_path(rob, qa, qb, ts))
+        assert np.all(dev <= dl * (1 + 1e-9) + 1e-12), (dev, dl)
+        dphi = np.cumsum(qb - qa)
+        for i in range(rob.n_spheres):
+            L = rob.sphere_link[i]
+            signed = (np.sum(rob.link_length[:L] * dphi[:L] ** 2) + rob.sphere_pos[i] * dphi[L] ** 2) / 8
+            understated += int(dev[i] > signed * (1 + 1e-9) + 1e-12)
+    assert understated > 0
 
 
 def test_delta_pure_translation_is_zero(oracle_lib):
