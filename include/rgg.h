@@ -4,15 +4,15 @@
  *
  * Method (Arad et al., "Serialized Red-Green-Gray: Quicker Heuristic
  * Validation of Edges in Dynamic Roadmap Graphs"):
- *   Sec. 3.1   an edge whose inner approximation meets an obstacle is RED,
+ *   Sec. 4.1   an edge whose inner approximation meets an obstacle is RED,
  *              one whose outer approximation misses every obstacle is GREEN,
  *              any other edge is GRAY (unknown, left for a full check);
- *   Sec. 2.2   cfg(e) = |e|/eps configurations along the edge; an outer
+ *   Sec. 3.2   cfg(e) = |e|/eps configurations along the edge; an outer
  *              (inner) approximation is a superset (subset) of the swept
  *              volume;
  *   Alg. 1     when an obstacle moves, only the components it touched before
  *              and touches now are revisited;
- *   Sec. 3.3   the approximations are stored once, resident on the GPU, and
+ *   Sec. 4.3   the approximations are stored once, resident on the GPU, and
  *              only the new obstacle poses go up per update; a uniform grid
  *              restricts the tests to edges near the moved obstacles.
  *
@@ -108,7 +108,7 @@ typedef struct {
     int64_t n_edges;
     const int64_t *edge_uv;       /* [n_edges][2] host node ids; the caller's
                                      edge order is the order of every output.
-                                     An edge (v, v) is node v (Sec. 2.1: a node
+                                     An edge (v, v) is node v (Sec. 3.1: a node
                                      is a degenerate edge): its one configuration
                                      gives node v's label, RED or GREEN, never
                                      GRAY                                       */
@@ -187,11 +187,11 @@ typedef struct rgg_batch rgg_batch;
 rgg_status rgg_context_create(int device, rgg_context **out);
 void rgg_context_destroy(rgg_context *ctx);
 
-/* Builds the approximations of every edge (Sec. 3.3 offline storage: built
+/* Builds the approximations of every edge (Sec. 4.3 offline storage: built
  * once, resident on the GPU): FP64 forward kinematics at every configuration
- * of cfg(e) (Sec. 2.2), per-sphere capsules, edge bounding boxes and the
- * uniform grid (Sec. 3.3 spatial filtering).  Every obstacle slot starts
- * ABSENT, so every label starts GREEN (Sec. 4: roadmaps are built without
+ * of cfg(e) (Sec. 3.2), per-sphere capsules, edge bounding boxes and the
+ * uniform grid (Sec. 4.3 spatial filtering).  Every obstacle slot starts
+ * ABSENT, so every label starts GREEN (Sec. 5: roadmaps are built without
  * obstacles).  Errors: RGG_E_INVALID_ARG (null pointer, node id out of
  * range, non-finite or non-unit input, bad option), RGG_E_OUT_OF_MEMORY,
  * RGG_E_DEVICE.  *out receives the roadmap. */
@@ -200,7 +200,7 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *roadmap, const rg
 rgg_status rgg_destroy(rgg_roadmap *rm);
 rgg_status rgg_roadmap_info_get(rgg_roadmap *rm, rgg_roadmap_info *out);
 
-/* One update (Alg. 1 for every slot whose box changed, Sec. 3.1 labels),
+/* One update (Alg. 1 for every slot whose box changed, Sec. 4.1 labels),
  * host buffers.  `obstacles_old` and `obstacles_new` are [m] host boxes;
  * m must equal n_obstacle_slots and `obstacles_old` must equal the resident
  * slots bit for bit (else RGG_E_STATE_MISMATCH, nothing changes).  Slots
@@ -275,7 +275,7 @@ rgg_status rgg_batch_destroy(rgg_batch *b);
  * the convenience form of the three calls above.  Blocks until done. */
 rgg_status rgg_update_batch(rgg_context *ctx, int32_t n, const rgg_update_req *reqs, void *stream);
 
-/* Autotuner of the work decomposition (Sec. 3.3 sizes grid cells by what
+/* Autotuner of the work decomposition (Sec. 4.3 sizes grid cells by what
  * one kernel can process; here the choice is made by measurement).  The
  * candidates are the roadmap's current configuration, every combination
  * of work-item size (512, 256, 128 or 64 edges per item, one block each) and
@@ -338,7 +338,7 @@ rgg_status rgg_batch_tune(rgg_batch *b, const rgg_box *const *obstacles_a, const
  * full collision check).  Decides, for each listed edge, whether any
  * configuration q(t), t in [0, 1], of its motion puts a robot sphere into a
  * present obstacle slot, by refining the outer and inner approximations of
- * Sec. 2.2 on dyadic sub-intervals [j 2^-l, (j+1) 2^-l]: an interval is
+ * Sec. 3.2 on dyadic sub-intervals [j 2^-l, (j+1) 2^-l]: an interval is
  * free when every sphere's capsule between its centres at the interval's
  * ends, inflated to r_i + delta_i 4^-l, misses every box; the search tests
  * the robot at the midpoints of the intervals that are not free, level by
@@ -378,7 +378,7 @@ rgg_status rgg_validate_async(rgg_roadmap *rm, void *stream, const int64_t *d_id
                               const rgg_update_result *d_count, int32_t max_level, int32_t max_active,
                               uint8_t *d_verdict, int32_t *d_level, double *d_witness, uint8_t *d_labels);
 
-/* Persistence between planning iterations (Sec. 1 and Sec. 3.3: the
+/* Persistence between planning iterations (Sec. 1 and Sec. 4.3: the
  * approximations are computed once and then stored and reloaded).
  * rgg_save writes `rm` to the file `path`: its binary64 sphere centres and
  * capsules, edge boxes, sphere radii, the resident obstacle slots, the per-edge
@@ -475,6 +475,13 @@ rgg_status rgg_debug_geometry(const rgg_roadmap_desc *roadmap, const rgg_robot *
                               const rgg_build_opts *opts, int64_t e0, int64_t e1,
                               int64_t *n_configs, double *centres, double *capsule,
                               float *aabb);
+
+/* Host-only view of rgg_load, for tests: reads the roadmap file `path` and
+ * runs every check rgg_load runs before it uses the device (header, sample
+ * offsets with 2 .. 2^24 configurations per edge, robot, truncation,
+ * checksum); *n_edges (may be NULL) receives its edge count.  Same errors as
+ * rgg_load's file checks. */
+rgg_status rgg_debug_read_file(const char *path, int64_t *n_edges);
 
 const char *rgg_last_error(void);
 const char *rgg_version(void);

@@ -1235,6 +1235,14 @@ struct FileIn {
     }
 };
 
+// What a roadmap file holds, read back on the host.
+struct LoadedFile {
+    FileHeader h;
+    HostGeometry g;
+    std::vector<rgg_box> resident;
+    std::vector<int2> cnt;
+};
+
 template <typename T>
 rgg_status read_back(std::vector<T> *v, const T *d, size_t n, const char *what)
 {
@@ -1320,14 +1328,17 @@ rgg_status rgg_save(rgg_roadmap *rm, const char *path)
     return RGG_OK;
 }
 
-rgg_status rgg_load(rgg_context *ctx, const char *path, rgg_roadmap **out)
+// Reads and checks a roadmap file (host only): everything rgg_load needs
+// before it touches the device.
+static rgg_status read_roadmap_file(const char *path, LoadedFile *L)
 {
-    if (!ctx || !path || !out) return fail(RGG_E_INVALID_ARG, "null argument");
-    auto t0 = std::chrono::steady_clock::now();
+    FileHeader &h = L->h;
+    HostGeometry &g = L->g;
+    std::vector<rgg_box> &resident = L->resident;
+    std::vector<int2> &cnt = L->cnt;
     FileIn in;
     in.f = fopen(path, "rb");
     if (!in.f) return fail(RGG_E_INVALID_ARG, "cannot open %s", path);
-    FileHeader h;
     in.get(&h, sizeof h);
     if (!in.ok || memcmp(h.magic, kMagic, sizeof kMagic) != 0) return fail(RGG_E_INVALID_ARG, "%s is not a roadmap file", path);
     if (h.version != kFileVersion) return fail(RGG_E_INVALID_ARG, "roadmap file version %u, expected %u", h.version, kFileVersion);
@@ -1335,7 +1346,6 @@ rgg_status rgg_load(rgg_context *ctx, const char *path, rgg_roadmap **out)
         h.M > 4096 || h.chunk < 1 || h.chunk > 512 || h.retest_capacity < 1 ||
         h.retest_capacity > (1 << 20) || !(h.band_rel > 0.0f) || h.n_cap != h.E * (2 * h.D + 1) * h.B || h.n_samp < 0)
         return fail(RGG_E_INVALID_ARG, "%s: inconsistent header", path);
-    HostGeometry g;
     g.D = h.D;
     g.B = h.B;
     g.E = h.E;
@@ -1344,9 +1354,13 @@ rgg_status rgg_load(rgg_context *ctx, const char *path, rgg_roadmap **out)
         in.get(g.soff.data(), sizeof(int64_t) * g.soff.size());
         if (!in.ok || g.soff[0] != 0 || (int64_t)copy_stride(h.D) * g.soff.back() != h.n_samp)
             return fail(RGG_E_INVALID_ARG, "%s: inconsistent sample offsets", path);
-        for (int64_t e = 0; e < h.E; ++e)
-            if (g.soff[(size_t)e + 1] < g.soff[(size_t)e] || (g.soff[(size_t)e + 1] - g.soff[(size_t)e]) % h.B != 0)
+        // each edge holds whole configurations, as many as a build can give
+        // (a zero count would leave the copy tests without a stride)
+        for (int64_t e = 0; e < h.E; ++e) {
+            const int64_t P = g.soff[(size_t)e + 1] - g.soff[(size_t)e];
+            if (P < kMinEdgeConfigs * h.B || P > kMaxEdgeConfigs * h.B || P % h.B != 0)
                 return fail(RGG_E_INVALID_ARG, "%s: inconsistent sample offsets", path);
+        }
         g.samp.resize((size_t)h.n_samp);
         g.cap.resize((size_t)h.n_cap);
         g.radius.resize((size_t)h.B);
@@ -1354,8 +1368,6 @@ rgg_status rgg_load(rgg_context *ctx, const char *path, rgg_roadmap **out)
     } catch (const std::bad_alloc &) {
         return fail(RGG_E_OUT_OF_MEMORY, "host memory for %s", path);
     }
-    std::vector<rgg_box> resident;
-    std::vector<int2> cnt;
     try {
         resident.resize((size_t)h.M);
         cnt.resize((size_t)h.E);
@@ -1400,6 +1412,18 @@ rgg_status rgg_load(rgg_context *ctx, const char *path, rgg_roadmap **out)
     if (in.ok) in.get(&sum, sizeof sum);
     if (!in.ok) return fail(RGG_E_INVALID_ARG, "%s is truncated", path);
     if (sum != want) return fail(RGG_E_INVALID_ARG, "%s: checksum mismatch", path);
+    return RGG_OK;
+}
+
+rgg_status rgg_load(rgg_context *ctx, const char *path, rgg_roadmap **out)
+{
+    if (!ctx || !path || !out) return fail(RGG_E_INVALID_ARG, "null argument");
+    auto t0 = std::chrono::steady_clock::now();
+    LoadedFile L;
+    rgg_status rs = read_roadmap_file(path, &L);
+    if (rs != RGG_OK) return rs;
+    const FileHeader &h = L.h;
+    const HostGeometry &g = L.g;
     HIP_OR_FAIL(hipSetDevice(ctx->device), "hipSetDevice");
     HostGrid grid;
     std::string err;
@@ -1407,9 +1431,19 @@ rgg_status rgg_load(rgg_context *ctx, const char *path, rgg_roadmap **out)
     if (st != RGG_OK) return fail(st, "%s", err.c_str());
     const RoadmapParams p = {h.M, h.mixed != 0, (double)h.band_rel, h.retest_capacity, h.chunk};
     rgg_roadmap *rm = nullptr;
-    if ((st = make_roadmap(ctx, g, grid, p, resident.data(), cnt.data(), &rm)) != RGG_OK) return st;
+    if ((st = make_roadmap(ctx, g, grid, p, L.resident.data(), L.cnt.data(), &rm)) != RGG_OK) return st;
     rm->info.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = rm;
+    return RGG_OK;
+}
+
+rgg_status rgg_debug_read_file(const char *path, int64_t *n_edges)
+{
+    if (!path) return fail(RGG_E_INVALID_ARG, "null argument");
+    LoadedFile L;
+    rgg_status st = read_roadmap_file(path, &L);
+    if (st != RGG_OK) return st;
+    if (n_edges) *n_edges = L.h.E;
     return RGG_OK;
 }
 

@@ -7,11 +7,11 @@
 //               one grid cell it also hands out the fixed work items;
 //   k_cells     grid mode: activate every grid cell a changed box overlaps
 //               and emit one work item per (cell, chunk of its edges)
-//               (Sec. 3.3);
+//               (Sec. 4.3);
 //   k_item32/64 one block per work item: pairs of the item's edges with the
 //               changed boxes of the cell, outer test (per-sphere capsule vs
 //               box), inner test (copies of the spheres whose capsule met),
-//               counter update (Sec. 3.1 rule; Alg. 1's intersection lists
+//               counter update (Sec. 4.1 rule; Alg. 1's intersection lists
 //               kept as counts).  In the FP32 mode a pair whose margin falls
 //               inside the rounding band is left to
 //   k_fp64      which decides it in binary64, one wavefront per pair; an

@@ -14,6 +14,10 @@ namespace rgg {
 constexpr int kMaxSpheres = 64;     // one wavefront covers every sphere of an edge
 constexpr int kMaxLinks = 32;
 constexpr int kAabbStride = 8;      // floats per edge box: lo[3], s, hi[3], pad
+// configurations per edge: at least 2 (both ends, a node (v, v) included), at
+// most 2^24 (the kernels index an edge's copies with 32-bit integers)
+constexpr int64_t kMinEdgeConfigs = 2;
+constexpr int64_t kMaxEdgeConfigs = (int64_t)1 << 24;
 
 // Approximations of a range of edges, built on the host in binary64.
 //
@@ -54,7 +58,7 @@ rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *rob,
                           const rgg_build_opts *opts, int64_t e0, int64_t e1, int threads,
                           HostGeometry *out, std::string *err);
 
-// Uniform grid over the edge boxes (Sec. 3.3 spatially filtered checking).
+// Uniform grid over the edge boxes (Sec. 4.3 spatially filtered checking).
 struct HostGrid {
     int32_t dim[3] = {1, 1, 1};
     double org[3] = {0, 0, 0};

@@ -117,6 +117,8 @@ struct rgg_server {
     std::unordered_map<uint64_t, Ticket> tickets;
     uint64_t next_ticket = 1;
     bool stopping = false;
+    bool closed = false;          // rgg_server_stop has joined the worker
+    int pollers = 0;              // threads waiting in rgg_server_poll
     std::string worker_error;
     std::thread worker;
     std::vector<rgg_roadmap *> seen;   // roadmaps this server has updated (worker only)
@@ -125,6 +127,7 @@ struct rgg_server {
     void run();
     bool dispatch(Slot &slot, std::vector<Pending> &batch);
     void complete(Slot &slot);
+    void fail_worker(const char *msg);
 };
 
 namespace {
@@ -227,6 +230,18 @@ void rgg_server::complete(Slot &slot)
     cv_done.notify_all();
 }
 
+// Records a worker error and wakes every waiting poller: their tickets will
+// not complete, and rgg_server_poll reports the error instead.
+void rgg_server::fail_worker(const char *msg)
+{
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        worker_error = msg;
+        stopping = true;
+    }
+    cv_done.notify_all();
+}
+
 void rgg_server::run()
 {
     hipSetDevice(device);
@@ -240,11 +255,8 @@ void rgg_server::run()
             if (q == hipSuccess) {
                 complete(sl);
             } else if (q != hipErrorNotReady) {
-                std::lock_guard<std::mutex> lk(mu);
-                worker_error = hipGetErrorString(q);
-                stopping = true;
-                any_busy = false;
-                break;
+                fail_worker(hipGetErrorString(q));
+                return;
             } else {
                 any_busy = true;
             }
@@ -311,9 +323,7 @@ void rgg_server::run()
                 free_slot->offs.push_back(pr.second);
             }
             if (!dispatch(*free_slot, batch)) {
-                std::lock_guard<std::mutex> lk(mu);
-                worker_error = "batch launch failed";
-                stopping = true;
+                fail_worker("batch launch failed");
                 return;
             }
         } else {
@@ -426,15 +436,19 @@ rgg_status rgg_server_poll(rgg_server *srv, uint64_t ticket, int32_t wait, int32
     std::unique_lock<std::mutex> lk(srv->mu);
     auto it = srv->tickets.find(ticket);
     if (it == srv->tickets.end()) return fail(RGG_E_INVALID_ARG, "unknown ticket %llu", (unsigned long long)ticket);
-    if (wait)
+    if (wait) {
+        srv->pollers++;
         srv->cv_done.wait(lk, [&] {
             auto t = srv->tickets.find(ticket);
-            return t == srv->tickets.end() || t->second.state == 2 || !srv->worker_error.empty();
+            return t == srv->tickets.end() || t->second.state == 2 || !srv->worker_error.empty() || srv->closed;
         });
+        if (--srv->pollers == 0 && srv->closed) srv->cv_done.notify_all();
+    }
     it = srv->tickets.find(ticket);
     if (it == srv->tickets.end()) return fail(RGG_E_INVALID_ARG, "ticket %llu was released", (unsigned long long)ticket);
     if (it->second.state != 2) {
         if (!srv->worker_error.empty()) return fail(RGG_E_DEVICE, "server stopped: %s", srv->worker_error.c_str());
+        if (srv->closed) return fail(RGG_E_INVALID_ARG, "server is stopping");
         *done = 0;
         return RGG_OK;
     }
@@ -454,6 +468,14 @@ rgg_status rgg_server_stop(rgg_server *srv)
     }
     srv->cv_work.notify_all();
     if (srv->worker.joinable()) srv->worker.join();
+    {
+        // wake every poller still waiting (their tickets cannot complete after
+        // a worker error) and free nothing until the last one has left
+        std::unique_lock<std::mutex> lk(srv->mu);
+        srv->closed = true;
+        srv->cv_done.notify_all();
+        srv->cv_done.wait(lk, [&] { return srv->pollers == 0; });
+    }
     const std::string err = srv->worker_error;
     hipSetDevice(srv->device);
     for (Slot &sl : srv->slots)

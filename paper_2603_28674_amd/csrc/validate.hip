@@ -3,7 +3,7 @@
 //
 // The check is continuous: does any configuration q(t), t in [0, 1], of the
 // edge's motion put a robot sphere into a present box?  It refines the two
-// approximations of Sec. 2.2 on dyadic sub-intervals [j 2^-l, (j+1) 2^-l]:
+// approximations of Sec. 3.2 on dyadic sub-intervals [j 2^-l, (j+1) 2^-l]:
 //   free(l, j)  every sphere's capsule from its centre at the interval's start
 //               to its centre at the end, radius r_i + delta_i 4^-l, misses
 //               every present box (delta_i 4^-l bounds the chord deviation

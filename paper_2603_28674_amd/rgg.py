@@ -134,7 +134,7 @@ EXPORTS = ["rgg_context_create", "rgg_context_destroy", "rgg_build", "rgg_destro
            "rgg_server_submit", "rgg_server_poll", "rgg_server_stop", "rgg_labels", "rgg_gray_list",
            "rgg_timing_enable", "rgg_timing_read", "rgg_tune", "rgg_batch_tune", "rgg_save", "rgg_load",
            "rgg_validate", "rgg_validate_async",
-           "rgg_debug_geometry",
+           "rgg_debug_geometry", "rgg_debug_read_file",
            "rgg_last_error", "rgg_version"]
 
 _lib = None
@@ -180,6 +180,7 @@ def lib():
         "rgg_validate_async": (I32, [P, P, P, I64, P, I32, I32, P, P, P, P]),
         "rgg_load": (I32, [P, C.c_char_p, C.POINTER(P)]),
         "rgg_debug_geometry": (I32, [P, P, P, I64, I64, P, P, P, P]),
+        "rgg_debug_read_file": (I32, [C.c_char_p, C.POINTER(I64)]),
         "rgg_last_error": (C.c_char_p, []),
         "rgg_version": (C.c_char_p, []),
     }
@@ -501,6 +502,14 @@ def rgg_debug_geometry(desc, robot, opts, e0, e1):
     _check(L.rgg_debug_geometry(C.byref(desc), C.byref(robot), C.byref(opts), e0, e1, _ptr(cnt),
                                 _ptr(ctr), _ptr(cap), _ptr(box)))
     return cnt, ctr[:int(cnt.sum())], cap[:e1 - e0], box[:e1 - e0]
+
+
+def rgg_debug_read_file(path):
+    """Reads and checks a roadmap file on the host as rgg_load does; returns
+    its edge count."""
+    n = C.c_int64(0)
+    _check(lib().rgg_debug_read_file(os.fsencode(path), C.byref(n)))
+    return n.value
 
 
 def rgg_last_error():

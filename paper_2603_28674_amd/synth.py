@@ -6,8 +6,8 @@ axis-aligned box obstacles and sequences of obstacle moves.  It holds none of
 the classification arithmetic (no forward kinematics, no interpolation, no
 distance tests); it only produces arrays.
 
-The paper evaluates on PRMs built without obstacles (Sec. 4, mobile-robot
-setup) and on random obstacle translations between updates (Sec. 4,
+The paper evaluates on PRMs built without obstacles (Sec. 5, mobile-robot
+setup) and on random obstacle translations between updates (Sec. 5,
 introduction of the experiments).  Its environments and robot models are not
 available, so the workloads below are synthetic stand-ins with the shapes and
 distributions stated for each configuration.

@@ -36,7 +36,7 @@ def mixed_workloads(n_updates):
     return specs
 
 
-def run_batched(ctx, specs, n_updates, one_shot=False):
+def run_batched(ctx, specs, n_updates, one_shot=False, item_edges=0):
     import torch
     from paper_2603_28674_amd import rgg
     import oracle
@@ -45,7 +45,7 @@ def run_batched(ctx, specs, n_updates, one_shot=False):
     gs, ors, bufs = [], [], []
     for w, prec, cell in specs:
         print(f"[batch] {w.name} E={w.n_edges} M={w.n_slots} prec={prec} cell={cell}", flush=True)
-        gs.append(rgg.Roadmap.from_workload(ctx, w, precision=prec, cell_size=cell))
+        gs.append(rgg.Roadmap.from_workload(ctx, w, precision=prec, cell_size=cell, item_edges=item_edges))
         ors.append(oracle.from_workload(w))
         states = torch.from_numpy(np.stack([w.absent()] + w.boxes)).to(dev)
         lab = torch.zeros(w.n_edges, dtype=torch.uint8, device=dev)
@@ -99,6 +99,22 @@ def test_batch_many_planar(ctx):
         specs.append((synth.planar_rigid(seed=600 + k, n_nodes=n, n_boxes=int(rng.integers(5, 40)), n_updates=3),
                       rgg.RGG_PREC_FP32_RECHECK, -1.0))
     run_batched(ctx, specs, 3)
+
+
+@pytest.mark.parametrize("item_edges", [482, 512])
+def test_batch_planar_tuned_decomposition(ctx, item_edges):
+    """The decomposition the planar batch is tuned to: items of 512 edges (the
+    second edge slot of every thread) over grid cells of twice the mean edge
+    extent (the build's default cell), plus one-cell roadmaps with the same
+    items."""
+    from paper_2603_28674_amd import rgg
+    rng = np.random.default_rng(59)
+    specs = []
+    for k in range(12):
+        n = int(round(np.exp(rng.uniform(np.log(300), np.log(6000)))))
+        specs.append((synth.planar_rigid(seed=700 + k, n_nodes=n, n_boxes=int(rng.integers(20, 120)), n_updates=3,
+                                         k=8), rgg.RGG_PREC_FP32_RECHECK, 0.0 if k % 3 else -1.0))
+    run_batched(ctx, specs, 3, item_edges=item_edges)
 
 
 def test_batch_errors(ctx):

@@ -4,7 +4,7 @@ rgg_batch_launch).
 
 The oracle cannot classify every edge of a 300k-edge roadmap against every
 update in a test's time, so it classifies a seeded sample of edge ids (the
-oracle's result for an edge depends on that edge alone, Sec. 3.2), and the
+oracle's result for an edge depends on that edge alone, Sec. 4.2), and the
 GPU's labels must equal its labels on the sample, bit for bit.  Properties
 that hold at any size are checked on every edge: labels are 0, 1 or 2, the
 gray list is exactly the ascending list of GRAY edge ids and n_gray its
@@ -46,10 +46,13 @@ def check_whole(labels, gray, n_gray):
 
 
 FULL = {
-    # name: (generator, precision, cell size as the benchmark uses it)
-    "spatial_fp32": (lambda n: synth.spatial_rigid(n_updates=n), "fp32", -1.0),
-    "planar_fp64": (lambda n: synth.planar_rigid(n_updates=n), "fp64", 0.0),
-    "arm_fp32": (lambda n: synth.planar_arm(n_updates=n), "fp32", 0.0),
+    # name: (generator, precision, cell size, edges per item): the work
+    # decompositions the benchmark's autotuner settles on for each workload
+    # (one cell; 288-, 64- and 482-edge items), plus the heuristic grid
+    "spatial_fp32": (lambda n: synth.spatial_rigid(n_updates=n), "fp32", -1.0, 288),
+    "planar_fp64": (lambda n: synth.planar_rigid(n_updates=n), "fp64", -1.0, 64),
+    "arm_fp32": (lambda n: synth.planar_arm(n_updates=n), "fp32", -1.0, 482),
+    "arm_fp32_grid": (lambda n: synth.planar_arm(n_updates=n), "fp32", 0.0, 256),
 }
 
 
@@ -57,14 +60,14 @@ FULL = {
 def test_full_size_sampled(ctx, name):
     import torch
     from paper_2603_28674_amd import rgg
-    gen, prec, cell = FULL[name]
+    gen, prec, cell, item = FULL[name]
     n_updates = 3
     w = gen(n_updates)
     precision = rgg.RGG_PREC_FP32_RECHECK if prec == "fp32" else rgg.RGG_PREC_FP64
-    print(f"[full] {name} E={w.n_edges} M={w.n_slots} cell={cell}", flush=True)
+    print(f"[full] {name} E={w.n_edges} M={w.n_slots} cell={cell} item_edges={item}", flush=True)
     idx, o = sample_oracle(w, 4000, seed=len(name))
     dev = torch.device("cuda:0")
-    g = rgg.Roadmap.from_workload(ctx, w, precision=precision, cell_size=cell)
+    g = rgg.Roadmap.from_workload(ctx, w, precision=precision, cell_size=cell, item_edges=item)
     states = torch.from_numpy(np.stack([w.absent()] + w.boxes)).to(dev)
     labels = torch.zeros(w.n_edges, dtype=torch.uint8, device=dev)
     gray = torch.zeros(w.n_edges, dtype=torch.int64, device=dev)
@@ -116,7 +119,9 @@ def test_full_size_planar_batch_sampled(ctx):
     ws = synth.batch_of_planar(seed=3, n_updates=n_rounds)
     print(f"[full] planar batch: {len(ws)} roadmaps, {sum(w.n_edges for w in ws)} edges", flush=True)
     dev = torch.device("cuda:0")
-    gs = [rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK, cell_size=0.0)
+    # the batch's tuned decomposition: 512-edge items, cells of twice the mean
+    # edge extent (the build's default cell)
+    gs = [rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK, cell_size=0.0, item_edges=512)
           for w in ws]
     bufs = []
     for w in ws:

@@ -2,14 +2,15 @@
 
 Every comparison is exact (labels are integers, gray lists are edge ids).
 Sizes span several label tiles (4096 edges) with a ragged tail; sequences
-start from the all-ABSENT state (Sec. 4: roadmaps are built without
-obstacles), add the first obstacle set, then move obstacles (Sec. 4: random
+start from the all-ABSENT state (Sec. 5: roadmaps are built without
+obstacles), add the first obstacle set, then move obstacles (Sec. 5: random
 translations), and include removals and re-additions through ABSENT.
 """
 import numpy as np
 import pytest
 
 from paper_2603_28674_amd import synth
+from neartangent import near_tangent_boxes
 
 pytestmark = pytest.mark.gpu
 
@@ -118,12 +119,24 @@ def test_grid_cell_size_does_not_change_labels(ctx, cell_size):
     check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, cell_size=cell_size)
 
 
-@pytest.mark.parametrize("item_edges", [64, 200, 300, 512])
+@pytest.mark.parametrize("item_edges", [64, 200, 300, 482, 512])
 @pytest.mark.parametrize("cell_size", [-1.0, 0.0])
-def test_item_size_does_not_change_labels(ctx, item_edges, cell_size):
+@pytest.mark.parametrize("kind", ["spatial", "planar", "arm"])
+def test_item_size_does_not_change_labels(ctx, kind, item_edges, cell_size):
+    """Every work decomposition gives the oracle's labels, for each robot
+    dimension: items of more than 256 edges use the second edge slot of each
+    thread (482 is the arm's tuned one-cell size, 512 the batch's)."""
     from paper_2603_28674_amd import rgg
-    w = with_removals(workload("spatial", seed=31), np.random.default_rng(8))
+    w = with_removals(workload(kind, seed=31), np.random.default_rng(8))
     check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, cell_size=cell_size, item_edges=item_edges)
+
+
+@pytest.mark.parametrize("item_edges", [482, 512])
+def test_item_size_fp64_planar_and_arm(ctx, item_edges):
+    from paper_2603_28674_amd import rgg
+    for kind in ("planar", "arm"):
+        w = workload(kind, n_updates=3, seed=32)
+        check_sequence(ctx, w, rgg.RGG_PREC_FP64, cell_size=-1.0, item_edges=item_edges)
 
 
 def test_device_buffer_entry_point(ctx):
@@ -203,48 +216,6 @@ def test_band_infinite_other_robots(ctx, kind):
     w = workload(kind, n_updates=2, seed=26)
     stats = check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, band_rel=float("inf"))
     assert all(s["n_rechecked"] == s["n_pairs"] > 0 for s in stats)
-
-
-def near_tangent_boxes(o, w, rng, n_boxes):
-    """Small boxes, each just beyond the extreme point of one edge's swept
-    robot along one axis: one face at distance r (1 + eps) from the extreme
-    sphere copy, or at R (1 + eps) from the extreme capsule axis end (R =
-    capsule radius), |eps| log-uniform in [1e-9, 1e-3] with a random sign.
-    Each box puts one edge's decisive distance test at or inside binary32
-    rounding of its threshold."""
-    D = w.robot.dim
-    rad = w.robot.sphere_radius
-    out = np.zeros((n_boxes, 6))
-    for b in range(n_boxes):
-        e = int(rng.integers(w.n_edges))
-        cen = o.centres(e)                      # [J, B, D]
-        ax = int(rng.integers(D))
-        side = float(rng.choice([-1.0, 1.0]))
-        eps = float(rng.choice([-1.0, 1.0]) * 10.0 ** rng.uniform(-9.0, -3.0))
-        if rng.random() < 0.5:
-            reach = side * cen[:, :, ax] + rad[None, :]
-            j, i = np.unravel_index(int(np.argmax(reach)), reach.shape)
-            p = cen[j, i]
-            dist = rad[i] * (1.0 + eps)
-        else:
-            R = o.capsule_radius(e)
-            ends = np.stack([cen[0], cen[-1]])  # [2, B, D]
-            reach = side * ends[:, :, ax] + R[None, :]
-            j, i = np.unravel_index(int(np.argmax(reach)), reach.shape)
-            p = ends[j, i]
-            dist = R[i] * (1.0 + eps)
-        face = p[ax] + side * dist
-        depth = rng.uniform(0.01, 0.1)
-        lo = np.zeros(3)
-        hi = np.zeros(3)
-        for k in range(D):
-            if k == ax:
-                lo[k], hi[k] = (face, face + depth) if side > 0 else (face - depth, face)
-            else:
-                lo[k] = p[k] - rng.uniform(0.01, 0.1)
-                hi[k] = p[k] + rng.uniform(0.01, 0.1)
-        out[b, :3], out[b, 3:] = lo, hi
-    return out
 
 
 @pytest.mark.parametrize("kind", ["spatial", "planar", "arm"])

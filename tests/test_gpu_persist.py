@@ -1,9 +1,9 @@
 """GPU tests of persistence (rgg_save / rgg_load) and of node labels.
 
-Sec. 1 and Sec. 3.3 keep the approximations between planning iterations:
+Sec. 1 and Sec. 4.3 keep the approximations between planning iterations:
 a roadmap read back from a file must hold the same labels and gray list as
 the one saved, and every later update of either must equal the FP64
-oracle's.  Sec. 2.1 treats a node as an edge whose two ends coincide: an
+oracle's.  Sec. 3.1 treats a node as an edge whose two ends coincide: an
 edge (v, v) carries node v's label, is never gray (its inner and outer
 approximations are the same spheres) and, because every edge's samples
 include its end configurations, a RED node makes every incident edge RED.

@@ -171,3 +171,71 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(out[f"{name} size"]) == ctypes.sizeof(st), name
         for field, *_ in st._fields_:
             assert int(out[f"{name}.{field}"]) == getattr(st, field).offset, f"{name}.{field}"
+
+
+# --------------------------------------------------------------------------
+# roadmap files: rgg_load's host-side checks, on crafted files
+# --------------------------------------------------------------------------
+
+def _fnv1a64(data: bytes) -> int:
+    h = 0xcbf29ce484222325
+    for b in data:
+        h = ((h ^ b) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def _roadmap_file(configs, checksum_ok=True):
+    """A planar one-sphere roadmap file, format version 2, whose edges hold
+    `configs[e]` configurations each; the checksum is recomputed over the
+    crafted bytes (as anyone editing such a file can do)."""
+    D, B, E, M, dof = 2, 1, len(configs), 1, 3
+    soff = np.concatenate([[0], np.cumsum(configs)]).astype(np.int64) * B
+    n_samp = int(soff[-1]) * 2                       # two values per planar copy
+    n_cap = E * (2 * D + 1) * B
+    hdr = np.zeros(1, dtype=np.dtype([
+        ("magic", "S8"), ("version", "<u4"), ("D", "<i4"), ("B", "<i4"), ("mixed", "<i4"),
+        ("chunk", "<i4"), ("retest", "<i4"), ("E", "<i8"), ("M", "<i8"), ("band", "<f4"),
+        ("one_cell", "<i4"), ("cell", "<f8"), ("n_samp", "<i8"), ("n_cap", "<i8")]))
+    assert hdr.dtype.itemsize == 80
+    hdr[0] = (b"RGGMAP01", 2, D, B, 1, 256, 1024, E, M, 1e-5, 1, float("inf"), n_samp, n_cap)
+    samp = np.linspace(0.0, 1.0, max(n_samp, 1))[:n_samp]
+    cap = np.zeros(n_cap)
+    cap[2 * D * B:: (2 * D + 1) * B] = 0.5
+    radius = np.array([0.25])
+    aabb = np.tile(np.array([-1, -1, 0, 1, 2, 2, 0, 0], dtype=np.float32), E)
+    resident = np.array([1.0, 1.0, 1.0, -1.0, -1.0, -1.0])
+    cnt = np.zeros(2 * E, dtype=np.int32)
+    vrob = np.zeros(1, dtype=np.dtype([("kind", "<i4"), ("B", "<i4"), ("L", "<i4"), ("dof", "<i4"),
+                                       ("base", "<f8", 2), ("pos", "<f8", 192), ("rad", "<f8", 64),
+                                       ("len", "<f8", 32), ("link", "<i4", 64)]))
+    assert vrob.dtype.itemsize == 2592
+    vrob["kind"], vrob["B"], vrob["dof"] = 0, B, dof
+    vrob["rad"][0, 0] = 0.25
+    motion = np.zeros(E * (2 * dof + 3))
+    delta = np.zeros(E * B)
+    body = b"".join(a.tobytes() for a in (hdr, soff, samp, cap, radius, aabb, resident, cnt, vrob,
+                                          motion, delta))
+    s = _fnv1a64(body) ^ (0 if checksum_ok else 1)
+    return body + np.array([s], dtype=np.uint64).tobytes()
+
+
+def test_load_refuses_edges_without_configurations(tmp_path):
+    """A file whose checksum is recomputed still has to describe what a build
+    can produce: every edge holds 2 .. 2^24 configurations (an edge with
+    none would give the copy tests no stride on the device)."""
+    good = tmp_path / "good.rggmap"
+    good.write_bytes(_roadmap_file([2, 3, 2]))
+    assert rgg.rgg_debug_read_file(str(good)) == 3
+    for name, configs in (("zero", [2, 0, 2]), ("one", [2, 1, 2])):
+        bad = tmp_path / f"{name}.rggmap"
+        bad.write_bytes(_roadmap_file(configs))
+        with pytest.raises(rgg.RggError, match="sample offsets"):
+            rgg.rgg_debug_read_file(str(bad))
+    corrupt = tmp_path / "sum.rggmap"
+    corrupt.write_bytes(_roadmap_file([2, 3, 2], checksum_ok=False))
+    with pytest.raises(rgg.RggError, match="checksum"):
+        rgg.rgg_debug_read_file(str(corrupt))
+    truncated = tmp_path / "short.rggmap"
+    truncated.write_bytes(_roadmap_file([2, 3, 2])[:-100])
+    with pytest.raises(rgg.RggError):
+        rgg.rgg_debug_read_file(str(truncated))

@@ -1,13 +1,13 @@
-"""Pins of the oracle's labels (paper Sec. 3.1 rule, Alg. 1 update).
+"""Pins of the oracle's labels (paper Sec. 4.1 rule, Alg. 1 update).
 
 * hand-built one-edge cases with labels derived by hand (golden fixture);
 * soundness against a dense brute-force check of the continuous motion on
   tiny roadmaps: RED implies a sampled configuration really collides, GREEN
-  implies no collision anywhere along the edge (Sec. 2.2: inner and outer
+  implies no collision anywhere along the edge (Sec. 3.2: inner and outer
   approximations are a subset and a superset of the swept volume);
 * monotonicity in the obstacle set, incremental == from scratch (Alg. 1 with
   RevalidateOldIntersections realised as counters), permutation invariance,
-  and degenerate edges (nodes, Sec. 2.1).
+  and degenerate edges (nodes, Sec. 3.1).
 """
 import json
 import math
@@ -221,3 +221,139 @@ def test_absent_boxes_touch_nothing(oracle_lib):
     b[:, 2], b[:, 5] = 1.0, 0.0
     lab, _ = rm.classify(b)
     assert np.all(lab == 0)
+
+
+# --------------------------------------------------------------------------
+# the two readings of S agree (Sec. 4.1: red means the inner approximation
+# meets the obstacle; S is taken sphere by sphere so that S implies C)
+# --------------------------------------------------------------------------
+
+def _copy_d2(cen, box, D):
+    """Squared distance of every copy centre (J, B, D) to the box, evaluated
+    as the point-box test is (per axis max(lo - c, 0, c - hi), squares summed
+    left to right)."""
+    acc = None
+    for k in range(D):
+        g = np.maximum(np.maximum(box[k] - cen[..., k], 0.0), cen[..., k] - box[3 + k])
+        acc = g * g if acc is None else acc + g * g
+    return acc
+
+
+def _s_forms(O, rm, rob, e, box):
+    """(C, per-sphere S, 'C and any copy' S, containment failures): the
+    oracle's S is 'for some sphere i, capsule i and a copy of sphere i meet
+    the box'; the other reading is 'some capsule meets and some copy meets'.
+    A containment failure is a sphere whose copy meets while its own capsule
+    misses: in exact arithmetic the copies lie inside the capsule, so only
+    rounding can produce one, and only then can the two readings differ."""
+    D = rob.dim
+    C, S = rm.pair(e, box)
+    cen = rm.centres(e)
+    hit = _copy_d2(cen, box, D) <= rob.sphere_radius[None, :] ** 2        # (J, B)
+    R = rm.capsule_radius(e)
+    fails = []
+    for i in np.nonzero(hit.any(axis=0))[0]:
+        fm = O.segbox_fmin(cen[0, i], cen[-1, i], box, D)
+        if not fm <= R[i] * R[i]:
+            d2 = float(np.min(_copy_d2(cen[:, i:i + 1], box, D)))
+            fails.append((d2, float(rob.sphere_radius[i] ** 2), fm, float(R[i] * R[i])))
+    return C, S, int(C and hit.any()), fails
+
+
+def _translation_roadmap(rng, kind):
+    """Pure translations (delta = 0: each capsule is exactly the swept
+    sphere) with boxes whose face is at r (1 +- eps), eps in [1e-18, 1e-12],
+    from an interior copy of one sphere: the copy test and the capsule test
+    of that sphere then decide at a binary64 tie."""
+    if kind == synth.SE2:
+        rob = synth.robot_se2(rng)
+        n = 24
+        q = np.zeros((2 * n, 3))
+        q[:n, :2] = rng.uniform(0, 6, (n, 2))
+        q[n:, :2] = q[:n, :2] + rng.normal(0, 0.7, (n, 2))
+        q[:, 2] = np.tile(rng.uniform(-math.pi, math.pi, n), 2)
+        res, spe = 0.05, 0
+    else:
+        rob = synth.robot_se3(rng)
+        n = 24
+        q = np.zeros((2 * n, 7))
+        q[:n, :3] = rng.uniform(0, 3, (n, 3))
+        q[n:, :3] = q[:n, :3] + rng.normal(0, 0.4, (n, 3))
+        quat = synth.nodes_se3(rng, n, 1.0)[:, 3:]
+        q[:n, 3:] = quat
+        q[n:, 3:] = quat
+        res, spe = 0.0, 20
+    edges = np.stack([np.arange(n), np.arange(n) + n], axis=1)
+    return rob, q, edges, res, spe
+
+
+@pytest.mark.parametrize("kind", [synth.SE2, synth.SE3, synth.ARM])
+def test_s_readings_agree_on_random_and_near_tangent_pairs(oracle_lib, kind):
+    """On every pair of the brute-force roadmaps and of near-tangent boxes
+    (a face at r (1 + eps) from an edge's extreme copy, or at R (1 + eps) from
+    its capsule end, |eps| in [1e-9, 1e-3]), the per-sphere S equals
+    'C and some copy meets'."""
+    from neartangent import near_tangent_boxes
+    O = oracle_lib
+    n_pairs = 0
+    for seed in (1, 2, 3):
+        rob, q, edges, res, spe, boxes = tiny(kind, seed)
+        w = synth.Workload("tiny", rob, q, edges, res, spe, [boxes], np.zeros(3), np.ones(3))
+        rm = O.Roadmap(rob, q, edges, res, spe, n_slots=len(boxes), threads=1)
+        near = near_tangent_boxes(rm, w, np.random.default_rng(seed), 24)
+        for box in np.concatenate([boxes, near]):
+            for e in range(len(edges)):
+                C, S, S_alt, fails = _s_forms(O, rm, rob, e, box)
+                assert S == S_alt, (e, box)
+                assert not fails, (e, box, fails)
+                assert S <= C
+                n_pairs += 1
+    assert n_pairs > 1000
+
+
+@pytest.mark.parametrize("kind", [synth.SE2, synth.SE3])
+def test_s_readings_split_only_at_binary64_ties(oracle_lib, kind):
+    """Translations with boxes tangent to interior copies within 1e-18 ..
+    1e-12 relative: the inputs most likely to separate the two readings.
+    Wherever a copy meets a box while its own capsule misses (the only way
+    they can differ), both tests sit at a binary64 tie: the copy's margin
+    d^2 - r^2 and the capsule's F_min - R^2 are each within 1e-12 of zero
+    relative to r^2.  The counts are printed for the record."""
+    O = oracle_lib
+    rng = np.random.default_rng(90 + kind)
+    rob, q, edges, res, spe = _translation_roadmap(rng, kind)
+    D = rob.dim
+    rm = O.Roadmap(rob, q, edges, res, spe, n_slots=1, threads=1)
+    splits = fails_n = tested = copy_hits = 0
+    for e in range(len(edges)):
+        # delta = 0 up to the rounding of a unit quaternion's self-product
+        assert np.all(rm.capsule_radius(e) - rob.sphere_radius <= 1e-12)
+        cen = rm.centres(e)
+        for _ in range(40):
+            j = int(rng.integers(1, cen.shape[0] - 1))
+            i = int(rng.integers(rob.n_spheres))
+            ax = int(rng.integers(D))
+            side = float(rng.choice([-1.0, 1.0]))
+            eps = float(rng.choice([-1.0, 1.0]) * 10.0 ** rng.uniform(-18.0, -12.0))
+            p = cen[j, i]
+            face = p[ax] + side * rob.sphere_radius[i] * (1.0 + eps)
+            box = np.zeros(6)
+            for k in range(D):
+                if k == ax:
+                    lo, hi = (face, face + 0.05) if side > 0 else (face - 0.05, face)
+                else:
+                    lo, hi = p[k] - 0.03, p[k] + 0.03
+                box[k], box[3 + k] = lo, hi
+            C, S, S_alt, fails = _s_forms(O, rm, rob, e, box)
+            tested += 1
+            copy_hits += int(_copy_d2(cen[j:j + 1, i:i + 1], box, D)[0, 0] <= rob.sphere_radius[i] ** 2)
+            splits += int(S != S_alt)
+            fails_n += len(fails)
+            for d2, r2, fm, R2 in fails:
+                assert d2 - r2 <= 0.0 and d2 - r2 >= -1e-12 * r2
+                assert fm - R2 > 0.0 and fm - R2 <= 1e-12 * r2
+            if S != S_alt:
+                assert fails, "the readings differ only through a containment failure"
+    print(f"[S readings] kind {kind}: {tested} tangent pairs ({copy_hits} with the tangent copy meeting), "
+          f"{fails_n} copies meeting outside their capsule by rounding, {splits} pairs where the readings differ")
+    assert copy_hits > tested // 4

@@ -1,6 +1,6 @@
 """Pins of the oracle's full validation of an edge (Alg. 1 when not lazy:
 every edge left unknown gets a full collision check; here a continuous one,
-by dyadic refinement of the outer and inner approximations of Sec. 2.2).
+by dyadic refinement of the outer and inner approximations of Sec. 3.2).
 
 * the validation's sin/cos against the C library's (numpy), with exact odd
   and even symmetry, which catches a wrong quadrant map;
