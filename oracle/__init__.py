@@ -29,7 +29,7 @@ _CFLAGS = ["-O2", "-std=gnu11", "-ffp-contract=off", "-fno-fast-math", "-fno-bui
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc into ``oracle/liboracle.so``."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
+        tmp = f"{_LIB}.tmp{os.getpid()}"   # one per process: parallel test workers build at once
         subprocess.run(["gcc", *_CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -50,6 +50,17 @@ def lib():
         L.orc_robot_free.argtypes = [P]
         L.orc_rm_build.restype = P
         L.orc_rm_build.argtypes = [P, I64, P, I64, P, D, C.c_int, I64, C.c_int]
+        L.orc_rm_build_ex.restype = P
+        L.orc_rm_build_ex.argtypes = [P, I64, P, I64, P, D, C.c_int, I64, C.c_int, C.c_int, C.c_int, D]
+        L.orc_rm_obb.restype = C.c_int
+        L.orc_rm_obb.argtypes = [P, I64, C.c_int, P, P, P]
+        L.orc_rm_spline.restype = I64
+        L.orc_rm_spline.argtypes = [P, I64, C.c_int, P]
+        L.orc_jacobi_eigen.argtypes = [C.c_int, P, P]
+        L.orc_obb_box_meet.restype = C.c_int
+        L.orc_obb_box_meet.argtypes = [C.c_int, P, P, P, P]
+        L.orc_sphere_spline.restype = I64
+        L.orc_sphere_spline.argtypes = [C.c_int, P, I64, D, D, D, P]
         L.orc_rm_free.argtypes = [P]
         L.orc_rm_classify.restype = I64
         L.orc_rm_classify.argtypes = [P, I64, P, P, P, I64, C.c_int]
@@ -146,6 +157,33 @@ def vsincos(x):
     return s.value, c.value
 
 
+def jacobi_eigen(a):
+    """Eigenvectors (columns) of the symmetric 2x2 or 3x3 matrix ``a`` by the
+    oriented boxes' Jacobi rotations."""
+    a = _f64(a)
+    D = a.shape[0]
+    v = np.zeros((D, D))
+    lib().orc_jacobi_eigen(D, _p(a), _p(v))
+    return v
+
+
+def obb_box_meet(c, u, h, box):
+    """The separating-axis test of an oriented box (centre c, axes u as rows,
+    half-extents h) against the box [lo(3), hi(3)]."""
+    c = _f64(c)
+    return bool(lib().orc_obb_box_meet(c.shape[0], _p(c), _p(_f64(u)), _p(_f64(h)), _p(_f64(box))))
+
+
+def sphere_spline(pts, rad, eta, tol):
+    """Shortcut spline of one sphere through the centres ``pts`` [n+1, D]:
+    segments [K, 2D+1] (A, B, rho)."""
+    pts = _f64(pts)
+    n1, D = pts.shape
+    out = np.zeros((max(n1 - 1, 1), 2 * D + 1))
+    K = lib().orc_sphere_spline(D, _p(pts), n1 - 1, float(rad), float(eta), float(tol), _p(out))
+    return out[:K].copy()
+
+
 def point_box_d2(c, box, D=None):
     c = _f64(c)
     D = D or c.shape[0]
@@ -161,16 +199,18 @@ def segbox_fmin(a, b, box, D=None):
 class Roadmap:
     """Roadmap geometry plus per-edge counters, built by the oracle."""
 
-    def __init__(self, robot, q, edges, resolution=0.0, samples_per_edge=0, n_slots=0, threads=0):
+    def __init__(self, robot, q, edges, resolution=0.0, samples_per_edge=0, n_slots=0, threads=0,
+                 outer_obb=False, inner_splines=False, spline_tol=0.25):
         self.robot = robot if isinstance(robot, Robot) else Robot(robot)
         self._q = _f64(q)
         self._uv = np.ascontiguousarray(edges, dtype=np.int64)
         self.E = int(self._uv.shape[0])
         self.M = int(n_slots)
         threads = threads or min(os.cpu_count() or 1, 16)
-        self.h = lib().orc_rm_build(self.robot.h, self._q.shape[0], _p(self._q), self.E,
-                                    _p(self._uv), float(resolution), int(samples_per_edge),
-                                    self.M, int(threads))
+        self.h = lib().orc_rm_build_ex(self.robot.h, self._q.shape[0], _p(self._q), self.E,
+                                       _p(self._uv), float(resolution), int(samples_per_edge),
+                                       self.M, int(threads), int(bool(outer_obb)), int(bool(inner_splines)),
+                                       float(spline_tol))
         if not self.h:
             raise ValueError("oracle rejected the roadmap")
         self.threads = threads
@@ -238,6 +278,25 @@ class Roadmap:
         lib().orc_rm_capsule_radius(self.h, int(e), _p(out))
         return out
 
+    def obb(self, e, b):
+        """(centre, axes as rows, half-extents) of body b's oriented box on
+        edge e, or None."""
+        D = self.robot.D
+        c, u, h = np.zeros(D), np.zeros((D, D)), np.zeros(D)
+        if not lib().orc_rm_obb(self.h, int(e), int(b), _p(c), _p(u), _p(h)):
+            return None
+        return c, u, h
+
+    def spline(self, e, i):
+        """Spline segments [K, 2D+1] (A, B, rho) of sphere i on edge e."""
+        D = self.robot.D
+        K = int(lib().orc_rm_spline(self.h, int(e), int(i), None))
+        if K < 0:
+            raise ValueError("the roadmap was built without splines")
+        out = np.zeros((max(K, 1), 2 * D + 1))
+        lib().orc_rm_spline(self.h, int(e), int(i), _p(out))
+        return out[:K].copy()
+
     def counters(self):
         o = np.zeros(self.E, dtype=np.int32)
         i = np.zeros(self.E, dtype=np.int32)
@@ -245,6 +304,7 @@ class Roadmap:
         return o, i
 
 
-def from_workload(w, threads=0):
+def from_workload(w, threads=0, outer_obb=False, inner_splines=False, spline_tol=0.25):
     """Oracle roadmap for a ``synth.Workload``."""
-    return Roadmap(w.robot, w.q, w.edges, w.resolution, w.samples_per_edge, w.n_slots, threads)
+    return Roadmap(w.robot, w.q, w.edges, w.resolution, w.samples_per_edge, w.n_slots, threads,
+                   outer_obb=outer_obb, inner_splines=inner_splines, spline_tol=spline_tol)

@@ -262,6 +262,292 @@ static void deltas(const orc_robot *r, const motion *m, double *dl)
 }
 
 /* ------------------------------------------------------------------------ */
+/* second outer form: an oriented box per robot body (Sec. 4.2)              */
+/* ------------------------------------------------------------------------ */
+/*
+ * Sec. 4.2 bounds the swept volume of each robot body along an edge by an
+ * oriented box fitted to the point cloud of the body's intermediate
+ * placements (an approximation of the smallest such box).  Here a body is
+ * the whole robot for the rigid kinds and one link for the arm, and its cloud
+ * is the centres of its spheres at every configuration of cfg(e).
+ *   axes    the principal axes of the cloud: eigenvectors of its scatter
+ *           matrix sum (p - mean)(p - mean)^T, found by cyclic Jacobi
+ *           rotations (one rotation in 2-D, eight sweeps in 3-D); their
+ *           product is a rotation, orthonormal up to rounding;
+ *   extent  along axis u_k, from min(u_k . c - r_i - eta_i) to
+ *           max(u_k . c + r_i + eta_i) over the cloud, eta_i = delta_i / n^2.
+ * Over one step [t_j, t_j+1] of length 1/n sphere i's centre stays within
+ * delta_i / n^2 of the chord between its two sampled positions (the same
+ * second-derivative bound as the capsule's, on an interval 1/n long), so
+ * the sphere's swept volume over that step lies in the capsule of radius
+ * r_i + eta_i around the chord, whose extent along any unit vector lies
+ * between the projections of the chord's ends widened by r_i + eta_i.  The
+ * box, the intersection of the D slabs, therefore holds the body's whole
+ * continuous swept volume.  Stored as centre c, axes u (row k = u_k) and
+ * half-extents h.
+ */
+#define JACOBI_SWEEPS_3D 8
+
+/* eigenvectors of the symmetric D x D matrix a (overwritten) into the
+ * columns of v: cyclic Jacobi rotations over the pairs (p, q), p < q */
+static void jacobi_eigen(int D, double a[3][3], double v[3][3])
+{
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) v[r][c] = r == c ? 1.0 : 0.0;
+    int sweeps = D == 3 ? JACOBI_SWEEPS_3D : 1;
+    for (int sw = 0; sw < sweeps; ++sw) {
+        for (int p = 0; p < D - 1; ++p) {
+            for (int q = p + 1; q < D; ++q) {
+                double apq = a[p][q];
+                if (apq == 0.0) continue;
+                /* the rotation angle phi zeroes a[p][q]: t = tan(phi) is the
+                 * smaller root of t^2 + 2 theta t - 1 = 0 */
+                double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+                double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
+                if (theta < 0.0) t = -t;
+                double c = 1.0 / sqrt(t * t + 1.0);
+                double s = t * c;
+                for (int r = 0; r < D; ++r) {
+                    if (r == p || r == q) continue;
+                    double arp = a[r][p], arq = a[r][q];
+                    a[r][p] = c * arp - s * arq;
+                    a[p][r] = a[r][p];
+                    a[r][q] = s * arp + c * arq;
+                    a[q][r] = a[r][q];
+                }
+                a[p][p] = a[p][p] - t * apq;
+                a[q][q] = a[q][q] + t * apq;
+                a[p][q] = 0.0;
+                a[q][p] = 0.0;
+                for (int r = 0; r < D; ++r) {
+                    double vrp = v[r][p], vrq = v[r][q];
+                    v[r][p] = c * vrp - s * vrq;
+                    v[r][q] = s * vrp + c * vrq;
+                }
+            }
+        }
+    }
+}
+
+/* body of sphere i: 0 for the rigid kinds, its link for the arm */
+static int body_of(const orc_robot *r, int i) { return r->kind == ORC_ARM ? r->link[i] : 0; }
+static int n_bodies(const orc_robot *r) { return r->kind == ORC_ARM ? r->L : 1; }
+
+/* Oriented box of body b for an edge with n+1 configurations of centres
+ * ctr [n+1][B][D] and chord bounds dl [B].  Returns 0 (and writes nothing)
+ * when the body carries no sphere. */
+static int body_obb(const orc_robot *r, int b, const double *ctr, int64_t n, const double *dl, double *c,
+                    double *u, double *h)
+{
+    int B = r->B, D = r->D;
+    double mu[3] = {0.0, 0.0, 0.0};
+    int64_t cnt = 0;
+    for (int64_t j = 0; j <= n; ++j)
+        for (int i = 0; i < B; ++i) {
+            if (body_of(r, i) != b) continue;
+            for (int k = 0; k < D; ++k) mu[k] = mu[k] + ctr[(j * B + i) * D + k];
+            ++cnt;
+        }
+    if (cnt == 0) return 0;
+    for (int k = 0; k < D; ++k) mu[k] = mu[k] / (double)cnt;
+    double a[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    for (int64_t j = 0; j <= n; ++j)
+        for (int i = 0; i < B; ++i) {
+            if (body_of(r, i) != b) continue;
+            double d[3];
+            for (int k = 0; k < D; ++k) d[k] = ctr[(j * B + i) * D + k] - mu[k];
+            for (int k = 0; k < D; ++k)
+                for (int l = k; l < D; ++l) a[k][l] = a[k][l] + d[k] * d[l];
+        }
+    for (int k = 0; k < D; ++k)
+        for (int l = 0; l < k; ++l) a[k][l] = a[l][k];
+    double v[3][3];
+    jacobi_eigen(D, a, v);
+    for (int k = 0; k < D; ++k)
+        for (int d = 0; d < D; ++d) u[k * D + d] = v[d][k];
+    double nn = (double)n * (double)n;
+    double mid[3];
+    for (int k = 0; k < D; ++k) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int64_t j = 0; j <= n; ++j)
+            for (int i = 0; i < B; ++i) {
+                if (body_of(r, i) != b) continue;
+                double pr = 0.0;
+                for (int d = 0; d < D; ++d) pr = pr + u[k * D + d] * ctr[(j * B + i) * D + d];
+                double eta = dl[i] / nn;
+                double l = (pr - r->rad[i]) - eta, g = (pr + r->rad[i]) + eta;
+                if (l < lo) lo = l;
+                if (g > hi) hi = g;
+            }
+        mid[k] = 0.5 * (lo + hi);
+        h[k] = 0.5 * (hi - lo);
+    }
+    for (int d = 0; d < D; ++d) {
+        double acc = 0.0;
+        for (int k = 0; k < D; ++k) acc = acc + mid[k] * u[k * D + d];
+        c[d] = acc;
+    }
+    return 1;
+}
+
+/* 1 when the oriented box (c, u, h) and the closed box [lo, hi] share a
+ * point.  Separating-axis theorem for two boxes: they are disjoint exactly
+ * when their projections on one of the candidate axes are -- the box's face
+ * normals e_d, the oriented box's axes u_k and, in 3-D, the nine products
+ * e_d x u_k.  On an axis L the projections of the centres differ by |T . L|
+ * (T = c - box centre) and the boxes reach sum_d bh_d |e_d . L| and
+ * sum_k h_k |u_k . L| from them; touching counts as sharing a point. */
+static int obb_box_meet(int D, const double *c, const double *u, const double *h, const double *lo,
+                        const double *hi)
+{
+    double bh[3], t[3], au[3][3];
+    for (int d = 0; d < D; ++d) {
+        bh[d] = 0.5 * (hi[d] - lo[d]);
+        t[d] = c[d] - 0.5 * (lo[d] + hi[d]);
+    }
+    for (int d = 0; d < D; ++d)
+        for (int k = 0; k < D; ++k) au[d][k] = fabs(u[k * D + d]);   /* |e_d . u_k| */
+    for (int d = 0; d < D; ++d) {
+        double rb = 0.0;
+        for (int k = 0; k < D; ++k) rb = rb + h[k] * au[d][k];
+        if (fabs(t[d]) > bh[d] + rb) return 0;
+    }
+    for (int k = 0; k < D; ++k) {
+        double ra = 0.0, tp = 0.0;
+        for (int d = 0; d < D; ++d) {
+            ra = ra + bh[d] * au[d][k];
+            tp = tp + u[k * D + d] * t[d];
+        }
+        if (fabs(tp) > h[k] + ra) return 0;
+    }
+    if (D == 3) {
+        /* L = e_d x u_k has components -u_k[d2] at d1 and u_k[d1] at d2
+         * (d1, d2 the next two axes after d); u_k1 . L = +-u_k2[d] and
+         * u_k2 . L = -+u_k1[d] for an orthonormal frame */
+        for (int d = 0; d < 3; ++d) {
+            int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+            for (int k = 0; k < 3; ++k) {
+                int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+                double ra = bh[d1] * au[d2][k] + bh[d2] * au[d1][k];
+                double rb = h[k1] * au[d][k2] + h[k2] * au[d][k1];
+                double tp = t[d2] * u[k * 3 + d1] - t[d1] * u[k * 3 + d2];
+                if (fabs(tp) > ra + rb) return 0;
+            }
+        }
+    }
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* second inner form: shortcut splines (Sec. 4.2)                            */
+/* ------------------------------------------------------------------------ */
+/*
+ * Sec. 4.2 joins the centres of the copies of a sphere along the edge into a
+ * polyline, the sphere's spline, and shortens it with the curve
+ * simplification of Agarwal et al.: vertices strictly between j and p may be
+ * dropped when each lies close enough to the segment from c_j to c_p.  For
+ * each sphere i, with err(a, b) = max over a < m < b of dist(c_m, [c_a, c_b])
+ * (0 when b = a + 1), the simplification here is their greedy one:
+ *   from vertex a (first 0), take b = a+1, a+2, a+4, ... (the last one
+ *   clamped to n) while err(a, b) <= tol r_i; between the last accepted and
+ *   the first rejected b, bisect for an accepted b whose successor is
+ *   rejected; keep the segment (a, b) and continue from b until b = n.
+ * A kept segment is the capsule around [c_a, c_b] of radius
+ *   rho = r_i - err(a, b) - eta_i,   eta_i = delta_i / n^2,
+ * dropped if rho < 0.  The capsule lies in the swept volume: a point x of
+ * the segment lies within err(a, b) of the polyline (walking the polyline
+ * from c_a to c_b passes a point y whose coordinate along the segment equals
+ * x's; y is on a polyline piece whose distance from the segment's line is at
+ * most its end vertices', and these are within err(a, b)); y, on the piece
+ * between c_m and c_m+1, is within eta_i of the centre at the matching
+ * parameter (the chord bound on an interval of length 1/n).  So x is within
+ * r_i - rho of a centre of sphere i on the path, and the ball of radius rho
+ * around x lies in that sphere.  The paper's splines have no thickness and
+ * accept err < r_i; a thickness that the tolerance leaves makes the spline
+ * a solid inner approximation of the sphere's sweep.
+ */
+
+/* squared distance from p to the segment [a, b] */
+static double point_seg_d2(int D, const double *p, const double *a, const double *b)
+{
+    double d[3], dd = 0.0, wd = 0.0;
+    for (int k = 0; k < D; ++k) {
+        d[k] = b[k] - a[k];
+        dd = dd + d[k] * d[k];
+        wd = wd + (p[k] - a[k]) * d[k];
+    }
+    double t = 0.0;
+    if (dd > 0.0) {
+        t = wd / dd;
+        if (t < 0.0) t = 0.0;
+        if (t > 1.0) t = 1.0;
+    }
+    double acc = 0.0;
+    for (int k = 0; k < D; ++k) {
+        double g = (a[k] + t * d[k]) - p[k];
+        acc = acc + g * g;
+    }
+    return acc;
+}
+
+/* err(a, b)^2 over the vertices pts + m * stride */
+static double shortcut_err2(int D, const double *pts, int64_t stride, int64_t a, int64_t b)
+{
+    double mx = 0.0;
+    for (int64_t m = a + 1; m < b; ++m) {
+        double v = point_seg_d2(D, pts + m * stride, pts + a * stride, pts + b * stride);
+        if (v > mx) mx = v;
+    }
+    return mx;
+}
+
+/* The spline of one sphere: vertices pts + j * stride, j = 0..n.  Writes
+ * the kept segments (A[D], B[D], rho) to out (may be NULL) and returns
+ * their count (at most n). */
+static int64_t sphere_spline(int D, const double *pts, int64_t stride, int64_t n, double rad, double eta,
+                             double tol, double *out)
+{
+    double lim = tol * rad;
+    double lim2 = lim * lim;
+    int64_t a = 0, K = 0;
+    while (a < n) {
+        int64_t lo = a + 1, hi = n + 1;   /* (a, lo) accepted; (a, hi) rejected unless hi = n + 1 */
+        int64_t step = 2;
+        for (;;) {
+            int64_t b = a + step < n ? a + step : n;
+            if (b <= lo) break;
+            if (shortcut_err2(D, pts, stride, a, b) <= lim2) {
+                lo = b;
+                if (b == n) break;
+                step = step * 2;
+            } else {
+                hi = b;
+                break;
+            }
+        }
+        while (hi - lo > 1 && hi <= n) {
+            int64_t mid = lo + (hi - lo) / 2;
+            if (shortcut_err2(D, pts, stride, a, mid) <= lim2) lo = mid;
+            else hi = mid;
+        }
+        double rho = (rad - sqrt(shortcut_err2(D, pts, stride, a, lo))) - eta;
+        if (rho >= 0.0) {
+            if (out) {
+                double *o = out + K * (2 * D + 1);
+                for (int k = 0; k < D; ++k) {
+                    o[k] = pts[a * stride + k];
+                    o[D + k] = pts[lo * stride + k];
+                }
+                o[2 * D] = rho;
+            }
+            ++K;
+        }
+        a = lo;
+    }
+    return K;
+}
+
+/* ------------------------------------------------------------------------ */
 /* distance predicates                                                       */
 /* ------------------------------------------------------------------------ */
 
@@ -391,7 +677,18 @@ typedef struct {
     double *resident;  /* [M][6] obstacle slots for the incremental mode  */
     double *q;         /* [n_nodes][dof] node configurations (validation) */
     int64_t *uv;       /* [E][2] edge end nodes (validation)              */
+    /* the second forms (Sec. 4.2), chosen at build */
+    int obb;           /* outer: capsules and per-body oriented boxes     */
+    int spl;           /* inner: shortcut splines instead of copies       */
+    double tol;        /* spline tolerance, in [0, 1)                     */
+    int nb;            /* bodies                                          */
+    int bhas[MAX_LINKS];   /* body b carries a sphere                     */
+    double *obbv;      /* [E][nb][2D + D*D] centre, axes (rows), half-extents */
+    int64_t *sseg;     /* [E*B + 1] first spline segment of (edge, sphere) */
+    double *seg;       /* [segments][2D + 1] spline segments (A, B, rho)  */
 } orc_rm;
+
+static int obb_len(int D) { return 2 * D + D * D; }
 
 typedef struct {
     orc_rm *rm;
@@ -400,7 +697,8 @@ typedef struct {
     double resolution;
     int spe;
     int64_t e0, e1;
-    int pass;          /* 0: count samples, 1: fill geometry             */
+    int pass;          /* 0: count samples, 1: fill geometry and count spline
+                          segments, 2: fill spline segments               */
     int status;
 } build_job;
 
@@ -421,12 +719,33 @@ static void *build_worker(void *arg)
             continue;
         }
         double *c = rm->ctr + rm->soff[e] * B * D;
+        if (j->pass == 2) {
+            deltas(r, &m, dl);
+            double nn = (double)n * (double)n;
+            for (int i = 0; i < B; ++i)
+                sphere_spline(D, c + i * D, (int64_t)B * D, n, r->rad[i], dl[i] / nn, rm->tol,
+                              rm->seg + rm->sseg[e * B + i] * (2 * D + 1));
+            continue;
+        }
         for (int64_t s = 0; s <= n; ++s) {
             double t = (double)s / (double)n;
             motion_at(r, &m, t, qt);
             fk(r, qt, c + s * B * D);
         }
         deltas(r, &m, dl);
+        if (rm->obb) {
+            for (int b = 0; b < rm->nb; ++b) {
+                double *o = rm->obbv + (e * rm->nb + b) * obb_len(D);
+                if (!body_obb(r, b, c, n, dl, o, o + D, o + D + D * D))
+                    for (int k = 0; k < obb_len(D); ++k) o[k] = 0.0;
+            }
+        }
+        if (rm->spl) {
+            double nn = (double)n * (double)n;
+            for (int i = 0; i < B; ++i)
+                rm->sseg[e * B + i + 1] =
+                    sphere_spline(D, c + i * D, (int64_t)B * D, n, r->rad[i], dl[i] / nn, rm->tol, NULL);
+        }
         double *first = c, *last = c + n * B * D;
         double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         for (int i = 0; i < B; ++i) {
@@ -483,17 +802,21 @@ void orc_rm_free(orc_rm *rm)
     free(rm->resident);
     free(rm->q);
     free(rm->uv);
+    free(rm->obbv);
+    free(rm->sseg);
+    free(rm->seg);
     free(rm);
 }
 
 /* Builds the approximations of every edge.  Returns NULL on invalid input
  * (node id out of range, non-positive resolution without a sample count,
  * a sample count below 2) or when memory runs out. */
-orc_rm *orc_rm_build(const orc_robot *rob, int64_t n_nodes, const double *q, int64_t n_edges,
-                     const int64_t *edge_uv, double resolution, int samples_per_edge,
-                     int64_t n_slots, int threads)
+orc_rm *orc_rm_build_ex(const orc_robot *rob, int64_t n_nodes, const double *q, int64_t n_edges,
+                        const int64_t *edge_uv, double resolution, int samples_per_edge, int64_t n_slots,
+                        int threads, int outer_obb, int inner_splines, double spline_tol)
 {
     if (!rob || n_edges < 0 || n_slots < 0) return NULL;
+    if (inner_splines && !(spline_tol >= 0.0 && spline_tol < 1.0)) return NULL;
     if (samples_per_edge == 1 || samples_per_edge < 0) return NULL;
     if (samples_per_edge == 0 && !(resolution > 0.0)) return NULL;
     for (int64_t e = 0; e < 2 * n_edges; ++e)
@@ -508,6 +831,26 @@ orc_rm *orc_rm_build(const orc_robot *rob, int64_t n_nodes, const double *q, int
     rm->outer = (int32_t *)calloc((size_t)n_edges + 1, sizeof(int32_t));
     rm->inner = (int32_t *)calloc((size_t)n_edges + 1, sizeof(int32_t));
     rm->M = n_slots;
+    rm->obb = outer_obb != 0;
+    rm->spl = inner_splines != 0;
+    rm->tol = spline_tol;
+    rm->nb = n_bodies(rob);
+    for (int b = 0; b < rm->nb; ++b) rm->bhas[b] = 0;
+    for (int i = 0; i < B; ++i) rm->bhas[body_of(rob, i)] = 1;
+    if (rm->obb) {
+        rm->obbv = (double *)malloc(sizeof(double) * (size_t)(n_edges * rm->nb * obb_len(D) + 1));
+        if (!rm->obbv) {
+            orc_rm_free(rm);
+            return NULL;
+        }
+    }
+    if (rm->spl) {
+        rm->sseg = (int64_t *)calloc((size_t)(n_edges * B + 1), sizeof(int64_t));
+        if (!rm->sseg) {
+            orc_rm_free(rm);
+            return NULL;
+        }
+    }
     rm->resident = (double *)malloc(sizeof(double) * (size_t)(n_slots * 6 + 1));
     rm->q = (double *)malloc(sizeof(double) * (size_t)(n_nodes * rob->dof + 1));
     rm->uv = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_edges * 2 + 1));
@@ -533,7 +876,25 @@ orc_rm *orc_rm_build(const orc_robot *rob, int64_t n_nodes, const double *q, int
         return NULL;
     }
     run_build_pass(rm, q, edge_uv, resolution, samples_per_edge, 1, threads);
+    if (rm->spl) {
+        for (int64_t k = 0; k < n_edges * B; ++k) rm->sseg[k + 1] += rm->sseg[k];
+        rm->seg = (double *)malloc(sizeof(double) * (size_t)(rm->sseg[n_edges * B] * (2 * D + 1) + 1));
+        if (!rm->seg) {
+            orc_rm_free(rm);
+            return NULL;
+        }
+        run_build_pass(rm, q, edge_uv, resolution, samples_per_edge, 2, threads);
+    }
     return rm;
+}
+
+/* the capsule and sample-copy forms of Sec. 4.2's approximations */
+orc_rm *orc_rm_build(const orc_robot *rob, int64_t n_nodes, const double *q, int64_t n_edges,
+                     const int64_t *edge_uv, double resolution, int samples_per_edge,
+                     int64_t n_slots, int threads)
+{
+    return orc_rm_build_ex(rob, n_nodes, q, n_edges, edge_uv, resolution, samples_per_edge, n_slots,
+                           threads, 0, 0, 0.0);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -565,14 +926,38 @@ static int copies_meet(const orc_rm *rm, int64_t e, int i, const double *box)
     return 0;
 }
 
+/* some kept spline segment of sphere i meets the box */
+static int splines_meet(const orc_rm *rm, int64_t e, int i, const double *box)
+{
+    int B = rm->rob.B, D = rm->rob.D;
+    for (int64_t k = rm->sseg[e * B + i]; k < rm->sseg[e * B + i + 1]; ++k) {
+        const double *g = rm->seg + k * (2 * D + 1);
+        if (segbox_fmin(D, g, g + D, box, box + 3) <= g[2 * D] * g[2 * D]) return 1;
+    }
+    return 0;
+}
+
+/* the oriented box of body b of edge e meets the box */
+static int body_obb_meets(const orc_rm *rm, int64_t e, int b, const double *box)
+{
+    int D = rm->rob.D;
+    if (!rm->bhas[b]) return 0;
+    const double *o = rm->obbv + (e * rm->nb + b) * obb_len(D);
+    return obb_box_meet(D, o, o + D, o + D + D * D, box, box + 3);
+}
+
 /* C and S of one (edge, box) pair, sphere by sphere:
- *   C = some capsule meets the box;
- *   S = for some sphere i, its capsule meets the box and a copy of sphere i
- *       meets it.
- * Every copy of sphere i lies inside capsule i (the inflation delta_i bounds
- * the centre's distance from the chord), so the conjunction never changes S
- * in exact arithmetic; it makes S imply C, and the copies of a sphere whose
- * capsule misses need no test. */
+ *   C = for some sphere i, its capsule meets the box (and, with the oriented
+ *       boxes, so does the box of sphere i's body);
+ *   S = for some sphere i, what C asks of sphere i holds and a copy of
+ *       sphere i (a spline segment of sphere i, with the splines) meets it.
+ * Every copy of sphere i, and every spline segment, lies inside capsule i
+ * (the inflation delta_i bounds the centre's distance from the chord) and
+ * inside the box of its body, so the conjunction never changes S in exact
+ * arithmetic; it makes S imply C, and the inner parts of a sphere whose
+ * outer parts miss need no test.  With the oriented boxes the outer
+ * approximation is the union over spheres of capsule_i intersected with the
+ * box of sphere i's body: still a superset of the swept volume. */
 void orc_rm_pair(const orc_rm *rm, int64_t e, const double *box, int32_t *C, int32_t *S)
 {
     const orc_robot *r = &rm->rob;
@@ -581,8 +966,9 @@ void orc_rm_pair(const orc_rm *rm, int64_t e, const double *box, int32_t *C, int
     if (!box_present(r->D, box)) return;
     for (int i = 0; i < r->B; ++i) {
         if (!capsule_meets(rm, e, i, box)) continue;
+        if (rm->obb && !body_obb_meets(rm, e, body_of(r, i), box)) continue;
         *C = 1;
-        if (copies_meet(rm, e, i, box)) {
+        if (rm->spl ? splines_meet(rm, e, i, box) : copies_meet(rm, e, i, box)) {
             *S = 1;
             return;
         }
@@ -1018,6 +1404,52 @@ void orc_rm_centres(const orc_rm *rm, int64_t e, double *out)
 void orc_rm_capsule_radius(const orc_rm *rm, int64_t e, double *out)
 {
     memcpy(out, rm->capR + e * rm->rob.B, sizeof(double) * (size_t)rm->rob.B);
+}
+
+/* oriented box of body b of edge e: centre [D], axes [D][D], half-extents
+ * [D]; returns 0 without writing when the roadmap has no boxes or the body
+ * carries no sphere */
+int orc_rm_obb(const orc_rm *rm, int64_t e, int b, double *c, double *u, double *h)
+{
+    int D = rm->rob.D;
+    if (!rm->obb || b < 0 || b >= rm->nb || !rm->bhas[b]) return 0;
+    const double *o = rm->obbv + (e * rm->nb + b) * obb_len(D);
+    memcpy(c, o, sizeof(double) * D);
+    memcpy(u, o + D, sizeof(double) * D * D);
+    memcpy(h, o + D + D * D, sizeof(double) * D);
+    return 1;
+}
+
+/* spline segments of sphere i of edge e, [K][2D + 1] (A, B, rho) into out
+ * (may be NULL); returns K, or -1 when the roadmap has no splines */
+int64_t orc_rm_spline(const orc_rm *rm, int64_t e, int i, double *out)
+{
+    int B = rm->rob.B, D = rm->rob.D;
+    if (!rm->spl) return -1;
+    int64_t k0 = rm->sseg[e * B + i], k1 = rm->sseg[e * B + i + 1];
+    if (out) memcpy(out, rm->seg + k0 * (2 * D + 1), sizeof(double) * (size_t)((k1 - k0) * (2 * D + 1)));
+    return k1 - k0;
+}
+
+/* the building blocks, for the tests */
+void orc_jacobi_eigen(int D, const double *a, double *v)
+{
+    double A[3][3], V[3][3];
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) A[r][c] = a[r * D + c];
+    jacobi_eigen(D, A, V);
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) v[r * D + c] = V[r][c];
+}
+
+int orc_obb_box_meet(int D, const double *c, const double *u, const double *h, const double *box)
+{
+    return obb_box_meet(D, c, u, h, box, box + 3);
+}
+
+int64_t orc_sphere_spline(int D, const double *pts, int64_t n, double rad, double eta, double tol, double *out)
+{
+    return sphere_spline(D, pts, D, n, rad, eta, tol, out);
 }
 
 void orc_rm_counters(const orc_rm *rm, int32_t *outer, int32_t *inner)

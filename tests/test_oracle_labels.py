@@ -42,7 +42,10 @@ def test_one_edge_golden(oracle_lib, case):
     rob = _robot(case["robot"])
     q = np.array(case["nodes"], dtype=float)
     rm = oracle_lib.Roadmap(rob, q, np.array([[0, 1]]), case["resolution"],
-                            case["samples_per_edge"], n_slots=1, threads=1)
+                            case["samples_per_edge"], n_slots=1, threads=1,
+                            outer_obb=bool(case.get("outer_obb", 0)),
+                            inner_splines=bool(case.get("inner_splines", 0)),
+                            spline_tol=case.get("spline_tol", 0.25))
     box = np.array(case["box"], dtype=float)
     C, S = rm.pair(0, box)
     assert (C, S) == (case["expect"]["C"], case["expect"]["S"])
