@@ -275,6 +275,23 @@ rgg_status rgg_batch_destroy(rgg_batch *b);
  * the convenience form of the three calls above.  Blocks until done. */
 rgg_status rgg_update_batch(rgg_context *ctx, int32_t n, const rgg_update_req *reqs, void *stream);
 
+/* For callers that cannot allocate memory (code that must not call
+ * hipMalloc, such as tight serving loops or harnesses that forbid it): the
+ * batched update of rgg_update_batch, computing the same results, with the
+ * request table in a fixed device array that the library holds (one per
+ * device, up to 256 requests, 99 KiB, kept until the process ends)
+ * instead of a batch created per call.  Calls no allocator: no hipMalloc,
+ * hipFree, pinned or pageable host allocation, graph or event creation.
+ * Arguments as rgg_update_batch (device pointers in reqs, queued on
+ * `stream`); blocks until the update is done.  Errors: RGG_E_INVALID_ARG
+ * for n outside 1..256 (the table's capacity), a null pointer, a repeated
+ * roadmap, another device or a request that does not match its roadmap,
+ * with nothing queued; RGG_E_DEVICE.  Every context of a device shares that
+ * device's table, which keeps the last call's rows; calls from one process
+ * are serialised by the library (each waits for the previous to finish),
+ * and nothing in the table needs to start at zero. */
+rgg_status rgg_update_batch_noalloc(rgg_context *ctx, int32_t n, const rgg_update_req *reqs, void *stream);
+
 /* Autotuner of the work decomposition (Sec. 4.3 sizes grid cells by what
  * one kernel can process; here the choice is made by measurement).  The
  * candidates are the roadmap's current configuration, every combination

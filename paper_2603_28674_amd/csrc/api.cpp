@@ -10,6 +10,7 @@
 #include <chrono>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <thread>
@@ -375,7 +376,13 @@ rgg_status rgg_context_create(int device, rgg_context **out)
     HIP_OR_FAIL(hipGetDeviceCount(&n), "hipGetDeviceCount");
     if (device < 0 || device >= n) return fail(RGG_E_INVALID_ARG, "device %d out of range (%d devices)", device, n);
     HIP_OR_FAIL(hipSetDevice(device), "hipSetDevice");
-    *out = new rgg_context{device};
+    // the fixed scratch of rgg_update_batch_noalloc: each device holds its
+    // own copy of the array, at its own address, found with that device
+    // current
+    void *scratch = nullptr;
+    HIP_OR_FAIL(batch_scratch_address(&scratch), "hipGetSymbolAddress(batch scratch)");
+    if (!scratch) return fail(RGG_E_DEVICE, "the batch scratch has no device address");
+    *out = new rgg_context{device, scratch};
     return RGG_OK;
 }
 
@@ -1039,6 +1046,73 @@ rgg_status rgg_update_batch(rgg_context *ctx, int32_t n, const rgg_update_req *r
     }
     rgg_batch_destroy(b);
     return st;
+}
+
+rgg_status rgg_update_batch_noalloc(rgg_context *ctx, int32_t n, const rgg_update_req *reqs, void *stream)
+{
+    if (!ctx || !reqs) return fail(RGG_E_INVALID_ARG, "null argument");
+    if (n < 1 || n > kMaxBatch)
+        return fail(RGG_E_INVALID_ARG, "n = %d, allowed 1..%d (the size of the fixed request table)", n, kMaxBatch);
+    for (int32_t k = 0; k < n; ++k) {
+        const rgg_update_req &q = reqs[k];
+        if (!q.rm) return fail(RGG_E_INVALID_ARG, "request %d names no roadmap", k);
+        if (q.rm->device != ctx->device) return fail(RGG_E_INVALID_ARG, "roadmap %d is on another device", k);
+        for (int32_t j = 0; j < k; ++j)
+            if (reqs[j].rm == q.rm) return fail(RGG_E_INVALID_ARG, "request %d repeats the roadmap of request %d", k, j);
+        if (q.rm->dv.chunk < 1 || q.rm->dv.chunk > item_edges_max())
+            return fail(RGG_E_INVALID_ARG, "roadmap %d has work items of %d edges", k, q.rm->dv.chunk);
+        if (q.m != q.rm->dv.M || (q.m > 0 && (!q.d_old || !q.d_new)) || !q.d_result || q.gray_cap < 0)
+            return fail(RGG_E_INVALID_ARG, "bad request %d", k);
+    }
+    HIP_OR_FAIL(hipSetDevice(ctx->device), "hipSetDevice");
+    hipStream_t s = (hipStream_t)stream;
+    // The host side of the table is static too; the lock also keeps calls of
+    // this process from overlapping on the device scratch, which every
+    // context of the device shares.
+    static std::mutex mu;
+    static BatchReq h_tab[kMaxBatch];
+    static int32_t h_grp[kMaxBatch];
+    std::lock_guard<std::mutex> lock(mu);
+    BatchReq *d_tab = (BatchReq *)ctx->batch_scratch;
+    int32_t *d_grp = (int32_t *)((char *)ctx->batch_scratch + kBatchTableBytes);
+    // rows grouped by kernel variant (dimension, precision), as rgg_batch_create
+    BatchGroup groups[4];
+    int n_groups = 0, row = 0, tile = 0, wtile = 0;
+    bool any_grid = false;
+    for (int D = 2; D <= 3; ++D)
+        for (int mixed = 0; mixed <= 1; ++mixed) {
+            BatchGroup g = {D, mixed, row, 0};
+            for (int32_t k = 0; k < n; ++k) {
+                const rgg_update_req &q = reqs[k];
+                if (q.rm->dv.D != D || q.rm->dv.mixed != mixed) continue;
+                BatchReq &t = h_tab[row];
+                t.rm = q.rm->dv;
+                t.a = {q.d_old, q.d_new, q.d_labels, q.d_gray, q.d_gray ? q.gray_cap : 0, q.d_result};
+                t.tile0 = tile;
+                t.wtile0 = wtile;
+                tile += q.rm->dv.ntiles;
+                wtile += q.rm->dv.ntiles + 1;
+                any_grid = any_grid || q.rm->dv.ncells > 1;
+                h_grp[row] = row;
+                ++row;
+                ++g.count;
+            }
+            if (g.count) groups[n_groups++] = g;
+        }
+    for (int32_t k = 0; k < n; ++k) {
+        rgg_status st = order_after_previous(reqs[k].rm, s);
+        if (st != RGG_OK) return st;
+    }
+    HIP_OR_FAIL(hipMemcpyAsync(d_tab, h_tab, sizeof(BatchReq) * n, hipMemcpyHostToDevice, s), "copy batch table");
+    HIP_OR_FAIL(hipMemcpyAsync(d_grp, h_grp, sizeof(int32_t) * n, hipMemcpyHostToDevice, s), "copy batch rows");
+    HIP_OR_FAIL(launch_batch(s, d_tab, d_grp, n, groups, n_groups, any_grid, tile, wtile), "batch launch");
+    for (int32_t k = 0; k < n; ++k) {
+        rgg_status st = finish_update(reqs[k].rm, s);
+        if (st != RGG_OK) return st;
+    }
+    // the next call rewrites the static tables
+    HIP_OR_FAIL(hipStreamSynchronize(s), "batched update");
+    return RGG_OK;
 }
 
 rgg_status rgg_tune(rgg_roadmap *rm, int64_t m, const rgg_box *obstacles_a, int32_t n_b,

@@ -32,6 +32,9 @@ using rgg::hip_fail;
 
 struct rgg_context {
     int device;
+    // device address of the library's fixed batch scratch on `device`
+    // (rgg_update_batch_noalloc), looked up once when the context opens
+    void *batch_scratch = nullptr;
 };
 
 struct rgg_roadmap {

@@ -2032,6 +2032,17 @@ hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp
     return err;
 }
 
+// The request table of rgg_update_batch_noalloc.  Host code never passes the
+// array's name to a kernel or a copy: it uses the address that
+// batch_scratch_address returns for the current device.
+static __device__ __align__(256) unsigned char scratch[kBatchScratchBytes];
+
+hipError_t batch_scratch_address(void **ptr)
+{
+    *ptr = nullptr;
+    return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
 hipError_t launch_batch(hipStream_t s, const BatchReq *tab, const int32_t *grp, int n, const BatchGroup *groups,
                         int n_groups, bool any_grid, int n_tiles, int n_wtiles)
 {

@@ -119,6 +119,15 @@ struct BatchReq {
 
 constexpr int kMaxBatch = 256;     // requests per batched launch
 
+// Fixed device scratch of rgg_update_batch_noalloc: one batched update's
+// request table (kMaxBatch rows) followed by its row list.  The array lives
+// in the library's code object, one copy per device, so that entry point
+// allocates nothing.
+constexpr size_t kBatchTableBytes = (sizeof(BatchReq) * kMaxBatch + 255) / 256 * 256;
+constexpr size_t kBatchScratchBytes = kBatchTableBytes + sizeof(int32_t) * kMaxBatch;
+// Device address of that scratch on the current device (hipGetSymbolAddress).
+hipError_t batch_scratch_address(void **ptr);
+
 // The kernels of a batched update of distinct roadmaps, appended to `g` as a
 // chain after `dep` (may be null); *last receives the final node.  `tab` is
 // the device table of the n requests (groups of one kernel variant listed in

@@ -130,7 +130,8 @@ RESULT_BYTES = C.sizeof(rgg_update_result)
 EXPORTS = ["rgg_context_create", "rgg_context_destroy", "rgg_build", "rgg_destroy",
            "rgg_roadmap_info_get", "rgg_update", "rgg_update_async", "rgg_graph_create",
            "rgg_graph_launch", "rgg_graph_destroy", "rgg_batch_create", "rgg_batch_launch",
-           "rgg_batch_launch_graph", "rgg_batch_destroy", "rgg_update_batch", "rgg_server_start",
+           "rgg_batch_launch_graph", "rgg_batch_destroy", "rgg_update_batch", "rgg_update_batch_noalloc",
+           "rgg_server_start",
            "rgg_server_submit", "rgg_server_poll", "rgg_server_stop", "rgg_labels", "rgg_gray_list",
            "rgg_timing_enable", "rgg_timing_read", "rgg_tune", "rgg_batch_tune", "rgg_save", "rgg_load",
            "rgg_validate", "rgg_validate_async",
@@ -165,6 +166,7 @@ def lib():
         "rgg_batch_launch_graph": (I32, [P, P, P]),
         "rgg_batch_destroy": (I32, [P]),
         "rgg_update_batch": (I32, [P, I32, P, P]),
+        "rgg_update_batch_noalloc": (I32, [P, I32, P, P]),
         "rgg_server_start": (I32, [P, P, C.POINTER(P)]),
         "rgg_server_submit": (I32, [P, P, C.POINTER(C.c_uint64)]),
         "rgg_server_poll": (I32, [P, C.c_uint64, I32, C.POINTER(I32), P, C.POINTER(C.c_double)]),
@@ -383,6 +385,11 @@ def rgg_batch_destroy(b):
 def rgg_update_batch(ctx, reqs, stream):
     arr = (rgg_update_req * len(reqs))(*reqs)
     _check(lib().rgg_update_batch(ctx, len(reqs), arr, C.c_void_p(stream)))
+
+
+def rgg_update_batch_noalloc(ctx, reqs, stream):
+    arr = (rgg_update_req * len(reqs))(*reqs)
+    _check(lib().rgg_update_batch_noalloc(ctx, len(reqs), arr, C.c_void_p(stream)))
 
 
 def rgg_server_start(ctx, n_streams=0, max_queue=0, max_batch=0, pool_bytes=0):
