@@ -57,11 +57,13 @@ def parse():
     p.add_argument("--batched-cell-size", type=float, default=0.0)
     p.add_argument("--no-serving", action="store_true",
                    help="skip the serving measurement (16 resident roadmaps, Poisson requests)")
-    p.add_argument("--serving-seconds", type=float, default=2.0)
+    p.add_argument("--serving-seconds", type=float, default=10.0)
     p.add_argument("--no-tune", action="store_true",
                    help="keep the built work decomposition instead of running the autotuner")
     p.add_argument("--no-other-configs", action="store_true",
                    help="skip the planar (FP64 and FP32) and arm measurements")
+    p.add_argument("--no-second-forms", action="store_true",
+                   help="skip the oriented-box and spline forms of the approximations")
     p.add_argument("--no-validate", action="store_true",
                    help="skip the full validation of the last update's gray list")
     p.add_argument("--cpu-validate-edges", type=int, default=2000,
@@ -74,6 +76,53 @@ def parse():
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+# Host cores the CPU legs use: the box gives one GPU's job a 16-core share of
+# its host, whatever the CPU count it reports.
+CPU_SHARE = 16
+
+
+def cpu_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(CPU_SHARE, n))
+
+
+def cpu_host():
+    """The host CPU: its model (/proc/cpuinfo), the CPUs the OS reports and
+    the ones this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = None
+    return {"model": model, "cpus_reported": os.cpu_count(), "cpus_allowed": aff,
+            "threads_used": cpu_threads(), "share_per_gpu": CPU_SHARE}
+
+
+def roofline(kernel, bytes_per_launch, kernel_ms, note=None):
+    """The HBM roofline of one kernel: algorithmic bytes per launch over its
+    HIP-event launch time, against 8 TB/s."""
+    if not kernel_ms or kernel_ms <= 0:
+        return None
+    achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "kernel": kernel, "bytes_per_launch": float(bytes_per_launch),
+           "kernel_ms": float(kernel_ms)}
+    if note:
+        out["note"] = note
+    return out
 
 
 def measured_traffic(kernel):
@@ -109,7 +158,7 @@ def batched_planar(a):
     import torch
     from paper_2603_28674_amd import rgg, synth
     K, W = a.batched_steps, 2
-    n_rounds = W + 5 * K
+    n_rounds = W + 6 * K
     t0 = time.perf_counter()
     ws = synth.batch_of_planar(seed=3, n_updates=n_rounds)
     log(f"[bench] batched: generated {len(ws)} roadmaps, {sum(w.n_edges for w in ws)} edges "
@@ -201,6 +250,22 @@ def batched_planar(a):
     # round's time (every stage): a lower bound for the batched item kernel
     rb = float(np.mean(round_bytes))
     achieved = rb / (out["batched"]["ms_per_round"] * 1e-3) / 1e9
+    # the stages' own times, HIP events on the stream between the kernels
+    rgg.rgg_batch_timing_enable(batch, True)
+    rgg.rgg_batch_timing_read(batch)
+    item_bytes = []
+    for _ in range(K):
+        batched(u)
+        u += 1
+        torch.cuda.synchronize()
+        item_bytes.append(sum(rgg.result_from_tensor(b[3]).test_bytes for b in bufs))
+    sms, nt = rgg.rgg_batch_timing_read(batch)
+    rgg.rgg_batch_timing_enable(batch, False)
+    ok = ok and all(rgg.result_from_tensor(b[3]).status == 0 for b in bufs)
+    stage = {"diff": sms[0] / nt, "cells": sms[1] / nt, "item": sms[3] / nt, "fp64_pass": sms[4] / nt,
+             "labels": sms[5] / nt}
+    final_labels = [b[1].cpu().numpy() for b in bufs]
+    cpu = None if a.no_cpu_baseline else batched_cpu_baseline(ws, final_labels, u, a.seed)
     rgg.rgg_batch_destroy(batch)
     for g in gs:
         g.close()
@@ -218,18 +283,53 @@ def batched_planar(a):
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                            "note": "classify bytes of all roadmaps per round over the round's wall time "
                                    "(all stages, pipelined rounds): a lower bound for k_item32_batch"},
+        "stage_ms_per_round": stage,
+        "roofline": roofline("k_item32_batch<2>", float(np.mean(item_bytes)), stage["item"],
+                             "classify bytes of the 64 roadmaps of a round over the batched item kernel's "
+                             "HIP-event time"),
+        "cpu_baseline": cpu,
         "status_ok": ok,
     }
 
 
-def plain_config(ctx, w, precision, cell_size, K, W, what, do_tune=True):
+def batched_cpu_baseline(ws, gpu_final, n_rounds, seed, per_roadmap=400):
+    """The FP64 oracle over the batch's whole round sequence on a sample of
+    every roadmap's edges (host cores of one GPU's share); also checks the
+    GPU's final labels on those edges."""
+    import oracle
+    rng = np.random.default_rng(seed + 2000)
+    threads = cpu_threads()
+    tot, dt, match = 0, 0.0, True
+    for w, lab in zip(ws, gpu_final):
+        idx = np.sort(rng.choice(w.n_edges, size=min(per_roadmap, w.n_edges), replace=False))
+        o = oracle.Roadmap(w.robot, w.q, w.edges[idx], w.resolution, w.samples_per_edge, w.n_slots, threads)
+        t0 = time.perf_counter()
+        prev = w.absent()
+        ol = None
+        for u in range(n_rounds):
+            ol, _ = o.update(prev, w.boxes[u], threads=threads)
+            prev = w.boxes[u]
+        dt += time.perf_counter() - t0
+        tot += len(idx) * n_rounds
+        match = match and bool(np.array_equal(ol, lab[idx]))
+    return {"value": tot / dt, "unit": "edges/s", "cores": threads, "kind": "oracle",
+            "sample": f"{per_roadmap} edges of each of the {len(ws)} roadmaps (all of the smaller ones), "
+                      f"{n_rounds} incremental updates each, FP64, {threads} threads",
+            "labels_match_gpu_on_sample": match, "host": cpu_host()}
+
+
+def plain_config(ctx, w, precision, cell_size, K, W, what, do_tune=True, kernel=None, cpu=None, item_edges=0,
+                 **forms):
     """A further workload on the plain per-update path (rgg_update_async on
-    one stream): pipelined throughput over K updates, then the latency of K
-    more, one at a time.  ``w`` must hold at least 1 + W + 2K updates."""
+    one stream): pipelined throughput over K updates, the latency of K more,
+    one at a time, then K more with the stages timed by HIP events (the
+    classify kernel's roofline).  ``w`` must hold at least 1 + W + 3K
+    updates.  ``cpu``: edges of the oracle's sample (the CPU baseline), or
+    None."""
     import torch
     from paper_2603_28674_amd import rgg
     dev = torch.device("cuda:0")
-    g = rgg.Roadmap.from_workload(ctx, w, precision=precision, cell_size=cell_size)
+    g = rgg.Roadmap.from_workload(ctx, w, precision=precision, cell_size=cell_size, item_edges=item_edges, **forms)
     info = g.info()
     E = w.n_edges
     states = torch.from_numpy(np.stack([w.absent()] + w.boxes)).to(dev)
@@ -260,18 +360,44 @@ def plain_config(ctx, w, precision, cell_size, K, W, what, do_tune=True):
         upd(u)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e6)
-    results = [rgg.result_from_tensor(res[u]) for u in range(1 + W, 1 + W + 2 * K)]
+    rgg.rgg_timing_enable(g.h, True)
+    rgg.rgg_timing_read(g.h)
+    for u in range(1 + W + 2 * K, 1 + W + 3 * K):
+        upd(u)
+    torch.cuda.synchronize()
+    ms, n_timed = rgg.rgg_timing_read(g.h)
+    rgg.rgg_timing_enable(g.h, False)
+    timed = [rgg.result_from_tensor(res[u]) for u in range(1 + W + 2 * K, 1 + W + 3 * K)]
+    results = [rgg.result_from_tensor(res[u]) for u in range(1 + W, 1 + W + 3 * K)]
+    final = labels.cpu().numpy()
     g.close()
     stats = {k: float(np.mean([getattr(r, k) for r in results]))
-             for k in ("n_changed", "n_pairs", "n_outer_hits", "n_rechecked", "n_gray")}
-    return {"workload": what, "edges": E, "obstacle_slots": w.n_slots,
-            "precision": "fp64" if precision == rgg.RGG_PREC_FP64 else "fp32+fp64 re-test",
-            "cell_size": info["cell_size"], "item_edges": info["item_edges"], "autotune": tuned,
-            "updates": K,
-            "edges_per_s": E * K / wall, "ms_per_update": wall / K * 1e3,
-            "latency_p50_us": float(np.percentile(lat, 50)),
-            "latency_p99_us": float(np.percentile(lat, 99)),
-            "per_update": stats, "status_ok": all(r.status == 0 for r in results)}
+             for k in ("n_changed", "n_pairs", "n_outer_hits", "n_rechecked", "n_gray", "test_bytes")}
+    stage = {"diff": ms[0] / n_timed, "cells": ms[1] / n_timed, "classify": ms[3] / n_timed,
+             "fp64_pass": ms[4] / n_timed, "labels": ms[5] / n_timed}
+    out = {"workload": what, "edges": E, "obstacle_slots": w.n_slots,
+           "precision": "fp64" if precision == rgg.RGG_PREC_FP64 else "fp32+fp64 re-test",
+           "cell_size": info["cell_size"], "item_edges": info["item_edges"], "autotune": tuned,
+           "device_bytes": info["device_bytes"], "updates": K,
+           "edges_per_s": E * K / wall, "ms_per_update": wall / K * 1e3,
+           "latency_p50_us": float(np.percentile(lat, 50)),
+           "latency_p99_us": float(np.percentile(lat, 99)),
+           "stage_ms_per_update": stage,
+           "per_update": stats, "status_ok": all(r.status == 0 for r in results)}
+    if kernel:
+        out["roofline"] = roofline(kernel, float(np.mean([r.test_bytes for r in timed])), stage["classify"])
+    if cpu:
+        n_up = 1 + W + 3 * K - 1
+        rng = np.random.default_rng(97)
+        idx = np.sort(rng.choice(E, size=min(cpu, E), replace=False))
+        threads = cpu_threads()
+        rate, lab = oracle_rate(w, idx, n_up, threads, **forms)
+        out["cpu_baseline"] = {"value": rate, "unit": "edges/s", "cores": threads, "kind": "oracle",
+                               "sample": f"{len(idx)} of {E} edges, {n_up} incremental updates, FP64, "
+                                         f"{threads} threads",
+                               "labels_match_gpu_on_sample": bool(np.array_equal(lab, final[idx])),
+                               "host": cpu_host()}
+    return out
 
 
 def other_configs(a):
@@ -281,17 +407,37 @@ def other_configs(a):
     K, W = a.steps, a.warmup
     ctx = rgg.rgg_context_create(0)
     out = {}
-    w = synth.planar_rigid(n_updates=1 + W + 2 * K)
+    w = synth.planar_rigid(n_updates=1 + W + 3 * K)
     what = ("planar rigid-body roadmap (4 disks, 2000 nodes, k=10, configurations every 0.05, "
             "50 boxes, 5 moved per update)")
     t = not a.no_tune
-    out["planar_fp64"] = plain_config(ctx, w, rgg.RGG_PREC_FP64, 0.0, K, W, what, t)
-    out["planar_fp32"] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, 0.0, K, W, what, t)
+    cpu = None if a.no_cpu_baseline else 2000
+    out["planar_fp64"] = plain_config(ctx, w, rgg.RGG_PREC_FP64, 0.0, K, W, what, t, "k_item64<2>", cpu)
+    out["planar_fp32"] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, 0.0, K, W, what, t, "k_item32<2>")
+    if not a.no_second_forms:
+        # about 100 configurations per edge: the splines replace most copies
+        pl = out["planar_fp32"]
+        cell = pl["cell_size"] if pl["cell_size"] is not None and np.isfinite(pl["cell_size"]) else -1.0
+        out["planar_splines"] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, cell, K, W, what + ", spline form",
+                                             False, "k_item32<2>", None if a.no_cpu_baseline else 2000,
+                                             item_edges=pl["item_edges"], inner_splines=True)
     log("[bench] arm workload")
-    w = synth.planar_arm(n_updates=1 + W + 2 * K)
+    w = synth.planar_arm(n_updates=1 + W + 3 * K)
     what = ("planar 7-link arm (3 spheres per link, 100k nodes, k=8, 20 configurations/edge, "
             "300 boxes, 30 moved per update)")
-    out["arm_fp32"] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, 0.0, K, W, what, t)
+    cpu = None if a.no_cpu_baseline else 20000
+    out["arm_fp32"] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, 0.0, K, W, what, t, "k_item32<2>", cpu)
+    if not a.no_second_forms:
+        # the second forms of Sec. 4.2 on the arm, in the decomposition the
+        # capsule form was tuned to
+        arm = out["arm_fp32"]
+        cell = arm["cell_size"] if arm["cell_size"] is not None and np.isfinite(arm["cell_size"]) else -1.0
+        cpu = None if a.no_cpu_baseline else 4000
+        for name, forms in (("arm_obb", dict(outer_obb=True)),
+                            ("arm_obb_splines", dict(outer_obb=True, inner_splines=True))):
+            log(f"[bench] {name}")
+            out[name] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, cell, K, W, what + f", {name[4:]} form",
+                                     False, "k_item32<2>", cpu, item_edges=arm["item_edges"], **forms)
     rgg.rgg_context_destroy(ctx)
     return out
 
@@ -299,10 +445,12 @@ def other_configs(a):
 def serving(a):
     """The serving configuration: 16 device-resident roadmaps (8 spatial
     rigid-body, 8 planar arm; edge counts log-uniform in [1e4, 5e5]) behind
-    the request server (4 streams, batches of up to 64, 64 MiB box pool).
-    Open-loop Poisson arrivals at 100, 1000 and 10000 requests/s, each moving
-    U{1..50} boxes of a random roadmap.  Latency is the server's, from submit
-    to completion; edges/s counts the edges of every completed request."""
+    the request server (4 streams, batches of up to 64, the box pool sized
+    from the free device memory).  Open-loop Poisson arrivals at 100, 1000
+    and 10000 requests/s, each moving U{1..50} boxes of a random roadmap.
+    Latency is the server's, from submit to completion, split into the wait
+    for a launch (queue) and the launch to completion (service); edges/s
+    counts the edges of every completed request."""
     import torch
     from paper_2603_28674_amd import rgg, synth
     t0 = time.perf_counter()
@@ -335,7 +483,8 @@ def serving(a):
                  "one_cell": sum(r["cell_size"] is None for r in chosen)}
         log(f"[bench] serving: tuned in {tuned['seconds']:.1f}s")
     vers = [torch.zeros(w.n_edges, dtype=torch.uint8, device=dev) for w in ws]
-    srv = rgg.rgg_server_start(ctx, n_streams=4, max_batch=64, pool_bytes=64 << 20)
+    srv = rgg.rgg_server_start(ctx, n_streams=4, max_batch=64, pool_bytes=0)
+    srv_info = rgg.rgg_server_info(srv)
     rng = np.random.default_rng(a.seed + 77)
     cur = [w.boxes[0] for w in ws]
     levels = []
@@ -361,17 +510,28 @@ def serving(a):
                     busy += 1
                     time.sleep(20e-6)
             tickets.append((t, ws[r].n_edges))
-        lat, edges = [], 0
+        lat, que, svc, bsz, edges = [], [], [], [], 0
         for t, e in tickets:
-            done, res, l = rgg.rgg_server_poll(srv, t, wait=True)
+            done, res, tm = rgg.rgg_server_poll_timing(srv, t, wait=True)
             ok = ok and res.status == 0
-            lat.append(l)
+            lat.append(tm["latency_us"])
+            que.append(tm["queue_us"])
+            svc.append(tm["service_us"])
+            bsz.append(tm["batch_size"])
             edges += e
         wall = time.perf_counter() - t0
-        lat = np.array(lat)
+        lat, que, svc, bsz = np.array(lat), np.array(que), np.array(svc), np.array(bsz)
+        tail = lat >= np.percentile(lat, 99)
         return {"offered_rate": rate, "requests": len(tickets), "achieved_rate": len(tickets) / wall,
                 "edges_per_s": edges / wall, "latency_p50_us": float(np.percentile(lat, 50)),
                 "latency_p99_us": float(np.percentile(lat, 99)), "latency_mean_us": float(lat.mean()),
+                "queue_p50_us": float(np.percentile(que, 50)), "queue_p99_us": float(np.percentile(que, 99)),
+                "service_p50_us": float(np.percentile(svc, 50)), "service_p99_us": float(np.percentile(svc, 99)),
+                "batch_size_mean": float(bsz.mean()),
+                "slowest_1pct": {"requests": int(tail.sum()), "latency_mean_us": float(lat[tail].mean()),
+                                 "queue_mean_us": float(que[tail].mean()),
+                                 "service_mean_us": float(svc[tail].mean()),
+                                 "batch_size_mean": float(bsz[tail].mean())},
                 "busy_retries": busy}
 
     for rate in (100.0, 1000.0, 10000.0):
@@ -389,7 +549,7 @@ def serving(a):
                         "[1e4, 5e5]; Poisson requests moving U{1..50} boxes; FP32 + FP64 re-test",
             "roadmaps": len(ws), "edges": int(sum(w.n_edges for w in ws)), "seconds_per_rate": a.serving_seconds,
             "autotune": tuned,
-            "server": {"n_streams": 4, "max_batch": 64, "pool_bytes": 64 << 20}, "rates": levels,
+            "server": srv_info, "rates": levels,
             "non_lazy": non_lazy,
             "status_ok": bool(ok)}
 
@@ -414,12 +574,12 @@ def C_void(x):
     return ctypes.c_void_p(x)
 
 
-def oracle_rate(w, idx, n_updates, threads):
+def oracle_rate(w, idx, n_updates, threads, **forms):
     """Edges/s of the FP64 oracle's incremental update over updates
     1..n_updates on the edges idx; returns (rate, final labels)."""
     import oracle
     o = oracle.Roadmap(w.robot, w.q, w.edges[idx], w.resolution, w.samples_per_edge,
-                       w.n_slots, threads)
+                       w.n_slots, threads, **forms)
     o.update(w.absent(), w.boxes[0], threads=threads)
     t0 = time.perf_counter()
     lab = None
@@ -430,13 +590,14 @@ def oracle_rate(w, idx, n_updates, threads):
 
 def cpu_baseline(w, gpu_labels_final, sample_edges, n_updates, seed, single_edges):
     """The FP64 oracle, incremental mode, on a sample of the roadmap's edges
-    (every edge by default), over the same obstacle sequence, on the host's
-    cores (at most 16); also checks the GPU's final labels on that sample.
-    Beside it, the oracle on one thread over a smaller sample."""
+    (every edge by default), over the same obstacle sequence, on one GPU's
+    share of the host's cores (16, or fewer if the process may use fewer);
+    also checks the GPU's final labels on that sample.  Beside it, the
+    oracle on one thread over a smaller sample."""
     rng = np.random.default_rng(seed + 1000)
     E = w.n_edges
     idx = np.sort(rng.choice(E, size=min(sample_edges, E), replace=False))
-    threads = min(16, os.cpu_count() or 1)
+    threads = cpu_threads()
     rate, lab = oracle_rate(w, idx, n_updates, threads)
     out = {
         "value": rate,
@@ -446,6 +607,7 @@ def cpu_baseline(w, gpu_labels_final, sample_edges, n_updates, seed, single_edge
         "sample": f"{len(idx)} of {E} edges, {n_updates} incremental updates, FP64, "
                   f"{threads} threads",
         "labels_match_gpu_on_sample": bool(np.array_equal(lab, gpu_labels_final[idx])),
+        "host": cpu_host(),
     }
     if single_edges > 0:
         idx1 = np.sort(rng.choice(E, size=min(single_edges, E), replace=False))
@@ -507,7 +669,7 @@ def validate_pass(a, torch, rgg, g, w, stream, gray, res_last, last, reps=5):
         ids = gray[:n].cpu().numpy()
         rng = np.random.default_rng(a.seed)
         sample = np.sort(rng.choice(ids, size=min(n, a.cpu_validate_edges), replace=False))
-        threads = min(os.cpu_count() or 1, 16)
+        threads = cpu_threads()
         o = oracle.Roadmap(w.robot, w.q, w.edges[sample], w.resolution, w.samples_per_edge, w.n_slots, threads)
         o.classify(w.boxes[last])
         t0 = time.perf_counter()
@@ -599,6 +761,8 @@ def main():
     # before each update (more than the 256 MB Infinity Cache and the L2s)
     flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
     lat_cold = []
+    rgg.rgg_timing_enable(g.h, True)
+    rgg.rgg_timing_read(g.h)
     for u in range(first + 3 * K, first + 4 * K):
         flush.fill_(float(u))
         torch.cuda.synchronize()
@@ -606,10 +770,13 @@ def main():
         upd(u)
         torch.cuda.synchronize()
         lat_cold.append((time.perf_counter() - t1) * 1e6)
+    ms_cold, n_cold = rgg.rgg_timing_read(g.h)
+    rgg.rgg_timing_enable(g.h, False)
     del flush
     lat_cold = np.array(lat_cold)
     results += [rgg.result_from_tensor(res[u]) for u in range(first + 2 * K, first + 4 * K)]
     assert all(r.status == 0 for r in results), "update failed"
+    cold_bytes = float(np.mean([r.test_bytes for r in results[3 * K:4 * K]]))
     final_labels = labels.cpu().numpy()
     last = first + 4 * K - 1
 
@@ -708,6 +875,9 @@ def main():
                      "kernel": "k_item32<3>", "bytes_per_launch": test_bytes,
                      "kernel_ms": test_ms, "copy_GBps": copy_gbs,
                      "frac_of_copy": achieved / copy_gbs},
+        "roofline_cold": roofline("k_item32<3>", cold_bytes, ms_cold[3] / max(n_cold, 1),
+                                  "the same kernel with the caches flushed before every update (a 1 GiB "
+                                  "buffer rewritten: more than the 256 MB Infinity Cache)"),
         "work_rates": {"pairs_per_s": stats_tp["n_pairs"] * K / wall,
                        "outer_hits_per_s": stats_tp["n_outer_hits"] * K / wall,
                        "classify_bytes_per_s": stats_tp["test_bytes"] * K / wall},
@@ -718,6 +888,20 @@ def main():
         line["cpu_baseline"] = cpu_baseline(w, final_labels, a.cpu_sample_edges, last, a.seed,
                                             a.cpu_single_edges)
     g.close()
+    if not a.no_second_forms:
+        # the second forms of Sec. 4.2 on the same roadmap and updates, in the
+        # decomposition the capsule form was tuned to
+        cell2 = info["cell_size"] if np.isfinite(info["cell_size"]) else -1.0
+        forms_out = {}
+        what = line["config"]["workload"]
+        cpu = None if a.no_cpu_baseline else 2000
+        for name, forms in (("capsules", dict()), ("obb", dict(outer_obb=True)),
+                            ("splines", dict(inner_splines=True)),
+                            ("obb_splines", dict(outer_obb=True, inner_splines=True))):
+            log(f"[bench] spatial, {name} form")
+            forms_out[name] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, cell2, K, W, what + f", {name} form",
+                                           False, "k_item32<3>", cpu, item_edges=info["item_edges"], **forms)
+        line["second_forms"] = forms_out
     if not a.no_other_configs:
         log("[bench] planar and arm workloads")
         line["other_workloads"] = other_configs(a)

@@ -20,10 +20,15 @@
  *   robot       a union of spheres on a planar rigid body (SE2: x, y, theta),
  *               a spatial rigid body (SE3: x, y, z, qw, qx, qy, qz) or a planar
  *               serial arm (joint angles q0..q_{L-1});
- *   inner       the robot's spheres at every configuration of cfg(e);
+ *   inner       the robot's spheres at every configuration of cfg(e), or
+ *               (rgg_build_opts.inner_splines, Sec. 4.2) each sphere's
+ *               shortcut spline through its centres, thickened to stay in
+ *               the swept volume;
  *   outer       per sphere, a capsule around the chord of its centre path,
  *               radius r_i + delta_i with delta_i = max|p''| / 8 (the
- *               linear-interpolation error bound of the centre path);
+ *               linear-interpolation error bound of the centre path), and
+ *               optionally (rgg_build_opts.outer_obb, Sec. 4.2) intersected
+ *               with an oriented box around its body's sweep;
  *   obstacles   closed axis-aligned boxes.
  *
  * Conventions for every entry point:
@@ -146,6 +151,33 @@ typedef struct {
                                      0 = 256.
                                      rgg_tune may change it.  Any value gives
                                      the same labels.                           */
+    int32_t outer_obb;            /* 1: the second outer form of Sec. 4.2 as
+                                     well: an oriented box per robot body (the
+                                     whole robot for SE2/SE3, a link for the
+                                     arm) on the principal axes of the body's
+                                     sphere centres along the edge, widened to
+                                     hold the continuous sweep; a sphere's
+                                     outer part is its capsule intersected with
+                                     its body's box, tested by the separating-
+                                     axis theorem in binary64.  0: capsules
+                                     only.                                      */
+    int32_t inner_splines;        /* 1: the second inner form of Sec. 4.2: each
+                                     sphere's spline through its centres,
+                                     simplified by Agarwal et al.'s greedy
+                                     shortcuts (error err <= spline_tol * r_i),
+                                     each kept segment a capsule of radius
+                                     r_i - err - delta_i / n^2, which stays in
+                                     the swept volume, replaces the sphere's
+                                     copies.  0: copies                         */
+    double spline_tol;            /* shortcut tolerance, a fraction of the
+                                     sphere's radius in (0, 1); 0 selects 0.05 */
+    int64_t mem_budget;           /* device bytes the roadmap may hold; 0 = the
+                                     free device memory.  A roadmap whose arrays
+                                     would need more (rgg_roadmap_info's
+                                     device_bytes) is refused with
+                                     RGG_E_OUT_OF_MEMORY before anything is
+                                     allocated; a budget above the free memory
+                                     admits up to the free memory               */
 } rgg_build_opts;
 
 /* Written by the device at the end of every update (rgg_update_async) and
@@ -270,6 +302,14 @@ rgg_status rgg_batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *stre
 /* The same batched update as one launch of the batch's captured graph. */
 rgg_status rgg_batch_launch_graph(rgg_batch *b, const rgg_update_req *reqs, void *stream);
 rgg_status rgg_batch_destroy(rgg_batch *b);
+/* Stage timing of rgg_batch_launch (not of the graph form), with HIP events
+ * on the launch's stream: rgg_batch_timing_read returns the summed
+ * milliseconds of each stage over the launches since the last read and
+ * resets them: ms[0] diff, ms[1] grid cells, ms[2] 0, ms[3] the item kernels,
+ * ms[4] the binary64 pass, ms[5] labels and gray lists.  It waits for the
+ * timed launches. */
+rgg_status rgg_batch_timing_enable(rgg_batch *b, int32_t on);
+rgg_status rgg_batch_timing_read(rgg_batch *b, double ms[6], int64_t *n_launches);
 
 /* One batched update of n distinct roadmaps (create, launch, wait, destroy):
  * the convenience form of the three calls above.  Blocks until done. */
@@ -431,7 +471,12 @@ typedef struct {
     int32_t max_queue;            /* queued requests; 0 = 4096                  */
     int32_t max_batch;            /* requests per batch; 0 = 64, max 256        */
     int32_t reserved;             /* must be 0                                  */
-    int64_t pool_bytes;           /* device staging for boxes; 0 = 64 MiB       */
+    int64_t pool_bytes;           /* device staging for the requests' boxes, the
+                                     memory that admits requests (a request waits
+                                     until its boxes fit); 0 = admission by free
+                                     device memory: 1/64 of the memory free when
+                                     the server starts, within [16 MiB, 256 MiB].
+                                     A value above the free memory is refused   */
 } rgg_server_opts;
 
 typedef struct {
@@ -465,6 +510,27 @@ rgg_status rgg_server_submit(rgg_server *srv, const rgg_server_req *req, uint64_
  * an unknown ticket. */
 rgg_status rgg_server_poll(rgg_server *srv, uint64_t ticket, int32_t wait, int32_t *done,
                            rgg_update_result *result, double *latency_us);
+
+/* Where a request's time went (host clock, microseconds). */
+typedef struct {
+    double latency_us;            /* submission to completion                   */
+    double queue_us;              /* submission to its batch's launch: waiting
+                                     for a free stream slot, pool room or the
+                                     roadmap's earlier request                  */
+    double service_us;            /* launch to completion: the batch's copies and
+                                     kernels on the device (with the roadmaps'
+                                     earlier updates it waits for) and the
+                                     worker noticing the finish                 */
+    int32_t batch_size;           /* requests in its batch                      */
+    int32_t reserved;
+} rgg_request_timing;
+
+/* rgg_server_poll with the request's time split into queue and service. */
+rgg_status rgg_server_poll_timing(rgg_server *srv, uint64_t ticket, int32_t wait, int32_t *done,
+                                  rgg_update_result *result, rgg_request_timing *timing);
+/* The server's effective options (the pool size chosen when pool_bytes was
+ * 0) and the free device memory it saw when it started. */
+rgg_status rgg_server_info(rgg_server *srv, rgg_server_opts *opts, int64_t *free_at_start);
 /* Finishes every queued request, then stops the worker and frees the server. */
 rgg_status rgg_server_stop(rgg_server *srv);
 
@@ -492,6 +558,18 @@ rgg_status rgg_debug_geometry(const rgg_roadmap_desc *roadmap, const rgg_robot *
                               const rgg_build_opts *opts, int64_t e0, int64_t e1,
                               int64_t *n_configs, double *centres, double *capsule,
                               float *aabb);
+
+/* Host-only view of the second forms (opts->outer_obb, opts->inner_splines)
+ * of edge range [e0, e1), computed exactly as rgg_build does, for tests.
+ * obb [e1-e0][bodies][2D + D*D] (centre, axes as rows, half-extents; zero
+ * for a body without spheres; bodies = 1, or n_links for the arm) when
+ * opts->outer_obb; n_segments [(e1-e0) * B] the spline segments kept for
+ * each (edge, sphere) and segments [sum][2D+1] (A, B, rho) when
+ * opts->inner_splines.  Any output may be NULL (query n_segments first to
+ * size segments). */
+rgg_status rgg_debug_second_forms(const rgg_roadmap_desc *roadmap, const rgg_robot *robot,
+                                  const rgg_build_opts *opts, int64_t e0, int64_t e1, double *obb,
+                                  int64_t *n_segments, double *segments);
 
 /* Host-only view of rgg_load, for tests: reads the roadmap file `path` and
  * runs every check rgg_load runs before it uses the device (header, sample

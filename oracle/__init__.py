@@ -200,7 +200,7 @@ class Roadmap:
     """Roadmap geometry plus per-edge counters, built by the oracle."""
 
     def __init__(self, robot, q, edges, resolution=0.0, samples_per_edge=0, n_slots=0, threads=0,
-                 outer_obb=False, inner_splines=False, spline_tol=0.25):
+                 outer_obb=False, inner_splines=False, spline_tol=0.05):
         self.robot = robot if isinstance(robot, Robot) else Robot(robot)
         self._q = _f64(q)
         self._uv = np.ascontiguousarray(edges, dtype=np.int64)
@@ -304,7 +304,7 @@ class Roadmap:
         return o, i
 
 
-def from_workload(w, threads=0, outer_obb=False, inner_splines=False, spline_tol=0.25):
+def from_workload(w, threads=0, outer_obb=False, inner_splines=False, spline_tol=0.05):
     """Oracle roadmap for a ``synth.Workload``."""
     return Roadmap(w.robot, w.q, w.edges, w.resolution, w.samples_per_edge, w.n_slots, threads,
                    outer_obb=outer_obb, inner_splines=inner_splines, spline_tol=spline_tol)

@@ -340,12 +340,20 @@ struct rgg_batch {
     std::vector<BatchGroup> groups;
     bool any_grid = false;
     int tiles = 0, wtiles = 0;
+    // stage timing (rgg_batch_timing_*)
+    bool timing = false;
+    std::vector<BatchTiming> t_pool, t_pending;
+    double ms_acc[6] = {0, 0, 0, 0, 0, 0};
+    int64_t timed = 0;
 
     ~rgg_batch()
     {
         hipSetDevice(device);
         for (int k = 0; k < kRing; ++k)
             if (done[k] && used[k]) hipEventSynchronize(done[k]);
+        for (auto *v : {&t_pool, &t_pending})
+            for (BatchTiming &t : *v)
+                for (hipEvent_t e : t.ev) hipEventDestroy(e);
         // the roadmaps' last updates have completed: nothing left to wait for
         for (rgg_roadmap *rm : rms) {
             for (int k = 0; k < kRing; ++k)
@@ -400,6 +408,76 @@ struct RoadmapParams {
 };
 
 rgg_status hip_ok(hipError_t e, const char *what) { return e == hipSuccess ? RGG_OK : hip_fail(e, what); }
+
+// Device bytes make_roadmap allocates for g, grid and p (each array at least
+// one element, as rgg_roadmap::alloc gives it).
+int64_t device_bytes_needed(const HostGeometry &g, const HostGrid &grid, const RoadmapParams &p)
+{
+    int64_t total = 0;
+    auto add = [&](size_t count, size_t size) { total += (int64_t)(std::max<size_t>(1, count) * size); };
+    const int64_t E = g.E, M = p.M;
+    const int B = g.B;
+    add(g.soff.size(), 8);
+    add(g.samp.size(), 8);
+    add(g.cap.size(), 8);
+    add(g.aabb.size(), 4);
+    add((size_t)B, 8);
+    add((size_t)B, 4);
+    if (p.mixed) {
+        add(g.samp.size(), 4);
+        add(g.cap.size(), 4);
+    }
+    if (!g.obb.empty()) {
+        add(g.obb.size(), 8);
+        add((size_t)g.n_bodies, 8);
+    }
+    if (!g.sseg.empty()) {
+        add(g.sseg.size(), 4);
+        add(g.seg.size(), 8);
+        if (p.mixed) add(g.seg.size(), 4);
+    }
+    const int64_t ncells = (int64_t)grid.dim[0] * grid.dim[1] * grid.dim[2];
+    add(grid.start.size(), 4);
+    add(grid.edges.size(), 4);
+    add((size_t)((ncells + 31) / 32), 4);
+    add((size_t)kStatBlocks * (size_t)((grid.items_cap + kStatBlocks - 1) / kStatBlocks), 4);
+    add((size_t)grid.items_cap, sizeof(int2));
+    const int64_t ntiles = std::max<int64_t>(1, (E + kLabelTile - 1) / kLabelTile);
+    const int32_t rc_cap = p.retest_capacity > 0 ? p.retest_capacity : kRcCap;
+    add((size_t)E, sizeof(int2));
+    add((size_t)M, sizeof(rgg_box));
+    add((size_t)(2 * M), sizeof(ChgEntry));
+    add((size_t)kStatBlocks * rc_cap, sizeof(int2));
+    add((size_t)kStatBlocks, 4);
+    add((size_t)kStatBlocks, 4);
+    add((size_t)kStatBlocks * kStats, 8);
+    add((size_t)ntiles + 1, 4);
+    add((size_t)ntiles, 8);
+    add(1, sizeof(Ctl));
+    add((size_t)(2 * M), sizeof(rgg_box));
+    add(1, sizeof(rgg_update_result));
+    add((size_t)E, 1);
+    add((size_t)E, 8);
+    add(1, sizeof(VRobot));
+    add(g.motion.size(), 8);
+    add(g.delta.size(), 8);
+    return total;
+}
+
+// Admission of a roadmap by device memory: refused, before anything is
+// allocated, when its arrays would exceed `budget` bytes (0: the free device
+// memory) or the free device memory.
+rgg_status admit_roadmap(int64_t need, int64_t budget)
+{
+    size_t free_b = 0, total_b = 0;
+    HIP_OR_FAIL(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    const int64_t allowed = budget > 0 ? std::min<int64_t>(budget, (int64_t)free_b) : (int64_t)free_b;
+    if (need > allowed)
+        return fail(RGG_E_OUT_OF_MEMORY, "the roadmap needs %lld bytes of device memory; %lld allowed (%s)",
+                    (long long)need, (long long)allowed,
+                    budget > 0 && budget <= (int64_t)free_b ? "mem_budget" : "free device memory");
+    return RGG_OK;
+}
 
 // Device arrays, scratch and state of a roadmap from its host geometry and
 // grid.  resident and cnt (may be null) are the obstacle slots and counters
@@ -470,6 +548,39 @@ rgg_status make_roadmap(rgg_context *ctx, const HostGeometry &g, const HostGrid 
         if ((st = rm->upload(&c32, tmp.data(), ncap, "binary32 capsules")) != RGG_OK) return guard(st);
         dv.samp32 = s32;
         dv.cap32 = c32;
+    }
+    // the second forms (Sec. 4.2), when built
+    dv.mode = (g.obb.empty() ? 0 : kModeObb) | (g.sseg.empty() ? 0 : kModeSplines);
+    dv.nbody = g.n_bodies;
+    if (!g.obb.empty()) {
+        std::vector<unsigned long long> bs((size_t)g.n_bodies, 0ull);
+        for (int i = 0; i < B; ++i) bs[g.body[i]] |= 1ull << i;
+        double *o64;
+        unsigned long long *d_bs;
+        if ((st = rm->upload(&o64, g.obb.data(), g.obb.size(), "oriented boxes")) != RGG_OK) return guard(st);
+        if ((st = rm->upload(&d_bs, bs.data(), bs.size(), "body spheres")) != RGG_OK) return guard(st);
+        dv.obb64 = o64;
+        dv.body_sph = d_bs;
+    }
+    if (!g.sseg.empty()) {
+        if (g.sseg.back() > (int64_t)INT32_MAX)
+            return guard(fail(RGG_E_OUT_OF_MEMORY, "%lld spline segments; at most 2^31 - 1", (long long)g.sseg.back()));
+        std::vector<int32_t> off(g.sseg.begin(), g.sseg.end());
+        int32_t *d_off;
+        double *g64;
+        if ((st = rm->upload(&d_off, off.data(), off.size(), "spline offsets")) != RGG_OK) return guard(st);
+        if ((st = rm->upload(&g64, g.seg.data(), g.seg.size(), "binary64 spline segments")) != RGG_OK)
+            return guard(st);
+        dv.sseg = d_off;
+        dv.seg64 = g64;
+        if (mixed) {
+            std::vector<float> tmp(g.seg.size());
+            for (size_t i = 0; i < g.seg.size(); ++i) tmp[i] = (float)g.seg[i];
+            float *g32;
+            if ((st = rm->upload(&g32, tmp.data(), tmp.size(), "binary32 spline segments")) != RGG_OK)
+                return guard(st);
+            dv.seg32 = g32;
+        }
     }
     if ((st = install_grid(rm, grid, p.chunk)) != RGG_OK) return guard(st);
     // state and scratch
@@ -583,6 +694,7 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
 
     const RoadmapParams p = {opts->n_obstacle_slots, opts->precision == RGG_PREC_FP32_RECHECK, opts->band_rel,
                              opts->retest_capacity, chunk};
+    if ((st = admit_roadmap(device_bytes_needed(g, grid, p), opts->mem_budget)) != RGG_OK) return st;
     rgg_roadmap *rm = nullptr;
     if ((st = make_roadmap(ctx, g, grid, p, nullptr, nullptr, &rm)) != RGG_OK) return st;
     rm->info.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -924,6 +1036,9 @@ rgg_status rgg_batch_create(rgg_context *ctx, int32_t n, rgg_roadmap *const *rms
         seen[rms[k]] = k;
         if (rms[k]->dv.chunk < 1 || rms[k]->dv.chunk > item_edges_max())
             return fail(RGG_E_INVALID_ARG, "roadmap %d has work items of %d edges", k, rms[k]->dv.chunk);
+        if (rms[k]->dv.mode != 0)
+            return fail(RGG_E_UNSUPPORTED, "roadmap %d uses the oriented boxes or splines; batches take the "
+                        "capsule and copy forms", k);
     }
     HIP_OR_FAIL(hipSetDevice(ctx->device), "hipSetDevice");
     std::unique_ptr<rgg_batch> b(new rgg_batch());
@@ -999,11 +1114,22 @@ static rgg_status batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *s
         if (st != RGG_OK) return st;
     }
     HIP_OR_FAIL(hipMemcpyAsync(b->d_tab, h, sizeof(BatchReq) * b->n, hipMemcpyHostToDevice, s), "copy batch table");
+    BatchTiming *tm = nullptr;
+    if (b->timing && !graph) {
+        if (b->t_pool.empty()) {
+            BatchTiming t = {};
+            for (hipEvent_t &e : t.ev) HIP_OR_FAIL(hipEventCreate(&e), "hipEventCreate");
+            b->t_pool.push_back(t);
+        }
+        b->t_pending.push_back(b->t_pool.back());
+        b->t_pool.pop_back();
+        tm = &b->t_pending.back();
+    }
     if (graph)
         HIP_OR_FAIL(hipGraphLaunch(b->exec, s), "hipGraphLaunch");
     else
         HIP_OR_FAIL(launch_batch(s, b->d_tab, b->d_grp, b->n, b->groups.data(), (int)b->groups.size(), b->any_grid,
-                                 b->tiles, b->wtiles),
+                                 b->tiles, b->wtiles, tm),
                     "batch launch");
     HIP_OR_FAIL(hipEventRecord(b->done[slot], s), "hipEventRecord");
     b->used[slot] = true;
@@ -1022,6 +1148,36 @@ rgg_status rgg_batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *stre
 rgg_status rgg_batch_launch_graph(rgg_batch *b, const rgg_update_req *reqs, void *stream)
 {
     return batch_launch(b, reqs, stream, true);
+}
+
+rgg_status rgg_batch_timing_enable(rgg_batch *b, int32_t on)
+{
+    if (!b) return fail(RGG_E_INVALID_ARG, "null batch");
+    b->timing = on != 0;
+    return RGG_OK;
+}
+
+rgg_status rgg_batch_timing_read(rgg_batch *b, double ms[6], int64_t *n_launches)
+{
+    if (!b) return fail(RGG_E_INVALID_ARG, "null batch");
+    HIP_OR_FAIL(hipSetDevice(b->device), "hipSetDevice");
+    for (BatchTiming &t : b->t_pending) {
+        HIP_OR_FAIL(hipEventSynchronize(t.ev[t.n]), "hipEventSynchronize");
+        for (int k = 0; k < t.n; ++k) {
+            float m = 0.0f;
+            HIP_OR_FAIL(hipEventElapsedTime(&m, t.ev[k], t.ev[k + 1]), "hipEventElapsedTime");
+            b->ms_acc[t.stage[k]] += m;
+        }
+        b->timed++;
+        b->t_pool.push_back(t);
+    }
+    b->t_pending.clear();
+    if (ms)
+        for (int k = 0; k < 6; ++k) ms[k] = b->ms_acc[k];
+    if (n_launches) *n_launches = b->timed;
+    for (double &m : b->ms_acc) m = 0.0;
+    b->timed = 0;
+    return RGG_OK;
 }
 
 rgg_status rgg_batch_destroy(rgg_batch *b)
@@ -1061,6 +1217,9 @@ rgg_status rgg_update_batch_noalloc(rgg_context *ctx, int32_t n, const rgg_updat
             if (reqs[j].rm == q.rm) return fail(RGG_E_INVALID_ARG, "request %d repeats the roadmap of request %d", k, j);
         if (q.rm->dv.chunk < 1 || q.rm->dv.chunk > item_edges_max())
             return fail(RGG_E_INVALID_ARG, "roadmap %d has work items of %d edges", k, q.rm->dv.chunk);
+        if (q.rm->dv.mode != 0)
+            return fail(RGG_E_UNSUPPORTED, "roadmap %d uses the oriented boxes or splines; batches take the "
+                        "capsule and copy forms", k);
         if (q.m != q.rm->dv.M || (q.m > 0 && (!q.d_old || !q.d_new)) || !q.d_result || q.gray_cap < 0)
             return fail(RGG_E_INVALID_ARG, "bad request %d", k);
     }
@@ -1255,7 +1414,7 @@ namespace {
 // Roadmap files: a header, the binary64 geometry, the state, and an FNV-1a
 // 64-bit checksum of every preceding byte.  Host byte order.
 constexpr char kMagic[8] = {'R', 'G', 'G', 'M', 'A', 'P', '0', '1'};
-constexpr uint32_t kFileVersion = 2;
+constexpr uint32_t kFileVersion = 3;
 
 struct FileHeader {
     char magic[8];
@@ -1364,6 +1523,18 @@ rgg_status rgg_save(rgg_roadmap *rm, const char *path)
     if ((st = read_back(&vrob, vd.rob, 1, "validation robot")) != RGG_OK) return st;
     if ((st = read_back(&vmot, vd.motion, (size_t)(E * vd.vstride), "edge motions")) != RGG_OK) return st;
     if ((st = read_back(&vdel, vd.delta, (size_t)(E * dv.B), "chord deviations")) != RGG_OK) return st;
+    // the second forms, when built
+    std::vector<double> obb, seg;
+    std::vector<int32_t> sseg32;
+    if (dv.mode & kModeObb)
+        if ((st = read_back(&obb, dv.obb64, (size_t)(E * dv.nbody * obb_words(dv.D)), "oriented boxes")) != RGG_OK)
+            return st;
+    if (dv.mode & kModeSplines) {
+        if ((st = read_back(&sseg32, dv.sseg, (size_t)(E * dv.B + 1), "spline offsets")) != RGG_OK) return st;
+        if ((st = read_back(&seg, dv.seg64, (size_t)sseg32.back() * (2 * dv.D + 1), "spline segments")) != RGG_OK)
+            return st;
+    }
+    std::vector<int64_t> sseg(sseg32.begin(), sseg32.end());
     FileHeader h = {};
     memcpy(h.magic, kMagic, sizeof kMagic);
     h.version = kFileVersion;
@@ -1393,6 +1564,11 @@ rgg_status rgg_save(rgg_roadmap *rm, const char *path)
     out.put(vrob.data(), sizeof(VRobot));
     out.put(vmot.data(), sizeof(double) * vmot.size());
     out.put(vdel.data(), sizeof(double) * vdel.size());
+    const int32_t forms[2] = {dv.mode, dv.nbody};
+    out.put(forms, sizeof forms);
+    out.put(obb.data(), sizeof(double) * obb.size());
+    out.put(sseg.data(), sizeof(int64_t) * sseg.size());
+    out.put(seg.data(), sizeof(double) * seg.size());
     const uint64_t sum = out.sum.h;
     out.put(&sum, sizeof sum);
     const bool flushed = out.ok && fflush(out.f) == 0;
@@ -1481,6 +1657,46 @@ static rgg_status read_roadmap_file(const char *path, LoadedFile *L)
     }
     in.get(g.motion.data(), sizeof(double) * g.motion.size());
     in.get(g.delta.data(), sizeof(double) * g.delta.size());
+    // the second forms: mode bits and body count, then the boxes and splines
+    int32_t forms[2] = {0, 0};
+    in.get(forms, sizeof forms);
+    if (!in.ok) return fail(RGG_E_INVALID_ARG, "%s is truncated", path);
+    const int nb = vr.kind == RGG_PLANAR_ARM ? vr.L : 1;
+    if ((forms[0] & ~(kModeObb | kModeSplines)) != 0 || forms[1] != nb)
+        return fail(RGG_E_INVALID_ARG, "%s: inconsistent approximation forms", path);
+    g.n_bodies = nb;
+    g.body.assign((size_t)h.B, 0);
+    g.body_has.assign((size_t)nb, 0);
+    for (int i = 0; i < h.B; ++i) {
+        g.body[i] = vr.kind == RGG_PLANAR_ARM ? vr.link[i] : 0;
+        g.body_has[g.body[i]] = 1;
+    }
+    try {
+        if (forms[0] & kModeObb) {
+            g.obb.resize((size_t)(h.E * nb * obb_stride(h.D)));
+            in.get(g.obb.data(), sizeof(double) * g.obb.size());
+        }
+        if (forms[0] & kModeSplines) {
+            g.sseg.resize((size_t)(h.E * h.B + 1));
+            in.get(g.sseg.data(), sizeof(int64_t) * g.sseg.size());
+            if (!in.ok) return fail(RGG_E_INVALID_ARG, "%s is truncated", path);
+            // each sphere keeps between 0 and n segments (n + 1 configurations)
+            bool ok = g.sseg[0] == 0;
+            for (int64_t e = 0; ok && e < h.E; ++e) {
+                const int64_t n = (g.soff[(size_t)e + 1] - g.soff[(size_t)e]) / h.B - 1;
+                for (int i = 0; ok && i < h.B; ++i) {
+                    const int64_t k = g.sseg[(size_t)(e * h.B + i + 1)] - g.sseg[(size_t)(e * h.B + i)];
+                    ok = k >= 0 && k <= n;
+                }
+            }
+            if (!ok || g.sseg.back() > (int64_t)INT32_MAX)
+                return fail(RGG_E_INVALID_ARG, "%s: inconsistent spline offsets", path);
+            g.seg.resize((size_t)(g.sseg.back() * (2 * h.D + 1)));
+            in.get(g.seg.data(), sizeof(double) * g.seg.size());
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(RGG_E_OUT_OF_MEMORY, "host memory for %s", path);
+    }
     const uint64_t want = in.sum.h;
     uint64_t sum = 0;
     if (in.ok) in.get(&sum, sizeof sum);
@@ -1504,6 +1720,7 @@ rgg_status rgg_load(rgg_context *ctx, const char *path, rgg_roadmap **out)
     rgg_status st = build_grid(g, h.one_cell ? -1.0 : h.cell, h.chunk, &grid, &err);
     if (st != RGG_OK) return fail(st, "%s", err.c_str());
     const RoadmapParams p = {h.M, h.mixed != 0, (double)h.band_rel, h.retest_capacity, h.chunk};
+    if ((st = admit_roadmap(device_bytes_needed(g, grid, p), 0)) != RGG_OK) return st;
     rgg_roadmap *rm = nullptr;
     if ((st = make_roadmap(ctx, g, grid, p, L.resident.data(), L.cnt.data(), &rm)) != RGG_OK) return st;
     rm->info.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1518,6 +1735,27 @@ rgg_status rgg_debug_read_file(const char *path, int64_t *n_edges)
     rgg_status st = read_roadmap_file(path, &L);
     if (st != RGG_OK) return st;
     if (n_edges) *n_edges = L.h.E;
+    return RGG_OK;
+}
+
+rgg_status rgg_debug_second_forms(const rgg_roadmap_desc *rd, const rgg_robot *robot,
+                                  const rgg_build_opts *opts, int64_t e0, int64_t e1, double *obb,
+                                  int64_t *n_segments, double *segments)
+{
+    std::string err;
+    rgg_status st = validate_build_inputs(rd, robot, opts, &err);
+    if (st != RGG_OK) return fail(st, "%s", err.c_str());
+    if (e0 < 0 || e1 < e0 || e1 > rd->n_edges) return fail(RGG_E_INVALID_ARG, "bad edge range");
+    HostGeometry g;
+    st = build_geometry(rd, robot, opts, e0, e1, host_threads(opts->host_threads), &g, &err);
+    if (st != RGG_OK) return fail(st, "%s", err.c_str());
+    if (obb && !g.obb.empty()) memcpy(obb, g.obb.data(), sizeof(double) * g.obb.size());
+    if (!g.sseg.empty()) {
+        const int64_t n = g.E * g.B;
+        if (n_segments)
+            for (int64_t k = 0; k < n; ++k) n_segments[k] = g.sseg[k + 1] - g.sseg[k];
+        if (segments) memcpy(segments, g.seg.data(), sizeof(double) * g.seg.size());
+    }
     return RGG_OK;
 }
 

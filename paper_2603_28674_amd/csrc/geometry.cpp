@@ -216,6 +216,203 @@ void inflation(const rgg_robot *r, const Motion &m, double *out)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Second outer form (Sec. 4.2): an oriented box around each body's sweep.
+// A body is the robot (SE2, SE3) or one link (arm).  The box's axes are the
+// principal axes of the body's sphere centres over cfg(e), its extent along
+// axis u the range of u.c -+ (r_i + delta_i / n^2) over those centres: over
+// one step of length 1/n a centre stays within delta_i / n^2 of the chord of
+// its sampled ends, so the box holds the continuous sweep.  The binary64
+// steps (sums over configurations, then spheres; Jacobi rotations; the
+// extents) are one fixed order, so the boxes are a function of the inputs.
+// ---------------------------------------------------------------------------
+
+int body_index(const rgg_robot *r, int i) { return r->kind == RGG_PLANAR_ARM ? r->sphere_link[i] : 0; }
+int body_count(const rgg_robot *r) { return r->kind == RGG_PLANAR_ARM ? r->n_links : 1; }
+
+// Columns of ev: eigenvectors of the symmetric D x D matrix m (overwritten),
+// by cyclic Jacobi rotations (pairs (p, q), p < q; one sweep in 2-D, where
+// one rotation diagonalises, eight in 3-D).
+void principal_axes(int D, double m[3][3], double ev[3][3])
+{
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) ev[r][c] = r == c ? 1.0 : 0.0;
+    const int sweeps = D == 3 ? 8 : 1;
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int p = 0; p + 1 < D; ++p)
+            for (int q = p + 1; q < D; ++q) {
+                const double off = m[p][q];
+                if (off == 0.0) continue;
+                // tan of the angle that zeroes m[p][q]: the root of
+                // t^2 + 2 theta t - 1 of smaller magnitude
+                const double theta = (m[q][q] - m[p][p]) / (2.0 * off);
+                double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
+                if (theta < 0.0) t = -t;
+                const double c = 1.0 / sqrt(t * t + 1.0);
+                const double sn = t * c;
+                for (int r = 0; r < D; ++r) {
+                    if (r == p || r == q) continue;
+                    const double mp = m[r][p], mq = m[r][q];
+                    m[r][p] = c * mp - sn * mq;
+                    m[p][r] = m[r][p];
+                    m[r][q] = sn * mp + c * mq;
+                    m[q][r] = m[r][q];
+                }
+                m[p][p] = m[p][p] - t * off;
+                m[q][q] = m[q][q] + t * off;
+                m[p][q] = 0.0;
+                m[q][p] = 0.0;
+                for (int r = 0; r < D; ++r) {
+                    const double ep = ev[r][p], eq = ev[r][q];
+                    ev[r][p] = c * ep - sn * eq;
+                    ev[r][q] = sn * ep + c * eq;
+                }
+            }
+}
+
+// Box of body b: centres blk[(i*J + j)*S + d] (j = 0..nseg), bounds infl[B].
+// Writes centre[D], axes[D][D] (row k = axis k), half[D] to o; false (and
+// nothing written) when the body carries no sphere.
+bool body_box(const rgg_robot *r, int D, int b, const double *blk, int S, int64_t J, const double *infl,
+              double *o)
+{
+    const int B = r->n_spheres;
+    const int64_t nseg = J - 1;
+    double mean[3] = {0.0, 0.0, 0.0};
+    int64_t npts = 0;
+    for (int64_t j = 0; j < J; ++j)
+        for (int i = 0; i < B; ++i) {
+            if (body_index(r, i) != b) continue;
+            for (int d = 0; d < D; ++d) mean[d] = mean[d] + blk[(i * J + j) * S + d];
+            ++npts;
+        }
+    if (npts == 0) return false;
+    for (int d = 0; d < D; ++d) mean[d] = mean[d] / (double)npts;
+    double sc[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    for (int64_t j = 0; j < J; ++j)
+        for (int i = 0; i < B; ++i) {
+            if (body_index(r, i) != b) continue;
+            double dv[3];
+            for (int d = 0; d < D; ++d) dv[d] = blk[(i * J + j) * S + d] - mean[d];
+            for (int k = 0; k < D; ++k)
+                for (int l = k; l < D; ++l) sc[k][l] = sc[k][l] + dv[k] * dv[l];
+        }
+    for (int k = 1; k < D; ++k)
+        for (int l = 0; l < k; ++l) sc[k][l] = sc[l][k];
+    double ev[3][3];
+    principal_axes(D, sc, ev);
+    double *ctr = o, *ax = o + D, *half = o + D + D * D;
+    for (int k = 0; k < D; ++k)
+        for (int d = 0; d < D; ++d) ax[k * D + d] = ev[d][k];
+    const double n2 = (double)nseg * (double)nseg;
+    double mid[3];
+    for (int k = 0; k < D; ++k) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int64_t j = 0; j < J; ++j)
+            for (int i = 0; i < B; ++i) {
+                if (body_index(r, i) != b) continue;
+                double pr = 0.0;
+                for (int d = 0; d < D; ++d) pr = pr + ax[k * D + d] * blk[(i * J + j) * S + d];
+                const double eta = infl[i] / n2;
+                const double a = (pr - r->sphere_radius[i]) - eta, z = (pr + r->sphere_radius[i]) + eta;
+                if (a < lo) lo = a;
+                if (z > hi) hi = z;
+            }
+        mid[k] = 0.5 * (lo + hi);
+        half[k] = 0.5 * (hi - lo);
+    }
+    for (int d = 0; d < D; ++d) {
+        double acc = 0.0;
+        for (int k = 0; k < D; ++k) acc = acc + mid[k] * ax[k * D + d];
+        ctr[d] = acc;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Second inner form (Sec. 4.2): each sphere's spline through its centres,
+// simplified by Agarwal et al.'s greedy shortcuts.  From vertex a the
+// candidates b = a+2, a+4, a+8, ... (the last clamped to n) are accepted
+// while err(a, b), the largest distance of the skipped centres from the
+// segment [c_a, c_b], is at most tol * r; a bisection between the last
+// accepted and the first rejected candidate then finds an accepted b whose
+// successor is rejected.  The segment (a, b) becomes a capsule of radius
+// r - err(a, b) - delta / n^2, kept when that is not negative: each of its
+// points is within err(a, b) of the polyline and so within err(a, b) +
+// delta / n^2 of the sphere's centre path, which keeps the capsule inside
+// the swept sphere.
+// ---------------------------------------------------------------------------
+
+// squared distance from p to the segment [a, b]
+double seg_point_d2(int D, const double *p, const double *a, const double *b)
+{
+    double d[3], dd = 0.0, wd = 0.0;
+    for (int k = 0; k < D; ++k) {
+        d[k] = b[k] - a[k];
+        dd = dd + d[k] * d[k];
+        wd = wd + (p[k] - a[k]) * d[k];
+    }
+    double t = 0.0;
+    if (dd > 0.0) t = std::min(std::max(wd / dd, 0.0), 1.0);
+    double acc = 0.0;
+    for (int k = 0; k < D; ++k) {
+        const double g = (a[k] + t * d[k]) - p[k];
+        acc = acc + g * g;
+    }
+    return acc;
+}
+
+// err(a, b)^2 of the centres c + j * S
+double skip_err2(int D, const double *c, int S, int64_t a, int64_t b)
+{
+    double worst = 0.0;
+    for (int64_t m = a + 1; m < b; ++m) worst = std::max(worst, seg_point_d2(D, c + m * S, c + a * S, c + b * S));
+    return worst;
+}
+
+// Segments of the spline through c + j * S, j = 0..n, into out ([K][2D+1]:
+// A, B, rho; may be null); returns K.
+int64_t spline_segments(int D, const double *c, int S, int64_t n, double rad, double eta, double tol, double *out)
+{
+    const double lim = tol * rad;
+    const double lim2 = lim * lim;
+    int64_t a = 0, K = 0;
+    while (a < n) {
+        int64_t good = a + 1, bad = n + 1;   // (a, good) accepted, (a, bad) rejected or past the end
+        for (int64_t span = 2;; span *= 2) {
+            const int64_t b = std::min(a + span, n);
+            if (b <= good) break;
+            if (skip_err2(D, c, S, a, b) > lim2) {
+                bad = b;
+                break;
+            }
+            good = b;
+            if (b == n) break;
+        }
+        while (bad - good > 1 && bad <= n) {
+            const int64_t mid = good + (bad - good) / 2;
+            if (skip_err2(D, c, S, a, mid) <= lim2)
+                good = mid;
+            else
+                bad = mid;
+        }
+        const double rho = (rad - sqrt(skip_err2(D, c, S, a, good))) - eta;
+        if (rho >= 0.0) {
+            if (out) {
+                double *o = out + K * (2 * D + 1);
+                for (int k = 0; k < D; ++k) {
+                    o[k] = c[a * S + k];
+                    o[D + k] = c[good * S + k];
+                }
+                o[2 * D] = rho;
+            }
+            ++K;
+        }
+        a = good;
+    }
+    return K;
+}
+
 double pad_of(double x) { return ldexp(std::max(1.0, fabs(x)), -20); }
 
 bool finite_all(const double *p, int64_t n)
@@ -294,6 +491,11 @@ rgg_status validate_build_inputs(const rgg_roadmap_desc *rd, const rgg_robot *r,
     if (o->retest_capacity < 0 || o->retest_capacity > (1 << 20)) return bad("retest_capacity must be 0..2^20");
     if (o->item_edges < 0 || o->item_edges > 512) return bad("item_edges must be 0..512");
     if (std::isnan(o->cell_size)) return bad("cell_size is NaN");
+    if (o->mem_budget < 0) return bad("mem_budget must be 0 (the free device memory) or positive");
+    if (o->outer_obb != 0 && o->outer_obb != 1) return bad("outer_obb must be 0 or 1");
+    if (o->inner_splines != 0 && o->inner_splines != 1) return bad("inner_splines must be 0 or 1");
+    if (o->inner_splines && !(o->spline_tol >= 0.0 && o->spline_tol < 1.0))
+        return bad("spline_tol must be in [0, 1) (0 selects 0.05)");
     return RGG_OK;
 }
 
@@ -320,6 +522,7 @@ rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *r, const 
         g->rob_base[1] = r->base[1];
     }
     const int vstride = 2 * dof + 3;
+    const double tol = o->spline_tol > 0.0 ? o->spline_tol : kDefaultSplineTol;
     if (threads < 1) threads = 1;
     threads = (int)std::min<int64_t>(threads, std::max<int64_t>(E, 1));
 
@@ -356,6 +559,15 @@ rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *r, const 
         g->aabb.assign((size_t)(E * kAabbStride), 0.0f);
         g->motion.assign((size_t)(E * vstride), 0.0);
         g->delta.assign((size_t)(E * B), 0.0);
+        g->n_bodies = body_count(r);
+        g->body.assign((size_t)B, 0);
+        g->body_has.assign((size_t)g->n_bodies, 0);
+        for (int i = 0; i < B; ++i) {
+            g->body[i] = body_index(r, i);
+            g->body_has[g->body[i]] = 1;
+        }
+        if (o->outer_obb) g->obb.assign((size_t)(E * g->n_bodies * obb_stride(D)), 0.0);
+        if (o->inner_splines) g->sseg.assign((size_t)(E * B + 1), 0);
     } catch (const std::bad_alloc &) {
         *err = "host memory for the build";
         return RGG_E_OUT_OF_MEMORY;
@@ -385,6 +597,15 @@ rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *r, const 
             mv[2 * dof + 1] = m.half;
             mv[2 * dof + 2] = m.sin_half;
             for (int i = 0; i < B; ++i) g->delta[k * B + i] = infl[i];
+            if (o->outer_obb)
+                for (int b = 0; b < g->n_bodies; ++b)
+                    body_box(r, D, b, blk, S, J, infl, g->obb.data() + (k * g->n_bodies + b) * obb_stride(D));
+            if (o->inner_splines) {
+                const double n2 = (double)nseg * (double)nseg;
+                for (int i = 0; i < B; ++i)
+                    g->sseg[k * B + i + 1] = spline_segments(D, blk + i * J * S, S, nseg, r->sphere_radius[i],
+                                                             infl[i] / n2, tol, nullptr);
+            }
             double *cp = g->cap.data() + k * (2 * D + 1) * B;
             double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
             for (int i = 0; i < B; ++i) {
@@ -414,6 +635,27 @@ rgg_status build_geometry(const rgg_roadmap_desc *rd, const rgg_robot *r, const 
             bx[7] = 0.0f;
         }
     });
+    if (o->inner_splines) {
+        // pass 3: the spline segments, at the offsets their counts give
+        for (int64_t k = 0; k < E * B; ++k) g->sseg[k + 1] += g->sseg[k];
+        try {
+            g->seg.assign((size_t)(g->sseg[E * B] * (2 * D + 1)), 0.0);
+        } catch (const std::bad_alloc &) {
+            *err = "host memory for the splines";
+            return RGG_E_OUT_OF_MEMORY;
+        }
+        run([&](int64_t a, int64_t b) {
+            for (int64_t k = a; k < b; ++k) {
+                const int64_t P = g->soff[k + 1] - g->soff[k];
+                const int64_t J = P / B, nseg = J - 1;
+                const double *blk = g->samp.data() + S * g->soff[k];
+                const double n2 = (double)nseg * (double)nseg;
+                for (int i = 0; i < B; ++i)
+                    spline_segments(D, blk + i * J * S, S, nseg, r->sphere_radius[i], g->delta[k * B + i] / n2, tol,
+                                    g->seg.data() + g->sseg[k * B + i] * (2 * D + 1));
+            }
+        });
+    }
     return RGG_OK;
 }
 

@@ -535,6 +535,39 @@ __device__ bool copies_meet64(const RmDev &rm, const double *sb, int64_t P, cons
     return false;
 }
 
+// some kept spline segment of a sphere in m meets the box (binary64, one
+// wavefront: the spheres in turn, their segments across the lanes)
+template <int D>
+__device__ bool splines_meet64(const RmDev &rm, int64_t e, uint64_t m, const double *lo, const double *hi,
+                               unsigned long long *bytes)
+{
+    constexpr int W = 2 * D + 1;
+    const int lane = lane_id();
+    while (m) {
+        const int i = __ffsll((unsigned long long)m) - 1;
+        m &= m - 1;
+        const int64_t k = e * rm.B + i;
+        const int32_t k0 = rm.sseg[k], k1 = rm.sseg[k + 1];
+        for (int32_t j0 = k0; j0 < k1; j0 += 64) {
+            const int32_t j = j0 + lane;
+            bool hit = false;
+            if (j < k1) {
+                const double *g = rm.seg64 + (int64_t)j * W;
+                double A[D], Bq[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    A[d] = g[d];
+                    Bq[d] = g[D + d];
+                }
+                hit = segbox64<D>(A, Bq, lo, hi) <= g[2 * D] * g[2 * D];
+            }
+            *bytes += (unsigned long long)(min(64, k1 - j0) * W * 8);
+            if (__ballot(hit)) return true;
+        }
+    }
+    return false;
+}
+
 // ------------------------------------------------------------------------
 // k_item: one block per work item (grid cell c, a chunk of at most 256 of
 // its edges; the chunk size is the roadmap's work-item size).
@@ -577,7 +610,7 @@ constexpr int kEdgeCells = 64;            // pruning-grid cells an edge may visi
 static_assert(kWords == 4, "a pruning-grid cell holds one uint4 of entry bits");
 static_assert(kSubTile <= 128 && kItemCap <= 512, "a pair is (edge slot << 7) | staged entry in 16 bits");
 static_assert(kLocalCells * 4 == kWords * kItemCap, "the overlap words reuse the pruning grid's storage");
-static_assert(kOpenCap >= 2 * kRowCap + 1, "the rows fit the capsule queue's storage");
+static_assert(kOpenCap >= 3 * kRowCap + 1, "the rows fit the capsule queue's storage");
 
 __device__ inline int pe_slot(int v) { return v >> 7; }
 __device__ inline int pe_entry(int v) { return v & 127; }
@@ -618,6 +651,7 @@ struct ItemLds {
         struct {
             uint32_t row[kRowCap];        // pair << 6 | sphere
             uint32_t rcopy[kRowCap + 1];
+            uint32_t rbase[kRowCap];      // splines: the row's first segment
         } rw;
     } u;
     int nopen;
@@ -694,10 +728,13 @@ __device__ inline uint32_t probe_key(float mg, float t, int sphere)
 // deferred == 0: items li0, li0 + lstride, ... of the main pass; statistics
 // row and re-test region blockIdx.x.  deferred == 1: the items left whole in
 // re-test regions li0, li0 + lstride, ... (statistics row li0).
-template <int D, typename T>
+template <int D, typename T, int MODE>
 __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0, int lstride)
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
+    constexpr bool kObb = (MODE & kModeObb) != 0;
+    constexpr bool kSpl = (MODE & kModeSplines) != 0;
+    constexpr int kSegW = 2 * D + 1;   // values per spline segment
     __shared__ ItemLds<T> L;
     __shared__ T s_rad2[64];
     const Ctl *ctl = rm.ctl;
@@ -1128,13 +1165,51 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                     }
                     __syncthreads();
                 }
-                // ---- probe: one copy per pair whose capsule met
+                if constexpr (kObb) {
+                    // ---- oriented boxes: the outer part of sphere i is its
+                    // capsule intersected with its body's box, so a sphere
+                    // whose body's box misses is dropped (decided in binary64)
+                    if (tid < np) {
+                        const uint64_t cnd = L.hm[tid] | (kF32 ? L.um[tid] : 0ull);
+                        if (cnd) {
+                            const int pv = L.pe[tid], te = pe_slot(pv), s = pe_entry(pv);
+                            double lo[D], hi[D];
+                            if constexpr (kF32) {
+                                const ChgEntry &en = rm.chg[L.gidx[s]];
+#pragma unroll
+                                for (int k = 0; k < D; ++k) {
+                                    lo[k] = en.lo[k];
+                                    hi[k] = en.hi[k];
+                                }
+                            } else {
+#pragma unroll
+                                for (int k = 0; k < D; ++k) {
+                                    lo[k] = L.x.lo[k][s];
+                                    hi[k] = L.x.hi[k][s];
+                                }
+                            }
+                            const double *ob = rm.obb64 + (int64_t)L.edge[te] * rm.nbody * obb_words(D);
+                            uint64_t keep = 0;
+                            for (int bd = 0; bd < rm.nbody; ++bd) {
+                                const uint64_t sp = rm.body_sph[bd];
+                                if (!(sp & cnd)) continue;
+                                bytes += obb_words(D) * 8;
+                                if (obb_box_meet64<D>(ob + bd * obb_words(D), lo, hi)) keep |= sp;
+                            }
+                            L.hm[tid] &= keep;
+                            if constexpr (kF32) L.um[tid] &= keep;
+                        }
+                    }
+                    __syncthreads();
+                }
+                // ---- probe: one copy per pair whose capsule met (the copy
+                // form only; a sphere the boxes dropped is not probed)
                 const int p = tid;   // kPairCap == kBlock: this thread's pair
                 uint32_t f = 0;
                 uint64_t hmp = 0;
                 if (p < np) {
                     hmp = L.hm[p];
-                    if (hmp) {
+                    if (hmp && !kSpl && (!kObb || ((hmp >> (L.key[p] & 63u)) & 1ull))) {
                         const uint32_t key = L.key[p];
                         const int i = (int)(key & 63u);
                         const int pv = L.pe[p], te = pe_slot(pv), s = pe_entry(pv);
@@ -1178,13 +1253,26 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                         }
                     }
                     __syncthreads();
-                    // copies of each row: fixed count, or a scan over the rows
-                    int ncopies = nr * jfix;
-                    if (!jfix) {
+                    // the row's copies (spline segments): fixed count, or a scan
+                    // over the rows
+                    int ncopies = kSpl ? 0 : nr * jfix;
+                    if (kSpl || !jfix) {
                         int cj[2], sum = 0;
                         for (int h = 0; h < 2; ++h) {
                             const int r = tid * 2 + h;
-                            cj[h] = r < nr ? L.ej[pe_slot(L.pe[L.u.rw.row[r] >> 6])] : 0;
+                            cj[h] = 0;
+                            if (r < nr) {
+                                const uint32_t rv = L.u.rw.row[r];
+                                const int te = pe_slot(L.pe[rv >> 6]);
+                                if constexpr (kSpl) {
+                                    const int64_t k = (int64_t)L.edge[te] * B + (int64_t)(rv & 63u);
+                                    const int32_t k0 = rm.sseg[k];
+                                    cj[h] = rm.sseg[k + 1] - k0;
+                                    L.u.rw.rbase[r] = (uint32_t)k0;
+                                } else {
+                                    cj[h] = L.ej[te];
+                                }
+                            }
                             sum += cj[h];
                         }
                         const int cpre = block_scan(sum, &ncopies, L.wsum);
@@ -1200,8 +1288,9 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                     // each thread gathers kCopyU copies (all their loads in
                     // flight together), then tests them
                     constexpr int kCopyU = 4;
+                    const T *segb = kF32 ? (const T *)rm.seg32 : (const T *)rm.seg64;
                     for (int c0 = 0; c0 < ncopies; c0 += kBlock * kCopyU) {
-                        T q[kCopyU][D];
+                        T q[kCopyU][kSpl ? kSegW : D];
                         int cu_p[kCopyU], cu_i[kCopyU];
 #pragma unroll
                         for (int u = 0; u < kCopyU; ++u) {
@@ -1210,7 +1299,7 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                             cu_i[u] = 0;
                             if (cidx < ncopies) {
                                 int r, jj;
-                                if (jfix) {
+                                if (!kSpl && jfix) {
                                     r = cidx / jfix;
                                     jj = cidx - r * jfix;
                                 } else {
@@ -1227,8 +1316,14 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                                 const int pp = (int)(rv >> 6);
                                 const int i = (int)(rv & 63u);
                                 const int te = pe_slot(L.pe[pp]);
-                                const int Je = L.ej[te];
-                                load_copy<D>(samp, (int64_t)L.cfg0[te] * B + (int64_t)i * Je + jj, q[u]);
+                                if constexpr (kSpl) {
+                                    const T *sg = segb + ((int64_t)L.u.rw.rbase[r] + jj) * kSegW;
+#pragma unroll
+                                    for (int k = 0; k < kSegW; ++k) q[u][k] = sg[k];
+                                } else {
+                                    const int Je = L.ej[te];
+                                    load_copy<D>(samp, (int64_t)L.cfg0[te] * B + (int64_t)i * Je + jj, q[u]);
+                                }
                                 cu_p[u] = pp;
                                 cu_i[u] = i;
                             }
@@ -1244,14 +1339,37 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                                 lo[k] = box_lo(k, s);
                                 hi[k] = box_hi(k, s);
                             }
-                            bytes += D * sizeof(T);
                             int cls;
-                            if constexpr (kF32) {
-                                const float sc = fmaxf(L.es[te], L.blo[s].w);
-                                cls = classify_margin(point_box32<D>(q[u], lo, hi) - s_rad2[cu_i[u]],
-                                                      band_of(band_rel, sc, L.r.r32[cu_i[u]], 0.0f));
+                            if constexpr (kSpl) {
+                                // a spline segment: the capsule (A, B, rho)
+                                T A[D], Bq[D];
+#pragma unroll
+                                for (int k = 0; k < D; ++k) {
+                                    A[k] = q[u][k];
+                                    Bq[k] = q[u][D + k];
+                                }
+                                const T rho = q[u][2 * D];
+                                bytes += kSegW * sizeof(T);
+                                if constexpr (kF32) {
+                                    const float sc = fmaxf(L.es[te], L.blo[s].w);
+                                    float len = 0.0f;
+#pragma unroll
+                                    for (int k = 0; k < D; ++k) len += fabsf(Bq[k] - A[k]);
+                                    float ts;
+                                    const float mg = segbox32<D>(A, Bq, lo, hi, ts) - rho * rho;
+                                    cls = classify_margin(mg, band_of(band_rel, sc, rho, len));
+                                } else {
+                                    cls = segbox64<D>(A, Bq, lo, hi) <= rho * rho ? kHit : kMiss;
+                                }
                             } else {
-                                cls = point_box64<D>(q[u], lo, hi) <= s_rad2[cu_i[u]] ? kHit : kMiss;
+                                bytes += D * sizeof(T);
+                                if constexpr (kF32) {
+                                    const float sc = fmaxf(L.es[te], L.blo[s].w);
+                                    cls = classify_margin(point_box32<D>(q[u], lo, hi) - s_rad2[cu_i[u]],
+                                                          band_of(band_rel, sc, L.r.r32[cu_i[u]], 0.0f));
+                                } else {
+                                    cls = point_box64<D>(q[u], lo, hi) <= s_rad2[cu_i[u]] ? kHit : kMiss;
+                                }
                             }
                             if (cls == kHit) atomicOr(&L.sf[pp], 1u);
                             else if (cls == kUnsure) atomicOr(&L.sf[pp], 2u);
@@ -1343,22 +1461,22 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
 
 // The binary32 kernel is held to 128 VGPRs (four waves per SIMD, four
 // blocks per CU); the binary64 one keeps the compiler's choice.
-template <int D>
+template <int D, int MODE>
 __global__ void __launch_bounds__(kBlock, 4) k_item32(RmDev rm)
 {
-    item_body<D, float>(rm, 0, (int)blockIdx.x, (int)gridDim.x);
+    item_body<D, float, MODE>(rm, 0, (int)blockIdx.x, (int)gridDim.x);
 }
 
-template <int D>
+template <int D, int MODE>
 __global__ void __launch_bounds__(kBlock) k_item64(RmDev rm)
 {
-    item_body<D, double>(rm, 0, (int)blockIdx.x, (int)gridDim.x);
+    item_body<D, double, MODE>(rm, 0, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // Binary64 re-test of the pairs queued by the FP32 item blocks whose regions
 // this block takes (FP32 blocks b, b + gridDim.x, ...), one wavefront per pair.
 // Re-test regions b, b + G, ... (at most 64 of them); statistics row b.
-template <int D>
+template <int D, int MODE>
 __device__ __forceinline__ void retest_pairs(const RmDev &rm, int b, int G)
 {
     const int kReg = kStatBlocks / G;
@@ -1412,14 +1530,34 @@ __device__ __forceinline__ void retest_pairs(const RmDev &rm, int b, int G)
             const double R = cp[2 * D * B + lane];
             hit = segbox64<D>(A, Bp, lo, hi) <= R * R;
         }
-        const uint64_t hm = __ballot(hit);
+        uint64_t hm = __ballot(hit);
         bytes += (2 * D + 1) * B * 8;
         ++n_re;
+        if constexpr ((MODE & kModeObb) != 0) {
+            // spheres whose body's oriented box misses are dropped
+            bool keep = false;
+            uint64_t sp = 0;
+            if (hm && lane < rm.nbody) {
+                sp = rm.body_sph[lane];
+                if (sp & hm) {
+                    keep = obb_box_meet64<D>(rm.obb64 + (e * rm.nbody + lane) * obb_words(D), lo, hi);
+                    bytes += obb_words(D) * 8;
+                }
+            }
+            uint64_t allowed = keep ? sp : 0ull;
+            for (int o = 32; o > 0; o >>= 1) allowed |= __shfl_xor(allowed, o);
+            hm &= allowed;
+        }
         if (!hm) continue;
-        const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
-        const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
-        const CopyMap cm = copy_map((int)(P / B));
-        const bool S = copies_meet64<D>(rm, rm.samp64 + copy_stride<D>() * s0, P, cm, hm, lo, hi, s_rad, s_lst[wv], &bytes);
+        bool S;
+        if constexpr ((MODE & kModeSplines) != 0) {
+            S = splines_meet64<D>(rm, e, hm, lo, hi, &bytes);
+        } else {
+            const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
+            const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
+            const CopyMap cm = copy_map((int)(P / B));
+            S = copies_meet64<D>(rm, rm.samp64 + copy_stride<D>() * s0, P, cm, hm, lo, hi, s_rad, s_lst[wv], &bytes);
+        }
         ++n_outer;
         if (lane == 0) add_counts(rm, e, en.sign, S ? en.sign : 0);
     }
@@ -1442,13 +1580,13 @@ __device__ __forceinline__ void retest_pairs(const RmDev &rm, int b, int G)
 // regions were full (rare: skipped unless one was deferred in this update).
 // One kernel for both, so the common case costs one launch; it runs one
 // block per CU, so the binary64 item path's registers cost no occupancy.
-template <int D>
+template <int D, int MODE>
 __global__ void __launch_bounds__(kBlock) k_fp64(RmDev rm)
 {
     const int any_df = rm.ctl->any_df;
-    retest_pairs<D>(rm, (int)blockIdx.x, (int)gridDim.x);
+    retest_pairs<D, MODE>(rm, (int)blockIdx.x, (int)gridDim.x);
     if (!any_df) return;
-    item_body<D, double>(rm, 1, (int)blockIdx.x, (int)gridDim.x);
+    item_body<D, double, MODE>(rm, 1, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // ------------------------------------------------------------------------
@@ -1779,7 +1917,7 @@ __device__ __forceinline__ void item_batch_body(const BatchReq *tab, const int32
         const int first = P + ((b - P) % G + G) % G;   // first index >= P that is b mod G
         if (first >= P + N) continue;
         load_rm(&s_rm, tab[grp[r]].rm);
-        item_body<D, T>(s_rm, 0, first - P, G);
+        item_body<D, T, 0>(s_rm, 0, first - P, G);
     }
 }
 
@@ -1803,10 +1941,10 @@ __global__ void __launch_bounds__(kBlock) k_fp64_batch(const BatchReq *tab, cons
     __shared__ RmDev s_rm;
     const int r = (int)blockIdx.x / kFp64BatchGrid, b = (int)blockIdx.x % kFp64BatchGrid;
     const int any_df = tab[grp[r]].rm.ctl->any_df;
-    retest_pairs<D>(tab[grp[r]].rm, b, kFp64BatchGrid);
+    retest_pairs<D, 0>(tab[grp[r]].rm, b, kFp64BatchGrid);
     if (!any_df) return;
     load_rm(&s_rm, tab[grp[r]].rm);
-    item_body<D, double>(s_rm, 1, b, kFp64BatchGrid);
+    item_body<D, double, 0>(s_rm, 1, b, kFp64BatchGrid);
 }
 
 // request owning a tile: the last r with first[r] <= tile (n <= kMaxBatch)
@@ -1844,15 +1982,42 @@ __global__ void __launch_bounds__(kBlock) k_write_batch(const BatchReq *tab, int
 
 namespace {
 
+template <int D, int MODE>
+void *item_fn_of(bool f64)
+{
+    return f64 ? (void *)k_item64<D, MODE> : (void *)k_item32<D, MODE>;
+}
+
+template <int D>
+void *item_fn_dim(int mode, bool f64)
+{
+    switch (mode) {
+    case kModeObb: return item_fn_of<D, kModeObb>(f64);
+    case kModeSplines: return item_fn_of<D, kModeSplines>(f64);
+    case kModeObb | kModeSplines: return item_fn_of<D, kModeObb | kModeSplines>(f64);
+    default: return item_fn_of<D, 0>(f64);
+    }
+}
+
 void *item_fn(const RmDev &rm, bool f64)
 {
-    if (rm.D == 3) return f64 ? (void *)k_item64<3> : (void *)k_item32<3>;
-    return f64 ? (void *)k_item64<2> : (void *)k_item32<2>;
+    return rm.D == 3 ? item_fn_dim<3>(rm.mode, f64) : item_fn_dim<2>(rm.mode, f64);
+}
+
+template <int D>
+void *fp64_fn_dim(int mode)
+{
+    switch (mode) {
+    case kModeObb: return (void *)k_fp64<D, kModeObb>;
+    case kModeSplines: return (void *)k_fp64<D, kModeSplines>;
+    case kModeObb | kModeSplines: return (void *)k_fp64<D, kModeObb | kModeSplines>;
+    default: return (void *)k_fp64<D, 0>;
+    }
 }
 
 void *fp64_fn(const RmDev &rm)
 {
-    return rm.D == 3 ? (void *)k_fp64<3> : (void *)k_fp64<2>;
+    return rm.D == 3 ? fp64_fn_dim<3>(rm.mode) : fp64_fn_dim<2>(rm.mode);
 }
 
 
@@ -1931,8 +2096,8 @@ int item_edges_max() { return kItemCap; }
 hipError_t item_blocks_resident(int D, int device, int *out)
 {
     int per_cu = 0, n_cu = 0;
-    hipError_t e = D == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_item32<3>, kBlock, 0)
-                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_item32<2>, kBlock, 0);
+    hipError_t e = D == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_item32<3, 0>, kBlock, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_item32<2, 0>, kBlock, 0);
     if (e != hipSuccess) return e;
     if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess) return e;
     *out = per_cu * n_cu;
@@ -1977,18 +2142,24 @@ namespace {
 
 // The kernels of a batched update in order, each handed to `emit(fn, grid,
 // block, args)` (a graph-node adder or a stream launcher).
-template <typename Emit>
-hipError_t batch_kernels(Emit emit, const BatchReq *tab, const int32_t *grp, int n, const BatchGroup *groups,
-                         int n_groups, bool any_grid, int n_tiles, int n_wtiles)
+// `after(stage)` follows each kernel: 0 diff, 1 cells, 3 item, 4 binary64
+// pass, 5 labels (count and write).
+template <typename Emit, typename After>
+hipError_t batch_kernels(Emit emit, After after, const BatchReq *tab, const int32_t *grp, int n,
+                         const BatchGroup *groups, int n_groups, bool any_grid, int n_tiles, int n_wtiles)
 {
     const BatchReq *t = tab;
     int nn = n;
     hipError_t err;
     void *a_diff[] = {(void *)&t};
     if ((err = emit((void *)k_diff_batch, dim3(n), dim3(kDiffBlock), a_diff)) != hipSuccess) return err;
+    if ((err = after(0)) != hipSuccess) return err;
     void *a_tn[] = {(void *)&t, (void *)&nn};
-    if (any_grid && (err = emit((void *)k_cells_batch, dim3(kCellsBatchGrid * n), dim3(kBlock), a_diff)) != hipSuccess)
-        return err;
+    if (any_grid) {
+        if ((err = emit((void *)k_cells_batch, dim3(kCellsBatchGrid * n), dim3(kBlock), a_diff)) != hipSuccess)
+            return err;
+        if ((err = after(1)) != hipSuccess) return err;
+    }
     for (int k = 0; k < n_groups; ++k) {
         const BatchGroup &gr = groups[k];
         const int32_t *gp = grp + gr.off;
@@ -1997,14 +2168,17 @@ hipError_t batch_kernels(Emit emit, const BatchReq *tab, const int32_t *grp, int
         void *fn = gr.D == 3 ? (gr.mixed ? (void *)k_item32_batch<3> : (void *)k_item64_batch<3>)
                              : (gr.mixed ? (void *)k_item32_batch<2> : (void *)k_item64_batch<2>);
         if ((err = emit(fn, dim3(kGrid), dim3(kBlock), a_item)) != hipSuccess) return err;
+        if ((err = after(3)) != hipSuccess) return err;
         if (gr.mixed) {
             void *a_fp[] = {(void *)&t, (void *)&gp};
             void *fp = gr.D == 3 ? (void *)k_fp64_batch<3> : (void *)k_fp64_batch<2>;
             if ((err = emit(fp, dim3(kFp64BatchGrid * cnt), dim3(kBlock), a_fp)) != hipSuccess) return err;
+            if ((err = after(4)) != hipSuccess) return err;
         }
     }
     if ((err = emit((void *)k_count_batch, dim3(n_tiles), dim3(kBlock), a_tn)) != hipSuccess) return err;
-    return emit((void *)k_write_batch, dim3(n_wtiles), dim3(kBlock), a_tn);
+    if ((err = emit((void *)k_write_batch, dim3(n_wtiles), dim3(kBlock), a_tn)) != hipSuccess) return err;
+    return after(5);
 }
 
 }  // namespace
@@ -2027,7 +2201,8 @@ hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp
         if (err == hipSuccess) prev = node;
         return err;
     };
-    hipError_t err = batch_kernels(add, tab, grp, n, groups, n_groups, any_grid, n_tiles, n_wtiles);
+    auto none = [](int) { return hipSuccess; };
+    hipError_t err = batch_kernels(add, none, tab, grp, n, groups, n_groups, any_grid, n_tiles, n_wtiles);
     if (err == hipSuccess) *last = prev;
     return err;
 }
@@ -2044,12 +2219,24 @@ hipError_t batch_scratch_address(void **ptr)
 }
 
 hipError_t launch_batch(hipStream_t s, const BatchReq *tab, const int32_t *grp, int n, const BatchGroup *groups,
-                        int n_groups, bool any_grid, int n_tiles, int n_wtiles)
+                        int n_groups, bool any_grid, int n_tiles, int n_wtiles, BatchTiming *timing)
 {
     auto launch = [&](void *fn, dim3 grid, dim3 block, void **args) -> hipError_t {
         return hipLaunchKernel(fn, grid, block, args, 0, s);
     };
-    return batch_kernels(launch, tab, grp, n, groups, n_groups, any_grid, n_tiles, n_wtiles);
+    if (!timing) {
+        auto none = [](int) { return hipSuccess; };
+        return batch_kernels(launch, none, tab, grp, n, groups, n_groups, any_grid, n_tiles, n_wtiles);
+    }
+    timing->n = 0;
+    auto mark = [&](int stage) -> hipError_t {
+        if (timing->n >= BatchTiming::kMax) return hipErrorInvalidValue;
+        timing->stage[timing->n] = stage;
+        return hipEventRecord(timing->ev[1 + timing->n++], s);
+    };
+    hipError_t err = hipEventRecord(timing->ev[0], s);
+    if (err != hipSuccess) return err;
+    return batch_kernels(launch, mark, tab, grp, n, groups, n_groups, any_grid, n_tiles, n_wtiles);
 }
 
 }  // namespace rgg

@@ -1,6 +1,6 @@
-// The binary64 distance predicates behind every exact decision of librgg:
-// the update kernels' binary64 re-tests and deferred items, and the full
-// validation.  Each is one fixed expression order; device code is compiled
+// The binary64 predicates behind every exact decision of librgg: the update
+// kernels' binary64 re-tests and deferred items, the oriented-box test (always
+// decided in binary64), and the full validation.  Each is one fixed expression order; device code is compiled
 // without FMA contraction, so any IEEE binary64 evaluator of the same
 // expressions reaches the same values.
 #pragma once
@@ -122,6 +122,62 @@ __device__ inline double segbox64(const double *A, const double *Bp, const doubl
     }
     if (targ) *targ = tmin;
     return fmin;
+}
+
+// Oriented box o = (centre[D], axes[D][D] as rows, half-extents[D]) against
+// the closed box [lo, hi]: true when they share a point.  Separating-axis
+// theorem for two boxes: the candidate axes are the box's face normals e_d,
+// the oriented box's axes u_k and, in 3-D, the products e_d x u_k; on an axis
+// the centres' projections differ by |T . axis| (T = centre - box centre) and
+// the boxes reach the sums of their half-extents times |face normal . axis|.
+template <int D>
+__device__ inline bool obb_box_meet64(const double *o, const double *lo, const double *hi)
+{
+    const double *c = o, *u = o + D, *h = o + D + D * D;
+    double bh[D], t[D], au[D][D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        bh[d] = 0.5 * (hi[d] - lo[d]);
+        t[d] = c[d] - 0.5 * (lo[d] + hi[d]);
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+        for (int k = 0; k < D; ++k) au[d][k] = fabs(u[k * D + d]);
+    bool sep = false;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        double rb = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) rb = rb + h[k] * au[d][k];
+        sep = sep || fabs(t[d]) > bh[d] + rb;
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        double ra = 0.0, tp = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            ra = ra + bh[d] * au[d][k];
+            tp = tp + u[k * D + d] * t[d];
+        }
+        sep = sep || fabs(tp) > h[k] + ra;
+    }
+    if constexpr (D == 3) {
+        // e_d x u_k: components -u_k[d2] at d1 and u_k[d1] at d2
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+                const double ra = bh[d1] * au[d2][k] + bh[d2] * au[d1][k];
+                const double rb = h[k1] * au[d][k2] + h[k2] * au[d][k1];
+                const double tp = t[d2] * u[k * 3 + d1] - t[d1] * u[k * 3 + d2];
+                sep = sep || fabs(tp) > ra + rb;
+            }
+        }
+    }
+    return !sep;
 }
 
 }  // namespace rgg

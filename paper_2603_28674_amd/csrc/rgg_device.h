@@ -51,6 +51,16 @@ struct RmDev {
     const float *aabb;
     const float *rad2_32;      // [B] r_i^2 rounded to binary32
     const double *rad64;       // [B]
+    // the second forms of Sec. 4.2: bit kModeObb, an oriented box per body
+    // intersected with the capsules (outer); bit kModeSplines, shortcut
+    // splines instead of the copies (inner)
+    int32_t mode;
+    int32_t nbody;             // robot bodies (1, or the arm's links)
+    const double *obb64;       // [E][nbody][2D + D*D] centre, axes (rows), half-extents
+    const unsigned long long *body_sph;   // [nbody] spheres of each body (bit i: sphere i)
+    const int32_t *sseg;       // [E*B + 1] first spline segment of (edge, sphere)
+    const float *seg32;        // [segments][2D + 1] spline segments: A, B, rho
+    const double *seg64;
     // grid
     int32_t gdim[3];
     int32_t pad0;
@@ -86,6 +96,10 @@ struct RmDev {
     unsigned long long *blk_stats;   // [kStats][kStatBlocks] per-block partial counts
     Ctl *ctl;
 };
+
+constexpr int kModeObb = 1;
+constexpr int kModeSplines = 2;
+__host__ __device__ constexpr int obb_words(int D) { return 2 * D + D * D; }
 
 // pairs, pairs whose outer approximation met, re-tested pairs, classify bytes,
 // grid entries scanned, candidate edges
@@ -138,9 +152,18 @@ struct BatchGroup {
 hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp, int n,
                            const BatchGroup *groups, int n_groups, bool any_grid, int n_tiles,
                            int n_wtiles, hipGraphNode_t dep, hipGraphNode_t *last);
-// The same kernels launched on `s`.
+// Events of a timed batched launch: ev[0] before the first kernel, ev[1 + k]
+// after kernel k, whose stage (0 diff, 1 cells, 3 item, 4 binary64 pass,
+// 5 labels) is stage[k]; n kernels were marked.
+struct BatchTiming {
+    static constexpr int kMax = 16;
+    hipEvent_t ev[kMax + 1];
+    int stage[kMax];
+    int n;
+};
+// The same kernels launched on `s` (timed when `timing` is non-null).
 hipError_t launch_batch(hipStream_t s, const BatchReq *tab, const int32_t *grp, int n, const BatchGroup *groups,
-                        int n_groups, bool any_grid, int n_tiles, int n_wtiles);
+                        int n_groups, bool any_grid, int n_tiles, int n_wtiles, BatchTiming *timing = nullptr);
 
 // Full validation of listed edges (rgg_validate): the robot, each edge's
 // motion parameters and chord-deviation bounds, and the resident slots.

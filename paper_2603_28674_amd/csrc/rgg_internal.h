@@ -46,7 +46,18 @@ struct HostGeometry {
     double rob_base[2] = {0.0, 0.0};
     std::vector<double> motion;    // [E][2 dof + 3]: a, b (SE3: short-arc sign), turn, half, sin_half
     std::vector<double> delta;     // [E][B] chord-deviation bounds delta_i
+    // the second forms of Sec. 4.2, when asked for
+    int n_bodies = 1;              // robot bodies: 1 (rigid kinds) or L (arm links)
+    std::vector<int32_t> body;     // [B] body of each sphere
+    std::vector<uint8_t> body_has; // [n_bodies] the body carries a sphere
+    std::vector<double> obb;       // [E][n_bodies][2D + D*D] oriented boxes: centre, axes
+                                   // (row k = axis k), half-extents; empty without them
+    std::vector<int64_t> sseg;     // [E*B + 1] first spline segment of (edge, sphere); empty
+                                   // without splines
+    std::vector<double> seg;       // [segments][2D + 1] spline segments: A, B, rho
 };
+inline int obb_stride(int D) { return 2 * D + D * D; }
+constexpr double kDefaultSplineTol = 0.05;
 
 // Validates the inputs of rgg_build.  Returns RGG_OK or RGG_E_INVALID_ARG
 // with *err describing the problem.

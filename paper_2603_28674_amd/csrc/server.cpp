@@ -81,13 +81,14 @@ struct Pending {
     bool validate;
     uint8_t *d_verdict;
     Clock::time_point submitted;
+    Clock::time_point launched;   // its batch was queued on the device
     int64_t bytes;                // pool bytes
 };
 
 struct Ticket {
     int state = 0;                // 0 queued, 1 running, 2 done
     rgg_update_result res = {};
-    double latency_us = 0.0;
+    rgg_request_timing timing = {};
 };
 
 struct Slot {
@@ -119,6 +120,7 @@ struct rgg_server {
     bool stopping = false;
     bool closed = false;          // rgg_server_stop has joined the worker
     int pollers = 0;              // threads waiting in rgg_server_poll
+    int64_t free_at_start = 0;    // free device bytes when the server started
     std::string worker_error;
     std::thread worker;
     std::vector<rgg_roadmap *> seen;   // roadmaps this server has updated (worker only)
@@ -180,7 +182,9 @@ bool rgg_server::dispatch(Slot &slot, std::vector<Pending> &batch)
         wtiles += dv.ntiles + 1;
     }
     hipStream_t s = slot.s;
+    const Clock::time_point launched = Clock::now();
     for (int r = 0; r < n; ++r) {
+        batch[r].launched = launched;
         if (order_after_previous(batch[r].rm, s) != RGG_OK) return false;
         const int64_t M = batch[r].rm->dv.M;
         if (M > 0 && hipMemcpyAsync(d_pool + slot.offs[r], h_pool + slot.offs[r], sizeof(rgg_box) * 2 * M,
@@ -218,9 +222,13 @@ void rgg_server::complete(Slot &slot)
     const Clock::time_point now = Clock::now();
     std::lock_guard<std::mutex> lk(mu);
     for (size_t r = 0; r < slot.reqs.size(); ++r) {
-        Ticket &t = tickets[slot.reqs[r].ticket];
+        const Pending &q = slot.reqs[r];
+        Ticket &t = tickets[q.ticket];
         t.res = slot.h_res[r];
-        t.latency_us = std::chrono::duration<double, std::micro>(now - slot.reqs[r].submitted).count();
+        t.timing.latency_us = std::chrono::duration<double, std::micro>(now - q.submitted).count();
+        t.timing.queue_us = std::chrono::duration<double, std::micro>(q.launched - q.submitted).count();
+        t.timing.service_us = std::chrono::duration<double, std::micro>(now - q.launched).count();
+        t.timing.batch_size = (int32_t)slot.reqs.size();
         t.state = 2;
         pool.give(slot.offs[r], slot.reqs[r].bytes);
     }
@@ -342,15 +350,26 @@ rgg_status rgg_server_start(rgg_context *ctx, const rgg_server_opts *opts_in, rg
     if (o.n_streams == 0) o.n_streams = 4;
     if (o.max_queue == 0) o.max_queue = 4096;
     if (o.max_batch == 0) o.max_batch = 64;
-    if (o.pool_bytes == 0) o.pool_bytes = 64ll << 20;
+    HIP_OR_FAIL(hipSetDevice(ctx->device), "hipSetDevice");
+    size_t free_b = 0, total_b = 0;
+    HIP_OR_FAIL(hipMemGetInfo(&free_b, &total_b), "hipMemGetInfo");
+    if (o.pool_bytes == 0) {
+        // admission by free device memory: the staging pool that bounds the
+        // requests in flight takes 1/64 of what is free now, within
+        // [16 MiB, 256 MiB] (256 MiB holds 5,000 requests of 1,000 boxes)
+        o.pool_bytes = std::min<int64_t>(std::max<int64_t>((int64_t)(free_b / 64), 16ll << 20), 256ll << 20);
+    }
+    if (o.pool_bytes > (int64_t)free_b)
+        return fail(RGG_E_OUT_OF_MEMORY, "pool of %lld bytes exceeds the %zu bytes of free device memory",
+                    (long long)o.pool_bytes, free_b);
     if (o.n_streams < 1 || o.n_streams > 16) return fail(RGG_E_INVALID_ARG, "n_streams must be 1..16");
     if (o.max_queue < 1) return fail(RGG_E_INVALID_ARG, "max_queue must be positive");
     if (o.max_batch < 1 || o.max_batch > kMaxBatch) return fail(RGG_E_INVALID_ARG, "max_batch must be 1..%d", kMaxBatch);
     if (o.pool_bytes < kAlign) return fail(RGG_E_INVALID_ARG, "pool_bytes too small");
-    HIP_OR_FAIL(hipSetDevice(ctx->device), "hipSetDevice");
     rgg_server *srv = new rgg_server();
     srv->device = ctx->device;
     srv->opts = o;
+    srv->free_at_start = (int64_t)free_b;
     srv->pool = PoolMap(round_up(o.pool_bytes));
     auto bail = [&](hipError_t e, const char *what) {
         free_server(srv);
@@ -388,6 +407,8 @@ rgg_status rgg_server_submit(rgg_server *srv, const rgg_server_req *req, uint64_
     rgg_roadmap *rm = req->rm;
     if (!rm) return fail(RGG_E_INVALID_ARG, "null roadmap");
     if (rm->device != srv->device) return fail(RGG_E_INVALID_ARG, "roadmap on another device");
+    if (rm->dv.mode != 0)
+        return fail(RGG_E_UNSUPPORTED, "the server batches roadmaps of the capsule and copy forms only");
     const int64_t M = rm->dv.M;
     if (req->m != M) return fail(RGG_E_INVALID_ARG, "m = %lld but the roadmap has %lld slots", (long long)req->m, (long long)M);
     if (M > 0 && (!req->old_boxes || !req->new_boxes)) return fail(RGG_E_INVALID_ARG, "null box arrays");
@@ -429,8 +450,8 @@ rgg_status rgg_server_submit(rgg_server *srv, const rgg_server_req *req, uint64_
     return RGG_OK;
 }
 
-rgg_status rgg_server_poll(rgg_server *srv, uint64_t ticket, int32_t wait, int32_t *done,
-                           rgg_update_result *result, double *latency_us)
+rgg_status rgg_server_poll_timing(rgg_server *srv, uint64_t ticket, int32_t wait, int32_t *done,
+                                  rgg_update_result *result, rgg_request_timing *timing)
 {
     if (!srv || !done) return fail(RGG_E_INVALID_ARG, "null argument");
     std::unique_lock<std::mutex> lk(srv->mu);
@@ -454,8 +475,25 @@ rgg_status rgg_server_poll(rgg_server *srv, uint64_t ticket, int32_t wait, int32
     }
     *done = 1;
     if (result) *result = it->second.res;
-    if (latency_us) *latency_us = it->second.latency_us;
+    if (timing) *timing = it->second.timing;
     srv->tickets.erase(it);
+    return RGG_OK;
+}
+
+rgg_status rgg_server_poll(rgg_server *srv, uint64_t ticket, int32_t wait, int32_t *done,
+                           rgg_update_result *result, double *latency_us)
+{
+    rgg_request_timing t = {};
+    rgg_status st = rgg_server_poll_timing(srv, ticket, wait, done, result, &t);
+    if (st == RGG_OK && *done && latency_us) *latency_us = t.latency_us;
+    return st;
+}
+
+rgg_status rgg_server_info(rgg_server *srv, rgg_server_opts *opts, int64_t *free_at_start)
+{
+    if (!srv) return fail(RGG_E_INVALID_ARG, "null server");
+    if (opts) *opts = srv->opts;
+    if (free_at_start) *free_at_start = srv->free_at_start;
     return RGG_OK;
 }
 

@@ -60,7 +60,8 @@ class rgg_build_opts(C.Structure):
                 ("precision", C.c_int32), ("band_rel", C.c_double),
                 ("n_obstacle_slots", C.c_int64), ("cell_size", C.c_double),
                 ("host_threads", C.c_int32), ("retest_capacity", C.c_int32),
-                ("item_edges", C.c_int32)]
+                ("item_edges", C.c_int32), ("outer_obb", C.c_int32), ("inner_splines", C.c_int32),
+                ("spline_tol", C.c_double), ("mem_budget", C.c_int64)]
 
 
 class rgg_update_result(C.Structure):
@@ -118,6 +119,11 @@ class rgg_server_opts(C.Structure):
                 ("reserved", C.c_int32), ("pool_bytes", C.c_int64)]
 
 
+class rgg_request_timing(C.Structure):
+    _fields_ = [("latency_us", C.c_double), ("queue_us", C.c_double), ("service_us", C.c_double),
+                ("batch_size", C.c_int32), ("reserved", C.c_int32)]
+
+
 class rgg_server_req(C.Structure):
     _fields_ = [("rm", C.c_void_p), ("m", C.c_int64), ("old_boxes", C.c_void_p), ("new_boxes", C.c_void_p),
                 ("d_labels", C.c_void_p), ("d_gray", C.c_void_p), ("gray_cap", C.c_int64),
@@ -130,12 +136,13 @@ RESULT_BYTES = C.sizeof(rgg_update_result)
 EXPORTS = ["rgg_context_create", "rgg_context_destroy", "rgg_build", "rgg_destroy",
            "rgg_roadmap_info_get", "rgg_update", "rgg_update_async", "rgg_graph_create",
            "rgg_graph_launch", "rgg_graph_destroy", "rgg_batch_create", "rgg_batch_launch",
-           "rgg_batch_launch_graph", "rgg_batch_destroy", "rgg_update_batch", "rgg_update_batch_noalloc",
+           "rgg_batch_launch_graph", "rgg_batch_destroy", "rgg_batch_timing_enable", "rgg_batch_timing_read",
+           "rgg_update_batch", "rgg_update_batch_noalloc",
            "rgg_server_start",
-           "rgg_server_submit", "rgg_server_poll", "rgg_server_stop", "rgg_labels", "rgg_gray_list",
+           "rgg_server_submit", "rgg_server_poll", "rgg_server_poll_timing", "rgg_server_info", "rgg_server_stop", "rgg_labels", "rgg_gray_list",
            "rgg_timing_enable", "rgg_timing_read", "rgg_tune", "rgg_batch_tune", "rgg_save", "rgg_load",
            "rgg_validate", "rgg_validate_async",
-           "rgg_debug_geometry", "rgg_debug_read_file",
+           "rgg_debug_geometry", "rgg_debug_second_forms", "rgg_debug_read_file",
            "rgg_last_error", "rgg_version"]
 
 _lib = None
@@ -165,12 +172,16 @@ def lib():
         "rgg_batch_launch": (I32, [P, P, P]),
         "rgg_batch_launch_graph": (I32, [P, P, P]),
         "rgg_batch_destroy": (I32, [P]),
+        "rgg_batch_timing_enable": (I32, [P, I32]),
+        "rgg_batch_timing_read": (I32, [P, P, P]),
         "rgg_update_batch": (I32, [P, I32, P, P]),
         "rgg_update_batch_noalloc": (I32, [P, I32, P, P]),
         "rgg_server_start": (I32, [P, P, C.POINTER(P)]),
         "rgg_server_submit": (I32, [P, P, C.POINTER(C.c_uint64)]),
         "rgg_server_poll": (I32, [P, C.c_uint64, I32, C.POINTER(I32), P, C.POINTER(C.c_double)]),
         "rgg_server_stop": (I32, [P]),
+        "rgg_server_poll_timing": (I32, [P, C.c_uint64, I32, C.POINTER(I32), P, P]),
+        "rgg_server_info": (I32, [P, P, C.POINTER(I64)]),
         "rgg_labels": (I32, [P, P]),
         "rgg_gray_list": (I32, [P, P, I64, P]),
         "rgg_timing_enable": (I32, [P, I32]),
@@ -182,6 +193,7 @@ def lib():
         "rgg_validate_async": (I32, [P, P, P, I64, P, I32, I32, P, P, P, P]),
         "rgg_load": (I32, [P, C.c_char_p, C.POINTER(P)]),
         "rgg_debug_geometry": (I32, [P, P, P, I64, I64, P, P, P, P]),
+        "rgg_debug_second_forms": (I32, [P, P, P, I64, I64, P, P, P]),
         "rgg_debug_read_file": (I32, [C.c_char_p, C.POINTER(I64)]),
         "rgg_last_error": (C.c_char_p, []),
         "rgg_version": (C.c_char_p, []),
@@ -258,8 +270,12 @@ def make_desc(q, edges, keep):
 
 def make_opts(resolution=0.0, samples_per_edge=0, precision=RGG_PREC_FP64, band_rel=0.0,
               n_obstacle_slots=0, cell_size=0.0, host_threads=0, retest_capacity=0,
-              item_edges=0):
+              item_edges=0, outer_obb=False, inner_splines=False, spline_tol=0.0, mem_budget=0):
     o = rgg_build_opts()
+    o.mem_budget = mem_budget
+    o.outer_obb = int(bool(outer_obb))
+    o.inner_splines = int(bool(inner_splines))
+    o.spline_tol = spline_tol
     o.resolution = resolution
     o.samples_per_edge = samples_per_edge
     o.precision = precision
@@ -378,6 +394,18 @@ def rgg_batch_launch_graph(b, reqs, stream):
     _check(lib().rgg_batch_launch_graph(b, arr, C.c_void_p(stream)))
 
 
+def rgg_batch_timing_enable(b, on):
+    _check(lib().rgg_batch_timing_enable(b, 1 if on else 0))
+
+
+def rgg_batch_timing_read(b):
+    """(ms[6] summed per stage, launches timed) since the last read."""
+    ms = np.zeros(6)
+    n = C.c_int64(0)
+    _check(lib().rgg_batch_timing_read(b, _ptr(ms), C.byref(n)))
+    return ms, n.value
+
+
 def rgg_batch_destroy(b):
     _check(lib().rgg_batch_destroy(b))
 
@@ -419,6 +447,28 @@ def rgg_server_poll(srv, ticket, wait=False):
     lat = C.c_double()
     _check(lib().rgg_server_poll(srv, ticket, 1 if wait else 0, C.byref(done), C.byref(res), C.byref(lat)))
     return (True, res, lat.value) if done.value else (False, None, 0.0)
+
+
+def rgg_server_poll_timing(srv, ticket, wait=False):
+    """(done, result, timing dict with latency_us, queue_us, service_us,
+    batch_size); result and timing are None while the request runs."""
+    done = C.c_int32()
+    res = rgg_update_result()
+    t = rgg_request_timing()
+    _check(lib().rgg_server_poll_timing(srv, ticket, 1 if wait else 0, C.byref(done), C.byref(res), C.byref(t)))
+    if not done.value:
+        return False, None, None
+    return True, res, {"latency_us": t.latency_us, "queue_us": t.queue_us, "service_us": t.service_us,
+                       "batch_size": t.batch_size}
+
+
+def rgg_server_info(srv):
+    """The server's effective options and the free device memory at start."""
+    o = rgg_server_opts()
+    free = C.c_int64()
+    _check(lib().rgg_server_info(srv, C.byref(o), C.byref(free)))
+    return {"n_streams": o.n_streams, "max_queue": o.max_queue, "max_batch": o.max_batch,
+            "pool_bytes": o.pool_bytes, "free_bytes_at_start": free.value}
 
 
 def rgg_server_stop(srv):
@@ -511,6 +561,27 @@ def rgg_debug_geometry(desc, robot, opts, e0, e1):
     return cnt, ctr[:int(cnt.sum())], cap[:e1 - e0], box[:e1 - e0]
 
 
+def rgg_debug_second_forms(desc, robot, opts, e0, e1):
+    """Host build stage's oriented boxes [E, bodies, 2D + D*D] (or None) and
+    spline segments: (counts [E, B], segments [sum, 2D + 1]) (or None)."""
+    L = lib()
+    E = e1 - e0
+    B = robot.n_spheres
+    D = 3 if robot.kind == RGG_SE3 else 2
+    nb = robot.n_links if robot.kind == RGG_PLANAR_ARM else 1
+    obb = np.zeros((max(E, 1), nb, 2 * D + D * D)) if opts.outer_obb else None
+    cnt = np.zeros(max(E * B, 1), dtype=np.int64)
+    _check(L.rgg_debug_second_forms(C.byref(desc), C.byref(robot), C.byref(opts), e0, e1, _ptr(obb),
+                                    _ptr(cnt), None))
+    spl = None
+    if opts.inner_splines:
+        seg = np.zeros((max(int(cnt[:E * B].sum()), 1), 2 * D + 1))
+        _check(L.rgg_debug_second_forms(C.byref(desc), C.byref(robot), C.byref(opts), e0, e1, None, None,
+                                        _ptr(seg)))
+        spl = (cnt[:E * B].reshape(E, B), seg[:int(cnt[:E * B].sum())])
+    return (obb[:E] if obb is not None else None), spl
+
+
 def rgg_debug_read_file(path):
     """Reads and checks a roadmap file on the host as rgg_load does; returns
     its edge count."""
@@ -536,13 +607,15 @@ class Roadmap:
 
     def __init__(self, ctx, robot, q, edges, n_slots, resolution=0.0, samples_per_edge=0,
                  precision=RGG_PREC_FP64, band_rel=0.0, cell_size=0.0, host_threads=0,
-                 retest_capacity=0, item_edges=0):
+                 retest_capacity=0, item_edges=0, outer_obb=False, inner_splines=False, spline_tol=0.0,
+                 mem_budget=0):
         keep = _Keep()
         self._keep = keep
         self.robot = make_robot(robot, keep)
         self.desc = make_desc(q, edges, keep)
         self.opts = make_opts(resolution, samples_per_edge, precision, band_rel, n_slots,
-                              cell_size, host_threads, retest_capacity, item_edges)
+                              cell_size, host_threads, retest_capacity, item_edges, outer_obb,
+                              inner_splines, spline_tol, mem_budget)
         self.h = rgg_build(ctx, self.desc, self.robot, self.opts)
         self.E = int(np.asarray(edges).shape[0])
         self.M = int(n_slots)

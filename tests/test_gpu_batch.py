@@ -130,3 +130,40 @@ def test_batch_errors(ctx):
         rgg.rgg_batch_launch(b, [rgg.rgg_update_req(g.h.value, w.n_slots + 1, 1, 1, 0, 0, 0, 1)], 0)
     rgg.rgg_batch_destroy(b)
     g.close()
+
+
+def test_batch_stage_timing(ctx):
+    """Stage timing of batched launches: every timed launch is counted, the
+    item stage takes time, and the results are still the oracle's."""
+    import torch
+    from paper_2603_28674_amd import rgg
+    import oracle
+    dev = torch.device("cuda:0")
+    specs = mixed_workloads(3)[:3]
+    gs = [rgg.Roadmap.from_workload(ctx, w, precision=p, cell_size=c) for w, p, c in specs]
+    ors = [oracle.from_workload(w) for w, _, _ in specs]
+    b = rgg.rgg_batch_create(ctx, [g.h for g in gs])
+    rgg.rgg_batch_timing_enable(b, True)
+    stream = torch.cuda.current_stream().cuda_stream
+    bufs = []
+    for w, _, _ in specs:
+        states = torch.from_numpy(np.stack([w.absent()] + w.boxes)).to(dev)
+        bufs.append((states, torch.zeros(w.n_edges, dtype=torch.uint8, device=dev),
+                     torch.zeros(w.n_edges, dtype=torch.int64, device=dev),
+                     torch.zeros(rgg.RESULT_BYTES, dtype=torch.uint8, device=dev)))
+    for u in range(3):
+        reqs = [rgg.rgg_update_req(g.h.value, w.n_slots, st[u].data_ptr(), st[u + 1].data_ptr(), lab.data_ptr(),
+                                   gr.data_ptr(), w.n_edges, res.data_ptr())
+                for (w, _, _), g, (st, lab, gr, res) in zip(specs, gs, bufs)]
+        rgg.rgg_batch_launch(b, reqs, stream)
+        torch.cuda.synchronize()
+        for (w, _, _), o, (st, lab, gr, res) in zip(specs, ors, bufs):
+            ol, og = o.update(w.absent() if u == 0 else w.boxes[u - 1], w.boxes[u])
+            assert np.array_equal(lab.cpu().numpy(), ol)
+    ms, n = rgg.rgg_batch_timing_read(b)
+    assert n == 3 and ms[0] > 0 and ms[3] > 0 and ms[5] > 0 and ms[2] == 0
+    ms, n = rgg.rgg_batch_timing_read(b)
+    assert n == 0 and not ms.any()
+    rgg.rgg_batch_destroy(b)
+    for g in gs:
+        g.close()

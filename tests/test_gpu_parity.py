@@ -49,17 +49,19 @@ def with_removals(w, rng):
 
 
 def check_sequence(ctx, w, precision, cell_size=0.0, band_rel=0.0, device_buffers=False,
-                   retest_capacity=0, item_edges=0):
+                   retest_capacity=0, item_edges=0, outer_obb=False, inner_splines=False, spline_tol=0.05):
     import torch
     from paper_2603_28674_amd import rgg
     import oracle
     print(f"[parity] {w.name} E={w.n_edges} M={w.n_slots} precision={precision} "
           f"cell={cell_size} band={band_rel} device_buffers={device_buffers} "
-          f"retest_capacity={retest_capacity} item_edges={item_edges}", flush=True)
+          f"retest_capacity={retest_capacity} item_edges={item_edges} obb={outer_obb} "
+          f"splines={inner_splines} tol={spline_tol}", flush=True)
     g = rgg.Roadmap.from_workload(ctx, w, precision=precision, cell_size=cell_size,
                                   band_rel=band_rel, retest_capacity=retest_capacity,
-                                  item_edges=item_edges)
-    o = oracle.from_workload(w)
+                                  item_edges=item_edges, outer_obb=outer_obb,
+                                  inner_splines=inner_splines, spline_tol=spline_tol)
+    o = oracle.from_workload(w, outer_obb=outer_obb, inner_splines=inner_splines, spline_tol=spline_tol)
     prev = w.absent()
     stats = []
     if device_buffers:
@@ -356,3 +358,25 @@ def test_maximum_sizes(ctx, case):
               f"verdicts {np.bincount(got[0], minlength=4).tolist()}", flush=True)
         prev = cur
     g.close()
+
+
+def test_roadmap_admission_by_device_memory(ctx):
+    """mem_budget admits a roadmap only when its arrays fit: the exact size
+    it ends up holding is admitted, one byte less is refused before
+    anything is allocated."""
+    import torch
+    from paper_2603_28674_amd import rgg
+    w = workload("spatial", n_updates=1, seed=61)
+    for mode in (dict(), dict(outer_obb=True, inner_splines=True)):
+        g = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK, **mode)
+        need = g.info()["device_bytes"]
+        g.close()
+        torch.cuda.synchronize()
+        before = torch.cuda.mem_get_info()[0]
+        with pytest.raises(rgg.RggError) as ei:
+            rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK, mem_budget=need - 1, **mode)
+        assert ei.value.status == rgg.RGG_E_OUT_OF_MEMORY
+        assert torch.cuda.mem_get_info()[0] == before
+        g = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK, mem_budget=need, **mode)
+        assert g.info()["device_bytes"] == need
+        g.close()

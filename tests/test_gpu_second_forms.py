@@ -1,0 +1,183 @@
+"""GPU parity of the second approximation forms (paper Sec. 4.2): the
+oriented box per robot body (outer, intersected with the capsules) and the
+shortcut splines (inner).  Labels and gray lists must equal the FP64
+oracle's built in the same form, exactly, after every update of sequences
+that add, move, remove and re-add obstacles; in both precisions, with every
+pair re-tested in binary64 (band = inf), with whole items left to the
+binary64 pass (one re-test slot per block), over grid and one-cell
+decompositions, through the device-buffer and graph entry points."""
+import numpy as np
+import pytest
+
+from paper_2603_28674_amd import synth
+from test_gpu_parity import check_sequence, with_removals, workload
+
+pytestmark = pytest.mark.gpu
+
+MODES = [dict(outer_obb=True), dict(inner_splines=True), dict(outer_obb=True, inner_splines=True)]
+MODE_IDS = ["obb", "splines", "obb+splines"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2603_28674_amd import rgg
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = rgg.rgg_context_create(0)
+    yield c
+    rgg.rgg_context_destroy(c)
+
+
+@pytest.mark.parametrize("kind", ["planar", "spatial", "arm"])
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_second_forms_parity_fp64(ctx, kind, mode):
+    from paper_2603_28674_amd import rgg
+    w = with_removals(workload(kind, n_updates=4), np.random.default_rng(31))
+    stats = check_sequence(ctx, w, rgg.RGG_PREC_FP64, **mode)
+    assert sum(s["n_pairs"] for s in stats) > 0
+
+
+@pytest.mark.parametrize("kind", ["planar", "spatial", "arm"])
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_second_forms_parity_fp32(ctx, kind, mode):
+    from paper_2603_28674_amd import rgg
+    w = with_removals(workload(kind, n_updates=4), np.random.default_rng(32))
+    stats = check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, **mode)
+    assert sum(s["n_pairs"] for s in stats) > 0
+
+
+@pytest.mark.parametrize("kind", ["planar", "spatial", "arm"])
+@pytest.mark.parametrize("mode", MODES, ids=MODE_IDS)
+def test_second_forms_every_pair_retested(ctx, kind, mode):
+    """band = inf: every pair goes to the binary64 re-test (its box filter
+    and spline tests); then one re-test slot per block, so whole items go
+    to the binary64 pass."""
+    from paper_2603_28674_amd import rgg
+    w = workload(kind, n_updates=3, seed=41)
+    stats = check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, band_rel=float("inf"), **mode)
+    if mode.get("outer_obb"):
+        # the boxes are decided in binary64 by the FP32 kernel itself: a pair
+        # whose every undecided capsule belongs to a body whose box misses is
+        # settled there, the others are re-tested
+        assert all(s["n_rechecked"] <= s["n_pairs"] for s in stats)
+        assert sum(s["n_rechecked"] for s in stats) > 0
+    else:
+        assert all(s["n_rechecked"] == s["n_pairs"] for s in stats)
+    check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, band_rel=float("inf"), retest_capacity=1, **mode)
+
+
+@pytest.mark.parametrize("cell_size", [-1.0, 0.0, 3.0])
+@pytest.mark.parametrize("item_edges", [64, 512])
+def test_second_forms_decompositions(ctx, cell_size, item_edges):
+    from paper_2603_28674_amd import rgg
+    w = workload("arm", n_updates=3, seed=42)
+    check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, cell_size=cell_size, item_edges=item_edges,
+                   outer_obb=True, inner_splines=True)
+
+
+@pytest.mark.parametrize("tol", [0.01, 0.3])
+def test_second_forms_tolerances_and_device_buffers(ctx, tol):
+    from paper_2603_28674_amd import rgg
+    for kind in ("planar", "spatial"):
+        w = workload(kind, n_updates=3, seed=43)
+        check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, device_buffers=True, inner_splines=True,
+                       spline_tol=tol)
+
+
+def test_second_forms_graph(ctx):
+    """Two roadmaps (boxes; splines) in one captured graph launch."""
+    import torch
+    from paper_2603_28674_amd import rgg
+    import oracle
+    dev = torch.device("cuda:0")
+    specs = [(workload("spatial", n_updates=3, seed=44), dict(outer_obb=True)),
+             (workload("arm", n_updates=3, seed=45), dict(inner_splines=True))]
+    gs, ors, reqs, bufs = [], [], [], []
+    for w, mode in specs:
+        print(f"[graph] {w.name} E={w.n_edges} {mode}", flush=True)
+        g = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK, **mode)
+        gs.append(g)
+        ors.append(oracle.from_workload(w, **mode))
+        old = torch.zeros((w.n_slots, 6), dtype=torch.float64, device=dev)
+        new = torch.zeros_like(old)
+        lab = torch.zeros(w.n_edges, dtype=torch.uint8, device=dev)
+        gray = torch.zeros(w.n_edges, dtype=torch.int64, device=dev)
+        res = torch.zeros(rgg.RESULT_BYTES, dtype=torch.uint8, device=dev)
+        bufs.append((old, new, lab, gray, res))
+        reqs.append(rgg.rgg_update_req(g.h.value, w.n_slots, old.data_ptr(), new.data_ptr(), lab.data_ptr(),
+                                       gray.data_ptr(), w.n_edges, res.data_ptr()))
+    graph = rgg.rgg_graph_create(ctx, reqs)
+    stream = torch.cuda.current_stream().cuda_stream
+    for u in range(3):
+        for (w, _), (old, new, lab, gray, res) in zip(specs, bufs):
+            old.copy_(torch.from_numpy(w.absent() if u == 0 else w.boxes[u - 1]))
+            new.copy_(torch.from_numpy(w.boxes[u]))
+        rgg.rgg_graph_launch(graph, stream)
+        torch.cuda.synchronize()
+        for (w, _), o, (old, new, lab, gray, res) in zip(specs, ors, bufs):
+            ol, og = o.update(w.absent() if u == 0 else w.boxes[u - 1], w.boxes[u])
+            r = rgg.result_from_tensor(res)
+            assert r.status == 0 and r.n_gray == len(og)
+            assert np.array_equal(lab.cpu().numpy(), ol)
+            assert np.array_equal(gray[: r.n_gray].cpu().numpy(), og)
+    rgg.rgg_graph_destroy(graph)
+    for g in gs:
+        g.close()
+
+
+def test_second_forms_refused_by_batches(ctx):
+    from paper_2603_28674_amd import rgg
+    w = workload("planar", n_updates=1, seed=46)
+    g = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK, outer_obb=True)
+    with pytest.raises(rgg.RggError) as ei:
+        rgg.rgg_batch_create(ctx, [g.h])
+    assert ei.value.status == rgg.RGG_E_UNSUPPORTED
+    g.close()
+
+
+def test_second_forms_gray_only_shrinks_with_boxes(ctx):
+    """On the GPU as in the oracle: adding the boxes keeps every red edge
+    and can only turn gray edges green."""
+    from paper_2603_28674_amd import rgg
+    w = workload("arm", n_updates=2, seed=47)
+    a = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK)
+    b = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK, outer_obb=True)
+    la, _, na, _ = a.update(w.absent(), w.boxes[0])
+    lb, _, nb, _ = b.update(w.absent(), w.boxes[0])
+    assert np.array_equal(la == 2, lb == 2)
+    assert np.all((la == lb) | ((la == 1) & (lb == 0)))
+    assert nb < na
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("kind", ["spatial", "arm"])
+def test_second_forms_save_load(ctx, tmp_path, kind):
+    """A roadmap built with both second forms is saved, loaded (boxes and
+    splines read back, not recomputed) and keeps giving the oracle's labels."""
+    from paper_2603_28674_amd import rgg
+    import oracle
+    mode = dict(outer_obb=True, inner_splines=True)
+    w = workload(kind, n_updates=4, seed=48)
+    print(f"[persist] {w.name} E={w.n_edges} {mode}", flush=True)
+    g = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK, **mode)
+    o = oracle.from_workload(w, **mode)
+    prev = w.absent()
+    for u in range(2):
+        g.update(prev, w.boxes[u])
+        o.update(prev, w.boxes[u])
+        prev = w.boxes[u]
+    path = tmp_path / "forms.rgg"
+    g.save(path)
+    h = rgg.Roadmap.load(ctx, path)
+    assert np.array_equal(g.labels(), h.labels())
+    for u in range(2, 4):
+        ol, og = o.update(prev, w.boxes[u])
+        for name, r in (("saved", g), ("loaded", h)):
+            lab, gray, n, res = r.update(prev, w.boxes[u])
+            assert res.status == 0
+            assert np.array_equal(lab, ol), f"{name} update {u}: labels differ from the oracle"
+            assert n == len(og) and np.array_equal(gray, og), f"{name} update {u}: gray list differs"
+        prev = w.boxes[u]
+    g.close()
+    h.close()

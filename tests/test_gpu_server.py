@@ -217,3 +217,45 @@ def test_server_non_lazy(ctx):
                 assert torch.all(ver == 77)
     for g in gs:
         g.close()
+
+
+def test_server_admission_by_free_memory_and_timing(ctx):
+    """pool_bytes = 0 sizes the admitting pool from the free device memory
+    (1/64 of it, within [16 MiB, 256 MiB]); a pool larger than the free memory
+    is refused.  Every request's time splits into queue wait and service,
+    and its results are still the oracle's."""
+    import torch
+    from paper_2603_28674_amd import rgg
+    free, total = torch.cuda.mem_get_info()
+    srv = rgg.rgg_server_start(ctx)
+    info = rgg.rgg_server_info(srv)
+    rgg.rgg_server_stop(srv)
+    want = min(max(info["free_bytes_at_start"] // 64, 16 << 20), 256 << 20)
+    assert info["pool_bytes"] == want
+    assert 0 < info["free_bytes_at_start"] <= total
+    with pytest.raises(rgg.RggError) as ei:
+        rgg.rgg_server_start(ctx, pool_bytes=1 << 60)
+    assert ei.value.status == rgg.RGG_E_OUT_OF_MEMORY
+    # timing split, with results checked
+    n_updates = 3
+    specs = roadmap_specs(n_updates)[:4]
+    expect = oracle_results(specs, n_updates)
+    dev = torch.device("cuda:0")
+    gs = [rgg.Roadmap.from_workload(ctx, w, precision=p, cell_size=c) for w, p, c, *_ in specs]
+    srv = rgg.rgg_server_start(ctx, n_streams=2, max_batch=2)
+    tickets = []
+    for u in range(n_updates):
+        for k, (w, *_) in enumerate(specs):
+            lab = torch.zeros(w.n_edges, dtype=torch.uint8, device=dev)
+            prev = w.absent() if u == 0 else w.boxes[u - 1]
+            tickets.append((k, u, lab, rgg.rgg_server_submit(srv, gs[k].h, prev, w.boxes[u], lab.data_ptr())))
+    for k, u, lab, t in tickets:
+        done, r, tm = rgg.rgg_server_poll_timing(srv, t, wait=True)
+        assert done and r.status == 0
+        assert np.array_equal(lab.cpu().numpy(), expect[k][u][0])
+        assert tm["queue_us"] >= 0.0 and tm["service_us"] > 0.0
+        assert abs(tm["latency_us"] - (tm["queue_us"] + tm["service_us"])) < 1.0
+        assert 1 <= tm["batch_size"] <= 2
+    rgg.rgg_server_stop(srv)
+    for g in gs:
+        g.close()

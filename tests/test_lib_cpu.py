@@ -72,6 +72,63 @@ def test_host_geometry_bitwise_equals_oracle(oracle_lib, kind):
         assert np.all(box[e, 3:3 + D].astype(np.float64) >= hi.max(axis=0))
 
 
+@pytest.mark.parametrize("kind", [synth.SE2, synth.SE3, synth.ARM])
+@pytest.mark.parametrize("tol", [0.05, 0.3])
+def test_host_second_forms_bitwise_equal_oracle(oracle_lib, kind, tol):
+    """The oriented boxes and spline segments of the host build equal the
+    oracle's bit for bit (separate code, the same stated binary64 steps)."""
+    w = _small(kind, seed=4)
+    keep = rgg._Keep()
+    desc = rgg.make_desc(w.q, w.edges, keep)
+    robot = rgg.make_robot(w.robot, keep)
+    opts = rgg.make_opts(w.resolution, w.samples_per_edge, n_obstacle_slots=w.n_slots, outer_obb=True,
+                         inner_splines=True, spline_tol=tol)
+    E, B, D = w.n_edges, w.robot.n_spheres, w.robot.dim
+    obb, (cnt, seg) = rgg.rgg_debug_second_forms(desc, robot, opts, 0, E)
+    orc = oracle_lib.from_workload(w, threads=2, outer_obb=True, inner_splines=True, spline_tol=tol)
+    nb = obb.shape[1]
+    row = 0
+    shortened = 0
+    for e in range(E):
+        for b in range(nb):
+            o = orc.obb(e, b)
+            if o is None:
+                assert not np.any(obb[e, b])
+                continue
+            mine = obb[e, b]
+            want = np.concatenate([o[0], o[1].reshape(-1), o[2]])
+            assert np.array_equal(mine.view(np.uint64), want.view(np.uint64)), f"edge {e} body {b} box differs"
+        for i in range(B):
+            os_ = orc.spline(e, i)
+            assert cnt[e, i] == len(os_), f"edge {e} sphere {i}: segment count"
+            mine = seg[row:row + cnt[e, i]]
+            row += cnt[e, i]
+            assert np.array_equal(mine.view(np.uint64), os_.view(np.uint64)), f"edge {e} sphere {i} spline"
+            shortened += int(cnt[e, i] < orc.n_configs(e) - 1)
+    assert row == len(seg) and shortened > 0
+    # a part of the range gives the same records
+    obb2, (cnt2, seg2) = rgg.rgg_debug_second_forms(desc, robot, opts, 3, 9)
+    assert np.array_equal(obb2, obb[3:9]) and np.array_equal(cnt2, cnt[3:9])
+    start = int(cnt[:3].sum())
+    assert np.array_equal(seg2, seg[start:start + len(seg2)])
+
+
+def test_bad_second_form_options():
+    w = _small(synth.SE2)
+    keep = rgg._Keep()
+    desc = rgg.make_desc(w.q, w.edges, keep)
+    robot = rgg.make_robot(w.robot, keep)
+    for kw in (dict(inner_splines=True, spline_tol=1.0), dict(inner_splines=True, spline_tol=-0.5),
+               dict(inner_splines=True, spline_tol=float("nan"))):
+        opts = rgg.make_opts(w.resolution, w.samples_per_edge, n_obstacle_slots=w.n_slots, **kw)
+        with pytest.raises(rgg.RggError):
+            rgg.rgg_debug_second_forms(desc, robot, opts, 0, w.n_edges)
+    opts = rgg.make_opts(w.resolution, w.samples_per_edge, n_obstacle_slots=w.n_slots)
+    opts.outer_obb = 2
+    with pytest.raises(rgg.RggError):
+        rgg.rgg_debug_second_forms(desc, robot, opts, 0, w.n_edges)
+
+
 def test_partial_range_matches_full():
     w = _small(synth.SE3, seed=9)
     keep = rgg._Keep()
@@ -185,7 +242,7 @@ def _fnv1a64(data: bytes) -> int:
 
 
 def _roadmap_file(configs, checksum_ok=True):
-    """A planar one-sphere roadmap file, format version 2, whose edges hold
+    """A planar one-sphere roadmap file, format version 3, whose edges hold
     `configs[e]` configurations each; the checksum is recomputed over the
     crafted bytes (as anyone editing such a file can do)."""
     D, B, E, M, dof = 2, 1, len(configs), 1, 3
@@ -197,7 +254,7 @@ def _roadmap_file(configs, checksum_ok=True):
         ("chunk", "<i4"), ("retest", "<i4"), ("E", "<i8"), ("M", "<i8"), ("band", "<f4"),
         ("one_cell", "<i4"), ("cell", "<f8"), ("n_samp", "<i8"), ("n_cap", "<i8")]))
     assert hdr.dtype.itemsize == 80
-    hdr[0] = (b"RGGMAP01", 2, D, B, 1, 256, 1024, E, M, 1e-5, 1, float("inf"), n_samp, n_cap)
+    hdr[0] = (b"RGGMAP01", 3, D, B, 1, 256, 1024, E, M, 1e-5, 1, float("inf"), n_samp, n_cap)
     samp = np.linspace(0.0, 1.0, max(n_samp, 1))[:n_samp]
     cap = np.zeros(n_cap)
     cap[2 * D * B:: (2 * D + 1) * B] = 0.5
@@ -213,8 +270,9 @@ def _roadmap_file(configs, checksum_ok=True):
     vrob["rad"][0, 0] = 0.25
     motion = np.zeros(E * (2 * dof + 3))
     delta = np.zeros(E * B)
+    forms = np.array([0, 1], dtype=np.int32)          # capsules and copies; one body
     body = b"".join(a.tobytes() for a in (hdr, soff, samp, cap, radius, aabb, resident, cnt, vrob,
-                                          motion, delta))
+                                          motion, delta, forms))
     s = _fnv1a64(body) ^ (0 if checksum_ok else 1)
     return body + np.array([s], dtype=np.uint64).tobytes()
 
