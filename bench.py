@@ -68,6 +68,9 @@ def parse():
                    help="skip the full validation of the last update's gray list")
     p.add_argument("--cpu-validate-edges", type=int, default=2000,
                    help="gray edges the oracle validates for the CPU comparison")
+    p.add_argument("--only", choices=["arm", "batched"], default=None,
+                   help="run one further configuration alone (for profiling): the planar arm on the plain "
+                        "path, or the batched planar roadmaps; prints that section as the JSON line")
     p.add_argument("--copy-calibration", action="store_true",
                    help="also run a plain 1 GiB device copy 5 times (reference kernel for "
                         "scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -109,6 +112,37 @@ def cpu_host():
         aff = None
     return {"model": model, "cpus_reported": os.cpu_count(), "cpus_allowed": aff,
             "threads_used": cpu_threads(), "share_per_gpu": CPU_SHARE}
+
+
+def pair_bytes(r):
+    """Algorithmic bytes of one update's balanced pair testing (k_pairs;
+    zero unless the roadmap lists pairs) or, in the FP64 mode, of its item
+    kernel (k_item64): the classify bytes less the FP32 item kernel's and the
+    binary64 pass's."""
+    return r.test_bytes - r.item_bytes - r.fp64_bytes
+
+
+def item_bytes(r, fp64):
+    """Algorithmic bytes of one update's item kernel: k_item32 (pair listing
+    and the inline pair tests) in the FP32 mode, k_item64 in the FP64 mode."""
+    return pair_bytes(r) if fp64 else r.item_bytes
+
+
+def stages(ms, n, fp64):
+    """Milliseconds per update of each stage from rgg_timing_read's sums."""
+    n = max(n, 1)
+    return {"diff": ms[0] / n, "cells": ms[1] / n, "item_kernel": (ms[3] if fp64 else ms[2]) / n,
+            "pair_testing": 0.0 if fp64 else ms[3] / n, "fp64_pass": ms[4] / n, "labels": ms[5] / n}
+
+
+def item_rooflines(kernel, timed, stage, fp64):
+    """The item kernel's roofline (and the pair testing's, when it ran)."""
+    out = {"roofline": roofline(kernel, float(np.mean([item_bytes(r, fp64) for r in timed])),
+                                stage["item_kernel"])}
+    pb = float(np.mean([pair_bytes(r) for r in timed]))
+    if not fp64 and pb > 0:
+        out["roofline_pairs"] = roofline(kernel.replace("k_item32", "k_pairs"), pb, stage["pair_testing"])
+    return out
 
 
 def roofline(kernel, bytes_per_launch, kernel_ms, note=None):
@@ -253,12 +287,12 @@ def batched_planar(a):
     # the stages' own times, HIP events on the stream between the kernels
     rgg.rgg_batch_timing_enable(batch, True)
     rgg.rgg_batch_timing_read(batch)
-    item_bytes = []
+    batch_item_bytes = []   # the batched item kernels count their bytes as pair testing
     for _ in range(K):
         batched(u)
         u += 1
         torch.cuda.synchronize()
-        item_bytes.append(sum(rgg.result_from_tensor(b[3]).test_bytes for b in bufs))
+        batch_item_bytes.append(sum(pair_bytes(rgg.result_from_tensor(b[3])) for b in bufs))
     sms, nt = rgg.rgg_batch_timing_read(batch)
     rgg.rgg_batch_timing_enable(batch, False)
     ok = ok and all(rgg.result_from_tensor(b[3]).status == 0 for b in bufs)
@@ -284,7 +318,7 @@ def batched_planar(a):
                            "note": "classify bytes of all roadmaps per round over the round's wall time "
                                    "(all stages, pipelined rounds): a lower bound for k_item32_batch"},
         "stage_ms_per_round": stage,
-        "roofline": roofline("k_item32_batch<2>", float(np.mean(item_bytes)), stage["item"],
+        "roofline": roofline("k_item32_batch<2>", float(np.mean(batch_item_bytes)), stage["item"],
                              "classify bytes of the 64 roadmaps of a round over the batched item kernel's "
                              "HIP-event time"),
         "cpu_baseline": cpu,
@@ -373,10 +407,10 @@ def plain_config(ctx, w, precision, cell_size, K, W, what, do_tune=True, kernel=
     g.close()
     stats = {k: float(np.mean([getattr(r, k) for r in results]))
              for k in ("n_changed", "n_pairs", "n_outer_hits", "n_rechecked", "n_gray", "test_bytes")}
-    stage = {"diff": ms[0] / n_timed, "cells": ms[1] / n_timed, "classify": ms[3] / n_timed,
-             "fp64_pass": ms[4] / n_timed, "labels": ms[5] / n_timed}
+    fp64 = precision == rgg.RGG_PREC_FP64
+    stage = stages(ms, n_timed, fp64)
     out = {"workload": what, "edges": E, "obstacle_slots": w.n_slots,
-           "precision": "fp64" if precision == rgg.RGG_PREC_FP64 else "fp32+fp64 re-test",
+           "precision": "fp64" if fp64 else "fp32+fp64 re-test",
            "cell_size": info["cell_size"], "item_edges": info["item_edges"], "autotune": tuned,
            "device_bytes": info["device_bytes"], "updates": K,
            "edges_per_s": E * K / wall, "ms_per_update": wall / K * 1e3,
@@ -385,7 +419,7 @@ def plain_config(ctx, w, precision, cell_size, K, W, what, do_tune=True, kernel=
            "stage_ms_per_update": stage,
            "per_update": stats, "status_ok": all(r.status == 0 for r in results)}
     if kernel:
-        out["roofline"] = roofline(kernel, float(np.mean([r.test_bytes for r in timed])), stage["classify"])
+        out.update(item_rooflines(kernel, timed, stage, fp64))
     if cpu:
         n_up = 1 + W + 3 * K - 1
         rng = np.random.default_rng(97)
@@ -691,6 +725,22 @@ def main():
     import torch
     from paper_2603_28674_amd import rgg, synth
 
+    if a.only:
+        out = {"only": a.only}
+        if a.only == "arm":
+            a.no_second_forms = True
+            K, W = a.steps, a.warmup
+            ctx = rgg.rgg_context_create(0)
+            w = synth.planar_arm(n_updates=1 + W + 3 * K)
+            out["arm_fp32"] = plain_config(ctx, w, rgg.RGG_PREC_FP32_RECHECK, a.cell_size, K, W, "planar arm",
+                                           not a.no_tune, "k_item32<2>", None, item_edges=a.item_edges)
+        else:
+            out["batched_planar"] = batched_planar(a)
+        if a.copy_calibration:
+            copy_calibration(torch)
+        print(json.dumps(out), flush=True)
+        return
+
     K, W = a.steps, a.warmup
     n_updates = W + 5 * K
     log(f"[bench] generating spatial workload: {a.nodes} nodes, {n_updates} updates")
@@ -776,7 +826,7 @@ def main():
     lat_cold = np.array(lat_cold)
     results += [rgg.result_from_tensor(res[u]) for u in range(first + 2 * K, first + 4 * K)]
     assert all(r.status == 0 for r in results), "update failed"
-    cold_bytes = float(np.mean([r.test_bytes for r in results[3 * K:4 * K]]))
+    cold_bytes = float(np.mean([item_bytes(r, False) for r in results[3 * K:4 * K]]))
     final_labels = labels.cpu().numpy()
     last = first + 4 * K - 1
 
@@ -827,11 +877,13 @@ def main():
             rgg.rgg_graph_destroy(h)
         g2.close()
 
-    test_bytes = np.mean([r.test_bytes for r in results[K:2 * K]])   # the event-timed updates
+    timed_res = results[K:2 * K]   # the event-timed updates
+    st = stages(ms, n_timed, False)
+    test_bytes = float(np.mean([item_bytes(r, False) for r in timed_res]))
     stats_tp = {k: float(np.mean([getattr(r, k) for r in results[:K]]))   # the throughput pass
                 for k in ("n_pairs", "n_outer_hits", "test_bytes")}
     copy_gbs = copy_bandwidth(torch, dev)
-    test_ms = ms[3] / max(n_timed, 1)
+    test_ms = st["item_kernel"]
     achieved = test_bytes / (test_ms * 1e-3) / 1e9
     stats = {k: float(np.mean([getattr(r, k) for r in results]))
              for k in ("n_changed", "n_candidate_edges", "n_pairs", "n_outer_hits", "n_rechecked",
@@ -866,16 +918,14 @@ def main():
                          "latency_p99_us": float(np.percentile(host_lat, 99)), "updates": int(n_host),
                          "note": "rgg_update: boxes uploaded from host memory, labels and gray ids "
                                  "copied back to host memory; one update at a time"},
-        "stage_ms_per_update": {"diff": ms[0] / n_timed, "cells": ms[1] / n_timed,
-                                "classify": ms[3] / n_timed, "fp64_pass": ms[4] / n_timed,
-                                "labels": ms[5] / n_timed},
+        "stage_ms_per_update": st,
         "per_update": stats,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("k_item32<3>"),
                      "kernel": "k_item32<3>", "bytes_per_launch": test_bytes,
                      "kernel_ms": test_ms, "copy_GBps": copy_gbs,
                      "frac_of_copy": achieved / copy_gbs},
-        "roofline_cold": roofline("k_item32<3>", cold_bytes, ms_cold[3] / max(n_cold, 1),
+        "roofline_cold": roofline("k_item32<3>", cold_bytes, stages(ms_cold, n_cold, False)["item_kernel"],
                                   "the same kernel with the caches flushed before every update (a 1 GiB "
                                   "buffer rewritten: more than the 256 MB Infinity Cache)"),
         "work_rates": {"pairs_per_s": stats_tp["n_pairs"] * K / wall,
@@ -912,13 +962,20 @@ def main():
         log("[bench] serving")
         line["serving"] = serving(a)
     if a.copy_calibration:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        line["copy_calibration_bytes"] = src.numel() * 4
+        line["copy_calibration_bytes"] = copy_calibration(torch)
     print(json.dumps(line), flush=True)
+
+
+def copy_calibration(torch):
+    """A plain 1 GiB device copy, 5 times, and a 1 GiB fill: the reference
+    kernels of known size for scaling FETCH_SIZE / WRITE_SIZE."""
+    dev = torch.device("cuda:0")
+    src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    return src.numel() * 4
 
 
 if __name__ == "__main__":

@@ -84,6 +84,11 @@ typedef int32_t rgg_status;
                                      the rounding band is re-tested in
                                      binary64, so labels equal the FP64 ones */
 
+/* rgg_build_opts.inline_rounds: how the FP32 mode splits the pair tests
+ * between the blocks that list an item's pairs and the balanced pair testing */
+#define RGG_INLINE_ALL 0          /* every round (one fused kernel; default)   */
+#define RGG_INLINE_NONE (-1)      /* no round (every pair listed)              */
+
 /* A closed axis-aligned box.  Planar roadmaps use indices 0 and 1; indices 2
  * must still be finite.  A box with lo[k] > hi[k] on any used axis is ABSENT:
  * it meets nothing.  The canonical ABSENT box, held by every slot after
@@ -171,6 +176,22 @@ typedef struct {
                                      copies.  0: copies                         */
     double spline_tol;            /* shortcut tolerance, a fraction of the
                                      sphere's radius in (0, 1); 0 selects 0.05 */
+    int32_t pair_list_capacity;   /* FP32 mode with pair listing (see
+                                     inline_rounds): pairs each of the 2048
+                                     listing blocks may hand to the balanced
+                                     pair testing (rounds that do not fit it
+                                     tests itself); 0 = 512, at most 2^20.  Any
+                                     value gives the same labels                */
+    int32_t inline_rounds;        /* FP32 mode: pair rounds (of up to 256 pairs)
+                                     of each work item that its listing block
+                                     tests itself before it lists the rest for
+                                     the balanced pair testing.  RGG_INLINE_ALL
+                                     (0, the default) = every round: one fused
+                                     kernel, no pair lists allocated, the pair
+                                     testing not launched; n > 0 = the first n
+                                     rounds (at most 2^20); RGG_INLINE_NONE =
+                                     none, every round listed.  Any value gives
+                                     the same labels                            */
     int64_t mem_budget;           /* device bytes the roadmap may hold; 0 = the
                                      free device memory.  A roadmap whose arrays
                                      would need more (rgg_roadmap_info's
@@ -193,7 +214,12 @@ typedef struct {
     int64_t n_outer_hits;         /* pairs whose outer approximation met        */
     int64_t n_rechecked;          /* pairs re-decided in binary64               */
     int64_t n_cells_visited;      /* (cell, edge) entries scanned by the grid   */
-    int64_t test_bytes;           /* bytes the classify kernel read and wrote   */
+    int64_t test_bytes;           /* bytes the classify kernels read and wrote:
+                                     the item kernel, the balanced pair testing
+                                     and the binary64 pass together             */
+    int64_t item_bytes;           /* the FP32 item kernel's part of test_bytes
+                                     (its pair listing and inline pair tests)   */
+    int64_t fp64_bytes;           /* the binary64 pass's part of test_bytes     */
 } rgg_update_result;
 
 typedef struct {
@@ -542,9 +568,12 @@ rgg_status rgg_gray_list(rgg_roadmap *rm, int64_t *out, int64_t cap, int64_t *n)
 /* Per-update kernel timing with HIP events on the update's stream (off by
  * default).  rgg_timing_read returns the summed milliseconds of each stage
  * over the updates since the last read, and resets them:
- * ms[0] diff, ms[1] grid cells, ms[2] grid scan, ms[3] classify, ms[4] FP64
- * re-test, ms[5] labels and gray compaction.  *n_updates receives the number
- * of updates timed. */
+ * ms[0] diff, ms[1] grid cells, ms[2] the FP32 item kernel (pair listing
+ * and the inline pair tests: every test by default), ms[3] the balanced pair
+ * testing (FP32 mode with pair listing) or the binary64 item kernel (FP64
+ * mode), ms[4] FP64 re-test, ms[5] labels and gray compaction.  *n_updates
+ * receives the number of updates timed.  Each event adds a few microseconds
+ * to the timeline of a timed update. */
 rgg_status rgg_timing_enable(rgg_roadmap *rm, int32_t on);
 rgg_status rgg_timing_read(rgg_roadmap *rm, double ms[6], int64_t *n_updates);
 

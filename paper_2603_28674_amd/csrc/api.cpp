@@ -405,7 +405,16 @@ struct RoadmapParams {
     double band_rel;           // as rgg_build_opts.band_rel
     int32_t retest_capacity;   // as rgg_build_opts.retest_capacity
     int32_t chunk;             // edges per work item
+    int32_t pair_list_capacity;   // as rgg_build_opts.pair_list_capacity
+    int32_t inline_rounds;        // RmDev::inline_rounds (resolved: 0..2^20 or kInlineAll)
 };
+
+// RmDev::inline_rounds for rgg_build_opts.inline_rounds
+int32_t inline_rounds_of(int32_t opt)
+{
+    if (opt == RGG_INLINE_ALL) return kInlineAll;
+    return opt == RGG_INLINE_NONE ? 0 : opt;
+}
 
 rgg_status hip_ok(hipError_t e, const char *what) { return e == hipSuccess ? RGG_OK : hip_fail(e, what); }
 
@@ -450,6 +459,15 @@ int64_t device_bytes_needed(const HostGeometry &g, const HostGrid &grid, const R
     add((size_t)kStatBlocks * rc_cap, sizeof(int2));
     add((size_t)kStatBlocks, 4);
     add((size_t)kStatBlocks, 4);
+    if (p.mixed) {
+        add((size_t)kStatBlocks, 4);
+        if (p.inline_rounds != kInlineAll) {
+            const int32_t pl_cap = p.pair_list_capacity > 0 ? p.pair_list_capacity : kPairListCap;
+            add((size_t)kStatBlocks * pl_cap, sizeof(int2));
+            add((size_t)kStatBlocks * rt_cap_of(pl_cap), sizeof(int2));
+            add((size_t)kStatBlocks, 4);
+        }
+    }
     add((size_t)kStatBlocks * kStats, 8);
     add((size_t)ntiles + 1, 4);
     add((size_t)ntiles, 8);
@@ -598,6 +616,24 @@ rgg_status make_roadmap(rgg_context *ctx, const HostGeometry &g, const HostGrid 
     if ((st = rm->alloc(&dv.rc, (size_t)kStatBlocks * dv.rc_cap, "re-test regions")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.rc_cnt, (size_t)kStatBlocks, "re-test counts")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.df_cnt, (size_t)kStatBlocks, "deferred counts")) != RGG_OK) return guard(st);
+    if (mixed) {
+        dv.pl_cap = p.pair_list_capacity > 0 ? p.pair_list_capacity : kPairListCap;
+        dv.inline_rounds = p.inline_rounds;
+        int slots = 0;
+        const hipError_t he = test_blocks_resident(dv.D, ctx->device, &slots);
+        if (he != hipSuccess) return guard(hip_fail(he, "occupancy query"));
+        dv.test_slots = slots;
+        // the listing kernel writes its blocks' pair counts in every form;
+        // the lists and the shares' re-test regions exist only with listing
+        if ((st = rm->alloc(&dv.pl_cnt, (size_t)kStatBlocks, "pair list counts")) != RGG_OK) return guard(st);
+        if (dv.inline_rounds != kInlineAll) {
+            if ((st = rm->alloc(&dv.pl, (size_t)kStatBlocks * dv.pl_cap, "pair lists")) != RGG_OK) return guard(st);
+            if ((st = rm->alloc(&dv.rt, (size_t)kStatBlocks * rt_cap_of(dv.pl_cap), "share re-test regions")) !=
+                RGG_OK)
+                return guard(st);
+            if ((st = rm->alloc(&dv.rt_cnt, (size_t)kStatBlocks, "share re-test counts")) != RGG_OK) return guard(st);
+        }
+    }
     if ((st = rm->alloc(&dv.blk_stats, (size_t)kStatBlocks * kStats, "statistics")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.tile_cnt, (size_t)dv.ntiles + 1, "tile counts")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.tile_state, (size_t)dv.ntiles, "tile states")) != RGG_OK) return guard(st);
@@ -651,6 +687,14 @@ rgg_status make_roadmap(rgg_context *ctx, const HostGeometry &g, const HostGrid 
     if ((st = hip_ok(hipMemset(dv.tile_state, 0, sizeof(unsigned long long) * dv.ntiles), "clear tile states")) != RGG_OK) return guard(st);
     if ((st = hip_ok(hipMemset(dv.rc_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear re-test counts")) != RGG_OK) return guard(st);
     if ((st = hip_ok(hipMemset(dv.df_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear deferred counts")) != RGG_OK) return guard(st);
+    if (mixed) {
+        if ((st = hip_ok(hipMemset(dv.pl_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear pair list counts")) != RGG_OK)
+            return guard(st);
+        if (dv.rt_cnt &&
+            (st = hip_ok(hipMemset(dv.rt_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear share re-test counts")) !=
+                RGG_OK)
+            return guard(st);
+    }
     if ((st = hip_ok(hipMemset(dv.blk_stats, 0, sizeof(unsigned long long) * kStatBlocks * kStats), "clear statistics")) != RGG_OK) return guard(st);
     if ((st = hip_ok(hipMemset(rm->d_labels, 0, std::max<int64_t>(E, 1)), "clear labels")) != RGG_OK) return guard(st);
     if ((st = hip_ok(hipHostMalloc((void **)&rm->h_stage, sizeof(rgg_box) * std::max<int64_t>(2 * M, 1)), "pinned staging")) != RGG_OK) return guard(st);
@@ -693,7 +737,8 @@ rgg_status rgg_build(rgg_context *ctx, const rgg_roadmap_desc *rd, const rgg_rob
     if (st != RGG_OK) return fail(st, "%s", err.c_str());
 
     const RoadmapParams p = {opts->n_obstacle_slots, opts->precision == RGG_PREC_FP32_RECHECK, opts->band_rel,
-                             opts->retest_capacity, chunk};
+                             opts->retest_capacity, chunk, opts->pair_list_capacity,
+                             inline_rounds_of(opts->inline_rounds)};
     if ((st = admit_roadmap(device_bytes_needed(g, grid, p), opts->mem_budget)) != RGG_OK) return st;
     rgg_roadmap *rm = nullptr;
     if ((st = make_roadmap(ctx, g, grid, p, nullptr, nullptr, &rm)) != RGG_OK) return st;
@@ -1414,7 +1459,7 @@ namespace {
 // Roadmap files: a header, the binary64 geometry, the state, and an FNV-1a
 // 64-bit checksum of every preceding byte.  Host byte order.
 constexpr char kMagic[8] = {'R', 'G', 'G', 'M', 'A', 'P', '0', '1'};
-constexpr uint32_t kFileVersion = 3;
+constexpr uint32_t kFileVersion = 4;
 
 struct FileHeader {
     char magic[8];
@@ -1471,6 +1516,8 @@ struct FileIn {
 // What a roadmap file holds, read back on the host.
 struct LoadedFile {
     FileHeader h;
+    int32_t pl_cap = 0;        // pair-list capacity (0 in the FP64 mode)
+    int32_t inline_rounds = 0; // RmDev::inline_rounds (0 in the FP64 mode)
     HostGeometry g;
     std::vector<rgg_box> resident;
     std::vector<int2> cnt;
@@ -1564,7 +1611,7 @@ rgg_status rgg_save(rgg_roadmap *rm, const char *path)
     out.put(vrob.data(), sizeof(VRobot));
     out.put(vmot.data(), sizeof(double) * vmot.size());
     out.put(vdel.data(), sizeof(double) * vdel.size());
-    const int32_t forms[2] = {dv.mode, dv.nbody};
+    const int32_t forms[4] = {dv.mode, dv.nbody, dv.pl_cap, dv.inline_rounds};
     out.put(forms, sizeof forms);
     out.put(obb.data(), sizeof(double) * obb.size());
     out.put(sseg.data(), sizeof(int64_t) * sseg.size());
@@ -1658,12 +1705,16 @@ static rgg_status read_roadmap_file(const char *path, LoadedFile *L)
     in.get(g.motion.data(), sizeof(double) * g.motion.size());
     in.get(g.delta.data(), sizeof(double) * g.delta.size());
     // the second forms: mode bits and body count, then the boxes and splines
-    int32_t forms[2] = {0, 0};
+    // and the pair-list capacity and inline rounds of the FP32 mode
+    int32_t forms[4] = {0, 0, 0, 0};
     in.get(forms, sizeof forms);
     if (!in.ok) return fail(RGG_E_INVALID_ARG, "%s is truncated", path);
     const int nb = vr.kind == RGG_PLANAR_ARM ? vr.L : 1;
-    if ((forms[0] & ~(kModeObb | kModeSplines)) != 0 || forms[1] != nb)
+    if ((forms[0] & ~(kModeObb | kModeSplines)) != 0 || forms[1] != nb || forms[2] < 0 ||
+        forms[2] > (1 << 20) || (forms[3] != kInlineAll && (forms[3] < 0 || forms[3] > (1 << 20))))
         return fail(RGG_E_INVALID_ARG, "%s: inconsistent approximation forms", path);
+    L->pl_cap = forms[2];
+    L->inline_rounds = forms[3];
     g.n_bodies = nb;
     g.body.assign((size_t)h.B, 0);
     g.body_has.assign((size_t)nb, 0);
@@ -1719,7 +1770,8 @@ rgg_status rgg_load(rgg_context *ctx, const char *path, rgg_roadmap **out)
     std::string err;
     rgg_status st = build_grid(g, h.one_cell ? -1.0 : h.cell, h.chunk, &grid, &err);
     if (st != RGG_OK) return fail(st, "%s", err.c_str());
-    const RoadmapParams p = {h.M, h.mixed != 0, (double)h.band_rel, h.retest_capacity, h.chunk};
+    const RoadmapParams p = {h.M, h.mixed != 0, (double)h.band_rel, h.retest_capacity, h.chunk, L.pl_cap,
+                             L.inline_rounds};
     if ((st = admit_roadmap(device_bytes_needed(g, grid, p), 0)) != RGG_OK) return st;
     rgg_roadmap *rm = nullptr;
     if ((st = make_roadmap(ctx, g, grid, p, L.resident.data(), L.cnt.data(), &rm)) != RGG_OK) return st;

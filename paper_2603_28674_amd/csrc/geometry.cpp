@@ -492,6 +492,10 @@ rgg_status validate_build_inputs(const rgg_roadmap_desc *rd, const rgg_robot *r,
     if (o->item_edges < 0 || o->item_edges > 512) return bad("item_edges must be 0..512");
     if (std::isnan(o->cell_size)) return bad("cell_size is NaN");
     if (o->mem_budget < 0) return bad("mem_budget must be 0 (the free device memory) or positive");
+    if (o->pair_list_capacity < 0 || o->pair_list_capacity > (1 << 20))
+        return bad("pair_list_capacity must be 0..2^20");
+    if (o->inline_rounds < RGG_INLINE_NONE || o->inline_rounds > (1 << 20))
+        return bad("inline_rounds must be RGG_INLINE_NONE, RGG_INLINE_ALL or a round count up to 2^20");
     if (o->outer_obb != 0 && o->outer_obb != 1) return bad("outer_obb must be 0 or 1");
     if (o->inner_splines != 0 && o->inner_splines != 1) return bad("inner_splines must be 0 or 1");
     if (o->inner_splines && !(o->spline_tol >= 0.0 && o->spline_tol < 1.0))

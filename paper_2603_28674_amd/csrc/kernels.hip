@@ -12,8 +12,12 @@
 //               changed boxes of the cell, outer test (per-sphere capsule vs
 //               box), inner test (copies of the spheres whose capsule met),
 //               counter update (Sec. 4.1 rule; Alg. 1's intersection lists
-//               kept as counts).  In the FP32 mode a pair whose margin falls
-//               inside the rounding band is left to
+//               kept as counts).  Optionally (inline_rounds) the FP32 item
+//               kernel tests only an item's first pair rounds and lists the
+//               rest for
+//   k_pairs     which cuts the listed pairs into equal shares, one per
+//               block, and runs the same tests on them.  In the FP32 mode a
+//               pair whose margin falls inside the rounding band is left to
 //   k_fp64      which decides it in binary64, one wavefront per pair; an
 //               item whose block ran out of re-test room is then run again
 //               whole in binary64 by the same kernel (skipped otherwise);
@@ -568,6 +572,66 @@ __device__ bool splines_meet64(const RmDev &rm, int64_t e, uint64_t m, const dou
     return false;
 }
 
+// Binary64 decision of one (edge e, changed entry ci) pair by one wavefront:
+// C and S by their definition (capsules, the oriented boxes, then copies or
+// spline segments), added to the edge's counters.  lst: 64 ints of LDS for
+// the wavefront; rad: the binary64 radii in LDS.
+template <int D, int MODE>
+__device__ inline void retest_one(const RmDev &rm, int64_t e, int ci, int *lst, const double *rad, uint32_t &n_outer,
+                                  unsigned long long &bytes)
+{
+    const int lane = lane_id();
+    const int B = rm.B;
+    const ChgEntry &en = rm.chg[ci];
+    double lo[D], hi[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        lo[d] = en.lo[d];
+        hi[d] = en.hi[d];
+    }
+    bool hit = false;
+    if (lane < B) {
+        const double *cp = rm.cap64 + e * (2 * D + 1) * B;
+        double A[D], Bp[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            A[d] = cp[d * B + lane];
+            Bp[d] = cp[(D + d) * B + lane];
+        }
+        const double R = cp[2 * D * B + lane];
+        hit = segbox64<D>(A, Bp, lo, hi) <= R * R;
+    }
+    uint64_t hm = __ballot(hit);
+    bytes += (2 * D + 1) * B * 8;
+    if constexpr ((MODE & kModeObb) != 0) {
+        // spheres whose body's oriented box misses are dropped
+        bool keep = false;
+        uint64_t sp = 0;
+        if (hm && lane < rm.nbody) {
+            sp = rm.body_sph[lane];
+            if (sp & hm) {
+                keep = obb_box_meet64<D>(rm.obb64 + (e * rm.nbody + lane) * obb_words(D), lo, hi);
+                bytes += obb_words(D) * 8;
+            }
+        }
+        uint64_t allowed = keep ? sp : 0ull;
+        for (int o = 32; o > 0; o >>= 1) allowed |= __shfl_xor(allowed, o);
+        hm &= allowed;
+    }
+    if (!hm) return;
+    bool S;
+    if constexpr ((MODE & kModeSplines) != 0) {
+        S = splines_meet64<D>(rm, e, hm, lo, hi, &bytes);
+    } else {
+        const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
+        const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
+        const CopyMap cm = copy_map((int)(P / B));
+        S = copies_meet64<D>(rm, rm.samp64 + copy_stride<D>() * s0, P, cm, hm, lo, hi, rad, lst, &bytes);
+    }
+    ++n_outer;
+    if (lane == 0) add_counts(rm, e, en.sign, S ? en.sign : 0);
+}
+
 // ------------------------------------------------------------------------
 // k_item: one block per work item (grid cell c, a chunk of at most 256 of
 // its edges; the chunk size is the roadmap's work-item size).
@@ -603,17 +667,19 @@ constexpr int kSlots = 2;                 // edge slots per thread
 constexpr int kItemCap = kSlots * kBlock; // edges per work item at most
 constexpr int kWords = kSubTile / 32;     // overlap words per edge
 constexpr int kPairCap = kBlock;          // pairs per round (one per thread)
+static_assert(rt_cap_of(1) == kPairCap, "a share's re-test region holds a round");
 constexpr int kRowCap = 256;              // (pair, sphere) rows per copy round
 constexpr int kOpenCap = 1024;            // capsule tests queued for the exact part
 constexpr int kWideCells = 64;            // pruning-grid cells an entry may cover
 constexpr int kEdgeCells = 64;            // pruning-grid cells an edge may visit
 static_assert(kWords == 4, "a pruning-grid cell holds one uint4 of entry bits");
-static_assert(kSubTile <= 128 && kItemCap <= 512, "a pair is (edge slot << 7) | staged entry in 16 bits");
+static_assert(kSubTile <= 65536 && kItemCap <= 65536, "a pair is (edge slot << 16) | entry in 32 bits");
 static_assert(kLocalCells * 4 == kWords * kItemCap, "the overlap words reuse the pruning grid's storage");
 static_assert(kOpenCap >= 3 * kRowCap + 1, "the rows fit the capsule queue's storage");
+static_assert(kOpenCap * 4 >= kPairCap * 8 + kBlock * 4 + 64 * 8, "the overflow re-test fits the queue's storage");
 
-__device__ inline int pe_slot(int v) { return v >> 7; }
-__device__ inline int pe_entry(int v) { return v & 127; }
+__device__ inline int pe_slot(uint32_t v) { return (int)(v >> 16); }
+__device__ inline int pe_entry(uint32_t v) { return (int)(v & 0xFFFFu); }
 
 template <typename T>
 struct ExactBoxes {
@@ -641,12 +707,13 @@ struct ItemLds {
     int edge[kItemCap], ej[kItemCap];     // edge id, configurations per sphere
     float es[kItemCap];                   // edge s (largest |coordinate| of its box)
     int dC[kItemCap], dS[kItemCap];
-    uint16_t pe[kPairCap];                // edge slot << 7 | staged entry
+    uint32_t pe[kPairCap];                // edge slot << 16 | staged entry
     unsigned long long hm[kPairCap], um[kPairCap];
     uint32_t key[kPairCap];               // probe_key of the deepest capsule hit
     // the capsule-test queue is dead once the exact part has run; the rows
-    // and their copy offsets live after it, in the same storage
-    union {
+    // and their copy offsets live after it, in the same storage, and after
+    // the decisions it is the scratch of a binary64 overflow re-test
+    union alignas(8) {
         uint32_t open[kOpenCap];          // queued (pair << 6 | sphere) capsule tests
         struct {
             uint32_t row[kRowCap];        // pair << 6 | sphere
@@ -658,6 +725,7 @@ struct ItemLds {
     uint32_t sf[kPairCap];
     int wsum[kWaves];
     int rc_n, rc_start, defer, df_n;
+    int pl_n, pl_start;                   // pairs this block listed (pair listing)
     unsigned long long acc[kStats];
 };
 
@@ -722,30 +790,453 @@ __device__ inline uint32_t probe_key(float mg, float t, int sphere)
     return (ordered_key(mg) & 0xFFFF0000u) | (tq << 6) | (uint32_t)sphere;
 }
 
-// deferred == 0: the main pass, one block per item (grid kGrid).  deferred
-// == 1: the binary64 pass over the items the FP32 blocks left whole; block b
-// of that grid takes the item lists of FP32 blocks b, b + gridDim.x, ...
-// deferred == 0: items li0, li0 + lstride, ... of the main pass; statistics
-// row and re-test region blockIdx.x.  deferred == 1: the items left whole in
-// re-test regions li0, li0 + lstride, ... (statistics row li0).
-template <int D, typename T, int MODE>
-__device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0, int lstride)
+// One round of at most kPairCap pairs listed in L.pe (edge slot << 16 |
+// entry): the outer test (capsules, then the oriented boxes), the probe, the
+// inner test (copies or spline segments) and the decisions.  Item blocks
+// (kShare false) sum each edge's counter deltas in L.dC / L.dS and leave
+// their item whole to the binary64 pass when the re-test region is full;
+// pair-share blocks (kShare true: slot and entry are the pair itself) add
+// the deltas to the counters at once and re-test an overflow themselves.
+template <int D, typename T, int MODE, bool kShare, typename Lds>
+__device__ __forceinline__ void test_round(const RmDev &rm, Lds &L, const T *s_rad2, const int *s_lane, int np,
+                                           uint32_t &n_pairs, uint32_t &n_outer, unsigned long long &bytes)
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
     constexpr bool kObb = (MODE & kModeObb) != 0;
     constexpr bool kSpl = (MODE & kModeSplines) != 0;
     constexpr int kSegW = 2 * D + 1;   // values per spline segment
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    const int B = rm.B;
+    const int Gw = 64 / B;
+    const T *capb = kF32 ? (const T *)rm.cap32 : (const T *)rm.cap64;
+    const T *samp = kF32 ? (const T *)rm.samp32 : (const T *)rm.samp64;
+    const float band_rel = rm.band_rel;
+    const int jfix = rm.p_fixed ? rm.p_fixed / B : 0;
+    // coordinates of entry s in the kernel's precision
+    auto box_lo = [&](int k, int s) -> T {
+        if constexpr (kF32) return k == 0 ? L.blo[s].x : (k == 1 ? L.blo[s].y : L.blo[s].z);
+        else return L.x.lo[k][s];
+    };
+    auto box_hi = [&](int k, int s) -> T {
+        if constexpr (kF32) return k == 0 ? L.bhi[s].x : (k == 1 ? L.bhi[s].y : L.bhi[s].z);
+        else return L.x.hi[k][s];
+    };
+    // per-pair results start empty (kPairCap == kBlock: pair tid)
+    if (tid < np) {
+        L.hm[tid] = 0ull;
+        L.um[tid] = 0ull;
+        L.key[tid] = ~0u;
+    }
+    if (tid == 0) L.nopen = 0;
+    __syncthreads();
+    n_pairs += np;
+    // a (pair, sphere) result: capsule hit bits, the deepest hit as
+    // the probe key, undecided bits
+    auto record = [&](int p, int i, int cls, float mg, float tpar) {
+        if (cls == kHit) {
+            atomicOr(&L.hm[p], 1ull << i);
+            atomicMin(&L.key[p], probe_key(mg, tpar, i));
+        } else if (cls == kUnsure) {
+            atomicOr(&L.um[p], 1ull << i);
+        }
+    };
+    // ---- outer test, quick part: lanes = (pair, sphere); each lane
+    // takes two pairs per step and issues both capsules' loads first.
+    // FP32 lanes the quick tests leave open are queued for the exact
+    // part, so the segment-box minimum runs on dense wavefronts.
+    constexpr int kCapU = 2;
+    const int slot = s_lane[lane] >> 8, ci = s_lane[lane] & 255;
+    for (int p0 = 0; p0 < np; p0 += kWaves * Gw * kCapU) {
+        T A[kCapU][D], Bq[kCapU][D], R2[kCapU];
+        int pu[kCapU];
+#pragma unroll
+        for (int u = 0; u < kCapU; ++u) {
+            pu[u] = p0 + (u * kWaves + wv) * Gw + slot;
+            R2[u] = T(0);
+            if (slot < Gw && pu[u] < np) {
+                const int te = pe_slot(L.pe[pu[u]]);
+                const T *cp = capb + (int64_t)L.edge[te] * (2 * D + 1) * B;
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    A[u][k] = cp[k * B + ci];
+                    Bq[u][k] = cp[(D + k) * B + ci];
+                }
+                R2[u] = cp[2 * D * B + ci];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCapU; ++u) {
+            const int p = pu[u];
+            const bool act = slot < Gw && p < np;
+            int cls = kMiss;
+            T lo[D], hi[D];
+            float band = 0.0f, mg = 0.0f, tpar = 0.0f;
+            const T R = R2[u];
+            const T RR = R * R;
+            if (act) {
+                const int s = pe_entry(L.pe[p]);
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    lo[k] = box_lo(k, s);
+                    hi[k] = box_hi(k, s);
+                }
+                if constexpr (kF32) {
+                    const float sc = fmaxf(L.es[pe_slot(L.pe[p])], L.blo[s].w);
+                    float len = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < D; ++k) len += fabsf(Bq[u][k] - A[u][k]);
+                    band = band_of(band_rel, sc, R, len);
+                    float sep = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        sep = fmaxf(sep, fmaxf(lo[k] - fmaxf(A[u][k], Bq[u][k]), fminf(A[u][k], Bq[u][k]) - hi[k]));
+                    const float dA = point_box32<D>(A[u], lo, hi), dB = point_box32<D>(Bq[u], lo, hi);
+                    mg = fminf(dA, dB) - RR;
+                    tpar = dA <= dB ? 0.0f : 1.0f;
+                    cls = (sep > 0.0f && sep * sep - RR > band) ? kMiss : (mg < -band ? kHit : kOpen);
+                } else {
+                    double ts;
+                    const double v = segbox64<D>(A[u], Bq[u], lo, hi, &ts);
+                    cls = v <= RR ? kHit : kMiss;
+                    mg = (float)(v - RR);
+                    tpar = (float)ts;
+                }
+            }
+            if constexpr (kF32) {
+                const bool op = cls == kOpen;
+                const uint64_t ob = __ballot(op);
+                if (ob) {
+                    int base = 0;
+                    if (lane == 0) base = atomicAdd(&L.nopen, __popcll(ob));
+                    base = __shfl(base, 0);
+                    if (op) {
+                        const int q = base + __popcll(ob & lanes_below());
+                        if (q < kOpenCap) {
+                            L.u.open[q] = ((uint32_t)p << 6) | (uint32_t)ci;
+                            cls = kMiss;     // decided by the exact part
+                        } else {
+                            cls = kUnsure;   // queue full: the binary64 re-test decides
+                        }
+                    }
+                }
+            }
+            if (act) record(p, ci, cls, mg, tpar);
+        }
+    }
+    __syncthreads();
+    if constexpr (kF32) {
+        // ---- outer test, exact part: the queued tasks, one per lane
+        const int nq = min(L.nopen, kOpenCap);
+        for (int q = tid; q < nq; q += kBlock) {
+            const uint32_t tk = L.u.open[q];
+            const int p = (int)(tk >> 6), i = (int)(tk & 63u);
+            const uint32_t pv = L.pe[p], te = pe_slot(pv), s = pe_entry(pv);
+            const float *cp = (const float *)capb + (int64_t)L.edge[te] * (2 * D + 1) * B;
+            float A[D], Bq[D], lo[D], hi[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                A[k] = cp[k * B + i];
+                Bq[k] = cp[(D + k) * B + i];
+                lo[k] = box_lo(k, s);
+                hi[k] = box_hi(k, s);
+            }
+            const float R = cp[2 * D * B + i];
+            const float sc = fmaxf(L.es[te], L.blo[s].w);
+            float len = 0.0f;
+#pragma unroll
+            for (int k = 0; k < D; ++k) len += fabsf(Bq[k] - A[k]);
+            float ts;
+            const float mg = segbox32<D>(A, Bq, lo, hi, ts) - R * R;
+            record(p, i, classify_margin(mg, band_of(band_rel, sc, R, len)), mg, ts);
+        }
+        __syncthreads();
+    }
+    if constexpr (kObb) {
+        // ---- oriented boxes: the outer part of sphere i is its
+        // capsule intersected with its body's box, so a sphere
+        // whose body's box misses is dropped (decided in binary64)
+        if (tid < np) {
+            const uint64_t cnd = L.hm[tid] | (kF32 ? L.um[tid] : 0ull);
+            if (cnd) {
+                const uint32_t pv = L.pe[tid], te = pe_slot(pv), s = pe_entry(pv);
+                double lo[D], hi[D];
+                if constexpr (kF32) {
+                    const ChgEntry &en = rm.chg[L.gidx[s]];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        lo[k] = en.lo[k];
+                        hi[k] = en.hi[k];
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        lo[k] = L.x.lo[k][s];
+                        hi[k] = L.x.hi[k][s];
+                    }
+                }
+                const double *ob = rm.obb64 + (int64_t)L.edge[te] * rm.nbody * obb_words(D);
+                uint64_t keep = 0;
+                for (int bd = 0; bd < rm.nbody; ++bd) {
+                    const uint64_t sp = rm.body_sph[bd];
+                    if (!(sp & cnd)) continue;
+                    bytes += obb_words(D) * 8;
+                    if (obb_box_meet64<D>(ob + bd * obb_words(D), lo, hi)) keep |= sp;
+                }
+                L.hm[tid] &= keep;
+                if constexpr (kF32) L.um[tid] &= keep;
+            }
+        }
+        __syncthreads();
+    }
+    // ---- probe: one copy per pair whose capsule met (the copy
+    // form only; a sphere the boxes dropped is not probed)
+    const int p = tid;   // kPairCap == kBlock: this thread's pair
+    uint32_t f = 0;
+    uint64_t hmp = 0;
+    if (p < np) {
+        hmp = L.hm[p];
+        if (hmp && !kSpl && (!kObb || ((hmp >> (L.key[p] & 63u)) & 1ull))) {
+            const uint32_t key = L.key[p];
+            const int i = (int)(key & 63u);
+            const uint32_t pv = L.pe[p], te = pe_slot(pv), s = pe_entry(pv);
+            const int Je = L.ej[te];
+            // the configuration nearest the deepest capsule's closest point
+            const int jj = min(Je - 1, (int)((float)((key >> 6) & 1023u) * (1.0f / 1023.0f) * (float)(Je - 1) + 0.5f));
+            T q[D], lo[D], hi[D];
+            load_copy<D>(samp, (int64_t)L.cfg0[te] * B + (int64_t)i * Je + jj, q);
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                lo[k] = box_lo(k, s);
+                hi[k] = box_hi(k, s);
+            }
+            bytes += D * sizeof(T);
+            if constexpr (kF32) {
+                const float sc = fmaxf(L.es[te], L.blo[s].w);
+                const int cls = classify_margin(point_box32<D>(q, lo, hi) - s_rad2[i],
+                                                band_of(band_rel, sc, L.r.r32[i], 0.0f));
+                f = cls == kHit ? 1u : (cls == kUnsure ? 2u : 0u);
+            } else {
+                f = point_box64<D>(q, lo, hi) <= s_rad2[i] ? 1u : 0u;
+            }
+        }
+        L.sf[p] = f;
+    }
+    // ---- rows: one per (open pair, sphere whose capsule met)
+    const int ra = (p < np && !(f & 1u)) ? __popcll(hmp) : 0;
+    int nrows;
+    const int rpre = block_scan(ra, &nrows, L.wsum);
+    __syncthreads();
+    for (int q0 = 0; q0 < nrows; q0 += kRowCap) {
+        const int nr = min(kRowCap, nrows - q0);
+        if (ra > 0 && rpre < q0 + nr && rpre + ra > q0) {
+            uint64_t m = hmp;
+            int r = rpre;
+            while (m && r < q0 + nr) {
+                const int i = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1;
+                if (r >= q0) L.u.rw.row[r - q0] = ((uint32_t)p << 6) | (uint32_t)i;
+                ++r;
+            }
+        }
+        __syncthreads();
+        // the row's copies (spline segments): fixed count, or a scan
+        // over the rows
+        int ncopies = kSpl ? 0 : nr * jfix;
+        if (kSpl || !jfix) {
+            int cj[2], sum = 0;
+            for (int h = 0; h < 2; ++h) {
+                const int r = tid * 2 + h;
+                cj[h] = 0;
+                if (r < nr) {
+                    const uint32_t rv = L.u.rw.row[r];
+                    const int te = pe_slot(L.pe[rv >> 6]);
+                    if constexpr (kSpl) {
+                        const int64_t k = (int64_t)L.edge[te] * B + (int64_t)(rv & 63u);
+                        const int32_t k0 = rm.sseg[k];
+                        cj[h] = rm.sseg[k + 1] - k0;
+                        L.u.rw.rbase[r] = (uint32_t)k0;
+                    } else {
+                        cj[h] = L.ej[te];
+                    }
+                }
+                sum += cj[h];
+            }
+            const int cpre = block_scan(sum, &ncopies, L.wsum);
+            int acc = cpre;
+            for (int h = 0; h < 2; ++h) {
+                const int r = tid * 2 + h;
+                if (r < nr) L.u.rw.rcopy[r] = acc;
+                acc += cj[h];
+            }
+            if (tid == 0) L.u.rw.rcopy[nr] = ncopies;
+            __syncthreads();
+        }
+        // each thread gathers kCopyU copies (all their loads in
+        // flight together), then tests them
+        constexpr int kCopyU = 4;
+        const T *segb = kF32 ? (const T *)rm.seg32 : (const T *)rm.seg64;
+        for (int c0 = 0; c0 < ncopies; c0 += kBlock * kCopyU) {
+            T q[kCopyU][kSpl ? kSegW : D];
+            int cu_p[kCopyU], cu_i[kCopyU];
+#pragma unroll
+            for (int u = 0; u < kCopyU; ++u) {
+                const int cidx = c0 + u * kBlock + tid;
+                cu_p[u] = -1;
+                cu_i[u] = 0;
+                if (cidx < ncopies) {
+                    int r, jj;
+                    if (!kSpl && jfix) {
+                        r = cidx / jfix;
+                        jj = cidx - r * jfix;
+                    } else {
+                        int lo_ = 0, hi_ = nr - 1;   // last row with rcopy[r] <= cidx
+                        while (lo_ < hi_) {
+                            const int mid = (lo_ + hi_ + 1) >> 1;
+                            if (L.u.rw.rcopy[mid] <= (uint32_t)cidx) lo_ = mid;
+                            else hi_ = mid - 1;
+                        }
+                        r = lo_;
+                        jj = cidx - (int)L.u.rw.rcopy[r];
+                    }
+                    const uint32_t rv = L.u.rw.row[r];
+                    const int pp = (int)(rv >> 6);
+                    const int i = (int)(rv & 63u);
+                    const int te = pe_slot(L.pe[pp]);
+                    if constexpr (kSpl) {
+                        const T *sg = segb + ((int64_t)L.u.rw.rbase[r] + jj) * kSegW;
+#pragma unroll
+                        for (int k = 0; k < kSegW; ++k) q[u][k] = sg[k];
+                    } else {
+                        const int Je = L.ej[te];
+                        load_copy<D>(samp, (int64_t)L.cfg0[te] * B + (int64_t)i * Je + jj, q[u]);
+                    }
+                    cu_p[u] = pp;
+                    cu_i[u] = i;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kCopyU; ++u) {
+                const int pp = cu_p[u];
+                if (pp < 0) continue;
+                const uint32_t pv = L.pe[pp], te = pe_slot(pv), s = pe_entry(pv);
+                T lo[D], hi[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    lo[k] = box_lo(k, s);
+                    hi[k] = box_hi(k, s);
+                }
+                int cls;
+                if constexpr (kSpl) {
+                    // a spline segment: the capsule (A, B, rho)
+                    T A[D], Bq[D];
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        A[k] = q[u][k];
+                        Bq[k] = q[u][D + k];
+                    }
+                    const T rho = q[u][2 * D];
+                    bytes += kSegW * sizeof(T);
+                    if constexpr (kF32) {
+                        const float sc = fmaxf(L.es[te], L.blo[s].w);
+                        float len = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < D; ++k) len += fabsf(Bq[k] - A[k]);
+                        float ts;
+                        const float mg = segbox32<D>(A, Bq, lo, hi, ts) - rho * rho;
+                        cls = classify_margin(mg, band_of(band_rel, sc, rho, len));
+                    } else {
+                        cls = segbox64<D>(A, Bq, lo, hi) <= rho * rho ? kHit : kMiss;
+                    }
+                } else {
+                    bytes += D * sizeof(T);
+                    if constexpr (kF32) {
+                        const float sc = fmaxf(L.es[te], L.blo[s].w);
+                        cls = classify_margin(point_box32<D>(q[u], lo, hi) - s_rad2[cu_i[u]],
+                                              band_of(band_rel, sc, L.r.r32[cu_i[u]], 0.0f));
+                    } else {
+                        cls = point_box64<D>(q[u], lo, hi) <= s_rad2[cu_i[u]] ? kHit : kMiss;
+                    }
+                }
+                if (cls == kHit) atomicOr(&L.sf[pp], 1u);
+                else if (cls == kUnsure) atomicOr(&L.sf[pp], 2u);
+            }
+        }
+        __syncthreads();
+    }
+    // ---- decisions
+    bool unsure = false;
+    int2 rec = make_int2(0, 0);
+    if (p < np) {
+        const uint64_t ump = kF32 ? L.um[p] : 0ull;
+        if (hmp || ump) {
+            const uint32_t fp = L.sf[p];
+            const uint32_t pv = L.pe[p], te = pe_slot(pv), s = pe_entry(pv);
+            unsure = kF32 && (!hmp || (!(fp & 1u) && ((fp & 2u) || ump)));
+            if (unsure) {
+                rec = make_int2(L.edge[te], L.gidx[s]);
+            } else {
+                const int sign = L.sign[s];
+                if constexpr (kShare) {
+                    add_counts(rm, L.edge[te], sign, (fp & 1u) ? sign : 0);
+                } else {
+                    atomicAdd(&L.dC[te], sign);
+                    if (fp & 1u) atomicAdd(&L.dS[te], sign);
+                }
+                ++n_outer;
+            }
+        }
+    }
+    if constexpr (kF32) {
+        // undecided pairs go to the block's re-test region for the binary64
+        // pass.  An item block whose region is full leaves its item whole to
+        // that pass; a pair share never fills its own region (it holds at
+        // most rt_cap_of(pl_cap) pairs)
+        int tot_u;
+        const int upre = block_scan(unsure ? 1 : 0, &tot_u, L.wsum);
+        if (tot_u > 0) {
+            const int base = L.rc_n;
+            if constexpr (kShare) {
+                if (unsure) rm.rt[(int64_t)blockIdx.x * rt_cap_of(rm.pl_cap) + base + upre] = rec;
+                __syncthreads();
+                if (tid == 0) L.rc_n = base + tot_u;
+            } else {
+                const bool fits = !L.defer && base + tot_u <= rm.rc_cap;
+                if (fits && unsure) rm.rc[(int64_t)blockIdx.x * rm.rc_cap + base + upre] = rec;
+                __syncthreads();
+                if (tid == 0) {
+                    if (fits) L.rc_n = base + tot_u;
+                    else L.defer = 1;
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// deferred == 0: the main pass, one block per item (grid kGrid): items li0,
+// li0 + lstride, ... (statistics row and re-test region blockIdx.x).
+// deferred == 1: the binary64 pass over the items the FP32 blocks left whole;
+// block b of that grid takes the item lists of FP32 blocks li0, li0 +
+// lstride, ... (statistics row li0).
+//
+// kList: the pair listing of the FP32 mode.  Each round of pairs goes to this
+// block's region of the pair list (rm.pl, for the pair-share kernel) while
+// the region has room; a round that does not fit is tested here, as the
+// fused kernel does.
+template <int D, typename T, int MODE, bool kList = false>
+__device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0, int lstride)
+{
+    constexpr bool kF32 = std::is_same<T, float>::value;
+    static_assert(!kList || kF32, "the pair listing serves the FP32 mode");
     __shared__ ItemLds<T> L;
     __shared__ T s_rad2[64];
     const Ctl *ctl = rm.ctl;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
     const int B = rm.B;
-    const int Gw = 64 / B;
     // lane -> (pair slot, sphere) of the capsule phase, read from LDS where
     // needed rather than held in registers through the whole kernel
     __shared__ int s_lane[64];
     if (tid < 64) s_lane[tid] = ((tid / B) << 8) | (tid - (tid / B) * B);
-    const uint64_t gmask = B == 64 ? ~0ull : ((1ull << B) - 1ull);
     if (tid < kStats) L.acc[tid] = 0;
     if (tid < B) s_rad2[tid] = kF32 ? (T)rm.rad2_32[tid] : (T)(rm.rad64[tid] * rm.rad64[tid]);
     if constexpr (kF32) {
@@ -754,6 +1245,7 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
     if (tid == 0) {
         L.rc_n = 0;
         L.df_n = 0;
+        L.pl_n = 0;
     }
     const int status = ctl->status;
     __shared__ int s_dfn[64];
@@ -773,9 +1265,6 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
     const int n_items = min(ctl->n_items, (int32_t)rm.items_cap);
     const bool single = rm.ncells == 1;
     const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
-    const T *capb = kF32 ? (const T *)rm.cap32 : (const T *)rm.cap64;
-    const T *samp = kF32 ? (const T *)rm.samp32 : (const T *)rm.samp64;
-    const float band_rel = rm.band_rel;
     const int jfix = rm.p_fixed ? rm.p_fixed / B : 0;
     const int lgn = rm.lg_dim[0] * rm.lg_dim[1] * rm.lg_dim[2];
     // next work item of this block; false when there is none
@@ -795,15 +1284,6 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
         it = rm.df[(int64_t)(li0 + rk * lstride) * rm.df_cap + li];
         ++li;
         return true;
-    };
-    // coordinates of staged entry s in the kernel's precision
-    auto box_lo = [&](int k, int s) -> T {
-        if constexpr (kF32) return k == 0 ? L.blo[s].x : (k == 1 ? L.blo[s].y : L.blo[s].z);
-        else return L.x.lo[k][s];
-    };
-    auto box_hi = [&](int k, int s) -> T {
-        if constexpr (kF32) return k == 0 ? L.bhi[s].x : (k == 1 ? L.bhi[s].y : L.bhi[s].z);
-        else return L.x.hi[k][s];
     };
     int it;
     while (next_item(it)) {
@@ -870,12 +1350,15 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
         if (wv == 0) visited += (uint32_t)n_e;
         if (tid == 0) {
             L.rc_start = L.rc_n;
+            L.pl_start = L.pl_n;
             L.defer = 0;
             // the main pass visits every item once: clear the cell's mark with
             // its first chunk, so the next update starts from zero marks
             if (!deferred && !single && item.y == 0) atomicAnd(&rm.cell_bits[c >> 5], ~(1u << (c & 31)));
         }
         uint32_t had = 0;   // bit h: edge slot h has pairs
+        bool fused = !kList;   // some round of this item was tested here
+        int n_round = 0;       // this item's pair rounds so far
         for (int j0 = 0; j0 < n_chg; j0 += kSubTile) {
             // the pruning grid starts empty (the previous tile or item is
             // done with its storage); the staging scan's barriers order this
@@ -1029,394 +1512,38 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                             while (m && k < r0 + np) {
                                 const int s = (w << 5) + __ffs(m) - 1;
                                 m &= m - 1;
-                                if (k >= r0) L.pe[k - r0] = (uint16_t)((sl << 7) | s);
+                                if (k >= r0) L.pe[k - r0] = ((uint32_t)sl << 16) | (uint32_t)s;
                                 ++k;
                             }
                         }
                     }
                 }
-                // per-pair results start empty (kPairCap == kBlock: pair tid)
-                if (tid < np) {
-                    L.hm[tid] = 0ull;
-                    L.um[tid] = 0ull;
-                    L.key[tid] = ~0u;
+                if constexpr (kList) {
+                    // after the item's first inline_rounds rounds, a round
+                    // goes to the pair list when the region has room
+                    if (n_round++ >= rm.inline_rounds) {
+                        __syncthreads();   // the round's pairs are in L.pe
+                        const int base = L.pl_n;
+                        if (base + np <= rm.pl_cap) {
+                            if (tid < np) {
+                                const uint32_t v = L.pe[tid];
+                                rm.pl[(int64_t)blockIdx.x * rm.pl_cap + base + tid] =
+                                    make_int2(L.edge[pe_slot(v)], L.gidx[pe_entry(v)]);
+                            }
+                            bytes += tid < np ? 8 : 0;
+                            __syncthreads();
+                            if (tid == 0) L.pl_n = base + np;
+                            __syncthreads();
+                            continue;
+                        }
+                    }
+                    fused = true;
                 }
-                if (tid == 0) L.nopen = 0;
-                __syncthreads();
-                n_pairs += np;
-                // a (pair, sphere) result: capsule hit bits, the deepest hit as
-                // the probe key, undecided bits
-                auto record = [&](int p, int i, int cls, float mg, float tpar) {
-                    if (cls == kHit) {
-                        atomicOr(&L.hm[p], 1ull << i);
-                        atomicMin(&L.key[p], probe_key(mg, tpar, i));
-                    } else if (cls == kUnsure) {
-                        atomicOr(&L.um[p], 1ull << i);
-                    }
-                };
-                // ---- outer test, quick part: lanes = (pair, sphere); each lane
-                // takes two pairs per step and issues both capsules' loads first.
-                // FP32 lanes the quick tests leave open are queued for the exact
-                // part, so the segment-box minimum runs on dense wavefronts.
-                constexpr int kCapU = 2;
-                const int slot = s_lane[lane] >> 8, ci = s_lane[lane] & 255;
-                for (int p0 = 0; p0 < np; p0 += kWaves * Gw * kCapU) {
-                    T A[kCapU][D], Bq[kCapU][D], R2[kCapU];
-                    int pu[kCapU];
-#pragma unroll
-                    for (int u = 0; u < kCapU; ++u) {
-                        pu[u] = p0 + (u * kWaves + wv) * Gw + slot;
-                        R2[u] = T(0);
-                        if (slot < Gw && pu[u] < np) {
-                            const int te = pe_slot(L.pe[pu[u]]);
-                            const T *cp = capb + (int64_t)L.edge[te] * (2 * D + 1) * B;
-#pragma unroll
-                            for (int k = 0; k < D; ++k) {
-                                A[u][k] = cp[k * B + ci];
-                                Bq[u][k] = cp[(D + k) * B + ci];
-                            }
-                            R2[u] = cp[2 * D * B + ci];
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < kCapU; ++u) {
-                        const int p = pu[u];
-                        const bool act = slot < Gw && p < np;
-                        int cls = kMiss;
-                        T lo[D], hi[D];
-                        float band = 0.0f, mg = 0.0f, tpar = 0.0f;
-                        const T R = R2[u];
-                        const T RR = R * R;
-                        if (act) {
-                            const int s = pe_entry(L.pe[p]);
-#pragma unroll
-                            for (int k = 0; k < D; ++k) {
-                                lo[k] = box_lo(k, s);
-                                hi[k] = box_hi(k, s);
-                            }
-                            if constexpr (kF32) {
-                                const float sc = fmaxf(L.es[pe_slot(L.pe[p])], L.blo[s].w);
-                                float len = 0.0f;
-#pragma unroll
-                                for (int k = 0; k < D; ++k) len += fabsf(Bq[u][k] - A[u][k]);
-                                band = band_of(band_rel, sc, R, len);
-                                float sep = 0.0f;
-#pragma unroll
-                                for (int k = 0; k < D; ++k)
-                                    sep = fmaxf(sep, fmaxf(lo[k] - fmaxf(A[u][k], Bq[u][k]), fminf(A[u][k], Bq[u][k]) - hi[k]));
-                                const float dA = point_box32<D>(A[u], lo, hi), dB = point_box32<D>(Bq[u], lo, hi);
-                                mg = fminf(dA, dB) - RR;
-                                tpar = dA <= dB ? 0.0f : 1.0f;
-                                cls = (sep > 0.0f && sep * sep - RR > band) ? kMiss : (mg < -band ? kHit : kOpen);
-                            } else {
-                                double ts;
-                                const double v = segbox64<D>(A[u], Bq[u], lo, hi, &ts);
-                                cls = v <= RR ? kHit : kMiss;
-                                mg = (float)(v - RR);
-                                tpar = (float)ts;
-                            }
-                        }
-                        if constexpr (kF32) {
-                            const bool op = cls == kOpen;
-                            const uint64_t ob = __ballot(op);
-                            if (ob) {
-                                int base = 0;
-                                if (lane == 0) base = atomicAdd(&L.nopen, __popcll(ob));
-                                base = __shfl(base, 0);
-                                if (op) {
-                                    const int q = base + __popcll(ob & lanes_below());
-                                    if (q < kOpenCap) {
-                                        L.u.open[q] = ((uint32_t)p << 6) | (uint32_t)ci;
-                                        cls = kMiss;     // decided by the exact part
-                                    } else {
-                                        cls = kUnsure;   // queue full: the binary64 re-test decides
-                                    }
-                                }
-                            }
-                        }
-                        if (act) record(p, ci, cls, mg, tpar);
-                    }
-                }
-                __syncthreads();
-                if constexpr (kF32) {
-                    // ---- outer test, exact part: the queued tasks, one per lane
-                    const int nq = min(L.nopen, kOpenCap);
-                    for (int q = tid; q < nq; q += kBlock) {
-                        const uint32_t tk = L.u.open[q];
-                        const int p = (int)(tk >> 6), i = (int)(tk & 63u);
-                        const int pv = L.pe[p], te = pe_slot(pv), s = pe_entry(pv);
-                        const float *cp = (const float *)capb + (int64_t)L.edge[te] * (2 * D + 1) * B;
-                        float A[D], Bq[D], lo[D], hi[D];
-#pragma unroll
-                        for (int k = 0; k < D; ++k) {
-                            A[k] = cp[k * B + i];
-                            Bq[k] = cp[(D + k) * B + i];
-                            lo[k] = box_lo(k, s);
-                            hi[k] = box_hi(k, s);
-                        }
-                        const float R = cp[2 * D * B + i];
-                        const float sc = fmaxf(L.es[te], L.blo[s].w);
-                        float len = 0.0f;
-#pragma unroll
-                        for (int k = 0; k < D; ++k) len += fabsf(Bq[k] - A[k]);
-                        float ts;
-                        const float mg = segbox32<D>(A, Bq, lo, hi, ts) - R * R;
-                        record(p, i, classify_margin(mg, band_of(band_rel, sc, R, len)), mg, ts);
-                    }
-                    __syncthreads();
-                }
-                if constexpr (kObb) {
-                    // ---- oriented boxes: the outer part of sphere i is its
-                    // capsule intersected with its body's box, so a sphere
-                    // whose body's box misses is dropped (decided in binary64)
-                    if (tid < np) {
-                        const uint64_t cnd = L.hm[tid] | (kF32 ? L.um[tid] : 0ull);
-                        if (cnd) {
-                            const int pv = L.pe[tid], te = pe_slot(pv), s = pe_entry(pv);
-                            double lo[D], hi[D];
-                            if constexpr (kF32) {
-                                const ChgEntry &en = rm.chg[L.gidx[s]];
-#pragma unroll
-                                for (int k = 0; k < D; ++k) {
-                                    lo[k] = en.lo[k];
-                                    hi[k] = en.hi[k];
-                                }
-                            } else {
-#pragma unroll
-                                for (int k = 0; k < D; ++k) {
-                                    lo[k] = L.x.lo[k][s];
-                                    hi[k] = L.x.hi[k][s];
-                                }
-                            }
-                            const double *ob = rm.obb64 + (int64_t)L.edge[te] * rm.nbody * obb_words(D);
-                            uint64_t keep = 0;
-                            for (int bd = 0; bd < rm.nbody; ++bd) {
-                                const uint64_t sp = rm.body_sph[bd];
-                                if (!(sp & cnd)) continue;
-                                bytes += obb_words(D) * 8;
-                                if (obb_box_meet64<D>(ob + bd * obb_words(D), lo, hi)) keep |= sp;
-                            }
-                            L.hm[tid] &= keep;
-                            if constexpr (kF32) L.um[tid] &= keep;
-                        }
-                    }
-                    __syncthreads();
-                }
-                // ---- probe: one copy per pair whose capsule met (the copy
-                // form only; a sphere the boxes dropped is not probed)
-                const int p = tid;   // kPairCap == kBlock: this thread's pair
-                uint32_t f = 0;
-                uint64_t hmp = 0;
-                if (p < np) {
-                    hmp = L.hm[p];
-                    if (hmp && !kSpl && (!kObb || ((hmp >> (L.key[p] & 63u)) & 1ull))) {
-                        const uint32_t key = L.key[p];
-                        const int i = (int)(key & 63u);
-                        const int pv = L.pe[p], te = pe_slot(pv), s = pe_entry(pv);
-                        const int Je = L.ej[te];
-                        // the configuration nearest the deepest capsule's closest point
-                        const int jj = min(Je - 1, (int)((float)((key >> 6) & 1023u) * (1.0f / 1023.0f) * (float)(Je - 1) + 0.5f));
-                        T q[D], lo[D], hi[D];
-                        load_copy<D>(samp, (int64_t)L.cfg0[te] * B + (int64_t)i * Je + jj, q);
-#pragma unroll
-                        for (int k = 0; k < D; ++k) {
-                            lo[k] = box_lo(k, s);
-                            hi[k] = box_hi(k, s);
-                        }
-                        bytes += D * sizeof(T);
-                        if constexpr (kF32) {
-                            const float sc = fmaxf(L.es[te], L.blo[s].w);
-                            const int cls = classify_margin(point_box32<D>(q, lo, hi) - s_rad2[i],
-                                                            band_of(band_rel, sc, L.r.r32[i], 0.0f));
-                            f = cls == kHit ? 1u : (cls == kUnsure ? 2u : 0u);
-                        } else {
-                            f = point_box64<D>(q, lo, hi) <= s_rad2[i] ? 1u : 0u;
-                        }
-                    }
-                    L.sf[p] = f;
-                }
-                // ---- rows: one per (open pair, sphere whose capsule met)
-                const int ra = (p < np && !(f & 1u)) ? __popcll(hmp) : 0;
-                int nrows;
-                const int rpre = block_scan(ra, &nrows, L.wsum);
-                __syncthreads();
-                for (int q0 = 0; q0 < nrows; q0 += kRowCap) {
-                    const int nr = min(kRowCap, nrows - q0);
-                    if (ra > 0 && rpre < q0 + nr && rpre + ra > q0) {
-                        uint64_t m = hmp;
-                        int r = rpre;
-                        while (m && r < q0 + nr) {
-                            const int i = __ffsll((unsigned long long)m) - 1;
-                            m &= m - 1;
-                            if (r >= q0) L.u.rw.row[r - q0] = ((uint32_t)p << 6) | (uint32_t)i;
-                            ++r;
-                        }
-                    }
-                    __syncthreads();
-                    // the row's copies (spline segments): fixed count, or a scan
-                    // over the rows
-                    int ncopies = kSpl ? 0 : nr * jfix;
-                    if (kSpl || !jfix) {
-                        int cj[2], sum = 0;
-                        for (int h = 0; h < 2; ++h) {
-                            const int r = tid * 2 + h;
-                            cj[h] = 0;
-                            if (r < nr) {
-                                const uint32_t rv = L.u.rw.row[r];
-                                const int te = pe_slot(L.pe[rv >> 6]);
-                                if constexpr (kSpl) {
-                                    const int64_t k = (int64_t)L.edge[te] * B + (int64_t)(rv & 63u);
-                                    const int32_t k0 = rm.sseg[k];
-                                    cj[h] = rm.sseg[k + 1] - k0;
-                                    L.u.rw.rbase[r] = (uint32_t)k0;
-                                } else {
-                                    cj[h] = L.ej[te];
-                                }
-                            }
-                            sum += cj[h];
-                        }
-                        const int cpre = block_scan(sum, &ncopies, L.wsum);
-                        int acc = cpre;
-                        for (int h = 0; h < 2; ++h) {
-                            const int r = tid * 2 + h;
-                            if (r < nr) L.u.rw.rcopy[r] = acc;
-                            acc += cj[h];
-                        }
-                        if (tid == 0) L.u.rw.rcopy[nr] = ncopies;
-                        __syncthreads();
-                    }
-                    // each thread gathers kCopyU copies (all their loads in
-                    // flight together), then tests them
-                    constexpr int kCopyU = 4;
-                    const T *segb = kF32 ? (const T *)rm.seg32 : (const T *)rm.seg64;
-                    for (int c0 = 0; c0 < ncopies; c0 += kBlock * kCopyU) {
-                        T q[kCopyU][kSpl ? kSegW : D];
-                        int cu_p[kCopyU], cu_i[kCopyU];
-#pragma unroll
-                        for (int u = 0; u < kCopyU; ++u) {
-                            const int cidx = c0 + u * kBlock + tid;
-                            cu_p[u] = -1;
-                            cu_i[u] = 0;
-                            if (cidx < ncopies) {
-                                int r, jj;
-                                if (!kSpl && jfix) {
-                                    r = cidx / jfix;
-                                    jj = cidx - r * jfix;
-                                } else {
-                                    int lo_ = 0, hi_ = nr - 1;   // last row with rcopy[r] <= cidx
-                                    while (lo_ < hi_) {
-                                        const int mid = (lo_ + hi_ + 1) >> 1;
-                                        if (L.u.rw.rcopy[mid] <= (uint32_t)cidx) lo_ = mid;
-                                        else hi_ = mid - 1;
-                                    }
-                                    r = lo_;
-                                    jj = cidx - (int)L.u.rw.rcopy[r];
-                                }
-                                const uint32_t rv = L.u.rw.row[r];
-                                const int pp = (int)(rv >> 6);
-                                const int i = (int)(rv & 63u);
-                                const int te = pe_slot(L.pe[pp]);
-                                if constexpr (kSpl) {
-                                    const T *sg = segb + ((int64_t)L.u.rw.rbase[r] + jj) * kSegW;
-#pragma unroll
-                                    for (int k = 0; k < kSegW; ++k) q[u][k] = sg[k];
-                                } else {
-                                    const int Je = L.ej[te];
-                                    load_copy<D>(samp, (int64_t)L.cfg0[te] * B + (int64_t)i * Je + jj, q[u]);
-                                }
-                                cu_p[u] = pp;
-                                cu_i[u] = i;
-                            }
-                        }
-#pragma unroll
-                        for (int u = 0; u < kCopyU; ++u) {
-                            const int pp = cu_p[u];
-                            if (pp < 0) continue;
-                            const int pv = L.pe[pp], te = pe_slot(pv), s = pe_entry(pv);
-                            T lo[D], hi[D];
-#pragma unroll
-                            for (int k = 0; k < D; ++k) {
-                                lo[k] = box_lo(k, s);
-                                hi[k] = box_hi(k, s);
-                            }
-                            int cls;
-                            if constexpr (kSpl) {
-                                // a spline segment: the capsule (A, B, rho)
-                                T A[D], Bq[D];
-#pragma unroll
-                                for (int k = 0; k < D; ++k) {
-                                    A[k] = q[u][k];
-                                    Bq[k] = q[u][D + k];
-                                }
-                                const T rho = q[u][2 * D];
-                                bytes += kSegW * sizeof(T);
-                                if constexpr (kF32) {
-                                    const float sc = fmaxf(L.es[te], L.blo[s].w);
-                                    float len = 0.0f;
-#pragma unroll
-                                    for (int k = 0; k < D; ++k) len += fabsf(Bq[k] - A[k]);
-                                    float ts;
-                                    const float mg = segbox32<D>(A, Bq, lo, hi, ts) - rho * rho;
-                                    cls = classify_margin(mg, band_of(band_rel, sc, rho, len));
-                                } else {
-                                    cls = segbox64<D>(A, Bq, lo, hi) <= rho * rho ? kHit : kMiss;
-                                }
-                            } else {
-                                bytes += D * sizeof(T);
-                                if constexpr (kF32) {
-                                    const float sc = fmaxf(L.es[te], L.blo[s].w);
-                                    cls = classify_margin(point_box32<D>(q[u], lo, hi) - s_rad2[cu_i[u]],
-                                                          band_of(band_rel, sc, L.r.r32[cu_i[u]], 0.0f));
-                                } else {
-                                    cls = point_box64<D>(q[u], lo, hi) <= s_rad2[cu_i[u]] ? kHit : kMiss;
-                                }
-                            }
-                            if (cls == kHit) atomicOr(&L.sf[pp], 1u);
-                            else if (cls == kUnsure) atomicOr(&L.sf[pp], 2u);
-                        }
-                    }
-                    __syncthreads();
-                }
-                // ---- decisions
-                bool unsure = false;
-                int2 rec = make_int2(0, 0);
-                if (p < np) {
-                    const uint64_t ump = kF32 ? L.um[p] : 0ull;
-                    if (hmp || ump) {
-                        const uint32_t fp = L.sf[p];
-                        const int pv = L.pe[p], te = pe_slot(pv), s = pe_entry(pv);
-                        unsure = kF32 && (!hmp || (!(fp & 1u) && ((fp & 2u) || ump)));
-                        if (unsure) {
-                            rec = make_int2(L.edge[te], L.gidx[s]);
-                        } else {
-                            const int sign = L.sign[s];
-                            atomicAdd(&L.dC[te], sign);
-                            if (fp & 1u) atomicAdd(&L.dS[te], sign);
-                            ++n_outer;
-                        }
-                    }
-                }
-                if constexpr (kF32) {
-                    // undecided pairs go to this block's re-test region; when it
-                    // is full the item is left whole to the binary64 pass
-                    int tot_u;
-                    const int upre = block_scan(unsure ? 1 : 0, &tot_u, L.wsum);
-                    if (tot_u > 0) {
-                        const int base = L.rc_n;
-                        const bool fits = !L.defer && base + tot_u <= rm.rc_cap;
-                        if (fits && unsure) rm.rc[(int64_t)blockIdx.x * rm.rc_cap + base + upre] = rec;
-                        __syncthreads();
-                        if (tid == 0) {
-                            if (fits) L.rc_n = base + tot_u;
-                            else L.defer = 1;
-                        }
-                    }
-                }
-                __syncthreads();
+                test_round<D, T, MODE, false>(rm, L, s_rad2, s_lane, np, n_pairs, n_outer, bytes);
             }
         }
         cand += (uint32_t)(__popcll(__ballot(had & 1u)) + __popcll(__ballot(had & 2u)));
-        bytes += (unsigned long long)__popc(had) * ((2 * D + 1) * B * sizeof(T) + 16);
+        if (fused) bytes += (unsigned long long)__popc(had) * ((2 * D + 1) * B * sizeof(T) + 16);
         __syncthreads();
         if (!L.defer) {
 #pragma unroll
@@ -1425,7 +1552,12 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
                 if (sl < n_e) add_counts(rm, L.edge[sl], L.dC[sl], L.dS[sl]);
             }
         } else if (tid == 0) {
+            // the whole item goes to the binary64 pass: its queued re-tests
+            // and listed pairs are withdrawn (the withdrawn pairs are
+            // counted here, as the rounds this block tested are)
+            L.acc[0] += (unsigned long long)(L.pl_n - L.pl_start);
             L.rc_n = L.rc_start;
+            L.pl_n = L.pl_start;
             rm.df[(int64_t)blockIdx.x * rm.df_cap + L.df_n] = it;
             L.df_n += 1;
         }
@@ -1436,9 +1568,10 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
     // one address from every lane are slow
     const unsigned long long w_outer = wave_sum_u64(n_outer), w_bytes = wave_sum_u64(bytes);
     if (tid == 0 && n_pairs) atomicAdd(&L.acc[deferred ? 2 : 0], (unsigned long long)n_pairs);
+    const int byte_row = deferred ? kStatFp64Bytes : (kList ? kStatItemBytes : kStatPairBytes);
     if (lane == 0) {
         if (w_outer) atomicAdd(&L.acc[1], w_outer);
-        if (w_bytes) atomicAdd(&L.acc[3], w_bytes);
+        if (w_bytes) atomicAdd(&L.acc[byte_row], w_bytes);
         if (visited) atomicAdd(&L.acc[4], (unsigned long long)visited);
         if (cand) atomicAdd(&L.acc[5], (unsigned long long)cand);
     }
@@ -1451,11 +1584,12 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
             rm.rc_cnt[blockIdx.x] = L.rc_n;
             rm.df_cnt[blockIdx.x] = L.df_n;
             if (L.df_n) rm.ctl->any_df = 1;
+            if (kList) rm.pl_cnt[blockIdx.x] = L.pl_n;
         }
-    } else if (tid == 0 && (L.acc[1] | L.acc[2] | L.acc[3])) {
+    } else if (tid == 0 && (L.acc[1] | L.acc[2] | L.acc[kStatFp64Bytes])) {
         bs[1 * kStatBlocks] += L.acc[1];
         bs[2 * kStatBlocks] += L.acc[2];
-        bs[3 * kStatBlocks] += L.acc[3];
+        bs[kStatFp64Bytes * kStatBlocks] += L.acc[kStatFp64Bytes];
     }
 }
 
@@ -1464,7 +1598,7 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
 template <int D, int MODE>
 __global__ void __launch_bounds__(kBlock, 4) k_item32(RmDev rm)
 {
-    item_body<D, float, MODE>(rm, 0, (int)blockIdx.x, (int)gridDim.x);
+    item_body<D, float, MODE, true>(rm, 0, (int)blockIdx.x, (int)gridDim.x);
 }
 
 template <int D, int MODE>
@@ -1473,9 +1607,10 @@ __global__ void __launch_bounds__(kBlock) k_item64(RmDev rm)
     item_body<D, double, MODE>(rm, 0, (int)blockIdx.x, (int)gridDim.x);
 }
 
-// Binary64 re-test of the pairs queued by the FP32 item blocks whose regions
-// this block takes (FP32 blocks b, b + gridDim.x, ...), one wavefront per pair.
-// Re-test regions b, b + G, ... (at most 64 of them); statistics row b.
+// Binary64 re-test of the pairs queued by the FP32 blocks whose regions this
+// block takes, one wavefront per pair: the item blocks' re-test regions b,
+// b + G, ... (at most 64 of them), then the pair shares' regions of the same
+// blocks; statistics row b.
 template <int D, int MODE>
 __device__ __forceinline__ void retest_pairs(const RmDev &rm, int b, int G)
 {
@@ -1488,82 +1623,40 @@ __device__ __forceinline__ void retest_pairs(const RmDev &rm, int b, int G)
     const bool ok = rm.ctl->status == RGG_OK;
     if (tid < rm.B) s_rad[tid] = rm.rad64[tid];
     if (tid < 3) s_acc[tid] = 0;
-    // pair counts of this block's regions, as an exclusive prefix
-    if (tid < 64) {
-        int n = 0;
-        if (tid < kReg) {
-            int *rc = rm.rc_cnt + b + tid * G;
-            n = ok ? *rc : 0;
-            *rc = 0;   // cleared for the next update
-        }
-        int tot;
-        const int pre = wave_prefix(n, &tot);
-        if (tid < kReg) s_off[tid] = pre;
-        if (tid == 0) s_off[kReg] = tot;
-    }
-    __syncthreads();
-    const int total = s_off[kReg];
-    unsigned long long n_re = 0, n_outer = 0, bytes = 0;
-    const int B = rm.B;
-    int reg = 0;
-    for (int q = wv; q < total; q += kWaves) {
-        while (s_off[reg + 1] <= q) ++reg;
-        const int k = q - s_off[reg];
-        const int2 pr = rm.rc[(int64_t)(b + reg * G) * rm.rc_cap + k];
-        const int64_t e = pr.x;
-        const ChgEntry &en = rm.chg[pr.y];
-        double lo[D], hi[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) {
-            lo[d] = en.lo[d];
-            hi[d] = en.hi[d];
-        }
-        bool hit = false;
-        if (lane < B) {
-            const double *cp = rm.cap64 + e * (2 * D + 1) * B;
-            double A[D], Bp[D];
-#pragma unroll
-            for (int d = 0; d < D; ++d) {
-                A[d] = cp[d * B + lane];
-                Bp[d] = cp[(D + d) * B + lane];
+    unsigned long long n_re = 0, bytes = 0;
+    uint32_t n_outer = 0;
+    // regions [kReg] at reg[(b + k G) * cap], counts cnt[b + k G]
+    auto run = [&](int32_t *cnt, const int2 *reg_base, int32_t cap) {
+        __syncthreads();   // s_off is free
+        // pair counts of this block's regions, as an exclusive prefix
+        if (tid < 64) {
+            int n = 0;
+            if (tid < kReg) {
+                int *rc = cnt + b + tid * G;
+                n = ok ? *rc : 0;
+                *rc = 0;   // cleared for the next update
             }
-            const double R = cp[2 * D * B + lane];
-            hit = segbox64<D>(A, Bp, lo, hi) <= R * R;
+            int tot;
+            const int pre = wave_prefix(n, &tot);
+            if (tid < kReg) s_off[tid] = pre;
+            if (tid == 0) s_off[kReg] = tot;
         }
-        uint64_t hm = __ballot(hit);
-        bytes += (2 * D + 1) * B * 8;
-        ++n_re;
-        if constexpr ((MODE & kModeObb) != 0) {
-            // spheres whose body's oriented box misses are dropped
-            bool keep = false;
-            uint64_t sp = 0;
-            if (hm && lane < rm.nbody) {
-                sp = rm.body_sph[lane];
-                if (sp & hm) {
-                    keep = obb_box_meet64<D>(rm.obb64 + (e * rm.nbody + lane) * obb_words(D), lo, hi);
-                    bytes += obb_words(D) * 8;
-                }
-            }
-            uint64_t allowed = keep ? sp : 0ull;
-            for (int o = 32; o > 0; o >>= 1) allowed |= __shfl_xor(allowed, o);
-            hm &= allowed;
+        __syncthreads();
+        const int total = s_off[kReg];
+        int reg = 0;
+        for (int q = wv; q < total; q += kWaves) {
+            while (s_off[reg + 1] <= q) ++reg;
+            const int k = q - s_off[reg];
+            const int2 pr = reg_base[(int64_t)(b + reg * G) * cap + k];
+            retest_one<D, MODE>(rm, pr.x, pr.y, s_lst[wv], s_rad, n_outer, bytes);
+            ++n_re;
         }
-        if (!hm) continue;
-        bool S;
-        if constexpr ((MODE & kModeSplines) != 0) {
-            S = splines_meet64<D>(rm, e, hm, lo, hi, &bytes);
-        } else {
-            const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
-            const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
-            const CopyMap cm = copy_map((int)(P / B));
-            S = copies_meet64<D>(rm, rm.samp64 + copy_stride<D>() * s0, P, cm, hm, lo, hi, s_rad, s_lst[wv], &bytes);
-        }
-        ++n_outer;
-        if (lane == 0) add_counts(rm, e, en.sign, S ? en.sign : 0);
-    }
+    };
+    run(rm.rc_cnt, rm.rc, rm.rc_cap);
+    if (rm.rt) run(rm.rt_cnt, rm.rt, rt_cap_of(rm.pl_cap));
     if (lane == 0 && n_re) {
         atomicAdd(&s_acc[0], n_re);
-        atomicAdd(&s_acc[1], n_outer);
+        atomicAdd(&s_acc[1], (unsigned long long)n_outer);
         atomicAdd(&s_acc[2], bytes);
     }
     __syncthreads();
@@ -1571,7 +1664,7 @@ __device__ __forceinline__ void retest_pairs(const RmDev &rm, int b, int G)
         unsigned long long *bs = rm.blk_stats + b;
         bs[1 * kStatBlocks] += s_acc[1];
         bs[2 * kStatBlocks] += s_acc[0];
-        bs[3 * kStatBlocks] += s_acc[2];
+        bs[kStatFp64Bytes * kStatBlocks] += s_acc[2];
     }
 }
 
@@ -1587,6 +1680,152 @@ __global__ void __launch_bounds__(kBlock) k_fp64(RmDev rm)
     retest_pairs<D, MODE>(rm, (int)blockIdx.x, (int)gridDim.x);
     if (!any_df) return;
     item_body<D, double, MODE>(rm, 1, (int)blockIdx.x, (int)gridDim.x);
+}
+
+// ------------------------------------------------------------------------
+// k_pairs: the balanced pair testing of the FP32 mode (launched only when
+// the item kernel lists pairs).  The listing leaves each block's pairs in
+// its region of rm.pl; this kernel cuts the concatenation of the regions
+// into equal shares, as many as the device holds at once while a share fits
+// one round, so every block tests the same number of pairs whatever the
+// items' sizes were.  A share runs in rounds of kPairCap pairs through the
+// same phases as an item block's round (each pair is its own edge slot and
+// entry); counter deltas go to the counters at once.
+// ------------------------------------------------------------------------
+
+struct ShareLds {
+    float4 blo[kPairCap], bhi[kPairCap];  // the pairs' entries: (lo, sbox), (hi, 0)
+    int sign[kPairCap], gidx[kPairCap];
+    NoBoxes x;
+    Radii32 r;
+    uint32_t cfg0[kPairCap];              // first configuration of each pair's edge
+    int edge[kPairCap], ej[kPairCap];     // edge id, configurations per sphere
+    float es[kPairCap];                   // edge s (largest |coordinate| of its box)
+    uint32_t pe[kPairCap];                // pair << 16 | pair
+    unsigned long long hm[kPairCap], um[kPairCap];
+    uint32_t key[kPairCap];
+    union alignas(8) {
+        uint32_t open[kOpenCap];
+        struct {
+            uint32_t row[kRowCap];
+            uint32_t rcopy[kRowCap + 1];
+            uint32_t rbase[kRowCap];
+        } rw;
+    } u;
+    int nopen;
+    uint32_t sf[kPairCap];
+    int wsum[kWaves];
+    int rc_n;
+    int pref[kStatBlocks + 1];            // listed pairs before each region
+    unsigned long long acc[kStats];
+};
+
+template <int D, int MODE>
+__device__ __forceinline__ void share_body(const RmDev &rm)
+{
+    __shared__ ShareLds L;
+    __shared__ float s_rad2[64];
+    __shared__ int s_lane[64];
+    const int tid = threadIdx.x, lane = lane_id();
+    const int B = rm.B;
+    if (tid < 64) s_lane[tid] = ((tid / B) << 8) | (tid - (tid / B) * B);
+    if (tid < kStats) L.acc[tid] = 0;
+    if (tid < B) {
+        s_rad2[tid] = rm.rad2_32[tid];
+        L.r.r32[tid] = (float)rm.rad64[tid];
+    }
+    if (tid == 0) L.rc_n = 0;   // pairs queued in this share's re-test region
+    // prefix of the regions' pair counts: kPer consecutive regions per thread
+    constexpr int kPer = kStatBlocks / kBlock;
+    static_assert(kStatBlocks % kBlock == 0, "regions are scanned kPer per thread");
+    int c[kPer], sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        c[k] = rm.pl_cnt[tid * kPer + k];
+        sum += c[k];
+    }
+    int total;
+    int pre = block_scan(sum, &total, L.wsum);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        L.pref[tid * kPer + k] = pre;
+        pre += c[k];
+    }
+    if (tid == 0) L.pref[kStatBlocks] = total;
+    __syncthreads();
+    // the shares: as many as fit on the device at once while each is at most
+    // one round, more (up to the grid) when the pairs need more rounds; a
+    // share then holds at most max(kPairCap, pl_cap) pairs
+    const int G = min((int)gridDim.x, max(rm.test_slots, (total + kPairCap - 1) / kPairCap));
+    const int b = (int)blockIdx.x;
+    const int64_t lo = b < G ? (int64_t)total * b / G : 0;
+    const int64_t hi = b < G ? (int64_t)total * (b + 1) / G : 0;
+    const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
+    const int jfix = rm.p_fixed ? rm.p_fixed / B : 0;
+    uint32_t n_pairs = 0, n_outer = 0;
+    unsigned long long bytes = 0;
+    for (int64_t r0 = lo; r0 < hi; r0 += kPairCap) {
+        const int np = (int)min((int64_t)kPairCap, hi - r0);
+        if (tid < np) {
+            // the pair's region: the last one whose first pair is at most g
+            const int g = (int)(r0 + tid);
+            int a = 0, z = kStatBlocks - 1;
+            while (a < z) {
+                const int m = (a + z + 1) >> 1;
+                if (L.pref[m] <= g) a = m;
+                else z = m - 1;
+            }
+            const int2 pr = rm.pl[(int64_t)a * rm.pl_cap + (g - L.pref[a])];
+            const int e = pr.x, j = pr.y;
+            const float4 *q = reinterpret_cast<const float4 *>(&rm.chg[j]);
+            const float4 qa = q[0], qb = q[1];   // lo32[0..2], hi32[0]; hi32[1..2], sbox, sign
+            L.blo[tid] = make_float4(qa.x, qa.y, qa.z, qb.z);
+            L.bhi[tid] = make_float4(qa.w, qb.x, qb.y, 0.0f);
+            L.sign[tid] = __float_as_int(qb.w);
+            L.gidx[tid] = j;
+            L.edge[tid] = e;
+            L.es[tid] = aabb[2 * (int64_t)e].w;
+            if (jfix) {
+                L.ej[tid] = jfix;
+                L.cfg0[tid] = (uint32_t)((int64_t)e * jfix);
+            } else {
+                const int64_t s0 = rm.soff[e];
+                L.cfg0[tid] = (uint32_t)(s0 / B);
+                L.ej[tid] = (int)((rm.soff[e + 1] - s0) / B);
+            }
+            L.pe[tid] = ((uint32_t)tid << 16) | (uint32_t)tid;
+            // the pair record and entry, the edge's box word; its capsules
+            // once per run of pairs of one edge
+            bytes += 8 + 32 + 4;
+        }
+        __syncthreads();
+        if (tid < np && (tid == 0 || L.edge[tid] != L.edge[tid - 1]))
+            bytes += (unsigned long long)((2 * D + 1) * B * sizeof(float) + (jfix ? 0 : 16));
+        test_round<D, float, MODE, true>(rm, L, s_rad2, s_lane, np, n_pairs, n_outer, bytes);
+    }
+    __syncthreads();
+    const unsigned long long w_outer = wave_sum_u64(n_outer), w_bytes = wave_sum_u64(bytes);
+    if (tid == 0 && n_pairs) atomicAdd(&L.acc[0], (unsigned long long)n_pairs);
+    if (lane == 0) {
+        if (w_outer) atomicAdd(&L.acc[1], w_outer);
+        if (w_bytes) atomicAdd(&L.acc[kStatPairBytes], w_bytes);
+    }
+    __syncthreads();
+    // the listing wrote this block's rows; the shares add to them
+    unsigned long long *bs = rm.blk_stats + blockIdx.x;
+    if (tid == 0) {
+        if (L.acc[0]) bs[0] += L.acc[0];
+        if (L.acc[1]) bs[1 * kStatBlocks] += L.acc[1];
+        if (L.acc[2]) bs[2 * kStatBlocks] += L.acc[2];
+        if (L.acc[kStatPairBytes]) bs[kStatPairBytes * kStatBlocks] += L.acc[kStatPairBytes];
+        rm.rt_cnt[blockIdx.x] = L.rc_n;
+    }
+}
+
+template <int D, int MODE>
+__global__ void __launch_bounds__(kBlock, 4) k_pairs(RmDev rm)
+{
+    share_body<D, MODE>(rm);
 }
 
 // ------------------------------------------------------------------------
@@ -1673,12 +1912,21 @@ __device__ __forceinline__ void fold_stats(const RmDev &rm, rgg_update_result *r
         if (lane == 0) s_part[wv][k] = a;
     }
     __syncthreads();
-    if (tid < kStats) {
-        unsigned long long a = 0;
-        for (int w = 0; w < kWaves; ++w) a += s_part[w][tid];
-        int64_t *dst = tid == 0 ? &res->n_pairs : tid == 1 ? &res->n_outer_hits : tid == 2 ? &res->n_rechecked
-                     : tid == 3 ? &res->test_bytes : tid == 4 ? &res->n_cells_visited : &res->n_candidate_edges;
-        *dst = (int64_t)a;
+    if (tid == 0) {
+        int64_t a[kStats];
+        for (int k = 0; k < kStats; ++k) {
+            unsigned long long t = 0;
+            for (int w = 0; w < kWaves; ++w) t += s_part[w][k];
+            a[k] = (int64_t)t;
+        }
+        res->n_pairs = a[0];
+        res->n_outer_hits = a[1];
+        res->n_rechecked = a[2];
+        res->test_bytes = a[kStatPairBytes] + a[kStatItemBytes] + a[kStatFp64Bytes];
+        res->n_cells_visited = a[4];
+        res->n_candidate_edges = a[5];
+        res->item_bytes = a[kStatItemBytes];
+        res->fp64_bytes = a[kStatFp64Bytes];
     }
 }
 
@@ -1982,43 +2230,32 @@ __global__ void __launch_bounds__(kBlock) k_write_batch(const BatchReq *tab, int
 
 namespace {
 
+// The kernel of role k for the roadmap's dimension and form: 0 the pair
+// listing, 1 the pair testing, 2 the binary64 pass (FP32 mode), 3 the
+// binary64 item kernel (FP64 mode).
 template <int D, int MODE>
-void *item_fn_of(bool f64)
+void *fn_of(int k)
 {
-    return f64 ? (void *)k_item64<D, MODE> : (void *)k_item32<D, MODE>;
-}
-
-template <int D>
-void *item_fn_dim(int mode, bool f64)
-{
-    switch (mode) {
-    case kModeObb: return item_fn_of<D, kModeObb>(f64);
-    case kModeSplines: return item_fn_of<D, kModeSplines>(f64);
-    case kModeObb | kModeSplines: return item_fn_of<D, kModeObb | kModeSplines>(f64);
-    default: return item_fn_of<D, 0>(f64);
+    switch (k) {
+    case 0: return (void *)k_item32<D, MODE>;
+    case 1: return (void *)k_pairs<D, MODE>;
+    case 2: return (void *)k_fp64<D, MODE>;
+    default: return (void *)k_item64<D, MODE>;
     }
 }
 
-void *item_fn(const RmDev &rm, bool f64)
-{
-    return rm.D == 3 ? item_fn_dim<3>(rm.mode, f64) : item_fn_dim<2>(rm.mode, f64);
-}
-
 template <int D>
-void *fp64_fn_dim(int mode)
+void *fn_dim(int mode, int k)
 {
     switch (mode) {
-    case kModeObb: return (void *)k_fp64<D, kModeObb>;
-    case kModeSplines: return (void *)k_fp64<D, kModeSplines>;
-    case kModeObb | kModeSplines: return (void *)k_fp64<D, kModeObb | kModeSplines>;
-    default: return (void *)k_fp64<D, 0>;
+    case kModeObb: return fn_of<D, kModeObb>(k);
+    case kModeSplines: return fn_of<D, kModeSplines>(k);
+    case kModeObb | kModeSplines: return fn_of<D, kModeObb | kModeSplines>(k);
+    default: return fn_of<D, 0>(k);
     }
 }
 
-void *fp64_fn(const RmDev &rm)
-{
-    return rm.D == 3 ? fp64_fn_dim<3>(rm.mode) : fp64_fn_dim<2>(rm.mode);
-}
+void *fn(const RmDev &rm, int k) { return rm.D == 3 ? fn_dim<3>(rm.mode, k) : fn_dim<2>(rm.mode, k); }
 
 
 struct Node {
@@ -2029,18 +2266,27 @@ struct Node {
 };
 
 // The kernels of one update, in order.  Stage events: ev[0] before, ev[1]
-// after the diff, ev[2] and ev[3] after the cell activation, ev[4] after the
-// item kernel, ev[5] after the binary64 pass, ev[6] after the labels.  With
-// a single grid cell there is nothing to activate: k_diff emits the items.
+// after the diff, ev[2] after the cell activation, ev[3] after the pair
+// listing, ev[4] after the pair testing, ev[5] after the binary64 pass,
+// ev[6] after the labels.  The FP64 mode's one item kernel stands for the
+// testing (ev[3] before it).  With a single grid cell there is nothing to
+// activate: k_diff emits the items.
 int plan(const RmDev &rm, Node out[7])
 {
     int n = 0;
     const bool single = rm.ncells == 1;
-    out[n++] = {(void *)k_diff, dim3(1), 0, 1, single ? 3 : 1};
-    if (!single) out[n++] = {(void *)k_cells, dim3(kCellsGrid), 1, 2, 3};
-    out[n++] = {item_fn(rm, !rm.mixed), dim3(kGrid), 1, 4, rm.mixed ? 4 : 5};
     if (rm.mixed) {
-        out[n++] = {fp64_fn(rm), dim3(kFp64Grid), 1, 5, 5};
+        out[n++] = {(void *)k_diff, dim3(1), 0, 1, single ? 2 : 1};
+        if (!single) out[n++] = {(void *)k_cells, dim3(kCellsGrid), 1, 2, 2};
+        // with every round tested inline there is nothing to share out
+        const bool share = rm.inline_rounds != kInlineAll;
+        out[n++] = {fn(rm, 0), dim3(kGrid), 1, 3, share ? 3 : 4};
+        if (share) out[n++] = {fn(rm, 1), dim3(kGrid), 1, 4, 4};
+        out[n++] = {fn(rm, 2), dim3(kFp64Grid), 1, 5, 5};
+    } else {
+        out[n++] = {(void *)k_diff, dim3(1), 0, 1, single ? 3 : 1};
+        if (!single) out[n++] = {(void *)k_cells, dim3(kCellsGrid), 1, 2, 3};
+        out[n++] = {fn(rm, 3), dim3(kGrid), 1, 4, 5};
     }
     out[n++] = {(void *)k_labels, dim3(rm.ntiles + 1), 4, 6, 6};
     return n;
@@ -2092,6 +2338,17 @@ hipError_t launch_update(const RmDev &rm, const UpdateArgs &a, hipStream_t s, hi
 }
 
 int item_edges_max() { return kItemCap; }
+
+hipError_t test_blocks_resident(int D, int device, int *out)
+{
+    int per_cu = 0, n_cu = 0;
+    hipError_t e = D == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pairs<3, 0>, kBlock, 0)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pairs<2, 0>, kBlock, 0);
+    if (e != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess) return e;
+    *out = per_cu * n_cu;
+    return hipSuccess;
+}
 
 hipError_t item_blocks_resident(int D, int device, int *out)
 {

@@ -41,7 +41,7 @@ struct RmDev {
     float band_rel;
     int32_t ntiles;            // label tiles of kLabelTile edges
     int32_t p_fixed;           // sphere samples per edge when every edge has the same count, else 0
-    int32_t pad1;
+    int32_t test_slots;        // blocks of the pair testing resident at once on the device
     // approximations (see HostGeometry for the layouts)
     const int64_t *soff;
     const float *samp32;
@@ -90,6 +90,15 @@ struct RmDev {
     int32_t *df;               // [kStatBlocks][df_cap] items a block left whole to the
                                // binary64 pass (its re-test region was full)
     int32_t *df_cnt;           // [kStatBlocks]
+    // the FP32 mode's pair listing and pair testing
+    int32_t pl_cap;            // pairs each listing block may leave for the pair testing
+    int32_t inline_rounds;     // pair rounds of an item its listing block tests before it
+                               // lists the rest (kInlineAll: every round, no pair testing)
+    int2 *pl;                  // [kStatBlocks][pl_cap] (edge, entry) pairs
+    int32_t *pl_cnt;           // [kStatBlocks] pairs each listing block left
+    int2 *rt;                  // [kStatBlocks][rt_cap(pl_cap)] pairs each share left to the
+                               // binary64 re-test (a share holds at most that many pairs)
+    int32_t *rt_cnt;           // [kStatBlocks]
     int32_t *tile_cnt;         // [ntiles] gray edges per label tile
     unsigned long long *tile_state;   // [ntiles] look-back words of the one-pass label
                                       // kernel: flag (bits 62-63) | gray count
@@ -101,9 +110,11 @@ constexpr int kModeObb = 1;
 constexpr int kModeSplines = 2;
 __host__ __device__ constexpr int obb_words(int D) { return 2 * D + D * D; }
 
-// pairs, pairs whose outer approximation met, re-tested pairs, classify bytes,
-// grid entries scanned, candidate edges
-constexpr int kStats = 6;
+// per-block statistics rows: pairs, pairs whose outer approximation met,
+// re-tested pairs, bytes of the testing kernels, grid entries scanned,
+// candidate edges, bytes of the pair listing, bytes of the binary64 pass
+constexpr int kStats = 8;
+constexpr int kStatPairBytes = 3, kStatItemBytes = 6, kStatFp64Bytes = 7;
 constexpr int kStatBlocks = 2048;  // blocks of the item kernels
 constexpr int kMaxSlots = 4096;    // 2*slots changed entries at most
 
@@ -111,6 +122,12 @@ constexpr int kLocalCells = 512;   // cells of the item kernel's pruning grid (a
 constexpr int kCopyStride3 = 4;    // values per sample copy in 3-D (xyz + pad)
 constexpr int kCopyStride2 = 2;    // in 2-D
 constexpr int kRcCap = 1024;       // default re-test pairs one item-kernel block may queue
+constexpr int kPairListCap = 512;  // pairs one listing block may hand to the pair testing
+constexpr int kInlineAll = 0x7fffffff;   // inline_rounds: every round tested by the listing block
+// Capacity of a share's re-test region: a share holds at most one round
+// (kPairCap pairs) or, when the shares span every statistics block, at most
+// one listing block's capacity.
+__host__ __device__ constexpr int32_t rt_cap_of(int32_t pl_cap) { return pl_cap > 256 ? pl_cap : 256; }
 constexpr int kLabelTile = 4096;   // edges per block of the label kernels
 
 struct UpdateArgs {
@@ -216,5 +233,7 @@ int item_edges_max();
 // Blocks of the binary32 item kernel for dimension D resident on `device` at
 // once (blocks per CU times CUs).
 hipError_t item_blocks_resident(int D, int device, int *out);
+// blocks of the FP32 pair testing resident at once (RmDev::test_slots)
+hipError_t test_blocks_resident(int D, int device, int *out);
 
 }  // namespace rgg

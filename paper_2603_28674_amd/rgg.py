@@ -29,6 +29,7 @@ RGG_E_BUSY = -7
 RGG_SE2, RGG_SE3, RGG_PLANAR_ARM = 0, 1, 2
 RGG_GREEN, RGG_GRAY, RGG_RED = 0, 1, 2
 RGG_PREC_FP64, RGG_PREC_FP32_RECHECK = 0, 1
+RGG_INLINE_ALL, RGG_INLINE_NONE = 0, -1
 RGG_VERDICT_FREE, RGG_VERDICT_COLLIDES, RGG_VERDICT_UNRESOLVED, RGG_VERDICT_BAD_ID = 0, 2, 3, 255
 RGG_VALIDATE_DEFAULT_LEVELS, RGG_VALIDATE_DEFAULT_ACTIVE = 24, 256
 
@@ -61,14 +62,16 @@ class rgg_build_opts(C.Structure):
                 ("n_obstacle_slots", C.c_int64), ("cell_size", C.c_double),
                 ("host_threads", C.c_int32), ("retest_capacity", C.c_int32),
                 ("item_edges", C.c_int32), ("outer_obb", C.c_int32), ("inner_splines", C.c_int32),
-                ("spline_tol", C.c_double), ("mem_budget", C.c_int64)]
+                ("spline_tol", C.c_double), ("pair_list_capacity", C.c_int32), ("inline_rounds", C.c_int32),
+                ("mem_budget", C.c_int64)]
 
 
 class rgg_update_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("n_changed", C.c_int32), ("n_gray", C.c_int64),
                 ("n_candidate_edges", C.c_int64), ("n_pairs", C.c_int64),
                 ("n_outer_hits", C.c_int64), ("n_rechecked", C.c_int64),
-                ("n_cells_visited", C.c_int64), ("test_bytes", C.c_int64)]
+                ("n_cells_visited", C.c_int64), ("test_bytes", C.c_int64), ("item_bytes", C.c_int64),
+                ("fp64_bytes", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -270,9 +273,12 @@ def make_desc(q, edges, keep):
 
 def make_opts(resolution=0.0, samples_per_edge=0, precision=RGG_PREC_FP64, band_rel=0.0,
               n_obstacle_slots=0, cell_size=0.0, host_threads=0, retest_capacity=0,
-              item_edges=0, outer_obb=False, inner_splines=False, spline_tol=0.0, mem_budget=0):
+              item_edges=0, outer_obb=False, inner_splines=False, spline_tol=0.0, mem_budget=0,
+              pair_list_capacity=0, inline_rounds=0):
     o = rgg_build_opts()
     o.mem_budget = mem_budget
+    o.pair_list_capacity = pair_list_capacity
+    o.inline_rounds = inline_rounds
     o.outer_obb = int(bool(outer_obb))
     o.inner_splines = int(bool(inner_splines))
     o.spline_tol = spline_tol
@@ -608,14 +614,14 @@ class Roadmap:
     def __init__(self, ctx, robot, q, edges, n_slots, resolution=0.0, samples_per_edge=0,
                  precision=RGG_PREC_FP64, band_rel=0.0, cell_size=0.0, host_threads=0,
                  retest_capacity=0, item_edges=0, outer_obb=False, inner_splines=False, spline_tol=0.0,
-                 mem_budget=0):
+                 mem_budget=0, pair_list_capacity=0, inline_rounds=0):
         keep = _Keep()
         self._keep = keep
         self.robot = make_robot(robot, keep)
         self.desc = make_desc(q, edges, keep)
         self.opts = make_opts(resolution, samples_per_edge, precision, band_rel, n_slots,
                               cell_size, host_threads, retest_capacity, item_edges, outer_obb,
-                              inner_splines, spline_tol, mem_budget)
+                              inner_splines, spline_tol, mem_budget, pair_list_capacity, inline_rounds)
         self.h = rgg_build(ctx, self.desc, self.robot, self.opts)
         self.E = int(np.asarray(edges).shape[0])
         self.M = int(n_slots)

@@ -49,18 +49,21 @@ def with_removals(w, rng):
 
 
 def check_sequence(ctx, w, precision, cell_size=0.0, band_rel=0.0, device_buffers=False,
-                   retest_capacity=0, item_edges=0, outer_obb=False, inner_splines=False, spline_tol=0.05):
+                   retest_capacity=0, item_edges=0, outer_obb=False, inner_splines=False, spline_tol=0.05,
+                   pair_list_capacity=0, inline_rounds=0):
     import torch
     from paper_2603_28674_amd import rgg
     import oracle
     print(f"[parity] {w.name} E={w.n_edges} M={w.n_slots} precision={precision} "
           f"cell={cell_size} band={band_rel} device_buffers={device_buffers} "
           f"retest_capacity={retest_capacity} item_edges={item_edges} obb={outer_obb} "
-          f"splines={inner_splines} tol={spline_tol}", flush=True)
+          f"splines={inner_splines} tol={spline_tol} pair_list_capacity={pair_list_capacity} "
+          f"inline_rounds={inline_rounds}", flush=True)
     g = rgg.Roadmap.from_workload(ctx, w, precision=precision, cell_size=cell_size,
                                   band_rel=band_rel, retest_capacity=retest_capacity,
                                   item_edges=item_edges, outer_obb=outer_obb,
-                                  inner_splines=inner_splines, spline_tol=spline_tol)
+                                  inner_splines=inner_splines, spline_tol=spline_tol,
+                                  pair_list_capacity=pair_list_capacity, inline_rounds=inline_rounds)
     o = oracle.from_workload(w, outer_obb=outer_obb, inner_splines=inner_splines, spline_tol=spline_tol)
     prev = w.absent()
     stats = []
@@ -200,14 +203,45 @@ def test_band_infinite_rechecks_every_decision(ctx):
 
 
 @pytest.mark.parametrize("kind", ["spatial", "planar"])
-def test_full_retest_regions_defer_whole_items(ctx, kind):
+@pytest.mark.parametrize("pair_list_capacity,inline_rounds", [(0, 0), (0, -1), (1, -1), (64, -1), (0, 2)])
+def test_full_retest_regions_defer_whole_items(ctx, kind, pair_list_capacity, inline_rounds):
     """With room for one re-test pair per block and every decision inside the
-    band, blocks leave whole work items to the binary64 pass."""
+    band, blocks leave whole work items to the binary64 pass.  With room for
+    one pair (or 64) in each listing block's pair list, the listing blocks
+    test most rounds themselves (the fused path, deferring items and
+    withdrawing their listed pairs); with no inline rounds (-1) the shares
+    get every round that fits, with every round inline (0, the fused kernel)
+    there are no shares.  The pairs of a deferred item count once whichever
+    block listed or tested them."""
     from paper_2603_28674_amd import rgg
     w = workload(kind, n_updates=2, seed=26)
     stats = check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, band_rel=float("inf"),
-                           retest_capacity=1)
-    assert all(s["n_rechecked"] > 0 for s in stats)
+                           retest_capacity=1, pair_list_capacity=pair_list_capacity, inline_rounds=inline_rounds)
+    assert all(s["n_rechecked"] == s["n_pairs"] > 0 for s in stats)
+
+
+@pytest.mark.parametrize("kind", ["spatial", "planar", "arm"])
+@pytest.mark.parametrize("inline_rounds", [-1, 1, 3])
+def test_inline_rounds_do_not_change_labels(ctx, kind, inline_rounds):
+    """However the pair rounds are split between the listing blocks and the
+    balanced pair testing, labels and gray lists are the oracle's, and every
+    pair is counted once."""
+    from paper_2603_28674_amd import rgg
+    w = with_removals(workload(kind, n_updates=3, seed=28), np.random.default_rng(6))
+    stats = check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, inline_rounds=inline_rounds)
+    ref = check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK)   # every round inline
+    assert [s["n_pairs"] for s in stats] == [s["n_pairs"] for s in ref]
+
+
+@pytest.mark.parametrize("kind", ["spatial", "arm"])
+@pytest.mark.parametrize("pair_list_capacity", [1, 100])
+def test_pair_list_capacity_does_not_change_labels(ctx, kind, pair_list_capacity):
+    """Pair lists too small for the items: rounds that do not fit are tested
+    by the listing blocks themselves; labels do not change."""
+    from paper_2603_28674_amd import rgg
+    w = with_removals(workload(kind, n_updates=3, seed=27), np.random.default_rng(5))
+    check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, pair_list_capacity=pair_list_capacity,
+                   inline_rounds=rgg.RGG_INLINE_NONE)
 
 
 @pytest.mark.parametrize("kind", ["planar", "arm"])
@@ -380,3 +414,34 @@ def test_roadmap_admission_by_device_memory(ctx):
         g = rgg.Roadmap.from_workload(ctx, w, precision=rgg.RGG_PREC_FP32_RECHECK, mem_budget=need, **mode)
         assert g.info()["device_bytes"] == need
         g.close()
+
+
+@pytest.mark.parametrize("precision,inline_rounds", [(1, 0), (1, -1), (0, 0)])
+def test_stage_timing(ctx, precision, inline_rounds):
+    """Per-update stage timing: every timed update is counted, the item
+    kernel's stage takes time in its slot (FP32: ms[2], with the pair
+    testing in ms[3] when pairs are listed; FP64: ms[3]), and the timed
+    updates still give the oracle's labels."""
+    from paper_2603_28674_amd import rgg
+    import oracle
+    w = workload("spatial", n_updates=3, seed=29)
+    print(f"[timing] precision={precision} inline_rounds={inline_rounds}", flush=True)
+    g = rgg.Roadmap.from_workload(ctx, w, precision=precision, inline_rounds=inline_rounds)
+    o = oracle.from_workload(w)
+    rgg.rgg_timing_enable(g.h, True)
+    prev = w.absent()
+    for cur in w.boxes:
+        gl, gg, n, r = g.update(prev, cur)
+        ol, og = o.update(prev, cur)
+        assert np.array_equal(gl, ol) and np.array_equal(gg, og)
+        prev = cur
+    ms, n = rgg.rgg_timing_read(g.h)
+    assert n == len(w.boxes) and ms[0] > 0 and ms[5] > 0
+    if precision == rgg.RGG_PREC_FP64:
+        assert ms[3] > 0
+    else:
+        assert ms[2] > 0 and ms[4] > 0
+        assert r.item_bytes > 0 and (r.test_bytes - r.item_bytes - r.fp64_bytes > 0) == (inline_rounds != 0)
+    ms, n = rgg.rgg_timing_read(g.h)
+    assert n == 0 and not ms.any()
+    g.close()

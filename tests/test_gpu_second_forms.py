@@ -64,6 +64,10 @@ def test_second_forms_every_pair_retested(ctx, kind, mode):
     else:
         assert all(s["n_rechecked"] == s["n_pairs"] for s in stats)
     check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, band_rel=float("inf"), retest_capacity=1, **mode)
+    check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, band_rel=float("inf"), retest_capacity=1,
+                   pair_list_capacity=1, inline_rounds=rgg.RGG_INLINE_NONE, **mode)
+    check_sequence(ctx, w, rgg.RGG_PREC_FP32_RECHECK, band_rel=float("inf"), retest_capacity=1,
+                   inline_rounds=rgg.RGG_INLINE_NONE, **mode)
 
 
 @pytest.mark.parametrize("cell_size", [-1.0, 0.0, 3.0])

@@ -119,7 +119,8 @@ def test_bad_second_form_options():
     desc = rgg.make_desc(w.q, w.edges, keep)
     robot = rgg.make_robot(w.robot, keep)
     for kw in (dict(inner_splines=True, spline_tol=1.0), dict(inner_splines=True, spline_tol=-0.5),
-               dict(inner_splines=True, spline_tol=float("nan"))):
+               dict(inner_splines=True, spline_tol=float("nan")), dict(inline_rounds=-2),
+               dict(inline_rounds=(1 << 20) + 1), dict(pair_list_capacity=-1)):
         opts = rgg.make_opts(w.resolution, w.samples_per_edge, n_obstacle_slots=w.n_slots, **kw)
         with pytest.raises(rgg.RggError):
             rgg.rgg_debug_second_forms(desc, robot, opts, 0, w.n_edges)
@@ -242,7 +243,7 @@ def _fnv1a64(data: bytes) -> int:
 
 
 def _roadmap_file(configs, checksum_ok=True):
-    """A planar one-sphere roadmap file, format version 3, whose edges hold
+    """A planar one-sphere roadmap file, format version 4, whose edges hold
     `configs[e]` configurations each; the checksum is recomputed over the
     crafted bytes (as anyone editing such a file can do)."""
     D, B, E, M, dof = 2, 1, len(configs), 1, 3
@@ -254,7 +255,7 @@ def _roadmap_file(configs, checksum_ok=True):
         ("chunk", "<i4"), ("retest", "<i4"), ("E", "<i8"), ("M", "<i8"), ("band", "<f4"),
         ("one_cell", "<i4"), ("cell", "<f8"), ("n_samp", "<i8"), ("n_cap", "<i8")]))
     assert hdr.dtype.itemsize == 80
-    hdr[0] = (b"RGGMAP01", 3, D, B, 1, 256, 1024, E, M, 1e-5, 1, float("inf"), n_samp, n_cap)
+    hdr[0] = (b"RGGMAP01", 4, D, B, 1, 256, 1024, E, M, 1e-5, 1, float("inf"), n_samp, n_cap)
     samp = np.linspace(0.0, 1.0, max(n_samp, 1))[:n_samp]
     cap = np.zeros(n_cap)
     cap[2 * D * B:: (2 * D + 1) * B] = 0.5
@@ -270,7 +271,8 @@ def _roadmap_file(configs, checksum_ok=True):
     vrob["rad"][0, 0] = 0.25
     motion = np.zeros(E * (2 * dof + 3))
     delta = np.zeros(E * B)
-    forms = np.array([0, 1], dtype=np.int32)          # capsules and copies; one body
+    # capsules and copies; one body; pair lists of 512 pairs, every round listed
+    forms = np.array([0, 1, 512, 0], dtype=np.int32)
     body = b"".join(a.tobytes() for a in (hdr, soff, samp, cap, radius, aabb, resident, cnt, vrob,
                                           motion, delta, forms))
     s = _fnv1a64(body) ^ (0 if checksum_ok else 1)
