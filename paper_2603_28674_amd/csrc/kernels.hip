@@ -2212,18 +2212,76 @@ __device__ inline int owner_of(const BatchReq *tab, int n, int tile, bool write_
     return s_r;
 }
 
+// The batch's two label passes.  The first writes the labels as it counts
+// a tile's GRAY edges (when the update succeeded and the caller asked for
+// labels), so the second reads one byte per edge instead of the 8-byte
+// counters to place the GRAY ids.
 __global__ void __launch_bounds__(kBlock) k_count_batch(const BatchReq *tab, int n)
 {
+    __shared__ int s_w[kWaves];
     const int r = owner_of(tab, n, (int)blockIdx.x, false);
     const BatchReq &q = tab[r];
-    count_body(q.rm, (int)blockIdx.x - q.tile0);
+    const RmDev &rm = q.rm;
+    const int tile = (int)blockIdx.x - q.tile0;
+    const int tid = threadIdx.x;
+    const int64_t e0 = (int64_t)tile * kLabelTile + (int64_t)tid * kLabelRun;
+    uint8_t lab[kLabelRun];
+    const int ng = run_labels(rm, e0, lab);
+    if (q.a.labels && rm.ctl->status == RGG_OK) store_run(rm, q.a.labels, nullptr, 0, e0, lab, 0);
+    const int tot = block_sum(ng, s_w);
+    if (tid == 0) rm.tile_cnt[tile] = tot;
+}
+
+// A run's labels as k_count_batch wrote them.
+__device__ __forceinline__ int load_labels(const RmDev &rm, const uint8_t *labels, int64_t e0,
+                                           uint8_t (&lab)[kLabelRun])
+{
+    if (e0 + kLabelRun <= rm.E && ((uintptr_t)(labels + e0) & 15u) == 0) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(labels + e0);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int h = 0; h < kLabelRun; ++h) lab[h] = (uint8_t)(w[h >> 2] >> (8 * (h & 3)));
+    } else {
+#pragma unroll
+        for (int h = 0; h < kLabelRun; ++h) lab[h] = e0 + h < rm.E ? labels[e0 + h] : (uint8_t)RGG_GREEN;
+    }
+    int ng = 0;
+#pragma unroll
+    for (int h = 0; h < kLabelRun; ++h) ng += (e0 + h < rm.E && lab[h] == RGG_GRAY) ? 1 : 0;
+    return ng;
 }
 
 __global__ void __launch_bounds__(kBlock) k_write_batch(const BatchReq *tab, int n)
 {
     const int r = owner_of(tab, n, (int)blockIdx.x, true);
     const BatchReq &q = tab[r];
-    write_body(q.rm, q.a.labels, q.a.gray, q.a.gray_cap, q.a.res, 0, (int)blockIdx.x - q.wtile0);
+    const int tile = (int)blockIdx.x - q.wtile0;
+    if (!q.a.labels || tile == q.rm.ntiles) {
+        write_body(q.rm, q.a.labels, q.a.gray, q.a.gray_cap, q.a.res, 0, tile);
+        return;
+    }
+    // the labels are written: the GRAY ids from them
+    __shared__ int s_w[kWaves];
+    const RmDev &rm = q.rm;
+    const int tid = threadIdx.x;
+    const int status = rm.ctl->status;
+    if (tid == 0 && tile == 0 && q.a.res) {
+        q.a.res->status = status;
+        q.a.res->n_changed = rm.ctl->n_chg;
+        if (status != RGG_OK) q.a.res->n_gray = 0;
+    }
+    if (status != RGG_OK) return;
+    int before = 0;
+    for (int t = tid; t < tile; t += kBlock) before += rm.tile_cnt[t];
+    before = block_sum(before, s_w);
+    const int64_t e0 = (int64_t)tile * kLabelTile + (int64_t)tid * kLabelRun;
+    uint8_t lab[kLabelRun];
+    const int ng = load_labels(rm, q.a.labels, e0, lab);
+    int tot;
+    const int pre = block_scan(ng, &tot, s_w);
+    if (tid == 0 && tile == rm.ntiles - 1 && q.a.res) q.a.res->n_gray = (int64_t)before + tot;
+    if (tot == 0) return;
+    store_run(rm, nullptr, q.a.gray, q.a.gray_cap, e0, lab, (int64_t)before + pre);
 }
 
 }  // namespace
