@@ -790,6 +790,23 @@ __device__ inline uint32_t probe_key(float mg, float t, int sphere)
     return (ordered_key(mg) & 0xFFFF0000u) | (tq << 6) | (uint32_t)sphere;
 }
 
+// A step in [1, n) coprime with n, near n / 2 (1 for n <= 2): k * step % n
+// then visits 0 .. n-1 in a spread order.
+__device__ inline int coprime_step(int n)
+{
+    if (n <= 2) return 1;
+    for (int s = n / 2 + 1; s < n; ++s) {
+        int a = s, b = n;
+        while (b) {
+            const int t = a % b;
+            a = b;
+            b = t;
+        }
+        if (a == 1) return s;
+    }
+    return 1;
+}
+
 // One round of at most kPairCap pairs listed in L.pe (edge slot << 16 |
 // entry): the outer test (capsules, then the oriented boxes), the probe, the
 // inner test (copies or spline segments) and the decisions.  Item blocks
@@ -1072,20 +1089,45 @@ __device__ __forceinline__ void test_round(const RmDev &rm, Lds &L, const T *s_r
             __syncthreads();
         }
         // each thread gathers kCopyU copies (all their loads in
-        // flight together), then tests them
+        // flight together), then tests them.  When the copies take several
+        // passes (every sphere has jfix copies), the passes go through the
+        // copy indices in groups of kCopyU, a group of one row per thread,
+        // the groups in a strided order; a row whose pair has already met
+        // the box is skipped: that pair's S is decided.
         constexpr int kCopyU = 4;
         const T *segb = kF32 ? (const T *)rm.seg32 : (const T *)rm.seg64;
-        for (int c0 = 0; c0 < ncopies; c0 += kBlock * kCopyU) {
+        const bool grouped = !kSpl && jfix && ncopies > kBlock * kCopyU;
+        const int ngr = grouped ? (jfix + kCopyU - 1) / kCopyU : 1;
+        const int gstep = grouped ? coprime_step(ngr) : 1;
+        const int nloop = grouped ? nr * ngr * kCopyU : ncopies;
+        for (int c0 = 0; c0 < nloop; c0 += kBlock * kCopyU) {
             T q[kCopyU][kSpl ? kSegW : D];
             int cu_p[kCopyU], cu_i[kCopyU];
+            int g_r = -1, g_j0 = 0;   // grouped: this thread's row and first copy index
+            if (grouped) {
+                const int f = c0 / kCopyU + tid;
+                if (f < nr * ngr) {
+                    const int g = f / nr;
+                    g_r = f - g * nr;
+                    g_j0 = ((g * gstep) % ngr) * kCopyU;
+                    // other waves may be setting the bit now: reading it
+                    // late only costs a skipped skip
+                    if (c0 > 0 && (__hip_atomic_load(&L.sf[L.u.rw.row[g_r] >> 6], __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP) & 1u))
+                        g_r = -1;
+                }
+            }
 #pragma unroll
             for (int u = 0; u < kCopyU; ++u) {
                 const int cidx = c0 + u * kBlock + tid;
                 cu_p[u] = -1;
                 cu_i[u] = 0;
-                if (cidx < ncopies) {
+                if (grouped ? (g_r >= 0 && g_j0 + u < jfix) : cidx < ncopies) {
                     int r, jj;
-                    if (!kSpl && jfix) {
+                    if (grouped) {
+                        r = g_r;
+                        jj = g_j0 + u;
+                    } else if (!kSpl && jfix) {
                         r = cidx / jfix;
                         jj = cidx - r * jfix;
                     } else {
