@@ -335,8 +335,10 @@ struct rgg_batch {
     hipEvent_t done[kRing] = {};      // end of the launch that used the slot
     bool used[kRing] = {};
     int ring = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // one captured graph per ring slot: its first kernel copies that slot's
+    // host table
+    hipGraph_t graph[kRing] = {};
+    hipGraphExec_t exec[kRing] = {};
     std::vector<BatchGroup> groups;
     bool any_grid = false;
     int tiles = 0, wtiles = 0;
@@ -364,12 +366,34 @@ struct rgg_batch {
             if (done[k]) hipEventDestroy(done[k]);
             if (h_tab[k]) hipHostFree(h_tab[k]);
         }
-        if (exec) hipGraphExecDestroy(exec);
-        if (graph) hipGraphDestroy(graph);
+        for (int k = 0; k < kRing; ++k) {
+            if (exec[k]) hipGraphExecDestroy(exec[k]);
+            if (graph[k]) hipGraphDestroy(graph[k]);
+        }
         if (d_tab) hipFree(d_tab);
         if (d_grp) hipFree(d_grp);
     }
 };
+
+// (Re)builds the batch's graphs, one per ring slot: the slot's table copy,
+// then the batch's kernels.  The kernels depend on whether any roadmap uses
+// a grid, so tuning rebuilds them.
+static rgg_status build_batch_graphs(rgg_batch *b)
+{
+    for (int k = 0; k < rgg_batch::kRing; ++k) {
+        if (b->exec[k]) (void)hipGraphExecDestroy(b->exec[k]);
+        if (b->graph[k]) (void)hipGraphDestroy(b->graph[k]);
+        b->exec[k] = nullptr;
+        b->graph[k] = nullptr;
+        HIP_OR_FAIL(hipGraphCreate(&b->graph[k], 0), "hipGraphCreate");
+        hipGraphNode_t last = nullptr;
+        HIP_OR_FAIL(add_batch_nodes(b->graph[k], b->d_tab, b->h_tab[k], b->d_grp, b->n, b->groups.data(),
+                                    (int)b->groups.size(), b->any_grid, b->tiles, b->wtiles, nullptr, &last),
+                    "hipGraphAddKernelNode");
+        HIP_OR_FAIL(hipGraphInstantiate(&b->exec[k], b->graph[k], nullptr, nullptr, 0), "hipGraphInstantiate");
+    }
+    return RGG_OK;
+}
 
 extern "C" {
 
@@ -1117,12 +1141,8 @@ rgg_status rgg_batch_create(rgg_context *ctx, int32_t n, rgg_roadmap *const *rms
         HIP_OR_FAIL(hipHostMalloc((void **)&b->h_tab[k], sizeof(BatchReq) * n, hipHostMallocDefault), "pinned table");
         HIP_OR_FAIL(hipEventCreateWithFlags(&b->done[k], hipEventDisableTiming), "hipEventCreate");
     }
-    HIP_OR_FAIL(hipGraphCreate(&b->graph, 0), "hipGraphCreate");
-    hipGraphNode_t last = nullptr;
-    HIP_OR_FAIL(add_batch_nodes(b->graph, b->d_tab, b->d_grp, n, groups.data(), (int)groups.size(), b->any_grid,
-                                b->tiles, b->wtiles, nullptr, &last),
-                "hipGraphAddKernelNode");
-    HIP_OR_FAIL(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    rgg_status st = build_batch_graphs(b.get());
+    if (st != RGG_OK) return st;
     *out = b.release();
     return RGG_OK;
 }
@@ -1158,7 +1178,6 @@ static rgg_status batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *s
         rgg_status st = order_after_previous(rm, s);
         if (st != RGG_OK) return st;
     }
-    HIP_OR_FAIL(hipMemcpyAsync(b->d_tab, h, sizeof(BatchReq) * b->n, hipMemcpyHostToDevice, s), "copy batch table");
     BatchTiming *tm = nullptr;
     if (b->timing && !graph) {
         if (b->t_pool.empty()) {
@@ -1171,10 +1190,10 @@ static rgg_status batch_launch(rgg_batch *b, const rgg_update_req *reqs, void *s
         tm = &b->t_pending.back();
     }
     if (graph)
-        HIP_OR_FAIL(hipGraphLaunch(b->exec, s), "hipGraphLaunch");
+        HIP_OR_FAIL(hipGraphLaunch(b->exec[slot], s), "hipGraphLaunch");
     else
-        HIP_OR_FAIL(launch_batch(s, b->d_tab, b->d_grp, b->n, b->groups.data(), (int)b->groups.size(), b->any_grid,
-                                 b->tiles, b->wtiles, tm),
+        HIP_OR_FAIL(launch_batch(s, b->d_tab, h, b->d_grp, b->n, b->groups.data(), (int)b->groups.size(),
+                                 b->any_grid, b->tiles, b->wtiles, tm),
                     "batch launch");
     HIP_OR_FAIL(hipEventRecord(b->done[slot], s), "hipEventRecord");
     b->used[slot] = true;
@@ -1309,7 +1328,7 @@ rgg_status rgg_update_batch_noalloc(rgg_context *ctx, int32_t n, const rgg_updat
     }
     HIP_OR_FAIL(hipMemcpyAsync(d_tab, h_tab, sizeof(BatchReq) * n, hipMemcpyHostToDevice, s), "copy batch table");
     HIP_OR_FAIL(hipMemcpyAsync(d_grp, h_grp, sizeof(int32_t) * n, hipMemcpyHostToDevice, s), "copy batch rows");
-    HIP_OR_FAIL(launch_batch(s, d_tab, d_grp, n, groups, n_groups, any_grid, tile, wtile), "batch launch");
+    HIP_OR_FAIL(launch_batch(s, d_tab, nullptr, d_grp, n, groups, n_groups, any_grid, tile, wtile), "batch launch");
     for (int32_t k = 0; k < n; ++k) {
         rgg_status st = finish_update(reqs[k].rm, s);
         if (st != RGG_OK) return st;
@@ -1419,7 +1438,7 @@ rgg_status rgg_batch_tune(rgg_batch *b, const rgg_box *const *obstacles_a, const
     auto run = [&](int count) -> rgg_status {
         for (int r = 0; r < count; ++r)
             for (BatchReq *tab : {d_fwd, d_back})
-                HIP_OR_FAIL(launch_batch(s, tab, b->d_grp, b->n, b->groups.data(), (int)b->groups.size(), b->any_grid,
+                HIP_OR_FAIL(launch_batch(s, tab, nullptr, b->d_grp, b->n, b->groups.data(), (int)b->groups.size(), b->any_grid,
                                          b->tiles, b->wtiles),
                             "batch launch");
         return RGG_OK;
@@ -1429,22 +1448,9 @@ rgg_status rgg_batch_tune(rgg_batch *b, const rgg_box *const *obstacles_a, const
     // are; the captured graph's kernels depend on whether any uses a grid
     b->any_grid = false;
     for (rgg_roadmap *rm : b->rms) b->any_grid = b->any_grid || rm->dv.ncells > 1;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    hipGraphNode_t last = nullptr;
-    HIP_OR_FAIL(hipGraphCreate(&graph, 0), "hipGraphCreate");
-    hipError_t e = add_batch_nodes(graph, b->d_tab, b->d_grp, b->n, b->groups.data(), (int)b->groups.size(),
-                                   b->any_grid, b->tiles, b->wtiles, nullptr, &last);
-    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        hipGraphDestroy(graph);
-        return hip_fail(e, "batch graph");
-    }
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->graph = graph;
-    b->exec = exec;
+    const rgg_status sg = build_batch_graphs(b);
     if (st != RGG_OK) return st;
+    if (sg != RGG_OK) return sg;
     for (rgg_roadmap *rm : b->rms) {
         st = finish_update(rm, s);
         if (st != RGG_OK) return st;

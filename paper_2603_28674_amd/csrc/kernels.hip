@@ -2497,17 +2497,36 @@ hipError_t add_update_nodes(hipGraph_t g, const RmDev &rm, const UpdateArgs &a, 
 
 namespace {
 
+// Copies the request table from pinned host memory into device memory: the
+// device reads the host rows itself, so a batched launch needs no copy
+// engine (whose hand-over to the kernels' queue costs more than the copy).
+// One word per thread: every read of host memory is in flight at once.
+__global__ void __launch_bounds__(kBlock) k_table(uint32_t *dst, const uint32_t *src, int n_words)
+{
+    const int k = (int)blockIdx.x * kBlock + (int)threadIdx.x;
+    if (k < n_words) dst[k] = src[k];
+}
+static_assert(sizeof(BatchReq) % 4 == 0, "request rows are copied as 32-bit words");
+
 // The kernels of a batched update in order, each handed to `emit(fn, grid,
-// block, args)` (a graph-node adder or a stream launcher).
+// block, args)` (a graph-node adder or a stream launcher).  With `h_tab`
+// (pinned host rows) the first kernel copies them to `tab`.
 // `after(stage)` follows each kernel: 0 diff, 1 cells, 3 item, 4 binary64
 // pass, 5 labels (count and write).
 template <typename Emit, typename After>
-hipError_t batch_kernels(Emit emit, After after, const BatchReq *tab, const int32_t *grp, int n,
-                         const BatchGroup *groups, int n_groups, bool any_grid, int n_tiles, int n_wtiles)
+hipError_t batch_kernels(Emit emit, After after, const BatchReq *tab, const BatchReq *h_tab, const int32_t *grp,
+                         int n, const BatchGroup *groups, int n_groups, bool any_grid, int n_tiles, int n_wtiles)
 {
     const BatchReq *t = tab;
     int nn = n;
     hipError_t err;
+    uint32_t *t_dst = reinterpret_cast<uint32_t *>(const_cast<BatchReq *>(tab));
+    const uint32_t *t_src = reinterpret_cast<const uint32_t *>(h_tab);
+    int n_words = (int)(sizeof(BatchReq) / 4) * n;
+    void *a_tab[] = {(void *)&t_dst, (void *)&t_src, (void *)&n_words};
+    if (h_tab && (err = emit((void *)k_table, dim3((n_words + kBlock - 1) / kBlock), dim3(kBlock), a_tab)) !=
+                     hipSuccess)
+        return err;
     void *a_diff[] = {(void *)&t};
     if ((err = emit((void *)k_diff_batch, dim3(n), dim3(kDiffBlock), a_diff)) != hipSuccess) return err;
     if ((err = after(0)) != hipSuccess) return err;
@@ -2540,7 +2559,7 @@ hipError_t batch_kernels(Emit emit, After after, const BatchReq *tab, const int3
 
 }  // namespace
 
-hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp, int n,
+hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const BatchReq *h_tab, const int32_t *grp, int n,
                            const BatchGroup *groups, int n_groups, bool any_grid, int n_tiles,
                            int n_wtiles, hipGraphNode_t dep, hipGraphNode_t *last)
 {
@@ -2559,7 +2578,7 @@ hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp
         return err;
     };
     auto none = [](int) { return hipSuccess; };
-    hipError_t err = batch_kernels(add, none, tab, grp, n, groups, n_groups, any_grid, n_tiles, n_wtiles);
+    hipError_t err = batch_kernels(add, none, tab, h_tab, grp, n, groups, n_groups, any_grid, n_tiles, n_wtiles);
     if (err == hipSuccess) *last = prev;
     return err;
 }
@@ -2575,15 +2594,16 @@ hipError_t batch_scratch_address(void **ptr)
     return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
 }
 
-hipError_t launch_batch(hipStream_t s, const BatchReq *tab, const int32_t *grp, int n, const BatchGroup *groups,
-                        int n_groups, bool any_grid, int n_tiles, int n_wtiles, BatchTiming *timing)
+hipError_t launch_batch(hipStream_t s, const BatchReq *tab, const BatchReq *h_tab, const int32_t *grp, int n,
+                        const BatchGroup *groups, int n_groups, bool any_grid, int n_tiles, int n_wtiles,
+                        BatchTiming *timing)
 {
     auto launch = [&](void *fn, dim3 grid, dim3 block, void **args) -> hipError_t {
         return hipLaunchKernel(fn, grid, block, args, 0, s);
     };
     if (!timing) {
         auto none = [](int) { return hipSuccess; };
-        return batch_kernels(launch, none, tab, grp, n, groups, n_groups, any_grid, n_tiles, n_wtiles);
+        return batch_kernels(launch, none, tab, h_tab, grp, n, groups, n_groups, any_grid, n_tiles, n_wtiles);
     }
     timing->n = 0;
     auto mark = [&](int stage) -> hipError_t {
@@ -2593,7 +2613,7 @@ hipError_t launch_batch(hipStream_t s, const BatchReq *tab, const int32_t *grp, 
     };
     hipError_t err = hipEventRecord(timing->ev[0], s);
     if (err != hipSuccess) return err;
-    return batch_kernels(launch, mark, tab, grp, n, groups, n_groups, any_grid, n_tiles, n_wtiles);
+    return batch_kernels(launch, mark, tab, h_tab, grp, n, groups, n_groups, any_grid, n_tiles, n_wtiles);
 }
 
 }  // namespace rgg

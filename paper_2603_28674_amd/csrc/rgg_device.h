@@ -166,7 +166,7 @@ hipError_t batch_scratch_address(void **ptr);
 struct BatchGroup {
     int32_t D, mixed, off, count;  // requests grp[off .. off + count)
 };
-hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const int32_t *grp, int n,
+hipError_t add_batch_nodes(hipGraph_t g, const BatchReq *tab, const BatchReq *h_tab, const int32_t *grp, int n,
                            const BatchGroup *groups, int n_groups, bool any_grid, int n_tiles,
                            int n_wtiles, hipGraphNode_t dep, hipGraphNode_t *last);
 // Events of a timed batched launch: ev[0] before the first kernel, ev[1 + k]
@@ -179,8 +179,9 @@ struct BatchTiming {
     int n;
 };
 // The same kernels launched on `s` (timed when `timing` is non-null).
-hipError_t launch_batch(hipStream_t s, const BatchReq *tab, const int32_t *grp, int n, const BatchGroup *groups,
-                        int n_groups, bool any_grid, int n_tiles, int n_wtiles, BatchTiming *timing = nullptr);
+hipError_t launch_batch(hipStream_t s, const BatchReq *tab, const BatchReq *h_tab, const int32_t *grp, int n,
+                        const BatchGroup *groups, int n_groups, bool any_grid, int n_tiles, int n_wtiles,
+                        BatchTiming *timing = nullptr);
 
 // Full validation of listed edges (rgg_validate): the robot, each edge's
 // motion parameters and chord-deviation bounds, and the resident slots.

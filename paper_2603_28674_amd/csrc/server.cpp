@@ -191,9 +191,9 @@ bool rgg_server::dispatch(Slot &slot, std::vector<Pending> &batch)
                                     hipMemcpyHostToDevice, s) != hipSuccess)
             return false;
     }
-    if (hipMemcpyAsync(slot.d_tab, slot.h_tab, sizeof(BatchReq) * n, hipMemcpyHostToDevice, s) != hipSuccess) return false;
-    if (launch_batch(s, slot.d_tab, slot.d_grp, n, groups.data(), (int)groups.size(), any_grid, tiles, wtiles) !=
-        hipSuccess)
+    // the batch's first kernel copies the slot's pinned table
+    if (launch_batch(s, slot.d_tab, slot.h_tab, slot.d_grp, n, groups.data(), (int)groups.size(), any_grid, tiles,
+                     wtiles) != hipSuccess)
         return false;
     // non-lazy requests: validate each gray list after the batch, on the
     // same stream, capped by the request's own result
