@@ -21,7 +21,8 @@
 #include "rgg_internal.h"
 #include "api_internal.h"
 
-static_assert(rgg::kLocalGridCells == rgg::kLocalCells, "pruning-grid size of host and device");
+static_assert(rgg::local_slabs(2) == rgg::slabs_of(2) && rgg::local_slabs(3) == rgg::slabs_of(3),
+              "slab counts of host and device");
 static_assert(rgg::kCopyStride3 == 4 && rgg::kCopyStride2 == 2, "sample layout of host and device");
 
 using namespace rgg;
@@ -112,11 +113,10 @@ rgg_status install_grid(rgg_roadmap *rm, const HostGrid &grid, int32_t chunk)
     for (int d = 0; d < 3; ++d) {
         dv.gdim[d] = grid.dim[d];
         dv.gorg[d] = grid.org[d];
-        dv.lg_org[d] = grid.lg_org[d];
-        dv.lg_dim[d] = grid.lg_dim[d];
+        dv.sl_org[d] = grid.sl_org[d];
+        dv.sl_inv[d] = grid.sl_inv[d];
     }
     dv.ginv = grid.inv;
-    dv.lg_inv = grid.lg_inv;
     dv.ncells = ncells;
     dv.items_cap = grid.items_cap;
     rgg_roadmap_info &in = rm->info;

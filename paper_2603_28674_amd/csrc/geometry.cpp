@@ -714,22 +714,11 @@ rgg_status build_grid_body(const HostGeometry &g, double cell_size, int32_t chun
     }
     out->inv = single ? 0.0 : 1.0 / h;
     out->cell = single ? INFINITY : h;
-    // local pruning grid: cells of the mean edge extent, at most kLocalGridCells
-    double hl = E ? ext_sum / (double)E : 0.0;
-    if (hl > 0.0 && std::isfinite(hl)) {
-        for (int it = 0; it < 256; ++it) {
-            double cells = 1.0;
-            for (int d = 0; d < D; ++d) cells *= std::max(1.0, ceil((hi[d] - lo[d]) / hl));
-            if (cells <= (double)kLocalGridCells) break;
-            hl *= 1.1;
-        }
-        for (int d = 0; d < 3; ++d) {
-            out->lg_org[d] = d < D ? (float)lo[d] : 0.0f;
-            out->lg_dim[d] = d < D ? (int32_t)std::max(1.0, ceil((hi[d] - lo[d]) / hl)) : 1;
-        }
-        while ((int64_t)out->lg_dim[0] * out->lg_dim[1] * out->lg_dim[2] > kLocalGridCells)
-            for (int d = 0; d < D; ++d) out->lg_dim[d] = std::max(1, out->lg_dim[d] - 1);
-        out->lg_inv = (float)(1.0 / hl);
+    // block-local slab masks: local_slabs(D) slabs per axis over the bounds
+    for (int d = 0; d < 3; ++d) {
+        out->sl_org[d] = d < D ? (float)lo[d] : 0.0f;
+        const double ext = d < D ? hi[d] - lo[d] : 0.0;
+        out->sl_inv[d] = ext > 0.0 && std::isfinite(ext) ? (float)(local_slabs(D) / ext) : 0.0f;
     }
     const int64_t ncell = (int64_t)out->dim[0] * out->dim[1] * out->dim[2];
     std::vector<int64_t> count(ncell + 1, 0);

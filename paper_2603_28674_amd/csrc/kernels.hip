@@ -670,11 +670,12 @@ constexpr int kPairCap = kBlock;          // pairs per round (one per thread)
 static_assert(rt_cap_of(1) == kPairCap, "a share's re-test region holds a round");
 constexpr int kRowCap = 256;              // (pair, sphere) rows per copy round
 constexpr int kOpenCap = 1024;            // capsule tests queued for the exact part
-constexpr int kWideCells = 64;            // pruning-grid cells an entry may cover
-constexpr int kEdgeCells = 64;            // pruning-grid cells an edge may visit
-static_assert(kWords == 4, "a pruning-grid cell holds one uint4 of entry bits");
+static_assert(kWords == 4, "a slab mask holds one uint4 of entry bits");
 static_assert(kSubTile <= 65536 && kItemCap <= 65536, "a pair is (edge slot << 16) | entry in 32 bits");
-static_assert(kLocalCells * 4 == kWords * kItemCap, "the overlap words reuse the pruning grid's storage");
+static_assert(kLocalCells * 4 == kWords * kItemCap, "the overlap words reuse the slab masks' storage");
+static_assert(2 * 3 * slabs_of(3) <= kLocalCells && 2 * 2 * slabs_of(2) <= kLocalCells && slabs_of(2) <= 128 &&
+                  slabs_of(3) <= 128,
+              "the slab masks fit their storage and one wavefront's scan (two slabs a lane)");
 static_assert(kOpenCap >= 3 * kRowCap + 1, "the rows fit the capsule queue's storage");
 static_assert(kOpenCap * 4 >= kPairCap * 8 + kBlock * 4 + 64 * 8, "the overflow re-test fits the queue's storage");
 
@@ -699,10 +700,12 @@ struct ItemLds {
     typename std::conditional<std::is_same<T, double>::value, ExactBoxes<double>, NoBoxes>::type x;
     typename std::conditional<std::is_same<T, float>::value, Radii32, NoRadii>::type r;
     union {
-        uint4 lgm[kLocalCells];           // pruning grid: staged entries per cell,
+        // slab masks: sm[(2 d + 0) n + s] the staged entries whose slab range
+        // on axis d starts at or before slab s, sm[(2 d + 1) n + s] those
+        // whose range ends at or after it (n = slabs_of(D))
+        uint4 sm[kLocalCells];
         uint32_t om[kWords][kItemCap];    // then the staged entries each edge's box meets
     } g;
-    uint32_t wide[kWords];                // staged entries over many cells
     uint32_t cfg0[kItemCap];              // first configuration of each edge (sample / B)
     int edge[kItemCap], ej[kItemCap];     // edge id, configurations per sphere
     float es[kItemCap];                   // edge s (largest |coordinate| of its box)
@@ -755,23 +758,13 @@ __device__ inline float band_of(float tau, float s, float R, float L)
     return tau * (s + R) * (R + L) + (s > 0.0f ? tau * tau * s * s : 0.0f);
 }
 
-// Pruning-grid cell range of a box (lo.xyz, hi.xyz), clamped to the grid.
-// floor, the subtraction and the product are monotone, so two boxes that
-// share a point share a cell.
-__device__ inline int lg_cell(float x, float org, float inv, int n)
+// Slab of coordinate x on axis d of the block-local slab masks, clamped to
+// [0, n).  The subtraction, the product and floor are monotone, so the slab
+// ranges of two boxes that share a point overlap on every axis.
+__device__ inline int slab_of(const RmDev &rm, int d, float x, int n)
 {
-    const float f = floorf((x - org) * inv);
+    const float f = floorf((x - rm.sl_org[d]) * rm.sl_inv[d]);
     return (int)fminf(fmaxf(f, 0.0f), (float)(n - 1));
-}
-
-__device__ inline void lg_range(const RmDev &rm, const float4 &lo, const float4 &hi, int r0[3], int r1[3])
-{
-    r0[0] = lg_cell(lo.x, rm.lg_org[0], rm.lg_inv, rm.lg_dim[0]);
-    r1[0] = lg_cell(hi.x, rm.lg_org[0], rm.lg_inv, rm.lg_dim[0]);
-    r0[1] = lg_cell(lo.y, rm.lg_org[1], rm.lg_inv, rm.lg_dim[1]);
-    r1[1] = lg_cell(hi.y, rm.lg_org[1], rm.lg_inv, rm.lg_dim[1]);
-    r0[2] = lg_cell(lo.z, rm.lg_org[2], rm.lg_inv, rm.lg_dim[2]);
-    r1[2] = lg_cell(hi.z, rm.lg_org[2], rm.lg_inv, rm.lg_dim[2]);
 }
 
 // order-preserving map of a binary32 value to an unsigned key
@@ -1308,7 +1301,7 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
     const bool single = rm.ncells == 1;
     const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
     const int jfix = rm.p_fixed ? rm.p_fixed / B : 0;
-    const int lgn = rm.lg_dim[0] * rm.lg_dim[1] * rm.lg_dim[2];
+    constexpr int kSl = slabs_of(D);   // slabs per axis of the slab masks
     // next work item of this block; false when there is none
     int rk = 0, li = deferred ? 0 : li0;
     auto next_item = [&](int &it) -> bool {
@@ -1402,11 +1395,10 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
         bool fused = !kList;   // some round of this item was tested here
         int n_round = 0;       // this item's pair rounds so far
         for (int j0 = 0; j0 < n_chg; j0 += kSubTile) {
-            // the pruning grid starts empty (the previous tile or item is
-            // done with its storage); the staging scan's barriers order this
-            // before the grid is filled
-            for (int q = tid; q < lgn; q += kBlock) L.g.lgm[q] = make_uint4(0u, 0u, 0u, 0u);
-            if (tid < kWords) L.wide[tid] = 0u;
+            // the slab masks start empty (the previous tile or item is done
+            // with their storage); the staging scan's barriers order this
+            // before they are filled
+            for (int q = tid; q < 2 * D * kSl; q += kBlock) L.g.sm[q] = make_uint4(0u, 0u, 0u, 0u);
             // stage the entries covering this cell
             const int j = j0 + tid;
             const bool first = pf && j0 == 0;
@@ -1444,31 +1436,52 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
             if (nt == 0) continue;   // uniform: nt is the block total
             const int nw = (nt + 31) >> 5;
             __syncthreads();
-            // block-local pruning grid: each cell's mask of the staged
-            // entries whose box covers it (an entry over more than kWideCells
-            // cells is a candidate of every edge)
+            // block-local slab masks: each staged entry marks the slab its
+            // range starts in and the slab it ends in, on every axis ...
             if (tid < nt) {
                 const float4 l = L.blo[tid], h = L.bhi[tid];
-                int r0[3], r1[3];
-                lg_range(rm, l, h, r0, r1);
-                const int ncov = (r1[0] - r0[0] + 1) * (r1[1] - r0[1] + 1) * (r1[2] - r0[2] + 1);
+                const float lo3[3] = {l.x, l.y, l.z}, hi3[3] = {h.x, h.y, h.z};
                 const uint32_t bit = 1u << (tid & 31);
                 const int wd = tid >> 5;
-                if (ncov > kWideCells) {
-                    atomicOr(&L.wide[wd], bit);
-                } else {
-                    uint32_t *mw = reinterpret_cast<uint32_t *>(L.g.lgm);
-                    for (int z = r0[2]; z <= r1[2]; ++z)
-                        for (int y = r0[1]; y <= r1[1]; ++y)
-                            for (int x = r0[0]; x <= r1[0]; ++x)
-                                atomicOr(&mw[((z * rm.lg_dim[1] + y) * rm.lg_dim[0] + x) * 4 + wd], bit);
+                uint32_t *mw = reinterpret_cast<uint32_t *>(L.g.sm);
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    atomicOr(&mw[((2 * d) * kSl + slab_of(rm, d, lo3[d], kSl)) * 4 + wd], bit);
+                    atomicOr(&mw[((2 * d + 1) * kSl + slab_of(rm, d, hi3[d], kSl)) * 4 + wd], bit);
                 }
             }
             __syncthreads();
+            // ... then each axis's start marks become "starts at or before s"
+            // (an OR over slabs 0..s) and its end marks "ends at or after s"
+            // (an OR over s..n-1): one wavefront per (axis, mark), each lane
+            // two slabs, the lanes joined by a wavefront scan
+            for (int a = wv; a < 2 * D; a += kWaves) {
+                const bool up = (a & 1) == 0;   // start marks: forward
+                uint4 *arr = L.g.sm + a * kSl;
+                const int s0 = 2 * lane, s1 = 2 * lane + 1;
+                auto at = [&](int s) -> uint4 & { return arr[up ? s : kSl - 1 - s]; };
+                uint4 v0 = s0 < kSl ? at(s0) : make_uint4(0u, 0u, 0u, 0u);
+                uint4 v1 = s1 < kSl ? at(s1) : make_uint4(0u, 0u, 0u, 0u);
+                v1 = make_uint4(v1.x | v0.x, v1.y | v0.y, v1.z | v0.z, v1.w | v0.w);
+                uint4 ex = v1;   // inclusive OR over lanes 0..lane, then shifted
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const uint32_t x = __shfl_up(ex.x, o), y = __shfl_up(ex.y, o), z = __shfl_up(ex.z, o),
+                                   w = __shfl_up(ex.w, o);
+                    if (lane >= o) ex = make_uint4(ex.x | x, ex.y | y, ex.z | z, ex.w | w);
+                }
+                uint4 pre = make_uint4(__shfl_up(ex.x, 1), __shfl_up(ex.y, 1), __shfl_up(ex.z, 1),
+                                       __shfl_up(ex.w, 1));
+                if (lane == 0) pre = make_uint4(0u, 0u, 0u, 0u);
+                if (s0 < kSl) at(s0) = make_uint4(pre.x | v0.x, pre.y | v0.y, pre.z | v0.z, pre.w | v0.w);
+                if (s1 < kSl) at(s1) = make_uint4(pre.x | v1.x, pre.y | v1.y, pre.z | v1.z, pre.w | v1.w);
+            }
+            __syncthreads();
             // the staged entries each of this thread's edges meets, 32 per
-            // word: the candidates of the cells its box covers (all reads of
-            // the pruning grid first: its storage then takes the words), then
-            // the exact test against the edge's box
+            // word: the candidates whose slab range meets the edge's on
+            // every axis (all reads of the slab masks first: their storage
+            // then takes the words), then the exact test against the edge's
+            // box
             float4 bl[kSlots], bh[kSlots];
             uint32_t cw[kSlots][kWords];
             // both slots' boxes are requested before either is used
@@ -1488,25 +1501,20 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
 #pragma unroll
                 for (int w = 0; w < kWords; ++w) cw[h][w] = 0u;
                 if (sl < n_e) {
-                    int r0[3], r1[3];
-                    lg_range(rm, bl[h], bh[h], r0, r1);
-                    const int ncov = (r1[0] - r0[0] + 1) * (r1[1] - r0[1] + 1) * (r1[2] - r0[2] + 1);
-                    if (ncov > kEdgeCells) {
+                    const float lo3[3] = {bl[h].x, bl[h].y, bl[h].z}, hi3[3] = {bh[h].x, bh[h].y, bh[h].z};
+                    uint4 m = make_uint4(~0u, ~0u, ~0u, ~0u);
 #pragma unroll
-                        for (int w = 0; w < kWords; ++w) cw[h][w] = ~0u;
-                    } else {
-#pragma unroll
-                        for (int w = 0; w < kWords; ++w) cw[h][w] = L.wide[w];
-                        for (int z = r0[2]; z <= r1[2]; ++z)
-                            for (int y = r0[1]; y <= r1[1]; ++y)
-                                for (int x = r0[0]; x <= r1[0]; ++x) {
-                                    const uint4 m = L.g.lgm[(z * rm.lg_dim[1] + y) * rm.lg_dim[0] + x];
-                                    cw[h][0] |= m.x;
-                                    cw[h][1] |= m.y;
-                                    cw[h][2] |= m.z;
-                                    cw[h][3] |= m.w;
-                                }
+                    for (int d = 0; d < D; ++d) {
+                        // entries starting at or before the edge's last slab
+                        // and ending at or after its first
+                        const uint4 st = L.g.sm[(2 * d) * kSl + slab_of(rm, d, hi3[d], kSl)];
+                        const uint4 en = L.g.sm[(2 * d + 1) * kSl + slab_of(rm, d, lo3[d], kSl)];
+                        m = make_uint4(m.x & st.x & en.x, m.y & st.y & en.y, m.z & st.z & en.z, m.w & st.w & en.w);
                     }
+                    cw[h][0] = m.x;
+                    cw[h][1] = m.y;
+                    cw[h][2] = m.z;
+                    cw[h][3] = m.w;
                 }
             }
             __syncthreads();

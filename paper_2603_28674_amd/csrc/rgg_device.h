@@ -70,12 +70,12 @@ struct RmDev {
     const int32_t *cell_start;
     const int32_t *cell_edges;
     int64_t items_cap;
-    // block-local pruning grid (binary32): cell of x on axis d is
-    // clamp(floor((x - lg_org[d]) * lg_inv), 0, lg_dim[d] - 1)
-    float lg_org[3];
-    float lg_inv;
-    int32_t lg_dim[3];
-    int32_t pad2;
+    // block-local slab masks (binary32): slab of x on axis d is
+    // clamp(floor((x - sl_org[d]) * sl_inv[d]), 0, slabs_of(D) - 1)
+    float sl_org[3];
+    float pad2;
+    float sl_inv[3];
+    int32_t pad4;
     // state and per-update scratch
     int2 *cnt;                 // [E] (outer, inner) counters
     uint32_t *cell_bits;       // [ceil(ncells/32)] touched cells, zero between updates
@@ -118,7 +118,9 @@ constexpr int kStatPairBytes = 3, kStatItemBytes = 6, kStatFp64Bytes = 7;
 constexpr int kStatBlocks = 2048;  // blocks of the item kernels
 constexpr int kMaxSlots = 4096;    // 2*slots changed entries at most
 
-constexpr int kLocalCells = 512;   // cells of the item kernel's pruning grid (at most)
+constexpr int kLocalCells = 512;   // uint4 words of the item kernel's slab masks (at most)
+// Slabs per axis of the item kernel's block-local slab masks.
+__host__ __device__ constexpr int slabs_of(int D) { return D == 3 ? 80 : 128; }
 constexpr int kCopyStride3 = 4;    // values per sample copy in 3-D (xyz + pad)
 constexpr int kCopyStride2 = 2;    // in 2-D
 constexpr int kRcCap = 1024;       // default re-test pairs one item-kernel block may queue

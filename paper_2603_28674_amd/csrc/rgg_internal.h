@@ -78,15 +78,14 @@ struct HostGrid {
     std::vector<int32_t> start;    // [ncells+1]
     std::vector<int32_t> edges;    // edge ids per cell, ascending
     int64_t items_cap = 0;         // sum over cells of max(1, ceil(n/chunk))
-    // Block-local pruning grid of the item kernel: at most kLocalCells cells
-    // of about the mean edge extent over the same bounds, in binary32
-    // (kLocalGridCells at most).
-    float lg_org[3] = {0, 0, 0};
-    float lg_inv = 0.0f;           // 0: one cell
-    int32_t lg_dim[3] = {1, 1, 1};
+    // Block-local slab masks of the item kernel: local_slabs(D) slabs per
+    // axis over the same bounds, in binary32.
+    float sl_org[3] = {0, 0, 0};
+    float sl_inv[3] = {0, 0, 0};   // slabs per unit length; 0: one slab
 };
 
-constexpr int kLocalGridCells = 512;   // equals kLocalCells of the device header
+// Slabs per axis of the slab masks (slabs_of of the device header).
+constexpr int local_slabs(int D) { return D == 3 ? 80 : 128; }
 
 // Cell of coordinate x: floor((x - org) * inv), as an integer in [-1, n]
 // (-1 below the grid, n above it).  The device evaluates the same binary64
