@@ -345,7 +345,7 @@ rgg_status rgg_update_batch(rgg_context *ctx, int32_t n, const rgg_update_req *r
  * hipMalloc, such as tight serving loops or harnesses that forbid it): the
  * batched update of rgg_update_batch, computing the same results, with the
  * request table in a fixed device array that the library holds (one per
- * device, up to 256 requests, 99 KiB, kept until the process ends)
+ * device, up to 256 requests, 121 KiB, kept until the process ends)
  * instead of a batch created per call.  Calls no allocator: no hipMalloc,
  * hipFree, pinned or pageable host allocation, graph or event creation.
  * Arguments as rgg_update_batch (device pointers in reqs, queued on

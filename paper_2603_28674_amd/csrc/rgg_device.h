@@ -158,6 +158,7 @@ constexpr int kMaxBatch = 256;     // requests per batched launch
 // allocates nothing.
 constexpr size_t kBatchTableBytes = (sizeof(BatchReq) * kMaxBatch + 255) / 256 * 256;
 constexpr size_t kBatchScratchBytes = kBatchTableBytes + sizeof(int32_t) * kMaxBatch;
+static_assert(kBatchScratchBytes <= 121 * 1024, "the documented size of the fixed request table");
 // Device address of that scratch on the current device (hipGetSymbolAddress).
 hipError_t batch_scratch_address(void **ptr);
 
