@@ -167,3 +167,46 @@ def test_batch_stage_timing(ctx):
     rgg.rgg_batch_destroy(b)
     for g in gs:
         g.close()
+
+
+def test_batch_graph_ring_wraps(ctx):
+    """Ten graph launches in a row, past the eight ring slots (each slot has
+    its own graph, whose first node copies that slot's host rows): every
+    update is the oracle's, with and without a stream synchronisation
+    between launches."""
+    import torch
+    from paper_2603_28674_amd import rgg
+    import oracle
+    dev = torch.device("cuda:0")
+    specs = mixed_workloads(10)[:3]
+    gs = [rgg.Roadmap.from_workload(ctx, w, precision=p, cell_size=c) for w, p, c in specs]
+    ors = [oracle.from_workload(w) for w, _, _ in specs]
+    b = rgg.rgg_batch_create(ctx, [g.h for g in gs])
+    stream = torch.cuda.current_stream().cuda_stream
+    bufs = []
+    for w, _, _ in specs:
+        states = torch.from_numpy(np.stack([w.absent()] + w.boxes)).to(dev)
+        # one label / gray / result buffer per update, so pipelined launches
+        # do not overwrite what is checked afterwards
+        bufs.append((states, torch.zeros((10, w.n_edges), dtype=torch.uint8, device=dev),
+                     torch.zeros((10, w.n_edges), dtype=torch.int64, device=dev),
+                     torch.zeros((10, rgg.RESULT_BYTES), dtype=torch.uint8, device=dev)))
+    print("[batch graph ring] 10 launches", flush=True)
+    for u in range(10):
+        reqs = [rgg.rgg_update_req(g.h.value, w.n_slots, st[u].data_ptr(), st[u + 1].data_ptr(), lab[u].data_ptr(),
+                                   gr[u].data_ptr(), w.n_edges, res[u].data_ptr())
+                for (w, _, _), g, (st, lab, gr, res) in zip(specs, gs, bufs)]
+        rgg.rgg_batch_launch_graph(b, reqs, stream)
+        if u % 3 == 2:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    for u in range(10):
+        for (w, _, _), o, (st, lab, gr, res) in zip(specs, ors, bufs):
+            ol, og = o.update(w.absent() if u == 0 else w.boxes[u - 1], w.boxes[u])
+            r = rgg.result_from_tensor(res[u])
+            assert r.status == 0 and r.n_gray == len(og), f"update {u}"
+            assert np.array_equal(lab[u].cpu().numpy(), ol), f"update {u}: labels"
+            assert np.array_equal(gr[u][: r.n_gray].cpu().numpy(), og), f"update {u}: gray list"
+    rgg.rgg_batch_destroy(b)
+    for g in gs:
+        g.close()
