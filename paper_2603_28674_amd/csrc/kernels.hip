@@ -233,7 +233,8 @@ __device__ inline bool same_box(const rgg_box &a, const rgg_box &b)
     return s;
 }
 
-__device__ inline bool present(const rgg_box &b, int D)
+template <int D>
+__device__ inline bool present(const rgg_box &b)
 {
     bool p = true;
 #pragma unroll
@@ -241,14 +242,17 @@ __device__ inline bool present(const rgg_box &b, int D)
     return p;
 }
 
-// returns whether the box covers at least one grid cell
+// returns whether the box covers at least one grid cell (D is the
+// roadmap's dimension, so the loop below is straight-line code)
+template <int D>
 __device__ bool write_entry(const RmDev &rm, int pos, const rgg_box &b, int sign)
 {
     ChgEntry en;
     float s = 0.0f;
     bool empty = false;
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-        if (k < rm.D) {
+        if (k < D) {
             en.lo[k] = b.lo[k];
             en.hi[k] = b.hi[k];
             en.lo32[k] = round_down(b.lo[k]);
@@ -275,12 +279,22 @@ __device__ bool write_entry(const RmDev &rm, int pos, const rgg_box &b, int sign
     return !empty;
 }
 
+// One block: validates the update, writes the changed entries and commits
+// the new boxes.  The block's first half takes the entry of a slot's old
+// box, the second half that of its new box, so each thread writes at most
+// one entry (the entry is a chain of binary64 roundings and cell indices,
+// which one wavefront runs at its latency); a chunk of the update covers
+// kDiffBlock / 2 slots, its old boxes' entries first.
+template <int D>
 __device__ __forceinline__ void diff_body(const RmDev &rm, const rgg_box *__restrict__ old_b,
                                           const rgg_box *__restrict__ new_b)
 {
+    constexpr int kHalf = kDiffBlock / 2;
     __shared__ int s_tot[kDiffBlock / 64];
     __shared__ int s_bad, s_mism, s_base, s_any;
     const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const int side = tid / kHalf;        // 0: the old box's entry, 1: the new box's
+    const int j = tid - side * kHalf;    // slot within the chunk
     if (tid == 0) {
         s_bad = 0;
         s_mism = 0;
@@ -294,41 +308,32 @@ __device__ __forceinline__ void diff_body(const RmDev &rm, const rgg_box *__rest
     __syncthreads();
     bool dirty0 = false;   // the first chunk's slot changes (kept for the commit)
     rgg_box n0;
-    for (int64_t base = 0; base < rm.M; base += kDiffBlock) {
-        const int64_t k = base + tid;
-        int cnt = 0;
-        bool po = false, pn = false;
-        rgg_box o, n;
+    for (int64_t base = 0; base < rm.M; base += kHalf) {
+        const int64_t k = base + j;
+        bool emit = false;
+        rgg_box b;
         if (k < rm.M) {
-            o = old_b[k];
-            n = new_b[k];
-            const rgg_box r = rm.resident[k];
-            if (!box_ok(o) || !box_ok(n)) atomicOr(&s_bad, 1);
-            if (!same_box(o, r)) atomicOr(&s_mism, 1);
-            if (base == 0) {
+            const rgg_box o = old_b[k], n = new_b[k], r = rm.resident[k];
+            if (side == 0) {
+                if (!box_ok(o) || !box_ok(n)) atomicOr(&s_bad, 1);
+                if (!same_box(o, r)) atomicOr(&s_mism, 1);
+            } else if (base == 0) {
                 dirty0 = !same_box(n, r);
                 n0 = n;
             }
-            if (!same_box(o, n)) {
-                po = present(o, rm.D);
-                pn = present(n, rm.D);
-                cnt = (int)po + (int)pn;
-            }
+            b = side ? n : o;
+            emit = !same_box(o, n) && present<D>(b);
         }
-        const uint64_t b1 = __ballot(cnt >= 1), b2 = __ballot(cnt >= 2);
-        const int pre = __popcll(b1 & lanes_below()) + __popcll(b2 & lanes_below());
-        if (lane == 0) s_tot[wave] = __popcll(b1) + __popcll(b2);
+        const uint64_t bm = __ballot(emit);
+        if (lane == 0) s_tot[wave] = __popcll(bm);
         __syncthreads();
-        int off = s_base, tot = 0;
+        int pos = s_base, tot = 0;
         for (int w = 0; w < kDiffBlock / 64; ++w) {
-            if (w < wave) off += s_tot[w];
+            if (w < wave) pos += s_tot[w];
             tot += s_tot[w];
         }
-        int pos = off + pre;
-        bool any = false;
-        if (po) any = write_entry(rm, pos++, o, -1);
-        if (pn) any = write_entry(rm, pos, n, +1) || any;
-        if (any) s_any = 1;
+        pos += __popcll(bm & lanes_below());
+        if (emit && write_entry<D>(rm, pos, b, side ? +1 : -1)) s_any = 1;
         __syncthreads();
         if (tid == 0) s_base += tot;
         __syncthreads();
@@ -342,18 +347,19 @@ __device__ __forceinline__ void diff_body(const RmDev &rm, const rgg_box *__rest
         if (rm.ncells == 1) rm.ctl->n_items = (status == RGG_OK && s_any) ? (int32_t)rm.items_cap : 0;
     }
     if (status == RGG_OK) {
-        if (dirty0) rm.resident[tid] = n0;
-        for (int64_t k = kDiffBlock + tid; k < rm.M; k += kDiffBlock) {
+        if (dirty0) rm.resident[j] = n0;
+        for (int64_t k = kHalf + tid; k < rm.M; k += kDiffBlock) {
             rgg_box n = new_b[k];
             if (!same_box(n, rm.resident[k])) rm.resident[k] = n;
         }
     }
 }
 
+template <int D>
 __global__ void __launch_bounds__(kDiffBlock) k_diff(RmDev rm, const rgg_box *__restrict__ old_b,
                                                      const rgg_box *__restrict__ new_b)
 {
-    diff_body(rm, old_b, new_b);
+    diff_body<D>(rm, old_b, new_b);
 }
 
 // ------------------------------------------------------------------------
@@ -589,6 +595,13 @@ __device__ inline void retest_one(const RmDev &rm, int64_t e, int ci, int *lst, 
         lo[d] = en.lo[d];
         hi[d] = en.hi[d];
     }
+    // the edge's sample range is loaded with its capsules: it is needed as
+    // soon as one capsule meets, and would otherwise add a round trip
+    int64_t s0 = 0, P = 0;
+    if constexpr ((MODE & kModeSplines) == 0) {
+        s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
+        P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
+    }
     bool hit = false;
     if (lane < B) {
         const double *cp = rm.cap64 + e * (2 * D + 1) * B;
@@ -623,8 +636,6 @@ __device__ inline void retest_one(const RmDev &rm, int64_t e, int ci, int *lst, 
     if constexpr ((MODE & kModeSplines) != 0) {
         S = splines_meet64<D>(rm, e, hm, lo, hi, &bytes);
     } else {
-        const int64_t s0 = rm.p_fixed ? e * rm.p_fixed : rm.soff[e];
-        const int64_t P = rm.p_fixed ? rm.p_fixed : rm.soff[e + 1] - s0;
         const CopyMap cm = copy_map((int)(P / B));
         S = copies_meet64<D>(rm, rm.samp64 + copy_stride<D>() * s0, P, cm, hm, lo, hi, rad, lst, &bytes);
     }
@@ -1683,7 +1694,8 @@ __device__ __forceinline__ void retest_pairs(const RmDev &rm, int b, int G)
             int n = 0;
             if (tid < kReg) {
                 int *rc = cnt + b + tid * G;
-                n = ok ? *rc : 0;
+                const int v = *rc;   // loaded whatever the status, so both loads are in flight at once
+                n = ok ? v : 0;
                 *rc = 0;   // cleared for the next update
             }
             int tot;
@@ -1718,16 +1730,99 @@ __device__ __forceinline__ void retest_pairs(const RmDev &rm, int b, int G)
     }
 }
 
-// The binary64 pass of the FP32 mode, regions b, b + G, ... of one roadmap:
-// the queued pairs, then the items left whole because their blocks' re-test
-// regions were full (rare: skipped unless one was deferred in this update).
-// One kernel for both, so the common case costs one launch; it runs one
-// block per CU, so the binary64 item path's registers cost no occupancy.
+// Binary64 re-test of the queued pairs of one roadmap, spread over the whole
+// grid: every block sums the pair counts of all re-test regions (the item
+// blocks' regions r, then the pair shares' as regions kStatBlocks + r) into
+// one prefix in LDS, and wavefront w of W takes pairs w, w + W, ... of the
+// regions' concatenation.  The pairs of a heavy region are thus spread over
+// many wavefronts instead of one block's four.  The counts are not cleared
+// here (another block may still be reading them): every block of the item
+// kernel and of the pair-share kernel writes its own region's count at its
+// end, and the label kernel's statistics block clears them for the batched
+// pass, whose blocks write only the regions of roadmaps they visit.
+template <int D, int MODE>
+__device__ __forceinline__ void retest_spread(const RmDev &rm)
+{
+    constexpr int kReg = 2 * kStatBlocks;   // item regions, then share regions
+    constexpr int kPer = kReg / kBlock;     // consecutive regions per thread
+    __shared__ int s_pre[kReg];
+    __shared__ int s_lst[kWaves][64];
+    __shared__ double s_rad[64];
+    __shared__ int s_w[kWaves];
+    __shared__ unsigned long long s_acc[3];
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    const int32_t *rt_cnt = rm.rt ? rm.rt_cnt : nullptr;
+    if (tid < rm.B) s_rad[tid] = rm.rad64[tid];
+    if (tid < 3) s_acc[tid] = 0;
+    // coalesced loads of the counts, issued with the status load rather
+    // than after it, then each thread sums its own kPer
+    int n[kPer];
+#pragma unroll
+    for (int h = 0; h < kPer; ++h) {
+        const int r = h * kBlock + tid;
+        n[h] = r < kStatBlocks ? rm.rc_cnt[r] : (rt_cnt ? rt_cnt[r - kStatBlocks] : 0);
+    }
+    const bool ok = rm.ctl->status == RGG_OK;
+#pragma unroll
+    for (int h = 0; h < kPer; ++h) s_pre[h * kBlock + tid] = ok ? n[h] : 0;
+    __syncthreads();
+    int v[kPer], sum = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        v[j] = s_pre[tid * kPer + j];
+        sum += v[j];
+    }
+    int total;
+    int pre = block_scan(sum, &total, s_w);   // its barriers order the reads above before the writes below
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        s_pre[tid * kPer + j] = pre;
+        pre += v[j];
+    }
+    __syncthreads();
+    unsigned long long n_re = 0, bytes = 0;
+    uint32_t n_outer = 0;
+    const int W = (int)gridDim.x * kWaves;
+    const int32_t rt_cap = rt_cap_of(rm.pl_cap);
+    for (int q = (int)blockIdx.x * kWaves + wv; q < total; q += W) {
+        // the region holding pair q: the last r with s_pre[r] <= q
+        int lo = 0, hi = kReg - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pre[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        const int k = q - s_pre[lo];
+        const int2 pr = lo < kStatBlocks ? rm.rc[(int64_t)lo * rm.rc_cap + k]
+                                         : rm.rt[(int64_t)(lo - kStatBlocks) * rt_cap + k];
+        retest_one<D, MODE>(rm, pr.x, pr.y, s_lst[wv], s_rad, n_outer, bytes);
+        ++n_re;
+    }
+    if (lane == 0 && n_re) {
+        atomicAdd(&s_acc[0], n_re);
+        atomicAdd(&s_acc[1], (unsigned long long)n_outer);
+        atomicAdd(&s_acc[2], bytes);
+    }
+    __syncthreads();
+    if (tid == 0 && s_acc[0]) {
+        unsigned long long *bs = rm.blk_stats + blockIdx.x;
+        bs[1 * kStatBlocks] += s_acc[1];
+        bs[2 * kStatBlocks] += s_acc[0];
+        bs[kStatFp64Bytes * kStatBlocks] += s_acc[2];
+    }
+}
+
+// The binary64 pass of the FP32 mode of one roadmap: the queued pairs
+// (spread over the grid), then the items left whole because their blocks'
+// re-test regions were full (rare: skipped unless one was deferred in this
+// update; regions b, b + G, ...).  One kernel for both, so the common case
+// costs one launch; it runs one block per CU, so the binary64 item path's
+// registers cost no occupancy.
 template <int D, int MODE>
 __global__ void __launch_bounds__(kBlock) k_fp64(RmDev rm)
 {
     const int any_df = rm.ctl->any_df;
-    retest_pairs<D, MODE>(rm, (int)blockIdx.x, (int)gridDim.x);
+    retest_spread<D, MODE>(rm);
     if (!any_df) return;
     item_body<D, double, MODE>(rm, 1, (int)blockIdx.x, (int)gridDim.x);
 }
@@ -2084,6 +2179,15 @@ __device__ __forceinline__ void labels_body(const RmDev &rm, uint8_t *labels, in
     if (tile >= rm.ntiles) {
         // every block has its ticket: the counter starts from zero next time
         if (tid == 0) __hip_atomic_store(&rm.ctl->label_ticket, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the binary64 pass read the re-test counts without clearing them;
+        // a batched pass needs them zero, as its item blocks write only the
+        // regions of the roadmaps they visit
+        if (rm.mixed) {
+            for (int r = tid; r < kStatBlocks; r += kBlock) {
+                rm.rc_cnt[r] = 0;
+                if (rm.rt) rm.rt_cnt[r] = 0;
+            }
+        }
         if (res) fold_stats(rm, res);
         return;
     }
@@ -2169,7 +2273,8 @@ __global__ void __launch_bounds__(kBlock) k_write(RmDev rm, uint8_t *labels, int
 __global__ void __launch_bounds__(kDiffBlock) k_diff_batch(const BatchReq *tab)
 {
     const BatchReq &q = tab[blockIdx.x];
-    diff_body(q.rm, q.a.old_b, q.a.new_b);
+    if (q.rm.D == 3) diff_body<3>(q.rm, q.a.old_b, q.a.new_b);
+    else diff_body<2>(q.rm, q.a.old_b, q.a.new_b);
 }
 
 // kCellsBatchGrid blocks per request
@@ -2275,9 +2380,10 @@ __global__ void __launch_bounds__(kBlock) k_count_batch(const BatchReq *tab, int
     const int tile = (int)blockIdx.x - q.tile0;
     const int tid = threadIdx.x;
     const int64_t e0 = (int64_t)tile * kLabelTile + (int64_t)tid * kLabelRun;
+    const int status = rm.ctl->status;   // issued before the counters' loads are waited on
     uint8_t lab[kLabelRun];
     const int ng = run_labels(rm, e0, lab);
-    if (q.a.labels && rm.ctl->status == RGG_OK) store_run(rm, q.a.labels, nullptr, 0, e0, lab, 0);
+    if (q.a.labels && status == RGG_OK) store_run(rm, q.a.labels, nullptr, 0, e0, lab, 0);
     const int tot = block_sum(ng, s_w);
     if (tid == 0) rm.tile_cnt[tile] = tot;
 }
@@ -2314,19 +2420,21 @@ __global__ void __launch_bounds__(kBlock) k_write_batch(const BatchReq *tab, int
     __shared__ int s_w[kWaves];
     const RmDev &rm = q.rm;
     const int tid = threadIdx.x;
+    // the labels and the earlier tiles' counts are loaded with the status,
+    // not after it (unused when the update failed)
     const int status = rm.ctl->status;
+    int before = 0;
+    for (int t = tid; t < tile; t += kBlock) before += rm.tile_cnt[t];
+    const int64_t e0 = (int64_t)tile * kLabelTile + (int64_t)tid * kLabelRun;
+    uint8_t lab[kLabelRun];
+    const int ng = load_labels(rm, q.a.labels, e0, lab);
     if (tid == 0 && tile == 0 && q.a.res) {
         q.a.res->status = status;
         q.a.res->n_changed = rm.ctl->n_chg;
         if (status != RGG_OK) q.a.res->n_gray = 0;
     }
     if (status != RGG_OK) return;
-    int before = 0;
-    for (int t = tid; t < tile; t += kBlock) before += rm.tile_cnt[t];
     before = block_sum(before, s_w);
-    const int64_t e0 = (int64_t)tile * kLabelTile + (int64_t)tid * kLabelRun;
-    uint8_t lab[kLabelRun];
-    const int ng = load_labels(rm, q.a.labels, e0, lab);
     int tot;
     const int pre = block_scan(ng, &tot, s_w);
     if (tid == 0 && tile == rm.ntiles - 1 && q.a.res) q.a.res->n_gray = (int64_t)before + tot;
@@ -2383,8 +2491,9 @@ int plan(const RmDev &rm, Node out[7])
 {
     int n = 0;
     const bool single = rm.ncells == 1;
+    void *const diff_fn = rm.D == 3 ? (void *)k_diff<3> : (void *)k_diff<2>;
     if (rm.mixed) {
-        out[n++] = {(void *)k_diff, dim3(1), 0, 1, single ? 2 : 1};
+        out[n++] = {diff_fn, dim3(1), 0, 1, single ? 2 : 1};
         if (!single) out[n++] = {(void *)k_cells, dim3(kCellsGrid), 1, 2, 2};
         // with every round tested inline there is nothing to share out
         const bool share = rm.inline_rounds != kInlineAll;
@@ -2392,7 +2501,7 @@ int plan(const RmDev &rm, Node out[7])
         if (share) out[n++] = {fn(rm, 1), dim3(kGrid), 1, 4, 4};
         out[n++] = {fn(rm, 2), dim3(kFp64Grid), 1, 5, 5};
     } else {
-        out[n++] = {(void *)k_diff, dim3(1), 0, 1, single ? 3 : 1};
+        out[n++] = {diff_fn, dim3(1), 0, 1, single ? 3 : 1};
         if (!single) out[n++] = {(void *)k_cells, dim3(kCellsGrid), 1, 2, 3};
         out[n++] = {fn(rm, 3), dim3(kGrid), 1, 4, 5};
     }
