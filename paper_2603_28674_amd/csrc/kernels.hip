@@ -2090,31 +2090,45 @@ __device__ __forceinline__ int run_labels(const RmDev &rm, int64_t e0, uint8_t (
     return ng;
 }
 
-// Stores a run's labels and its GRAY ids from gray-list position pos on.
-__device__ __forceinline__ void store_run(const RmDev &rm, uint8_t *labels, int64_t *gray, int64_t cap, int64_t e0,
-                                          const uint8_t (&lab)[kLabelRun], int64_t pos)
+// Stores a run's labels (when labels is not null).
+__device__ __forceinline__ void store_run(const RmDev &rm, uint8_t *labels, int64_t e0, const uint8_t (&lab)[kLabelRun])
 {
-    if (labels) {
-        if (e0 + kLabelRun <= rm.E && ((uintptr_t)(labels + e0) & 15u) == 0) {
-            uint32_t wds[kLabelRun / 4];
+    if (!labels) return;
+    if (e0 + kLabelRun <= rm.E && ((uintptr_t)(labels + e0) & 15u) == 0) {
+        uint32_t wds[kLabelRun / 4];
 #pragma unroll
-            for (int q = 0; q < kLabelRun / 4; ++q)
-                wds[q] = (uint32_t)lab[4 * q] | ((uint32_t)lab[4 * q + 1] << 8) | ((uint32_t)lab[4 * q + 2] << 16) |
-                         ((uint32_t)lab[4 * q + 3] << 24);
-            *reinterpret_cast<uint4 *>(labels + e0) = make_uint4(wds[0], wds[1], wds[2], wds[3]);
-        } else {
+        for (int q = 0; q < kLabelRun / 4; ++q)
+            wds[q] = (uint32_t)lab[4 * q] | ((uint32_t)lab[4 * q + 1] << 8) | ((uint32_t)lab[4 * q + 2] << 16) |
+                     ((uint32_t)lab[4 * q + 3] << 24);
+        *reinterpret_cast<uint4 *>(labels + e0) = make_uint4(wds[0], wds[1], wds[2], wds[3]);
+    } else {
 #pragma unroll
-            for (int h = 0; h < kLabelRun; ++h)
-                if (e0 + h < rm.E) labels[e0 + h] = lab[h];
-        }
+        for (int h = 0; h < kLabelRun; ++h)
+            if (e0 + h < rm.E) labels[e0 + h] = lab[h];
     }
+}
+
+// Stores a tile's GRAY ids in ascending order from gray-list position
+// `before` on (when gray is not null; ids past cap are dropped).  Each
+// thread puts its run's ids in LDS at the tile-local positions pre, pre + 1,
+// ..., then consecutive threads write consecutive positions, so the 8-byte
+// stores coalesce instead of each thread's landing a few positions apart.
+// Every thread of the block calls it (one barrier).
+__device__ __forceinline__ void store_gray(const RmDev &rm, int64_t *gray, int64_t cap, int64_t e0,
+                                           const uint8_t (&lab)[kLabelRun], int64_t before, int pre, int tot)
+{
+    __shared__ uint16_t s_gid[kLabelTile];   // tile-local edge index of each GRAY id
+    static_assert(kLabelTile <= 65536, "a tile-local index fits 16 bits");
     if (!gray) return;
+    const int64_t t0 = e0 - (int64_t)threadIdx.x * kLabelRun;   // the tile's first edge
+    int p = pre;
 #pragma unroll
-    for (int h = 0; h < kLabelRun; ++h) {
-        if (e0 + h < rm.E && lab[h] == RGG_GRAY) {
-            if (pos < cap) gray[pos] = e0 + h;
-            ++pos;
-        }
+    for (int h = 0; h < kLabelRun; ++h)
+        if (e0 + h < rm.E && lab[h] == RGG_GRAY) s_gid[p++] = (uint16_t)(threadIdx.x * kLabelRun + h);
+    __syncthreads();
+    for (int i = threadIdx.x; i < tot; i += kBlock) {
+        const int64_t pos = before + i;
+        if (pos < cap) gray[pos] = t0 + s_gid[i];
     }
 }
 
@@ -2149,7 +2163,8 @@ __device__ __forceinline__ void write_body(const RmDev &rm, uint8_t *labels, int
     const int pre = block_scan(ng, &tot, s_w);
     if (tid == 0 && tile == rm.ntiles - 1 && res) res->n_gray = (int64_t)before + tot;
     if (tot == 0 && labels == nullptr) return;
-    store_run(rm, labels, gray, cap, e0, lab, (int64_t)before + pre);
+    store_run(rm, labels, e0, lab);
+    store_gray(rm, gray, cap, e0, lab, before, pre, tot);
 }
 
 // k_labels: k_count and k_write in one pass.  Blocks take their tiles in
@@ -2245,7 +2260,8 @@ __device__ __forceinline__ void labels_body(const RmDev &rm, uint8_t *labels, in
         if (res && s_fail) res->status = RGG_E_DEVICE;
         if (res && tile == rm.ntiles - 1) res->n_gray = before + tot;
     }
-    store_run(rm, labels, gray, cap, e0, lab, before + pre);
+    store_run(rm, labels, e0, lab);
+    store_gray(rm, gray, cap, e0, lab, before, pre, tot);
 }
 
 __global__ void __launch_bounds__(kBlock) k_labels(RmDev rm, uint8_t *labels, int64_t *gray, int64_t cap,
@@ -2270,9 +2286,26 @@ __global__ void __launch_bounds__(kBlock) k_write(RmDev rm, uint8_t *labels, int
 // them; each kernel finds its request in the device table
 // ------------------------------------------------------------------------
 
+// Copies a table row (or its device view) into LDS, all threads, barriers
+// around.  One round of vector loads replaces the chain of scalar loads the
+// compiler would otherwise issue field by field as the kernel needs them
+// (each waiting on the one before, since the view holds the pointers).
+template <typename R>
+__device__ inline void load_row(R *dst, const R &src)
+{
+    static_assert(sizeof(R) % 4 == 0, "a row is copied as 32-bit words");
+    __syncthreads();
+    const uint32_t *a = reinterpret_cast<const uint32_t *>(&src);
+    uint32_t *b = reinterpret_cast<uint32_t *>(dst);
+    for (int k = threadIdx.x; k < (int)(sizeof(R) / 4); k += blockDim.x) b[k] = a[k];
+    __syncthreads();
+}
+__device__ inline void load_rm(RmDev *dst, const RmDev &src) { load_row(dst, src); }
+
 __global__ void __launch_bounds__(kDiffBlock) k_diff_batch(const BatchReq *tab)
 {
-    const BatchReq &q = tab[blockIdx.x];
+    __shared__ BatchReq q;
+    load_row(&q, tab[blockIdx.x]);
     if (q.rm.D == 3) diff_body<3>(q.rm, q.a.old_b, q.a.new_b);
     else diff_body<2>(q.rm, q.a.old_b, q.a.new_b);
 }
@@ -2281,19 +2314,11 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff_batch(const BatchReq *tab)
 __global__ void __launch_bounds__(kBlock) k_cells_batch(const BatchReq *tab)
 {
     const BatchReq &q = tab[blockIdx.x / kCellsBatchGrid];
-    if (q.rm.ncells > 1) cells_body(q.rm, (int)(blockIdx.x % kCellsBatchGrid), kCellsBatchGrid);
+    if (q.rm.ncells <= 1) return;
+    __shared__ RmDev s_rm;
+    load_rm(&s_rm, q.rm);
+    cells_body(s_rm, (int)(blockIdx.x % kCellsBatchGrid), kCellsBatchGrid);
 }
-
-// copies a request's device view into LDS (all threads; barriers around)
-__device__ inline void load_rm(RmDev *dst, const RmDev &src)
-{
-    __syncthreads();
-    const uint32_t *a = reinterpret_cast<const uint32_t *>(&src);
-    uint32_t *b = reinterpret_cast<uint32_t *>(dst);
-    for (int k = threadIdx.x; k < (int)(sizeof(RmDev) / 4); k += blockDim.x) b[k] = a[k];
-    __syncthreads();
-}
-static_assert(sizeof(RmDev) % 4 == 0, "RmDev is copied as 32-bit words");
 
 // The items of all requests of one group form one range: request r owns
 // [P_r, P_r + n_items_r), and block b takes b, b + gridDim.x, ... of it.
@@ -2343,10 +2368,10 @@ __global__ void __launch_bounds__(kBlock) k_fp64_batch(const BatchReq *tab, cons
 {
     __shared__ RmDev s_rm;
     const int r = (int)blockIdx.x / kFp64BatchGrid, b = (int)blockIdx.x % kFp64BatchGrid;
-    const int any_df = tab[grp[r]].rm.ctl->any_df;
-    retest_pairs<D, 0>(tab[grp[r]].rm, b, kFp64BatchGrid);
-    if (!any_df) return;
     load_rm(&s_rm, tab[grp[r]].rm);
+    const int any_df = s_rm.ctl->any_df;
+    retest_pairs<D, 0>(s_rm, b, kFp64BatchGrid);
+    if (!any_df) return;
     item_body<D, double, 0>(s_rm, 1, b, kFp64BatchGrid);
 }
 
@@ -2374,8 +2399,9 @@ __device__ inline int owner_of(const BatchReq *tab, int n, int tile, bool write_
 __global__ void __launch_bounds__(kBlock) k_count_batch(const BatchReq *tab, int n)
 {
     __shared__ int s_w[kWaves];
+    __shared__ BatchReq q;
     const int r = owner_of(tab, n, (int)blockIdx.x, false);
-    const BatchReq &q = tab[r];
+    load_row(&q, tab[r]);
     const RmDev &rm = q.rm;
     const int tile = (int)blockIdx.x - q.tile0;
     const int tid = threadIdx.x;
@@ -2383,7 +2409,7 @@ __global__ void __launch_bounds__(kBlock) k_count_batch(const BatchReq *tab, int
     const int status = rm.ctl->status;   // issued before the counters' loads are waited on
     uint8_t lab[kLabelRun];
     const int ng = run_labels(rm, e0, lab);
-    if (q.a.labels && status == RGG_OK) store_run(rm, q.a.labels, nullptr, 0, e0, lab, 0);
+    if (status == RGG_OK) store_run(rm, q.a.labels, e0, lab);
     const int tot = block_sum(ng, s_w);
     if (tid == 0) rm.tile_cnt[tile] = tot;
 }
@@ -2409,8 +2435,9 @@ __device__ __forceinline__ int load_labels(const RmDev &rm, const uint8_t *label
 
 __global__ void __launch_bounds__(kBlock) k_write_batch(const BatchReq *tab, int n)
 {
+    __shared__ BatchReq q;
     const int r = owner_of(tab, n, (int)blockIdx.x, true);
-    const BatchReq &q = tab[r];
+    load_row(&q, tab[r]);
     const int tile = (int)blockIdx.x - q.wtile0;
     if (!q.a.labels || tile == q.rm.ntiles) {
         write_body(q.rm, q.a.labels, q.a.gray, q.a.gray_cap, q.a.res, 0, tile);
@@ -2439,7 +2466,7 @@ __global__ void __launch_bounds__(kBlock) k_write_batch(const BatchReq *tab, int
     const int pre = block_scan(ng, &tot, s_w);
     if (tid == 0 && tile == rm.ntiles - 1 && q.a.res) q.a.res->n_gray = (int64_t)before + tot;
     if (tot == 0) return;
-    store_run(rm, nullptr, q.a.gray, q.a.gray_cap, e0, lab, (int64_t)before + pre);
+    store_gray(rm, q.a.gray, q.a.gray_cap, e0, lab, before, pre, tot);
 }
 
 }  // namespace
