@@ -71,7 +71,6 @@ rgg_status install_grid(rgg_roadmap *rm, const HostGrid &grid, int32_t chunk)
     RmDev &dv = rm->dv;
     const int64_t ncells = (int64_t)grid.dim[0] * grid.dim[1] * grid.dim[2];
     const size_t ncw = (size_t)((ncells + 31) / 32);
-    const int32_t df_cap = (int32_t)((grid.items_cap + kStatBlocks - 1) / kStatBlocks);
     int32_t *cstart = nullptr, *cedges = nullptr, *df = nullptr;
     uint32_t *bits = nullptr;
     int2 *items = nullptr;
@@ -87,7 +86,8 @@ rgg_status install_grid(rgg_roadmap *rm, const HostGrid &grid, int32_t chunk)
     if ((st = rm->upload(&cstart, grid.start.data(), grid.start.size(), "grid starts")) != RGG_OK) return undo(st);
     if ((st = rm->upload(&cedges, grid.edges.data(), grid.edges.size(), "grid lists")) != RGG_OK) return undo(st);
     if ((st = rm->alloc(&bits, ncw, "cell marks")) != RGG_OK) return undo(st);
-    if ((st = rm->alloc(&df, (size_t)kStatBlocks * df_cap, "deferred items")) != RGG_OK) return undo(st);
+    if ((st = rm->alloc(&df, (size_t)std::max<int64_t>(grid.items_cap, 1), "deferred items")) != RGG_OK)
+        return undo(st);
     if (ncells == 1) {
         // the one cell's work items never change: (0, h) for every chunk h
         std::vector<int2> fixed((size_t)grid.items_cap);
@@ -108,7 +108,6 @@ rgg_status install_grid(rgg_roadmap *rm, const HostGrid &grid, int32_t chunk)
     dv.cell_bits = bits;
     dv.df = df;
     dv.items = items;
-    dv.df_cap = df_cap;
     dv.chunk = chunk;
     for (int d = 0; d < 3; ++d) {
         dv.gdim[d] = grid.dim[d];
@@ -473,7 +472,7 @@ int64_t device_bytes_needed(const HostGeometry &g, const HostGrid &grid, const R
     add(grid.start.size(), 4);
     add(grid.edges.size(), 4);
     add((size_t)((ncells + 31) / 32), 4);
-    add((size_t)kStatBlocks * (size_t)((grid.items_cap + kStatBlocks - 1) / kStatBlocks), 4);
+    add((size_t)std::max<int64_t>(grid.items_cap, 1), 4);
     add((size_t)grid.items_cap, sizeof(int2));
     const int64_t ntiles = std::max<int64_t>(1, (E + kLabelTile - 1) / kLabelTile);
     const int32_t rc_cap = p.retest_capacity > 0 ? p.retest_capacity : kRcCap;
@@ -481,7 +480,6 @@ int64_t device_bytes_needed(const HostGeometry &g, const HostGrid &grid, const R
     add((size_t)M, sizeof(rgg_box));
     add((size_t)(2 * M), sizeof(ChgEntry));
     add((size_t)kStatBlocks * rc_cap, sizeof(int2));
-    add((size_t)kStatBlocks, 4);
     add((size_t)kStatBlocks, 4);
     if (p.mixed) {
         add((size_t)kStatBlocks, 4);
@@ -639,7 +637,6 @@ rgg_status make_roadmap(rgg_context *ctx, const HostGeometry &g, const HostGrid 
     dv.rc_cap = p.retest_capacity > 0 ? p.retest_capacity : kRcCap;
     if ((st = rm->alloc(&dv.rc, (size_t)kStatBlocks * dv.rc_cap, "re-test regions")) != RGG_OK) return guard(st);
     if ((st = rm->alloc(&dv.rc_cnt, (size_t)kStatBlocks, "re-test counts")) != RGG_OK) return guard(st);
-    if ((st = rm->alloc(&dv.df_cnt, (size_t)kStatBlocks, "deferred counts")) != RGG_OK) return guard(st);
     if (mixed) {
         dv.pl_cap = p.pair_list_capacity > 0 ? p.pair_list_capacity : kPairListCap;
         dv.inline_rounds = p.inline_rounds;
@@ -710,7 +707,6 @@ rgg_status make_roadmap(rgg_context *ctx, const HostGeometry &g, const HostGrid 
     if ((st = hip_ok(hipMemset(dv.ctl, 0, sizeof(Ctl)), "clear control")) != RGG_OK) return guard(st);
     if ((st = hip_ok(hipMemset(dv.tile_state, 0, sizeof(unsigned long long) * dv.ntiles), "clear tile states")) != RGG_OK) return guard(st);
     if ((st = hip_ok(hipMemset(dv.rc_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear re-test counts")) != RGG_OK) return guard(st);
-    if ((st = hip_ok(hipMemset(dv.df_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear deferred counts")) != RGG_OK) return guard(st);
     if (mixed) {
         if ((st = hip_ok(hipMemset(dv.pl_cnt, 0, sizeof(int32_t) * kStatBlocks), "clear pair list counts")) != RGG_OK)
             return guard(st);

@@ -51,8 +51,12 @@ constexpr int kCellsGrid = 128;
 constexpr int kCellsBatchGrid = 16;   // blocks per roadmap of the batched cell activation
 constexpr int kGrid = kStatBlocks; // blocks of the item kernels
 constexpr int kFp64Grid = 256;     // blocks of the binary64 pass of the FP32 mode
+constexpr int kBatchItemGrid = 1024;  // blocks of a batched item kernel: the blocks of the
+                                      // FP32 kernel resident at once (4 per CU, 256 CUs)
+constexpr int kBatchStatic = 2;       // items a batched item block takes before it claims
 constexpr int kFp64BatchGrid = 32; // blocks per roadmap of the batched binary64 pass
 static_assert(kStatBlocks % kFp64Grid == 0 && kStatBlocks / kFp64BatchGrid <= 64, "re-test regions per block");
+static_assert(kBatchItemGrid <= kStatBlocks, "a batched item block's row and region exist");
 static_assert(kStatBlocks % 256 == 0, "statistics rows are folded 256 at a time");
 
 enum : int { kMiss = 0, kHit = 1, kUnsure = 2, kOpen = 3 };
@@ -301,7 +305,8 @@ __device__ __forceinline__ void diff_body(const RmDev &rm, const rgg_box *__rest
         s_base = 0;
         s_any = 0;
         rm.ctl->n_items = 0;
-        rm.ctl->any_df = 0;
+        rm.ctl->n_df = 0;
+        rm.ctl->claim = 0;
         rm.ctl->label_ticket = 0;
     }
     for (int t = tid; t < rm.ntiles; t += kDiffBlock) rm.tile_state[t] = 0ull;
@@ -738,7 +743,7 @@ struct ItemLds {
     int nopen;
     uint32_t sf[kPairCap];
     int wsum[kWaves];
-    int rc_n, rc_start, defer, df_n;
+    int rc_n, rc_start, defer;
     int pl_n, pl_start;                   // pairs this block listed (pair listing)
     unsigned long long acc[kStats];
 };
@@ -1259,17 +1264,21 @@ __device__ __forceinline__ void test_round(const RmDev &rm, Lds &L, const T *s_r
     __syncthreads();
 }
 
-// deferred == 0: the main pass, one block per item (grid kGrid): items li0,
-// li0 + lstride, ... (statistics row and re-test region blockIdx.x).
-// deferred == 1: the binary64 pass over the items the FP32 blocks left whole;
-// block b of that grid takes the item lists of FP32 blocks li0, li0 +
-// lstride, ... (statistics row li0).
+// deferred == 0: the main pass: items li0, li0 + lstride, ... (statistics
+// row and re-test region blockIdx.x).
+// deferred == 1: the binary64 pass over the items the FP32 blocks left whole
+// (their list rm.df, ctl->n_df long): entries li0, li0 + lstride, ...
+// (statistics row li0).
 //
 // kList: the pair listing of the FP32 mode.  Each round of pairs goes to this
 // block's region of the pair list (rm.pl, for the pair-share kernel) while
 // the region has room; a round that does not fit is tested here, as the
 // fused kernel does.
-template <int D, typename T, int MODE, bool kList = false>
+// kCont: this block may have visited the roadmap before in this launch (the
+// batched kernel's claimed items): its re-test region continues from the
+// count it wrote then, and its statistics are added to its row, which
+// start from zero (both are cleared after they are read).
+template <int D, typename T, int MODE, bool kList = false, bool kCont = false>
 __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0, int lstride)
 {
     constexpr bool kF32 = std::is_same<T, float>::value;
@@ -1289,20 +1298,11 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
         if (tid < B) L.r.r32[tid] = (float)rm.rad64[tid];
     }
     if (tid == 0) {
-        L.rc_n = 0;
-        L.df_n = 0;
+        L.rc_n = (kCont && kF32 && !deferred) ? rm.rc_cnt[blockIdx.x] : 0;
         L.pl_n = 0;
     }
     const int status = ctl->status;
-    __shared__ int s_dfn[64];
-    const int nreg = deferred ? kStatBlocks / lstride : 0;
-    if (tid < nreg) {
-        // read, then clear for the next update (a batched pass leaves the
-        // regions of roadmaps a block did not visit untouched)
-        int *dc = rm.df_cnt + li0 + tid * lstride;
-        s_dfn[tid] = status == RGG_OK ? *dc : 0;
-        *dc = 0;
-    }
+    const int n_df = (deferred && status == RGG_OK) ? ctl->n_df : 0;
     __syncthreads();
     // wavefront-uniform counts (kept in scalar registers) and per-lane ones
     uint32_t n_pairs = 0, visited = 0, cand = 0, n_outer = 0;
@@ -1314,21 +1314,16 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
     const int jfix = rm.p_fixed ? rm.p_fixed / B : 0;
     constexpr int kSl = slabs_of(D);   // slabs per axis of the slab masks
     // next work item of this block; false when there is none
-    int rk = 0, li = deferred ? 0 : li0;
+    int li = li0;
     auto next_item = [&](int &it) -> bool {
         if (!deferred) {
             if (status != RGG_OK || li >= n_items) return false;
             it = li;
-            li += lstride;
-            return true;
+        } else {
+            if (li >= n_df) return false;
+            it = rm.df[li];
         }
-        while (rk < nreg && li >= s_dfn[rk]) {
-            ++rk;
-            li = 0;
-        }
-        if (rk >= nreg) return false;
-        it = rm.df[(int64_t)(li0 + rk * lstride) * rm.df_cap + li];
-        ++li;
+        li += lstride;
         return true;
     };
     int it;
@@ -1619,8 +1614,9 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
             L.acc[0] += (unsigned long long)(L.pl_n - L.pl_start);
             L.rc_n = L.rc_start;
             L.pl_n = L.pl_start;
-            rm.df[(int64_t)blockIdx.x * rm.df_cap + L.df_n] = it;
-            L.df_n += 1;
+            // each item is left whole at most once per update, so the
+            // list (items_cap long) has room
+            rm.df[atomicAdd(&rm.ctl->n_df, 1)] = it;
         }
     }
     __syncthreads();
@@ -1640,11 +1636,12 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
     // statistic k at bs[k * kStatBlocks]
     unsigned long long *bs = rm.blk_stats + (deferred ? li0 : (int)blockIdx.x);
     if (!deferred) {
-        if (tid < kStats) bs[tid * kStatBlocks] = L.acc[tid];
+        if (tid < kStats) {
+            if (kCont) bs[tid * kStatBlocks] += L.acc[tid];
+            else bs[tid * kStatBlocks] = L.acc[tid];
+        }
         if (kF32 && tid == 0) {
             rm.rc_cnt[blockIdx.x] = L.rc_n;
-            rm.df_cnt[blockIdx.x] = L.df_n;
-            if (L.df_n) rm.ctl->any_df = 1;
             if (kList) rm.pl_cnt[blockIdx.x] = L.pl_n;
         }
     } else if (tid == 0 && (L.acc[1] | L.acc[2] | L.acc[kStatFp64Bytes])) {
@@ -1821,9 +1818,9 @@ __device__ __forceinline__ void retest_spread(const RmDev &rm)
 template <int D, int MODE>
 __global__ void __launch_bounds__(kBlock) k_fp64(RmDev rm)
 {
-    const int any_df = rm.ctl->any_df;
+    const int n_df = rm.ctl->n_df;
     retest_spread<D, MODE>(rm);
-    if (!any_df) return;
+    if (!n_df) return;
     item_body<D, double, MODE>(rm, 1, (int)blockIdx.x, (int)gridDim.x);
 }
 
@@ -2029,35 +2026,48 @@ __device__ __forceinline__ void count_body(const RmDev &rm, int tile)
     if (tid == 0) rm.tile_cnt[tile] = tot;
 }
 
-// Folds (and clears) the per-block statistics of the update into *res.
+// Folds the per-block statistics of the update into *res (when res is not
+// null) and clears them: the item kernels' blocks that may visit a roadmap
+// twice add to their rows.
+// kPass rows of every statistic are loaded at once: all of them (one round
+// of loads, 2 * kStats * kRows registers) where the kernel's other blocks
+// need few registers anyway, fewer where the fold's registers would cap how
+// many blocks of a large grid are resident.
+template <int kPass>
 __device__ __forceinline__ void fold_stats(const RmDev &rm, rgg_update_result *res)
 {
     __shared__ unsigned long long s_part[kWaves][kStats];
     const int tid = threadIdx.x;
-    // all of this thread's loads are issued before the first add
     constexpr int kRows = kStatBlocks / kBlock;
-    unsigned long long v[kRows][kStats];
+    static_assert(kRows % kPass == 0, "whole passes");
+    unsigned long long a[kStats];
 #pragma unroll
-    for (int h = 0; h < kRows; ++h)
+    for (int k = 0; k < kStats; ++k) a[k] = 0;
+#pragma unroll 1
+    for (int h0 = 0; h0 < kRows; h0 += kPass) {
+        unsigned long long v[kPass][kStats];
 #pragma unroll
-        for (int k = 0; k < kStats; ++k) v[h][k] = rm.blk_stats[k * kStatBlocks + h * kBlock + tid];
-    // cleared for the next update: a batched pass writes only the rows of
-    // the blocks that visited this roadmap
+        for (int h = 0; h < kPass; ++h)
 #pragma unroll
-    for (int h = 0; h < kRows; ++h)
+            for (int k = 0; k < kStats; ++k) v[h][k] = rm.blk_stats[k * kStatBlocks + (h0 + h) * kBlock + tid];
+        // cleared for the next update: a batched pass writes only the rows
+        // of the blocks that visited this roadmap
 #pragma unroll
-        for (int k = 0; k < kStats; ++k) rm.blk_stats[k * kStatBlocks + h * kBlock + tid] = 0ull;
+        for (int h = 0; h < kPass; ++h)
+#pragma unroll
+            for (int k = 0; k < kStats; ++k) {
+                rm.blk_stats[k * kStatBlocks + (h0 + h) * kBlock + tid] = 0ull;
+                a[k] += v[h][k];
+            }
+    }
     const int lane = lane_id(), wv = tid >> 6;
 #pragma unroll
     for (int k = 0; k < kStats; ++k) {
-        unsigned long long a = 0;
-#pragma unroll
-        for (int h = 0; h < kRows; ++h) a += v[h][k];
-        a = wave_sum_u64(a);
-        if (lane == 0) s_part[wv][k] = a;
+        const unsigned long long w = wave_sum_u64(a[k]);
+        if (lane == 0) s_part[wv][k] = w;
     }
     __syncthreads();
-    if (tid == 0) {
+    if (tid == 0 && res) {
         int64_t a[kStats];
         for (int k = 0; k < kStats; ++k) {
             unsigned long long t = 0;
@@ -2142,7 +2152,7 @@ __device__ __forceinline__ void write_body(const RmDev &rm, uint8_t *labels, int
     __shared__ int s_w[kWaves];
     const int tid = threadIdx.x;
     if (tile == rm.ntiles) {
-        if (!force && res) fold_stats(rm, res);
+        if (!force) fold_stats<1>(rm, res);
         return;
     }
     const int status = force ? RGG_OK : rm.ctl->status;
@@ -2203,7 +2213,7 @@ __device__ __forceinline__ void labels_body(const RmDev &rm, uint8_t *labels, in
                 if (rm.rt) rm.rt_cnt[r] = 0;
             }
         }
-        if (res) fold_stats(rm, res);
+        fold_stats<kStatBlocks / kBlock>(rm, res);
         return;
     }
     const int status = rm.ctl->status;
@@ -2321,13 +2331,20 @@ __global__ void __launch_bounds__(kBlock) k_cells_batch(const BatchReq *tab)
 }
 
 // The items of all requests of one group form one range: request r owns
-// [P_r, P_r + n_items_r), and block b takes b, b + gridDim.x, ... of it.
+// [P_r, P_r + n_items_r).  Block b of G takes items b, b + G, ..., up to
+// kBatchStatic of them, then claims the rest one at a time from a counter
+// (items kBatchStatic * G on), so blocks whose items were light take more
+// and the launch ends near the mean block time rather than the heaviest
+// block's.  A block may then visit a roadmap more than once: its re-test
+// region and statistics row continue across the visits (kCont).  The next
+// claim is issued before the current item runs, so its latency is hidden.
 template <int D, typename T>
 __device__ __forceinline__ void item_batch_body(const BatchReq *tab, const int32_t *grp, int n)
 {
     __shared__ RmDev s_rm;
     __shared__ int s_pref[kMaxBatch + 1];
     __shared__ int s_w[kWaves];
+    __shared__ int s_next;
     const int tid = threadIdx.x;
     int v = 0;
     if (tid < n) {
@@ -2339,13 +2356,29 @@ __device__ __forceinline__ void item_batch_body(const BatchReq *tab, const int32
     if (tid < n) s_pref[tid] = pre;
     if (tid == 0) s_pref[n] = tot;
     __syncthreads();
-    const int G = (int)gridDim.x, b = (int)blockIdx.x;
-    for (int r = 0; r < n; ++r) {
-        const int P = s_pref[r], N = s_pref[r + 1] - P;
-        const int first = P + ((b - P) % G + G) % G;   // first index >= P that is b mod G
-        if (first >= P + N) continue;
-        load_rm(&s_rm, tab[grp[r]].rm);
-        item_body<D, T, 0>(s_rm, 0, first - P, G);
+    const int G = (int)gridDim.x;
+    int32_t *const claim = &tab[grp[0]].rm.ctl->claim;   // reset by the diff of this update
+    int cur = -1;                                        // the request whose view s_rm holds
+    int g = (int)blockIdx.x;
+    for (int k = 0; g < tot; ++k) {
+        // the request owning item g: the last r with s_pref[r] <= g (uniform)
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_pref[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        const bool claims = k + 1 >= kBatchStatic;
+        int nxt = 0;
+        if (claims && tid == 0) nxt = kBatchStatic * G + atomicAdd(claim, 1);
+        if (lo != cur) {
+            load_rm(&s_rm, tab[grp[lo]].rm);
+            cur = lo;
+        }
+        item_body<D, T, 0, false, true>(s_rm, 0, g - s_pref[lo], 1 << 30);
+        if (claims && tid == 0) s_next = nxt;
+        __syncthreads();
+        g = claims ? s_next : g + G;
     }
 }
 
@@ -2369,9 +2402,9 @@ __global__ void __launch_bounds__(kBlock) k_fp64_batch(const BatchReq *tab, cons
     __shared__ RmDev s_rm;
     const int r = (int)blockIdx.x / kFp64BatchGrid, b = (int)blockIdx.x % kFp64BatchGrid;
     load_rm(&s_rm, tab[grp[r]].rm);
-    const int any_df = s_rm.ctl->any_df;
+    const int n_df = s_rm.ctl->n_df;
     retest_pairs<D, 0>(s_rm, b, kFp64BatchGrid);
-    if (!any_df) return;
+    if (!n_df) return;
     item_body<D, double, 0>(s_rm, 1, b, kFp64BatchGrid);
 }
 
@@ -2687,7 +2720,7 @@ hipError_t batch_kernels(Emit emit, After after, const BatchReq *tab, const Batc
         void *a_item[] = {(void *)&t, (void *)&gp, (void *)&cnt};
         void *fn = gr.D == 3 ? (gr.mixed ? (void *)k_item32_batch<3> : (void *)k_item64_batch<3>)
                              : (gr.mixed ? (void *)k_item32_batch<2> : (void *)k_item64_batch<2>);
-        if ((err = emit(fn, dim3(kGrid), dim3(kBlock), a_item)) != hipSuccess) return err;
+        if ((err = emit(fn, dim3(kBatchItemGrid), dim3(kBlock), a_item)) != hipSuccess) return err;
         if ((err = after(3)) != hipSuccess) return err;
         if (gr.mixed) {
             void *a_fp[] = {(void *)&t, (void *)&gp};

@@ -16,9 +16,10 @@ struct Ctl {
     int32_t status;        // RGG_OK / RGG_E_INVALID_ARG / RGG_E_STATE_MISMATCH
     int32_t n_chg;         // changed (box, sign) entries
     int32_t n_items;       // (cell, chunk) work items of the grid scan
-    int32_t any_df;        // some item was left whole to the binary64 pass
+    int32_t n_df;          // items left whole to the binary64 pass (their list's length)
     int32_t label_ticket;  // next tile of the one-pass label kernel (dispatch order)
-    int32_t pad;
+    int32_t claim;         // items claimed past the static ones by a batched item
+                           // launch (the counter of its group's first request)
 };
 
 // One changed obstacle entry: the box a slot held before (sign -1) or holds
@@ -86,10 +87,8 @@ struct RmDev {
                                // the FP32 item kernel leaves to the binary64 re-test
     int32_t *rc_cnt;           // [kStatBlocks]
     int32_t rc_cap;
-    int32_t df_cap;
-    int32_t *df;               // [kStatBlocks][df_cap] items a block left whole to the
-                               // binary64 pass (its re-test region was full)
-    int32_t *df_cnt;           // [kStatBlocks]
+    int32_t *df;               // [items_cap] items left whole to the binary64 pass (an
+                               // item block's re-test region was full), ctl->n_df of them
     // the FP32 mode's pair listing and pair testing
     int32_t pl_cap;            // pairs each listing block may leave for the pair testing
     int32_t inline_rounds;     // pair rounds of an item its listing block tests before it

@@ -36,7 +36,7 @@ def mixed_workloads(n_updates):
     return specs
 
 
-def run_batched(ctx, specs, n_updates, one_shot=False, item_edges=0):
+def run_batched(ctx, specs, n_updates, one_shot=False, item_edges=0, **build):
     import torch
     from paper_2603_28674_amd import rgg
     import oracle
@@ -45,7 +45,7 @@ def run_batched(ctx, specs, n_updates, one_shot=False, item_edges=0):
     gs, ors, bufs = [], [], []
     for w, prec, cell in specs:
         print(f"[batch] {w.name} E={w.n_edges} M={w.n_slots} prec={prec} cell={cell}", flush=True)
-        gs.append(rgg.Roadmap.from_workload(ctx, w, precision=prec, cell_size=cell, item_edges=item_edges))
+        gs.append(rgg.Roadmap.from_workload(ctx, w, precision=prec, cell_size=cell, item_edges=item_edges, **build))
         ors.append(oracle.from_workload(w))
         states = torch.from_numpy(np.stack([w.absent()] + w.boxes)).to(dev)
         lab = torch.zeros(w.n_edges, dtype=torch.uint8, device=dev)
@@ -115,6 +115,24 @@ def test_batch_planar_tuned_decomposition(ctx, item_edges):
         specs.append((synth.planar_rigid(seed=700 + k, n_nodes=n, n_boxes=int(rng.integers(20, 120)), n_updates=3,
                                          k=8), rgg.RGG_PREC_FP32_RECHECK, 0.0 if k % 3 else -1.0))
     run_batched(ctx, specs, 3, item_edges=item_edges)
+
+
+@pytest.mark.parametrize("band_rel,retest_capacity", [(0.0, 0), (0.0, 4), (float("inf"), 2)])
+def test_batch_claimed_items(ctx, band_rel, retest_capacity):
+    """More work items than the batched item kernel's blocks take statically
+    (two for each of its 1,024 blocks): seven one-cell planar roadmaps of
+    about 28,000 edges in 64-edge items, about 3,050 items, every one of them
+    work in every update.  Blocks claim the rest one at a time and come back
+    to roadmaps they visited, so re-test regions continue across visits.  A
+    re-test capacity of 4 pairs fills some regions; an infinite band with 2
+    pairs leaves nearly every item whole to the binary64 pass (its list of
+    deferred items); an FP64 roadmap rides along in its own group."""
+    from paper_2603_28674_amd import rgg
+    specs = [(synth.planar_rigid(seed=800 + k, n_nodes=6000, n_boxes=60, n_updates=3, k=8),
+              rgg.RGG_PREC_FP32_RECHECK, -1.0) for k in range(7)]
+    specs.append((synth.planar_rigid(seed=810, n_nodes=1500, n_boxes=40, n_updates=3, k=8), rgg.RGG_PREC_FP64, -1.0))
+    assert sum((w.n_edges + 63) // 64 for w, p, _ in specs if p == rgg.RGG_PREC_FP32_RECHECK) > 2 * 1024
+    run_batched(ctx, specs, 3, item_edges=64, band_rel=band_rel, retest_capacity=retest_capacity)
 
 
 def test_batch_errors(ctx):
