@@ -2547,6 +2547,14 @@ struct Node {
 // ev[6] after the labels.  The FP64 mode's one item kernel stands for the
 // testing (ev[3] before it).  With a single grid cell there is nothing to
 // activate: k_diff emits the items.
+// blocks of the item kernel for a one-cell roadmap: one per item, at most
+// kGrid (the rows of statistics and re-test regions past the grid stay zero:
+// their readers clear them after every update)
+unsigned fixed_items_grid(const RmDev &rm)
+{
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kGrid, rm.items_cap));
+}
+
 int plan(const RmDev &rm, Node out[7])
 {
     int n = 0;
@@ -2557,13 +2565,17 @@ int plan(const RmDev &rm, Node out[7])
         if (!single) out[n++] = {(void *)k_cells, dim3(kCellsGrid), 1, 2, 2};
         // with every round tested inline there is nothing to share out
         const bool share = rm.inline_rounds != kInlineAll;
-        out[n++] = {fn(rm, 0), dim3(kGrid), 1, 3, share ? 3 : 4};
+        // one grid cell: its items are fixed, and blocks past them would only
+        // start and stop (with pair listing every block writes its list's
+        // count, so the whole grid runs)
+        const unsigned grid = single && !share ? fixed_items_grid(rm) : kGrid;
+        out[n++] = {fn(rm, 0), dim3(grid), 1, 3, share ? 3 : 4};
         if (share) out[n++] = {fn(rm, 1), dim3(kGrid), 1, 4, 4};
         out[n++] = {fn(rm, 2), dim3(kFp64Grid), 1, 5, 5};
     } else {
         out[n++] = {diff_fn, dim3(1), 0, 1, single ? 3 : 1};
         if (!single) out[n++] = {(void *)k_cells, dim3(kCellsGrid), 1, 2, 3};
-        out[n++] = {fn(rm, 3), dim3(kGrid), 1, 4, 5};
+        out[n++] = {fn(rm, 3), dim3(single ? fixed_items_grid(rm) : kGrid), 1, 4, 5};
     }
     out[n++] = {(void *)k_labels, dim3(rm.ntiles + 1), 4, 6, 6};
     return n;
