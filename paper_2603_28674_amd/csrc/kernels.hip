@@ -57,6 +57,7 @@ constexpr int kBatchStatic = 2;       // items a batched item block takes before
 constexpr int kFp64BatchGrid = 32; // blocks per roadmap of the batched binary64 pass
 static_assert(kStatBlocks % kFp64Grid == 0 && kStatBlocks / kFp64BatchGrid <= 64, "re-test regions per block");
 static_assert(kBatchItemGrid <= kStatBlocks, "a batched item block's row and region exist");
+static_assert(kFp64Grid <= kStatRows && kFp64BatchGrid <= kStatRows, "a binary64 block owns a statistics row");
 static_assert(kStatBlocks % 256 == 0, "statistics rows are folded 256 at a time");
 
 enum : int { kMiss = 0, kHit = 1, kUnsure = 2, kOpen = 3 };
@@ -1633,13 +1634,12 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
         if (cand) atomicAdd(&L.acc[5], (unsigned long long)cand);
     }
     __syncthreads();
-    // statistic k at bs[k * kStatBlocks]
-    unsigned long long *bs = rm.blk_stats + (deferred ? li0 : (int)blockIdx.x);
+    // statistic k at bs[k * kStatBlocks]: item blocks add to row blockIdx &
+    // (kStatRows - 1), shared with other blocks (atomics); the binary64 pass's
+    // block li0 owns row li0
+    unsigned long long *bs = rm.blk_stats + (deferred ? li0 : (int)(blockIdx.x & (kStatRows - 1)));
     if (!deferred) {
-        if (tid < kStats) {
-            if (kCont) bs[tid * kStatBlocks] += L.acc[tid];
-            else bs[tid * kStatBlocks] = L.acc[tid];
-        }
+        if (tid < kStats && L.acc[tid]) atomicAdd(&bs[tid * kStatBlocks], L.acc[tid]);
         if (kF32 && tid == 0) {
             rm.rc_cnt[blockIdx.x] = L.rc_n;
             if (kList) rm.pl_cnt[blockIdx.x] = L.pl_n;
@@ -1953,13 +1953,13 @@ __device__ __forceinline__ void share_body(const RmDev &rm)
         if (w_bytes) atomicAdd(&L.acc[kStatPairBytes], w_bytes);
     }
     __syncthreads();
-    // the listing wrote this block's rows; the shares add to them
-    unsigned long long *bs = rm.blk_stats + blockIdx.x;
+    // the statistics rows are shared by blocks (atomics)
+    unsigned long long *bs = rm.blk_stats + (blockIdx.x & (kStatRows - 1));
     if (tid == 0) {
-        if (L.acc[0]) bs[0] += L.acc[0];
-        if (L.acc[1]) bs[1 * kStatBlocks] += L.acc[1];
-        if (L.acc[2]) bs[2 * kStatBlocks] += L.acc[2];
-        if (L.acc[kStatPairBytes]) bs[kStatPairBytes * kStatBlocks] += L.acc[kStatPairBytes];
+        if (L.acc[0]) atomicAdd(&bs[0], L.acc[0]);
+        if (L.acc[1]) atomicAdd(&bs[1 * kStatBlocks], L.acc[1]);
+        if (L.acc[2]) atomicAdd(&bs[2 * kStatBlocks], L.acc[2]);
+        if (L.acc[kStatPairBytes]) atomicAdd(&bs[kStatPairBytes * kStatBlocks], L.acc[kStatPairBytes]);
         rm.rt_cnt[blockIdx.x] = L.rc_n;
     }
 }
@@ -2026,44 +2026,22 @@ __device__ __forceinline__ void count_body(const RmDev &rm, int tile)
     if (tid == 0) rm.tile_cnt[tile] = tot;
 }
 
-// Folds the per-block statistics of the update into *res (when res is not
-// null) and clears them: the item kernels' blocks that may visit a roadmap
-// twice add to their rows.
-// kPass rows of every statistic are loaded at once: all of them (one round
-// of loads, 2 * kStats * kRows registers) where the kernel's other blocks
-// need few registers anyway, fewer where the fold's registers would cap how
-// many blocks of a large grid are resident.
-template <int kPass>
+// Folds the statistics rows of the update into *res (when res is not null)
+// and clears them for the next update (the item kernels add to them).
 __device__ __forceinline__ void fold_stats(const RmDev &rm, rgg_update_result *res)
 {
     __shared__ unsigned long long s_part[kWaves][kStats];
     const int tid = threadIdx.x;
-    constexpr int kRows = kStatBlocks / kBlock;
-    static_assert(kRows % kPass == 0, "whole passes");
-    unsigned long long a[kStats];
+    static_assert(kStatRows == kBlock, "one statistics row a thread");
+    unsigned long long v[kStats];
 #pragma unroll
-    for (int k = 0; k < kStats; ++k) a[k] = 0;
-#pragma unroll 1
-    for (int h0 = 0; h0 < kRows; h0 += kPass) {
-        unsigned long long v[kPass][kStats];
+    for (int k = 0; k < kStats; ++k) v[k] = rm.blk_stats[k * kStatBlocks + tid];
 #pragma unroll
-        for (int h = 0; h < kPass; ++h)
-#pragma unroll
-            for (int k = 0; k < kStats; ++k) v[h][k] = rm.blk_stats[k * kStatBlocks + (h0 + h) * kBlock + tid];
-        // cleared for the next update: a batched pass writes only the rows
-        // of the blocks that visited this roadmap
-#pragma unroll
-        for (int h = 0; h < kPass; ++h)
-#pragma unroll
-            for (int k = 0; k < kStats; ++k) {
-                rm.blk_stats[k * kStatBlocks + (h0 + h) * kBlock + tid] = 0ull;
-                a[k] += v[h][k];
-            }
-    }
+    for (int k = 0; k < kStats; ++k) rm.blk_stats[k * kStatBlocks + tid] = 0ull;
     const int lane = lane_id(), wv = tid >> 6;
 #pragma unroll
     for (int k = 0; k < kStats; ++k) {
-        const unsigned long long w = wave_sum_u64(a[k]);
+        const unsigned long long w = wave_sum_u64(v[k]);
         if (lane == 0) s_part[wv][k] = w;
     }
     __syncthreads();
@@ -2152,7 +2130,7 @@ __device__ __forceinline__ void write_body(const RmDev &rm, uint8_t *labels, int
     __shared__ int s_w[kWaves];
     const int tid = threadIdx.x;
     if (tile == rm.ntiles) {
-        if (!force) fold_stats<1>(rm, res);
+        if (!force) fold_stats(rm, res);
         return;
     }
     const int status = force ? RGG_OK : rm.ctl->status;
@@ -2213,7 +2191,7 @@ __device__ __forceinline__ void labels_body(const RmDev &rm, uint8_t *labels, in
                 if (rm.rt) rm.rt_cnt[r] = 0;
             }
         }
-        fold_stats<kStatBlocks / kBlock>(rm, res);
+        fold_stats(rm, res);
         return;
     }
     const int status = rm.ctl->status;

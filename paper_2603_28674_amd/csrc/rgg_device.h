@@ -115,6 +115,8 @@ __host__ __device__ constexpr int obb_words(int D) { return 2 * D + D * D; }
 constexpr int kStats = 8;
 constexpr int kStatPairBytes = 3, kStatItemBytes = 6, kStatFp64Bytes = 7;
 constexpr int kStatBlocks = 2048;  // blocks of the item kernels
+constexpr int kStatRows = 256;     // rows of blk_stats in use: item and pair-share blocks add
+                                   // to row blockIdx & 255 (atomics), binary64 blocks to their own
 constexpr int kMaxSlots = 4096;    // 2*slots changed entries at most
 
 constexpr int kLocalCells = 512;   // uint4 words of the item kernel's slab masks (at most)
