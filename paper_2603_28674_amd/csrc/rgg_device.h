@@ -23,7 +23,8 @@ struct Ctl {
 };
 
 // One changed obstacle entry: the box a slot held before (sign -1) or holds
-// now (sign +1).  Entries are ordered by slot, old before new.
+// now (sign +1).  In each chunk of 512 slots, the old boxes' entries come
+// first (in slot order), then the new boxes'.
 struct alignas(16) ChgEntry {
     // the first 32 bytes are what the binary32 kernels stage: two 16-byte loads
     float lo32[3], hi32[3];    // outward-rounded binary32 copy
