@@ -144,12 +144,13 @@ typedef struct {
     double cell_size;             /* grid cell edge; 0 = heuristic; < 0 = one
                                      cell covering everything                   */
     int32_t host_threads;         /* threads for the host build; 0 = automatic  */
-    int32_t retest_capacity;      /* FP32 mode: undecided pairs each of the 2048
-                                     item blocks may queue for the binary64
-                                     re-test before it leaves a whole work item
-                                     to the binary64 pass instead; 0 = 1024,
-                                     at most 2^20.  Any value gives the same
-                                     labels.                                    */
+    int32_t retest_capacity;      /* FP32 mode: undecided pairs each item block
+                                     (at most 2048 of them) may queue for the
+                                     binary64 re-test, over all the items it
+                                     takes of this roadmap in one update,
+                                     before it leaves a whole work item to the
+                                     binary64 pass instead; 0 = 1024, at most
+                                     2^20.  Any value gives the same labels.   */
     int32_t item_edges;           /* edges per work item of the classify
                                      kernels (one block of 256 threads each,
                                      up to two edges per thread), 1..512;
