@@ -29,10 +29,12 @@
 //
 // Binary64 code is compiled without FMA contraction and its sums run left to
 // right from 0.0, so a re-test reproduces the definition's values exactly.
-// Hot loops use no single global counter: on MI355X device-scope atomics on
-// one address serialise across the eight XCDs, so work lists are positional
-// and statistics are per-block partial sums (k_labels takes one ticket per
-// 4096-edge tile, a few dozen per update).
+// Hot loops keep off single global counters: on MI355X device-scope atomics
+// on one address serialise across the eight XCDs, so work lists are
+// positional and statistics go to 256 rows shared through atomics.  The few
+// single-address counters are k_labels' tickets (one per 4096-edge tile),
+// the batched item kernel's claims (one per item past two per block) and
+// the rare appends to a roadmap's list of items left whole.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -1812,7 +1814,7 @@ __device__ __forceinline__ void retest_spread(const RmDev &rm)
 // The binary64 pass of the FP32 mode of one roadmap: the queued pairs
 // (spread over the grid), then the items left whole because their blocks'
 // re-test regions were full (rare: skipped unless one was deferred in this
-// update; regions b, b + G, ...).  One kernel for both, so the common case
+// update; entries b, b + G, ... of the roadmap's list).  One kernel for both, so the common case
 // costs one launch; it runs one block per CU, so the binary64 item path's
 // registers cost no occupancy.
 template <int D, int MODE>
@@ -2290,10 +2292,20 @@ __device__ inline void load_row(R *dst, const R &src)
 }
 __device__ inline void load_rm(RmDev *dst, const RmDev &src) { load_row(dst, src); }
 
-__global__ void __launch_bounds__(kDiffBlock) k_diff_batch(const BatchReq *tab)
+// One block per roadmap.  With h_tab (this launch's pinned host rows) the
+// block reads its row from host memory and writes it to the device table,
+// where the later stages read it.
+__global__ void __launch_bounds__(kDiffBlock) k_diff_batch(BatchReq *tab, const BatchReq *h_tab)
 {
     __shared__ BatchReq q;
-    load_row(&q, tab[blockIdx.x]);
+    if (h_tab) {
+        load_row(&q, h_tab[blockIdx.x]);
+        const uint32_t *a = reinterpret_cast<const uint32_t *>(&q);
+        uint32_t *b = reinterpret_cast<uint32_t *>(&tab[blockIdx.x]);
+        for (int k = threadIdx.x; k < (int)(sizeof(BatchReq) / 4); k += blockDim.x) b[k] = a[k];
+    } else {
+        load_row(&q, tab[blockIdx.x]);
+    }
     if (q.rm.D == 3) diff_body<3>(q.rm, q.a.old_b, q.a.new_b);
     else diff_body<2>(q.rm, q.a.old_b, q.a.new_b);
 }
@@ -2668,16 +2680,11 @@ namespace {
 // device reads the host rows itself, so a batched launch needs no copy
 // engine (whose hand-over to the kernels' queue costs more than the copy).
 // One word per thread: every read of host memory is in flight at once.
-__global__ void __launch_bounds__(kBlock) k_table(uint32_t *dst, const uint32_t *src, int n_words)
-{
-    const int k = (int)blockIdx.x * kBlock + (int)threadIdx.x;
-    if (k < n_words) dst[k] = src[k];
-}
 static_assert(sizeof(BatchReq) % 4 == 0, "request rows are copied as 32-bit words");
 
 // The kernels of a batched update in order, each handed to `emit(fn, grid,
 // block, args)` (a graph-node adder or a stream launcher).  With `h_tab`
-// (pinned host rows) the first kernel copies them to `tab`.
+// (pinned host rows) the diff kernel copies them to `tab`.
 // `after(stage)` follows each kernel: 0 diff, 1 cells, 3 item, 4 binary64
 // pass, 5 labels (count and write).
 template <typename Emit, typename After>
@@ -2687,15 +2694,11 @@ hipError_t batch_kernels(Emit emit, After after, const BatchReq *tab, const Batc
     const BatchReq *t = tab;
     int nn = n;
     hipError_t err;
-    uint32_t *t_dst = reinterpret_cast<uint32_t *>(const_cast<BatchReq *>(tab));
-    const uint32_t *t_src = reinterpret_cast<const uint32_t *>(h_tab);
-    int n_words = (int)(sizeof(BatchReq) / 4) * n;
-    void *a_tab[] = {(void *)&t_dst, (void *)&t_src, (void *)&n_words};
-    if (h_tab && (err = emit((void *)k_table, dim3((n_words + kBlock - 1) / kBlock), dim3(kBlock), a_tab)) !=
-                     hipSuccess)
-        return err;
+    BatchReq *t_dst = const_cast<BatchReq *>(tab);
+    const BatchReq *t_src = h_tab;
+    void *a_first[] = {(void *)&t_dst, (void *)&t_src};
+    if ((err = emit((void *)k_diff_batch, dim3(n), dim3(kDiffBlock), a_first)) != hipSuccess) return err;
     void *a_diff[] = {(void *)&t};
-    if ((err = emit((void *)k_diff_batch, dim3(n), dim3(kDiffBlock), a_diff)) != hipSuccess) return err;
     if ((err = after(0)) != hipSuccess) return err;
     void *a_tn[] = {(void *)&t, (void *)&nn};
     if (any_grid) {

@@ -102,7 +102,8 @@ struct RmDev {
     int32_t *tile_cnt;         // [ntiles] gray edges per label tile
     unsigned long long *tile_state;   // [ntiles] look-back words of the one-pass label
                                       // kernel: flag (bits 62-63) | gray count
-    unsigned long long *blk_stats;   // [kStats][kStatBlocks] per-block partial counts
+    unsigned long long *blk_stats;   // [kStats][kStatBlocks] statistics rows (the first
+                                     // kStatRows in use), cleared by each update's fold
     Ctl *ctl;
 };
 
