@@ -317,7 +317,8 @@ rgg_status rgg_graph_destroy(rgg_graph *g);
  * reqs[n] gives, in the same order, each
  * roadmap's update arguments (reqs[k].rm must equal rms[k]); their device
  * pointers may differ from launch to launch, since the request table is
- * copied (from pinned host memory) in stream order before the graph runs.
+ * read from pinned host memory by the launch's first kernel, in stream
+ * order.
  * Errors: RGG_E_INVALID_ARG (null pointer, n out of range, a repeated
  * roadmap, another device, a request that does not match its roadmap),
  * RGG_E_DEVICE.  Device-side errors (bad box, state mismatch) are reported
