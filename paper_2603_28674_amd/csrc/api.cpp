@@ -74,12 +74,14 @@ rgg_status install_grid(rgg_roadmap *rm, const HostGrid &grid, int32_t chunk)
     int32_t *cstart = nullptr, *cedges = nullptr, *df = nullptr;
     uint32_t *bits = nullptr;
     int2 *items = nullptr;
+    int4 *cslot = nullptr;
     auto undo = [&](rgg_status s) {
         rm->release(cstart);
         rm->release(cedges);
         rm->release(bits);
         rm->release(df);
         rm->release(items);
+        rm->release(cslot);
         return s;
     };
     rgg_status st;
@@ -98,13 +100,24 @@ rgg_status install_grid(rgg_roadmap *rm, const HostGrid &grid, int32_t chunk)
     }
     hipError_t e = hipMemset(bits, 0, 4 * std::max<size_t>(ncw, 1));
     if (e != hipSuccess) return undo(hip_fail(e, "clear marks"));
+    if (ncells > 1 && !grid.edges.empty()) {
+        // the cell lists' slots with each edge's box size and sample range
+        const int64_t n = (int64_t)grid.edges.size();
+        if ((st = rm->alloc(&cslot, (size_t)n, "grid slots")) != RGG_OK) return undo(st);
+        RmDev view = dv;
+        view.cell_edges = cedges;
+        if ((e = fill_cell_slots(view, cslot, n, nullptr)) != hipSuccess) return undo(hip_fail(e, "grid slots"));
+        if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return undo(hip_fail(e, "grid slots"));
+    }
     rm->release(dv.cell_start);
     rm->release(dv.cell_edges);
     rm->release(dv.cell_bits);
     rm->release(dv.df);
     rm->release(dv.items);
+    rm->release(dv.cell_slot);
     dv.cell_start = cstart;
     dv.cell_edges = cedges;
+    dv.cell_slot = cslot;
     dv.cell_bits = bits;
     dv.df = df;
     dv.items = items;
@@ -471,6 +484,7 @@ int64_t device_bytes_needed(const HostGeometry &g, const HostGrid &grid, const R
     const int64_t ncells = (int64_t)grid.dim[0] * grid.dim[1] * grid.dim[2];
     add(grid.start.size(), 4);
     add(grid.edges.size(), 4);
+    if (ncells > 1 && !grid.edges.empty()) add(grid.edges.size(), sizeof(int4));
     add((size_t)((ncells + 31) / 32), 4);
     add((size_t)std::max<int64_t>(grid.items_cap, 1), 4);
     add((size_t)grid.items_cap, sizeof(int2));

@@ -1358,15 +1358,24 @@ __device__ __forceinline__ void item_body(const RmDev &rm, int deferred, int li0
             es[h] = 0.0f;
             j0[h] = 0;
             if (sl < n_e) {
-                e[h] = single ? (int)(beg + sl) : rm.cell_edges[beg + sl];
-                es[h] = aabb[2 * (int64_t)e[h]].w;
-                if (jfix) {
-                    J[h] = jfix;
-                    j0[h] = (uint32_t)((int64_t)e[h] * jfix);
+                if (!single) {
+                    // the cell list's slot: one contiguous load, no gather
+                    const int4 cs = rm.cell_slot[beg + sl];
+                    e[h] = cs.x;
+                    es[h] = __int_as_float(cs.y);
+                    j0[h] = (uint32_t)cs.z;
+                    J[h] = cs.w;
                 } else {
-                    const int64_t s0 = rm.soff[e[h]];
-                    j0[h] = (uint32_t)(s0 / B);
-                    J[h] = (int)((rm.soff[e[h] + 1] - s0) / B);
+                    e[h] = (int)(beg + sl);
+                    es[h] = aabb[2 * (int64_t)e[h]].w;
+                    if (jfix) {
+                        J[h] = jfix;
+                        j0[h] = (uint32_t)((int64_t)e[h] * jfix);
+                    } else {
+                        const int64_t s0 = rm.soff[e[h]];
+                        j0[h] = (uint32_t)(s0 / B);
+                        J[h] = (int)((rm.soff[e[h] + 1] - s0) / B);
+                    }
                 }
                 bytes += 32;
             }
@@ -2617,6 +2626,32 @@ hipError_t launch_update(const RmDev &rm, const UpdateArgs &a, hipStream_t s, hi
 }
 
 int item_edges_max() { return kItemCap; }
+
+__global__ void __launch_bounds__(kBlock) k_cell_slots(RmDev rm, int4 *out, int64_t n)
+{
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const int e = rm.cell_edges[k];
+    const float4 *aabb = reinterpret_cast<const float4 *>(rm.aabb);
+    const int jfix = rm.p_fixed ? rm.p_fixed / rm.B : 0;
+    int j0, J;
+    if (jfix) {
+        J = jfix;
+        j0 = (int)(uint32_t)((int64_t)e * jfix);
+    } else {
+        const int64_t s0 = rm.soff[e];
+        j0 = (int)(uint32_t)(s0 / rm.B);
+        J = (int)((rm.soff[e + 1] - s0) / rm.B);
+    }
+    out[k] = make_int4(e, __float_as_int(aabb[2 * (int64_t)e].w), j0, J);
+}
+
+hipError_t fill_cell_slots(const RmDev &rm, int4 *out, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    k_cell_slots<<<dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s>>>(rm, out, n);
+    return hipGetLastError();
+}
 
 hipError_t test_blocks_resident(int D, int device, int *out)
 {

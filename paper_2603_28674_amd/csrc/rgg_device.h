@@ -71,6 +71,12 @@ struct RmDev {
     int64_t ncells;
     const int32_t *cell_start;
     const int32_t *cell_edges;
+    // per slot of the cell lists (grid roadmaps; null with one cell): the
+    // edge, the bits of its box's largest |coordinate|, its first
+    // configuration / B and its configurations per sphere, so an item's
+    // edges come in one contiguous 16-byte load per slot instead of a
+    // gather through the edge id
+    const int4 *cell_slot;
     int64_t items_cap;
     // block-local slab masks (binary32): slab of x on axis d is
     // clamp(floor((x - sl_org[d]) * sl_inv[d]), 0, slabs_of(D) - 1)
@@ -237,6 +243,9 @@ hipError_t launch_labels(const RmDev &rm, const UpdateArgs &a, hipStream_t s);
 
 // Edges a work item of the classify kernels may hold (at most two per thread).
 int item_edges_max();
+// Fills rm.cell_slot (n = the cell lists' length) from the roadmap's edge
+// boxes and sample offsets, on stream s.
+hipError_t fill_cell_slots(const RmDev &rm, int4 *out, int64_t n, hipStream_t s);
 // Blocks of the binary32 item kernel for dimension D resident on `device` at
 // once (blocks per CU times CUs).
 hipError_t item_blocks_resident(int D, int device, int *out);
