@@ -4,9 +4,9 @@
 //   k_diff      validate the old/new boxes against the resident slots, list
 //               the changed (box, sign) entries in slot order, commit the
 //               slots (Alg. 1: a moved obstacle's old and new poses); with
-//               one grid cell it also hands out the fixed work items;
-//   k_cells     grid mode: activate every grid cell a changed box overlaps
-//               and emit one work item per (cell, chunk of its edges)
+//               one grid cell it also hands out the fixed work items, with
+//               several it activates every grid cell a changed box overlaps
+//               and emits one work item per (cell, chunk of its edges)
 //               (Sec. 4.3);
 //   k_item32/64 one block per work item: pairs of the item's edges with the
 //               changed boxes of the cell, outer test (per-sphere capsule vs
@@ -49,8 +49,6 @@ namespace {
 constexpr int kDiffBlock = 1024;
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
-constexpr int kCellsGrid = 128;
-constexpr int kCellsBatchGrid = 16;   // blocks per roadmap of the batched cell activation
 constexpr int kGrid = kStatBlocks; // blocks of the item kernels
 constexpr int kFp64Grid = 256;     // blocks of the binary64 pass of the FP32 mode
 constexpr int kBatchItemGrid = 1024;  // blocks of a batched item kernel: the blocks of the
@@ -286,6 +284,114 @@ __device__ bool write_entry(const RmDev &rm, int pos, const rgg_box &b, int sign
     return !empty;
 }
 
+// Block-wide exclusive prefix over the kNW wavefronts of a block (64-bit
+// values): returns this thread's prefix, *total the block's sum.
+template <int kNW>
+__device__ inline long long block_prefix64(long long v, long long *total, long long *wsum)
+{
+    const int lane = lane_id(), wv = (int)(threadIdx.x >> 6);
+    long long x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    long long off = 0, tot = 0;
+    for (int w = 0; w < kNW; ++w) {
+        off += w < wv ? wsum[w] : 0;
+        tot += wsum[w];
+    }
+    *total = tot;
+    return off + x - v;
+}
+
+// Grid roadmaps: the cells the n_chg changed entries cover are marked and
+// each newly marked cell emits one work item per chunk of its edges (an
+// empty cell one item, whose first chunk clears the mark).  One block of
+// kDiffBlock threads, right after the entries are written: the (entry,
+// cell) pairs are dealt over the threads (a prefix over the entries' cell
+// counts), so every mark of a pass is in flight at once, and the items go
+// to positions from a block scan (one block per roadmap: no global counter).
+__device__ __forceinline__ void activate_cells(const RmDev &rm, int n_chg)
+{
+    constexpr int kNW = kDiffBlock / 64;
+    __shared__ long long s_cpre[kDiffBlock];
+    __shared__ int s_rng[kDiffBlock][5];   // first cell (x, y, z), cells along x and y
+    __shared__ long long s_w64[kNW];
+    __shared__ int s_w32[kNW];
+    __shared__ int s_items;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid >> 6;
+    if (tid == 0) s_items = 0;
+    for (int q0 = 0; q0 < n_chg; q0 += kDiffBlock) {
+        const int q = q0 + tid;
+        long long cnt = 0;
+        if (q < n_chg) {
+            const ChgEntry &en = rm.chg[q];
+            const int32_t nx = en.c1[0] - en.c0[0] + 1, ny = en.c1[1] - en.c0[1] + 1, nz = en.c1[2] - en.c0[2] + 1;
+            if (nx > 0 && ny > 0 && nz > 0) cnt = (long long)nx * ny * nz;
+            s_rng[tid][0] = en.c0[0];
+            s_rng[tid][1] = en.c0[1];
+            s_rng[tid][2] = en.c0[2];
+            s_rng[tid][3] = nx;
+            s_rng[tid][4] = ny;
+        }
+        long long tot;
+        const long long pre = block_prefix64<kNW>(cnt, &tot, s_w64);
+        s_cpre[tid] = pre;
+        __syncthreads();
+        const int ne = min(kDiffBlock, n_chg - q0);
+        for (long long t0 = 0; t0 < tot; t0 += kDiffBlock) {
+            const long long t = t0 + tid;
+            int nch = 0;
+            long long c = 0;
+            if (t < tot) {
+                // the entry holding pair t: the last j with s_cpre[j] <= t
+                int lo = 0, hi = ne - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_cpre[mid] <= t) lo = mid;
+                    else hi = mid - 1;
+                }
+                const long long k = t - s_cpre[lo];
+                const int nx = s_rng[lo][3], ny = s_rng[lo][4];
+                const int32_t x = s_rng[lo][0] + (int32_t)(k % nx);
+                const int32_t y = s_rng[lo][1] + (int32_t)((k / nx) % ny);
+                const int32_t z = s_rng[lo][2] + (int32_t)(k / ((long long)nx * ny));
+                c = ((long long)z * rm.gdim[1] + y) * rm.gdim[0] + x;
+                const uint32_t bit = 1u << (c & 31);
+                const int32_t s0 = rm.cell_start[c], s1 = rm.cell_start[c + 1];
+                if (!(atomicOr(&rm.cell_bits[c >> 5], bit) & bit)) {
+                    const int32_t n = s1 - s0;
+                    nch = n > 0 ? (n + rm.chunk - 1) / rm.chunk : 1;
+                }
+            }
+            // positions of this pass's items
+            int x = nch;
+            for (int o = 1; o < 64; o <<= 1) {
+                const int y = __shfl_up(x, o);
+                if (lane >= o) x += y;
+            }
+            __syncthreads();
+            if (lane == 63) s_w32[wv] = x;
+            __syncthreads();
+            int off = s_items, ntot = 0;
+            for (int w = 0; w < kNW; ++w) {
+                off += w < wv ? s_w32[w] : 0;
+                ntot += s_w32[w];
+            }
+            const int pos = off + x - nch;
+            for (int h = 0; h < nch; ++h)
+                if ((int64_t)pos + h < rm.items_cap) rm.items[pos + h] = make_int2((int32_t)c, h);
+            __syncthreads();
+            if (tid == 0) s_items += ntot;
+            __syncthreads();
+        }
+    }
+    if (tid == 0) rm.ctl->n_items = s_items;
+}
+
 // One block: validates the update, writes the changed entries and commits
 // the new boxes.  The block's first half takes the entry of a slot's old
 // box, the second half that of its new box, so each thread writes at most
@@ -360,6 +466,11 @@ __device__ __forceinline__ void diff_body(const RmDev &rm, const rgg_box *__rest
             rgg_box n = new_b[k];
             if (!same_box(n, rm.resident[k])) rm.resident[k] = n;
         }
+        // the entries written above are read back by this block's threads
+        if (rm.ncells > 1) {
+            __syncthreads();
+            activate_cells(rm, s_base);
+        }
     }
 }
 
@@ -368,65 +479,6 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff(RmDev rm, const rgg_box *__
                                                      const rgg_box *__restrict__ new_b)
 {
     diff_body<D>(rm, old_b, new_b);
-}
-
-// ------------------------------------------------------------------------
-// k_cells: touched cells -> work items (cell, chunk)
-// ------------------------------------------------------------------------
-
-// block b of G blocks working on this roadmap
-__device__ __forceinline__ void cells_body(const RmDev &rm, int b, int G)
-{
-    const Ctl *ctl = rm.ctl;
-    if (ctl->status != RGG_OK) return;
-    const int n_chg = ctl->n_chg;
-    const int lane = lane_id();
-    const int nw = G * kWaves;
-    for (int q = b * kWaves + (threadIdx.x >> 6); q < n_chg; q += nw) {
-        const ChgEntry &en = rm.chg[q];
-        const int32_t nx = en.c1[0] - en.c0[0] + 1, ny = en.c1[1] - en.c0[1] + 1,
-                      nz = en.c1[2] - en.c0[2] + 1;
-        if (nx <= 0 || ny <= 0 || nz <= 0) continue;
-        const int64_t total = (int64_t)nx * ny * nz;
-        for (int64_t base = 0; base < total; base += 64) {
-            const int64_t k = base + lane;
-            int64_t c = 0;
-            int nch = 0;
-            if (k < total) {
-                const int32_t x = en.c0[0] + (int32_t)(k % nx);
-                const int32_t y = en.c0[1] + (int32_t)((k / nx) % ny);
-                const int32_t z = en.c0[2] + (int32_t)(k / ((int64_t)nx * ny));
-                c = ((int64_t)z * rm.gdim[1] + y) * rm.gdim[0] + x;
-                const uint32_t bit = 1u << (c & 31);
-                if (!(atomicOr(&rm.cell_bits[c >> 5], bit) & bit)) {
-                    const int32_t n = rm.cell_start[c + 1] - rm.cell_start[c];
-                    nch = n > 0 ? (n + rm.chunk - 1) / rm.chunk : 1;
-                }
-            }
-            int tot;
-            const int pre = wave_prefix(nch, &tot);
-            if (tot == 0) continue;
-            int pos0 = 0;
-            if (lane == 0) pos0 = atomicAdd(&rm.ctl->n_items, tot);
-            pos0 = __shfl(pos0, 0);
-            // every winner's items are written by the whole wavefront
-            uint64_t wm = __ballot(nch > 0);
-            while (wm) {
-                const int src = __ffsll((unsigned long long)wm) - 1;
-                wm &= wm - 1;
-                const int64_t cw = __shfl((long long)c, src);
-                const int nw_ = __shfl(nch, src);
-                const int pw = pos0 + __shfl(pre, src);
-                for (int h = lane; h < nw_; h += 64)
-                    if (pw + h < rm.items_cap) rm.items[pw + h] = make_int2((int32_t)cw, h);
-            }
-        }
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) k_cells(RmDev rm)
-{
-    cells_body(rm, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // ------------------------------------------------------------------------
@@ -2319,16 +2371,6 @@ __global__ void __launch_bounds__(kDiffBlock) k_diff_batch(BatchReq *tab, const 
     else diff_body<2>(q.rm, q.a.old_b, q.a.new_b);
 }
 
-// kCellsBatchGrid blocks per request
-__global__ void __launch_bounds__(kBlock) k_cells_batch(const BatchReq *tab)
-{
-    const BatchReq &q = tab[blockIdx.x / kCellsBatchGrid];
-    if (q.rm.ncells <= 1) return;
-    __shared__ RmDev s_rm;
-    load_rm(&s_rm, q.rm);
-    cells_body(s_rm, (int)(blockIdx.x % kCellsBatchGrid), kCellsBatchGrid);
-}
-
 // The items of all requests of one group form one range: request r owns
 // [P_r, P_r + n_items_r).  Block b of G takes items b, b + G, ..., up to
 // kBatchStatic of them, then claims the rest one at a time from a counter
@@ -2560,8 +2602,7 @@ int plan(const RmDev &rm, Node out[7])
     const bool single = rm.ncells == 1;
     void *const diff_fn = rm.D == 3 ? (void *)k_diff<3> : (void *)k_diff<2>;
     if (rm.mixed) {
-        out[n++] = {diff_fn, dim3(1), 0, 1, single ? 2 : 1};
-        if (!single) out[n++] = {(void *)k_cells, dim3(kCellsGrid), 1, 2, 2};
+        out[n++] = {diff_fn, dim3(1), 0, 1, 2};
         // with every round tested inline there is nothing to share out
         const bool share = rm.inline_rounds != kInlineAll;
         // one grid cell: its items are fixed, and blocks past them would only
@@ -2572,8 +2613,7 @@ int plan(const RmDev &rm, Node out[7])
         if (share) out[n++] = {fn(rm, 1), dim3(kGrid), 1, 4, 4};
         out[n++] = {fn(rm, 2), dim3(kFp64Grid), 1, 5, 5};
     } else {
-        out[n++] = {diff_fn, dim3(1), 0, 1, single ? 3 : 1};
-        if (!single) out[n++] = {(void *)k_cells, dim3(kCellsGrid), 1, 2, 3};
+        out[n++] = {diff_fn, dim3(1), 0, 1, 3};
         out[n++] = {fn(rm, 3), dim3(single ? fixed_items_grid(rm) : kGrid), 1, 4, 5};
     }
     out[n++] = {(void *)k_labels, dim3(rm.ntiles + 1), 4, 6, 6};
@@ -2736,11 +2776,8 @@ hipError_t batch_kernels(Emit emit, After after, const BatchReq *tab, const Batc
     void *a_diff[] = {(void *)&t};
     if ((err = after(0)) != hipSuccess) return err;
     void *a_tn[] = {(void *)&t, (void *)&nn};
-    if (any_grid) {
-        if ((err = emit((void *)k_cells_batch, dim3(kCellsBatchGrid * n), dim3(kBlock), a_diff)) != hipSuccess)
-            return err;
-        if ((err = after(1)) != hipSuccess) return err;
-    }
+    // the grid roadmaps' cells are activated by the diff kernel itself
+    if (any_grid && (err = after(1)) != hipSuccess) return err;
     for (int k = 0; k < n_groups; ++k) {
         const BatchGroup &gr = groups[k];
         const int32_t *gp = grp + gr.off;
